@@ -1,0 +1,111 @@
+"""CPU oracle for the exact global minimum cut (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it and
+shares no code with it.
+
+Routes (see ``oracle.cpp`` for the passages each follows):
+  bruteforce(g)        O1, enumeration of all sides (n <= 26)
+  pair_connectivity(g) lambda(G, s, t) for all pairs by enumeration (n <= 20)
+  stoer_wagner(g)      O2
+  noi(g, seed)         O3, sequential Nagamochi-Ono-Ibaraki
+  cut_value(g, side)   c(A) by definition
+Per-step references for the GPU kernels are in ``oracle.steps``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", _SRC,
+                               "-o", _LIB + ".tmp"])
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        vp = ctypes.c_void_p
+        lib.mco_cut_value.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
+        lib.mco_bruteforce.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
+        lib.mco_pair_connectivity.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
+        lib.mco_stoer_wagner.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
+        lib.mco_noi.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64, vp, vp, vp]
+        _lib = lib
+    return _lib
+
+
+def _arrs(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    w = np.ascontiguousarray(g.w, dtype=np.int32)
+    return rp, col, w
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def cut_value(g, side) -> int:
+    rp, col, w = _arrs(g)
+    s = np.ascontiguousarray(side, dtype=np.uint8)
+    out = np.zeros(1, np.int64)
+    _check(_load().mco_cut_value(g.n, _p(rp), _p(col), _p(w), _p(s), _p(out)), "cut_value")
+    return int(out[0])
+
+
+def bruteforce(g):
+    rp, col, w = _arrs(g)
+    lam = np.zeros(1, np.int64)
+    side = np.zeros(g.n, np.uint8)
+    _check(_load().mco_bruteforce(g.n, _p(rp), _p(col), _p(w), _p(lam), _p(side)), "bruteforce")
+    return int(lam[0]), side
+
+
+def pair_connectivity(g) -> np.ndarray:
+    rp, col, w = _arrs(g)
+    conn = np.zeros(g.n * g.n, np.int64)
+    _check(_load().mco_pair_connectivity(g.n, _p(rp), _p(col), _p(w), _p(conn)),
+           "pair_connectivity")
+    return conn.reshape(g.n, g.n)
+
+
+def stoer_wagner(g):
+    rp, col, w = _arrs(g)
+    lam = np.zeros(1, np.int64)
+    side = np.zeros(g.n, np.uint8)
+    _check(_load().mco_stoer_wagner(g.n, _p(rp), _p(col), _p(w), _p(lam), _p(side)),
+           "stoer_wagner")
+    return int(lam[0]), side
+
+
+def noi(g, seed: int = 0):
+    rp, col, w = _arrs(g)
+    lam = np.zeros(1, np.int64)
+    side = np.zeros(g.n, np.uint8)
+    rounds = np.zeros(1, np.int32)
+    _check(_load().mco_noi(g.n, _p(rp), _p(col), _p(w), ctypes.c_uint64(seed), _p(lam),
+                           _p(side), _p(rounds)), "noi")
+    return int(lam[0]), side, int(rounds[0])

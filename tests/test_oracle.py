@@ -1,0 +1,262 @@
+"""Pins for the CPU oracle against facts fixed by the mathematics.
+
+Each route (O1 enumeration, O2 Stoer-Wagner, O3 sequential NOI) is checked
+against closed forms of textbook graphs, hand-worked fixtures, invariants of
+the minimum cut (lambda <= minimum weighted degree, scaling, relabelling,
+monotonicity under edge insertion and contraction) and against each other on
+thousands of random tiny graphs.  A dropped term, a wrong sign or a
+transposed index in any route breaks one of these.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ROUTES = {
+    "bruteforce": lambda g: oracle.bruteforce(g)[:2],
+    "stoer_wagner": lambda g: oracle.stoer_wagner(g)[:2],
+    "noi": lambda g: oracle.noi(g, 7)[:2],
+}
+
+
+def min_degree(g):
+    deg = np.zeros(g.n, np.int64)
+    src = g.src()
+    keep = src != g.col
+    np.add.at(deg, src[keep], g.w[keep])
+    return int(deg.min())
+
+
+def check_side(g, lam, side):
+    side = np.asarray(side)
+    assert 0 < side.sum() < g.n, "side must be a non-empty proper subset"
+    assert oracle.cut_value(g, side) == lam
+
+
+def random_graph(rng, n, density, wmax, connected=True):
+    edges, ws = [], []
+    for u, v in itertools.combinations(range(n), 2):
+        if rng.random() < density:
+            edges.append((u, v))
+            ws.append(int(rng.integers(1, wmax + 1)))
+    if connected:  # a random spanning path keeps it connected
+        perm = rng.permutation(n)
+        for a, b in zip(perm[:-1], perm[1:]):
+            edges.append((int(a), int(b)))
+            ws.append(int(rng.integers(1, wmax + 1)))
+    if not edges:
+        edges, ws = [(0, 1)], [1]
+    return gg.from_edges(n, edges, ws)
+
+
+# --------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("route", list(ROUTES))
+@pytest.mark.parametrize("n,w", [(2, 1), (3, 1), (6, 1), (9, 1), (7, 5)])
+def test_complete_graph(route, n, w):
+    g = gg.complete(n, w)
+    lam, side = ROUTES[route](g)
+    assert lam == w * (n - 1)
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+@pytest.mark.parametrize("n,seed", [(3, 1), (5, 2), (12, 3), (17, 4)])
+def test_cycle_two_lightest(route, n, seed):
+    g = gg.cycle(n, seed, 1, 20)
+    # each cycle edge appears twice in the CSR; take weights per edge
+    src = g.src()
+    per_edge = np.sort(g.w[src < g.col])
+    lam, side = ROUTES[route](g)
+    assert lam == per_edge[0] + per_edge[1]
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+def test_trees_min_edge(route):
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        n = int(rng.integers(2, 14))
+        edges = [(int(rng.integers(0, v)), v) for v in range(1, n)]
+        ws = [int(x) for x in rng.integers(1, 30, size=n - 1)]
+        g = gg.from_edges(n, edges, ws)
+        lam, side = ROUTES[route](g)
+        assert lam == min(ws)
+        check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (3, 3), (4, 6), (5, 2)])
+def test_complete_bipartite(route, a, b):
+    edges = [(i, a + j) for i in range(a) for j in range(b)]
+    g = gg.from_edges(a + b, edges)
+    lam, side = ROUTES[route](g)
+    assert lam == min(a, b)
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_hypercube(route, d):
+    n = 1 << d
+    edges = [(v, v ^ (1 << i)) for v in range(n) for i in range(d) if v < v ^ (1 << i)]
+    g = gg.from_edges(n, edges)
+    lam, side = ROUTES[route](g)
+    assert lam == d
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+@pytest.mark.parametrize("a,k", [(4, 1), (5, 2), (6, 3), (6, 5), (6, 6), (8, 7)])
+def test_two_cliques(route, a, k):
+    # k < a: the k joining edges are the cheapest cut (a lone vertex without a
+    # joining edge costs a-1 >= k).  k == a: a perfect matching, every vertex
+    # has degree a and both the joining cut and every lone vertex cost a.
+    g = gg.two_cliques(a, k)
+    lam, side = ROUTES[route](g)
+    assert lam == (k if k < a else a)
+    check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+def test_two_vertices_parallel(route):
+    g = gg.from_edges(2, [(0, 1), (0, 1), (1, 0)], [3, 4, 5])
+    lam, side = ROUTES[route](g)
+    assert lam == 12
+    assert list(side) in ([0, 1], [1, 0])
+
+
+@pytest.mark.parametrize("route", list(ROUTES))
+def test_disconnected_is_zero(route):
+    g = gg.from_edges(7, [(0, 1), (1, 2), (3, 4), (4, 5), (5, 6), (6, 3)], [4, 4, 1, 1, 1, 1])
+    lam, side = ROUTES[route](g)
+    assert lam == 0
+    check_side(g, lam, side)
+
+
+def test_hand_examples():
+    spec = json.load(open(os.path.join(GOLDEN, "hand_examples.json")))
+    for ex in spec["graphs"]:
+        e = np.array(ex["edges"])
+        g = gg.from_edges(ex["n"], e[:, :2], e[:, 2])
+        for route, f in ROUTES.items():
+            lam, side = f(g)
+            assert lam == ex["lambda"], (ex["name"], route)
+            check_side(g, lam, side)
+        # O1 returns one minimiser; it must be among the listed sides
+        _, side = oracle.bruteforce(g)
+        s = set(np.flatnonzero(side).tolist())
+        comp = set(range(ex["n"])) - s
+        listed = [set(x) for x in ex["sides"]]
+        assert s in listed or comp in listed, ex["name"]
+
+
+# --------------------------------------------------------- cross-route sweep
+def test_routes_agree_on_random_tiny_graphs():
+    rng = np.random.default_rng(2024)
+    for trial in range(1500):
+        n = int(rng.integers(2, 11))
+        g = random_graph(rng, n, float(rng.uniform(0.1, 1.0)), int(rng.choice([1, 3, 10, 100])),
+                         connected=bool(rng.random() < 0.9))
+        lb, sb = oracle.bruteforce(g)
+        ls, ss = oracle.stoer_wagner(g)
+        ln, sn, _ = oracle.noi(g, trial)
+        assert lb == ls == ln, (trial, lb, ls, ln)
+        for s in (sb, ss, sn):
+            check_side(g, lb, s)
+        assert lb <= min_degree(g)
+
+
+def test_bruteforce_max_size_and_pairs():
+    rng = np.random.default_rng(5)
+    g = random_graph(rng, 18, 0.3, 5)
+    lb, sb = oracle.bruteforce(g)
+    assert lb == oracle.stoer_wagner(g)[0] == oracle.noi(g)[0]
+    conn = oracle.pair_connectivity(gg.from_edges(12, [(i, (i + 1) % 12) for i in range(12)]))
+    # on a unit cycle every pair has connectivity 2
+    assert (conn[~np.eye(12, dtype=bool)] == 2).all()
+
+
+def test_pair_connectivity_properties():
+    rng = np.random.default_rng(9)
+    for trial in range(30):
+        n = int(rng.integers(3, 10))
+        g = random_graph(rng, n, 0.5, 7)
+        conn = oracle.pair_connectivity(g)
+        off = conn[~np.eye(n, dtype=bool)]
+        assert (conn == conn.T).all()
+        assert off.min() == oracle.bruteforce(g)[0]
+        # ultrametric-like property of edge connectivity:
+        # lambda(s,t) >= min(lambda(s,x), lambda(x,t)) for every x
+        for s, t, x in itertools.permutations(range(n), 3):
+            assert conn[s, t] >= min(conn[s, x], conn[x, t])
+    # path: connectivity is the lightest edge between the two ends
+    g = gg.from_edges(4, [(0, 1), (1, 2), (2, 3)], [5, 2, 7])
+    conn = oracle.pair_connectivity(g)
+    assert conn[0, 1] == 5 and conn[0, 3] == 2 and conn[2, 3] == 7 and conn[1, 2] == 2
+
+
+# ---------------------------------------------------------------- invariants
+def test_invariants():
+    rng = np.random.default_rng(77)
+    for trial in range(150):
+        n = int(rng.integers(3, 11))
+        g = random_graph(rng, n, float(rng.uniform(0.2, 0.9)), 9)
+        lam = oracle.bruteforce(g)[0]
+        assert 1 <= lam <= min_degree(g)
+        # scaling every weight by s scales lambda by s
+        s = int(rng.integers(2, 6))
+        gs = gg.Graph(g.n, g.row_ptr, g.col, g.w * s)
+        assert oracle.noi(gs, trial)[0] == s * lam
+        assert oracle.stoer_wagner(gs)[0] == s * lam
+        # relabelling leaves lambda unchanged
+        perm = rng.permutation(n)
+        src = g.src()
+        e = np.stack([perm[src], perm[g.col]], 1)
+        keep = e[:, 0] < e[:, 1]
+        gp = gg.from_edges(n, e[keep], g.w[keep])
+        assert oracle.noi(gp, trial)[0] == lam
+        # adding an edge never lowers lambda
+        u, v = rng.choice(n, 2, replace=False)
+        e2 = np.concatenate([np.stack([src, g.col], 1)[src < g.col], [[u, v]]])
+        w2 = np.concatenate([g.w[src < g.col], [int(rng.integers(1, 5))]])
+        assert oracle.noi(gg.from_edges(n, e2, w2), trial)[0] >= lam
+        # contracting an edge never lowers lambda (when two or more remain)
+        a, b = int(src[0]), int(g.col[0])
+        relab = np.arange(n)
+        relab[b] = a
+        relab = np.unique(relab, return_inverse=True)[1]
+        ce = np.stack([relab[src], relab[g.col]], 1)
+        keep = ce[:, 0] < ce[:, 1]
+        if n - 1 >= 2:
+            gc = gg.from_edges(n - 1, ce[keep], g.w[keep])
+            assert oracle.bruteforce(gc)[0] >= lam
+
+
+def test_noi_seed_independent_on_workload_shapes():
+    # shapes of the workloads, small: planted clusters and a power-law core
+    graphs = [gg.batch_graph(g) for g in (1, 3, 4, 9)]
+    graphs.append(gg.chung_lu(17, 3000, 2.5, 16.0, 1, 50, kcore=0, lcc=True))
+    for g in graphs:
+        lams = {oracle.noi(g, s)[0] for s in range(4)}
+        assert len(lams) == 1
+        lam = lams.pop()
+        if g.n <= 2500:
+            assert oracle.stoer_wagner(g)[0] == lam
+        _, side, _ = oracle.noi(g, 1)
+        check_side(g, lam, side)
+
+
+@pytest.mark.slow
+def test_stoer_wagner_equals_noi_on_planted_4096():
+    g = gg.planted_4096()
+    ls, ss = oracle.stoer_wagner(g)
+    ln, sn, rounds = oracle.noi(g, 3)
+    assert ls == ln
+    check_side(g, ls, ss)
+    check_side(g, ln, sn)
