@@ -1,0 +1,147 @@
+/* Exact global minimum cut of undirected graphs with positive integer edge
+ * weights, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the bound-driven contraction loop of Henzinger, Noe and
+ * Schulz, "Shared-memory Exact Minimum Cuts": an upper bound lambda-hat
+ * (minimum weighted degree, optionally lowered by a VieCut-style clustering
+ * pass), Padberg-Rinaldi tests, many concurrent bounded CAPFOREST scans that
+ * mark contractible edges in a union-find (Algorithm 1, Lemmas 1 and 2), and
+ * graph contraction, repeated until every graph is solved (Algorithm 2).
+ * The result lambda is exact; one side of a minimum cut is also returned
+ * (section "Putting Things Together").
+ *
+ * Conventions for every entry point:
+ *  - Graphs are symmetric CSR arrays in DEVICE memory: row_ptr int64[n+1]
+ *    (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz), col int32[nnz],
+ *    w int32[nnz] with w >= 1.  Each undirected edge {u,v} appears in row u
+ *    and in row v with the same weight.  Self-loops are accepted and ignored
+ *    (they never cross a cut); repeated entries count with their total
+ *    weight.  Asymmetric input gives an undefined result.
+ *  - The sum of all weights of one graph (over entries) must not exceed
+ *    2 * (2^31 - 1), so every cut fits in 31 bits (MC_EOVERFLOW otherwise).
+ *  - At most 2^30 - 1 vertices in total and nnz < 2^32 per call.
+ *  - Inputs are never modified.  The caller owns all input and output
+ *    buffers; the library owns its workspace (allocated on first use, grown
+ *    when needed, kept per device until mc_release()).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls return
+ *    after the stream work has finished.  Calls are serialised internally.
+ *  - Every function returns MC_OK (0) or a negative MC_E* code; nothing
+ *    throws across the ABI.  On error the outputs are unspecified.
+ */
+#ifndef MINCUT_H
+#define MINCUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MC_OK = 0,
+  MC_EINVAL = -1,    /* null pointer, bad sizes, bad row_ptr, col out of range, w < 1 */
+  MC_ENOCUT = -2,    /* a graph with fewer than two vertices has no cut */
+  MC_EOVERFLOW = -3, /* total weight of a graph above 2 * (2^31 - 1) */
+  MC_ENOMEM = -4,    /* device workspace allocation failed */
+  MC_EHIP = -5,      /* a HIP runtime call failed */
+  MC_EBUSY = -6,     /* server admission full (non-blocking submit) */
+  MC_ESTATE = -7,    /* unknown ticket or server stopped */
+  MC_EINTERNAL = -8  /* a round made no progress (never expected; reported, not looped) */
+};
+
+typedef struct mc_graph {
+  int32_t n;              /* vertices, >= 2 */
+  int64_t nnz;            /* CSR entries (2 x undirected edges) */
+  const int64_t* row_ptr; /* device, n + 1 */
+  const int32_t* col;     /* device, nnz, in [0, n) */
+  const int32_t* w;       /* device, nnz, >= 1 */
+} mc_graph;
+
+/* Many independent graphs packed as one CSR (their disjoint union):
+ * graph g owns vertices [vtx_off[g], vtx_off[g+1]) and its entries hold
+ * GLOBAL vertex ids inside that range. */
+typedef struct mc_batch {
+  int32_t num_graphs;
+  int32_t n_total;
+  int64_t nnz_total;
+  const int64_t* row_ptr; /* device, n_total + 1 */
+  const int32_t* col;     /* device, nnz_total */
+  const int32_t* w;       /* device, nnz_total */
+  const int64_t* vtx_off; /* HOST, num_graphs + 1, vtx_off[0] = 0 */
+} mc_batch;
+
+typedef struct mc_options {
+  uint64_t seed;           /* scan start order */
+  int32_t use_pr;          /* 1: Padberg-Rinaldi tests every round (default 1) */
+  int32_t use_viecut;      /* 1: lower lambda-hat by clustering first (default 0) */
+  int32_t region_waves;    /* concurrent region scans; 0 = one per SIMD slot */
+  int32_t eager_blacklist; /* 1: skip neighbours already claimed elsewhere (default 1) */
+  int32_t max_pops;        /* per-scan budget (early termination); 0 = unbounded */
+  int32_t max_rounds;      /* safety cap on rounds; 0 = none */
+  int32_t timing;          /* 1: time kernel classes with HIP events (mc_timing) */
+  int32_t force_fallback;  /* debug: region scans find nothing, so the
+                              sequential fallback always runs */
+  int32_t whole_max;       /* graphs up to this size are scanned whole by one
+                              wave; 0 = default (6144) */
+  int32_t lp_sweeps;       /* clustering sweeps per level when use_viecut */
+  int32_t reserved[5];
+} mc_options;
+
+typedef struct mc_stats {
+  int32_t rounds;          /* contraction rounds */
+  int32_t fallbacks;       /* sequential CAPFOREST runs */
+  int64_t unions_pr;       /* pairs marked by Padberg-Rinaldi tests */
+  int64_t pairs_scan;      /* pairs marked by CAPFOREST scans */
+  int64_t scans;           /* scans started */
+  int64_t pops;            /* vertices visited by scans */
+  int64_t overflows;       /* scans ended because their LDS map filled */
+  int64_t lambda_initial;  /* single graph: minimum weighted degree */
+  int64_t lambda_viecut;   /* single graph: bound after clustering (or -1) */
+  double ms;               /* wall time of the call */
+  int32_t n_round[64];     /* vertices at the start of each round (first 64) */
+  int64_t nnz_round[64];   /* entries at the start of each round */
+} mc_stats;
+
+/* Fill `opt` with the defaults. */
+void mc_options_default(mc_options* opt);
+
+/* lambda (HOST int64) receives the minimum cut value.  side (DEVICE uint8[n],
+ * may be NULL) receives 1 for the vertices of one side of a minimum cut and
+ * 0 for the others, with side[0] = 0.  A disconnected graph gives lambda = 0
+ * and the side of every vertex outside vertex 0's component.  stats may be
+ * NULL.  MC_ENOCUT if n < 2. */
+int mc_mincut(const mc_graph* g, void* stream, const mc_options* opt, int64_t* lambda,
+              uint8_t* side, mc_stats* stats);
+
+/* All graphs of the batch in one packed solve.  lambdas: HOST int64[G].
+ * sides: DEVICE uint8[n_total] or NULL; for each graph its first vertex is
+ * on side 0.  MC_ENOCUT if any graph has fewer than two vertices. */
+int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, int64_t* lambdas,
+                      uint8_t* sides, mc_stats* stats);
+
+/* Device bytes the workspace needs for a packed problem of this size. */
+size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs);
+
+/* Free the cached workspace of the current device. */
+void mc_release(void);
+
+const char* mc_strerror(int code);
+
+/* Kernel-class timing, filled when mc_options.timing = 1: launches, summed
+ * device time (HIP events on the launch stream) and algorithmic bytes. */
+typedef struct mc_timing_entry {
+  char name[24];
+  int64_t launches;
+  double ms;
+  double algo_bytes;
+} mc_timing_entry;
+
+/* Copies up to `max` entries; returns how many classes exist. */
+int mc_timing_get(mc_timing_entry* out, int max);
+void mc_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MINCUT_H */

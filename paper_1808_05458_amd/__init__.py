@@ -1,0 +1,230 @@
+"""Exact global minimum cut on one MI355X: Python binding of ``libmincut.so``.
+
+Argument marshalling only.  Every step of the solve runs in the HIP kernels
+behind the C ABI declared in ``include/mincut.h``; PyTorch provides device
+memory and the stream.  There is no CPU fallback: if the library is not
+built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+_LIB = os.path.join(_HERE, "libmincut.so")
+_SOURCES = [os.path.join(_HERE, "csrc", "engine.hip")]
+HEADER = os.path.join(_ROOT, "include", "mincut.h")
+
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-result", "-Wno-unused-value"]
+
+MC_OK, MC_EINVAL, MC_ENOCUT, MC_EOVERFLOW, MC_ENOMEM, MC_EHIP, MC_EBUSY, MC_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MC_EINTERNAL = -8
+
+
+def build() -> str:
+    """Compile the HIP library for gfx950 (always recompiles)."""
+    out = _LIB + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, *_SOURCES, "-o", out]
+    subprocess.check_call(cmd, cwd=_ROOT)
+    os.replace(out, _LIB)
+    return _LIB
+
+
+class MincutError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        lib = _load()
+        msg = lib.mc_strerror(code).decode()
+        super().__init__(f"{what}: {msg} (code {code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("use_pr", ctypes.c_int32),
+                ("use_viecut", ctypes.c_int32), ("region_waves", ctypes.c_int32),
+                ("eager_blacklist", ctypes.c_int32), ("max_pops", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("force_fallback", ctypes.c_int32), ("whole_max", ctypes.c_int32),
+                ("lp_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("unions_pr", ctypes.c_int64), ("pairs_scan", ctypes.c_int64),
+                ("scans", ctypes.c_int64), ("pops", ctypes.c_int64),
+                ("overflows", ctypes.c_int64), ("lambda_initial", ctypes.c_int64),
+                ("lambda_viecut", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("n_round", ctypes.c_int32 * 64), ("nnz_round", ctypes.c_int64 * 64)]
+
+    def as_dict(self):
+        r = min(self.rounds, 64)
+        return {"rounds": self.rounds, "fallbacks": self.fallbacks,
+                "unions_pr": self.unions_pr, "pairs_scan": self.pairs_scan,
+                "scans": self.scans, "pops": self.pops, "overflows": self.overflows,
+                "lambda_initial": self.lambda_initial, "lambda_viecut": self.lambda_viecut,
+                "ms": self.ms, "n_round": list(self.n_round[:r]),
+                "nnz_round": list(self.nnz_round[:r])}
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int32), ("n_total", ctypes.c_int32),
+                ("nnz_total", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("vtx_off", ctypes.c_void_p)]
+
+
+class TimingEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("ms", ctypes.c_double), ("algo_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise RuntimeError(
+            f"{_LIB} is not built; run __graft_entry__.build() (hipcc, gfx950). "
+            "There is no CPU fallback.")
+    lib = ctypes.CDLL(_LIB)
+    vp = ctypes.c_void_p
+    lib.mc_options_default.argtypes = [vp]
+    lib.mc_options_default.restype = None
+    lib.mc_mincut.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mc_mincut.restype = ctypes.c_int
+    lib.mc_mincut_batched.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mc_mincut_batched.restype = ctypes.c_int
+    lib.mc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+    lib.mc_workspace_bytes.restype = ctypes.c_size_t
+    lib.mc_release.argtypes = []
+    lib.mc_release.restype = None
+    lib.mc_strerror.argtypes = [ctypes.c_int]
+    lib.mc_strerror.restype = ctypes.c_char_p
+    lib.mc_timing_get.argtypes = [vp, ctypes.c_int]
+    lib.mc_timing_get.restype = ctypes.c_int
+    lib.mc_timing_reset.argtypes = []
+    lib.mc_timing_reset.restype = None
+    _lib = lib
+    return lib
+
+
+def options(**kw) -> Options:
+    o = Options()
+    _load().mc_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mincut(row_ptr, col, w, *, want_side: bool = True, stream=None, opts: Optional[Options] = None,
+           **kw):
+    """lambda, side (uint8 tensor or None), stats dict for one graph whose
+    CSR arrays are device tensors (int64 row_ptr, int32 col, int32 w)."""
+    import torch
+    lib = _load()
+    n = row_ptr.numel() - 1
+    g = Graph(n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"))
+    o = opts if opts is not None else options(**kw)
+    side = torch.empty(max(n, 1), dtype=torch.uint8, device=row_ptr.device) if want_side else None
+    lam = ctypes.c_int64(-1)
+    st = Stats()
+    rc = lib.mc_mincut(ctypes.byref(g), _stream(stream), ctypes.byref(o), ctypes.byref(lam),
+                       ctypes.c_void_p(side.data_ptr()) if side is not None else None,
+                       ctypes.byref(st))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_mincut")
+    return int(lam.value), side, st.as_dict()
+
+
+def mincut_batched(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool = True,
+                   stream=None, opts: Optional[Options] = None, **kw):
+    """Solve all graphs of a packed CSR (global vertex ids; graph g owns
+    vertices [vtx_off[g], vtx_off[g+1])).  Returns (lambdas int64 ndarray,
+    sides uint8 tensor or None, stats dict)."""
+    import torch
+    lib = _load()
+    voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    G = len(voff) - 1
+    n = row_ptr.numel() - 1
+    b = Batch(G, n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"),
+              voff.ctypes.data_as(ctypes.c_void_p))
+    o = opts if opts is not None else options(**kw)
+    sides = torch.empty(max(n, 1), dtype=torch.uint8, device=row_ptr.device) if want_side else None
+    lams = np.full(G, -1, np.int64)
+    st = Stats()
+    rc = lib.mc_mincut_batched(ctypes.byref(b), _stream(stream), ctypes.byref(o),
+                               lams.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.c_void_p(sides.data_ptr()) if sides is not None else None,
+                               ctypes.byref(st))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_mincut_batched")
+    return lams, sides, st.as_dict()
+
+
+def workspace_bytes(n_total: int, nnz_total: int, num_graphs: int = 1) -> int:
+    return int(_load().mc_workspace_bytes(n_total, nnz_total, num_graphs))
+
+
+def release():
+    _load().mc_release()
+
+
+def timing():
+    lib = _load()
+    arr = (TimingEntry * 64)()
+    k = lib.mc_timing_get(arr, 64)
+    return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "ms": arr[i].ms,
+             "algo_bytes": arr[i].algo_bytes} for i in range(min(k, 64))]
+
+
+def timing_reset():
+    _load().mc_timing_reset()
+
+
+def to_device(g, device="cuda"):
+    """Copy a host CSR (numpy arrays) to device tensors."""
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(g.row_ptr, np.int64)).to(device),
+            torch.from_numpy(np.ascontiguousarray(g.col, np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(g.w, np.int32)).to(device))

@@ -1,0 +1,101 @@
+// Device-side helpers shared by the min-cut kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MC_WAVE 64
+
+namespace mc {
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, MC_WAVE); }
+
+// Wave-wide reductions (all lanes receive the result).
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, MC_WAVE);
+  return v;
+}
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, MC_WAVE);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t t = __shfl_xor(v, o, MC_WAVE);
+    v = t < v ? t : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t t = __shfl_xor(v, o, MC_WAVE);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// Relaxed device-scope loads and stores for data other waves update.
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Lock-free union-find over int32 parents.  Invariant: parent[v] <= v, so a
+// root is always linked under a smaller root and path halving only ever
+// shortens a path to an ancestor; concurrent finds and unions stay safe.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t p = ld_relaxed(parent + x);
+  while (p != x) {
+    int32_t gp = ld_relaxed(parent + p);
+    if (gp != p) st_relaxed(parent + x, gp);  // halving: point at grandparent
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+// Returns true if this call merged two different sets.
+__device__ __forceinline__ bool uf_union(int32_t* parent, int32_t a, int32_t b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return false;
+    if (a > b) { int32_t t = a; a = b; b = t; }
+    // link the larger root b under the smaller root a
+    int32_t expected = b;
+    if (__hip_atomic_compare_exchange_strong(parent + b, &expected, a, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+    b = expected;  // b gained a parent meanwhile; retry from there
+  }
+}
+
+__device__ __forceinline__ void atomic_min_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-stride helpers
+__device__ __forceinline__ int64_t gtid() {
+  return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+}  // namespace mc

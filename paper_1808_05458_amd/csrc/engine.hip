@@ -1,0 +1,666 @@
+// Round driver and C ABI of the exact minimum-cut library.
+//
+// Algorithm 2 (Parallel Minimum Cut) on a packed set of graphs: after
+// ingest (trivial bound, connectivity) every round runs Padberg-Rinaldi
+// tests, bounded CAPFOREST scans (the sequential fallback where a graph got
+// no contractible pair), union-find finish and block numbering, the bound
+// update from the scans' prefix cuts, contraction and the minimum-degree
+// bound of the contracted graph, until every graph has at most two vertices
+// or a zero bound.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mincut.h"
+#include "kernels.h"
+
+namespace mc {
+
+#define MC_HIP(call)                              \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) {                       \
+      last_hip_error() = e_;                      \
+      return MC_EHIP;                             \
+    }                                             \
+  } while (0)
+
+inline hipError_t& last_hip_error() {
+  static hipError_t e = hipSuccess;
+  return e;
+}
+
+constexpr int REGION_CAP = 1024;
+constexpr int WHOLE_CAP_S = 2048;
+constexpr int WHOLE_CAP_L = 8192;
+
+// ------------------------------------------------------------------ timing
+struct TimingClass {
+  std::string name;
+  int64_t launches = 0;
+  double ms = 0;
+  double bytes = 0;
+};
+
+struct Timer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<TimingClass> classes;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+
+  int cls(const char* name) {
+    for (size_t i = 0; i < classes.size(); ++i)
+      if (classes[i].name == name) return (int)i;
+    classes.push_back(TimingClass{name});
+    return (int)classes.size() - 1;
+  }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+  // begin/end bracket a launch (or a short sequence) of one class
+  int begin(const char* name, hipEvent_t& a) {
+    if (!on) return -1;
+    a = ev();
+    hipEventRecord(a, s);
+    return cls(name);
+  }
+  void end(int c, hipEvent_t a, double bytes) {
+    if (c < 0) return;
+    hipEvent_t b = ev();
+    hipEventRecord(b, s);
+    pending.push_back({c, a, b, bytes});
+  }
+  void collect() {
+    for (auto& p : pending) {
+      float ms = 0;
+      hipEventSynchronize(p.b);
+      hipEventElapsedTime(&ms, p.a, p.b);
+      classes[p.cls].launches += 1;
+      classes[p.cls].ms += ms;
+      classes[p.cls].bytes += p.bytes;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+};
+
+Timer& timer() {
+  static Timer t;
+  return t;
+}
+
+struct TimedScope {
+  int c;
+  hipEvent_t a{};
+  double bytes;
+  TimedScope(const char* name, double b) : bytes(b) { c = timer().begin(name, a); }
+  ~TimedScope() { timer().end(c, a, bytes); }
+};
+
+// --------------------------------------------------------------- workspace
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Workspace {
+  int device = -1;
+  int64_t capN = 0, capE = 0, capG = 0;
+  std::vector<void*> allocs;
+  // vertex arrays
+  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *newid, *map, *ogid;
+  uint8_t* fb_st;
+  int64_t *rp, *cdeg;
+  // entry arrays
+  int32_t *src, *col, *w;
+  uint64_t *keys, *keys_alt;
+  int32_t *vals, *vals_alt;
+  // graph arrays
+  int64_t *voff, *lhat, *wsum;
+  int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole,
+      *whole2, *fb_list, *root0, *flip, *nvoff;
+  uint64_t *bdeg, *balpha;
+  uint8_t* mode;
+  int32_t* scan_k;
+  int64_t scan_k_cap = 0;
+  void* tmp;
+  size_t tmp_bytes = 0;
+  Ctl* ctl;
+  Ctl* ctl_host = nullptr;
+
+  void release() {
+    for (void* p : allocs) hipFree(p);
+    allocs.clear();
+    if (ctl_host) hipHostFree(ctl_host);
+    ctl_host = nullptr;
+    capN = capE = capG = 0;
+  }
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
+  size_t b = 0;
+  b += align_up((N + 1) * 4) * 13 + align_up(N + 1);
+  b += align_up((N + 2) * 8) * 2;
+  b += align_up(E * 4) * 3 + align_up(E * 8) * 2 + align_up(E * 4) * 2;
+  b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 15 + align_up((G + 1) * 8) * 2 +
+       align_up(G + 1);
+  b += align_up((2 * N + G + 64) * 4);
+  size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
+  t = std::max(t, scan_tmp_bytes<int32_t>(N + 1));
+  b += align_up(t) + align_up(sizeof(Ctl));
+  return b;
+}
+
+int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
+  int dev = 0;
+  MC_HIP(hipGetDevice(&dev));
+  if (ws.device == dev && N <= ws.capN && E <= ws.capE && G <= ws.capG) return MC_OK;
+  ws.release();
+  ws.device = dev;
+  N = std::max<int64_t>(N, 16);
+  E = std::max<int64_t>(E, 64);
+  G = std::max<int64_t>(G, 1);
+  auto A = [&](size_t bytes, void** out) -> int {
+    void* p = nullptr;
+    if (hipMalloc(&p, align_up(bytes)) != hipSuccess) return MC_ENOMEM;
+    ws.allocs.push_back(p);
+    *out = p;
+    return MC_OK;
+  };
+#define ALLOC(ptr, bytes)                                     \
+  do {                                                        \
+    int rc_ = A((bytes), (void**)&(ptr));                     \
+    if (rc_) { ws.release(); return rc_; }                    \
+  } while (0)
+  ALLOC(ws.gid[0], (N + 1) * 4);
+  ALLOC(ws.gid[1], (N + 1) * 4);
+  ALLOC(ws.parent, (N + 1) * 4);
+  ALLOC(ws.lab, (N + 1) * 4);
+  ALLOC(ws.claim, (N + 1) * 4);
+  ALLOC(ws.step, (N + 1) * 4);
+  ALLOC(ws.fb_r, (N + 1) * 4);
+  ALLOC(ws.fb_step, (N + 1) * 4);
+  ALLOC(ws.newid, (N + 1) * 4);
+  ALLOC(ws.map, (N + 1) * 4);
+  ALLOC(ws.ogid, (N + 1) * 4);
+  ALLOC(ws.fb_st, N + 1);
+  ALLOC(ws.rp, (N + 2) * 8);
+  ALLOC(ws.cdeg, (N + 2) * 8);
+  ALLOC(ws.src, E * 4);
+  ALLOC(ws.col, E * 4);
+  ALLOC(ws.w, E * 4);
+  ALLOC(ws.keys, E * 8);
+  ALLOC(ws.keys_alt, E * 8);
+  ALLOC(ws.vals, E * 4);
+  ALLOC(ws.vals_alt, E * 4);
+  ALLOC(ws.voff, (G + 1) * 8);
+  ALLOC(ws.lhat, (G + 1) * 8);
+  ALLOC(ws.wsum, (G + 1) * 8);
+  ALLOC(ws.gn, (G + 1) * 4);
+  ALLOC(ws.cvoff, (G + 1) * 4);
+  ALLOC(ws.nnew, (G + 1) * 4);
+  ALLOC(ws.active, (G + 1) * 4);
+  ALLOC(ws.ucount, (G + 1) * 4);
+  ALLOC(ws.rec_type, (G + 1) * 4);
+  ALLOC(ws.rec_id, (G + 1) * 4);
+  ALLOC(ws.rec_k, (G + 1) * 4);
+  ALLOC(ws.fb_k, (G + 1) * 4);
+  ALLOC(ws.whole, (G + 1) * 4);
+  ALLOC(ws.whole2, (G + 1) * 4);
+  ALLOC(ws.fb_list, (G + 1) * 4);
+  ALLOC(ws.root0, (G + 1) * 4);
+  ALLOC(ws.flip, (G + 1) * 4);
+  ALLOC(ws.nvoff, (G + 1) * 4);
+  ALLOC(ws.bdeg, (G + 1) * 8);
+  ALLOC(ws.balpha, (G + 1) * 8);
+  ALLOC(ws.mode, G + 1);
+  ws.scan_k_cap = 2 * N + G + 64;
+  ALLOC(ws.scan_k, ws.scan_k_cap * 4);
+  ws.tmp_bytes = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
+  ws.tmp_bytes = std::max(ws.tmp_bytes, scan_tmp_bytes<int32_t>(N + 1));
+  ALLOC(ws.tmp, ws.tmp_bytes);
+  ALLOC(ws.ctl, sizeof(Ctl));
+#undef ALLOC
+  if (hipHostMalloc((void**)&ws.ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    ws.release();
+    return MC_ENOMEM;
+  }
+  ws.capN = N;
+  ws.capE = E;
+  ws.capG = G;
+  return MC_OK;
+}
+
+struct Problem {
+  int32_t G;
+  int32_t n;
+  int64_t nnz;
+  const int64_t* rp;
+  const int32_t* col;
+  const int32_t* w;
+  const int64_t* voff_host;
+};
+
+static int bitlen(uint64_t x) { return x == 0 ? 0 : 64 - __builtin_clzll(x); }
+
+struct Solver {
+  Workspace& ws;
+  hipStream_t s;
+  mc_options opt;
+  int num_cu = 256;
+
+  int read_ctl() {
+    MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipStreamSynchronize(s));
+    return MC_OK;
+  }
+
+  int solve(const Problem& P, int64_t* lambdas, uint8_t* side, mc_stats* st) {
+    const int32_t G = P.G;
+    const int32_t N = P.n;
+    const int64_t E = P.nnz;
+    const bool want_side = side != nullptr;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    MC_HIP(hipGetDevice(&dev));
+    MC_HIP(hipGetDeviceProperties(&prop, dev));
+    num_cu = prop.multiProcessorCount;
+    static bool attrs_set = false;
+    if (!attrs_set) {
+      MC_HIP(hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_L>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(ScanLds<WHOLE_CAP_L>)));
+      MC_HIP(hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_S>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(ScanLds<WHOLE_CAP_S>)));
+      attrs_set = true;
+    }
+
+    MC_HIP(hipMemcpyAsync(ws.voff, P.voff_host, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
+    GraphState S{ws.voff, ws.lhat, ws.gn, ws.cvoff, ws.nnew, ws.active, ws.bdeg, ws.balpha,
+                 ws.ucount, ws.rec_type, ws.rec_id, ws.rec_k, ws.fb_k, ws.mode, ws.whole,
+                 ws.fb_list, ws.wsum, ws.root0};
+    const int TB = 256;
+    auto grid = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 16)); };
+
+    // ---- ingest: validation, entry sources, weighted degrees, trivial bound
+    {
+      TimedScope t("ingest", (double)(N + 1) * 8 + (double)E * 12 + (double)E * 4 + N * 8);
+      hipLaunchKernelGGL(k_check_rowptr, grid(N), dim3(TB), 0, s, N, E, P.rp, ws.ctl);
+    }
+    int rc = read_ctl();
+    if (rc) return rc;
+    if (ws.ctl_host->err) return MC_EINVAL;
+    int32_t* gid = ws.gid[0];
+    int32_t* gid_next = ws.gid[1];
+    {
+      TimedScope t("ingest", (double)E * 12 + (double)N * 24);
+      hipLaunchKernelGGL(k_init_vertices, grid(N), dim3(TB), 0, s, N, ws.voff, G, gid, ws.ogid, ws.map);
+      fill<int64_t>(ws.cdeg, 0, N, s);
+      hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + 64 * INGEST_STEPS - 1) / (64 * INGEST_STEPS) * 64, TB, num_cu * 16)),
+                         dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, ws.src, ws.cdeg, ws.ctl);
+      fill<uint64_t>(ws.bdeg, ~0ull, G, s);
+      fill<int64_t>(ws.wsum, 0, G, s);
+      hipLaunchKernelGGL(k_min_degree, grid(N), dim3(TB), 0, s, N, ws.cdeg, gid, (const int32_t*)nullptr,
+                         ws.bdeg, ws.wsum);
+    }
+    // every col must lie inside its graph before any kernel indexes by it
+    rc = read_ctl();
+    if (rc) return rc;
+    if (ws.ctl_host->err) return MC_EINVAL;
+    {
+      TimedScope t("connectivity", (double)E * 8 + (double)N * 16);
+      hipLaunchKernelGGL(k_iota, grid(N), dim3(TB), 0, s, ws.parent, N);
+      hipLaunchKernelGGL(k_union_all_edges, grid(E), dim3(TB), 0, s, E, ws.src, P.col, ws.parent);
+      hipLaunchKernelGGL(k_flatten, grid(N), dim3(TB), 0, s, N, ws.parent);
+      fill<int32_t>(ws.nnew, 0, G, s);
+      hipLaunchKernelGGL(k_count_roots, grid(N), dim3(TB), 0, s, N, ws.parent, gid, ws.nnew);
+    }
+    hipLaunchKernelGGL(k_graph_init, grid(G), dim3(TB), 0, s, G, S, ws.root0, ws.parent, ws.ctl);
+    if (want_side) {
+      TimedScope t("side", (double)N * 13);
+      SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
+                  ws.fb_step, ws.parent, ws.root0, side, REC_DEG};
+      hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
+      sa.want = REC_DISCONNECTED;
+      hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
+    }
+    rc = read_ctl();
+    if (rc) return rc;
+    if (ws.ctl_host->err == -3) return MC_EOVERFLOW;
+    if (ws.ctl_host->err) return MC_EINVAL;
+    if (st) {
+      std::vector<int64_t> l0(G);
+      MC_HIP(hipMemcpy(l0.data(), ws.lhat, G * sizeof(int64_t), hipMemcpyDeviceToHost));
+      st->lambda_initial = l0[0];
+      st->lambda_viecut = -1;
+    }
+
+    // ---- the contraction loop
+    int32_t n = N;
+    int64_t nnz = E;
+    const int64_t* rp = P.rp;
+    const int32_t* col = P.col;
+    const int32_t* w = P.w;
+    int32_t n_active = ws.ctl_host->n_active;
+    int round = 0;
+    const int32_t whole_max = opt.whole_max > 0 ? opt.whole_max : (WHOLE_CAP_L * 3) / 4;
+    const int32_t whole_small = std::min(whole_max, (WHOLE_CAP_S * 3) / 4);
+    int region_waves = opt.region_waves > 0 ? opt.region_waves : num_cu * 16;
+    uint64_t seed = opt.seed ? opt.seed : 0x5EEDull;
+    while (n_active > 0 && (opt.max_rounds <= 0 || round < opt.max_rounds)) {
+      if (st && round < 64) { st->n_round[round] = n; st->nnz_round[round] = nnz; }
+      ++round;
+      // per-round control fields
+      MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
+      // plan: whole-graph scans for small graphs (two map sizes), region scans otherwise
+      hipLaunchKernelGGL(k_plan_split, grid(G), dim3(TB), 0, s, G, S, whole_small, whole_max,
+                         ws.whole2, ws.ctl);
+      hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
+      fill<int32_t>(ws.claim, -1, n, s);
+      if (opt.use_pr) {
+        TimedScope t("pr", (double)nnz * 8 + (double)nnz * 16 + (double)n * 16);
+        hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
+                           ws.lhat, ws.mode, ws.parent, ws.ucount, ws.ctl);
+      }
+      // scans
+      ScanArgs A{};
+      A.n = n; A.rp = rp; A.col = col; A.w = w; A.cdeg = ws.cdeg; A.gid = gid;
+      A.lhat = ws.lhat; A.gn = ws.gn; A.gvoff = ws.cvoff; A.gmode = ws.mode;
+      A.claim = ws.claim; A.step = ws.step; A.pairs = ws.keys_alt; A.pairs_cap = ws.capE;
+      A.best_alpha = ws.balpha; A.scan_k = ws.scan_k; A.scan_k_cap = (int32_t)std::min<int64_t>(ws.scan_k_cap, INT32_MAX);
+      A.ucount = ws.ucount; A.ctl = ws.ctl;
+      A.eager = opt.eager_blacklist;
+      A.max_pops = opt.max_pops > 0 ? opt.max_pops : INT32_MAX;
+      uint64_t rs = seed + 0x9E3779B97F4A7C15ull * (uint64_t)round;
+      rs ^= rs >> 31;
+      rs *= 0xBF58476D1CE4E5B9ull;
+      A.seed = rs;
+      A.perm_bits = std::max(1, bitlen((uint64_t)n - 1));
+      A.perm_a = (rs | 1ull) & ((1ull << A.perm_bits) - 1);
+      if (A.perm_a == 0) A.perm_a = 1;
+      A.perm_b = (rs >> 17) & ((1ull << A.perm_bits) - 1);
+      {
+        TimedScope t("capforest", (double)nnz * 8 + (double)n * 40);
+        if (!opt.force_fallback) {
+          A.whole_mode = 0;
+          A.whole = ws.whole;
+          A.whole_count = &ws.ctl->n_region;  // unused in region mode
+          const int wpb = 4;
+          size_t lds = sizeof(ScanLds<REGION_CAP>) * wpb;
+          int blocks = std::max(1, region_waves / wpb);
+          hipLaunchKernelGGL(k_capforest<REGION_CAP>, dim3(blocks), dim3(64 * wpb), lds, s, A);
+        }
+        // whole-graph scans: small map, then large map
+        MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
+        A.whole_mode = 1;
+        A.whole = ws.whole;
+        A.whole_count = &ws.ctl->n_whole;
+        hipLaunchKernelGGL(k_capforest<WHOLE_CAP_S>, dim3(num_cu * 4), dim3(64),
+                           sizeof(ScanLds<WHOLE_CAP_S>), s, A);
+        MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
+        A.whole = ws.whole2;
+        A.whole_count = &ws.ctl->n_whole2;
+        hipLaunchKernelGGL(k_capforest<WHOLE_CAP_L>, dim3(num_cu * 2), dim3(64),
+                           sizeof(ScanLds<WHOLE_CAP_L>), s, A);
+      }
+      {
+        TimedScope t("union", (double)n * 8);
+        hipLaunchKernelGGL(k_union_pairs, grid(n), dim3(TB), 0, s, ws.keys_alt, ws.ctl, ws.capE, ws.parent);
+      }
+      hipLaunchKernelGGL(k_fallback_list, grid(G), dim3(TB), 0, s, G, S, ws.ctl);
+      rc = read_ctl();
+      if (rc) return rc;
+      if (st) {
+        st->unions_pr += ws.ctl_host->unions_pr;
+        st->scans += ws.ctl_host->scan_ids;
+        st->pops += ws.ctl_host->pops;
+        st->overflows += ws.ctl_host->overflows;
+      }
+      if (ws.ctl_host->n_fallback > 0) {
+        // region pairs are united already; the fallback's pairs start afresh
+        MC_HIP(hipMemsetAsync(&ws.ctl->pairs, 0, sizeof(int64_t), s));
+        TimedScope t("fallback", (double)nnz * 8);
+        FallbackArgs F{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.fb_list,
+                       ws.ctl_host->n_fallback, ws.fb_r, ws.fb_st, ws.fb_step, ws.keys_alt,
+                       ws.capE, ws.balpha, ws.fb_k, ws.ucount, ws.ctl};
+        hipLaunchKernelGGL(k_capforest_fallback, dim3(std::min(ws.ctl_host->n_fallback, num_cu * 4)),
+                           dim3(64), 0, s, F);
+        hipLaunchKernelGGL(k_union_pairs, grid(n), dim3(TB), 0, s, ws.keys_alt, ws.ctl, ws.capE, ws.parent);
+        if (st) st->fallbacks += ws.ctl_host->n_fallback;
+      }
+      // union-find finish and block numbering
+      {
+        TimedScope t("compact", (double)n * 24);
+        hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+        exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, ws.active}, n, ws.newid,
+                                          &ws.ctl->n_next, ws.tmp, s);
+        fill<int32_t>(ws.nnew, 0, G, s);
+        hipLaunchKernelGGL(k_relabel, grid(n), dim3(TB), 0, s, n, ws.parent, gid, ws.active,
+                           ws.newid, ws.lab, gid_next, ws.nnew);
+      }
+      hipLaunchKernelGGL(k_update_alpha, grid(G), dim3(TB), 0, s, G, S, ws.scan_k, ws.ctl);
+      if (want_side) {
+        TimedScope t("side", (double)N * 21);
+        SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
+                    ws.fb_step, ws.parent, ws.root0, side, REC_ALPHA};
+        hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
+      }
+      rc = read_ctl();
+      if (rc) return rc;
+      const int32_t n_next = ws.ctl_host->n_next;
+      if (st) st->pairs_scan += ws.ctl_host->pairs;
+      // contraction: emit, sort, merge, CSR
+      const int bb = std::max(1, bitlen((uint64_t)std::max(n_next, 1) - 1));
+      {
+        TimedScope t("emit", (double)nnz * 12 + (double)nnz * 8);
+        hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, num_cu * 8)), dim3(TB), 0,
+                           s, nnz, ws.src, col, w, ws.lab, bb, ws.keys, ws.vals, ws.ctl);
+      }
+      rc = read_ctl();
+      if (rc) return rc;
+      const int64_t m = ws.ctl_host->emit;
+      int which = 0;
+      {
+        TimedScope t("sort", (double)m * 12 * 2);
+        which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s);
+      }
+      uint64_t* sk = which ? ws.keys_alt : ws.keys;
+      int32_t* sv = which ? ws.vals_alt : ws.vals;
+      int64_t* pos = (int64_t*)(which ? ws.keys : ws.keys_alt);
+      {
+        TimedScope t("merge", (double)m * 12 + (double)m * 8);
+        exclusive_scan<int64_t, HeadFlag>(HeadFlag{sk}, m, pos, (int64_t*)&ws.ctl->unique, ws.tmp, s);
+      }
+      rc = read_ctl();
+      if (rc) return rc;
+      const int64_t m2 = m > 0 ? ws.ctl_host->unique : 0;
+      {
+        TimedScope t("merge", (double)m * 20 + (double)m2 * 12);
+        fill<int32_t>(ws.w, 0, m2, s);
+        if (m > 0)
+          hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s,
+                             m, sk, sv, pos, bb, ws.src, ws.col, ws.w);
+      }
+      {
+        TimedScope t("csr", (double)m2 * 12 + (double)n_next * 16);
+        hipLaunchKernelGGL(k_rowptr, grid(n_next + 1), dim3(TB), 0, s, n_next, m2, ws.src, ws.rp);
+        fill<int64_t>(ws.cdeg, 0, n_next, s);
+        if (m2 > 0)
+          hipLaunchKernelGGL(k_degrees, dim3(grid_for((m2 + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0,
+                             s, m2, ws.src, ws.w, ws.cdeg);
+        hipLaunchKernelGGL(k_min_degree, grid(n_next), dim3(TB), 0, s, n_next, ws.cdeg, gid_next,
+                           (const int32_t*)nullptr, ws.bdeg, (int64_t*)nullptr);
+      }
+      exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff,
+                                                (int32_t*)nullptr, ws.tmp, s);
+      hipLaunchKernelGGL(k_compose_map, grid(N), dim3(TB), 0, s, N, ws.map, ws.lab);
+      MC_HIP(hipMemsetAsync(&ws.ctl->n_active, 0, sizeof(int32_t), s));
+      hipLaunchKernelGGL(k_finish_round, grid(G), dim3(TB), 0, s, G, S, ws.nvoff, ws.ctl);
+      if (want_side) {
+        TimedScope t("side", (double)N * 9);
+        SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
+                    ws.fb_step, ws.parent, ws.root0, side, REC_DEG};
+        hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
+      }
+      rc = read_ctl();
+      if (rc) return rc;
+      // every active graph contracts at least one edge per round (a whole
+      // scan or the fallback guarantees a contractible pair)
+      if (n_next >= n && n_active > 0) return MC_EINTERNAL;
+      n_active = ws.ctl_host->n_active;
+      std::swap(gid, gid_next);
+      n = n_next;
+      nnz = m2;
+      rp = ws.rp;
+      col = ws.col;
+      w = ws.w;
+      MC_HIP(hipGetLastError());
+    }
+    if (st) st->rounds = round;
+    if (want_side) {
+      hipLaunchKernelGGL(k_normalize_side, grid(G), dim3(TB), 0, s, G, ws.voff, side, ws.flip);
+      hipLaunchKernelGGL(k_apply_flip, grid(N), dim3(TB), 0, s, N, ws.ogid, ws.flip, side);
+    }
+    MC_HIP(hipMemcpyAsync(lambdas, ws.lhat, G * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipStreamSynchronize(s));
+    MC_HIP(hipGetLastError());
+    return MC_OK;
+  }
+};
+
+std::mutex& api_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+Workspace& global_ws() {
+  static Workspace ws;
+  return ws;
+}
+
+int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
+        mc_stats* st) {
+  if (!lambdas || !P.rp || !P.col || !P.w || P.G < 1 || P.n < 2 || P.nnz < 0) return MC_EINVAL;
+  if (P.n > (1 << 30) - 1 || P.nnz >= (int64_t)UINT32_MAX) return MC_EINVAL;
+  for (int32_t g = 0; g < P.G; ++g) {
+    if (P.voff_host[g + 1] < P.voff_host[g]) return MC_EINVAL;
+    if (P.voff_host[g + 1] - P.voff_host[g] < 2) return MC_ENOCUT;
+  }
+  if (P.voff_host[0] != 0 || P.voff_host[P.G] != P.n) return MC_EINVAL;
+  std::lock_guard<std::mutex> lock(api_mutex());
+  auto t0 = std::chrono::steady_clock::now();
+  mc_options o;
+  mc_options_default(&o);
+  if (opt) o = *opt;
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+  }
+  Workspace& ws = global_ws();
+  int rc = ensure(ws, P.n, P.nnz, P.G);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Timer& T = timer();
+  T.on = o.timing != 0;
+  T.s = s;
+  Solver sv{ws, s, o};
+  rc = sv.solve(P, lambdas, side, st);
+  if (T.on) T.collect();
+  T.on = false;
+  if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // namespace mc
+
+extern "C" {
+
+void mc_options_default(mc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->seed = 0x5EED;
+  o->use_pr = 1;
+  o->use_viecut = 0;
+  o->eager_blacklist = 1;
+  o->lp_sweeps = 2;
+}
+
+int mc_mincut(const mc_graph* g, void* stream, const mc_options* opt, int64_t* lambda,
+              uint8_t* side, mc_stats* stats) {
+  if (!g || !lambda) return MC_EINVAL;
+  if (g->n < 2) return MC_ENOCUT;
+  int64_t voff[2] = {0, g->n};
+  mc::Problem P{1, g->n, g->nnz, g->row_ptr, g->col, g->w, voff};
+  return mc::run(P, stream, opt, lambda, side, stats);
+}
+
+int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, int64_t* lambdas,
+                      uint8_t* sides, mc_stats* stats) {
+  if (!b || !lambdas || !b->vtx_off || b->num_graphs < 1) return MC_EINVAL;
+  mc::Problem P{b->num_graphs, b->n_total, b->nnz_total, b->row_ptr, b->col, b->w, b->vtx_off};
+  return mc::run(P, stream, opt, lambdas, sides, stats);
+}
+
+size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs) {
+  return mc::workspace_bytes(n_total, nnz_total, num_graphs);
+}
+
+void mc_release(void) {
+  std::lock_guard<std::mutex> lock(mc::api_mutex());
+  mc::global_ws().release();
+}
+
+const char* mc_strerror(int code) {
+  switch (code) {
+    case MC_OK: return "ok";
+    case MC_EINVAL: return "invalid argument or malformed graph";
+    case MC_ENOCUT: return "a graph with fewer than two vertices has no cut";
+    case MC_EOVERFLOW: return "total edge weight exceeds 2*(2^31-1)";
+    case MC_ENOMEM: return "device memory allocation failed";
+    case MC_EHIP: return "HIP runtime error";
+    case MC_EBUSY: return "server admission queue full";
+    case MC_ESTATE: return "unknown ticket or stopped server";
+    case MC_EINTERNAL: return "internal error: a round made no progress";
+    default: return "unknown error";
+  }
+}
+
+int mc_timing_get(mc_timing_entry* out, int max) {
+  auto& T = mc::timer();
+  int n = (int)T.classes.size();
+  for (int i = 0; i < n && i < max; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::strncpy(out[i].name, T.classes[i].name.c_str(), sizeof(out[i].name) - 1);
+    out[i].launches = T.classes[i].launches;
+    out[i].ms = T.classes[i].ms;
+    out[i].algo_bytes = T.classes[i].bytes;
+  }
+  return n;
+}
+
+void mc_timing_reset(void) { mc::timer().classes.clear(); }
+
+}  // extern "C"

@@ -1,0 +1,500 @@
+// Per-round kernels of the bound-driven contraction loop (Algorithm 2):
+// ingest and trivial bound, Padberg-Rinaldi tests, union-find passes,
+// block numbering, contraction by sort + merge, bound updates and side
+// materialisation.  Many graphs may be packed into one CSR; every graph
+// keeps a contiguous vertex range and its own bound lambda-hat.
+#pragma once
+#include "capforest.h"
+#include "prims.h"
+
+namespace mc {
+
+enum : int32_t { REC_NONE = 0, REC_ALPHA = 1, REC_DEG = 2, REC_DISCONNECTED = 3 };
+
+struct GraphState {  // per-graph device arrays
+  const int64_t* voff;  // original vertex offsets [G+1]
+  int64_t* lhat;        // best bound found so far (a real cut)
+  int32_t* n;           // current vertex count
+  int32_t* cvoff;       // current first vertex
+  int32_t* nnew;        // vertex count after this round's compaction
+  int32_t* active;
+  uint64_t* bdeg;       // (weighted degree << 32) | vertex, min over the graph
+  uint64_t* balpha;     // (alpha << 32) | scan id
+  int32_t* ucount;      // contractible pairs found this round
+  int32_t* rec_type;    // improvement this step
+  int32_t* rec_id;
+  int32_t* rec_k;
+  int32_t* fb_k;
+  uint8_t* mode;
+  int32_t* whole;       // list of whole-scan graphs
+  int32_t* fb_list;
+  int64_t* wsum;
+  int32_t* root0;       // component root of the graph's first vertex
+};
+
+// Segmented sum of `val` over runs of equal `key` within the wave (lanes in
+// order).  Returns the run total in the run's last lane; tail = last lane.
+template <typename K, typename V>
+__device__ __forceinline__ V wave_segsum(K key, V val, bool valid, bool& tail) {
+  const int lane = lane_id();
+  K prev = __shfl_up(key, 1, 64);
+  bool head = lane == 0 || prev != key;
+  int start = head ? lane : 0;
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(start, o, 64);
+    if (lane >= o && t > start) start = t;
+  }
+  V x = valid ? val : (V)0;
+  for (int o = 1; o < 64; o <<= 1) {
+    V t = __shfl_up(x, o, 64);
+    if (lane - o >= start) x += t;
+  }
+  K next = __shfl_down(key, 1, 64);
+  tail = lane == 63 || next != key;
+  return x;
+}
+
+// ------------------------------------------------------------------ ingest
+__global__ void k_check_rowptr(int32_t n, int64_t nnz, const int64_t* rp, Ctl* ctl) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    if (rp[v] > rp[v + 1]) atomicExch(&ctl->err, -1);
+  }
+  if (gtid() == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicExch(&ctl->err, -1);
+}
+
+// gid per vertex from the graph offsets; original-vertex map starts as id.
+__global__ void k_init_vertices(int32_t n, const int64_t* voff, int32_t G, int32_t* gid,
+                                int32_t* ogid, int32_t* map) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    int32_t lo = 0, hi = G;  // find g with voff[g] <= v < voff[g+1]
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if (voff[mid] <= v) lo = mid; else hi = mid;
+    }
+    gid[v] = lo;
+    ogid[v] = lo;
+    map[v] = (int32_t)v;
+  }
+}
+
+// Entry source ids, validation, and weighted degrees (self-loops excluded;
+// they never cross a cut).  Each wave walks 64 consecutive entries per step.
+constexpr int INGEST_STEPS = 16;
+__global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col,
+                                                const int32_t* __restrict__ w,
+                                                const int32_t* __restrict__ gid,
+                                                const int64_t* __restrict__ voff,
+                                                int32_t* __restrict__ src, int64_t* cdeg, Ctl* ctl) {
+  const int lane = lane_id();
+  const int64_t wave_global = gtid() >> 6;
+  const int64_t nwaves = gstride() >> 6;
+  for (int64_t chunk = wave_global; chunk * 64 * INGEST_STEPS < nnz; chunk += nwaves) {
+    int64_t e = chunk * 64 * INGEST_STEPS + lane;
+    // row of the first entry: upper_bound(rp, e) - 1
+    int32_t r = 0;
+    if (e < nnz) {
+      int32_t lo = 0, hi = n;  // rp[lo] <= e < rp[hi]
+      while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= e) lo = mid; else hi = mid;
+      }
+      r = lo;
+    }
+    for (int s = 0; s < INGEST_STEPS; ++s, e += 64) {
+      bool ok = e < nnz;
+      if (ok) while (rp[r + 1] <= e) ++r;
+      int32_t y = ok ? col[e] : 0;
+      int32_t c = ok ? w[e] : 0;
+      if (ok) {
+        src[e] = r;
+        int32_t g = gid[r];
+        if (y < voff[g] || y >= voff[g + 1] || c < 1) atomicExch(&ctl->err, -1);
+      }
+      int64_t val = (ok && y != r) ? (int64_t)c : 0;
+      bool tail;
+      int64_t sum = wave_segsum<int32_t, int64_t>(ok ? r : -1, val, ok, tail);
+      if (ok && tail && sum) atomicAdd((unsigned long long*)(cdeg + r), (unsigned long long)sum);
+    }
+  }
+}
+
+// Per-graph minimum weighted degree (the trivial cut, section "Basic
+// Concepts") and weight totals.
+__global__ void k_min_degree(int32_t n, const int64_t* cdeg, const int32_t* gid,
+                             const int32_t* active, uint64_t* bdeg, int64_t* wsum) {
+  for (int64_t v = gtid(); v - threadIdx.x % 64 < n; v += gstride()) {
+    bool ok = v < n;
+    int32_t g = ok ? gid[v] : -1;
+    if (ok && active && !active[g]) ok = false;
+    uint64_t key = ok ? (((uint64_t)cdeg[v] << 32) | (uint32_t)v) : ~0ull;
+    int32_t g0 = shfl(g, 0);
+    bool uniform = ballot(ok && g == g0) == ballot(ok) && ballot(ok) != 0;
+    if (uniform) {
+      uint64_t m = wave_min_u64(key);
+      int64_t s = wave_sum_i64(ok ? cdeg[v] : 0);
+      if (lane_id() == 0) {
+        atomic_min_u64(bdeg + g0, m);
+        if (wsum) atomicAdd((unsigned long long*)(wsum + g0), (unsigned long long)s);
+      }
+    } else if (ok) {
+      atomic_min_u64(bdeg + g, key);
+      if (wsum) atomicAdd((unsigned long long*)(wsum + g), (unsigned long long)cdeg[v]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ union-find
+__global__ void k_iota(int32_t* p, int32_t n) {
+  for (int64_t v = gtid(); v < n; v += gstride()) p[v] = (int32_t)v;
+}
+
+__global__ void k_union_all_edges(int64_t nnz, const int32_t* src, const int32_t* col, int32_t* parent) {
+  for (int64_t e = gtid(); e < nnz; e += gstride()) {
+    int32_t u = src[e], v = col[e];
+    if (u < v) uf_union(parent, u, v);
+  }
+}
+
+__global__ void k_flatten(int32_t n, int32_t* parent) {
+  for (int64_t v = gtid(); v < n; v += gstride()) parent[v] = uf_find(parent, (int32_t)v);
+}
+
+__global__ void k_union_pairs(const uint64_t* pairs, const Ctl* ctl, int64_t cap, int32_t* parent) {
+  int64_t np = ctl->pairs < cap ? ctl->pairs : cap;
+  for (int64_t i = gtid(); i < np; i += gstride()) {
+    uint64_t p = pairs[i];
+    uf_union(parent, (int32_t)(p >> 32), (int32_t)(uint32_t)p);
+  }
+}
+
+// Components per graph: disconnected graphs get lambda = 0 (section "Parallel
+// CAPFOREST": a disconnected graph leaves vertices unvisited).
+__global__ void k_count_roots(int32_t n, const int32_t* parent, const int32_t* gid, int32_t* cnt) {
+  for (int64_t v = gtid(); v < n; v += gstride())
+    if (parent[v] == v) atomicAdd(cnt + gid[v], 1);
+}
+
+// ----------------------------------------------------- per-graph bookkeeping
+__global__ void k_graph_init(int32_t G, GraphState S, int32_t* root0, const int32_t* parent, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    int32_t ng = (int32_t)(S.voff[g + 1] - S.voff[g]);
+    S.n[g] = ng;
+    S.cvoff[g] = (int32_t)S.voff[g];
+    uint64_t bd = S.bdeg[g];
+    int64_t lam = (int64_t)(bd >> 32);
+    S.lhat[g] = lam;
+    S.rec_type[g] = REC_DEG;
+    S.rec_id[g] = (int32_t)(uint32_t)bd;
+    S.rec_k[g] = 0;
+    if (S.wsum[g] > 2ll * 2147483647ll) atomicExch(&ctl->err, -3);
+    if (S.nnew[g] > 1) {  // more than one component
+      S.lhat[g] = 0;
+      S.rec_type[g] = REC_DISCONNECTED;
+      root0[g] = parent[S.voff[g]];
+      S.active[g] = 0;
+    } else {
+      S.active[g] = ng > 2 ? 1 : 0;
+    }
+    if (S.active[g]) atomicAdd(&ctl->n_active, 1);
+  }
+}
+
+// side[v] for graphs whose bound improved at this step.
+struct SideArgs {
+  int32_t n0;
+  const int32_t* ogid;
+  const int32_t* map;       // original -> current vertex (before this round's relabel for ALPHA)
+  const int32_t* rec_type;
+  const int32_t* rec_id;
+  const int32_t* rec_k;
+  const int32_t* claim;
+  const int32_t* step;
+  const int32_t* fb_step;
+  const int32_t* parent;    // for REC_DISCONNECTED
+  const int32_t* root0;
+  uint8_t* side;
+  int32_t want;             // record type this pass materialises
+};
+
+__global__ void k_side(SideArgs A) {
+  for (int64_t v = gtid(); v < A.n0; v += gstride()) {
+    int32_t g = A.ogid[v];
+    int32_t t = A.rec_type[g];
+    if (t != A.want) continue;
+    int32_t c = A.map[v];
+    uint8_t s = 0;
+    if (t == REC_DEG) {
+      s = c == A.rec_id[g];
+    } else if (t == REC_ALPHA) {
+      int32_t sid = A.rec_id[g], k = A.rec_k[g];
+      if (sid == FALLBACK_SID) s = A.fb_step[c] >= 1 && A.fb_step[c] <= k;
+      else s = A.claim[c] == sid && A.step[c] <= k;
+    } else if (t == REC_DISCONNECTED) {
+      s = A.parent[v] != A.root0[g];
+    }
+    A.side[v] = s;
+  }
+}
+
+// Round planning: graphs up to whole_small vertices are scanned whole with
+// the small LDS map (mode 1), up to whole_max with the large map (mode 3),
+// larger ones by region scans (mode 2).  Inactive graphs idle (mode 0).
+__global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32_t whole_max,
+                             int32_t* whole2, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    S.ucount[g] = 0;
+    S.balpha[g] = ~0ull;
+    S.bdeg[g] = ~0ull;
+    S.rec_type[g] = REC_NONE;
+    S.nnew[g] = 0;
+    uint8_t m = 0;
+    if (S.active[g]) {
+      if (S.n[g] <= whole_small) {
+        m = 1;
+        S.whole[atomicAdd(&ctl->n_whole, 1)] = (int32_t)g;
+      } else if (S.n[g] <= whole_max) {
+        m = 3;
+        whole2[atomicAdd(&ctl->n_whole2, 1)] = (int32_t)g;
+      } else {
+        m = 2;
+        atomicAdd(&ctl->n_region, 1);
+      }
+    }
+    S.mode[g] = m;
+  }
+}
+
+// ------------------------------------------------------- Padberg-Rinaldi
+// For e = (u, v), u < v: PR1 w >= lambda-hat, or PR2 2w > c(u) or
+// 2w > c(v) (strict).  Both keep every minimum cut when lambda-hat <= the
+// minimum degree (sections "Related Work" and "Inexact Shared-Memory
+// Minimum Cuts" name the tests; the conditions are restated here).
+__global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t* __restrict__ col,
+                     const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
+                     const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
+                     const uint8_t* __restrict__ mode, int32_t* parent, int32_t* ucount, Ctl* ctl) {
+  int64_t local = 0;
+  for (int64_t e = gtid(); e < nnz; e += gstride()) {
+    int32_t u = src[e], v = col[e];
+    if (u >= v) continue;
+    int32_t g = gid[u];
+    if (!mode[g]) continue;
+    int64_t c = w[e];
+    if (c >= lhat[g] || 2 * c > cdeg[u] || 2 * c > cdeg[v]) {
+      uf_union(parent, u, v);
+      atomicAdd(ucount + g, 1);
+      ++local;
+    }
+  }
+  if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
+}
+
+__global__ void k_fallback_list(int32_t G, GraphState S, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride())
+    if (S.mode[g] == 2 && S.ucount[g] == 0) {
+      int32_t i = atomicAdd(&ctl->n_fallback, 1);
+      S.fb_list[i] = (int32_t)g;
+    }
+}
+
+// ------------------------------------------------------------ compaction
+// Block ids: every union-find root of a graph that stays in play gets a new
+// id in [0, n'), in vertex order, so each graph's range stays contiguous.
+struct RootFlag {
+  const int32_t* parent;
+  const int32_t* gid;
+  const int32_t* keep;  // per graph
+  __device__ __forceinline__ int32_t operator()(int64_t v) const {
+    return (parent[v] == v && keep[gid[v]]) ? 1 : 0;
+  }
+};
+
+__global__ void k_relabel(int32_t n, const int32_t* parent, const int32_t* gid, const int32_t* keep,
+                          const int32_t* newid, int32_t* lab, int32_t* ngid, int32_t* nnew) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    int32_t g = gid[v];
+    int32_t r = parent[v];
+    if (!keep[g]) { lab[v] = -1; continue; }
+    lab[v] = newid[r];
+    if (r == v) { ngid[newid[v]] = g; atomicAdd(nnew + g, 1); }
+  }
+}
+
+// Bound update from the scans' best prefix cut alpha (section "Parallel
+// CAPFOREST": lambda-hat <- min(lambda-hat, alpha)).
+__global__ void k_update_alpha(int32_t G, GraphState S, const int32_t* scan_k, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    uint64_t b = S.balpha[g];
+    if (b == ~0ull || !S.mode[g]) continue;
+    int64_t a = (int64_t)(b >> 32);
+    if (a < S.lhat[g]) {
+      int32_t sid = (int32_t)(uint32_t)b;
+      S.lhat[g] = a;
+      S.rec_type[g] = REC_ALPHA;
+      S.rec_id[g] = sid;
+      S.rec_k[g] = sid == FALLBACK_SID ? S.fb_k[g] : scan_k[sid];
+      atomicAdd(&ctl->improved, 1);
+    }
+  }
+}
+
+// ----------------------------------------------------------- contraction
+// Emit (lab[u] << bits | lab[v], w) for every entry whose ends lie in
+// different blocks (internal edges vanish; section "Basic Concepts",
+// contraction G/(u,v)).  Workgroup-aggregated compaction.
+__global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __restrict__ src,
+                                              const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ w,
+                                              const int32_t* __restrict__ lab, int bits,
+                                              uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                              Ctl* ctl) {
+  __shared__ uint32_t wcnt[4];
+  __shared__ unsigned long long base_s;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int64_t tile = 256 * 8;
+  for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nnz; t0 += (int64_t)gridDim.x * tile) {
+    uint64_t k[8];
+    int32_t vv[8];
+    uint64_t msk[8];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      int64_t e = t0 + (int64_t)wave * 512 + r * 64 + lane;
+      bool ok = e < nnz;
+      int32_t a = ok ? lab[src[e]] : -1;
+      int32_t b = ok ? lab[col[e]] : -1;
+      ok = ok && a >= 0 && b >= 0 && a != b;
+      k[r] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
+      vv[r] = ok ? w[e] : 0;
+      msk[r] = ballot(ok);
+      mine += ok ? 1u : 0u;
+    }
+    uint32_t wtot = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) wtot += popc64(msk[r]);
+    if (lane == 0) wcnt[wave] = wtot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t s = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      base_s = s ? atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)s) : 0;
+    }
+    __syncthreads();
+    uint64_t o = base_s;
+    for (int i = 0; i < wave; ++i) o += wcnt[i];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      bool ok = (msk[r] >> lane) & 1;
+      if (ok) {
+        uint64_t at = o + popc64(msk[r] & lanemask_lt());
+        keys[at] = k[r];
+        vals[at] = vv[r];
+      }
+      o += popc64(msk[r]);
+    }
+    __syncthreads();
+    (void)mine;
+  }
+}
+
+struct HeadFlag {
+  const uint64_t* keys;
+  __device__ __forceinline__ int64_t operator()(int64_t i) const {
+    return (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+  }
+};
+
+// Merge runs of equal (a, b) keys: new entry index = number of run heads
+// before i; weights summed (wave-segmented, then one atomic per run piece).
+__global__ void __launch_bounds__(256) k_merge(int64_t m, const uint64_t* __restrict__ keys,
+                                               const int32_t* __restrict__ vals,
+                                               const int64_t* __restrict__ pos, int bits,
+                                               int32_t* nsrc, int32_t* ncol, int32_t* nw) {
+  const uint64_t mask = (1ull << bits) - 1;
+  for (int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); base < m;
+       base += (int64_t)gridDim.x * 256) {
+    int64_t i = base + lane_id();
+    bool ok = i < m;
+    uint64_t key = ok ? keys[i] : ~0ull;
+    int64_t p = ok ? pos[i] : -1;
+    bool head = ok && (i == 0 || keys[i - 1] != key);
+    if (head) {
+      nsrc[p] = (int32_t)(key >> bits);
+      ncol[p] = (int32_t)(key & mask);
+    }
+    bool tail;
+    int32_t s = wave_segsum<int64_t, int32_t>(p, ok ? vals[i] : 0, ok, tail);
+    if (ok && tail) atomicAdd(nw + p, s);
+  }
+}
+
+// row_ptr of the merged graph: rp[a] = first entry with source >= a.
+__global__ void k_rowptr(int32_t n, int64_t m, const int32_t* nsrc, int64_t* rp) {
+  for (int64_t a = gtid(); a <= n; a += gstride()) {
+    int64_t lo = 0, hi = m;  // first index with nsrc >= a
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (nsrc[mid] < a) lo = mid + 1; else hi = mid;
+    }
+    rp[a] = lo;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_degrees(int64_t m, const int32_t* __restrict__ nsrc,
+                                                 const int32_t* __restrict__ nw, int64_t* cdeg) {
+  for (int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); base < m;
+       base += (int64_t)gridDim.x * 256) {
+    int64_t i = base + lane_id();
+    bool ok = i < m;
+    int32_t a = ok ? nsrc[i] : -1;
+    bool tail;
+    int64_t s = wave_segsum<int32_t, int64_t>(a, ok ? (int64_t)nw[i] : 0, ok, tail);
+    if (ok && tail) atomicAdd((unsigned long long*)(cdeg + a), (unsigned long long)s);
+  }
+}
+
+// After contraction: new vertex counts and ranges, minimum degree bound of
+// the contracted graph (section "Parallel Graph Contraction"), activity.
+__global__ void k_finish_round(int32_t G, GraphState S, const int32_t* nvoff_scan, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    if (!S.mode[g]) {
+      if (S.active[g]) S.active[g] = 0;
+      S.n[g] = 0;
+      continue;
+    }
+    S.n[g] = S.nnew[g];
+    S.cvoff[g] = nvoff_scan[g];
+    if (S.nnew[g] >= 2) {
+      uint64_t bd = S.bdeg[g];
+      int64_t d = (int64_t)(bd >> 32);
+      if (bd != ~0ull && d < S.lhat[g]) {
+        S.lhat[g] = d;
+        S.rec_type[g] = REC_DEG;
+        S.rec_id[g] = (int32_t)(uint32_t)bd;
+        S.rec_k[g] = 0;
+        atomicAdd(&ctl->improved, 1);
+      }
+    }
+    int32_t act = (S.nnew[g] > 2 && S.lhat[g] > 0) ? 1 : 0;
+    S.active[g] = act;
+    if (act) atomicAdd(&ctl->n_active, 1);
+  }
+}
+
+__global__ void k_compose_map(int32_t n0, int32_t* map, const int32_t* lab) {
+  for (int64_t v = gtid(); v < n0; v += gstride()) {
+    int32_t c = map[v];
+    map[v] = c >= 0 ? lab[c] : -1;
+  }
+}
+
+__global__ void k_normalize_side(int32_t G, const int64_t* voff, uint8_t* side, int32_t* flip) {
+  for (int64_t g = gtid(); g < G; g += gstride()) flip[g] = side[voff[g]] ? 1 : 0;
+}
+
+__global__ void k_apply_flip(int32_t n0, const int32_t* ogid, const int32_t* flip, uint8_t* side) {
+  for (int64_t v = gtid(); v < n0; v += gstride())
+    if (flip[ogid[v]]) side[v] ^= 1;
+}
+
+}  // namespace mc

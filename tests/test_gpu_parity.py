@@ -1,0 +1,189 @@
+"""GPU parity: lambda from the HIP path equals the oracle's exactly (integer,
+tolerance 0), and every returned side is checked by recomputing its cut
+weight (sides are not unique, so identity is not compared)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import announce, check_side, random_graph, solve
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1808_05458_amd as mc
+    mc._load()
+    yield
+
+
+def test_closed_forms():
+    cases = [(gg.complete(8), 7), (gg.complete(12, 3), 33), (gg.two_cliques(10, 3), 3),
+             (gg.two_cliques(7, 7), 7), (gg.from_edges(2, [(0, 1), (0, 1)], [3, 4]), 7)]
+    cyc = gg.cycle(40, 5, 1, 30)
+    pe = np.sort(cyc.w[cyc.src() < cyc.col])
+    cases.append((cyc, int(pe[0] + pe[1])))
+    d = 6
+    cube = gg.from_edges(1 << d, [(v, v ^ (1 << i)) for v in range(1 << d) for i in range(d)
+                                  if v < v ^ (1 << i)])
+    cases.append((cube, d))
+    for g, expect in cases:
+        announce("closed form", g.name, g.n)
+        lam, side, _ = solve(g)
+        assert lam == expect, g.name
+        check_side(g, lam, side)
+
+
+def test_hand_examples():
+    spec = json.load(open(os.path.join(GOLDEN, "hand_examples.json")))
+    for ex in spec["graphs"]:
+        announce("hand", ex["name"])
+        e = np.array(ex["edges"])
+        g = gg.from_edges(ex["n"], e[:, :2], e[:, 2])
+        lam, side, _ = solve(g)
+        assert lam == ex["lambda"], ex["name"]
+        check_side(g, lam, side)
+
+
+def test_random_tiny_graphs_against_enumeration():
+    rng = np.random.default_rng(31)
+    for t in range(300):
+        n = int(rng.integers(2, 15))
+        g = random_graph(rng, n, float(rng.uniform(0.15, 1.0)), int(rng.choice([1, 4, 50])),
+                         connected=bool(rng.random() < 0.93))
+        if t % 50 == 0:
+            announce("tiny", t, n)
+        lam, side, _ = solve(g)
+        ref, _ = oracle.bruteforce(g)
+        assert lam == ref, (t, lam, ref)
+        check_side(g, lam, side)
+
+
+def test_medium_graphs_against_noi():
+    rng = np.random.default_rng(7)
+    for t in range(40):
+        n = int(rng.integers(30, 700))
+        g = random_graph(rng, n, float(rng.uniform(0.01, 0.2)), int(rng.choice([1, 3, 20])))
+        announce("medium", t, n, g.m)
+        lam, side, _ = solve(g)
+        ref, _, _ = oracle.noi(g, 2)
+        assert lam == ref, (t, lam, ref)
+        check_side(g, lam, side)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(use_pr=0), dict(eager_blacklist=0),
+                                  dict(force_fallback=1), dict(max_pops=3),
+                                  dict(whole_max=16), dict(whole_max=16, max_pops=5, use_pr=0)])
+def test_planted_4096_options(opts):
+    g = gg.planted_4096()
+    gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["planted_4096"]
+    assert g.n == gold["n"] and g.m == gold["m"]
+    announce("planted_4096", opts)
+    lam, side, st = solve(g, **opts)
+    assert lam == gold["lambda"]
+    check_side(g, lam, side)
+
+
+def test_region_scans_on_power_law_core():
+    # forces region scans (whole_max small) on a power-law k-core
+    g = gg.chung_lu(23, 20000, 2.5, 16.0, 1, 3, kcore=4, lcc=True)
+    ref, _, _ = oracle.noi(g, 1)
+    for opts in [dict(whole_max=64), dict(whole_max=64, eager_blacklist=0),
+                 dict(whole_max=64, max_pops=50), dict(whole_max=64, use_pr=0)]:
+        announce("chung_lu 20000", opts)
+        lam, side, st = solve(g, **opts)
+        assert lam == ref, opts
+        check_side(g, lam, side)
+
+
+def test_disconnected_and_edge_cases():
+    announce("disconnected")
+    g = gg.from_edges(9, [(0, 1), (1, 2), (2, 0), (3, 4), (4, 5), (5, 3), (6, 7), (7, 8), (8, 6)],
+                      [5] * 9)
+    lam, side, _ = solve(g)
+    assert lam == 0
+    check_side(g, lam, side)
+    announce("isolated vertex")
+    g = gg.from_edges(4, [(0, 1), (1, 2)], [2, 3])
+    lam, side, _ = solve(g)
+    assert lam == 0 and side[3] == 1
+    announce("self loops and repeated entries")
+    g = gg.from_edges(5, [(0, 1), (0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (2, 2), (3, 3)],
+                      [1, 1, 5, 5, 5, 5, 100, 7])
+    lam, side, _ = solve(g)
+    assert lam == oracle.bruteforce(g)[0]
+    check_side(g, lam, side)
+    announce("two vertices")
+    g = gg.from_edges(2, [(0, 1)], [9])
+    lam, side, _ = solve(g)
+    assert lam == 9 and list(side) == [0, 1]
+
+
+def test_invalid_inputs_are_rejected():
+    import torch
+    import paper_1808_05458_amd as mc
+    g = gg.complete(5)
+    rp, col, w = mc.to_device(g, "cuda")
+    bad = col.clone()
+    bad[3] = 99
+    announce("invalid col")
+    with pytest.raises(mc.MincutError) as e:
+        mc.mincut(rp, bad, w)
+    assert e.value.code == mc.MC_EINVAL
+    announce("zero weight")
+    w0 = w.clone()
+    w0[0] = 0
+    with pytest.raises(mc.MincutError) as e:
+        mc.mincut(rp, col, w0)
+    assert e.value.code == mc.MC_EINVAL
+    announce("bad row_ptr")
+    rpb = rp.clone()
+    rpb[2] = rpb[3] + 1
+    with pytest.raises(mc.MincutError) as e:
+        mc.mincut(rpb, col, w)
+    assert e.value.code == mc.MC_EINVAL
+    announce("one vertex")
+    with pytest.raises(mc.MincutError) as e:
+        mc.mincut(torch.zeros(2, dtype=torch.int64, device="cuda"),
+                  torch.zeros(0, dtype=torch.int32, device="cuda"),
+                  torch.zeros(0, dtype=torch.int32, device="cuda"))
+    assert e.value.code == mc.MC_ENOCUT
+    announce("overflow")
+    h = gg.from_edges(3, [(0, 1), (1, 2), (2, 0)], [1 << 30] * 3)
+    rp, col, w = mc.to_device(h, "cuda")
+    with pytest.raises(mc.MincutError) as e:
+        mc.mincut(rp, col, w)
+    assert e.value.code == mc.MC_EOVERFLOW
+    # the library still works after errors
+    lam, side, _ = solve(gg.complete(6))
+    assert lam == 5
+
+
+def test_batched_small_against_noi():
+    import torch
+    import paper_1808_05458_amd as mc
+    graphs = [gg.batch_graph(i) for i in range(24)]
+    graphs.append(gg.from_edges(6, [(0, 1), (1, 2), (3, 4), (4, 5)], [1, 1, 1, 1]))  # disconnected
+    graphs.append(gg.complete(3))
+    graphs.append(gg.from_edges(2, [(0, 1)], [17]))
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    announce("batched", len(graphs), packed.n, packed.m)
+    lams, sides, st = mc.mincut_batched(rp, col, w, vo)
+    s = sides.cpu().numpy()
+    for i, g in enumerate(graphs):
+        ref, _, _ = oracle.noi(g, 3)
+        assert lams[i] == ref, (i, lams[i], ref)
+        check_side(g, int(lams[i]), s[vo[i]:vo[i + 1]])
+    # each graph alone gives the same lambda
+    for i in (0, 5, 24, 26):
+        lam, _, _ = solve(graphs[i])
+        assert lam == lams[i]
