@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -265,6 +266,15 @@ struct Problem {
 
 static int bitlen(uint64_t x) { return x == 0 ? 0 : 64 - __builtin_clzll(x); }
 
+static bool debug_on() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("MC_DEBUG");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 struct Solver {
   Workspace& ws;
   hipStream_t s;
@@ -275,6 +285,39 @@ struct Solver {
     MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     MC_HIP(hipStreamSynchronize(s));
     return MC_OK;
+  }
+
+  void dump(const char* where, int32_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
+            const int32_t* w) {
+    if (!debug_on()) return;
+    hipStreamSynchronize(s);
+    int64_t lh = 0;
+    uint64_t ba = 0, bd = 0;
+    int32_t gn = 0;
+    hipMemcpy(&lh, ws.lhat, 8, hipMemcpyDeviceToHost);
+    hipMemcpy(&ba, ws.balpha, 8, hipMemcpyDeviceToHost);
+    hipMemcpy(&bd, ws.bdeg, 8, hipMemcpyDeviceToHost);
+    hipMemcpy(&gn, ws.gn, 4, hipMemcpyDeviceToHost);
+    Ctl c;
+    hipMemcpy(&c, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    fprintf(stderr, "[mc] %s n=%d nnz=%lld lhat0=%lld gn0=%d balpha=(%lld,%u) bdeg=(%lld,%u) "
+            "pairs=%lld pr=%lld scans=%d pops=%lld emit=%lld unique=%lld n_next=%d\n",
+            where, n, (long long)nnz, (long long)lh, gn, (long long)(ba >> 32), (unsigned)ba,
+            (long long)(bd >> 32), (unsigned)bd, (long long)c.pairs, (long long)c.unions_pr,
+            c.scan_ids, (long long)c.pops, (long long)c.emit, (long long)c.unique, c.n_next);
+    if (n <= 16 && nnz <= 256) {
+      std::vector<int64_t> hr(n + 1), cd(n);
+      std::vector<int32_t> hc(nnz), hw(nnz);
+      hipMemcpy(hr.data(), rp, (n + 1) * 8, hipMemcpyDeviceToHost);
+      hipMemcpy(hc.data(), col, nnz * 4, hipMemcpyDeviceToHost);
+      hipMemcpy(hw.data(), w, nnz * 4, hipMemcpyDeviceToHost);
+      hipMemcpy(cd.data(), ws.cdeg, n * 8, hipMemcpyDeviceToHost);
+      for (int v = 0; v < n; ++v) {
+        fprintf(stderr, "   v%d cdeg=%lld:", v, (long long)cd[v]);
+        for (int64_t e = hr[v]; e < hr[v + 1]; ++e) fprintf(stderr, " %d/%d", hc[e], hw[e]);
+        fprintf(stderr, "\n");
+      }
+    }
   }
 
   int solve(const Problem& P, int64_t* lambdas, uint8_t* side, mc_stats* st) {
@@ -367,6 +410,7 @@ struct Solver {
     const int32_t* w = P.w;
     int32_t n_active = ws.ctl_host->n_active;
     int round = 0;
+    dump("ingest", n, nnz, rp, col, w);
     const int32_t whole_max = opt.whole_max > 0 ? opt.whole_max : (WHOLE_CAP_L * 3) / 4;
     const int32_t whole_small = std::min(whole_max, (WHOLE_CAP_S * 3) / 4);
     int region_waves = opt.region_waves > 0 ? opt.region_waves : num_cu * 16;
@@ -471,6 +515,7 @@ struct Solver {
       }
       rc = read_ctl();
       if (rc) return rc;
+      dump("after-scans", n, nnz, rp, col, w);
       const int32_t n_next = ws.ctl_host->n_next;
       if (st) st->pairs_scan += ws.ctl_host->pairs;
       // contraction: emit, sort, merge, CSR
@@ -538,6 +583,7 @@ struct Solver {
       rp = ws.rp;
       col = ws.col;
       w = ws.w;
+      dump("contracted", n, nnz, rp, col, w);
       MC_HIP(hipGetLastError());
     }
     if (st) st->rounds = round;

@@ -292,7 +292,7 @@ __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t
 
 __global__ void k_fallback_list(int32_t G, GraphState S, Ctl* ctl) {
   for (int64_t g = gtid(); g < G; g += gstride())
-    if (S.mode[g] == 2 && S.ucount[g] == 0) {
+    if (S.mode[g] != 0 && S.ucount[g] == 0) {  // any scan kind may end early
       int32_t i = atomicAdd(&ctl->n_fallback, 1);
       S.fb_list[i] = (int32_t)g;
     }
@@ -405,7 +405,8 @@ struct HeadFlag {
 };
 
 // Merge runs of equal (a, b) keys: new entry index = number of run heads
-// before i; weights summed (wave-segmented, then one atomic per run piece).
+// up to and including i, minus one; weights summed (wave-segmented, then
+// one atomic per run piece).
 __global__ void __launch_bounds__(256) k_merge(int64_t m, const uint64_t* __restrict__ keys,
                                                const int32_t* __restrict__ vals,
                                                const int64_t* __restrict__ pos, int bits,
@@ -416,8 +417,10 @@ __global__ void __launch_bounds__(256) k_merge(int64_t m, const uint64_t* __rest
     int64_t i = base + lane_id();
     bool ok = i < m;
     uint64_t key = ok ? keys[i] : ~0ull;
-    int64_t p = ok ? pos[i] : -1;
     bool head = ok && (i == 0 || keys[i - 1] != key);
+    // pos[] counts the run heads strictly before i; a non-head element's own
+    // head is among them, so its run index is one less
+    int64_t p = ok ? pos[i] - (head ? 0 : 1) : -1;
     if (head) {
       nsrc[p] = (int32_t)(key >> bits);
       ncol[p] = (int32_t)(key & mask);
