@@ -85,7 +85,13 @@ typedef struct mc_options {
   int32_t whole_max;       /* graphs up to this size are scanned whole by one
                               wave; 0 = default (6144) */
   int32_t lp_sweeps;       /* clustering sweeps per level when use_viecut */
-  int32_t reserved[5];
+  int32_t scan_mode;       /* graphs above whole_max: 0 = one full-graph capped
+                              sweep per round (default); 1 = many concurrent
+                              bounded region scans (Algorithm 1), with the
+                              sweep as fallback when they find nothing */
+  int32_t sweep_handoff;   /* sweep batches above this many vertices run
+                              grid-wide; 0 = default (512) */
+  int32_t reserved[3];
 } mc_options;
 
 typedef struct mc_stats {

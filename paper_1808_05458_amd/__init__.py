@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
                 ("eager_blacklist", ctypes.c_int32), ("max_pops", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("force_fallback", ctypes.c_int32), ("whole_max", ctypes.c_int32),
-                ("lp_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("lp_sweeps", ctypes.c_int32), ("scan_mode", ctypes.c_int32),
+                ("sweep_handoff", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):

@@ -279,100 +279,4 @@ __global__ void __launch_bounds__(256) k_capforest(ScanArgs A) {
   }
 }
 
-// Sequential CAPFOREST over one whole graph with its state in global memory
-// (Algorithm 2's fallback when no contractible edge was found; a full scan of
-// a connected graph always finds one).  One wave per graph; the vertex range
-// [gvoff, gvoff + gn) indexes fb_r / fb_st directly.
-struct FallbackArgs {
-  const int64_t* rp;
-  const int32_t* col;
-  const int32_t* w;
-  const int64_t* cdeg;
-  const int64_t* lhat;
-  const int32_t* gn;
-  const int32_t* gvoff;
-  const int32_t* list;  // graphs needing the fallback
-  int32_t count;
-  int32_t* fb_r;
-  uint8_t* fb_st;       // 0 unseen, 1 frontier, 2 visited
-  int32_t* fb_step;
-  uint64_t* pairs;
-  int64_t pairs_cap;
-  uint64_t* best_alpha;
-  int32_t* fb_k;        // per graph best prefix length
-  int32_t* ucount;
-  Ctl* ctl;
-};
-
-__global__ void __launch_bounds__(64) k_capforest_fallback(FallbackArgs A) {
-  const int lane = lane_id();
-  for (int item = blockIdx.x; item < A.count; item += gridDim.x) {
-    const int32_t g = A.list[item];
-    const int32_t v0 = A.gvoff[g], ng = A.gn[g];
-    const int64_t lam = A.lhat[g];
-    for (int32_t i = lane; i < ng; i += 64) { A.fb_r[v0 + i] = 0; A.fb_st[v0 + i] = 0; A.fb_step[v0 + i] = 0; }
-    __threadfence_block();
-    if (lane == 0) A.fb_st[v0] = 1;
-    __threadfence_block();
-    int64_t alpha = 0, best_a = INT64_MAX;
-    int32_t k = 0, best_k = 0;
-    int64_t npairs = 0;
-    while (true) {
-      uint64_t best = 0;
-      for (int32_t i = lane; i < ng; i += 64) {
-        if (A.fb_st[v0 + i] == 1) {
-          int64_t key = A.fb_r[v0 + i];
-          if (key > lam) key = lam;
-          uint64_t c = ((uint64_t)(key + 1) << 32) | (uint32_t)i;
-          best = c > best ? c : best;
-        }
-      }
-      best = wave_max_u64(best);
-      if (best == 0) break;
-      const int32_t x = v0 + (int32_t)(uint32_t)best;
-      const int64_t rx = A.fb_r[x];
-      __threadfence_block();
-      if (lane == 0) { A.fb_st[x] = 2; A.fb_step[x] = k + 1; }
-      __threadfence_block();
-      ++k;
-      alpha += A.cdeg[x] - 2 * rx;
-      if (k < ng && alpha < best_a) { best_a = alpha; best_k = k; }
-      const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
-      for (int64_t base = e0; base < e1; base += 64) {
-        const int64_t e = base + lane;
-        bool act = e < e1;
-        int32_t y = act ? A.col[e] : 0;
-        int32_t c = act ? A.w[e] : 0;
-        if (y == x) act = false;
-        if (act && A.fb_st[y] == 2) act = false;
-        bool cross = false;
-        if (act) {
-          int64_t before = atomicAdd(A.fb_r + y, c);
-          int64_t after = before + c;
-          cross = before < lam && lam <= after;
-          A.fb_st[y] = 1;
-        }
-        uint64_t cm = ballot(cross);
-        if (cm) {
-          int cnt = popc64(cm);
-          int64_t pbase = 0;
-          if (lane == 0) pbase = atomicAdd((unsigned long long*)&A.ctl->pairs, (unsigned long long)cnt);
-          pbase = shfl(pbase, 0);
-          if (cross) {
-            int64_t at = pbase + popc64(cm & lanemask_lt());
-            if (at < A.pairs_cap) A.pairs[at] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
-          }
-          npairs += cnt;
-        }
-        __threadfence_block();
-      }
-    }
-    if (lane == 0) {
-      A.fb_k[g] = best_k;
-      if (best_a < lam) atomic_min_u64(A.best_alpha + g, ((uint64_t)best_a << 32) | (uint32_t)FALLBACK_SID);
-      atomicAdd(A.ucount + g, (int32_t)npairs);
-    }
-  }
-}
-
 }  // namespace mc

@@ -129,8 +129,11 @@ struct Workspace {
   int64_t capN = 0, capE = 0, capG = 0;
   std::vector<void*> allocs;
   // vertex arrays
-  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *newid, *map, *ogid;
-  uint8_t* fb_st;
+  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *fb_st, *capq, *sw_seg, *newid, *map,
+      *ogid;
+  SweepCtl* sweep;
+  SweepCtl* sweep_host = nullptr;
+  int64_t* sw_info;
   int64_t *rp, *cdeg;
   // entry arrays
   int32_t *src, *col, *w;
@@ -153,7 +156,9 @@ struct Workspace {
     for (void* p : allocs) hipFree(p);
     allocs.clear();
     if (ctl_host) hipHostFree(ctl_host);
+    if (sweep_host) hipHostFree(sweep_host);
     ctl_host = nullptr;
+    sweep_host = nullptr;
     capN = capE = capG = 0;
   }
 };
@@ -162,9 +167,9 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
   size_t b = 0;
-  b += align_up((N + 1) * 4) * 13 + align_up(N + 1);
+  b += align_up((N + 1) * 4) * 16 + align_up(sizeof(SweepCtl)) + align_up((G + 1) * 24);
   b += align_up((N + 2) * 8) * 2;
-  b += align_up(E * 4) * 3 + align_up(E * 8) * 2 + align_up(E * 4) * 2;
+  b += align_up(E * 4) * 3 + align_up((E + 64) * 8) * 2 + align_up(E * 4) * 2;
   b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 15 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
   b += align_up((2 * N + G + 64) * 4);
@@ -206,14 +211,18 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.newid, (N + 1) * 4);
   ALLOC(ws.map, (N + 1) * 4);
   ALLOC(ws.ogid, (N + 1) * 4);
-  ALLOC(ws.fb_st, N + 1);
+  ALLOC(ws.fb_st, (N + 1) * 4);
+  ALLOC(ws.capq, (N + 1) * 4);
+  ALLOC(ws.sw_seg, (N + 1) * 4);
+  ALLOC(ws.sweep, sizeof(SweepCtl));
+  ALLOC(ws.sw_info, (G + 1) * 3 * 8);
   ALLOC(ws.rp, (N + 2) * 8);
   ALLOC(ws.cdeg, (N + 2) * 8);
   ALLOC(ws.src, E * 4);
   ALLOC(ws.col, E * 4);
   ALLOC(ws.w, E * 4);
-  ALLOC(ws.keys, E * 8);
-  ALLOC(ws.keys_alt, E * 8);
+  ALLOC(ws.keys, (E + 64) * 8);
+  ALLOC(ws.keys_alt, (E + 64) * 8);  // also the sweep's bucket pool (one entry per relaxation)
   ALLOC(ws.vals, E * 4);
   ALLOC(ws.vals_alt, E * 4);
   ALLOC(ws.voff, (G + 1) * 8);
@@ -244,7 +253,8 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.tmp, ws.tmp_bytes);
   ALLOC(ws.ctl, sizeof(Ctl));
 #undef ALLOC
-  if (hipHostMalloc((void**)&ws.ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&ws.ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ws.sweep_host, sizeof(SweepCtl), hipHostMallocDefault) != hipSuccess) {
     ws.release();
     return MC_ENOMEM;
   }
@@ -318,6 +328,72 @@ struct Solver {
         fprintf(stderr, "\n");
       }
     }
+  }
+
+  // One full-graph capped sweep over graph g (vertex range [v0, v0 + ng)).
+  int sweep_graph(int32_t g, int32_t v0, int32_t ng, int64_t lam, int round, const int64_t* rp,
+                  const int32_t* col, const int32_t* w, int64_t nnz, const GraphState& S,
+                  mc_stats* st) {
+    if (lam <= 0 || ng < 2) return MC_OK;
+    SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_st, ws.fb_step, ws.capq,
+                (int2*)ws.keys_alt, ws.capE + 64, ws.sw_seg, ws.sweep, v0, ng, lam, 0, 1, 1, 0};
+    const int lb = bitlen((uint64_t)(lam - 1));
+    A.shift = lb > 12 ? lb - 12 : 0;
+    A.nb = (int32_t)(((lam - 1) >> A.shift) + 1);
+    A.nwords = (A.nb + 63) / 64;
+    A.big = opt.sweep_handoff > 0 ? opt.sweep_handoff : 512;
+    uint64_t h = (opt.seed ? opt.seed : 0x5EEDull) * 0x9E3779B97F4A7C15ull +
+                 (uint64_t)round * 0xBF58476D1CE4E5B9ull + (uint64_t)g;
+    h ^= h >> 29;
+    const int32_t start = v0 + (int32_t)(h % (uint64_t)ng);
+    const int TB = 256;
+    hipLaunchKernelGGL(k_sweep_init, dim3(grid_for(std::max<int64_t>(ng, SWEEP_BUCKETS), TB, num_cu * 16)),
+                       dim3(TB), 0, s, A);
+    hipLaunchKernelGGL(k_sweep_seed, dim3(1), dim3(64), 0, s, A, start);
+    for (int iter = 0;; ++iter) {
+      {
+        TimedScope t("sweep_seq", 0.0);
+        hipLaunchKernelGGL(k_sweep_seq, dim3(1), dim3(SWEEP_THREADS), 0, s, A);
+      }
+      MC_HIP(hipMemcpyAsync(ws.sweep_host, ws.sweep, 64, hipMemcpyDeviceToHost, s));
+      MC_HIP(hipStreamSynchronize(s));
+      const SweepCtl& c = *ws.sweep_host;
+      if (c.status == SW_DONE) break;
+      if (c.status != SW_BIG) return MC_EINTERNAL;
+      const int32_t bh = c.cap_head, bt = c.cap_tail;
+      const int64_t bsz = bt - bh;
+      {
+        // a batch reads its vertices' rows once: adjacency plus state of
+        // every neighbour
+        TimedScope t("sweep_big", (double)bsz * 24);
+        MC_HIP(hipMemsetAsync(&ws.sweep->batch_sum, 0, 16, s));
+        hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
+        hipLaunchKernelGGL(k_sweep_big_relax, dim3(grid_for(bsz * 64, TB, num_cu * 32)), dim3(TB), 0, s, A, bh,
+                           bt);
+        hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
+      }
+      {
+        // exact queue rebuild: two passes over the graph's vertices
+        TimedScope t("sweep_rebuild", (double)ng * 16);
+        hipLaunchKernelGGL(k_sweep_rb_zero, dim3(16), dim3(256), 0, s, A);
+        hipLaunchKernelGGL(k_sweep_rb_count, dim3(grid_for(ng, TB, num_cu * 4)), dim3(TB), 0, s, A);
+        hipLaunchKernelGGL(k_sweep_rb_scan, dim3(1), dim3(1024), 0, s, A);
+        hipLaunchKernelGGL(k_sweep_rb_fill, dim3((ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);
+      }
+    }
+    hipLaunchKernelGGL(k_sweep_report, dim3(1), dim3(64), 0, s, ws.sweep, g, S);
+    if (debug_on()) {
+      hipStreamSynchronize(s);
+      SweepCtl c;
+      hipMemcpy(&c, ws.sweep, sizeof(SweepCtl), hipMemcpyDeviceToHost);
+      fprintf(stderr, "[mc] sweep g=%d v0=%d ng=%d lam=%lld visited=%d singles=%d batches=%d big=%d "
+              "rebuilds=%d unions=%lld best_alpha=%lld step=%d\n", g, v0, ng, (long long)lam, c.visited,
+              c.singles, c.batches, c.big_batches, c.rebuilds, (long long)c.unions, (long long)c.best_alpha,
+              c.best_step);
+    }
+    (void)nnz;
+    (void)st;
+    return MC_OK;
   }
 
   int solve(const Problem& P, int64_t* lambdas, uint8_t* side, mc_stats* st) {
@@ -426,7 +502,8 @@ struct Solver {
       hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
       fill<int32_t>(ws.claim, -1, n, s);
       if (opt.use_pr) {
-        TimedScope t("pr", (double)nnz * 8 + (double)nnz * 16 + (double)n * 16);
+        // src, col, w per entry; both degrees for the half with u < v
+        TimedScope t("pr", (double)nnz * 12 + (double)nnz * 8);
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
                            ws.lhat, ws.mode, ws.parent, ws.ucount, ws.ctl);
       }
@@ -447,17 +524,22 @@ struct Solver {
       A.perm_a = (rs | 1ull) & ((1ull << A.perm_bits) - 1);
       if (A.perm_a == 0) A.perm_a = 1;
       A.perm_b = (rs >> 17) & ((1ull << A.perm_bits) - 1);
+      // algorithmic bytes of one scan launch: every adjacency entry once
+      // (col, w) plus the claim gather, and per vertex row_ptr, cdeg, claim
+      // and step
+      const double scan_bytes = (double)nnz * (8 + (opt.eager_blacklist ? 4 : 0)) + (double)n * 32;
+      if (opt.scan_mode == 1 && !opt.force_fallback) {
+        TimedScope t("capforest_region", scan_bytes);
+        A.whole_mode = 0;
+        A.whole = ws.whole;
+        A.whole_count = &ws.ctl->n_region;  // unused in region mode
+        const int wpb = 4;
+        size_t lds = sizeof(ScanLds<REGION_CAP>) * wpb;
+        int blocks = std::max(1, region_waves / wpb);
+        hipLaunchKernelGGL(k_capforest<REGION_CAP>, dim3(blocks), dim3(64 * wpb), lds, s, A);
+      }
       {
-        TimedScope t("capforest", (double)nnz * 8 + (double)n * 40);
-        if (!opt.force_fallback) {
-          A.whole_mode = 0;
-          A.whole = ws.whole;
-          A.whole_count = &ws.ctl->n_region;  // unused in region mode
-          const int wpb = 4;
-          size_t lds = sizeof(ScanLds<REGION_CAP>) * wpb;
-          int blocks = std::max(1, region_waves / wpb);
-          hipLaunchKernelGGL(k_capforest<REGION_CAP>, dim3(blocks), dim3(64 * wpb), lds, s, A);
-        }
+        TimedScope t("capforest_whole", scan_bytes);
         // whole-graph scans: small map, then large map
         MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
         A.whole_mode = 1;
@@ -475,7 +557,10 @@ struct Solver {
         TimedScope t("union", (double)n * 8);
         hipLaunchKernelGGL(k_union_pairs, grid(n), dim3(TB), 0, s, ws.keys_alt, ws.ctl, ws.capE, ws.parent);
       }
-      hipLaunchKernelGGL(k_fallback_list, grid(G), dim3(TB), 0, s, G, S, ws.ctl);
+      const int sweep_region = (opt.scan_mode == 0 || opt.force_fallback) ? 1 : 0;
+      hipLaunchKernelGGL(k_sweep_list, grid(G), dim3(TB), 0, s, G, S, sweep_region, ws.ctl);
+      hipLaunchKernelGGL(k_sweep_info, grid(G), dim3(TB), 0, s, ws.fb_list, ws.ctl, ws.cvoff, ws.gn,
+                         ws.lhat, ws.sw_info);
       rc = read_ctl();
       if (rc) return rc;
       if (st) {
@@ -484,17 +569,19 @@ struct Solver {
         st->pops += ws.ctl_host->pops;
         st->overflows += ws.ctl_host->overflows;
       }
-      if (ws.ctl_host->n_fallback > 0) {
-        // region pairs are united already; the fallback's pairs start afresh
-        MC_HIP(hipMemsetAsync(&ws.ctl->pairs, 0, sizeof(int64_t), s));
-        TimedScope t("fallback", (double)nnz * 8);
-        FallbackArgs F{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.fb_list,
-                       ws.ctl_host->n_fallback, ws.fb_r, ws.fb_st, ws.fb_step, ws.keys_alt,
-                       ws.capE, ws.balpha, ws.fb_k, ws.ucount, ws.ctl};
-        hipLaunchKernelGGL(k_capforest_fallback, dim3(std::min(ws.ctl_host->n_fallback, num_cu * 4)),
-                           dim3(64), 0, s, F);
-        hipLaunchKernelGGL(k_union_pairs, grid(n), dim3(TB), 0, s, ws.keys_alt, ws.ctl, ws.capE, ws.parent);
-        if (st) st->fallbacks += ws.ctl_host->n_fallback;
+      const int32_t n_sweeps = ws.ctl_host->n_fallback;
+      if (n_sweeps > 0) {
+        std::vector<int64_t> info((size_t)n_sweeps * 3);
+        std::vector<int32_t> glist(n_sweeps);
+        MC_HIP(hipMemcpyAsync(info.data(), ws.sw_info, info.size() * 8, hipMemcpyDeviceToHost, s));
+        MC_HIP(hipMemcpyAsync(glist.data(), ws.fb_list, n_sweeps * 4, hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        for (int32_t q = 0; q < n_sweeps; ++q) {
+          rc = sweep_graph(glist[q], (int32_t)info[3 * q], (int32_t)info[3 * q + 1], info[3 * q + 2],
+                           round, rp, col, w, nnz, S, st);
+          if (rc) return rc;
+        }
+        if (st) st->fallbacks += n_sweeps;
       }
       // union-find finish and block numbering
       {
@@ -521,7 +608,9 @@ struct Solver {
       // contraction: emit, sort, merge, CSR
       const int bb = std::max(1, bitlen((uint64_t)std::max(n_next, 1) - 1));
       {
-        TimedScope t("emit", (double)nnz * 12 + (double)nnz * 8);
+        // src, col, w and two label gathers per entry; the keys it writes are
+        // counted with the sort
+        TimedScope t("emit", (double)nnz * 20);
         hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, num_cu * 8)), dim3(TB), 0,
                            s, nnz, ws.src, col, w, ws.lab, bb, ws.keys, ws.vals, ws.ctl);
       }
@@ -530,22 +619,32 @@ struct Solver {
       const int64_t m = ws.ctl_host->emit;
       int which = 0;
       {
-        TimedScope t("sort", (double)m * 12 * 2);
-        which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s);
+        // per pass: the histogram reads every key (8 B); the scatter reads
+        // and writes key and weight (24 B)
+        int cur = -1;
+        hipEvent_t ev0{};
+        auto hook = [&](int kind, int) {
+          if (kind == 0) cur = timer().begin("sort_hist", ev0);
+          else if (kind == 1) timer().end(cur, ev0, (double)m * 8);
+          else if (kind == 2) cur = timer().begin("sort_scatter", ev0);
+          else timer().end(cur, ev0, (double)m * 24);
+        };
+        which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s, hook);
       }
       uint64_t* sk = which ? ws.keys_alt : ws.keys;
       int32_t* sv = which ? ws.vals_alt : ws.vals;
       int64_t* pos = (int64_t*)(which ? ws.keys : ws.keys_alt);
       {
-        TimedScope t("merge", (double)m * 12 + (double)m * 8);
+        TimedScope t("merge_scan", (double)m * 16 + (double)m * 8);
         exclusive_scan<int64_t, HeadFlag>(HeadFlag{sk}, m, pos, (int64_t*)&ws.ctl->unique, ws.tmp, s);
       }
       rc = read_ctl();
       if (rc) return rc;
       const int64_t m2 = m > 0 ? ws.ctl_host->unique : 0;
       {
-        TimedScope t("merge", (double)m * 20 + (double)m2 * 12);
         fill<int32_t>(ws.w, 0, m2, s);
+        // keys, weights and positions in; the merged entries out
+        TimedScope t("merge", (double)m * 20 + (double)m2 * 12);
         if (m > 0)
           hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s,
                              m, sk, sv, pos, bb, ws.src, ws.col, ws.w);

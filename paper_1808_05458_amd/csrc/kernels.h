@@ -6,6 +6,7 @@
 #pragma once
 #include "capforest.h"
 #include "prims.h"
+#include "sweep.h"
 
 namespace mc {
 
@@ -228,7 +229,7 @@ __global__ void k_side(SideArgs A) {
       s = c == A.rec_id[g];
     } else if (t == REC_ALPHA) {
       int32_t sid = A.rec_id[g], k = A.rec_k[g];
-      if (sid == FALLBACK_SID) s = A.fb_step[c] >= 1 && A.fb_step[c] <= k;
+      if (sid == SWEEP_SID) s = A.fb_step[c] >= 1 && A.fb_step[c] <= k;
       else s = A.claim[c] == sid && A.step[c] <= k;
     } else if (t == REC_DISCONNECTED) {
       s = A.parent[v] != A.root0[g];
@@ -290,12 +291,33 @@ __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
 
-__global__ void k_fallback_list(int32_t G, GraphState S, Ctl* ctl) {
+// Graphs that get a full-graph sweep this round: region-mode graphs when the
+// sweep is the scan of choice, and any graph whose scans found no pair.
+__global__ void k_sweep_list(int32_t G, GraphState S, int32_t sweep_region, Ctl* ctl) {
   for (int64_t g = gtid(); g < G; g += gstride())
-    if (S.mode[g] != 0 && S.ucount[g] == 0) {  // any scan kind may end early
+    if ((S.mode[g] == 2 && sweep_region) || (S.mode[g] != 0 && S.ucount[g] == 0)) {
       int32_t i = atomicAdd(&ctl->n_fallback, 1);
       S.fb_list[i] = (int32_t)g;
     }
+}
+
+__global__ void k_sweep_info(const int32_t* list, const Ctl* ctl, const int32_t* cvoff, const int32_t* gn,
+                             const int64_t* lhat, int64_t* info) {
+  for (int64_t i = gtid(); i < ctl->n_fallback; i += gstride()) {
+    int32_t g = list[i];
+    info[3 * i] = cvoff[g];
+    info[3 * i + 1] = gn[g];
+    info[3 * i + 2] = lhat[g];
+  }
+}
+
+__global__ void k_sweep_report(const SweepCtl* c, int32_t g, GraphState S) {
+  if (gtid() != 0) return;
+  if (c->best_alpha < S.lhat[g]) {
+    S.fb_k[g] = c->best_step;
+    atomic_min_u64(S.balpha + g, ((uint64_t)c->best_alpha << 32) | (uint32_t)SWEEP_SID);
+  }
+  atomicAdd(S.ucount + g, (int32_t)(c->unions > 0x3FFFFFFF ? 0x3FFFFFFF : c->unions));
 }
 
 // ------------------------------------------------------------ compaction
@@ -333,7 +355,7 @@ __global__ void k_update_alpha(int32_t G, GraphState S, const int32_t* scan_k, C
       S.lhat[g] = a;
       S.rec_type[g] = REC_ALPHA;
       S.rec_id[g] = sid;
-      S.rec_k[g] = sid == FALLBACK_SID ? S.fb_k[g] : scan_k[sid];
+      S.rec_k[g] = sid == SWEEP_SID ? S.fb_k[g] : scan_k[sid];
       atomicAdd(&ctl->improved, 1);
     }
   }

@@ -219,9 +219,16 @@ inline size_t radix_tmp_bytes(int64_t n) {
 
 // Sorts (keys, vals) by the low `bits` bits of the key.  Ping-pongs between
 // the two buffer pairs; returns 0 if the result is in (keys, vals), 1 if in
-// (keys_alt, vals_alt).  Positions fit in 32 bits (n < 2^32).
+// (keys_alt, vals_alt).  Positions fit in 32 bits (n < 2^32).  `hook(kind,
+// pass)` is called before (kind 0/2) and after (kind 1/3) the histogram and
+// scatter launches of each pass (timing).
+struct NoHook {
+  void operator()(int, int) const {}
+};
+
+template <typename Hook = NoHook>
 inline int radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
-                            int64_t n, int bits, void* tmp, hipStream_t s) {
+                            int64_t n, int bits, void* tmp, hipStream_t s, Hook hook = Hook()) {
   if (n <= 1 || bits <= 0) return 0;
   int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
   size_t hb = ((size_t)ntiles * 256 * sizeof(uint32_t) + 255) & ~(size_t)255;
@@ -229,16 +236,20 @@ inline int radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, i
   uint32_t* offs = (uint32_t*)((char*)tmp + hb);
   void* stmp = (char*)tmp + 2 * hb;
   int which = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = 0, pass = 0; shift < bits; shift += 8, ++pass) {
     const uint64_t* ki = which ? keys_alt : keys;
     const int32_t* vi = which ? vals_alt : vals;
     uint64_t* ko = which ? keys : keys_alt;
     int32_t* vo = which ? vals : vals_alt;
+    hook(0, pass);
     hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, ki, n, shift, hist, ntiles);
+    hook(1, pass);
     exclusive_scan<uint32_t, ArrayIn<uint32_t>>(ArrayIn<uint32_t>{hist}, ntiles * 256, offs,
                                                 (uint32_t*)nullptr, stmp, s);
+    hook(2, pass);
     hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, ki, vi, n, shift, offs,
                        ntiles, ko, vo);
+    hook(3, pass);
     which ^= 1;
   }
   return which;

@@ -1,0 +1,550 @@
+// Full-graph CAPFOREST with bounded keys (appendix Algorithm 3 with the cap
+// of Lemma 1, section "Bounded Priority Queues"), run in parallel over ties.
+//
+// With keys capped at lambda-hat, every frontier vertex whose r has reached
+// the cap is a maximum of the priority queue, and no relaxation can lift any
+// key above the cap.  So all capped frontier vertices can be visited as one
+// batch: any order of them is a legal maximum-adjacency order, and every
+// value q(e) = r(y) produced while the batch is relaxed (atomic adds give
+// each edge the value of some order of the batch) is the q(e) of such a
+// legal run.  Vertices below the cap are popped one at a time from a bucket
+// queue, exactly as the sequential routine does.  The crossing rule
+// r(y) < lambda-hat <= r(y) + c(e) unites x and y; each vertex crosses at most
+// once, and crossing vertices form the next batch (a FIFO of batches).
+//
+// alpha = c(S) of the visited set is tracked at batch boundaries:
+//   alpha' = alpha + sum_{x in B} (c(x) - 2 r(x)) - 2 w(edges inside B).
+//
+// A persistent single-workgroup kernel runs the single pops and the small
+// batches; a batch larger than the hand-off size goes back to the host,
+// which runs it grid-wide (mark, relax, finish) and then rebuilds the bucket
+// queue exactly from the frontier (one counting sort), so that the lazy
+// entries made stale by a large batch never have to be walked.
+#pragma once
+#include "dev.h"
+
+namespace mc {
+
+constexpr int SWEEP_THREADS = 1024;
+constexpr int SWEEP_BUCKETS = 4096;  // bucket queue for keys below the cap
+constexpr int32_t SWEEP_SID = 0x7FFFFFFF;
+constexpr int RB_TILE = 4096;        // vertices per workgroup in the rebuild
+
+enum : int32_t { SW_RUNNING = 0, SW_DONE = 1, SW_BIG = 2 };
+
+struct SweepCtl {
+  int32_t cap_head, cap_tail;  // capped FIFO: [head, tail) is the pending batch
+  int32_t visited;
+  int32_t step;                // batches so far (visit order stamps)
+  int64_t alpha;
+  int64_t best_alpha;
+  int32_t best_step;
+  int32_t status;
+  int64_t pool_next;
+  int64_t batch_sum;           // grid-wide batch: sum c(x) - 2 r(x)
+  int64_t batch_internal;      // grid-wide batch: 2 w(inside)
+  int64_t unions;
+  int32_t singles, batches, big_batches, rebuilds;
+  uint64_t bitmap[SWEEP_BUCKETS / 64];
+  int32_t head[SWEEP_BUCKETS];     // recent pushes (lists through the pool)
+  int32_t seg_cur[SWEEP_BUCKETS];  // rebuilt segments of seg[]: unread part
+  int32_t seg_end[SWEEP_BUCKETS];
+  int32_t fill[SWEEP_BUCKETS];     // rebuild scratch
+};
+
+struct SweepArgs {
+  const int64_t* rp;
+  const int32_t* col;
+  const int32_t* w;
+  const int64_t* cdeg;
+  int32_t* parent;
+  int32_t* r;        // per vertex
+  int32_t* st;       // 0 unseen, 1 frontier, 2 visited
+  int32_t* step;     // visit stamp (batch number), 0 = not visited
+  int32_t* capq;     // capped FIFO (each vertex enters at most once)
+  int2* pool;        // bucket entries (vertex, next)
+  int64_t pool_cap;
+  int32_t* seg;      // bucket segments written by the rebuild
+  SweepCtl* ctl;
+  int32_t v0, ng;    // graph vertex range
+  int64_t lam;       // lambda-hat for this round
+  int32_t shift;     // bucket = key >> shift
+  int32_t nwords;    // bitmap words in use
+  int32_t nb;        // buckets in use
+  int32_t big;       // batches above this size go grid-wide
+};
+
+__device__ __forceinline__ int2 pool_at(const SweepArgs& A, int32_t idx) {
+  uint64_t u = ld_relaxed((const uint64_t*)(A.pool + idx));
+  return make_int2((int32_t)(uint32_t)u, (int32_t)(u >> 32));
+}
+
+__device__ __forceinline__ void pool_put(const SweepArgs& A, int64_t idx, int32_t v, int32_t next) {
+  st_relaxed((uint64_t*)(A.pool + idx), ((uint64_t)(uint32_t)next << 32) | (uint32_t)v);
+}
+
+// Relax edge (x, y, c) while batch `stamp` is being visited.  Every lane of
+// the wave calls this (act = false for idle lanes) so that queue and counter
+// updates are aggregated per wave.  Returns the weight to add to the
+// batch-internal sum (edge inside the batch).
+__device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, int32_t y, int32_t c,
+                                               int32_t stamp, bool act) {
+  const int lane = lane_id();
+  int64_t internal = 0;
+  bool cross = false, push = false;
+  int64_t nw = 0;
+  if (act && y == x) act = false;
+  if (act) {
+    int32_t s = ld_relaxed(A.st + y);
+    if (s == 2) {
+      if (ld_relaxed(A.step + y) == stamp) internal = c;
+    } else {
+      int32_t old = atomicAdd(A.r + y, c);
+      nw = (int64_t)old + c;
+      if (s == 0) st_relaxed(A.st + y, 1);
+      cross = old < A.lam && A.lam <= nw;
+      push = nw < A.lam;
+    }
+  }
+  // crossings: unite, and append y to the capped FIFO
+  const uint64_t cm = ballot(cross);
+  if (cm) {
+    const int leader = __builtin_ctzll(cm);
+    int32_t base = 0;
+    if (lane == leader) {
+      base = atomicAdd(&A.ctl->cap_tail, popc64(cm));
+      atomicAdd((unsigned long long*)&A.ctl->unions, (unsigned long long)popc64(cm));
+    }
+    base = shfl(base, leader);
+    if (cross) {
+      A.capq[base + popc64(cm & lanemask_lt())] = y;
+      uf_union(A.parent, x, y);
+    }
+  }
+  // pushes below the cap: one pool reservation per wave, then one list
+  // splice per distinct bucket
+  uint64_t pm = ballot(push);
+  if (pm) {
+    const int leader = __builtin_ctzll(pm);
+    int64_t pbase = 0;
+    if (lane == leader)
+      pbase = (int64_t)atomicAdd((unsigned long long*)&A.ctl->pool_next, (unsigned long long)popc64(pm));
+    pbase = shfl(pbase, leader);
+    const int64_t idx = pbase + popc64(pm & lanemask_lt());
+    const int32_t b = push ? (int32_t)(nw >> A.shift) : -1;
+    while (pm) {
+      const int32_t b0 = shfl(b, __builtin_ctzll(pm));
+      const bool mine = push && b == b0;
+      const uint64_t grp = ballot(mine);
+      pm &= ~grp;
+      const int hi = 63 - __builtin_clzll(grp);
+      const uint64_t lower = grp & lanemask_lt();
+      const int prev_lane = lower ? 63 - __builtin_clzll(lower) : lane;
+      // the highest lane of the group becomes the head; each lane links to
+      // the next lower lane of its group, the lowest to the old head
+      int32_t old_head = -1;
+      if (lane == hi) {
+        if (idx < A.pool_cap) old_head = atomicExch(&A.ctl->head[b0], (int32_t)idx);
+        const uint64_t wbit = 1ull << (b0 & 63);
+        if (!(ld_relaxed(&A.ctl->bitmap[b0 >> 6]) & wbit))
+          atomicOr((unsigned long long*)&A.ctl->bitmap[b0 >> 6], wbit);
+      }
+      old_head = shfl(old_head, hi);
+      const int64_t prev_idx = shfl(idx, prev_lane);
+      if (mine && idx < A.pool_cap) pool_put(A, idx, y, lower ? (int32_t)prev_idx : old_head);
+    }
+  }
+  return internal;
+}
+
+// Reset the graph's range and the queue.
+__global__ void k_sweep_init(SweepArgs A) {
+  for (int64_t i = gtid(); i < A.ng; i += gstride()) {
+    A.r[A.v0 + i] = 0;
+    A.st[A.v0 + i] = 0;
+    A.step[A.v0 + i] = 0;
+  }
+  for (int64_t i = gtid(); i < SWEEP_BUCKETS; i += gstride()) {
+    A.ctl->head[i] = -1;
+    A.ctl->seg_cur[i] = 0;
+    A.ctl->seg_end[i] = 0;
+  }
+  for (int64_t i = gtid(); i < SWEEP_BUCKETS / 64; i += gstride()) A.ctl->bitmap[i] = 0;
+  if (gtid() == 0) {
+    SweepCtl* c = A.ctl;
+    c->cap_head = c->cap_tail = 0;
+    c->visited = 0;
+    c->step = 0;
+    c->alpha = 0;
+    c->best_alpha = INT64_MAX;
+    c->best_step = 0;
+    c->status = SW_RUNNING;
+    c->pool_next = 1;
+    c->batch_sum = c->batch_internal = 0;
+    c->unions = 0;
+    c->singles = c->batches = c->big_batches = c->rebuilds = 0;
+  }
+}
+
+__global__ void k_sweep_seed(SweepArgs A, int32_t start) {
+  if (gtid() == 0) {
+    A.st[start] = 1;
+    A.pool[0] = make_int2(start, -1);  // (vertex, next)
+    A.ctl->head[0] = 0;
+    A.ctl->bitmap[0] = 1ull;
+  }
+}
+
+__device__ __forceinline__ void sweep_close_batch(SweepCtl* c, int32_t ng, int64_t sum, int64_t internal,
+                                                  int32_t size, int32_t stamp) {
+  c->alpha += sum - internal;
+  c->visited += size;
+  if (c->visited < ng && c->alpha < c->best_alpha) {
+    c->best_alpha = c->alpha;
+    c->best_step = stamp;
+  }
+}
+
+__device__ __forceinline__ bool live_in_bucket(const SweepArgs& A, int32_t v, int32_t b, int32_t& key) {
+  if (v < 0 || ld_relaxed(A.st + v) != 1) return false;
+  key = ld_relaxed(A.r + v);
+  return (int64_t)key < A.lam && (key >> A.shift) == b;
+}
+
+// Single pop by wave 0: the highest non-empty bucket (bitmap words read by
+// the lanes, one each); in it, the recent-push list (lane 0 walks it,
+// dropping stale entries) and then the rebuilt segment (64 entries per read,
+// cursor only moves forward).  With one key per bucket the first live entry
+// is a maximum; with wider buckets the largest live key of the whole bucket
+// is taken (the segment entry is then tombstoned).  -1: queue empty.
+__device__ int32_t sweep_pop_wave0(const SweepArgs& A) {
+  SweepCtl* c = A.ctl;
+  const int lane = lane_id();
+  while (true) {
+    uint64_t word = lane < A.nwords ? ld_relaxed(&c->bitmap[lane]) : 0ull;
+    uint64_t m = ballot(word != 0);
+    if (m == 0) return -1;
+    const int bw = 63 - __builtin_clzll(m);
+    const uint64_t wv = shfl(word, bw);
+    const int b = bw * 64 + 63 - __builtin_clzll(wv);
+    int32_t x = -1;
+    if (A.shift == 0) {
+      if (lane == 0) {
+        int32_t idx = ld_relaxed(&c->head[b]);
+        while (idx >= 0) {
+          int2 e = pool_at(A, idx);
+          idx = e.y;
+          int32_t k;
+          if (live_in_bucket(A, e.x, b, k)) { x = e.x; break; }
+        }
+        st_relaxed(&c->head[b], idx);
+      }
+      x = shfl(x, 0);
+      if (x >= 0) return x;
+      int32_t cur = ld_relaxed(&c->seg_cur[b]);
+      const int32_t end = ld_relaxed(&c->seg_end[b]);
+      while (cur < end) {
+        const int32_t i = cur + lane;
+        const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
+        int32_t k;
+        const uint64_t ok = ballot(live_in_bucket(A, v, b, k));
+        if (ok) {
+          const int first = __builtin_ctzll(ok);
+          x = shfl(v, first);
+          cur += first + 1;
+          break;
+        }
+        cur += 64;
+      }
+      if (lane == 0) st_relaxed(&c->seg_cur[b], cur < end ? cur : end);
+      if (x >= 0) return x;
+    } else {
+      // wide bucket: exact maximum over the list and the segment
+      int64_t best_key = -1;
+      int32_t best_v = -1, best_idx = -1, best_prev = -1;
+      if (lane == 0) {
+        int32_t idx = ld_relaxed(&c->head[b]), prev = -1;
+        while (idx >= 0) {
+          int2 e = pool_at(A, idx);
+          int32_t k;
+          if (!live_in_bucket(A, e.x, b, k)) {
+            if (prev < 0) st_relaxed(&c->head[b], e.y);
+            else pool_put(A, prev, pool_at(A, prev).x, e.y);
+          } else {
+            if (k > best_key) { best_key = k; best_v = e.x; best_idx = idx; best_prev = prev; }
+            prev = idx;
+          }
+          idx = e.y;
+        }
+      }
+      best_key = shfl(best_key, 0);
+      best_v = shfl(best_v, 0);
+      int64_t seg_best = -1;
+      int32_t seg_pos = -1;
+      const int32_t cur0 = ld_relaxed(&c->seg_cur[b]);
+      const int32_t end = ld_relaxed(&c->seg_end[b]);
+      for (int32_t base = cur0; base < end; base += 64) {
+        const int32_t i = base + lane;
+        const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
+        int32_t k;
+        if (live_in_bucket(A, v, b, k) && k > seg_best) { seg_best = k; seg_pos = i; }
+      }
+      const uint64_t packed =
+          wave_max_u64(seg_best < 0 ? 0ull : (((uint64_t)(seg_best + 1) << 32) | (uint32_t)seg_pos));
+      if (packed != 0 && (int64_t)(packed >> 32) - 1 > best_key) {
+        const int32_t pos = (int32_t)(uint32_t)packed;
+        x = ld_relaxed(A.seg + pos);
+        if (lane == 0) st_relaxed(A.seg + pos, -1);
+      } else if (best_v >= 0) {
+        x = best_v;
+        if (lane == 0) {
+          const int32_t nx = pool_at(A, best_idx).y;
+          if (best_prev < 0) st_relaxed(&c->head[b], nx);
+          else pool_put(A, best_prev, pool_at(A, best_prev).x, nx);
+        }
+      }
+      if (x >= 0) return x;
+      if (lane == 0) {
+        st_relaxed(&c->head[b], -1);
+        st_relaxed(&c->seg_cur[b], end);
+      }
+    }
+    // the bucket holds no live entry
+    if (lane == 0) atomicAnd((unsigned long long*)&c->bitmap[bw], ~(1ull << (b & 63)));
+  }
+}
+
+// The persistent workgroup.  Exits with SW_DONE (queue empty) or SW_BIG (a
+// batch larger than A.big is pending; cap_head..cap_tail untouched).
+__global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
+  __shared__ int32_t sh_x, sh_cmd, sh_h, sh_t, sh_stamp;
+  __shared__ int64_t sh_sum[SWEEP_THREADS / 64], sh_int[SWEEP_THREADS / 64];
+  SweepCtl* c = A.ctl;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int nwaves = SWEEP_THREADS / 64;
+  while (true) {
+    if (wave == 0) {
+      const int32_t h = ld_relaxed(&c->cap_head), t = ld_relaxed(&c->cap_tail);
+      int cmd;
+      int32_t x = -1;
+      if (t > h) {
+        cmd = (t - h > A.big) ? 2 : 1;  // 2: hand the batch to the grid
+      } else {
+        x = sweep_pop_wave0(A);
+        cmd = x < 0 ? 0 : 3;
+      }
+      if (lane == 0) {
+        sh_cmd = cmd;
+        sh_x = x;
+        sh_h = h;
+        sh_t = t;
+        if (cmd == 1 || cmd == 3) {
+          sh_stamp = c->step + 1;
+          c->step = c->step + 1;
+          if (cmd == 1) c->batches += 1; else c->singles += 1;
+        }
+      }
+    }
+    __syncthreads();
+    const int cmd = sh_cmd;
+    if (cmd == 0 || cmd == 2) {
+      if (threadIdx.x == 0) c->status = cmd == 0 ? SW_DONE : SW_BIG;
+      return;
+    }
+    const int32_t stamp = sh_stamp;
+    int64_t sum = 0, internal = 0;
+    int32_t size;
+    if (cmd == 3) {
+      const int32_t x = sh_x;
+      if (threadIdx.x == 0) {
+        st_relaxed(A.st + x, 2);
+        st_relaxed(A.step + x, stamp);
+        sum = A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
+      }
+      size = 1;
+      __threadfence();
+      __syncthreads();
+      const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
+      for (int64_t base = e0 + wave * 64; base < e1; base += SWEEP_THREADS) {
+        const int64_t e = base + lane;
+        const bool act = e < e1;
+        internal += sweep_relax(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+      }
+    } else {
+      const int32_t h = sh_h, t = sh_t;
+      size = t - h;
+      for (int32_t i = h + threadIdx.x; i < t; i += SWEEP_THREADS) {
+        int32_t x = ld_relaxed(A.capq + i);
+        st_relaxed(A.st + x, 2);
+        st_relaxed(A.step + x, stamp);
+        sum += A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
+      }
+      __threadfence();
+      __syncthreads();
+      for (int32_t i = h + wave; i < t; i += nwaves) {
+        const int32_t x = ld_relaxed(A.capq + i);
+        const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
+        for (int64_t base = e0; base < e1; base += 64) {
+          const int64_t e = base + lane;
+          const bool act = e < e1;
+          internal += sweep_relax(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+        }
+      }
+    }
+    sum = wave_sum_i64(sum);
+    internal = wave_sum_i64(internal);
+    if (lane == 0) { sh_sum[wave] = sum; sh_int[wave] = internal; }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t s = 0, in = 0;
+      for (int i = 0; i < nwaves; ++i) { s += sh_sum[i]; in += sh_int[i]; }
+      if (cmd == 1) c->cap_head = sh_t;
+      sweep_close_batch(c, A.ng, s, in, size, stamp);
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+// Grid-wide batch [h, t): mark every vertex visited.
+__global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
+  SweepCtl* c = A.ctl;
+  const int32_t stamp = c->step + 1;
+  int64_t sum = 0;
+  for (int64_t i = h + gtid(); i - lane_id() < t; i += gstride()) {  // wave-uniform bound
+    if (i < t) {
+      int32_t x = A.capq[i];
+      A.st[x] = 2;
+      A.step[x] = stamp;
+      sum += A.cdeg[x] - 2 * (int64_t)A.r[x];
+    }
+  }
+  sum = wave_sum_i64(sum);
+  if (lane_id() == 0 && sum) atomicAdd((unsigned long long*)&c->batch_sum, (unsigned long long)sum);
+}
+
+// Grid-wide batch [h, t): relax every edge of the batch, one wave per vertex.
+__global__ void k_sweep_big_relax(SweepArgs A, int32_t h, int32_t t) {
+  SweepCtl* c = A.ctl;
+  const int32_t stamp = c->step + 1;
+  const int lane = lane_id();
+  const int64_t wave0 = gtid() >> 6, nw = gstride() >> 6;
+  int64_t internal = 0;
+  for (int64_t i = h + wave0; i < t; i += nw) {
+    const int32_t x = A.capq[i];
+    const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
+    for (int64_t base = e0; base < e1; base += 64) {
+      const int64_t e = base + lane;
+      const bool act = e < e1;
+      internal += sweep_relax(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+    }
+  }
+  internal = wave_sum_i64(internal);
+  if (lane == 0 && internal) atomicAdd((unsigned long long*)&c->batch_internal, (unsigned long long)internal);
+}
+
+__global__ void k_sweep_big_finish(SweepArgs A, int32_t t) {
+  if (gtid() != 0) return;
+  SweepCtl* c = A.ctl;
+  const int32_t h = c->cap_head;
+  const int32_t stamp = ++c->step;
+  c->batches += 1;
+  c->big_batches += 1;
+  c->cap_head = t;
+  sweep_close_batch(c, A.ng, c->batch_sum, c->batch_internal, t - h, stamp);
+  c->batch_sum = 0;
+  c->batch_internal = 0;
+  c->status = SW_RUNNING;
+}
+
+// ---- exact rebuild of the bucket queue from the frontier (counting sort)
+__global__ void k_sweep_rb_zero(SweepArgs A) {
+  for (int64_t i = gtid(); i < SWEEP_BUCKETS; i += gstride()) A.ctl->seg_end[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_sweep_rb_count(SweepArgs A) {
+  __shared__ int32_t h[SWEEP_BUCKETS];
+  for (int i = threadIdx.x; i < A.nb; i += 256) h[i] = 0;
+  __syncthreads();
+  for (int64_t i = gtid(); i < A.ng; i += gstride()) {
+    const int32_t v = A.v0 + (int32_t)i;
+    if (A.st[v] == 1 && (int64_t)A.r[v] < A.lam) atomicAdd(&h[A.r[v] >> A.shift], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < A.nb; i += 256)
+    if (h[i]) atomicAdd(&A.ctl->seg_end[i], h[i]);
+}
+
+// One workgroup: segment bounds from the counts; lists and pool emptied.
+__global__ void __launch_bounds__(1024) k_sweep_rb_scan(SweepArgs A) {
+  __shared__ int32_t part[1024];
+  SweepCtl* c = A.ctl;
+  const int per = (A.nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per;
+  int32_t s = 0;
+  for (int k = 0; k < per && b0 + k < A.nb; ++k) s += c->seg_end[b0 + k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < 1024; ++i) { int32_t t = part[i]; part[i] = run; run += t; }
+  }
+  __syncthreads();
+  int32_t run = part[threadIdx.x];
+  for (int k = 0; k < per && b0 + k < A.nb; ++k) {
+    const int b = b0 + k;
+    const int32_t cnt = c->seg_end[b];
+    c->seg_cur[b] = run;
+    c->fill[b] = run;
+    c->seg_end[b] = run + cnt;
+    c->head[b] = -1;
+    run += cnt;
+  }
+  __syncthreads();
+  for (int wd = threadIdx.x; wd < SWEEP_BUCKETS / 64; wd += 1024) {
+    uint64_t bits = 0;
+    for (int k = 0; k < 64; ++k) {
+      const int b = wd * 64 + k;
+      if (b < A.nb && c->seg_end[b] > c->seg_cur[b]) bits |= 1ull << k;
+    }
+    c->bitmap[wd] = bits;
+  }
+  if (threadIdx.x == 0) {
+    c->pool_next = 0;
+    c->rebuilds += 1;
+  }
+}
+
+// Frontier vertices into their bucket segments: per workgroup a local
+// histogram, one range reservation per bucket, then the writes.
+__global__ void __launch_bounds__(256) k_sweep_rb_fill(SweepArgs A) {
+  __shared__ int32_t h[SWEEP_BUCKETS];
+  constexpr int PER = RB_TILE / 256;
+  for (int i = threadIdx.x; i < A.nb; i += 256) h[i] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * RB_TILE;
+  int32_t bk[PER], rk[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int64_t i = t0 + q * 256 + threadIdx.x;
+    bk[q] = -1;
+    rk[q] = 0;
+    if (i < A.ng) {
+      const int32_t v = A.v0 + (int32_t)i;
+      if (A.st[v] == 1 && (int64_t)A.r[v] < A.lam) {
+        bk[q] = A.r[v] >> A.shift;
+        rk[q] = atomicAdd(&h[bk[q]], 1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < A.nb; i += 256)
+    if (h[i]) h[i] = atomicAdd(&A.ctl->fill[i], h[i]);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    if (bk[q] >= 0) A.seg[h[bk[q]] + rk[q]] = A.v0 + (int32_t)(t0 + q * 256 + threadIdx.x);
+}
+
+}  // namespace mc

@@ -81,7 +81,12 @@ def test_medium_graphs_against_noi():
 
 @pytest.mark.parametrize("opts", [dict(), dict(use_pr=0), dict(eager_blacklist=0),
                                   dict(force_fallback=1), dict(max_pops=3),
-                                  dict(whole_max=16), dict(whole_max=16, max_pops=5, use_pr=0)])
+                                  dict(whole_max=16), dict(whole_max=16, use_pr=0),
+                                  dict(whole_max=16, scan_mode=1),
+                                  dict(whole_max=16, scan_mode=1, max_pops=5, use_pr=0),
+                                  dict(whole_max=16, scan_mode=1, eager_blacklist=0),
+                                  dict(whole_max=16, sweep_handoff=1),
+                                  dict(whole_max=16, sweep_handoff=3, use_pr=0)])
 def test_planted_4096_options(opts):
     g = gg.planted_4096()
     gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["planted_4096"]
@@ -93,11 +98,15 @@ def test_planted_4096_options(opts):
 
 
 def test_region_scans_on_power_law_core():
-    # forces region scans (whole_max small) on a power-law k-core
+    # graphs above whole_max: full-graph sweeps (scan_mode 0) or region scans
+    # with the sweep as fallback (scan_mode 1), on a power-law k-core
     g = gg.chung_lu(23, 20000, 2.5, 16.0, 1, 3, kcore=4, lcc=True)
     ref, _, _ = oracle.noi(g, 1)
-    for opts in [dict(whole_max=64), dict(whole_max=64, eager_blacklist=0),
-                 dict(whole_max=64, max_pops=50), dict(whole_max=64, use_pr=0)]:
+    for opts in [dict(whole_max=64), dict(whole_max=64, use_pr=0),
+                 dict(whole_max=64, sweep_handoff=4),
+                 dict(whole_max=64, scan_mode=1), dict(whole_max=64, scan_mode=1, eager_blacklist=0),
+                 dict(whole_max=64, scan_mode=1, max_pops=50),
+                 dict(whole_max=64, scan_mode=1, use_pr=0)]:
         announce("chung_lu 20000", opts)
         lam, side, st = solve(g, **opts)
         assert lam == ref, opts
@@ -187,3 +196,29 @@ def test_batched_small_against_noi():
     for i in (0, 5, 24, 26):
         lam, _, _ = solve(graphs[i])
         assert lam == lams[i]
+
+
+def test_sweep_on_weighted_graphs_with_wide_buckets():
+    # bound above 4096 makes the sweep's bucket queue hold several keys per
+    # bucket (exact maximum search inside the top bucket)
+    rng = np.random.default_rng(3)
+    for t in range(6):
+        n = int(rng.integers(200, 1500))
+        g = random_graph(rng, n, float(rng.uniform(0.02, 0.1)), 5000)
+        ref, _, _ = oracle.noi(g, 1)
+        announce("wide buckets", t, n, ref)
+        for opts in [dict(whole_max=16), dict(whole_max=16, use_pr=0),
+                     dict(whole_max=16, sweep_handoff=2)]:
+            lam, side, _ = solve(g, **opts)
+            assert lam == ref, (t, opts)
+            check_side(g, lam, side)
+
+
+def test_sweep_on_larger_power_law_graph():
+    g = gg.chung_lu(29, 200000, 2.5, 16.0, 1, 1, kcore=5, lcc=True)
+    ref, _, _ = oracle.noi(g, 1)
+    announce("chung_lu 200000 5-core", g.n, g.m, ref)
+    lam, side, st = solve(g)
+    assert lam == ref
+    check_side(g, lam, side)
+    assert st["rounds"] <= 6
