@@ -129,8 +129,8 @@ struct Workspace {
   int64_t capN = 0, capE = 0, capG = 0;
   std::vector<void*> allocs;
   // vertex arrays
-  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *fb_st, *capq, *sw_seg, *newid, *map,
-      *ogid;
+  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *fb_st, *capq, *capx, *sw_seg, *newid,
+      *map, *ogid;
   SweepCtl* sweep;
   SweepCtl* sweep_host = nullptr;
   int64_t* sw_info;
@@ -167,7 +167,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
   size_t b = 0;
-  b += align_up((N + 1) * 4) * 16 + align_up(sizeof(SweepCtl)) + align_up((G + 1) * 24);
+  b += align_up((N + 1) * 4) * 17 + align_up(sizeof(SweepCtl)) + align_up((G + 1) * 24);
   b += align_up((N + 2) * 8) * 2;
   b += align_up(E * 4) * 3 + align_up((E + 64) * 8) * 2 + align_up(E * 4) * 2;
   b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 15 + align_up((G + 1) * 8) * 2 +
@@ -213,6 +213,7 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.ogid, (N + 1) * 4);
   ALLOC(ws.fb_st, (N + 1) * 4);
   ALLOC(ws.capq, (N + 1) * 4);
+  ALLOC(ws.capx, (N + 1) * 4);
   ALLOC(ws.sw_seg, (N + 1) * 4);
   ALLOC(ws.sweep, sizeof(SweepCtl));
   ALLOC(ws.sw_info, (G + 1) * 3 * 8);
@@ -335,7 +336,7 @@ struct Solver {
                   const int32_t* col, const int32_t* w, int64_t nnz, const GraphState& S,
                   mc_stats* st) {
     if (lam <= 0 || ng < 2) return MC_OK;
-    SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_st, ws.fb_step, ws.capq,
+    SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_st, ws.fb_step, ws.capq, ws.capx,
                 (int2*)ws.keys_alt, ws.capE + 64, ws.sw_seg, ws.sweep, v0, ng, lam, 0, 1, 1, 0};
     const int lb = bitlen((uint64_t)(lam - 1));
     A.shift = lb > 12 ? lb - 12 : 0;
@@ -362,16 +363,23 @@ struct Solver {
       if (c.status != SW_BIG) return MC_EINTERNAL;
       const int32_t bh = c.cap_head, bt = c.cap_tail;
       const int64_t bsz = bt - bh;
+      MC_HIP(hipMemsetAsync(&ws.sweep->batch_sum, 0, 24, s));
+      hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
+      int64_t deg_sum = 0;
+      if (timer().on) {
+        MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &ws.sweep->batch_deg, 8, hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        deg_sum = ws.sweep_host->batch_deg;
+      }
       {
-        // a batch reads its vertices' rows once: adjacency plus state of
-        // every neighbour
-        TimedScope t("sweep_big", (double)bsz * 24);
-        MC_HIP(hipMemsetAsync(&ws.sweep->batch_sum, 0, 16, s));
-        hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
+        // every row of the batch once (col, w: 8 B per entry), the state
+        // gather and the r read-modify-write of each neighbour (12 B), and
+        // per batch vertex its FIFO slot and row bounds (20 B)
+        TimedScope t("sweep_relax", (double)deg_sum * 20 + (double)bsz * 20);
         hipLaunchKernelGGL(k_sweep_big_relax, dim3(grid_for(bsz * 64, TB, num_cu * 32)), dim3(TB), 0, s, A, bh,
                            bt);
-        hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
       }
+      hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
       {
         // exact queue rebuild: two passes over the graph's vertices
         TimedScope t("sweep_rebuild", (double)ng * 16);
@@ -381,14 +389,15 @@ struct Solver {
         hipLaunchKernelGGL(k_sweep_rb_fill, dim3((ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);
       }
     }
+    hipLaunchKernelGGL(k_sweep_unite, dim3(grid_for(ng, TB, num_cu * 16)), dim3(TB), 0, s, A);
     hipLaunchKernelGGL(k_sweep_report, dim3(1), dim3(64), 0, s, ws.sweep, g, S);
     if (debug_on()) {
       hipStreamSynchronize(s);
       SweepCtl c;
       hipMemcpy(&c, ws.sweep, sizeof(SweepCtl), hipMemcpyDeviceToHost);
       fprintf(stderr, "[mc] sweep g=%d v0=%d ng=%d lam=%lld visited=%d singles=%d batches=%d big=%d "
-              "rebuilds=%d unions=%lld best_alpha=%lld step=%d\n", g, v0, ng, (long long)lam, c.visited,
-              c.singles, c.batches, c.big_batches, c.rebuilds, (long long)c.unions, (long long)c.best_alpha,
+              "rebuilds=%d unions=%d best_alpha=%lld step=%d\n", g, v0, ng, (long long)lam, c.visited,
+              c.singles, c.batches, c.big_batches, c.rebuilds, c.cap_tail, (long long)c.best_alpha,
               c.best_step);
     }
     (void)nnz;
@@ -401,11 +410,14 @@ struct Solver {
     const int32_t N = P.n;
     const int64_t E = P.nnz;
     const bool want_side = side != nullptr;
-    hipDeviceProp_t prop;
     int dev = 0;
     MC_HIP(hipGetDevice(&dev));
-    MC_HIP(hipGetDeviceProperties(&prop, dev));
-    num_cu = prop.multiProcessorCount;
+    static int cached_dev = -1, cached_cu = 0;
+    if (cached_dev != dev) {
+      MC_HIP(hipDeviceGetAttribute(&cached_cu, hipDeviceAttributeMultiprocessorCount, dev));
+      cached_dev = dev;
+    }
+    num_cu = cached_cu;
     static bool attrs_set = false;
     if (!attrs_set) {
       MC_HIP(hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_L>,
@@ -496,17 +508,22 @@ struct Solver {
       ++round;
       // per-round control fields
       MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
-      // plan: whole-graph scans for small graphs (two map sizes), region scans otherwise
-      hipLaunchKernelGGL(k_plan_split, grid(G), dim3(TB), 0, s, G, S, whole_small, whole_max,
-                         ws.whole2, ws.ctl);
+      hipLaunchKernelGGL(k_round_reset, grid(G), dim3(TB), 0, s, G, S);
       hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
       fill<int32_t>(ws.claim, -1, n, s);
       if (opt.use_pr) {
         // src, col, w per entry; both degrees for the half with u < v
         TimedScope t("pr", (double)nnz * 12 + (double)nnz * 8);
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
-                           ws.lhat, ws.mode, ws.parent, ws.ucount, ws.ctl);
+                           ws.lhat, ws.active, ws.parent, ws.ucount, ws.ctl);
       }
+      // blocks left by the tests; graphs already at two blocks skip the scans
+      hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+      hipLaunchKernelGGL(k_count_roots, grid(n), dim3(TB), 0, s, n, ws.parent, gid, ws.nnew);
+      // plan: whole-graph scans for small graphs (two map sizes), sweeps or
+      // region scans otherwise
+      hipLaunchKernelGGL(k_plan_split, grid(G), dim3(TB), 0, s, G, S, whole_small, whole_max,
+                         ws.whole2, ws.ctl);
       // scans
       ScanArgs A{};
       A.n = n; A.rp = rp; A.col = col; A.w = w; A.cdeg = ws.cdeg; A.gid = gid;

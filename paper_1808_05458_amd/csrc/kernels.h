@@ -241,17 +241,26 @@ __global__ void k_side(SideArgs A) {
 // Round planning: graphs up to whole_small vertices are scanned whole with
 // the small LDS map (mode 1), up to whole_max with the large map (mode 3),
 // larger ones by region scans (mode 2).  Inactive graphs idle (mode 0).
-__global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32_t whole_max,
-                             int32_t* whole2, Ctl* ctl) {
+__global__ void k_round_reset(int32_t G, GraphState S) {
   for (int64_t g = gtid(); g < G; g += gstride()) {
     S.ucount[g] = 0;
     S.balpha[g] = ~0ull;
     S.bdeg[g] = ~0ull;
     S.rec_type[g] = REC_NONE;
     S.nnew[g] = 0;
+  }
+}
+
+// Mode 4: the Padberg-Rinaldi unions alone leave at most two blocks, so the
+// graph goes straight to contraction.  nnew holds the blocks after the tests.
+__global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32_t whole_max,
+                             int32_t* whole2, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
     uint8_t m = 0;
     if (S.active[g]) {
-      if (S.n[g] <= whole_small) {
+      if (S.nnew[g] <= 2) {
+        m = 4;
+      } else if (S.n[g] <= whole_small) {
         m = 1;
         S.whole[atomicAdd(&ctl->n_whole, 1)] = (int32_t)g;
       } else if (S.n[g] <= whole_max) {
@@ -263,6 +272,7 @@ __global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32
       }
     }
     S.mode[g] = m;
+    S.nnew[g] = 0;
   }
 }
 
@@ -274,13 +284,13 @@ __global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32
 __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                      const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
                      const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
-                     const uint8_t* __restrict__ mode, int32_t* parent, int32_t* ucount, Ctl* ctl) {
+                     const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount, Ctl* ctl) {
   int64_t local = 0;
   for (int64_t e = gtid(); e < nnz; e += gstride()) {
     int32_t u = src[e], v = col[e];
     if (u >= v) continue;
     int32_t g = gid[u];
-    if (!mode[g]) continue;
+    if (!active[g]) continue;
     int64_t c = w[e];
     if (c >= lhat[g] || 2 * c > cdeg[u] || 2 * c > cdeg[v]) {
       uf_union(parent, u, v);
@@ -317,7 +327,7 @@ __global__ void k_sweep_report(const SweepCtl* c, int32_t g, GraphState S) {
     S.fb_k[g] = c->best_step;
     atomic_min_u64(S.balpha + g, ((uint64_t)c->best_alpha << 32) | (uint32_t)SWEEP_SID);
   }
-  atomicAdd(S.ucount + g, (int32_t)(c->unions > 0x3FFFFFFF ? 0x3FFFFFFF : c->unions));
+  atomicAdd(S.ucount + g, c->cap_tail);  // every crossing vertex entered the FIFO once
 }
 
 // ------------------------------------------------------------ compaction

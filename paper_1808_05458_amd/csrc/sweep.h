@@ -43,7 +43,7 @@ struct SweepCtl {
   int64_t pool_next;
   int64_t batch_sum;           // grid-wide batch: sum c(x) - 2 r(x)
   int64_t batch_internal;      // grid-wide batch: 2 w(inside)
-  int64_t unions;
+  int64_t batch_deg;           // grid-wide batch: sum of row lengths
   int32_t singles, batches, big_batches, rebuilds;
   uint64_t bitmap[SWEEP_BUCKETS / 64];
   int32_t head[SWEEP_BUCKETS];     // recent pushes (lists through the pool)
@@ -62,6 +62,7 @@ struct SweepArgs {
   int32_t* st;       // 0 unseen, 1 frontier, 2 visited
   int32_t* step;     // visit stamp (batch number), 0 = not visited
   int32_t* capq;     // capped FIFO (each vertex enters at most once)
+  int32_t* capx;     // the vertex whose edge made capq[i] cross (united later)
   int2* pool;        // bucket entries (vertex, next)
   int64_t pool_cap;
   int32_t* seg;      // bucket segments written by the rebuild
@@ -87,8 +88,10 @@ __device__ __forceinline__ void pool_put(const SweepArgs& A, int64_t idx, int32_
 // the wave calls this (act = false for idle lanes) so that queue and counter
 // updates are aggregated per wave.  Returns the weight to add to the
 // batch-internal sum (edge inside the batch).
+template <bool PUSH = true>
 __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, int32_t y, int32_t c,
-                                               int32_t stamp, bool act) {
+                                               int32_t stamp, bool act, int32_t* wbuf = nullptr,
+                                               int32_t* wcnt = nullptr) {
   const int lane = lane_id();
   int64_t internal = 0;
   bool cross = false, push = false;
@@ -103,27 +106,36 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, in
       nw = (int64_t)old + c;
       if (s == 0) st_relaxed(A.st + y, 1);
       cross = old < A.lam && A.lam <= nw;
-      push = nw < A.lam;
+      push = PUSH && nw < A.lam;
     }
   }
-  // crossings: unite, and append y to the capped FIFO
+  // crossings: unite, and append y to the capped FIFO (through a per-wave
+  // LDS buffer when one is given)
   const uint64_t cm = ballot(cross);
-  if (cm) {
+  if (cm && wbuf) {
+    const int32_t at = *wcnt;
+    if (cross) {
+      const int32_t k = at + popc64(cm & lanemask_lt());
+      wbuf[2 * k] = y;
+      wbuf[2 * k + 1] = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) *wcnt = at + popc64(cm);
+    __builtin_amdgcn_wave_barrier();
+  } else if (cm) {
     const int leader = __builtin_ctzll(cm);
     int32_t base = 0;
-    if (lane == leader) {
-      base = atomicAdd(&A.ctl->cap_tail, popc64(cm));
-      atomicAdd((unsigned long long*)&A.ctl->unions, (unsigned long long)popc64(cm));
-    }
+    if (lane == leader) base = atomicAdd(&A.ctl->cap_tail, popc64(cm));
     base = shfl(base, leader);
     if (cross) {
-      A.capq[base + popc64(cm & lanemask_lt())] = y;
-      uf_union(A.parent, x, y);
+      const int32_t q = base + popc64(cm & lanemask_lt());
+      A.capq[q] = y;
+      A.capx[q] = x;
     }
   }
   // pushes below the cap: one pool reservation per wave, then one list
   // splice per distinct bucket
-  uint64_t pm = ballot(push);
+  uint64_t pm = PUSH ? ballot(push) : 0ull;
   if (pm) {
     const int leader = __builtin_ctzll(pm);
     int64_t pbase = 0;
@@ -181,7 +193,7 @@ __global__ void k_sweep_init(SweepArgs A) {
     c->status = SW_RUNNING;
     c->pool_next = 1;
     c->batch_sum = c->batch_internal = 0;
-    c->unions = 0;
+    c->batch_deg = 0;
     c->singles = c->batches = c->big_batches = c->rebuilds = 0;
   }
 }
@@ -362,7 +374,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
         sum = A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
       }
       size = 1;
-      __threadfence();
+      __threadfence_block();
       __syncthreads();
       const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
       for (int64_t base = e0 + wave * 64; base < e1; base += SWEEP_THREADS) {
@@ -379,7 +391,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
         st_relaxed(A.step + x, stamp);
         sum += A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
       }
-      __threadfence();
+      __threadfence_block();
       __syncthreads();
       for (int32_t i = h + wave; i < t; i += nwaves) {
         const int32_t x = ld_relaxed(A.capq + i);
@@ -394,7 +406,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
     sum = wave_sum_i64(sum);
     internal = wave_sum_i64(internal);
     if (lane == 0) { sh_sum[wave] = sum; sh_int[wave] = internal; }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
     if (threadIdx.x == 0) {
       int64_t s = 0, in = 0;
@@ -402,33 +414,67 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
       if (cmd == 1) c->cap_head = sh_t;
       sweep_close_batch(c, A.ng, s, in, size, stamp);
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
   }
+}
+
+// The crossing edges found by the sweep, united after it: (capx[i], capq[i]).
+__global__ void k_sweep_unite(SweepArgs A) {
+  const int32_t n = A.ctl->cap_tail;
+  for (int64_t i = gtid(); i < n; i += gstride()) uf_union(A.parent, A.capx[i], A.capq[i]);
 }
 
 // Grid-wide batch [h, t): mark every vertex visited.
 __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
   SweepCtl* c = A.ctl;
   const int32_t stamp = c->step + 1;
-  int64_t sum = 0;
+  int64_t sum = 0, deg = 0;
   for (int64_t i = h + gtid(); i - lane_id() < t; i += gstride()) {  // wave-uniform bound
     if (i < t) {
       int32_t x = A.capq[i];
       A.st[x] = 2;
       A.step[x] = stamp;
       sum += A.cdeg[x] - 2 * (int64_t)A.r[x];
+      deg += A.rp[x + 1] - A.rp[x];
     }
   }
   sum = wave_sum_i64(sum);
+  deg = wave_sum_i64(deg);
   if (lane_id() == 0 && sum) atomicAdd((unsigned long long*)&c->batch_sum, (unsigned long long)sum);
+  if (lane_id() == 0 && deg) atomicAdd((unsigned long long*)&c->batch_deg, (unsigned long long)deg);
 }
 
 // Grid-wide batch [h, t): relax every edge of the batch, one wave per vertex.
-__global__ void k_sweep_big_relax(SweepArgs A, int32_t h, int32_t t) {
+// No queue pushes (the queue is rebuilt exactly after the batch); crossing
+// vertices collect in a per-wave LDS buffer and go to the FIFO in blocks.
+constexpr int BIG_BUF = 256;
+__device__ __forceinline__ void flush_wave_buf(const SweepArgs& A, int32_t* wbuf, int32_t* wcnt) {
+  const int lane = lane_id();
+  const int32_t cnt = *wcnt;
+  if (cnt == 0) return;
+  int32_t base = 0;
+  if (lane == 0) base = atomicAdd(&A.ctl->cap_tail, cnt);
+  base = shfl(base, 0);
+  for (int32_t i = lane; i < cnt; i += 64) {
+    A.capq[base + i] = wbuf[2 * i];
+    A.capx[base + i] = wbuf[2 * i + 1];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) *wcnt = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h, int32_t t) {
+  __shared__ int32_t buf[4][2 * BIG_BUF];
+  __shared__ int32_t cnt[4];
   SweepCtl* c = A.ctl;
   const int32_t stamp = c->step + 1;
-  const int lane = lane_id();
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int32_t* wbuf = buf[wave];
+  int32_t* wcnt = &cnt[wave];
+  if (lane == 0) *wcnt = 0;
+  __builtin_amdgcn_wave_barrier();
   const int64_t wave0 = gtid() >> 6, nw = gstride() >> 6;
   int64_t internal = 0;
   for (int64_t i = h + wave0; i < t; i += nw) {
@@ -437,9 +483,11 @@ __global__ void k_sweep_big_relax(SweepArgs A, int32_t h, int32_t t) {
     for (int64_t base = e0; base < e1; base += 64) {
       const int64_t e = base + lane;
       const bool act = e < e1;
-      internal += sweep_relax(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+      internal += sweep_relax<false>(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act, wbuf, wcnt);
+      if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
     }
   }
+  flush_wave_buf(A, wbuf, wcnt);
   internal = wave_sum_i64(internal);
   if (lane == 0 && internal) atomicAdd((unsigned long long*)&c->batch_internal, (unsigned long long)internal);
 }
