@@ -92,6 +92,22 @@ __device__ __forceinline__ void atomic_min_u64(uint64_t* p, uint64_t v) {
   __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// arr[key] += val for every active lane, with one atomic per distinct key
+// in the wave (lanes of a wave usually share the graph id).  Must be called
+// by all lanes of the wave.
+__device__ __forceinline__ void wave_add_by_key(int32_t* arr, int32_t key, int32_t val, bool active) {
+  uint64_t todo = ballot(active);
+  while (todo) {
+    const int32_t k0 = __shfl(key, __builtin_ctzll(todo), 64);
+    const bool mine = active && key == k0;
+    const uint64_t grp = ballot(mine);
+    todo &= ~grp;
+    int32_t sum = mine ? val : 0;
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane_id() == __builtin_ctzll(grp)) atomicAdd(arr + k0, sum);
+  }
+}
+
 // Grid-stride helpers
 __device__ __forceinline__ int64_t gtid() {
   return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -172,8 +172,11 @@ __global__ void k_union_pairs(const uint64_t* pairs, const Ctl* ctl, int64_t cap
 // Components per graph: disconnected graphs get lambda = 0 (section "Parallel
 // CAPFOREST": a disconnected graph leaves vertices unvisited).
 __global__ void k_count_roots(int32_t n, const int32_t* parent, const int32_t* gid, int32_t* cnt) {
-  for (int64_t v = gtid(); v < n; v += gstride())
-    if (parent[v] == v) atomicAdd(cnt + gid[v], 1);
+  for (int64_t v = gtid(); v - lane_id() < n; v += gstride()) {  // wave-uniform bound
+    const bool ok = v < n;
+    const bool root = ok && parent[v] == v;
+    wave_add_by_key(cnt, ok ? gid[v] : -1, 1, root);
+  }
 }
 
 // ----------------------------------------------------- per-graph bookkeeping
@@ -286,17 +289,24 @@ __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t
                      const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
                      const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount, Ctl* ctl) {
   int64_t local = 0;
-  for (int64_t e = gtid(); e < nnz; e += gstride()) {
-    int32_t u = src[e], v = col[e];
-    if (u >= v) continue;
-    int32_t g = gid[u];
-    if (!active[g]) continue;
-    int64_t c = w[e];
-    if (c >= lhat[g] || 2 * c > cdeg[u] || 2 * c > cdeg[v]) {
-      uf_union(parent, u, v);
-      atomicAdd(ucount + g, 1);
-      ++local;
+  for (int64_t e = gtid(); e - lane_id() < nnz; e += gstride()) {  // wave-uniform bound
+    bool hit = false;
+    int32_t g = -1;
+    if (e < nnz) {
+      const int32_t u = src[e], v = col[e];
+      if (u < v) {
+        g = gid[u];
+        if (active[g]) {
+          const int64_t c = w[e];
+          if (c >= lhat[g] || 2 * c > cdeg[u] || 2 * c > cdeg[v]) {
+            uf_union(parent, u, v);
+            hit = true;
+            ++local;
+          }
+        }
+      }
     }
+    wave_add_by_key(ucount, g, 1, hit);
   }
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
@@ -344,12 +354,22 @@ struct RootFlag {
 
 __global__ void k_relabel(int32_t n, const int32_t* parent, const int32_t* gid, const int32_t* keep,
                           const int32_t* newid, int32_t* lab, int32_t* ngid, int32_t* nnew) {
-  for (int64_t v = gtid(); v < n; v += gstride()) {
-    int32_t g = gid[v];
-    int32_t r = parent[v];
-    if (!keep[g]) { lab[v] = -1; continue; }
-    lab[v] = newid[r];
-    if (r == v) { ngid[newid[v]] = g; atomicAdd(nnew + g, 1); }
+  for (int64_t v = gtid(); v - lane_id() < n; v += gstride()) {  // wave-uniform bound
+    const bool ok = v < n;
+    const int32_t g = ok ? gid[v] : -1;
+    const bool kept = ok && keep[g];
+    bool root = false;
+    if (ok) {
+      const int32_t r = parent[v];
+      if (!kept) {
+        lab[v] = -1;
+      } else {
+        lab[v] = newid[r];
+        root = r == v;
+        if (root) ngid[newid[v]] = g;
+      }
+    }
+    wave_add_by_key(nnew, g, 1, root);
   }
 }
 

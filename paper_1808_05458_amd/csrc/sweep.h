@@ -75,6 +75,23 @@ struct SweepArgs {
   int32_t big;       // batches above this size go grid-wide
 };
 
+// The queue and FIFO bookkeeping, addressed through generic pointers: the
+// persistent workgroup works on LDS copies, the grid-wide kernels on the
+// global SweepCtl.
+struct SweepQ {
+  int32_t* cap_head;
+  int32_t* cap_tail;
+  int64_t* pool_next;
+  uint64_t* bitmap;
+  int32_t* head;
+  int32_t* seg_cur;
+  int32_t* seg_end;
+};
+
+__device__ __forceinline__ SweepQ global_q(SweepCtl* c) {
+  return SweepQ{&c->cap_head, &c->cap_tail, &c->pool_next, c->bitmap, c->head, c->seg_cur, c->seg_end};
+}
+
 __device__ __forceinline__ int2 pool_at(const SweepArgs& A, int32_t idx) {
   uint64_t u = ld_relaxed((const uint64_t*)(A.pool + idx));
   return make_int2((int32_t)(uint32_t)u, (int32_t)(u >> 32));
@@ -89,8 +106,8 @@ __device__ __forceinline__ void pool_put(const SweepArgs& A, int64_t idx, int32_
 // updates are aggregated per wave.  Returns the weight to add to the
 // batch-internal sum (edge inside the batch).
 template <bool PUSH = true>
-__device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, int32_t y, int32_t c,
-                                               int32_t stamp, bool act, int32_t* wbuf = nullptr,
+__device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ& q, int32_t x, int32_t y,
+                                               int32_t c, int32_t stamp, bool act, int32_t* wbuf = nullptr,
                                                int32_t* wcnt = nullptr) {
   const int lane = lane_id();
   int64_t internal = 0;
@@ -125,7 +142,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, in
   } else if (cm) {
     const int leader = __builtin_ctzll(cm);
     int32_t base = 0;
-    if (lane == leader) base = atomicAdd(&A.ctl->cap_tail, popc64(cm));
+    if (lane == leader) base = atomicAdd(q.cap_tail, popc64(cm));
     base = shfl(base, leader);
     if (cross) {
       const int32_t q = base + popc64(cm & lanemask_lt());
@@ -140,7 +157,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, in
     const int leader = __builtin_ctzll(pm);
     int64_t pbase = 0;
     if (lane == leader)
-      pbase = (int64_t)atomicAdd((unsigned long long*)&A.ctl->pool_next, (unsigned long long)popc64(pm));
+      pbase = (int64_t)atomicAdd((unsigned long long*)q.pool_next, (unsigned long long)popc64(pm));
     pbase = shfl(pbase, leader);
     const int64_t idx = pbase + popc64(pm & lanemask_lt());
     const int32_t b = push ? (int32_t)(nw >> A.shift) : -1;
@@ -156,10 +173,10 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, int32_t x, in
       // the next lower lane of its group, the lowest to the old head
       int32_t old_head = -1;
       if (lane == hi) {
-        if (idx < A.pool_cap) old_head = atomicExch(&A.ctl->head[b0], (int32_t)idx);
+        if (idx < A.pool_cap) old_head = atomicExch(&q.head[b0], (int32_t)idx);
         const uint64_t wbit = 1ull << (b0 & 63);
-        if (!(ld_relaxed(&A.ctl->bitmap[b0 >> 6]) & wbit))
-          atomicOr((unsigned long long*)&A.ctl->bitmap[b0 >> 6], wbit);
+        if (!(ld_relaxed(&q.bitmap[b0 >> 6]) & wbit))
+          atomicOr((unsigned long long*)&q.bitmap[b0 >> 6], wbit);
       }
       old_head = shfl(old_head, hi);
       const int64_t prev_idx = shfl(idx, prev_lane);
@@ -229,11 +246,10 @@ __device__ __forceinline__ bool live_in_bucket(const SweepArgs& A, int32_t v, in
 // cursor only moves forward).  With one key per bucket the first live entry
 // is a maximum; with wider buckets the largest live key of the whole bucket
 // is taken (the segment entry is then tombstoned).  -1: queue empty.
-__device__ int32_t sweep_pop_wave0(const SweepArgs& A) {
-  SweepCtl* c = A.ctl;
+__device__ int32_t sweep_pop_wave0(const SweepArgs& A, const SweepQ& q) {
   const int lane = lane_id();
   while (true) {
-    uint64_t word = lane < A.nwords ? ld_relaxed(&c->bitmap[lane]) : 0ull;
+    uint64_t word = lane < A.nwords ? ld_relaxed(&q.bitmap[lane]) : 0ull;
     uint64_t m = ballot(word != 0);
     if (m == 0) return -1;
     const int bw = 63 - __builtin_clzll(m);
@@ -242,19 +258,19 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A) {
     int32_t x = -1;
     if (A.shift == 0) {
       if (lane == 0) {
-        int32_t idx = ld_relaxed(&c->head[b]);
+        int32_t idx = ld_relaxed(&q.head[b]);
         while (idx >= 0) {
           int2 e = pool_at(A, idx);
           idx = e.y;
           int32_t k;
           if (live_in_bucket(A, e.x, b, k)) { x = e.x; break; }
         }
-        st_relaxed(&c->head[b], idx);
+        st_relaxed(&q.head[b], idx);
       }
       x = shfl(x, 0);
       if (x >= 0) return x;
-      int32_t cur = ld_relaxed(&c->seg_cur[b]);
-      const int32_t end = ld_relaxed(&c->seg_end[b]);
+      int32_t cur = ld_relaxed(&q.seg_cur[b]);
+      const int32_t end = ld_relaxed(&q.seg_end[b]);
       while (cur < end) {
         const int32_t i = cur + lane;
         const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
@@ -268,19 +284,19 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A) {
         }
         cur += 64;
       }
-      if (lane == 0) st_relaxed(&c->seg_cur[b], cur < end ? cur : end);
+      if (lane == 0) st_relaxed(&q.seg_cur[b], cur < end ? cur : end);
       if (x >= 0) return x;
     } else {
       // wide bucket: exact maximum over the list and the segment
       int64_t best_key = -1;
       int32_t best_v = -1, best_idx = -1, best_prev = -1;
       if (lane == 0) {
-        int32_t idx = ld_relaxed(&c->head[b]), prev = -1;
+        int32_t idx = ld_relaxed(&q.head[b]), prev = -1;
         while (idx >= 0) {
           int2 e = pool_at(A, idx);
           int32_t k;
           if (!live_in_bucket(A, e.x, b, k)) {
-            if (prev < 0) st_relaxed(&c->head[b], e.y);
+            if (prev < 0) st_relaxed(&q.head[b], e.y);
             else pool_put(A, prev, pool_at(A, prev).x, e.y);
           } else {
             if (k > best_key) { best_key = k; best_v = e.x; best_idx = idx; best_prev = prev; }
@@ -293,8 +309,8 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A) {
       best_v = shfl(best_v, 0);
       int64_t seg_best = -1;
       int32_t seg_pos = -1;
-      const int32_t cur0 = ld_relaxed(&c->seg_cur[b]);
-      const int32_t end = ld_relaxed(&c->seg_end[b]);
+      const int32_t cur0 = ld_relaxed(&q.seg_cur[b]);
+      const int32_t end = ld_relaxed(&q.seg_end[b]);
       for (int32_t base = cur0; base < end; base += 64) {
         const int32_t i = base + lane;
         const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
@@ -311,76 +327,171 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A) {
         x = best_v;
         if (lane == 0) {
           const int32_t nx = pool_at(A, best_idx).y;
-          if (best_prev < 0) st_relaxed(&c->head[b], nx);
+          if (best_prev < 0) st_relaxed(&q.head[b], nx);
           else pool_put(A, best_prev, pool_at(A, best_prev).x, nx);
         }
       }
       if (x >= 0) return x;
       if (lane == 0) {
-        st_relaxed(&c->head[b], -1);
-        st_relaxed(&c->seg_cur[b], end);
+        st_relaxed(&q.head[b], -1);
+        st_relaxed(&q.seg_cur[b], end);
       }
     }
     // the bucket holds no live entry
-    if (lane == 0) atomicAnd((unsigned long long*)&c->bitmap[bw], ~(1ull << (b & 63)));
+    if (lane == 0) atomicAnd((unsigned long long*)&q.bitmap[bw], ~(1ull << (b & 63)));
   }
 }
 
-// The persistent workgroup.  Exits with SW_DONE (queue empty) or SW_BIG (a
-// batch larger than A.big is pending; cap_head..cap_tail untouched).
+constexpr int FAST_BATCH = 32;     // batches up to this size run on wave 0 alone
+constexpr int64_t FAST_DEG = 2048;  // single pops with rows up to this run on wave 0 alone
+
+// Relax the rows of `cnt` batch vertices held by lanes 0..cnt-1 of `xs` with
+// one wave; returns the batch-internal weight of this wave's lanes.
+__device__ __forceinline__ int64_t wave_relax_rows(const SweepArgs& A, const SweepQ& q, int32_t xs, int cnt,
+                                                   int32_t stamp) {
+  const int lane = lane_id();
+  int64_t internal = 0;
+  for (int j = 0; j < cnt; ++j) {
+    const int32_t x = shfl(xs, j);
+    const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
+    for (int64_t base = e0; base < e1; base += 64) {
+      const int64_t e = base + lane;
+      const bool act = e < e1;
+      internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+    }
+  }
+  return internal;
+}
+
+// The persistent workgroup.  Wave 0 drives: it pops, and runs single pops
+// with short rows and small batches by itself.  Wide steps (a long row, a
+// larger batch) are shared with the other waves, which wait at a barrier for
+// the next command.  Exits with SW_DONE (queue empty) or SW_BIG (a batch
+// larger than A.big is pending; cap_head..cap_tail untouched).
+enum : int32_t { CMD_EXIT_DONE = 0, CMD_BATCH = 1, CMD_EXIT_BIG = 2, CMD_SINGLE = 3 };
+
 __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
   __shared__ int32_t sh_x, sh_cmd, sh_h, sh_t, sh_stamp;
   __shared__ int64_t sh_sum[SWEEP_THREADS / 64], sh_int[SWEEP_THREADS / 64];
+  // queue state, resident in LDS while this workgroup runs
+  __shared__ int32_t l_head[SWEEP_BUCKETS], l_cur[SWEEP_BUCKETS], l_end[SWEEP_BUCKETS];
+  __shared__ uint64_t l_bitmap[SWEEP_BUCKETS / 64];
+  __shared__ int32_t l_cap_head, l_cap_tail;
+  __shared__ int64_t l_pool_next;
   SweepCtl* c = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int nwaves = SWEEP_THREADS / 64;
+  for (int i = threadIdx.x; i < A.nb; i += SWEEP_THREADS) {
+    l_head[i] = c->head[i];
+    l_cur[i] = c->seg_cur[i];
+    l_end[i] = c->seg_end[i];
+  }
+  for (int i = threadIdx.x; i < SWEEP_BUCKETS / 64; i += SWEEP_THREADS) l_bitmap[i] = c->bitmap[i];
+  // bookkeeping of thread 0 (the only thread that closes batches)
+  int32_t step = 0, visited = 0, best_step = 0, singles = 0, batches = 0;
+  int64_t alpha = 0, best_alpha = 0;
+  if (threadIdx.x == 0) {
+    l_cap_head = c->cap_head;
+    l_cap_tail = c->cap_tail;
+    l_pool_next = c->pool_next;
+    step = c->step;
+    visited = c->visited;
+    alpha = c->alpha;
+    best_alpha = c->best_alpha;
+    best_step = c->best_step;
+    singles = c->singles;
+    batches = c->batches;
+  }
+  __syncthreads();
+  const SweepQ q{&l_cap_head, &l_cap_tail, &l_pool_next, l_bitmap, l_head, l_cur, l_end};
+  auto close = [&](int64_t sum, int64_t internal, int32_t size, int32_t stamp) {
+    alpha += sum - internal;
+    visited += size;
+    if (visited < A.ng && alpha < best_alpha) {
+      best_alpha = alpha;
+      best_step = stamp;
+    }
+  };
+  int exit_cmd = -1;
   while (true) {
     if (wave == 0) {
-      const int32_t h = ld_relaxed(&c->cap_head), t = ld_relaxed(&c->cap_tail);
-      int cmd;
-      int32_t x = -1;
-      if (t > h) {
-        cmd = (t - h > A.big) ? 2 : 1;  // 2: hand the batch to the grid
-      } else {
-        x = sweep_pop_wave0(A);
-        cmd = x < 0 ? 0 : 3;
-      }
-      if (lane == 0) {
-        sh_cmd = cmd;
-        sh_x = x;
-        sh_h = h;
-        sh_t = t;
-        if (cmd == 1 || cmd == 3) {
-          sh_stamp = c->step + 1;
-          c->step = c->step + 1;
-          if (cmd == 1) c->batches += 1; else c->singles += 1;
+      // fast loop: steps that one wave handles without barriers
+      int cmd = -1;
+      while (cmd < 0) {
+        const int32_t h = ld_relaxed(q.cap_head), t = ld_relaxed(q.cap_tail);
+        const int32_t stamp = shfl(step, 0) + 1;
+        if (t > h) {
+          const int32_t size = t - h;
+          if (size > A.big) { cmd = CMD_EXIT_BIG; break; }
+          if (size > FAST_BATCH) {
+            if (lane == 0) { sh_h = h; sh_t = t; sh_stamp = stamp; step = stamp; batches += 1; }
+            cmd = CMD_BATCH;
+            break;
+          }
+          int32_t xs = -1;
+          int64_t sum = 0;
+          if (lane < size) {
+            xs = ld_relaxed(A.capq + h + lane);
+            st_relaxed(A.st + xs, 2);
+            st_relaxed(A.step + xs, stamp);
+            sum = A.cdeg[xs] - 2 * (int64_t)ld_relaxed(A.r + xs);
+          }
+          // the marks must be visible before the rows are relaxed (edges
+          // inside the batch are recognised by their stamp)
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          int64_t internal = wave_relax_rows(A, q, xs, size, stamp);
+          sum = wave_sum_i64(sum);
+          internal = wave_sum_i64(internal);
+          if (lane == 0) {
+            step = stamp;
+            batches += 1;
+            *q.cap_head = t;
+            close(sum, internal, size, stamp);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        } else {
+          const int32_t x = sweep_pop_wave0(A, q);
+          if (x < 0) { cmd = CMD_EXIT_DONE; break; }
+          const int64_t deg = A.rp[x + 1] - A.rp[x];
+          int64_t sum = 0;
+          if (lane == 0) {
+            st_relaxed(A.st + x, 2);
+            st_relaxed(A.step + x, stamp);
+            sum = A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
+          }
+          if (deg > FAST_DEG) {
+            if (lane == 0) { sh_x = x; sh_stamp = stamp; step = stamp; singles += 1; sh_sum[0] = sum; }
+            cmd = CMD_SINGLE;
+            break;
+          }
+          // a single vertex has no edge inside its batch (self-loops skipped)
+          int64_t internal = wave_relax_rows(A, q, lane == 0 ? x : -1, 1, stamp);
+          internal = wave_sum_i64(internal);
+          if (lane == 0) {
+            step = stamp;
+            singles += 1;
+            close(sum, internal, 1, stamp);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         }
       }
+      if (lane == 0) sh_cmd = cmd;
     }
+    __threadfence_block();
     __syncthreads();
     const int cmd = sh_cmd;
-    if (cmd == 0 || cmd == 2) {
-      if (threadIdx.x == 0) c->status = cmd == 0 ? SW_DONE : SW_BIG;
-      return;
-    }
+    if (cmd == CMD_EXIT_DONE || cmd == CMD_EXIT_BIG) { exit_cmd = cmd; break; }
+    // a wide step shared by all waves
     const int32_t stamp = sh_stamp;
     int64_t sum = 0, internal = 0;
-    int32_t size;
-    if (cmd == 3) {
+    int32_t size = 1;
+    if (cmd == CMD_SINGLE) {
       const int32_t x = sh_x;
-      if (threadIdx.x == 0) {
-        st_relaxed(A.st + x, 2);
-        st_relaxed(A.step + x, stamp);
-        sum = A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
-      }
-      size = 1;
-      __threadfence_block();
-      __syncthreads();
       const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
       for (int64_t base = e0 + wave * 64; base < e1; base += SWEEP_THREADS) {
         const int64_t e = base + lane;
         const bool act = e < e1;
-        internal += sweep_relax(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+        internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
       }
     } else {
       const int32_t h = sh_h, t = sh_t;
@@ -399,23 +510,48 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
         for (int64_t base = e0; base < e1; base += 64) {
           const int64_t e = base + lane;
           const bool act = e < e1;
-          internal += sweep_relax(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+          internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
         }
       }
     }
     sum = wave_sum_i64(sum);
     internal = wave_sum_i64(internal);
-    if (lane == 0) { sh_sum[wave] = sum; sh_int[wave] = internal; }
-    __threadfence_block();
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t s = 0, in = 0;
-      for (int i = 0; i < nwaves; ++i) { s += sh_sum[i]; in += sh_int[i]; }
-      if (cmd == 1) c->cap_head = sh_t;
-      sweep_close_batch(c, A.ng, s, in, size, stamp);
+    if (lane == 0) {
+      if (cmd == CMD_SINGLE) sh_sum[wave] = wave == 0 ? sh_sum[0] : 0;
+      else sh_sum[wave] = sum;
+      sh_int[wave] = internal;
     }
     __threadfence_block();
     __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t s2 = 0, in = 0;
+      for (int i = 0; i < nwaves; ++i) { s2 += sh_sum[i]; in += sh_int[i]; }
+      if (cmd == CMD_BATCH) *q.cap_head = sh_t;
+      close(s2, in, size, stamp);
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // write the state back for the host and the grid-wide kernels
+  for (int i = threadIdx.x; i < A.nb; i += SWEEP_THREADS) {
+    c->head[i] = l_head[i];
+    c->seg_cur[i] = l_cur[i];
+    c->seg_end[i] = l_end[i];
+  }
+  for (int i = threadIdx.x; i < SWEEP_BUCKETS / 64; i += SWEEP_THREADS) c->bitmap[i] = l_bitmap[i];
+  if (threadIdx.x == 0) {
+    c->cap_head = l_cap_head;
+    c->cap_tail = l_cap_tail;
+    c->pool_next = l_pool_next;
+    c->step = step;
+    c->visited = visited;
+    c->alpha = alpha;
+    c->best_alpha = best_alpha;
+    c->best_step = best_step;
+    c->singles = singles;
+    c->batches = batches;
+    c->status = exit_cmd == CMD_EXIT_DONE ? SW_DONE : SW_BIG;
   }
 }
 
@@ -476,6 +612,7 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
   if (lane == 0) *wcnt = 0;
   __builtin_amdgcn_wave_barrier();
   const int64_t wave0 = gtid() >> 6, nw = gstride() >> 6;
+  const SweepQ gq = global_q(c);
   int64_t internal = 0;
   for (int64_t i = h + wave0; i < t; i += nw) {
     const int32_t x = A.capq[i];
@@ -483,7 +620,7 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
     for (int64_t base = e0; base < e1; base += 64) {
       const int64_t e = base + lane;
       const bool act = e < e1;
-      internal += sweep_relax<false>(A, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act, wbuf, wcnt);
+      internal += sweep_relax<false>(A, gq, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act, wbuf, wcnt);
       if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
     }
   }
