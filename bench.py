@@ -92,14 +92,28 @@ def main():
     log("kernel classes: " + ", ".join(f"{c['name']}={c['ms'] / args.steps:.2f}ms"
                                       for c in sorted(classes, key=lambda c: -c["ms"])))
 
+    def rate(c):
+        per_launch_s = c["ms"] / 1000.0 / c["launches"]
+        per_launch_bytes = c["algo_bytes"] / c["launches"]
+        return per_launch_bytes / per_launch_s / 1e9, per_launch_bytes
+
     dom = max(classes, key=lambda c: c["ms"])
-    per_launch_s = dom["ms"] / 1000.0 / dom["launches"]
-    per_launch_bytes = dom["algo_bytes"] / dom["launches"]
-    achieved = per_launch_bytes / per_launch_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+    achieved, dom_bytes = rate(dom)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        tr = json.load(open(tpath)).get(dom["name"])
+        if tr:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
                 "kernel": dom["name"], "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
-                "launches_per_step": dom["launches"] / args.steps}
+                "launches_per_step": dom["launches"] / args.steps,
+                "algo_bytes_per_launch": dom_bytes,
+                "kernels": {c["name"]: {"ms_per_step": round(c["ms"] / args.steps, 3),
+                                        "GBps": round(rate(c)[0], 1),
+                                        "frac": round(rate(c)[0] / HBM_PEAK_GBS, 4)}
+                            for c in sorted(classes, key=lambda c: -c["ms"])[:8]}}
 
     verified = None
     if not args.no_verify:

@@ -90,7 +90,15 @@ struct Timer {
     hipEventRecord(b, s);
     pending.push_back({c, a, b, bytes});
   }
+  // bytes known only after a class's launches have run
+  void add_bytes(const char* name, double bytes) {
+    if (!on) return;
+    pending_bytes.push_back({cls(name), bytes});
+  }
+  std::vector<std::pair<int, double>> pending_bytes;
   void collect() {
+    for (auto& pb : pending_bytes) classes[pb.first].bytes += pb.second;
+    pending_bytes.clear();
     for (auto& p : pending) {
       float ms = 0;
       hipEventSynchronize(p.b);
@@ -351,6 +359,8 @@ struct Solver {
     hipLaunchKernelGGL(k_sweep_init, dim3(grid_for(std::max<int64_t>(ng, SWEEP_BUCKETS), TB, num_cu * 16)),
                        dim3(TB), 0, s, A);
     hipLaunchKernelGGL(k_sweep_seed, dim3(1), dim3(64), 0, s, A, start);
+    double big_deg = 0;
+    int64_t seq_vertices = ng;
     for (int iter = 0;; ++iter) {
       {
         TimedScope t("sweep_seq", 0.0);
@@ -370,6 +380,8 @@ struct Solver {
         MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &ws.sweep->batch_deg, 8, hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
         deg_sum = ws.sweep_host->batch_deg;
+        big_deg += (double)deg_sum;
+        seq_vertices -= bsz;
       }
       {
         // every row of the batch once (col, w: 8 B per entry), the state
@@ -388,6 +400,15 @@ struct Solver {
         hipLaunchKernelGGL(k_sweep_rb_scan, dim3(1), dim3(1024), 0, s, A);
         hipLaunchKernelGGL(k_sweep_rb_fill, dim3((ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);
       }
+    }
+    if (timer().on) {
+      // the sequential kernel relaxed every row the grid-wide batches did not
+      int64_t ends[2] = {0, 0};
+      MC_HIP(hipMemcpyAsync(&ends[0], rp + v0, 8, hipMemcpyDeviceToHost, s));
+      MC_HIP(hipMemcpyAsync(&ends[1], rp + v0 + ng, 8, hipMemcpyDeviceToHost, s));
+      MC_HIP(hipStreamSynchronize(s));
+      const double seq_rows = (double)(ends[1] - ends[0]) - big_deg;
+      timer().add_bytes("sweep_seq", seq_rows * 20 + (double)seq_vertices * 32);
     }
     hipLaunchKernelGGL(k_sweep_unite, dim3(grid_for(ng, TB, num_cu * 16)), dim3(TB), 0, s, A);
     hipLaunchKernelGGL(k_sweep_report, dim3(1), dim3(64), 0, s, ws.sweep, g, S);
