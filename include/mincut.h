@@ -82,13 +82,16 @@ typedef struct mc_options {
   int32_t timing;          /* 1: time kernel classes with HIP events (mc_timing) */
   int32_t force_fallback;  /* debug: region scans find nothing, so the
                               sequential fallback always runs */
-  int32_t whole_max;       /* graphs up to this size are scanned whole by one
-                              wave; 0 = default (6144) */
+  int32_t whole_max;       /* graphs up to this size are scanned whole inside
+                              one workgroup; 0 = default (8192) */
   int32_t lp_sweeps;       /* clustering sweeps per level when use_viecut */
-  int32_t scan_mode;       /* graphs above whole_max: 0 = one full-graph capped
-                              sweep per round (default); 1 = many concurrent
+  int32_t scan_mode;       /* 0 (default): full-graph capped sweeps (small
+                              graphs in LDS, large ones grid-wide);
+                              1: graphs above whole_max get many concurrent
                               bounded region scans (Algorithm 1), with the
-                              sweep as fallback when they find nothing */
+                              sweep as fallback when they find nothing;
+                              2: small graphs get one-pop-at-a-time scans
+                              with an LDS hash map (no batching) */
   int32_t sweep_handoff;   /* sweep batches above this many vertices run
                               grid-wide; 0 = default (512) */
   int32_t reserved[3];
@@ -125,6 +128,26 @@ int mc_mincut(const mc_graph* g, void* stream, const mc_options* opt, int64_t* l
  * on side 0.  MC_ENOCUT if any graph has fewer than two vertices. */
 int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, int64_t* lambdas,
                       uint8_t* sides, mc_stats* stats);
+
+/* Test hook for per-step parity: runs ingest and the first round's
+ * Padberg-Rinaldi tests and CAPFOREST scans (Algorithm 2, first loop
+ * iteration up to the contraction), then stops.  lhat_in (HOST int64[G] or
+ * NULL) caps each graph's starting bound (it must be the value of a real cut).
+ * labels (DEVICE int32[n_total]) receives the union-find root of every
+ * vertex, i.e. the blocks the round would contract; lhat_used (HOST
+ * int64[G]) the bound each graph's tests and scans used.  Contracting the
+ * blocks must keep every cut below that bound. */
+int mc_debug_first_round(const mc_batch* b, void* stream, const mc_options* opt, const int64_t* lhat_in,
+                          int32_t* labels, int64_t* lhat_used);
+
+/* Test hook for the contraction step alone (section "Parallel Graph
+ * Contraction"): labels (DEVICE int32[n], values in [0, n_new)) name each
+ * vertex's block; the contracted graph (one vertex per block, parallel
+ * edges summed, internal edges dropped, rows sorted by neighbour) is written
+ * to row_ptr_out (DEVICE int64[n_new+1]), col_out and w_out (DEVICE int32,
+ * at least g->nnz entries); *nnz_out (HOST) receives its entry count. */
+int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, void* stream,
+                      int64_t* row_ptr_out, int32_t* col_out, int32_t* w_out, int64_t* nnz_out);
 
 /* Device bytes the workspace needs for a packed problem of this size. */
 size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs);

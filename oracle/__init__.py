@@ -10,7 +10,8 @@ Routes (see ``oracle.cpp`` for the passages each follows):
   stoer_wagner(g)      O2
   noi(g, seed)         O3, sequential Nagamochi-Ono-Ibaraki
   cut_value(g, side)   c(A) by definition
-Per-step references for the GPU kernels are in ``oracle.steps``.
+  contract(g, labels)  G with every block of `labels` contracted to one
+                       vertex (Preliminaries, contraction G/(u,v)), numpy
 """
 from __future__ import annotations
 
@@ -109,3 +110,24 @@ def noi(g, seed: int = 0):
     _check(_load().mco_noi(g.n, _p(rp), _p(col), _p(w), ctypes.c_uint64(seed), _p(lam),
                            _p(side), _p(rounds)), "noi")
     return int(lam[0]), side, int(rounds[0])
+
+
+def contract(g, labels):
+    """Contract every block of `labels` (any integer per vertex; equal values
+    form a block) into one vertex: parallel edges summed, edges inside a block
+    dropped (Preliminaries, contraction G/(u,v)).  Returns (graph, block id
+    per vertex); blocks are numbered in order of their smallest label."""
+    import graphgen as gg
+    lab = np.asarray(labels)
+    uniq, blk = np.unique(lab, return_inverse=True)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    a, b = blk[src], blk[g.col]
+    keep = a < b
+    if not keep.any():
+        return gg.Graph(len(uniq), np.zeros(len(uniq) + 1, np.int64), np.zeros(0, np.int32),
+                        np.zeros(0, np.int32), "contracted"), blk
+    pairs = np.stack([a[keep], b[keep]], 1)
+    keys, inv = np.unique(pairs, axis=0, return_inverse=True)
+    wsum = np.zeros(len(keys), np.int64)
+    np.add.at(wsum, inv.reshape(-1), g.w[keep].astype(np.int64))
+    return gg.from_edges(len(uniq), keys, wsum, name="contracted"), blk

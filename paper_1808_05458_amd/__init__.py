@@ -113,6 +113,10 @@ def _load():
     lib.mc_mincut.restype = ctypes.c_int
     lib.mc_mincut_batched.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_mincut_batched.restype = ctypes.c_int
+    lib.mc_debug_first_round.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mc_debug_first_round.restype = ctypes.c_int
+    lib.mc_debug_contract.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+    lib.mc_debug_contract.restype = ctypes.c_int
     lib.mc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.mc_workspace_bytes.restype = ctypes.c_size_t
     lib.mc_release.argtypes = []
@@ -201,6 +205,52 @@ def mincut_batched(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool =
     if rc != MC_OK:
         raise MincutError(rc, "mc_mincut_batched")
     return lams, sides, st.as_dict()
+
+
+def debug_first_round(row_ptr, col, w, vtx_off, *, lhat_in=None, stream=None,
+                      opts: Optional[Options] = None, **kw):
+    """Union-find roots after the first round's tests and scans (blocks that
+    round would contract) and the bound each graph used."""
+    import torch
+    lib = _load()
+    voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    G = len(voff) - 1
+    n = row_ptr.numel() - 1
+    b = Batch(G, n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"),
+              voff.ctypes.data_as(ctypes.c_void_p))
+    o = opts if opts is not None else options(**kw)
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=row_ptr.device)
+    lh = np.zeros(G, np.int64)
+    lin = None if lhat_in is None else np.ascontiguousarray(np.asarray(lhat_in, np.int64))
+    rc = lib.mc_debug_first_round(ctypes.byref(b), _stream(stream), ctypes.byref(o),
+                                  None if lin is None else lin.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.c_void_p(labels.data_ptr()),
+                                  lh.ctypes.data_as(ctypes.c_void_p))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_debug_first_round")
+    return labels[:n], lh
+
+
+def debug_contract(row_ptr, col, w, labels, n_new, *, stream=None):
+    """The contraction kernels alone: (row_ptr, col, w) of the graph with
+    every block of `labels` (int32 in [0, n_new)) contracted to one vertex."""
+    import torch
+    lib = _load()
+    n = row_ptr.numel() - 1
+    g = Graph(n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"))
+    rp_o = torch.empty(n_new + 1, dtype=torch.int64, device=row_ptr.device)
+    col_o = torch.empty(max(col.numel(), 1), dtype=torch.int32, device=row_ptr.device)
+    w_o = torch.empty(max(col.numel(), 1), dtype=torch.int32, device=row_ptr.device)
+    nnz = ctypes.c_int64(0)
+    rc = lib.mc_debug_contract(ctypes.byref(g), _dev_ptr(labels, torch.int32, "labels"), n_new,
+                               _stream(stream), ctypes.c_void_p(rp_o.data_ptr()),
+                               ctypes.c_void_p(col_o.data_ptr()), ctypes.c_void_p(w_o.data_ptr()),
+                               ctypes.byref(nnz))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_debug_contract")
+    return rp_o, col_o[: nnz.value], w_o[: nnz.value]
 
 
 def workspace_bytes(n_total: int, nnz_total: int, num_graphs: int = 1) -> int:

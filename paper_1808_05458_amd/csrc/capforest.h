@@ -46,6 +46,8 @@ struct Ctl {
   int32_t improved;
   int64_t pops;          // vertices visited by scans
   int64_t overflows;     // scans ended because the map filled
+  int64_t whole_nnz;     // adjacency entries of the graphs scanned whole
+  int64_t whole_nv;      // vertices of the graphs scanned whole
 };
 
 struct ScanArgs {

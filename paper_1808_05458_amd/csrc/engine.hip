@@ -40,6 +40,8 @@ inline hipError_t& last_hip_error() {
 constexpr int REGION_CAP = 1024;
 constexpr int WHOLE_CAP_S = 2048;
 constexpr int WHOLE_CAP_L = 8192;
+constexpr int SMALL_CAP_S = 2048;  // LDS-resident sweeps of whole small graphs
+constexpr int SMALL_CAP_L = 8192;
 
 // ------------------------------------------------------------------ timing
 struct TimingClass {
@@ -150,7 +152,7 @@ struct Workspace {
   // graph arrays
   int64_t *voff, *lhat, *wsum;
   int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole,
-      *whole2, *fb_list, *root0, *flip, *nvoff;
+      *whole2, *fb_list, *root0, *flip, *nvoff, *npairs;
   uint64_t *bdeg, *balpha;
   uint8_t* mode;
   int32_t* scan_k;
@@ -178,7 +180,7 @@ size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
   b += align_up((N + 1) * 4) * 17 + align_up(sizeof(SweepCtl)) + align_up((G + 1) * 24);
   b += align_up((N + 2) * 8) * 2;
   b += align_up(E * 4) * 3 + align_up((E + 64) * 8) * 2 + align_up(E * 4) * 2;
-  b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 15 + align_up((G + 1) * 8) * 2 +
+  b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 16 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
   b += align_up((2 * N + G + 64) * 4);
   size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
@@ -252,6 +254,7 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.root0, (G + 1) * 4);
   ALLOC(ws.flip, (G + 1) * 4);
   ALLOC(ws.nvoff, (G + 1) * 4);
+  ALLOC(ws.npairs, (G + 1) * 4);
   ALLOC(ws.bdeg, (G + 1) * 8);
   ALLOC(ws.balpha, (G + 1) * 8);
   ALLOC(ws.mode, G + 1);
@@ -299,6 +302,9 @@ struct Solver {
   hipStream_t s;
   mc_options opt;
   int num_cu = 256;
+  int32_t* debug_labels = nullptr;  // first round only: union-find roots
+  int64_t* debug_lhat = nullptr;    // first round only: the bound used (host)
+  const int64_t* lhat_in = nullptr; // optional starting bounds (host, per graph)
 
   int read_ctl() {
     MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -313,10 +319,24 @@ struct Solver {
     int64_t lh = 0;
     uint64_t ba = 0, bd = 0;
     int32_t gn = 0;
-    hipMemcpy(&lh, ws.lhat, 8, hipMemcpyDeviceToHost);
-    hipMemcpy(&ba, ws.balpha, 8, hipMemcpyDeviceToHost);
-    hipMemcpy(&bd, ws.bdeg, 8, hipMemcpyDeviceToHost);
-    hipMemcpy(&gn, ws.gn, 4, hipMemcpyDeviceToHost);
+    static int dg = -1;
+    if (dg < 0) {
+      const char* e = getenv("MC_DEBUG_G");
+      dg = e ? atoi(e) : 0;
+    }
+    hipMemcpy(&lh, ws.lhat + dg, 8, hipMemcpyDeviceToHost);
+    hipMemcpy(&ba, ws.balpha + dg, 8, hipMemcpyDeviceToHost);
+    hipMemcpy(&bd, ws.bdeg + dg, 8, hipMemcpyDeviceToHost);
+    hipMemcpy(&gn, ws.gn + dg, 4, hipMemcpyDeviceToHost);
+    int32_t md = 0, act = 0, np = 0, uc = 0, cv = 0;
+    hipMemcpy(&act, ws.active + dg, 4, hipMemcpyDeviceToHost);
+    hipMemcpy(&np, ws.npairs + dg, 4, hipMemcpyDeviceToHost);
+    hipMemcpy(&uc, ws.ucount + dg, 4, hipMemcpyDeviceToHost);
+    hipMemcpy(&cv, ws.cvoff + dg, 4, hipMemcpyDeviceToHost);
+    uint8_t mdb = 0;
+    hipMemcpy(&mdb, ws.mode + dg, 1, hipMemcpyDeviceToHost);
+    md = mdb;
+    fprintf(stderr, "[mc] g=%d mode=%d active=%d npairs=%d ucount=%d cvoff=%d\n", dg, md, act, np, uc, cv);
     Ctl c;
     hipMemcpy(&c, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
     fprintf(stderr, "[mc] %s n=%d nnz=%lld lhat0=%lld gn0=%d balpha=(%lld,%u) bdeg=(%lld,%u) "
@@ -447,6 +467,9 @@ struct Solver {
       MC_HIP(hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_S>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sizeof(ScanLds<WHOLE_CAP_S>)));
+      MC_HIP(hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(SmallSweepLds<SMALL_CAP_L>)));
       attrs_set = true;
     }
 
@@ -457,6 +480,8 @@ struct Solver {
                  ws.fb_list, ws.wsum, ws.root0};
     const int TB = 256;
     auto grid = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 16)); };
+    // reductions into per-graph counters: fewer, longer-running threads
+    auto gridr = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 2)); };
 
     // ---- ingest: validation, entry sources, weighted degrees, trivial bound
     {
@@ -476,20 +501,26 @@ struct Solver {
                          dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, ws.src, ws.cdeg, ws.ctl);
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
       fill<int64_t>(ws.wsum, 0, G, s);
-      hipLaunchKernelGGL(k_min_degree, grid(N), dim3(TB), 0, s, N, ws.cdeg, gid, (const int32_t*)nullptr,
+      hipLaunchKernelGGL(k_min_degree, gridr(N), dim3(TB), 0, s, N, ws.cdeg, gid, (const int32_t*)nullptr,
                          ws.bdeg, ws.wsum);
     }
     // every col must lie inside its graph before any kernel indexes by it
     rc = read_ctl();
     if (rc) return rc;
     if (ws.ctl_host->err) return MC_EINVAL;
-    {
+    if (opt.scan_mode == 1) {
+      // Region scans may never cover a component, so components are found
+      // up front.  Sweeps and whole scans need no such pass: a scan that
+      // covers a component reports alpha = 0, and a component contracted to
+      // one vertex has degree 0.
       TimedScope t("connectivity", (double)E * 8 + (double)N * 16);
       hipLaunchKernelGGL(k_iota, grid(N), dim3(TB), 0, s, ws.parent, N);
       hipLaunchKernelGGL(k_union_all_edges, grid(E), dim3(TB), 0, s, E, ws.src, P.col, ws.parent);
       hipLaunchKernelGGL(k_flatten, grid(N), dim3(TB), 0, s, N, ws.parent);
       fill<int32_t>(ws.nnew, 0, G, s);
-      hipLaunchKernelGGL(k_count_roots, grid(N), dim3(TB), 0, s, N, ws.parent, gid, ws.nnew);
+      hipLaunchKernelGGL(k_count_roots, gridr(N), dim3(TB), 0, s, N, ws.parent, gid, ws.nnew);
+    } else {
+      fill<int32_t>(ws.nnew, 1, G, s);  // one component assumed; see above
     }
     hipLaunchKernelGGL(k_graph_init, grid(G), dim3(TB), 0, s, G, S, ws.root0, ws.parent, ws.ctl);
     if (want_side) {
@@ -499,6 +530,15 @@ struct Solver {
       hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
       sa.want = REC_DISCONNECTED;
       hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
+    }
+    if (lhat_in) {
+      // a caller-supplied upper bound (a real cut value) lowers lambda-hat
+      std::vector<int64_t> l0(G);
+      MC_HIP(hipMemcpyAsync(l0.data(), ws.lhat, G * 8, hipMemcpyDeviceToHost, s));
+      MC_HIP(hipStreamSynchronize(s));
+      for (int32_t g = 0; g < G; ++g) l0[g] = std::min(l0[g], lhat_in[g]);
+      MC_HIP(hipMemcpyAsync(ws.lhat, l0.data(), G * 8, hipMemcpyHostToDevice, s));
+      MC_HIP(hipStreamSynchronize(s));
     }
     rc = read_ctl();
     if (rc) return rc;
@@ -520,8 +560,14 @@ struct Solver {
     int32_t n_active = ws.ctl_host->n_active;
     int round = 0;
     dump("ingest", n, nnz, rp, col, w);
-    const int32_t whole_max = opt.whole_max > 0 ? opt.whole_max : (WHOLE_CAP_L * 3) / 4;
-    const int32_t whole_small = std::min(whole_max, (WHOLE_CAP_S * 3) / 4);
+    // graphs scanned whole by one workgroup (modes 1 and 3): LDS-resident
+    // capped sweeps index the graph directly; the hash-map scans of
+    // scan_mode 2 keep their map at most 3/4 full
+    const bool hashed = opt.scan_mode == 2;
+    const int32_t cap_l = hashed ? (WHOLE_CAP_L * 3) / 4 : SMALL_CAP_L;
+    const int32_t cap_s = hashed ? (WHOLE_CAP_S * 3) / 4 : SMALL_CAP_S;
+    const int32_t whole_max = std::min(opt.whole_max > 0 ? opt.whole_max : cap_l, cap_l);
+    const int32_t whole_small = std::min(whole_max, cap_s);
     int region_waves = opt.region_waves > 0 ? opt.region_waves : num_cu * 16;
     uint64_t seed = opt.seed ? opt.seed : 0x5EEDull;
     while (n_active > 0 && (opt.max_rounds <= 0 || round < opt.max_rounds)) {
@@ -540,10 +586,10 @@ struct Solver {
       }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
-      hipLaunchKernelGGL(k_count_roots, grid(n), dim3(TB), 0, s, n, ws.parent, gid, ws.nnew);
+      hipLaunchKernelGGL(k_count_roots, gridr(n), dim3(TB), 0, s, n, ws.parent, gid, ws.nnew);
       // plan: whole-graph scans for small graphs (two map sizes), sweeps or
       // region scans otherwise
-      hipLaunchKernelGGL(k_plan_split, grid(G), dim3(TB), 0, s, G, S, whole_small, whole_max,
+      hipLaunchKernelGGL(k_plan_split, grid(G), dim3(TB), 0, s, G, S, rp, whole_small, whole_max,
                          ws.whole2, ws.ctl);
       // scans
       ScanArgs A{};
@@ -562,9 +608,10 @@ struct Solver {
       A.perm_a = (rs | 1ull) & ((1ull << A.perm_bits) - 1);
       if (A.perm_a == 0) A.perm_a = 1;
       A.perm_b = (rs >> 17) & ((1ull << A.perm_bits) - 1);
-      // algorithmic bytes of one scan launch: every adjacency entry once
-      // (col, w) plus the claim gather, and per vertex row_ptr, cdeg, claim
-      // and step
+      // algorithmic bytes of one region-scan launch: every adjacency entry
+      // once (col, w) plus the claim gather, and per vertex row_ptr, cdeg,
+      // claim and step.  Whole-graph scans count the graphs they were given
+      // (added once the plan's sizes are read back).
       const double scan_bytes = (double)nnz * (8 + (opt.eager_blacklist ? 4 : 0)) + (double)n * 32;
       if (opt.scan_mode == 1 && !opt.force_fallback) {
         TimedScope t("capforest_region", scan_bytes);
@@ -576,9 +623,9 @@ struct Solver {
         int blocks = std::max(1, region_waves / wpb);
         hipLaunchKernelGGL(k_capforest<REGION_CAP>, dim3(blocks), dim3(64 * wpb), lds, s, A);
       }
-      {
-        TimedScope t("capforest_whole", scan_bytes);
-        // whole-graph scans: small map, then large map
+      if (hashed) {
+        TimedScope t("capforest_whole", 0.0);
+        // whole-graph scans, one pop at a time: small map, then large map
         MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
         A.whole_mode = 1;
         A.whole = ws.whole;
@@ -590,17 +637,43 @@ struct Solver {
         A.whole_count = &ws.ctl->n_whole2;
         hipLaunchKernelGGL(k_capforest<WHOLE_CAP_L>, dim3(num_cu * 2), dim3(64),
                            sizeof(ScanLds<WHOLE_CAP_L>), s, A);
+      } else {
+        // whole small graphs: LDS-resident capped sweeps, one workgroup each
+        SmallSweepArgs SA{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.whole, &ws.ctl->n_whole,
+                          &ws.ctl->work_next, ws.fb_step, ws.capq, ws.capx, ws.npairs, ws.balpha,
+                          ws.fb_k, ws.ucount, A.seed};
+        {
+          TimedScope t("small_sweep", 0.0);
+          MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
+          hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_S>, dim3(num_cu * 8), dim3(SS_THREADS),
+                             sizeof(SmallSweepLds<SMALL_CAP_S>), s, SA);
+          MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
+          SA.list = ws.whole2;
+          SA.list_count = &ws.ctl->n_whole2;
+          hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_L>, dim3(num_cu * 2), dim3(SS_THREADS),
+                             sizeof(SmallSweepLds<SMALL_CAP_L>), s, SA);
+        }
+        hipLaunchKernelGGL(k_small_sweep_unite, dim3(num_cu * 4), dim3(TB), 0, s, ws.whole, &ws.ctl->n_whole,
+                           ws.cvoff, ws.npairs, ws.capq, ws.capx, ws.parent);
+        hipLaunchKernelGGL(k_small_sweep_unite, dim3(num_cu * 4), dim3(TB), 0, s, ws.whole2, &ws.ctl->n_whole2,
+                           ws.cvoff, ws.npairs, ws.capq, ws.capx, ws.parent);
       }
       {
         TimedScope t("union", (double)n * 8);
         hipLaunchKernelGGL(k_union_pairs, grid(n), dim3(TB), 0, s, ws.keys_alt, ws.ctl, ws.capE, ws.parent);
       }
-      const int sweep_region = (opt.scan_mode == 0 || opt.force_fallback) ? 1 : 0;
+      const int sweep_region = (opt.scan_mode != 1 || opt.force_fallback) ? 1 : 0;
       hipLaunchKernelGGL(k_sweep_list, grid(G), dim3(TB), 0, s, G, S, sweep_region, ws.ctl);
       hipLaunchKernelGGL(k_sweep_info, grid(G), dim3(TB), 0, s, ws.fb_list, ws.ctl, ws.cvoff, ws.gn,
                          ws.lhat, ws.sw_info);
       rc = read_ctl();
       if (rc) return rc;
+      // whole scans: col and w per entry; row_ptr, cdeg, claim and step (one-pop
+      // scans) or row_ptr, cdeg and two stamp writes (LDS sweeps) per vertex
+      if (hashed)
+        timer().add_bytes("capforest_whole", (double)ws.ctl_host->whole_nnz * 8 + (double)ws.ctl_host->whole_nv * 32);
+      else
+        timer().add_bytes("small_sweep", (double)ws.ctl_host->whole_nnz * 8 + (double)ws.ctl_host->whole_nv * 24);
       if (st) {
         st->unions_pr += ws.ctl_host->unions_pr;
         st->scans += ws.ctl_host->scan_ids;
@@ -625,6 +698,12 @@ struct Solver {
       {
         TimedScope t("compact", (double)n * 24);
         hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+        if (debug_labels) {
+          MC_HIP(hipMemcpyAsync(debug_labels, ws.parent, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+          MC_HIP(hipMemcpyAsync(debug_lhat, ws.lhat, (size_t)G * 8, hipMemcpyDeviceToHost, s));
+          MC_HIP(hipStreamSynchronize(s));
+          return MC_OK;
+        }
         exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, ws.active}, n, ws.newid,
                                           &ws.ctl->n_next, ws.tmp, s);
         fill<int32_t>(ws.nnew, 0, G, s);
@@ -694,7 +773,7 @@ struct Solver {
         if (m2 > 0)
           hipLaunchKernelGGL(k_degrees, dim3(grid_for((m2 + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0,
                              s, m2, ws.src, ws.w, ws.cdeg);
-        hipLaunchKernelGGL(k_min_degree, grid(n_next), dim3(TB), 0, s, n_next, ws.cdeg, gid_next,
+        hipLaunchKernelGGL(k_min_degree, gridr(n_next), dim3(TB), 0, s, n_next, ws.cdeg, gid_next,
                            (const int32_t*)nullptr, ws.bdeg, (int64_t*)nullptr);
       }
       exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff,
@@ -746,7 +825,8 @@ Workspace& global_ws() {
 }
 
 int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
-        mc_stats* st) {
+        mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
+        const int64_t* lhat_in = nullptr) {
   if (!lambdas || !P.rp || !P.col || !P.w || P.G < 1 || P.n < 2 || P.nnz < 0) return MC_EINVAL;
   if (P.n > (1 << 30) - 1 || P.nnz >= (int64_t)UINT32_MAX) return MC_EINVAL;
   for (int32_t g = 0; g < P.G; ++g) {
@@ -770,6 +850,9 @@ int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas,
   T.on = o.timing != 0;
   T.s = s;
   Solver sv{ws, s, o};
+  sv.debug_labels = debug_labels;
+  sv.debug_lhat = debug_lhat;
+  sv.lhat_in = lhat_in;
   rc = sv.solve(P, lambdas, side, st);
   if (T.on) T.collect();
   T.on = false;
@@ -805,6 +888,64 @@ int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, in
   if (!b || !lambdas || !b->vtx_off || b->num_graphs < 1) return MC_EINVAL;
   mc::Problem P{b->num_graphs, b->n_total, b->nnz_total, b->row_ptr, b->col, b->w, b->vtx_off};
   return mc::run(P, stream, opt, lambdas, sides, stats);
+}
+
+int mc_debug_first_round(const mc_batch* b, void* stream, const mc_options* opt, const int64_t* lhat_in,
+                          int32_t* labels, int64_t* lhat_used) {
+  if (!b || !labels || !lhat_used || !b->vtx_off || b->num_graphs < 1) return MC_EINVAL;
+  std::vector<int64_t> lam(b->num_graphs);
+  mc::Problem P{b->num_graphs, b->n_total, b->nnz_total, b->row_ptr, b->col, b->w, b->vtx_off};
+  return mc::run(P, stream, opt, lam.data(), nullptr, nullptr, labels, lhat_used, lhat_in);
+}
+
+int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, void* stream,
+                      int64_t* row_ptr_out, int32_t* col_out, int32_t* w_out, int64_t* nnz_out) {
+  using namespace mc;
+  if (!g || !labels || !row_ptr_out || !col_out || !w_out || !nnz_out || n_new < 1) return MC_EINVAL;
+  std::lock_guard<std::mutex> lock(api_mutex());
+  Workspace& ws = global_ws();
+  int rc = ensure(ws, std::max(g->n, n_new), g->nnz, 1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, ncu = 0;
+  MC_HIP(hipGetDevice(&dev));
+  MC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int TB = 256;
+  const int64_t nnz = g->nnz;
+  MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
+  // entry sources
+  fill<int64_t>(ws.cdeg, 0, g->n, s);
+  int64_t voff[2] = {0, g->n};
+  MC_HIP(hipMemcpyAsync(ws.voff, voff, 16, hipMemcpyHostToDevice, s));
+  fill<int32_t>(ws.gid[0], 0, g->n, s);
+  hipLaunchKernelGGL(k_ingest, dim3(grid_for((nnz + 64 * INGEST_STEPS - 1) / (64 * INGEST_STEPS) * 64, TB, ncu * 16)),
+                     dim3(TB), 0, s, g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff, ws.src, ws.cdeg,
+                     ws.ctl);
+  const int bb = std::max(1, bitlen((uint64_t)n_new - 1));
+  hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, ncu * 8)), dim3(TB), 0, s, nnz,
+                     ws.src, g->col, g->w, labels, bb, ws.keys, ws.vals, ws.ctl);
+  MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  MC_HIP(hipStreamSynchronize(s));
+  if (ws.ctl_host->err) return MC_EINVAL;
+  const int64_t m = ws.ctl_host->emit;
+  const int which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s);
+  uint64_t* sk = which ? ws.keys_alt : ws.keys;
+  int32_t* sv = which ? ws.vals_alt : ws.vals;
+  int64_t* pos = (int64_t*)(which ? ws.keys : ws.keys_alt);
+  exclusive_scan<int64_t, HeadFlag>(HeadFlag{sk}, m, pos, (int64_t*)&ws.ctl->unique, ws.tmp, s);
+  MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  MC_HIP(hipStreamSynchronize(s));
+  const int64_t m2 = m > 0 ? ws.ctl_host->unique : 0;
+  fill<int32_t>(w_out, 0, m2, s);
+  if (m > 0)
+    hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, ncu * 16)), dim3(TB), 0, s, m, sk, sv,
+                       pos, bb, ws.src, col_out, w_out);
+  hipLaunchKernelGGL(k_rowptr, dim3(grid_for(n_new + 1, TB, ncu * 16)), dim3(TB), 0, s, n_new, m2, ws.src,
+                     row_ptr_out);
+  MC_HIP(hipStreamSynchronize(s));
+  MC_HIP(hipGetLastError());
+  *nnz_out = m2;
+  return MC_OK;
 }
 
 size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs) {

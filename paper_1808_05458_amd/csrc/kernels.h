@@ -6,6 +6,7 @@
 #pragma once
 #include "capforest.h"
 #include "prims.h"
+#include "smallsweep.h"
 #include "sweep.h"
 
 namespace mc {
@@ -122,26 +123,41 @@ __global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const in
 
 // Per-graph minimum weighted degree (the trivial cut, section "Basic
 // Concepts") and weight totals.
+// Each lane keeps a running minimum and sum for the graph it is in and
+// flushes when the graph changes; the last flush is combined per wave.
 __global__ void k_min_degree(int32_t n, const int64_t* cdeg, const int32_t* gid,
                              const int32_t* active, uint64_t* bdeg, int64_t* wsum) {
-  for (int64_t v = gtid(); v - threadIdx.x % 64 < n; v += gstride()) {
-    bool ok = v < n;
-    int32_t g = ok ? gid[v] : -1;
-    if (ok && active && !active[g]) ok = false;
-    uint64_t key = ok ? (((uint64_t)cdeg[v] << 32) | (uint32_t)v) : ~0ull;
-    int32_t g0 = shfl(g, 0);
-    bool uniform = ballot(ok && g == g0) == ballot(ok) && ballot(ok) != 0;
-    if (uniform) {
-      uint64_t m = wave_min_u64(key);
-      int64_t s = wave_sum_i64(ok ? cdeg[v] : 0);
-      if (lane_id() == 0) {
-        atomic_min_u64(bdeg + g0, m);
-        if (wsum) atomicAdd((unsigned long long*)(wsum + g0), (unsigned long long)s);
+  int32_t cur = -1;
+  uint64_t best = ~0ull;
+  int64_t sum = 0;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    const int32_t g = gid[v];
+    if (active && !active[g]) continue;
+    if (g != cur) {
+      if (cur >= 0) {
+        atomic_min_u64(bdeg + cur, best);
+        if (wsum) atomicAdd((unsigned long long*)(wsum + cur), (unsigned long long)sum);
       }
-    } else if (ok) {
-      atomic_min_u64(bdeg + g, key);
-      if (wsum) atomicAdd((unsigned long long*)(wsum + g), (unsigned long long)cdeg[v]);
+      cur = g;
+      best = ~0ull;
+      sum = 0;
     }
+    const uint64_t key = ((uint64_t)cdeg[v] << 32) | (uint32_t)v;
+    best = key < best ? key : best;
+    sum += cdeg[v];
+  }
+  const int32_t g0 = shfl(cur, 0);
+  const bool uniform = ballot(cur == g0) == ~0ull;
+  if (uniform && g0 >= 0) {
+    const uint64_t m = wave_min_u64(best);
+    const int64_t s = wave_sum_i64(sum);
+    if (lane_id() == 0) {
+      atomic_min_u64(bdeg + g0, m);
+      if (wsum) atomicAdd((unsigned long long*)(wsum + g0), (unsigned long long)s);
+    }
+  } else if (cur >= 0) {
+    atomic_min_u64(bdeg + cur, best);
+    if (wsum) atomicAdd((unsigned long long*)(wsum + cur), (unsigned long long)sum);
   }
 }
 
@@ -157,8 +173,20 @@ __global__ void k_union_all_edges(int64_t nnz, const int32_t* src, const int32_t
   }
 }
 
+// Point every vertex at its root.  The walk up is read-only: a halving store
+// from one thread could land after another thread's root store on the same
+// entry and leave it at a non-root ancestor.  Each thread writes only its
+// own entry, and only with the root, so concurrent walks see either the old
+// parent (an ancestor) or the root, and every entry ends at its root.
 __global__ void k_flatten(int32_t n, int32_t* parent) {
-  for (int64_t v = gtid(); v < n; v += gstride()) parent[v] = uf_find(parent, (int32_t)v);
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    int32_t x = (int32_t)v, p = ld_relaxed(parent + x);
+    while (p != x) {
+      x = p;
+      p = ld_relaxed(parent + x);
+    }
+    st_relaxed(parent + v, x);
+  }
 }
 
 __global__ void k_union_pairs(const uint64_t* pairs, const Ctl* ctl, int64_t cap, int32_t* parent) {
@@ -172,11 +200,18 @@ __global__ void k_union_pairs(const uint64_t* pairs, const Ctl* ctl, int64_t cap
 // Components per graph: disconnected graphs get lambda = 0 (section "Parallel
 // CAPFOREST": a disconnected graph leaves vertices unvisited).
 __global__ void k_count_roots(int32_t n, const int32_t* parent, const int32_t* gid, int32_t* cnt) {
-  for (int64_t v = gtid(); v - lane_id() < n; v += gstride()) {  // wave-uniform bound
-    const bool ok = v < n;
-    const bool root = ok && parent[v] == v;
-    wave_add_by_key(cnt, ok ? gid[v] : -1, 1, root);
+  int32_t cur = -1, acc = 0;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    if (parent[v] != v) continue;
+    const int32_t g = gid[v];
+    if (g != cur) {
+      if (acc) atomicAdd(cnt + cur, acc);
+      cur = g;
+      acc = 0;
+    }
+    ++acc;
   }
+  wave_add_by_key(cnt, cur, acc, acc > 0);
 }
 
 // ----------------------------------------------------- per-graph bookkeeping
@@ -256,8 +291,8 @@ __global__ void k_round_reset(int32_t G, GraphState S) {
 
 // Mode 4: the Padberg-Rinaldi unions alone leave at most two blocks, so the
 // graph goes straight to contraction.  nnew holds the blocks after the tests.
-__global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32_t whole_max,
-                             int32_t* whole2, Ctl* ctl) {
+__global__ void k_plan_split(int32_t G, GraphState S, const int64_t* rp, int32_t whole_small,
+                             int32_t whole_max, int32_t* whole2, Ctl* ctl) {
   for (int64_t g = gtid(); g < G; g += gstride()) {
     uint8_t m = 0;
     if (S.active[g]) {
@@ -272,6 +307,11 @@ __global__ void k_plan_split(int32_t G, GraphState S, int32_t whole_small, int32
       } else {
         m = 2;
         atomicAdd(&ctl->n_region, 1);
+      }
+      if (m == 1 || m == 3) {  // sizes for the scan's byte count
+        const int32_t v0 = S.cvoff[g];
+        atomicAdd((unsigned long long*)&ctl->whole_nnz, (unsigned long long)(rp[v0 + S.n[g]] - rp[v0]));
+        atomicAdd((unsigned long long*)&ctl->whole_nv, (unsigned long long)S.n[g]);
       }
     }
     S.mode[g] = m;

@@ -86,7 +86,9 @@ def test_medium_graphs_against_noi():
                                   dict(whole_max=16, scan_mode=1, max_pops=5, use_pr=0),
                                   dict(whole_max=16, scan_mode=1, eager_blacklist=0),
                                   dict(whole_max=16, sweep_handoff=1),
-                                  dict(whole_max=16, sweep_handoff=3, use_pr=0)])
+                                  dict(whole_max=16, sweep_handoff=3, use_pr=0),
+                                  dict(scan_mode=2), dict(scan_mode=2, max_pops=3),
+                                  dict(scan_mode=2, eager_blacklist=0, use_pr=0)])
 def test_planted_4096_options(opts):
     g = gg.planted_4096()
     gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["planted_4096"]
@@ -176,6 +178,24 @@ def test_invalid_inputs_are_rejected():
     assert lam == 5
 
 
+def test_batched_workload_sample_against_noi():
+    # 160 graphs of the 4096-graph batch recipe, in one packed solve, under
+    # the default (LDS sweeps) and the one-pop-at-a-time whole scans
+    import paper_1808_05458_amd as mc
+    graphs = [gg.batch_graph(i) for i in range(160)]
+    refs = [oracle.noi(g, 5)[0] for g in graphs]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    for opts in [dict(), dict(scan_mode=2), dict(use_pr=0), dict(seed=2), dict(seed=3, scan_mode=2),
+                 dict(seed=4, scan_mode=2)]:
+        announce("batch sample", opts, packed.n, packed.m)
+        lams, sides, st = mc.mincut_batched(rp, col, w, vo, **opts)
+        s = sides.cpu().numpy()
+        assert list(lams) == refs, opts
+        for i, g in enumerate(graphs):
+            check_side(g, int(lams[i]), s[vo[i]:vo[i + 1]])
+
+
 def test_batched_small_against_noi():
     import torch
     import paper_1808_05458_amd as mc
@@ -222,3 +242,81 @@ def test_sweep_on_larger_power_law_graph():
     assert lam == ref
     check_side(g, lam, side)
     assert st["rounds"] <= 6
+
+
+def _round_is_sound(graphs, margins, **opts):
+    """First round under a starting bound lambda + margin: contracting the
+    GPU's blocks must keep a minimum cut (every cut below the bound)."""
+    import paper_1808_05458_amd as mc
+    lams = [oracle.noi(g, 5)[0] for g in graphs]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    for margin in margins:
+        lin = [l + margin for l in lams]
+        labels, used = mc.debug_first_round(rp, col, w, vo, lhat_in=lin, **opts)
+        lab = labels.cpu().numpy()
+        # every label is a root: the relabelling that follows numbers blocks
+        # by their root, so a vertex left at a non-root ancestor would be
+        # contracted into a different block than the one checked here
+        assert np.array_equal(lab[lab], lab), (margin, opts)
+        nxt = []
+        for i, g in enumerate(graphs):
+            h, _ = oracle.contract(g, lab[vo[i]:vo[i + 1]])
+            assert used[i] <= lin[i]
+            if lams[i] < used[i]:
+                assert h.n >= 2, (i, margin)
+                assert oracle.noi(h, 1)[0] == lams[i], (i, margin, opts)
+            nxt.append(h)
+    return nxt
+
+
+def test_round_soundness_batch_recipe():
+    graphs = [gg.batch_graph(i) for i in range(120, 160)]
+    announce("round soundness", len(graphs))
+    for opts in [dict(), dict(scan_mode=2), dict(use_pr=0), dict(whole_max=64)]:
+        _round_is_sound(graphs, [1, 20, 200], **opts)
+
+
+def test_round_soundness_second_round():
+    # second-round conditions: contracted, weighted graphs and a bound far
+    # below their minimum degree
+    graphs = [gg.batch_graph(i) for i in range(130, 150)]
+    lams = [oracle.noi(g, 5)[0] for g in graphs]
+    import paper_1808_05458_amd as mc
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    labels, used = mc.debug_first_round(rp, col, w, vo, lhat_in=[l + 20 for l in lams])
+    lab = labels.cpu().numpy()
+    g2 = [oracle.contract(g, lab[vo[i]:vo[i + 1]])[0] for i, g in enumerate(graphs)]
+    keep = [i for i, h in enumerate(g2) if h.n > 2]
+    announce("second round", len(keep))
+    for opts in [dict(), dict(scan_mode=2), dict(use_pr=0)]:
+        _round_is_sound([g2[i] for i in keep], [1, 20], **opts)
+
+
+def test_contraction_kernels_equal_cpu_contraction():
+    # emit + radix sort + merge + CSR against the numpy contraction, on
+    # block structures of every size: few large blocks (long runs of equal
+    # keys across tiles), many small ones, identity labels (merging
+    # duplicates and dropping self-loops)
+    import torch
+    import paper_1808_05458_amd as mc
+    rng = np.random.default_rng(12)
+    cases = [gg.batch_graph(140), gg.chung_lu(31, 300000, 2.5, 16.0, 1, 9, kcore=0, lcc=True)]
+    packed, vo, eo = gg.pack([gg.batch_graph(i) for i in range(100, 160)])
+    cases.append(packed)
+    cases.append(gg.from_edges(5, [(0, 1), (0, 1), (1, 2), (2, 2), (3, 4), (4, 0)], [1, 2, 3, 9, 4, 5]))
+    for g in cases:
+        for k in [1, 2, 3, 17, 1000, g.n]:
+            k = min(k, g.n)
+            lab = rng.integers(0, k, size=g.n) if k < g.n else np.arange(g.n)
+            lab = np.unique(lab, return_inverse=True)[1].astype(np.int32)
+            n_new = int(lab.max()) + 1
+            announce("contract", g.name, g.n, k)
+            rp, col, w = mc.to_device(g, "cuda")
+            rpo, colo, wo = mc.debug_contract(rp, col, w, torch.from_numpy(lab).cuda(), n_new)
+            h, blk = oracle.contract(g, lab)
+            assert h.n == n_new
+            assert np.array_equal(rpo.cpu().numpy(), h.row_ptr)
+            assert np.array_equal(colo.cpu().numpy(), h.col)
+            assert np.array_equal(wo.cpu().numpy(), h.w)

@@ -260,3 +260,25 @@ def test_stoer_wagner_equals_noi_on_planted_4096():
     assert ls == ln
     check_side(g, ls, ss)
     check_side(g, ln, sn)
+
+
+def test_contract_keeps_block_aligned_cuts():
+    # a cut whose side is a union of blocks has the same value before and
+    # after contraction; the contracted graph has one vertex per block
+    rng = np.random.default_rng(41)
+    for trial in range(40):
+        n = int(rng.integers(4, 30))
+        g = random_graph(rng, n, 0.3, 9)
+        k = int(rng.integers(2, n + 1))
+        labels = rng.integers(0, k, size=n)
+        h, blk = oracle.contract(g, labels)
+        assert h.n == len(np.unique(labels))
+        for _ in range(5):
+            pick = rng.random(h.n) < 0.5
+            if pick.all() or not pick.any():
+                continue
+            assert oracle.cut_value(g, pick[blk]) == oracle.cut_value(h, pick)
+    # hand example: path 0-1-2-3 with weights 1,2,3; blocks {0,1},{2,3}
+    g = gg.from_edges(4, [(0, 1), (1, 2), (2, 3)], [1, 2, 3])
+    h, blk = oracle.contract(g, [7, 7, 9, 9])
+    assert h.n == 2 and h.nnz == 2 and list(h.w) == [2, 2]
