@@ -43,6 +43,58 @@ def cpu_baseline():
                       f"(n={g.n}, m={g.m}, lambda={lam}, {rounds} rounds) in {dt:.2f} s"}
 
 
+def batched_form(steps, warmup):
+    """The 4096-graph batch (planted clusters, n log-uniform in [64, 8192],
+    2-16 clusters, intra degree U[8, 32], 1-4 inter edges per cluster pair,
+    weights U[1, 100]) solved as one packed CSR, against a host loop of
+    single-graph solves over the same graphs, already resident in HBM."""
+    import torch
+    import graphgen as gg
+    import paper_1808_05458_amd as mc
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))["batch_4096"]
+    t0 = time.time()
+    graphs = [gg.batch_graph(i) for i in range(gold["graphs"])]
+    packed, vo, eo = gg.pack(graphs)
+    log(f"batch: {len(graphs)} graphs, sum n={packed.n} sum m={packed.m} in {time.time() - t0:.1f}s")
+    rp, col, w = mc.to_device(packed, "cuda:0")
+    ref = np.asarray(gold["lambdas"], np.int64)
+    for i in range(warmup):
+        lams, sides, st = mc.mincut_batched(rp, col, w, vo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        lams, sides, st = mc.mincut_batched(rp, col, w, vo)
+    torch.cuda.synchronize()
+    dt_packed = (time.perf_counter() - t0) / steps
+    packed_ok = bool(np.array_equal(lams, ref))
+    s = sides.cpu().numpy()
+    src = packed.src()
+    cut = np.zeros(len(graphs), np.int64)
+    gid = np.repeat(np.arange(len(graphs)), np.diff(vo))
+    crossing = s[src] != s[packed.col]
+    np.add.at(cut, gid[src[crossing]], packed.w[crossing].astype(np.int64))
+    sides_ok = bool(np.array_equal(cut // 2, ref))
+    log(f"batch packed: {dt_packed * 1e3:.1f} ms, {st['rounds']} rounds, lambdas equal: {packed_ok}, "
+        f"side weights equal: {sides_ok}")
+    # the loop: one single-graph solve per graph, same device-resident CSRs
+    dev = [mc.to_device(g, "cuda:0") for g in graphs]
+    for g in dev[:16]:
+        mc.mincut(*g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    looped = [mc.mincut(*g)[0] for g in dev]
+    torch.cuda.synchronize()
+    dt_loop = time.perf_counter() - t0
+    loop_ok = bool(np.array_equal(np.asarray(looped), ref))
+    log(f"batch looped: {dt_loop * 1e3:.1f} ms, lambdas equal: {loop_ok}")
+    return {"graphs": len(graphs), "sum_n": packed.n, "sum_m": packed.m,
+            "packed": {"ms": round(dt_packed * 1e3, 2), "edges_per_s": packed.m / dt_packed,
+                       "rounds": st["rounds"], "steps": steps},
+            "looped": {"ms": round(dt_loop * 1e3, 2), "edges_per_s": packed.m / dt_loop},
+            "speedup": round(dt_loop / dt_packed, 2),
+            "verified": {"lambdas_equal_oracle": packed_ok and loop_ok, "side_weights_equal": sides_ok}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +103,11 @@ def main():
     ap.add_argument("--n-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--workload", choices=["chung_lu", "batched"], default="chung_lu")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (the reference "
+                         "kernel for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the batched and served forms "
@@ -63,6 +120,23 @@ def main():
     import paper_1808_05458_amd as mc
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copied {x.numel() * 4} bytes three times")
+        return
+    if args.workload == "batched":
+        b = batched_form(args.steps, args.warmup)
+        out = {"metric": "batched exact min-cut edges/s (sum of m / packed solve time) at 1 GPU",
+               "value": b["packed"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["packed"]["ms"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+               "data": "synthetic", "config": {"workload": "batch of 4096 planted-cluster graphs", **b}}
+        print(json.dumps(out), flush=True)
+        return
     t0 = time.time()
     g = gg.chung_lu_4m_8core(args.n_log2)
     log(f"generated {g.name}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
@@ -127,6 +201,10 @@ def main():
                     "oracle_lambda": gold["lambda"] if gold else None}
         log(f"verify: {verified}")
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_form(max(1, min(args.steps, 3)), 1)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -140,7 +218,7 @@ def main():
            "config": {"workload": f"chung_lu n=2^{args.n_log2} exp2.5 avgdeg32 unit-weight "
                                   f"8-core LCC", "n": g.n, "m": g.m,
                       "rounds": st["rounds"], "verified": verified},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "batched": batched}
     print(json.dumps(out), flush=True)
 
 
