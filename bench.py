@@ -173,12 +173,16 @@ def main():
 
     dom = max(classes, key=lambda c: c["ms"])
     achieved, dom_bytes = rate(dom)
+    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of
+    # this workload (scaled by the same counters on a plain copy), when the
+    # summary is present; it is only valid for the build it was taken on
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    tpath = os.path.join(ROOT, "profiles", f"hbm_traffic_chung_lu_2^{args.n_log2}_8core.txt")
     if os.path.exists(tpath):
-        tr = json.load(open(tpath)).get(dom["name"])
-        if tr:
-            traffic = tr.get("bytes_per_launch")
+        for line in open(tpath):
+            f = line.split()
+            if len(f) == 7 and f[0] == "traffic" and f[1] == dom["name"]:
+                traffic = int(f[6])
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
                 "kernel": dom["name"], "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
