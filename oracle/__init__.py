@@ -9,6 +9,8 @@ Routes (see ``oracle.cpp`` for the passages each follows):
   pair_connectivity(g) lambda(G, s, t) for all pairs by enumeration (n <= 20)
   stoer_wagner(g)      O2
   noi(g, seed)         O3, sequential Nagamochi-Ono-Ibaraki
+  viecut(g, ...)       VieCut-style upper bound (Algorithm 2, first step)
+  lp_sweep(g, labels)  its label-propagation step
   cut_value(g, side)   c(A) by definition
   contract(g, labels)  G with every block of `labels` contracted to one
                        vertex (Preliminaries, contraction G/(u,v)), numpy
@@ -49,6 +51,9 @@ def _load():
         lib.mco_pair_connectivity.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
         lib.mco_stoer_wagner.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         lib.mco_noi.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64, vp, vp, vp]
+        lib.mco_lp_sweep.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
+        i32 = ctypes.c_int32
+        lib.mco_viecut.argtypes = [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -110,6 +115,27 @@ def noi(g, seed: int = 0):
     _check(_load().mco_noi(g.n, _p(rp), _p(col), _p(w), ctypes.c_uint64(seed), _p(lam),
                            _p(side), _p(rounds)), "noi")
     return int(lam[0]), side, int(rounds[0])
+
+
+def lp_sweep(g, labels):
+    """One synchronous label-propagation sweep: each vertex takes the
+    neighbour label of largest total weight, ties to the smallest label."""
+    rp, col, w = _arrs(g)
+    lin = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.zeros(g.n, np.int32)
+    _check(_load().mco_lp_sweep(g.n, _p(rp), _p(col), _p(w), _p(lin), _p(out)), "lp_sweep")
+    return out
+
+
+def viecut(g, sweeps: int = 2, stop_n: int = 2, max_levels: int = 32):
+    """VieCut-style upper bound: (lambda-hat, side, levels)."""
+    rp, col, w = _arrs(g)
+    lam = np.zeros(1, np.int64)
+    side = np.zeros(g.n, np.uint8)
+    levels = np.zeros(1, np.int32)
+    _check(_load().mco_viecut(g.n, _p(rp), _p(col), _p(w), sweeps, stop_n, max_levels, _p(lam),
+                              _p(side), _p(levels)), "viecut")
+    return int(lam[0]), side, int(levels[0])
 
 
 def contract(g, labels):

@@ -18,6 +18,8 @@
 //                              (Preliminaries, contraction G/(u,v)).
 // Helpers: mco_cut_value (c(A) by definition) and mco_pair_connectivity
 // (lambda(G,s,t) for all pairs by enumeration).
+// Upper bound: mco_viecut (the VieCut-style bound of Algorithm 2's first
+// step) and its label-propagation step mco_lp_sweep.
 //
 // All arithmetic is exact 64-bit integer.  Inputs are a symmetric CSR
 // (row_ptr int64[n+1], col int32[nnz], w int32[nnz]); self-loops are ignored
@@ -207,18 +209,10 @@ void uf_union(std::vector<int32_t>& p, int32_t a, int32_t b) {
   if (a != b) p[std::max(a, b)] = std::min(a, b);
 }
 
-// Contract every union-find block into one vertex: block ids in [0, n')
-// numbered by smallest member; parallel edges summed, internal edges
-// dropped (Preliminaries, contraction G/(u,v); "Parallel Graph
-// Contraction" for the block-id scheme).
-WGraph contract(const WGraph& g, std::vector<int32_t>& p, std::vector<int32_t>& lab) {
-  lab.assign(g.n, -1);
-  int32_t nn = 0;
-  for (int32_t v = 0; v < g.n; ++v) {
-    int32_t r = uf_find(p, v);
-    if (lab[r] < 0) lab[r] = nn++;
-    lab[v] = lab[r];
-  }
+// Contract every block into one vertex, given each vertex's block id in
+// [0, nn): parallel edges summed, internal edges dropped (Preliminaries,
+// contraction G/(u,v)).
+WGraph contract_blocks(const WGraph& g, const std::vector<int32_t>& lab, int32_t nn) {
   std::vector<std::pair<uint64_t, i64>> kv;
   kv.reserve(g.col.size());
   for (int32_t u = 0; u < g.n; ++u)
@@ -246,6 +240,36 @@ WGraph contract(const WGraph& g, std::vector<int32_t>& p, std::vector<int32_t>& 
   return h;
 }
 
+// Contract every union-find block: block ids numbered by smallest member
+// ("Parallel Graph Contraction" for the block-id scheme).
+WGraph contract(const WGraph& g, std::vector<int32_t>& p, std::vector<int32_t>& lab) {
+  lab.assign(g.n, -1);
+  int32_t nn = 0;
+  for (int32_t v = 0; v < g.n; ++v) {
+    int32_t r = uf_find(p, v);
+    if (lab[r] < 0) lab[r] = nn++;
+    lab[v] = lab[r];
+  }
+  return contract_blocks(g, lab, nn);
+}
+
+WGraph from_input(const Csr& in) {  // G without self-loops
+  WGraph g;
+  g.n = in.n;
+  g.rp.assign(in.n + 1, 0);
+  g.deg.assign(in.n, 0);
+  for (int32_t u = 0; u < in.n; ++u)
+    for (i64 e = in.rp[u]; e < in.rp[u + 1]; ++e)
+      if (in.col[e] != u) {
+        g.col.push_back(in.col[e]);
+        g.w.push_back(in.w[e]);
+        g.rp[u + 1]++;
+        g.deg[u] += in.w[e];
+      }
+  for (int32_t v = 0; v < in.n; ++v) g.rp[v + 1] += g.rp[v];
+  return g;
+}
+
 int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* rounds_out) {
   const int32_t n0 = in.n;
   if (n0 < 2) return -2;
@@ -259,19 +283,7 @@ int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* r
   }
   // G_C = G without self-loops (parallel entries stay separate until the
   // first contraction merges them).
-  WGraph g;
-  g.n = n0;
-  g.rp.assign(n0 + 1, 0);
-  g.deg.assign(n0, 0);
-  for (int32_t u = 0; u < n0; ++u)
-    for (i64 e = in.rp[u]; e < in.rp[u + 1]; ++e)
-      if (in.col[e] != u) {
-        g.col.push_back(in.col[e]);
-        g.w.push_back(in.w[e]);
-        g.rp[u + 1]++;
-        g.deg[u] += in.w[e];
-      }
-  for (int32_t v = 0; v < n0; ++v) g.rp[v + 1] += g.rp[v];
+  WGraph g = from_input(in);
 
   std::vector<int32_t> map(n0);  // original vertex -> current vertex
   for (int32_t v = 0; v < n0; ++v) map[v] = v;
@@ -337,6 +349,112 @@ int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* r
   return 0;
 }
 
+// --------------------------------------------------------------------------
+// VieCut-style upper bound (section "Inexact Shared-Memory Minimum Cuts" and
+// Algorithm 2's first step: an inexact solver clusters the graph by label
+// propagation, contracts the clusters and applies the Padberg-Rinaldi tests;
+// the paper does not restate the details, so they are read as follows).
+//
+// One synchronous label-propagation sweep: every vertex takes, among its
+// neighbours' current labels, the one with the largest total edge weight,
+// ties to the smallest label; a vertex without neighbours keeps its label.
+void lp_sweep(const WGraph& g, const std::vector<int32_t>& cur, std::vector<int32_t>& nxt) {
+  std::vector<std::pair<int32_t, i64>> acc;
+  for (int32_t v = 0; v < g.n; ++v) {
+    acc.clear();
+    for (i64 e = g.rp[v]; e < g.rp[v + 1]; ++e) acc.push_back({cur[g.col[e]], g.w[e]});
+    if (acc.empty()) {
+      nxt[v] = cur[v];
+      continue;
+    }
+    std::sort(acc.begin(), acc.end());
+    int32_t best = acc[0].first;
+    i64 best_sum = -1;
+    for (size_t i = 0; i < acc.size();) {
+      size_t j = i;
+      i64 sum = 0;
+      while (j < acc.size() && acc[j].first == acc[i].first) sum += acc[j++].second;
+      if (sum > best_sum) {  // labels ascend, so the first maximum is the smallest label
+        best_sum = sum;
+        best = acc[i].first;
+      }
+      i = j;
+    }
+    nxt[v] = best;
+  }
+}
+
+// Levels: `sweeps` label-propagation sweeps from distinct labels; contract
+// the label classes (blocks numbered by label value); bound by the minimum
+// degree; PR1 (w >= lambda-hat) and PR2 (2w > c(u) or 2w > c(v), strict) on
+// that graph with the current bound, contract their components (blocks
+// numbered by smallest member); bound again.  Repeat while the graph has
+// more than stop_n vertices, fewer than max_levels levels ran and the last
+// level removed at least a tenth of the vertices.  Every vertex of a
+// contracted graph is a vertex set of G, so every bound is a real cut value.
+int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i64* lambda,
+           uint8_t* side_out, int32_t* levels_out) {
+  const int32_t n0 = in.n;
+  if (n0 < 2) return -2;
+  WGraph g = from_input(in);
+  std::vector<int32_t> map(n0);
+  for (int32_t v = 0; v < n0; ++v) map[v] = v;
+  std::vector<uint8_t> side(n0, 0);
+  i64 lhat = INT64_MAX;
+  auto bound = [&]() {  // minimum degree of the current graph, smallest vertex on ties
+    if (g.n < 2) return;
+    int32_t arg = 0;
+    for (int32_t v = 1; v < g.n; ++v)
+      if (g.deg[v] < g.deg[arg]) arg = v;
+    if (g.deg[arg] < lhat) {
+      lhat = g.deg[arg];
+      for (int32_t v = 0; v < n0; ++v) side[v] = (map[v] == arg) ? 1 : 0;
+    }
+  };
+  bound();
+  int32_t levels = 0;
+  while (g.n > stop_n && levels < max_levels) {
+    ++levels;
+    const int32_t n_before = g.n;
+    std::vector<int32_t> label(g.n), nxt(g.n);
+    for (int32_t v = 0; v < g.n; ++v) label[v] = v;
+    for (int32_t k = 0; k < sweeps; ++k) {
+      lp_sweep(g, label, nxt);
+      label.swap(nxt);
+    }
+    // label classes, numbered by label value
+    std::vector<uint8_t> used(g.n, 0);
+    for (int32_t v = 0; v < g.n; ++v) used[label[v]] = 1;
+    std::vector<int32_t> rank(g.n, -1), lab(g.n);
+    int32_t nn = 0;
+    for (int32_t l = 0; l < g.n; ++l)
+      if (used[l]) rank[l] = nn++;
+    for (int32_t v = 0; v < g.n; ++v) lab[v] = rank[label[v]];
+    g = contract_blocks(g, lab, nn);
+    for (int32_t v = 0; v < n0; ++v) map[v] = lab[map[v]];
+    bound();
+    if (g.n > 2) {
+      std::vector<int32_t> p(g.n);
+      for (int32_t v = 0; v < g.n; ++v) p[v] = v;
+      for (int32_t u = 0; u < g.n; ++u)
+        for (i64 e = g.rp[u]; e < g.rp[u + 1]; ++e) {
+          const int32_t v = g.col[e];
+          const i64 c = g.w[e];
+          if (u < v && (c >= lhat || 2 * c > g.deg[u] || 2 * c > g.deg[v])) uf_union(p, u, v);
+        }
+      std::vector<int32_t> lab2;
+      g = contract(g, p, lab2);
+      for (int32_t v = 0; v < n0; ++v) map[v] = lab2[map[v]];
+      bound();
+    }
+    if ((int64_t)g.n * 10 > (int64_t)n_before * 9) break;  // shrank by less than a tenth
+  }
+  *lambda = lhat;
+  if (side_out) std::memcpy(side_out, side.data(), n0);
+  if (levels_out) *levels_out = levels;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -369,6 +487,23 @@ int mco_stoer_wagner(int32_t n, const int64_t* rp, const int32_t* col, const int
 int mco_noi(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, uint64_t seed,
             int64_t* lambda, uint8_t* side, int32_t* rounds) {
   return noi(Csr{n, rp, col, w}, seed, lambda, side, rounds);
+}
+
+
+// One label-propagation sweep over the graph as given (self-loops ignored).
+int mco_lp_sweep(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w,
+                 const int32_t* labels_in, int32_t* labels_out) {
+  if (n < 0) return -1;
+  WGraph g = from_input(Csr{n, rp, col, w});
+  std::vector<int32_t> cur(labels_in, labels_in + n), nxt(n);
+  lp_sweep(g, cur, nxt);
+  std::memcpy(labels_out, nxt.data(), sizeof(int32_t) * n);
+  return 0;
+}
+
+int mco_viecut(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, int32_t sweeps,
+               int32_t stop_n, int32_t max_levels, int64_t* lambda, uint8_t* side, int32_t* levels) {
+  return viecut(Csr{n, rp, col, w}, sweeps, stop_n, max_levels, lambda, side, levels);
 }
 
 }  // extern "C"

@@ -282,3 +282,81 @@ def test_contract_keeps_block_aligned_cuts():
     g = gg.from_edges(4, [(0, 1), (1, 2), (2, 3)], [1, 2, 3])
     h, blk = oracle.contract(g, [7, 7, 9, 9])
     assert h.n == 2 and h.nnz == 2 and list(h.w) == [2, 2]
+
+
+# ------------------------------------------------ VieCut-style upper bound
+def _fixture_graph(ex):
+    if isinstance(ex["edges"], str):
+        kind, *args = ex["edges"].split()
+        return gg.two_cliques(*map(int, args)) if kind == "two_cliques" else gg.complete(int(args[0]))
+    e = np.array(ex["edges"])
+    return gg.from_edges(ex["n"], e[:, :2], e[:, 2])
+
+
+def test_lp_sweep_hand_examples():
+    spec = json.load(open(os.path.join(GOLDEN, "lp_examples.json")))
+    for ex in spec["sweeps"]:
+        g = _fixture_graph(ex)
+        assert oracle.lp_sweep(g, ex["labels_in"]).tolist() == ex["labels_out"], ex["name"]
+
+
+def test_viecut_hand_examples():
+    spec = json.load(open(os.path.join(GOLDEN, "lp_examples.json")))
+    for ex in spec["bounds"]:
+        g = _fixture_graph(ex)
+        lam, side, levels = oracle.viecut(g)
+        assert (lam, levels) == (ex["bound"], ex["levels"]), ex["name"]
+        assert oracle.cut_value(g, side) == lam and 0 < side.sum() < g.n, ex["name"]
+
+
+@pytest.mark.parametrize("a", [4, 5, 6, 8, 12])
+def test_viecut_finds_the_bridge_between_cliques(a):
+    # two sweeps turn each clique into one class, so the bound is exact
+    lam, side, _ = oracle.viecut(gg.two_cliques(a, 1))
+    assert lam == 1
+    assert sorted([int(side.sum()), a]) == [a, a]
+
+
+def test_lp_sweep_is_synchronous_and_label_invariant():
+    # renaming labels by an increasing map commutes with a sweep (ties to the
+    # smallest label are preserved); a vertex's new label is always one of
+    # its neighbours' labels
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        n = int(rng.integers(2, 30))
+        g = random_graph(rng, n, float(rng.uniform(0.1, 0.8)), int(rng.choice([1, 5, 50])),
+                         connected=bool(rng.random() < 0.8))
+        lab = rng.integers(0, n, size=n).astype(np.int32)
+        out = oracle.lp_sweep(g, lab)
+        up = np.sort(rng.choice(10 * n, size=n, replace=False)).astype(np.int32)  # increasing map
+        assert np.array_equal(oracle.lp_sweep(g, up[lab]), up[out]), trial
+        src = g.src()
+        for v in range(n):
+            nb = g.col[(src == v) & (g.col != v)]
+            if len(nb):
+                assert out[v] in set(lab[nb].tolist())
+            else:
+                assert out[v] == lab[v]
+
+
+def test_viecut_bound_properties_on_random_graphs():
+    # lambda <= bound <= minimum degree, and the side realises the bound
+    rng = np.random.default_rng(77)
+    for trial in range(400):
+        n = int(rng.integers(2, 14))
+        g = random_graph(rng, n, float(rng.uniform(0.15, 1.0)), int(rng.choice([1, 3, 20])),
+                         connected=bool(rng.random() < 0.9))
+        lam = oracle.bruteforce(g)[0]
+        for sweeps in (1, 2, 3):
+            b, side, _ = oracle.viecut(g, sweeps=sweeps)
+            assert lam <= b <= min_degree(g), (trial, sweeps)
+            check_side(g, b, side)
+
+
+def test_viecut_on_workload_shapes():
+    for g in [gg.planted_4096()] + [gg.batch_graph(i) for i in range(0, 400, 37)]:
+        lam = oracle.noi(g, 1)[0]
+        b, side, levels = oracle.viecut(g)
+        assert lam <= b <= min_degree(g), g.name
+        assert oracle.cut_value(g, side) == b
+        assert levels >= 1
