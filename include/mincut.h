@@ -94,7 +94,11 @@ typedef struct mc_options {
                               with an LDS hash map (no batching) */
   int32_t sweep_handoff;   /* sweep batches above this many vertices run
                               grid-wide; 0 = default (512) */
-  int32_t reserved[3];
+  int32_t viecut_stop;     /* clustering levels stop at this many vertices
+                              per graph; 0 = default (2) */
+  int32_t viecut_levels;   /* at most this many clustering levels; 0 =
+                              default (32) */
+  int32_t reserved[1];
 } mc_options;
 
 typedef struct mc_stats {
@@ -140,6 +144,33 @@ int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, in
 int mc_debug_first_round(const mc_batch* b, void* stream, const mc_options* opt, const int64_t* lhat_in,
                           int32_t* labels, int64_t* lhat_used);
 
+/* The VieCut-style upper bound alone (section "Inexact Shared-Memory
+ * Minimum Cuts"; the first step of Algorithm 2), for every graph of the
+ * batch.  Per level: opt->lp_sweeps synchronous label-propagation sweeps
+ * (each vertex takes the neighbour label of largest total weight, ties to
+ * the smallest label), contraction of the label classes, the Padberg-
+ * Rinaldi tests (PR1 w >= bound, PR2 2w > c(u) or c(v)) on that graph and
+ * contraction of their components; after each contraction the minimum
+ * weighted degree (a real cut: every vertex is a vertex set of the input)
+ * lowers the bound, starting from the input's minimum degree.  Levels stop
+ * at opt->viecut_stop vertices, after opt->viecut_levels levels, or when a
+ * level removes less than a tenth of a graph's vertices.  The result does
+ * not depend on scheduling.
+ *   bounds: HOST int64[G], each >= the graph's minimum cut.
+ *   sides:  DEVICE uint8[n_total] or NULL: a side whose cut weight equals
+ *           the bound, the graph's first vertex on side 0.
+ *   levels: HOST int32 or NULL: the most levels any graph ran.
+ * Errors as mc_mincut_batched.  mc_mincut and mc_mincut_batched run the
+ * same bound first when opt->use_viecut = 1. */
+int mc_viecut_bound(const mc_batch* b, void* stream, const mc_options* opt, int64_t* bounds,
+                    uint8_t* sides, int32_t* levels);
+
+/* Test hook for one label-propagation sweep of the clustering bound (the
+ * rule of mc_viecut_bound) on one graph: labels_in and labels_out are
+ * DEVICE int32[n], labels in [0, n).  Self-loops are ignored; a vertex
+ * without neighbours keeps its label. */
+int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labels_out, void* stream);
+
 /* Test hook for the contraction step alone (section "Parallel Graph
  * Contraction"): labels (DEVICE int32[n], values in [0, n_new)) name each
  * vertex's block; the contracted graph (one vertex per block, parallel
@@ -151,6 +182,10 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
 
 /* Device bytes the workspace needs for a packed problem of this size. */
 size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs);
+
+/* Additional device bytes held once the clustering bound has run
+ * (use_viecut or mc_viecut_bound): two level graphs and their labels. */
+size_t mc_viecut_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs);
 
 /* Free the cached workspace of the current device. */
 void mc_release(void);

@@ -388,9 +388,10 @@ void lp_sweep(const WGraph& g, const std::vector<int32_t>& cur, std::vector<int3
 // the label classes (blocks numbered by label value); bound by the minimum
 // degree; PR1 (w >= lambda-hat) and PR2 (2w > c(u) or 2w > c(v), strict) on
 // that graph with the current bound, contract their components (blocks
-// numbered by smallest member); bound again.  Repeat while the graph has
-// more than stop_n vertices, fewer than max_levels levels ran and the last
-// level removed at least a tenth of the vertices.  Every vertex of a
+// numbered by smallest member) unless the graph is already down to stop_n
+// vertices; bound again.  Repeat while the graph has more than stop_n
+// vertices, the bound is above 0, fewer than max_levels levels ran and the
+// last level removed at least a tenth of the vertices.  Every vertex of a
 // contracted graph is a vertex set of G, so every bound is a real cut value.
 int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i64* lambda,
            uint8_t* side_out, int32_t* levels_out) {
@@ -413,7 +414,7 @@ int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i6
   };
   bound();
   int32_t levels = 0;
-  while (g.n > stop_n && levels < max_levels) {
+  while (g.n > stop_n && levels < max_levels && lhat > 0) {
     ++levels;
     const int32_t n_before = g.n;
     std::vector<int32_t> label(g.n), nxt(g.n);
@@ -433,7 +434,7 @@ int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i6
     g = contract_blocks(g, lab, nn);
     for (int32_t v = 0; v < n0; ++v) map[v] = lab[map[v]];
     bound();
-    if (g.n > 2) {
+    if (g.n > stop_n && lhat > 0) {
       std::vector<int32_t> p(g.n);
       for (int32_t v = 0; v < g.n; ++v) p[v] = v;
       for (int32_t u = 0; u < g.n; ++u)

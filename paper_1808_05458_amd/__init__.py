@@ -53,7 +53,8 @@ class Options(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("force_fallback", ctypes.c_int32), ("whole_max", ctypes.c_int32),
                 ("lp_sweeps", ctypes.c_int32), ("scan_mode", ctypes.c_int32),
-                ("sweep_handoff", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("sweep_handoff", ctypes.c_int32), ("viecut_stop", ctypes.c_int32),
+                ("viecut_levels", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -117,8 +118,14 @@ def _load():
     lib.mc_debug_first_round.restype = ctypes.c_int
     lib.mc_debug_contract.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
     lib.mc_debug_contract.restype = ctypes.c_int
+    lib.mc_debug_lp_sweep.argtypes = [vp, vp, vp, vp]
+    lib.mc_debug_lp_sweep.restype = ctypes.c_int
+    lib.mc_viecut_bound.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mc_viecut_bound.restype = ctypes.c_int
     lib.mc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.mc_workspace_bytes.restype = ctypes.c_size_t
+    lib.mc_viecut_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+    lib.mc_viecut_workspace_bytes.restype = ctypes.c_size_t
     lib.mc_release.argtypes = []
     lib.mc_release.restype = None
     lib.mc_strerror.argtypes = [ctypes.c_int]
@@ -205,6 +212,48 @@ def mincut_batched(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool =
     if rc != MC_OK:
         raise MincutError(rc, "mc_mincut_batched")
     return lams, sides, st.as_dict()
+
+
+def viecut_bound(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool = True, stream=None,
+                 opts: Optional[Options] = None, **kw):
+    """The clustering upper bound alone for every graph of a packed CSR:
+    (bounds int64 ndarray, sides uint8 tensor or None, levels run)."""
+    import torch
+    lib = _load()
+    voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    G = len(voff) - 1
+    n = row_ptr.numel() - 1
+    b = Batch(G, n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"),
+              voff.ctypes.data_as(ctypes.c_void_p))
+    o = opts if opts is not None else options(**kw)
+    sides = torch.empty(max(n, 1), dtype=torch.uint8, device=row_ptr.device) if want_side else None
+    bounds = np.full(G, -1, np.int64)
+    levels = ctypes.c_int32(0)
+    rc = lib.mc_viecut_bound(ctypes.byref(b), _stream(stream), ctypes.byref(o),
+                             bounds.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.c_void_p(sides.data_ptr()) if sides is not None else None,
+                             ctypes.byref(levels))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_viecut_bound")
+    return bounds, sides, int(levels.value)
+
+
+def debug_lp_sweep(row_ptr, col, w, labels, *, stream=None):
+    """One label-propagation sweep on one graph (device tensors); returns
+    the new labels."""
+    import torch
+    lib = _load()
+    n = row_ptr.numel() - 1
+    g = Graph(n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"))
+    lin = labels.to(torch.int32).contiguous()
+    out = torch.empty_like(lin)
+    rc = lib.mc_debug_lp_sweep(ctypes.byref(g), _dev_ptr(lin, torch.int32, "labels"),
+                               ctypes.c_void_p(out.data_ptr()), _stream(stream))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_debug_lp_sweep")
+    return out
 
 
 def debug_first_round(row_ptr, col, w, vtx_off, *, lhat_in=None, stream=None,

@@ -161,8 +161,24 @@ struct Workspace {
   size_t tmp_bytes = 0;
   Ctl* ctl;
   Ctl* ctl_host = nullptr;
+  // clustering levels (allocated on first use): two level graphs that the
+  // contractions alternate between, labels, class flags, the long-row list,
+  // the map from input vertices to level vertices, per-graph state
+  struct Vc {
+    int64_t capN = 0, capE = 0, capG = 0;
+    std::vector<void*> allocs;
+    int32_t *src[2], *col[2], *w[2], *gid[2], *label[2], *map, *flag, *heavy, *act, *n0;
+    int64_t *rp[2], *cdeg[2];
+  } vc;
+
+  void release_vc() {
+    for (void* p : vc.allocs) hipFree(p);
+    vc.allocs.clear();
+    vc.capN = vc.capE = vc.capG = 0;
+  }
 
   void release() {
+    release_vc();
     for (void* p : allocs) hipFree(p);
     allocs.clear();
     if (ctl_host) hipHostFree(ctl_host);
@@ -276,6 +292,51 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   return MC_OK;
 }
 
+size_t vc_workspace_bytes(int64_t N, int64_t E, int64_t G) {
+  return 2 * (3 * align_up(E * 4) + 2 * align_up((N + 1) * 4) + 2 * align_up((N + 2) * 8)) +
+         3 * align_up((N + 1) * 4) + 2 * align_up((G + 1) * 4);
+}
+
+int ensure_vc(Workspace& ws, int64_t N, int64_t E, int64_t G) {
+  Workspace::Vc& v = ws.vc;
+  if (N <= v.capN && E <= v.capE && G <= v.capG) return MC_OK;
+  ws.release_vc();
+  N = std::max<int64_t>(N, 16);
+  E = std::max<int64_t>(E, 64);
+  G = std::max<int64_t>(G, 1);
+  auto A = [&](size_t bytes, void** out) -> int {
+    void* p = nullptr;
+    if (hipMalloc(&p, align_up(bytes)) != hipSuccess) return MC_ENOMEM;
+    v.allocs.push_back(p);
+    *out = p;
+    return MC_OK;
+  };
+#define ALLOC(ptr, bytes)                                     \
+  do {                                                        \
+    int rc_ = A((bytes), (void**)&(ptr));                     \
+    if (rc_) { ws.release_vc(); return rc_; }                 \
+  } while (0)
+  for (int k = 0; k < 2; ++k) {
+    ALLOC(v.src[k], E * 4);
+    ALLOC(v.col[k], E * 4);
+    ALLOC(v.w[k], E * 4);
+    ALLOC(v.gid[k], (N + 1) * 4);
+    ALLOC(v.label[k], (N + 1) * 4);
+    ALLOC(v.rp[k], (N + 2) * 8);
+    ALLOC(v.cdeg[k], (N + 2) * 8);
+  }
+  ALLOC(v.map, (N + 1) * 4);
+  ALLOC(v.flag, (N + 1) * 4);
+  ALLOC(v.heavy, (N + 1) * 4);
+  ALLOC(v.act, (G + 1) * 4);
+  ALLOC(v.n0, (G + 1) * 4);
+#undef ALLOC
+  v.capN = N;
+  v.capE = E;
+  v.capG = G;
+  return MC_OK;
+}
+
 struct Problem {
   int32_t G;
   int32_t n;
@@ -305,6 +366,8 @@ struct Solver {
   int32_t* debug_labels = nullptr;  // first round only: union-find roots
   int64_t* debug_lhat = nullptr;    // first round only: the bound used (host)
   const int64_t* lhat_in = nullptr; // optional starting bounds (host, per graph)
+  bool viecut_only = false;         // stop after the clustering bound
+  int32_t vc_levels_run = 0;        // clustering levels run (most over graphs)
 
   int read_ctl() {
     MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -446,6 +509,214 @@ struct Solver {
     return MC_OK;
   }
 
+  // Timing class names of one contraction's stages.
+  struct StageNames {
+    const char *emit, *sort_hist, *sort_scatter, *merge_scan, *merge, *csr;
+  };
+  static constexpr StageNames kExactNames{"emit", "sort_hist", "sort_scatter", "merge_scan", "merge", "csr"};
+  static constexpr StageNames kVcNames{"vc_contract", "vc_contract", "vc_contract",
+                                       "vc_contract", "vc_contract", "vc_contract"};
+  struct Out {
+    int32_t *src, *col, *w;
+    int64_t *rp, *cdeg;
+  };
+
+  // Contract the graph given per entry (src, col, w over nnz entries) by the
+  // block of every vertex (lab in [0, n_next), -1 = dropped) into n_next
+  // vertices (Preliminaries, contraction G/(u,v); section "Parallel Graph
+  // Contraction"): emit a (lab u, lab v) key per crossing entry, radix-sort,
+  // merge runs of equal keys, build row_ptr and the weighted degrees, and
+  // fold each graph's minimum degree into ws.bdeg (cleared by the caller).
+  // The entry inputs are consumed before the outputs are written, so `out`
+  // may alias them.
+  int contract(int64_t nnz, const int32_t* src, const int32_t* col, const int32_t* w, const int32_t* lab,
+               int32_t n_next, const int32_t* gid_next, Out out, int64_t* m2_out, const StageNames& nm) {
+    const int TB = 256;
+    auto grid = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 16)); };
+    auto gridr = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 2)); };
+    const int bb = std::max(1, bitlen((uint64_t)std::max(n_next, 1) - 1));
+    MC_HIP(hipMemsetAsync(&ws.ctl->emit, 0, sizeof(int64_t), s));
+    {
+      // src, col, w and two label gathers per entry; the keys it writes are
+      // counted with the sort
+      TimedScope t(nm.emit, (double)nnz * 20);
+      hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, num_cu * 8)), dim3(TB), 0, s, nnz,
+                         src, col, w, lab, bb, ws.keys, ws.vals, ws.ctl);
+    }
+    int rc = read_ctl();
+    if (rc) return rc;
+    const int64_t m = ws.ctl_host->emit;
+    int which = 0;
+    {
+      // per pass: the histogram reads every key (8 B); the scatter reads
+      // and writes key and weight (24 B)
+      int cur = -1;
+      hipEvent_t ev0{};
+      auto hook = [&](int kind, int) {
+        if (kind == 0) cur = timer().begin(nm.sort_hist, ev0);
+        else if (kind == 1) timer().end(cur, ev0, (double)m * 8);
+        else if (kind == 2) cur = timer().begin(nm.sort_scatter, ev0);
+        else timer().end(cur, ev0, (double)m * 24);
+      };
+      which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s, hook);
+    }
+    uint64_t* sk = which ? ws.keys_alt : ws.keys;
+    int32_t* sv = which ? ws.vals_alt : ws.vals;
+    int64_t* pos = (int64_t*)(which ? ws.keys : ws.keys_alt);
+    {
+      TimedScope t(nm.merge_scan, (double)m * 16 + (double)m * 8);
+      exclusive_scan<int64_t, HeadFlag>(HeadFlag{sk}, m, pos, (int64_t*)&ws.ctl->unique, ws.tmp, s);
+    }
+    rc = read_ctl();
+    if (rc) return rc;
+    const int64_t m2 = m > 0 ? ws.ctl_host->unique : 0;
+    {
+      fill<int32_t>(out.w, 0, m2, s);
+      // keys, weights and positions in; the merged entries out
+      TimedScope t(nm.merge, (double)m * 20 + (double)m2 * 12);
+      if (m > 0)
+        hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s, m, sk,
+                           sv, pos, bb, out.src, out.col, out.w);
+    }
+    {
+      TimedScope t(nm.csr, (double)m2 * 12 + (double)n_next * 16);
+      hipLaunchKernelGGL(k_rowptr, grid(n_next + 1), dim3(TB), 0, s, n_next, m2, out.src, out.rp);
+      fill<int64_t>(out.cdeg, 0, n_next, s);
+      if (m2 > 0)
+        hipLaunchKernelGGL(k_degrees, dim3(grid_for((m2 + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s, m2,
+                           out.src, out.w, out.cdeg);
+      hipLaunchKernelGGL(k_min_degree, gridr(n_next), dim3(TB), 0, s, n_next, out.cdeg, gid_next,
+                         (const int32_t*)nullptr, ws.bdeg, (int64_t*)nullptr);
+    }
+    *m2_out = m2;
+    return MC_OK;
+  }
+
+  // VieCut-style upper bound (section "Inexact Shared-Memory Minimum Cuts";
+  // Algorithm 2 starts from it).  Per level: label-propagation sweeps,
+  // contraction of the label classes, the minimum degree as a bound, the
+  // Padberg-Rinaldi tests against the current bound, contraction of their
+  // components, the minimum degree again.  Every vertex of a level graph is
+  // a vertex set of the input, so each bound is a real cut; the side of a
+  // new bound is written at once.  The input graph's entries, sources and
+  // degrees are left as they are for the exact loop, and no union found
+  // here enters it.
+  int viecut(const Problem& P, GraphState S, const int32_t* gid_in, uint8_t* side) {
+    const int32_t G = P.G, N = P.n;
+    int rc = ensure_vc(ws, N, P.nnz, G);
+    if (rc) return rc;
+    Workspace::Vc& V = ws.vc;
+    const int TB = 256;
+    auto grid = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 16)); };
+    const int32_t stop = opt.viecut_stop > 0 ? opt.viecut_stop : 2;
+    const int32_t max_levels = opt.viecut_levels > 0 ? opt.viecut_levels : 32;
+    const int32_t sweeps = std::max(0, opt.lp_sweeps);
+    MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
+    hipLaunchKernelGGL(k_vc_init, grid(G), dim3(TB), 0, s, G, S, stop, V.act, V.n0, ws.ctl);
+    hipLaunchKernelGGL(k_iota, grid(N), dim3(TB), 0, s, V.map, N);
+    rc = read_ctl();
+    if (rc) return rc;
+    int32_t n_act = ws.ctl_host->n_active;
+    // the current level graph; the input first
+    int32_t n = N;
+    int64_t nnz = P.nnz;
+    const int64_t* rp = P.rp;
+    const int32_t* col = P.col;
+    const int32_t* w = P.w;
+    const int32_t* src = ws.src;
+    const int64_t* cdeg = ws.cdeg;
+    const int32_t* gid = gid_in;
+    int next = 0;  // level-graph buffer the next contraction writes
+    SideArgs sa{N, ws.ogid, V.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
+                ws.fb_step, ws.parent, ws.root0, side, REC_DEG};
+    // contract the current graph by ws.lab (ws.nnew holds the new per-graph
+    // counts), update the bounds and sides, and move to the new graph
+    auto step = [&](int32_t n_next, int end_of_level, int last_level) -> int {
+      fill<uint64_t>(ws.bdeg, ~0ull, G, s);
+      int64_t m2 = 0;
+      Out o{V.src[next], V.col[next], V.w[next], V.rp[next], V.cdeg[next]};
+      int r = contract(nnz, src, col, w, ws.lab, n_next, V.gid[next], o, &m2, kVcNames);
+      if (r) return r;
+      exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff, (int32_t*)nullptr,
+                                                ws.tmp, s);
+      MC_HIP(hipMemsetAsync(&ws.ctl->n_active, 0, sizeof(int32_t), s));
+      hipLaunchKernelGGL(k_vc_level, grid(G), dim3(TB), 0, s, G, S, ws.nvoff, stop, end_of_level, last_level,
+                         V.act, V.n0, ws.ctl);
+      hipLaunchKernelGGL(k_compose_map, grid(N), dim3(TB), 0, s, N, V.map, ws.lab);
+      if (side) {
+        TimedScope t("side", (double)N * 13);
+        hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
+      }
+      r = read_ctl();
+      if (r) return r;
+      n_act = ws.ctl_host->n_active;
+      n = n_next;
+      nnz = m2;
+      rp = V.rp[next];
+      col = V.col[next];
+      w = V.w[next];
+      src = V.src[next];
+      cdeg = V.cdeg[next];
+      gid = V.gid[next];
+      next ^= 1;
+      return MC_OK;
+    };
+    int level = 0;
+    for (; level < max_levels && n_act > 0; ++level) {
+      const int last = level + 1 >= max_levels;
+      // label propagation from distinct labels
+      int32_t* cur = V.label[0];
+      int32_t* nxt = V.label[1];
+      {
+        TimedScope t("vc_lp", (double)nnz * 12 * std::max(sweeps, 1) + (double)n * 24);
+        hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, cur, n);
+        MC_HIP(hipMemsetAsync(&ws.ctl->lp_heavy, 0, sizeof(int32_t), s));
+        for (int k = 0; k < sweeps; ++k) {
+          LpArgs L{n, rp, col, w, gid, V.act, cur, nxt, V.heavy, &ws.ctl->lp_heavy, k == 0 ? 1 : 0};
+          hipLaunchKernelGGL(k_lp_wave, dim3(grid_for((int64_t)n * 64, 64 * LP_WAVES, num_cu * 16)),
+                             dim3(64 * LP_WAVES), 0, s, L);
+          hipLaunchKernelGGL(k_lp_block, dim3(num_cu * 2), dim3(LP_BLOCK_THREADS), 0, s, L);
+          std::swap(cur, nxt);
+        }
+        // classes numbered by label value
+        fill<int32_t>(V.flag, 0, n, s);
+        hipLaunchKernelGGL(k_lp_flag, grid(n), dim3(TB), 0, s, n, cur, gid, V.act, V.flag);
+        exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{V.flag}, n, ws.newid, &ws.ctl->n_next,
+                                                  ws.tmp, s);
+        fill<int32_t>(ws.nnew, 0, G, s);
+        hipLaunchKernelGGL(k_lp_relabel, grid(n), dim3(TB), 0, s, n, cur, gid, V.act, V.flag, ws.newid, ws.lab,
+                           V.gid[next], ws.nnew);
+      }
+      rc = read_ctl();
+      if (rc) return rc;
+      rc = step(ws.ctl_host->n_next, 0, last);
+      if (rc) return rc;
+      if (n_act > 0) {
+        // Padberg-Rinaldi tests on the level graph, components contracted
+        {
+          TimedScope t("vc_pr", (double)nnz * 20 + (double)n * 16);
+          hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
+          hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, src, col, w, cdeg, gid, ws.lhat, V.act,
+                             ws.parent, ws.ucount, ws.ctl);
+          hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+          exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, V.act}, n, ws.newid, &ws.ctl->n_next, ws.tmp,
+                                            s);
+          fill<int32_t>(ws.nnew, 0, G, s);
+          hipLaunchKernelGGL(k_relabel, grid(n), dim3(TB), 0, s, n, ws.parent, gid, V.act, ws.newid, ws.lab,
+                             V.gid[next], ws.nnew);
+        }
+        rc = read_ctl();
+        if (rc) return rc;
+        rc = step(ws.ctl_host->n_next, 1, last);
+        if (rc) return rc;
+      }
+    }
+    vc_levels_run = level;
+    MC_HIP(hipMemsetAsync(&ws.ctl->n_active, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_vc_done, grid(G), dim3(TB), 0, s, G, S, ws.ctl);
+    return MC_OK;
+  }
+
   int solve(const Problem& P, int64_t* lambdas, uint8_t* side, mc_stats* st) {
     const int32_t G = P.G;
     const int32_t N = P.n;
@@ -549,6 +820,25 @@ struct Solver {
       MC_HIP(hipMemcpy(l0.data(), ws.lhat, G * sizeof(int64_t), hipMemcpyDeviceToHost));
       st->lambda_initial = l0[0];
       st->lambda_viecut = -1;
+    }
+    if (opt.use_viecut || viecut_only) {
+      rc = viecut(P, S, gid, side);
+      if (rc) return rc;
+      rc = read_ctl();
+      if (rc) return rc;
+      if (st) {
+        MC_HIP(hipMemcpyAsync(&st->lambda_viecut, ws.lhat, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+      }
+      if (viecut_only) {
+        if (want_side) {
+          hipLaunchKernelGGL(k_normalize_side, grid(G), dim3(TB), 0, s, G, ws.voff, side, ws.flip);
+          hipLaunchKernelGGL(k_apply_flip, grid(N), dim3(TB), 0, s, N, ws.ogid, ws.flip, side);
+        }
+        MC_HIP(hipMemcpyAsync(lambdas, ws.lhat, G * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        return MC_OK;
+      }
     }
 
     // ---- the contraction loop
@@ -722,60 +1012,11 @@ struct Solver {
       dump("after-scans", n, nnz, rp, col, w);
       const int32_t n_next = ws.ctl_host->n_next;
       if (st) st->pairs_scan += ws.ctl_host->pairs;
-      // contraction: emit, sort, merge, CSR
-      const int bb = std::max(1, bitlen((uint64_t)std::max(n_next, 1) - 1));
-      {
-        // src, col, w and two label gathers per entry; the keys it writes are
-        // counted with the sort
-        TimedScope t("emit", (double)nnz * 20);
-        hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, num_cu * 8)), dim3(TB), 0,
-                           s, nnz, ws.src, col, w, ws.lab, bb, ws.keys, ws.vals, ws.ctl);
-      }
-      rc = read_ctl();
+      // contraction: emit, sort, merge, CSR, degrees
+      int64_t m2 = 0;
+      rc = contract(nnz, ws.src, col, w, ws.lab, n_next, gid_next,
+                    Out{ws.src, ws.col, ws.w, ws.rp, ws.cdeg}, &m2, kExactNames);
       if (rc) return rc;
-      const int64_t m = ws.ctl_host->emit;
-      int which = 0;
-      {
-        // per pass: the histogram reads every key (8 B); the scatter reads
-        // and writes key and weight (24 B)
-        int cur = -1;
-        hipEvent_t ev0{};
-        auto hook = [&](int kind, int) {
-          if (kind == 0) cur = timer().begin("sort_hist", ev0);
-          else if (kind == 1) timer().end(cur, ev0, (double)m * 8);
-          else if (kind == 2) cur = timer().begin("sort_scatter", ev0);
-          else timer().end(cur, ev0, (double)m * 24);
-        };
-        which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s, hook);
-      }
-      uint64_t* sk = which ? ws.keys_alt : ws.keys;
-      int32_t* sv = which ? ws.vals_alt : ws.vals;
-      int64_t* pos = (int64_t*)(which ? ws.keys : ws.keys_alt);
-      {
-        TimedScope t("merge_scan", (double)m * 16 + (double)m * 8);
-        exclusive_scan<int64_t, HeadFlag>(HeadFlag{sk}, m, pos, (int64_t*)&ws.ctl->unique, ws.tmp, s);
-      }
-      rc = read_ctl();
-      if (rc) return rc;
-      const int64_t m2 = m > 0 ? ws.ctl_host->unique : 0;
-      {
-        fill<int32_t>(ws.w, 0, m2, s);
-        // keys, weights and positions in; the merged entries out
-        TimedScope t("merge", (double)m * 20 + (double)m2 * 12);
-        if (m > 0)
-          hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s,
-                             m, sk, sv, pos, bb, ws.src, ws.col, ws.w);
-      }
-      {
-        TimedScope t("csr", (double)m2 * 12 + (double)n_next * 16);
-        hipLaunchKernelGGL(k_rowptr, grid(n_next + 1), dim3(TB), 0, s, n_next, m2, ws.src, ws.rp);
-        fill<int64_t>(ws.cdeg, 0, n_next, s);
-        if (m2 > 0)
-          hipLaunchKernelGGL(k_degrees, dim3(grid_for((m2 + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0,
-                             s, m2, ws.src, ws.w, ws.cdeg);
-        hipLaunchKernelGGL(k_min_degree, gridr(n_next), dim3(TB), 0, s, n_next, ws.cdeg, gid_next,
-                           (const int32_t*)nullptr, ws.bdeg, (int64_t*)nullptr);
-      }
       exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff,
                                                 (int32_t*)nullptr, ws.tmp, s);
       hipLaunchKernelGGL(k_compose_map, grid(N), dim3(TB), 0, s, N, ws.map, ws.lab);
@@ -826,7 +1067,7 @@ Workspace& global_ws() {
 
 int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
         mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
-        const int64_t* lhat_in = nullptr) {
+        const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
   if (!lambdas || !P.rp || !P.col || !P.w || P.G < 1 || P.n < 2 || P.nnz < 0) return MC_EINVAL;
   if (P.n > (1 << 30) - 1 || P.nnz >= (int64_t)UINT32_MAX) return MC_EINVAL;
   for (int32_t g = 0; g < P.G; ++g) {
@@ -853,7 +1094,9 @@ int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas,
   sv.debug_labels = debug_labels;
   sv.debug_lhat = debug_lhat;
   sv.lhat_in = lhat_in;
+  sv.viecut_only = viecut_levels != nullptr;
   rc = sv.solve(P, lambdas, side, st);
+  if (viecut_levels) *viecut_levels = sv.vc_levels_run;
   if (T.on) T.collect();
   T.on = false;
   if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -896,6 +1139,40 @@ int mc_debug_first_round(const mc_batch* b, void* stream, const mc_options* opt,
   std::vector<int64_t> lam(b->num_graphs);
   mc::Problem P{b->num_graphs, b->n_total, b->nnz_total, b->row_ptr, b->col, b->w, b->vtx_off};
   return mc::run(P, stream, opt, lam.data(), nullptr, nullptr, labels, lhat_used, lhat_in);
+}
+
+int mc_viecut_bound(const mc_batch* b, void* stream, const mc_options* opt, int64_t* bounds,
+                    uint8_t* sides, int32_t* levels) {
+  if (!b || !bounds || !b->vtx_off || b->num_graphs < 1) return MC_EINVAL;
+  mc::Problem P{b->num_graphs, b->n_total, b->nnz_total, b->row_ptr, b->col, b->w, b->vtx_off};
+  int32_t lv = 0;
+  int rc = mc::run(P, stream, opt, bounds, sides, nullptr, nullptr, nullptr, nullptr, &lv);
+  if (levels) *levels = lv;
+  return rc;
+}
+
+int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labels_out, void* stream) {
+  using namespace mc;
+  if (!g || !labels_in || !labels_out || g->n < 1 || !g->row_ptr || !g->col || !g->w) return MC_EINVAL;
+  std::lock_guard<std::mutex> lock(api_mutex());
+  Workspace& ws = global_ws();
+  int rc = ensure(ws, g->n, g->nnz, 1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, ncu = 0;
+  MC_HIP(hipGetDevice(&dev));
+  MC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
+  fill<int32_t>(ws.gid[0], 0, g->n, s);
+  fill<int32_t>(ws.active, 1, 1, s);
+  LpArgs L{g->n, g->row_ptr, g->col, g->w, ws.gid[0], ws.active, labels_in, labels_out, ws.newid,
+           &ws.ctl->lp_heavy, 1};
+  hipLaunchKernelGGL(k_lp_wave, dim3(grid_for((int64_t)g->n * 64, 64 * LP_WAVES, ncu * 16)), dim3(64 * LP_WAVES),
+                     0, s, L);
+  hipLaunchKernelGGL(k_lp_block, dim3(ncu * 2), dim3(LP_BLOCK_THREADS), 0, s, L);
+  MC_HIP(hipStreamSynchronize(s));
+  MC_HIP(hipGetLastError());
+  return MC_OK;
 }
 
 int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, void* stream,
@@ -950,6 +1227,10 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
 
 size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs) {
   return mc::workspace_bytes(n_total, nnz_total, num_graphs);
+}
+
+size_t mc_viecut_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs) {
+  return mc::vc_workspace_bytes(n_total, nnz_total, num_graphs);
 }
 
 void mc_release(void) {

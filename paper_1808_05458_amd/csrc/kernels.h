@@ -8,6 +8,7 @@
 #include "prims.h"
 #include "smallsweep.h"
 #include "sweep.h"
+#include "lp.h"
 
 namespace mc {
 
@@ -571,6 +572,65 @@ __global__ void k_finish_round(int32_t G, GraphState S, const int32_t* nvoff_sca
       }
     }
     int32_t act = (S.nnew[g] > 2 && S.lhat[g] > 0) ? 1 : 0;
+    S.active[g] = act;
+    if (act) atomicAdd(&ctl->n_active, 1);
+  }
+}
+
+// ------------------------------------------------ VieCut-style levels
+// Per graph during the clustering levels: S.n / S.cvoff follow the level
+// graph, vc_act marks graphs still being coarsened, vc_n0 holds the vertex
+// count at the start of the level.
+__global__ void k_vc_init(int32_t G, GraphState S, int32_t stop, int32_t* vc_act, int32_t* vc_n0, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    const int32_t act = (S.active[g] && S.n[g] > stop && S.lhat[g] > 0) ? 1 : 0;
+    vc_act[g] = act;
+    vc_n0[g] = S.n[g];
+    S.rec_type[g] = REC_NONE;
+    if (act) atomicAdd(&ctl->n_active, 1);
+  }
+}
+
+// After a contraction of the level: the new graph's minimum degree bounds
+// lambda-hat (each of its vertices is a vertex set of the input graph).
+// end_of_level: also stop graphs that shrank by less than a tenth over the
+// level, or reached the level limit.
+__global__ void k_vc_level(int32_t G, GraphState S, const int32_t* nvoff_scan, int32_t stop, int32_t end_of_level,
+                           int32_t last_level, int32_t* vc_act, int32_t* vc_n0, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    S.rec_type[g] = REC_NONE;
+    if (!vc_act[g]) continue;
+    const int32_t nn = S.nnew[g];
+    S.n[g] = nn;
+    S.cvoff[g] = nvoff_scan[g];
+    if (nn >= 2) {
+      const uint64_t bd = S.bdeg[g];
+      const int64_t d = (int64_t)(bd >> 32);
+      if (bd != ~0ull && d < S.lhat[g]) {
+        S.lhat[g] = d;
+        S.rec_type[g] = REC_DEG;
+        S.rec_id[g] = (int32_t)(uint32_t)bd;
+        S.rec_k[g] = 0;
+        atomicAdd(&ctl->improved, 1);
+      }
+    }
+    bool go = nn > stop && S.lhat[g] > 0;
+    if (end_of_level) {
+      go = go && !last_level && (int64_t)nn * 10 <= (int64_t)vc_n0[g] * 9;
+      vc_n0[g] = nn;
+    }
+    vc_act[g] = go ? 1 : 0;
+    if (go) atomicAdd(&ctl->n_active, 1);
+  }
+}
+
+// Back to the input graphs for the exact loop; a zero bound is final.
+__global__ void k_vc_done(int32_t G, GraphState S, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    S.n[g] = (int32_t)(S.voff[g + 1] - S.voff[g]);
+    S.cvoff[g] = (int32_t)S.voff[g];
+    S.rec_type[g] = REC_NONE;
+    const int32_t act = (S.active[g] && S.lhat[g] > 0) ? 1 : 0;
     S.active[g] = act;
     if (act) atomicAdd(&ctl->n_active, 1);
   }
