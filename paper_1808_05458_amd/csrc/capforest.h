@@ -48,7 +48,7 @@ struct Ctl {
   int64_t overflows;     // scans ended because the map filled
   int64_t whole_nnz;     // adjacency entries of the graphs scanned whole
   int64_t whole_nv;      // vertices of the graphs scanned whole
-  int32_t lp_heavy;      // rows left to the workgroup path of label propagation
+  int32_t lp_items;      // workgroup items of label propagation (long rows)
   int32_t pad;
 };
 

@@ -91,6 +91,9 @@ __device__ __forceinline__ bool uf_union(int32_t* parent, int32_t a, int32_t b) 
 __device__ __forceinline__ void atomic_min_u64(uint64_t* p, uint64_t v) {
   __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void atomic_max_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // arr[key] += val for every active lane, with one atomic per distinct key
 // in the wave (lanes of a wave usually share the graph id).  Must be called

@@ -167,8 +167,9 @@ struct Workspace {
   struct Vc {
     int64_t capN = 0, capE = 0, capG = 0;
     std::vector<void*> allocs;
-    int32_t *src[2], *col[2], *w[2], *gid[2], *label[2], *map, *flag, *heavy, *act, *n0;
+    int32_t *src[2], *col[2], *w[2], *gid[2], *label[2], *map, *flag, *item_off, *act, *n0;
     int64_t *rp[2], *cdeg[2];
+    uint64_t* best;
   } vc;
 
   void release_vc() {
@@ -294,7 +295,7 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
 
 size_t vc_workspace_bytes(int64_t N, int64_t E, int64_t G) {
   return 2 * (3 * align_up(E * 4) + 2 * align_up((N + 1) * 4) + 2 * align_up((N + 2) * 8)) +
-         3 * align_up((N + 1) * 4) + 2 * align_up((G + 1) * 4);
+         3 * align_up((N + 1) * 4) + align_up((N + 1) * 8) + 2 * align_up((G + 1) * 4);
 }
 
 int ensure_vc(Workspace& ws, int64_t N, int64_t E, int64_t G) {
@@ -327,7 +328,8 @@ int ensure_vc(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   }
   ALLOC(v.map, (N + 1) * 4);
   ALLOC(v.flag, (N + 1) * 4);
-  ALLOC(v.heavy, (N + 1) * 4);
+  ALLOC(v.item_off, (N + 1) * 4);
+  ALLOC(v.best, (N + 1) * 8);
   ALLOC(v.act, (G + 1) * 4);
   ALLOC(v.n0, (G + 1) * 4);
 #undef ALLOC
@@ -335,6 +337,21 @@ int ensure_vc(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   v.capE = E;
   v.capG = G;
   return MC_OK;
+}
+
+// One label-propagation sweep (L.cur -> L.nxt): short rows on the wave
+// path, the passes of long rows as workgroup items, then their results.
+// L.item_off must hold the items' prefix (lp_items_prefix) and L.best must
+// be zero; the sweep leaves it zero.
+void lp_items_prefix(const LpArgs& L, Workspace& ws, hipStream_t s) {
+  exclusive_scan<int32_t, LpItems>(LpItems{L}, L.n, (int32_t*)L.item_off, &ws.ctl->lp_items, ws.tmp, s);
+}
+
+void lp_sweep(const LpArgs& L, int num_cu, hipStream_t s) {
+  hipLaunchKernelGGL(k_lp_wave, dim3(grid_for((int64_t)L.n * 64, 64 * LP_WAVES, num_cu * 16)), dim3(64 * LP_WAVES),
+                     0, s, L);
+  hipLaunchKernelGGL(k_lp_items, dim3(num_cu * 4), dim3(LP_BLOCK_THREADS), 0, s, L);
+  hipLaunchKernelGGL(k_lp_finish, dim3(grid_for(L.n, 256, num_cu * 16)), dim3(256), 0, s, L);
 }
 
 struct Problem {
@@ -670,12 +687,13 @@ struct Solver {
       {
         TimedScope t("vc_lp", (double)nnz * 12 * std::max(sweeps, 1) + (double)n * 24);
         hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, cur, n);
-        MC_HIP(hipMemsetAsync(&ws.ctl->lp_heavy, 0, sizeof(int32_t), s));
+        fill<uint64_t>(V.best, 0, n, s);
+        LpArgs L{n, rp, col, w, gid, V.act, cur, nxt, V.item_off, &ws.ctl->lp_items, V.best};
+        if (sweeps > 0) lp_items_prefix(L, ws, s);
         for (int k = 0; k < sweeps; ++k) {
-          LpArgs L{n, rp, col, w, gid, V.act, cur, nxt, V.heavy, &ws.ctl->lp_heavy, k == 0 ? 1 : 0};
-          hipLaunchKernelGGL(k_lp_wave, dim3(grid_for((int64_t)n * 64, 64 * LP_WAVES, num_cu * 16)),
-                             dim3(64 * LP_WAVES), 0, s, L);
-          hipLaunchKernelGGL(k_lp_block, dim3(num_cu * 2), dim3(LP_BLOCK_THREADS), 0, s, L);
+          L.cur = cur;
+          L.nxt = nxt;
+          lp_sweep(L, num_cu, s);
           std::swap(cur, nxt);
         }
         // classes numbered by label value
@@ -689,6 +707,9 @@ struct Solver {
       }
       rc = read_ctl();
       if (rc) return rc;
+      if (debug_on())
+        fprintf(stderr, "[mc] viecut level %d: n=%d nnz=%lld long-row items=%d classes=%d active=%d\n", level, n,
+                (long long)nnz, ws.ctl_host->lp_items, ws.ctl_host->n_next, n_act);
       rc = step(ws.ctl_host->n_next, 0, last);
       if (rc) return rc;
       if (n_act > 0) {
@@ -1162,14 +1183,16 @@ int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labe
   int dev = 0, ncu = 0;
   MC_HIP(hipGetDevice(&dev));
   MC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  rc = ensure_vc(ws, g->n, g->nnz, 1);
+  if (rc) return rc;
   MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
   fill<int32_t>(ws.gid[0], 0, g->n, s);
   fill<int32_t>(ws.active, 1, 1, s);
-  LpArgs L{g->n, g->row_ptr, g->col, g->w, ws.gid[0], ws.active, labels_in, labels_out, ws.newid,
-           &ws.ctl->lp_heavy, 1};
-  hipLaunchKernelGGL(k_lp_wave, dim3(grid_for((int64_t)g->n * 64, 64 * LP_WAVES, ncu * 16)), dim3(64 * LP_WAVES),
-                     0, s, L);
-  hipLaunchKernelGGL(k_lp_block, dim3(ncu * 2), dim3(LP_BLOCK_THREADS), 0, s, L);
+  fill<uint64_t>(ws.vc.best, 0, g->n, s);
+  LpArgs L{g->n, g->row_ptr, g->col, g->w, ws.gid[0], ws.active, labels_in, labels_out, ws.vc.item_off,
+           &ws.ctl->lp_items, ws.vc.best};
+  lp_items_prefix(L, ws, s);
+  lp_sweep(L, ncu, s);
   MC_HIP(hipStreamSynchronize(s));
   MC_HIP(hipGetLastError());
   return MC_OK;

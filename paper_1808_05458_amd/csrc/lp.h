@@ -8,10 +8,12 @@
 //
 // The per-label sums of a row are gathered in an LDS open-addressing map.
 // Rows up to LP_WAVE_MAX entries take one wave and a map of at least twice
-// the row length (it cannot fill).  Longer rows take a workgroup and a fixed
-// map; a row with more entries than one pass holds is split into passes by a
-// hash of the label, so each pass sees a disjoint set of labels; a pass whose
-// map would fill is redone with twice the passes.
+// the row length (it cannot fill).  Longer rows become workgroup items: a
+// row with more entries than one pass holds is split into passes by a hash
+// of the label, each pass an item of its own on any workgroup, so the
+// passes see disjoint label sets; a pass whose map would fill splits itself
+// further.  The best candidate of every item is folded into the row by a
+// 64-bit atomic max.
 //
 // The weights of one vertex sum to less than 2^31 (the total weight of a
 // graph is limited to 2(2^31 - 1) over its entries), so a map slot's sum
@@ -27,7 +29,7 @@ constexpr int LP_WAVE_MAX = 256;      // longest row of the one-wave path
 constexpr int LP_WAVE_SLOTS = 512;    // its map (>= 2 * LP_WAVE_MAX)
 constexpr int LP_WAVES = 4;           // waves per workgroup of the one-wave path
 constexpr int LP_BLOCK_SLOTS = 8192;  // map of the workgroup path
-constexpr int LP_BLOCK_LOAD = 4096;   // entries per pass of the workgroup path
+constexpr int LP_BLOCK_LOAD = 4096;   // entries per pass of the workgroup path (<= slots / 2)
 constexpr int LP_BLOCK_THREADS = 256;
 constexpr uint32_t LP_EMPTY = 0xFFFFFFFFu;
 
@@ -40,12 +42,18 @@ struct LpArgs {
   const int32_t* active;   // per graph: only these graphs' vertices are swept
   const int32_t* cur;      // labels before the sweep
   int32_t* nxt;            // labels after it
-  int32_t* heavy;          // rows longer than LP_WAVE_MAX, for the workgroup path
-  int32_t* heavy_count;
-  int32_t collect;         // append long rows to `heavy` (first sweep of a level)
+  const int32_t* item_off; // exclusive prefix of the workgroup items per vertex
+  const int32_t* nitems;   // device: total workgroup items
+  uint64_t* best;          // per vertex: best (sum, label) over its items, 0 = none
 };
 
 __device__ __forceinline__ uint32_t lp_hash(uint32_t label) { return label * 0x9E3779B1u; }
+
+// A second hash, a bijection of the label, that splits long rows into passes.
+__device__ __forceinline__ uint32_t lp_hash2(uint32_t label) {
+  uint32_t h = label * 0x85EBCA6Bu;
+  return h ^ (h >> 13);
+}
 
 // Add c to the slot of `label`, inserting it if absent.  The caller
 // guarantees an empty slot exists.
@@ -66,6 +74,21 @@ __device__ __forceinline__ uint64_t lp_pack(uint32_t sum, uint32_t label) {
   return ((uint64_t)sum << 32) | (uint32_t)~label;
 }
 
+__device__ __forceinline__ bool lp_long(const LpArgs& A, int64_t v) {
+  return A.rp[v + 1] - A.rp[v] > LP_WAVE_MAX && A.active[A.gid[v]];
+}
+
+// Workgroup items of a vertex: none for rows the wave path takes, else one
+// per pass of at most LP_BLOCK_LOAD entries.
+struct LpItems {
+  LpArgs A;
+  __device__ __forceinline__ int32_t operator()(int64_t v) const {
+    if (!lp_long(A, v)) return 0;
+    const int64_t d = A.rp[v + 1] - A.rp[v];
+    return (int32_t)((d + LP_BLOCK_LOAD - 1) / LP_BLOCK_LOAD);
+  }
+};
+
 // One wave per vertex for rows up to LP_WAVE_MAX entries.
 __global__ void __launch_bounds__(64 * LP_WAVES) k_lp_wave(LpArgs A) {
   __shared__ uint32_t keys_s[LP_WAVES][LP_WAVE_SLOTS];
@@ -78,10 +101,7 @@ __global__ void __launch_bounds__(64 * LP_WAVES) k_lp_wave(LpArgs A) {
     if (!A.active[A.gid[v]]) continue;
     const int64_t e0 = A.rp[v], e1 = A.rp[v + 1];
     const int64_t d = e1 - e0;
-    if (d > LP_WAVE_MAX) {
-      if (A.collect && lane == 0) A.heavy[atomicAdd(A.heavy_count, 1)] = (int32_t)v;
-      continue;
-    }
+    if (d > LP_WAVE_MAX) continue;  // a workgroup item
     // map size: a power of two >= max(64, 2d)
     int logm = 6;
     while ((1ll << logm) < 2 * d) ++logm;
@@ -111,63 +131,82 @@ __global__ void __launch_bounds__(64 * LP_WAVES) k_lp_wave(LpArgs A) {
   }
 }
 
-// One workgroup per long row, over the list the wave path collected.
-__global__ void __launch_bounds__(LP_BLOCK_THREADS) k_lp_block(LpArgs A) {
+// Workgroup items: pass p of a long row.  A row of d entries has
+// P = ceil(d / LP_BLOCK_LOAD) passes; pass p gathers the labels whose second
+// hash is p modulo P, so the passes of one row see disjoint label sets and
+// run on different workgroups.  A pass whose map would pass 3/4 full splits
+// itself by the next hash digit into twice as many sub-passes and starts
+// over.  Every item folds its best (sum, label) into best[v].
+__global__ void __launch_bounds__(LP_BLOCK_THREADS) k_lp_items(LpArgs A) {
   __shared__ uint32_t keys[LP_BLOCK_SLOTS];
   __shared__ uint32_t sums[LP_BLOCK_SLOTS];
   __shared__ int32_t used, overflow;
   __shared__ uint64_t wbest[LP_BLOCK_THREADS / 64];
-  constexpr int LOG = __builtin_ctz(LP_BLOCK_SLOTS);
-  constexpr uint32_t MASK = LP_BLOCK_SLOTS - 1;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int32_t cnt = *A.heavy_count;
-  for (int32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
-    const int32_t v = A.heavy[item];
+  const int32_t nitems = *A.nitems;
+  for (int32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    // the vertex: the last v with item_off[v] <= item (its range is non-empty)
+    int32_t lo = 0, hi = A.n - 1;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo + 1) / 2;
+      if (A.item_off[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t v = lo;
     const int64_t e0 = A.rp[v], e1 = A.rp[v + 1];
-    uint32_t passes = (uint32_t)((e1 - e0 + LP_BLOCK_LOAD - 1) / LP_BLOCK_LOAD);
+    const int64_t d = e1 - e0;
+    const uint32_t P = (uint32_t)((d + LP_BLOCK_LOAD - 1) / LP_BLOCK_LOAD);
+    const uint32_t p = (uint32_t)(item - A.item_off[v]);
+    // map: a power of two >= 2d for a single pass (it cannot fill), else all slots
+    int logm = 6;
+    while ((1ll << logm) < 2 * d && (1 << logm) < LP_BLOCK_SLOTS) ++logm;
+    const uint32_t m = 1u << logm, mask = m - 1;
+    const int shift = 32 - logm;
+    uint32_t K = 1;     // sub-passes of this pass
     uint64_t best = 0;  // meaningful in thread 0
-    for (uint32_t p = 0; p < passes; ++p) {
-      for (int i = threadIdx.x; i < LP_BLOCK_SLOTS; i += LP_BLOCK_THREADS) { keys[i] = LP_EMPTY; sums[i] = 0; }
+    for (uint32_t k = 0; k < K; ++k) {
+      for (uint32_t i = threadIdx.x; i < m; i += LP_BLOCK_THREADS) { keys[i] = LP_EMPTY; sums[i] = 0; }
       if (threadIdx.x == 0) { used = 0; overflow = 0; }
       __syncthreads();
       for (int64_t e = e0 + threadIdx.x; e < e1; e += LP_BLOCK_THREADS) {
         const int32_t y = A.col[e];
         if (y == v) continue;
         const uint32_t label = (uint32_t)A.cur[y];
-        // the pass of a label: a second hash, independent of the slot hash
-        if (passes > 1 && ((label * 0x85EBCA6Bu) ^ (label >> 13)) % passes != p) continue;
-        uint32_t h = (lp_hash(label) >> (32 - LOG)) & MASK;
+        const uint32_t h2 = lp_hash2(label);
+        if (P > 1 && h2 % P != p) continue;
+        if (K > 1 && (h2 / P) % K != k) continue;
+        uint32_t h = (lp_hash(label) >> shift) & mask;
         const uint32_t c = (uint32_t)A.w[e];
         while (true) {
-          uint32_t k = keys[h];
-          if (k == LP_EMPTY) {
+          uint32_t key = keys[h];
+          if (key == LP_EMPTY) {
             // claim a new slot only while the map stays at most 3/4 full
-            if (atomicAdd(&used, 1) >= (LP_BLOCK_SLOTS * 3) / 4) {
+            if (atomicAdd(&used, 1) >= (int32_t)(m * 3 / 4)) {
               atomicSub(&used, 1);
               overflow = 1;
               break;
             }
-            k = atomicCAS(&keys[h], LP_EMPTY, label);
-            if (k == LP_EMPTY) { atomicAdd(&sums[h], c); break; }
+            key = atomicCAS(&keys[h], LP_EMPTY, label);
+            if (key == LP_EMPTY) { atomicAdd(&sums[h], c); break; }
             atomicSub(&used, 1);
           }
-          if (k == label) { atomicAdd(&sums[h], c); break; }
-          h = (h + 1) & MASK;
+          if (key == label) { atomicAdd(&sums[h], c); break; }
+          h = (h + 1) & mask;
         }
       }
       __syncthreads();
-      if (overflow) {  // block-uniform: redo the row with twice the passes
-        passes *= 2;
-        p = (uint32_t)-1;
+      if (overflow) {  // workgroup-uniform: split into twice the sub-passes
+        K *= 2;
+        k = (uint32_t)-1;
         if (threadIdx.x == 0) best = 0;
         __syncthreads();
         continue;
       }
       uint64_t b = 0;
-      for (int i = threadIdx.x; i < LP_BLOCK_SLOTS; i += LP_BLOCK_THREADS) {
-        const uint32_t k = keys[i];
-        if (k != LP_EMPTY) {
-          const uint64_t c = lp_pack(sums[i], k);
+      for (uint32_t i = threadIdx.x; i < m; i += LP_BLOCK_THREADS) {
+        const uint32_t key = keys[i];
+        if (key != LP_EMPTY) {
+          const uint64_t c = lp_pack(sums[i], key);
           b = c > b ? c : b;
         }
       }
@@ -175,10 +214,20 @@ __global__ void __launch_bounds__(LP_BLOCK_THREADS) k_lp_block(LpArgs A) {
       if (lane == 0) wbest[wave] = b;
       __syncthreads();
       if (threadIdx.x == 0)
-        for (int k = 0; k < LP_BLOCK_THREADS / 64; ++k) best = wbest[k] > best ? wbest[k] : best;
+        for (int q = 0; q < LP_BLOCK_THREADS / 64; ++q) best = wbest[q] > best ? wbest[q] : best;
       __syncthreads();
     }
-    if (threadIdx.x == 0) A.nxt[v] = best ? (int32_t)~(uint32_t)best : A.cur[v];
+    if (threadIdx.x == 0 && best) atomic_max_u64(A.best + v, best);
+  }
+}
+
+// Long rows take the best over their items; best is cleared for the next sweep.
+__global__ void k_lp_finish(LpArgs A) {
+  for (int64_t v = gtid(); v < A.n; v += gstride()) {
+    if (!lp_long(A, v)) continue;
+    const uint64_t b = A.best[v];
+    A.nxt[v] = b ? (int32_t)~(uint32_t)b : A.cur[v];
+    A.best[v] = 0;
   }
 }
 
