@@ -900,7 +900,7 @@ struct Solver {
       hipLaunchKernelGGL(k_count_roots, gridr(n), dim3(TB), 0, s, n, ws.parent, gid, ws.nnew);
       // plan: whole-graph scans for small graphs (two map sizes), sweeps or
       // region scans otherwise
-      hipLaunchKernelGGL(k_plan_split, grid(G), dim3(TB), 0, s, G, S, rp, whole_small, whole_max,
+      hipLaunchKernelGGL(k_plan_split, dim3(1), dim3(PLAN_THREADS), 0, s, G, S, rp, whole_small, whole_max,
                          ws.whole2, ws.ctl);
       // scans
       ScanArgs A{};
@@ -949,18 +949,14 @@ struct Solver {
         hipLaunchKernelGGL(k_capforest<WHOLE_CAP_L>, dim3(num_cu * 2), dim3(64),
                            sizeof(ScanLds<WHOLE_CAP_L>), s, A);
       } else {
-        // whole small graphs: LDS-resident capped sweeps, one workgroup each
-        SmallSweepArgs SA{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.whole, &ws.ctl->n_whole,
-                          &ws.ctl->work_next, ws.fb_step, ws.capq, ws.capx, ws.npairs, ws.balpha,
-                          ws.fb_k, ws.ucount, A.seed};
+        // whole small graphs: LDS-resident capped sweeps, one workgroup each,
+        // the large-map list first (both lists are ordered largest first)
+        SmallSweepArgs SA{rp, col, w, ws.lhat, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
+                          &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_step, ws.capq, ws.capx, ws.npairs,
+                          ws.balpha, ws.fb_k, ws.ucount, A.seed};
         {
           TimedScope t("small_sweep", 0.0);
           MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
-          hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_S>, dim3(num_cu * 8), dim3(SS_THREADS),
-                             sizeof(SmallSweepLds<SMALL_CAP_S>), s, SA);
-          MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
-          SA.list = ws.whole2;
-          SA.list_count = &ws.ctl->n_whole2;
           hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_L>, dim3(num_cu * 2), dim3(SS_THREADS),
                              sizeof(SmallSweepLds<SMALL_CAP_L>), s, SA);
         }

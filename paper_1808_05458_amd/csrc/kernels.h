@@ -292,32 +292,66 @@ __global__ void k_round_reset(int32_t G, GraphState S) {
 
 // Mode 4: the Padberg-Rinaldi unions alone leave at most two blocks, so the
 // graph goes straight to contraction.  nnew holds the blocks after the tests.
-__global__ void k_plan_split(int32_t G, GraphState S, const int64_t* rp, int32_t whole_small,
-                             int32_t whole_max, int32_t* whole2, Ctl* ctl) {
-  for (int64_t g = gtid(); g < G; g += gstride()) {
+// One workgroup: graph modes, and the two whole-graph lists ordered largest
+// first (by size class, a quarter octave wide), so that the persistent
+// sweep workgroups take the longest graphs first and finish together.
+constexpr int PLAN_THREADS = 1024;
+constexpr int PLAN_CLASSES = 128;
+
+__device__ __forceinline__ int plan_class(int32_t n) {
+  const int lz = 31 - __builtin_clz((uint32_t)max(n, 1));
+  const int frac = lz >= 2 ? ((n >> (lz - 2)) & 3) : 0;
+  return lz * 4 + frac;
+}
+
+__global__ void __launch_bounds__(PLAN_THREADS) k_plan_split(int32_t G, GraphState S, const int64_t* rp,
+                                                             int32_t whole_small, int32_t whole_max,
+                                                             int32_t* whole2, Ctl* ctl) {
+  __shared__ int32_t off[2][PLAN_CLASSES];
+  for (int i = threadIdx.x; i < 2 * PLAN_CLASSES; i += PLAN_THREADS) off[i / PLAN_CLASSES][i % PLAN_CLASSES] = 0;
+  __syncthreads();
+  int64_t nnz_acc = 0, nv_acc = 0;
+  int32_t region = 0;
+  for (int64_t g = threadIdx.x; g < G; g += PLAN_THREADS) {
     uint8_t m = 0;
     if (S.active[g]) {
-      if (S.nnew[g] <= 2) {
-        m = 4;
-      } else if (S.n[g] <= whole_small) {
-        m = 1;
-        S.whole[atomicAdd(&ctl->n_whole, 1)] = (int32_t)g;
-      } else if (S.n[g] <= whole_max) {
-        m = 3;
-        whole2[atomicAdd(&ctl->n_whole2, 1)] = (int32_t)g;
-      } else {
-        m = 2;
-        atomicAdd(&ctl->n_region, 1);
-      }
-      if (m == 1 || m == 3) {  // sizes for the scan's byte count
-        const int32_t v0 = S.cvoff[g];
-        atomicAdd((unsigned long long*)&ctl->whole_nnz, (unsigned long long)(rp[v0 + S.n[g]] - rp[v0]));
-        atomicAdd((unsigned long long*)&ctl->whole_nv, (unsigned long long)S.n[g]);
-      }
+      if (S.nnew[g] <= 2) m = 4;
+      else if (S.n[g] <= whole_small) m = 1;
+      else if (S.n[g] <= whole_max) m = 3;
+      else m = 2;
     }
     S.mode[g] = m;
+    if (m == 1 || m == 3) {
+      atomicAdd(&off[m == 3][plan_class(S.n[g])], 1);
+      const int32_t v0 = S.cvoff[g];
+      nnz_acc += rp[v0 + S.n[g]] - rp[v0];
+      nv_acc += S.n[g];
+    }
+    region += m == 2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {  // exclusive offsets, largest class first
+    int32_t run = 0;
+    for (int c = PLAN_CLASSES - 1; c >= 0; --c) {
+      const int32_t k = off[threadIdx.x][c];
+      off[threadIdx.x][c] = run;
+      run += k;
+    }
+    if (threadIdx.x == 0) ctl->n_whole = run;
+    else ctl->n_whole2 = run;
+  }
+  __syncthreads();
+  for (int64_t g = threadIdx.x; g < G; g += PLAN_THREADS) {
+    const uint8_t m = S.mode[g];
+    if (m == 1 || m == 3) {
+      const int32_t at = atomicAdd(&off[m == 3][plan_class(S.n[g])], 1);
+      (m == 3 ? whole2 : S.whole)[at] = (int32_t)g;
+    }
     S.nnew[g] = 0;
   }
+  if (nnz_acc) atomicAdd((unsigned long long*)&ctl->whole_nnz, (unsigned long long)nnz_acc);
+  if (nv_acc) atomicAdd((unsigned long long*)&ctl->whole_nv, (unsigned long long)nv_acc);
+  if (region) atomicAdd(&ctl->n_region, region);
 }
 
 // ------------------------------------------------------- Padberg-Rinaldi

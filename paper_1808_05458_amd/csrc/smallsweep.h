@@ -1,12 +1,24 @@
 // Capped CAPFOREST sweep of a whole small graph inside one workgroup
 // (appendix Algorithm 3 with the cap of Lemma 1; batches of capped vertices
 // as in sweep.h).  The graph's vertices [v0, v0 + ng) index LDS arrays
-// directly: r (weight to the visited set) and the state, so every priority
-// update is an LDS atomic.  Each step makes one pass over the graph's slots:
-// all frontier vertices whose key reached the cap form the batch; if there
-// are none, the frontier vertex with the largest key (< cap) is the batch.
-// Crossing edges r(y) < cap <= r(y) + c(e) are recorded as pairs and united
-// after the kernel; alpha (= c(S) of the visited set) is tracked per batch.
+// directly (16-bit local ids): r (weight to the visited set) and the state,
+// so every priority update is an LDS atomic.
+//
+// A vertex enters the capped queue when its r crosses the cap (exactly one
+// relaxation crosses, since r only grows).  A step's batch is the part of
+// the queue filled since the last step: every unvisited vertex at the cap,
+// and nothing can exceed the cap, so they are all maxima of the capped keys
+// and any order among them is a legal maximum-adjacency order.  With the
+// queue empty every unvisited vertex is below the cap, and one wave pops
+// singles by itself, without workgroup barriers, until some vertex reaches
+// the cap.  Its maximum comes from a two-level structure: per chunk of 64
+// vertices an upper bound of r over the chunk's unvisited vertices (raised
+// by an atomic max on every relaxation), and an exact scan of the best
+// chunk, which lowers a stale bound and retries.  A batch is relaxed by the
+// whole workgroup with its entries spread evenly over the threads.  The
+// crossings are the contractible pairs r(y) < cap <= r(y) + c(e) of
+// Algorithm 1; alpha (= c(S) of the visited set) is tracked per step from
+// the row sums, r and the batch-internal weight.
 #pragma once
 #include "capforest.h"
 #include "sweep.h"
@@ -17,12 +29,13 @@ struct SmallSweepArgs {
   const int64_t* rp;
   const int32_t* col;
   const int32_t* w;
-  const int64_t* cdeg;
   const int64_t* lhat;
   const int32_t* gn;
   const int32_t* gvoff;
-  const int32_t* list;         // graphs to sweep
-  const int32_t* list_count;   // device count of `list`
+  const int32_t* list_a;       // graphs to sweep: list_a then list_b, largest first
+  const int32_t* count_a;      // device counts of the lists
+  const int32_t* list_b;
+  const int32_t* count_b;
   int32_t* work;               // work counter (zeroed by the host)
   int32_t* fb_step;            // visit stamp per vertex (side materialisation)
   int32_t* capq;               // crossing pairs (capx[i], capq[i]) at v0 + i
@@ -35,145 +48,265 @@ struct SmallSweepArgs {
 };
 
 constexpr int SS_THREADS = 256;
+constexpr int SS_NW = SS_THREADS / 64;
+constexpr int SS_UNROLL = 4;  // entries in flight per thread in a batch relax
 
 template <int CAP>
 struct SmallSweepLds {
+  static_assert(CAP <= 65536 && CAP % 64 == 0, "16-bit local vertex ids, whole chunks");
+  static constexpr int NC = CAP / 64;
   int32_t r[CAP];
-  int32_t batch[CAP];
-  uint8_t st[CAP];  // 0 unseen, 1 frontier, 2 visited, 3 in the current batch
-  int32_t nbatch, npairs;
-  uint64_t best;
-  int64_t wsum[SS_THREADS / 64], wint[SS_THREADS / 64];
-  uint64_t wbest[SS_THREADS / 64];
+  uint16_t capped[CAP];  // vertices in the order their r reached the cap
+  uint8_t st[CAP];       // 0 unvisited, 2 visited, 3 in the current batch
+  uint32_t cmax[NC];     // per 64-vertex chunk: >= r of its unvisited vertices
+  int32_t boff[SS_THREADS + 1];  // a batch chunk: entry offsets of its rows
+  int32_t bbase[SS_THREADS];     //   and each row's first entry (graph-relative)
+  int32_t wtot[SS_NW];
+  int32_t cap_head, cap_tail, npairs, first;
+  int32_t b0, nb, stamp;  // the batch capped[b0, b0 + nb); nb < 0: sweep done
+  int64_t wsum[SS_NW], wint[SS_NW];
 };
+
+__device__ __forceinline__ void ss_wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Relax one entry x -> y of weight c (local ids): update r(y) and its chunk
+// bound, and record the crossing r(y) < cap <= r(y) + c as a pair and a
+// capped vertex.  Must be called by all lanes of the wave.
+template <int CAP>
+__device__ __forceinline__ void ss_relax(SmallSweepLds<CAP>& L, const SmallSweepArgs& A, int32_t v0, int64_t lam,
+                                         bool ok, int32_t xl, int32_t yl, int32_t c, int64_t& rows,
+                                         int64_t& internal) {
+  bool cross = false;
+  if (ok && yl != xl) {
+    rows += c;
+    const uint8_t s = L.st[yl];
+    if (s == 3) {
+      internal += c;
+    } else if (s == 0) {
+      const int32_t old = atomicAdd(&L.r[yl], c);
+      atomicMax(&L.cmax[yl >> 6], (uint32_t)(old + c));
+      cross = (int64_t)old < lam && lam <= (int64_t)old + c;
+    }
+  }
+  const uint64_t cm = ballot(cross);
+  if (cm) {
+    int32_t at = 0, qa = 0;
+    if (lane_id() == 0) {
+      at = atomicAdd(&L.npairs, popc64(cm));
+      qa = atomicAdd(&L.cap_tail, popc64(cm));
+    }
+    at = shfl(at, 0);
+    qa = shfl(qa, 0);
+    if (cross) {
+      const int32_t rank = popc64(cm & lanemask_lt());
+      A.capq[v0 + at + rank] = v0 + yl;
+      A.capx[v0 + at + rank] = v0 + xl;
+      L.capped[qa + rank] = (uint16_t)yl;
+    }
+  }
+}
+
+// The unvisited vertex of largest r > 0 (one wave, no other wave active);
+// -1 when none is left.
+template <int CAP>
+__device__ __forceinline__ int32_t ss_select(SmallSweepLds<CAP>& L, int32_t ng) {
+  constexpr int NC = SmallSweepLds<CAP>::NC;
+  const int lane = lane_id();
+  const int nc = (ng + 63) >> 6;
+  while (true) {
+    uint64_t bc = 0;
+    for (int c = lane; c < nc && c < NC; c += 64) {
+      const uint64_t k = ((uint64_t)L.cmax[c] << 32) | (uint32_t)c;
+      bc = k > bc ? k : bc;
+    }
+    bc = wave_max_u64(bc);
+    const uint32_t bound = (uint32_t)(bc >> 32);
+    if (bound == 0) return -1;
+    const int c = (int)(uint32_t)bc;
+    const int32_t v = c * 64 + lane;
+    const uint32_t key = (v < ng && L.st[v] == 0) ? (uint32_t)L.r[v] : 0u;
+    const uint64_t kv = wave_max_u64(((uint64_t)key << 32) | (uint32_t)v);
+    const uint32_t exact = (uint32_t)(kv >> 32);
+    if (exact == bound) return (int32_t)(uint32_t)kv;
+    if (lane == 0) L.cmax[c] = exact;  // the bound was stale: lower it, retry
+    ss_wave_sync();
+  }
+}
 
 template <int CAP>
 __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
   extern __shared__ char lds_raw[];
   SmallSweepLds<CAP>& L = *reinterpret_cast<SmallSweepLds<CAP>*>(lds_raw);
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  constexpr int NW = SS_THREADS / 64;
   __shared__ int32_t sh_item;
   while (true) {
     if (threadIdx.x == 0) sh_item = atomicAdd(A.work, 1);
     __syncthreads();
     const int32_t item = sh_item;
-    if (item >= *A.list_count) return;
-    const int32_t g = A.list[item];
+    const int32_t na = *A.count_a;
+    if (item >= na + *A.count_b) return;
+    const int32_t g = item < na ? A.list_a[item] : A.list_b[item - na];
     const int32_t v0 = A.gvoff[g], ng = A.gn[g];
     const int64_t lam = A.lhat[g];
+    const int64_t ebase = A.rp[v0];
     for (int i = threadIdx.x; i < ng; i += SS_THREADS) {
       L.r[i] = 0;
       L.st[i] = 0;
       A.fb_step[v0 + i] = 0;
     }
+    for (int c = threadIdx.x; c < SmallSweepLds<CAP>::NC; c += SS_THREADS) L.cmax[c] = 0;
     uint64_t h = A.seed * 0x9E3779B97F4A7C15ull + (uint64_t)g * 0xBF58476D1CE4E5B9ull;
     h ^= h >> 29;
-    const int32_t start = (int32_t)(h % (uint64_t)ng);
-    if (threadIdx.x == 0) L.npairs = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) L.st[start] = 1;
-    int64_t alpha = 0, best_alpha = INT64_MAX;  // meaningful in thread 0
-    int32_t visited = 0, best_step = 0, stamp = 0;
+    if (threadIdx.x == 0) {
+      L.first = (int32_t)(h % (uint64_t)ng);  // the start
+      L.cap_head = L.cap_tail = 0;
+      L.npairs = 0;
+      L.nb = 0;
+      L.stamp = 0;
+    }
+    // alpha = c(S) of the visited prefix S; kept by wave 0, lane 0
+    int64_t alpha = 0, best_alpha = INT64_MAX, pend = 0;
+    int32_t visited = 0, best_step = 0;
     __syncthreads();
     while (true) {
-      // pass 1: capped frontier vertices form the batch; also the largest
-      // key below the cap
-      if (threadIdx.x == 0) L.nbatch = 0;
-      __syncthreads();
-      uint64_t best = 0;
-      for (int base = wave * 64; base < ng; base += SS_THREADS) {
-        const int i = base + lane;
-        bool capped = false;
-        if (i < ng && L.st[i] == 1) {
-          const int64_t key = L.r[i];
-          if (key >= lam) {
-            capped = true;
+      if (wave == 0) {
+        // fold the batch step just relaxed by the workgroup
+        const int32_t pnb = L.nb;
+        if (pnb > 0) {
+          if (lane == 0) {
+            int64_t sum = 0, in = 0;
+            for (int k = 0; k < SS_NW; ++k) { sum += L.wsum[k]; in += L.wint[k]; }
+            alpha += sum - pend - in;
+            visited += pnb;
+            if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = L.stamp; }
+          }
+          const int32_t pb0 = L.b0;
+          for (int k = lane; k < pnb; k += 64) L.st[L.capped[pb0 + k]] = 2;
+          ss_wave_sync();
+        }
+        // single pops, by this wave alone, while no vertex is at the cap
+        int32_t stamp = L.stamp;
+        bool done = false;
+        while (true) {
+          ss_wave_sync();
+          if (L.cap_head != L.cap_tail) break;
+          int32_t xl = L.first;
+          if (xl >= 0) {
+            ss_wave_sync();
+            if (lane == 0) L.first = -1;
           } else {
-            const uint64_t c = ((uint64_t)(key + 1) << 32) | (uint32_t)i;
-            best = c > best ? c : best;
+            xl = ss_select<CAP>(L, ng);
+          }
+          if (xl < 0) { done = true; break; }
+          ++stamp;
+          if (lane == 0) {
+            L.st[xl] = 3;
+            A.fb_step[v0 + xl] = stamp;
+          }
+          ss_wave_sync();
+          const int64_t e0 = A.rp[v0 + xl], e1 = A.rp[v0 + xl + 1];
+          int64_t rows = 0, internal = 0;
+          for (int64_t base = e0; base < e1; base += 64) {
+            const int64_t e = base + lane;
+            const bool ok = e < e1;
+            ss_relax<CAP>(L, A, v0, lam, ok, xl, ok ? A.col[e] - v0 : 0, ok ? A.w[e] : 0, rows, internal);
+          }
+          rows = wave_sum_i64(rows);
+          if (lane == 0) {
+            alpha += rows - 2 * (int64_t)L.r[xl];
+            visited += 1;
+            if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = stamp; }
+            L.st[xl] = 2;
           }
         }
-        const uint64_t m = ballot(capped);
-        if (m) {
-          int32_t at = 0;
-          if (lane == 0) at = atomicAdd(&L.nbatch, popc64(m));
-          at = shfl(at, 0);
-          if (capped) L.batch[at + popc64(m & lanemask_lt())] = i;
+        // publish the next batch: every vertex that reached the cap; mark it
+        if (!done) ++stamp;
+        if (lane == 0) {
+          if (done) {
+            L.nb = -1;
+          } else {
+            L.b0 = L.cap_head;
+            L.nb = L.cap_tail - L.cap_head;
+            L.cap_head = L.cap_tail;
+          }
+          L.stamp = stamp;
+        }
+        ss_wave_sync();
+        if (!done) {
+          const int32_t b0 = L.b0, nb = L.nb;
+          int64_t r2 = 0;
+          for (int k = lane; k < nb; k += 64) {
+            const int32_t x = L.capped[b0 + k];
+            L.st[x] = 3;
+            A.fb_step[v0 + x] = stamp;
+            r2 += 2 * (int64_t)L.r[x];
+          }
+          r2 = wave_sum_i64(r2);
+          pend = r2;
         }
       }
-      best = wave_max_u64(best);
-      if (lane == 0) L.wbest[wave] = best;
       __syncthreads();
-      if (threadIdx.x == 0) {
-        uint64_t b = 0;
-        for (int k = 0; k < NW; ++k) b = L.wbest[k] > b ? L.wbest[k] : b;
-        if (L.nbatch == 0 && b != 0) {
-          L.batch[0] = (int32_t)(uint32_t)b;
-          L.nbatch = 1;
+      const int32_t nb = L.nb;
+      if (nb < 0) break;
+      // batch relax: the batch's entries spread evenly over the workgroup, in
+      // chunks of SS_THREADS rows
+      const int32_t b0 = L.b0;
+      int64_t rows = 0, internal = 0;
+      for (int32_t c0 = 0; c0 < nb; c0 += SS_THREADS) {
+        const int32_t cn = min(SS_THREADS, nb - c0);
+        int32_t deg = 0;
+        if ((int32_t)threadIdx.x < cn) {
+          const int32_t x = v0 + L.capped[b0 + c0 + threadIdx.x];
+          const int64_t a = A.rp[x];
+          deg = (int32_t)(A.rp[x + 1] - a);
+          L.bbase[threadIdx.x] = (int32_t)(a - ebase);
         }
-      }
-      __syncthreads();
-      const int32_t nb = L.nbatch;
-      if (nb == 0) break;  // frontier empty
-      ++stamp;
-      // mark the batch
-      int64_t sum = 0;
-      for (int k = threadIdx.x; k < nb; k += SS_THREADS) {
-        const int32_t x = L.batch[k];
-        L.st[x] = 3;
-        A.fb_step[v0 + x] = stamp;
-        sum += A.cdeg[v0 + x] - 2 * (int64_t)L.r[x];
-      }
-      __syncthreads();
-      // relax the batch's rows: a wave per batch vertex, lanes over the row
-      int64_t internal = 0;
-      for (int k = wave; k < nb; k += NW) {
-        const int32_t xl = L.batch[k];
-        const int32_t x = v0 + xl;
-        const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
-        for (int64_t base = e0; base < e1; base += 64) {
-          const int64_t e = base + lane;
-          bool cross = false;
-          int32_t yl = 0;
-          if (e < e1) {
-            yl = A.col[e] - v0;
-            const int32_t c = A.w[e];
-            const uint8_t s = L.st[yl];
-            if (yl == xl) {
-            } else if (s == 3) {
-              internal += c;
-            } else if (s != 2) {
-              const int32_t old = atomicAdd(&L.r[yl], c);
-              if (s == 0) L.st[yl] = 1;
-              cross = (int64_t)old < lam && lam <= (int64_t)old + c;
+        int32_t incl = deg;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int32_t t = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += t;
+        }
+        if (lane == 63) L.wtot[wave] = incl;
+        __syncthreads();
+        int32_t before = 0;
+        for (int k = 0; k < wave; ++k) before += L.wtot[k];
+        if ((int32_t)threadIdx.x < cn) L.boff[threadIdx.x] = before + incl - deg;
+        if ((int32_t)threadIdx.x == cn - 1) L.boff[cn] = before + incl;
+        __syncthreads();
+        const int32_t total = L.boff[cn];
+        for (int32_t i0 = 0; i0 < total; i0 += SS_THREADS * SS_UNROLL) {
+          int32_t ys[SS_UNROLL], cs[SS_UNROLL], xs[SS_UNROLL];
+#pragma unroll
+          for (int u = 0; u < SS_UNROLL; ++u) {
+            const int32_t i = i0 + u * SS_THREADS + (int32_t)threadIdx.x;
+            xs[u] = -1;
+            ys[u] = 0;
+            cs[u] = 0;
+            if (i < total) {
+              int32_t lo = 0, hi = cn - 1;  // the row: last k with boff[k] <= i
+              while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (L.boff[mid] <= i) lo = mid;
+                else hi = mid - 1;
+              }
+              const int64_t e = ebase + L.bbase[lo] + (i - L.boff[lo]);
+              xs[u] = L.capped[b0 + c0 + lo];
+              ys[u] = A.col[e] - v0;
+              cs[u] = A.w[e];
             }
           }
-          const uint64_t cm = ballot(cross);
-          if (cm) {
-            int32_t at = 0;
-            if (lane == 0) at = atomicAdd(&L.npairs, popc64(cm));
-            at = shfl(at, 0);
-            if (cross) {
-              const int32_t q = v0 + at + popc64(cm & lanemask_lt());
-              A.capq[q] = v0 + yl;
-              A.capx[q] = x;
-            }
-          }
+#pragma unroll
+          for (int u = 0; u < SS_UNROLL; ++u)
+            ss_relax<CAP>(L, A, v0, lam, xs[u] >= 0, xs[u], ys[u], cs[u], rows, internal);
         }
+        __syncthreads();  // boff and bbase are reused by the next chunk
       }
-      sum = wave_sum_i64(sum);
+      rows = wave_sum_i64(rows);
       internal = wave_sum_i64(internal);
-      if (lane == 0) { L.wsum[wave] = sum; L.wint[wave] = internal; }
-      __syncthreads();
-      for (int k = threadIdx.x; k < nb; k += SS_THREADS) L.st[L.batch[k]] = 2;
-      if (threadIdx.x == 0) {
-        int64_t s = 0, in = 0;
-        for (int k = 0; k < NW; ++k) { s += L.wsum[k]; in += L.wint[k]; }
-        alpha += s - in;
-        visited += nb;
-        if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = stamp; }
-      }
+      if (lane == 0) { L.wsum[wave] = rows; L.wint[wave] = internal; }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
