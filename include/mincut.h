@@ -192,6 +192,72 @@ void mc_release(void);
 
 const char* mc_strerror(int code);
 
+/* ---------------------------------------------------------- served form
+ * A request loop with continuous batching (no counterpart in the paper; the
+ * solver underneath is the same).  Requests are host CSRs of single graphs
+ * (same layout and rules as mc_graph, 0-based ids).  `lanes` host threads,
+ * each with its own HIP stream and workspace, take requests from a FIFO
+ * queue while their device footprint fits mem_budget: a request with more
+ * than small_max_nnz entries runs alone, a run of smaller ones is packed
+ * into one mc_mincut_batched-style solve (at most max_batch graphs).  Lanes
+ * run concurrently, so newly arrived requests start while earlier ones are
+ * still on the GPU.  A request's lambda does not depend on its batch.
+ * Timing (mc_options.timing) is per host thread and ignored by the lanes. */
+typedef struct mc_server mc_server;
+
+typedef struct mc_server_cfg {
+  int32_t lanes;           /* concurrent solves; default 2 */
+  int32_t max_batch;       /* graphs per packed solve; default 4096 */
+  int64_t small_max_nnz;   /* larger requests run alone; default 2^22 */
+  int64_t mem_budget;      /* device bytes of the requests in flight (input,
+                              side and solver workspace share); 0 = half of
+                              the free memory at creation */
+  int32_t queue_cap;       /* waiting requests before MC_EBUSY; default 65536 */
+  int32_t device;          /* HIP device; -1 = the current one */
+  int32_t validate;        /* 1 (default): check every request on submit */
+  int32_t reserved;
+  mc_options opt;          /* solver options of every solve */
+} mc_server_cfg;
+
+typedef struct mc_request {
+  int32_t n;
+  int32_t borrow;          /* 1: the server reads the caller's arrays, which
+                              must stay valid until mc_server_wait returns;
+                              0: they are copied on submit */
+  int64_t nnz;
+  const int64_t* row_ptr;  /* HOST, n + 1 */
+  const int32_t* col;      /* HOST, nnz */
+  const int32_t* w;        /* HOST, nnz */
+} mc_request;
+
+typedef struct mc_latency {
+  double queue_ms;         /* submit -> admitted by a lane */
+  double solve_ms;         /* admitted -> result on the host (upload, solve, side) */
+  double total_ms;         /* submit -> result */
+  int32_t batch_graphs;    /* graphs in the packed solve it ran in */
+  int32_t lane;
+} mc_latency;
+
+void mc_server_cfg_default(mc_server_cfg* cfg);
+
+/* Start the lanes.  *out receives the server.  MC_EINVAL for a bad
+ * configuration, MC_EHIP if the device is unusable. */
+int mc_server_create(const mc_server_cfg* cfg, mc_server** out);
+
+/* Queue one request; *ticket identifies it.  MC_ENOCUT (n < 2), MC_EINVAL /
+ * MC_EOVERFLOW (validation), MC_ENOMEM (footprint above the budget),
+ * MC_EBUSY (queue full), MC_ESTATE (server stopping). */
+int mc_server_submit(mc_server* srv, const mc_request* req, uint64_t* ticket);
+
+/* Block until the request is done; lambda (HOST), side (HOST uint8[n] or
+ * NULL; side[0] = 0) and lat (or NULL) receive its result.  The ticket is
+ * released.  MC_ESTATE for an unknown ticket; otherwise the solve's code. */
+int mc_server_wait(mc_server* srv, uint64_t ticket, int64_t* lambda, uint8_t* side, mc_latency* lat);
+
+/* Finish every queued request, stop the lanes and free the server.
+ * Results not collected by mc_server_wait are dropped. */
+int mc_server_destroy(mc_server* srv);
+
 /* Kernel-class timing, filled when mc_options.timing = 1: launches, summed
  * device time (HIP events on the launch stream) and algorithmic bytes. */
 typedef struct mc_timing_entry {

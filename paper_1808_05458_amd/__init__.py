@@ -44,6 +44,7 @@ class MincutError(RuntimeError):
         msg = lib.mc_strerror(code).decode()
         super().__init__(f"{what}: {msg} (code {code})")
         self.code = code
+        self.code = code
 
 
 class Options(ctypes.Structure):
@@ -134,8 +135,102 @@ def _load():
     lib.mc_timing_get.restype = ctypes.c_int
     lib.mc_timing_reset.argtypes = []
     lib.mc_timing_reset.restype = None
+    lib.mc_server_cfg_default.argtypes = [vp]
+    lib.mc_server_cfg_default.restype = None
+    lib.mc_server_create.argtypes = [vp, vp]
+    lib.mc_server_create.restype = ctypes.c_int
+    lib.mc_server_submit.argtypes = [vp, vp, vp]
+    lib.mc_server_submit.restype = ctypes.c_int
+    lib.mc_server_wait.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
+    lib.mc_server_wait.restype = ctypes.c_int
+    lib.mc_server_destroy.argtypes = [vp]
+    lib.mc_server_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("small_max_nnz", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
+                ("queue_cap", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32), ("opt", Options)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("borrow", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class Latency(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("batch_graphs", ctypes.c_int32),
+                ("lane", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Server:
+    """The served form: host CSR requests, continuous batching over lanes.
+    submit() returns a ticket; wait(ticket) returns (lambda, side, latency).
+    With borrow=True the arrays are kept referenced here until wait()."""
+
+    def __init__(self, opts: Optional[Options] = None, **cfg):
+        lib = _load()
+        c = ServerCfg()
+        lib.mc_server_cfg_default(ctypes.byref(c))
+        if opts is not None:
+            c.opt = opts
+        for k, v in cfg.items():
+            if not hasattr(c, k):
+                raise TypeError(f"unknown server setting {k}")
+            setattr(c, k, v)
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        rc = lib.mc_server_create(ctypes.byref(c), ctypes.byref(self._h))
+        if rc != MC_OK:
+            raise MincutError(rc, "mc_server_create")
+        self._held = {}
+        self._n = {}
+
+    def submit(self, g, borrow: bool = True) -> int:
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(g.col, dtype=np.int32)
+        w = np.ascontiguousarray(g.w, dtype=np.int32)
+        r = Request(g.n, 1 if borrow else 0, len(col), rp.ctypes.data, col.ctypes.data, w.ctypes.data)
+        t = ctypes.c_uint64(0)
+        rc = self._lib.mc_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
+        if rc != MC_OK:
+            raise MincutError(rc, "mc_server_submit")
+        if borrow:
+            self._held[t.value] = (rp, col, w)
+        self._n[t.value] = g.n
+        return t.value
+
+    def wait(self, ticket: int, want_side: bool = True):
+        n = self._n.pop(ticket)
+        side = np.zeros(n, np.uint8) if want_side else None
+        lam = ctypes.c_int64(-1)
+        lat = Latency()
+        rc = self._lib.mc_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(lam),
+                                      side.ctypes.data_as(ctypes.c_void_p) if side is not None else None,
+                                      ctypes.byref(lat))
+        self._held.pop(ticket, None)
+        if rc != MC_OK:
+            raise MincutError(rc, "mc_server_wait")
+        return int(lam.value), side, lat.as_dict()
+
+    def close(self):
+        if self._h:
+            self._lib.mc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def options(**kw) -> Options:

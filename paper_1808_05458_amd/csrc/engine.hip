@@ -115,8 +115,10 @@ struct Timer {
   }
 };
 
+// One timer per host thread: concurrent solves (the server's lanes) never
+// share one, and mc_timing_get reports the calling thread's.
 Timer& timer() {
-  static Timer t;
+  static thread_local Timer t;
   return t;
 }
 
@@ -745,25 +747,24 @@ struct Solver {
     const bool want_side = side != nullptr;
     int dev = 0;
     MC_HIP(hipGetDevice(&dev));
-    static int cached_dev = -1, cached_cu = 0;
-    if (cached_dev != dev) {
-      MC_HIP(hipDeviceGetAttribute(&cached_cu, hipDeviceAttributeMultiprocessorCount, dev));
-      cached_dev = dev;
-    }
-    num_cu = cached_cu;
-    static bool attrs_set = false;
-    if (!attrs_set) {
-      MC_HIP(hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_L>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sizeof(ScanLds<WHOLE_CAP_L>)));
-      MC_HIP(hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_S>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sizeof(ScanLds<WHOLE_CAP_S>)));
-      MC_HIP(hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sizeof(SmallSweepLds<SMALL_CAP_L>)));
-      attrs_set = true;
-    }
+    MC_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    // kernels with more than 64 KiB of dynamic LDS, once per process
+    static std::once_flag attrs_once;
+    static hipError_t attrs_err = hipSuccess;
+    std::call_once(attrs_once, [] {
+      hipError_t e = hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_L>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)sizeof(ScanLds<WHOLE_CAP_L>));
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(ScanLds<WHOLE_CAP_S>));
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(SmallSweepLds<SMALL_CAP_L>));
+      attrs_err = e;
+    });
+    MC_HIP(attrs_err);
 
     MC_HIP(hipMemcpyAsync(ws.voff, P.voff_host, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
@@ -1082,9 +1083,10 @@ Workspace& global_ws() {
   return ws;
 }
 
-int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
-        mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
-        const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
+// A solve on a given workspace and stream (no lock: the caller owns both).
+int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
+           mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
+           const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
   if (!lambdas || !P.rp || !P.col || !P.w || P.G < 1 || P.n < 2 || P.nnz < 0) return MC_EINVAL;
   if (P.n > (1 << 30) - 1 || P.nnz >= (int64_t)UINT32_MAX) return MC_EINVAL;
   for (int32_t g = 0; g < P.G; ++g) {
@@ -1092,7 +1094,6 @@ int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas,
     if (P.voff_host[g + 1] - P.voff_host[g] < 2) return MC_ENOCUT;
   }
   if (P.voff_host[0] != 0 || P.voff_host[P.G] != P.n) return MC_EINVAL;
-  std::lock_guard<std::mutex> lock(api_mutex());
   auto t0 = std::chrono::steady_clock::now();
   mc_options o;
   mc_options_default(&o);
@@ -1100,7 +1101,6 @@ int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas,
   if (st) {
     std::memset(st, 0, sizeof(*st));
   }
-  Workspace& ws = global_ws();
   int rc = ensure(ws, P.n, P.nnz, P.G);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -1118,6 +1118,15 @@ int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas,
   T.on = false;
   if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
+}
+
+// The library's own entry points share one cached workspace per process.
+int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
+        mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
+        const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
+  std::lock_guard<std::mutex> lock(api_mutex());
+  return run_on(global_ws(), P, stream, opt, lambdas, side, st, debug_labels, debug_lhat, lhat_in,
+                viecut_levels);
 }
 
 }  // namespace mc
@@ -1288,3 +1297,5 @@ int mc_timing_get(mc_timing_entry* out, int max) {
 void mc_timing_reset(void) { mc::timer().classes.clear(); }
 
 }  // extern "C"
+
+#include "server.h"

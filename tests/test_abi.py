@@ -64,9 +64,10 @@ def test_struct_layouts_match_header():
     #include <stddef.h>
     #include "mincut.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mc_graph), sizeof(mc_batch),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mc_graph), sizeof(mc_batch),
              sizeof(mc_options), sizeof(mc_stats), sizeof(mc_timing_entry),
-             offsetof(mc_stats, ms), offsetof(mc_options, timing));
+             offsetof(mc_stats, ms), offsetof(mc_options, timing), sizeof(mc_server_cfg),
+             sizeof(mc_request), sizeof(mc_latency), offsetof(mc_server_cfg, opt));
       return 0;
     }
     """
@@ -81,6 +82,10 @@ def test_struct_layouts_match_header():
     assert vals[2] == ctypes.sizeof(mc.Options)
     assert vals[3] == ctypes.sizeof(mc.Stats)
     assert vals[4] == ctypes.sizeof(mc.TimingEntry)
+    assert vals[7] == ctypes.sizeof(mc.ServerCfg)
+    assert vals[8] == ctypes.sizeof(mc.Request)
+    assert vals[9] == ctypes.sizeof(mc.Latency)
+    assert vals[10] == mc.ServerCfg.opt.offset
     assert vals[5] == mc.Stats.ms.offset
     assert vals[6] == mc.Options.timing.offset
 

@@ -1,0 +1,166 @@
+"""GPU tests of the served form: requests in a mix (coalesced into packed
+solves, several lanes, arrivals while others run) give the same lambda as
+the same graphs solved alone and as the oracle, sides realise lambda, and
+admission by memory, validation and error paths behave as declared."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import announce, check_side, random_graph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1808_05458_amd as mc
+    mc._load()
+    yield
+
+
+def _requests():
+    rng = np.random.default_rng(17)
+    graphs = [gg.batch_graph(i) for i in range(0, 600, 7)]
+    graphs += [random_graph(rng, int(rng.integers(2, 30)), 0.3, 9) for _ in range(30)]
+    graphs += [gg.from_edges(2, [(0, 1)], [5]), gg.complete(6),
+               gg.from_edges(6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)])]  # disconnected
+    graphs += [gg.served_request(i) for i in (3, 11)]
+    graphs.append(gg.planted_4096())
+    rng.shuffle(graphs)
+    return graphs
+
+
+@pytest.fixture(scope="module")
+def reqs():
+    graphs = _requests()
+    refs = [oracle.noi(g, 2)[0] for g in graphs]
+    return graphs, refs
+
+
+def _check(g, ref, lam, side):
+    assert lam == ref, (g.name, lam, ref)
+    check_side(g, lam, side)
+
+
+def test_mix_equals_alone_and_oracle(reqs):
+    import paper_1808_05458_amd as mc
+    graphs, refs = reqs
+    # alone: the single-graph entry point
+    alone = []
+    for g in graphs:
+        rp, col, w = mc.to_device(g, "cuda")
+        alone.append(mc.mincut(rp, col, w, want_side=False)[0])
+    assert alone == refs
+    # in the mix: everything submitted at once; small requests coalesce, the
+    # two largest run alone (small_max_nnz)
+    for lanes, small_max in [(1, 1 << 22), (3, 1 << 22), (2, 50000)]:
+        announce("server mix", len(graphs), "lanes", lanes, "small_max", small_max)
+        with mc.Server(lanes=lanes, small_max_nnz=small_max) as srv:
+            tickets = [srv.submit(g) for g in graphs]
+            out = [srv.wait(t) for t in tickets]
+        batched = 0
+        for g, ref, (lam, side, lat) in zip(graphs, refs, out):
+            _check(g, ref, lam, side)
+            assert lat["total_ms"] >= lat["solve_ms"] >= 0 and lat["queue_ms"] >= 0
+            if g.nnz > small_max:
+                assert lat["batch_graphs"] == 1
+            batched = max(batched, lat["batch_graphs"])
+        assert batched > 1  # small requests did coalesce
+
+
+def test_arrivals_while_solving(reqs):
+    # a producer submits with pauses while a consumer waits: later requests
+    # are admitted while earlier ones are still on the GPU
+    import paper_1808_05458_amd as mc
+    graphs, refs = reqs
+    announce("server arrivals", len(graphs))
+    results = {}
+    with mc.Server(lanes=2) as srv:
+        tickets = []
+        lock = threading.Lock()
+
+        def produce():
+            rng = np.random.default_rng(3)
+            for i, g in enumerate(graphs):
+                t = srv.submit(g, borrow=bool(i % 2))
+                with lock:
+                    tickets.append((i, t))
+                time.sleep(float(rng.exponential(0.002)))
+
+        th = threading.Thread(target=produce)
+        th.start()
+        done = 0
+        while done < len(graphs):
+            with lock:
+                pending = tickets[done:]
+            if not pending:
+                time.sleep(0.001)
+                continue
+            i, t = pending[0]
+            results[i] = srv.wait(t)
+            done += 1
+        th.join()
+    lanes_used = set()
+    for i, (lam, side, lat) in results.items():
+        _check(graphs[i], refs[i], lam, side)
+        lanes_used.add(lat["lane"])
+    assert lanes_used <= {0, 1}
+
+
+def test_memory_budget_admits_one_at_a_time(reqs):
+    import paper_1808_05458_amd as mc
+    graphs, refs = reqs
+    small = [(g, r) for g, r in zip(graphs, refs) if g.n < 3000][:20]
+    announce("server budget", len(small))
+
+    def footprint(g):  # as the server counts it: input, side, solver share
+        return (g.n + 1) * 8 + g.nnz * 8 + g.n + mc.workspace_bytes(g.n, g.nnz, 1)
+
+    fp = [footprint(g) for g, _ in small]
+    budget = max(fp)  # the largest request fits alone
+    with mc.Server(lanes=2, mem_budget=budget) as srv:
+        ts = [srv.submit(g) for g, _ in small]
+        out = [srv.wait(t) for t in ts]
+    for (g, ref), (lam, side, lat) in zip(small, out):
+        _check(g, ref, lam, side)
+        # the two lanes together never hold more than the budget
+        assert lat["batch_graphs"] * min(fp) <= budget
+    # a request above the budget is refused on submit
+    with mc.Server(lanes=1, mem_budget=1 << 16) as srv:
+        with pytest.raises(mc.MincutError) as e:
+            srv.submit(gg.planted_4096())
+        assert e.value.code == mc.MC_ENOMEM
+
+
+def test_invalid_requests_are_refused():
+    import paper_1808_05458_amd as mc
+    with mc.Server(lanes=1) as srv:
+        bad = gg.from_edges(3, [(0, 1), (1, 2)], [1, 1])
+        bad.col = bad.col.copy()
+        bad.col[0] = 7  # out of range
+        with pytest.raises(mc.MincutError) as e:
+            srv.submit(bad)
+        assert e.value.code == mc.MC_EINVAL
+        zero = gg.from_edges(3, [(0, 1), (1, 2)], [1, 0])
+        with pytest.raises(mc.MincutError) as e:
+            srv.submit(zero)
+        assert e.value.code == mc.MC_EINVAL
+        one = gg.from_edges(1, np.zeros((0, 2), np.int64), [])
+        with pytest.raises(mc.MincutError) as e:
+            srv.submit(one)
+        assert e.value.code == mc.MC_ENOCUT
+        # the server still works after refusals; an unknown ticket is refused
+        t = srv.submit(gg.complete(5))
+        lam, side, lat = srv.wait(t)
+        assert lam == 4
+        with pytest.raises(mc.MincutError) as e:
+            srv._n[12345] = 3
+            srv.wait(12345)
+        assert e.value.code == mc.MC_ESTATE
