@@ -95,6 +95,94 @@ def batched_form(steps, warmup):
             "verified": {"lambdas_equal_oracle": packed_ok and loop_ok, "side_weights_equal": sides_ok}}
 
 
+def served_form(requests, pool_size, lanes, seed=5):
+    """Poisson arrivals of min-cut requests (Chung-Lu, exponent 2.5, average
+    degree 16, n log-uniform in [2^10, 2^20], weights in [1, 50], largest
+    component) drawn from a pool of generated graphs, served with continuous
+    batching.  The capacity is measured closed-loop first; the open-loop
+    runs arrive at 0.3 and 0.7 of it.  Latency = submit -> result on the host
+    (host CSR in, upload included)."""
+    import threading
+    import torch
+    import graphgen as gg
+    import paper_1808_05458_amd as mc
+    t0 = time.time()
+    pool = [gg.served_request(i) for i in range(pool_size)]
+    log(f"served: pool of {pool_size} requests, sum n={sum(g.n for g in pool)} "
+        f"sum m={sum(g.m for g in pool)} in {time.time() - t0:.1f}s")
+    alone = []
+    for g in pool:
+        rp, col, w = mc.to_device(g, "cuda:0")
+        alone.append(mc.mincut(rp, col, w, want_side=False)[0])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    order = rng.integers(0, pool_size, size=requests)
+    mean_m = float(np.mean([pool[i].m for i in order]))
+
+    def run(rate):
+        """rate None: everything submitted at once (closed loop)."""
+        lat, ok = [], True
+        with mc.Server(lanes=lanes) as srv:
+            for i in range(min(8, pool_size)):  # warm the lanes
+                srv.wait(srv.submit(pool[i]))
+            tickets = [None] * requests
+            ready = threading.Semaphore(0)
+
+            def produce():
+                gaps = rng.exponential(1.0 / rate, size=requests) if rate else np.zeros(requests)
+                start = time.perf_counter()
+                due = start
+                for k in range(requests):
+                    due += gaps[k]
+                    d = due - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[k] = srv.submit(pool[order[k]])
+                    ready.release()
+
+            t_start = time.perf_counter()
+            th = threading.Thread(target=produce)
+            th.start()
+            for k in range(requests):
+                ready.acquire()
+                lam, _, l = srv.wait(tickets[k], want_side=False)
+                ok = ok and lam == alone[order[k]]
+                lat.append(l["total_ms"])
+            t_end = time.perf_counter()
+            th.join()
+        lat = np.asarray(lat)
+        span = t_end - t_start
+        return {"requests": requests, "span_s": round(span, 3),
+                "edges_per_s": float(sum(pool[i].m for i in order) / span),
+                "requests_per_s": round(requests / span, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "same_as_alone": bool(ok)}
+
+    cap = run(None)
+    log(f"served closed loop: {cap}")
+    # the same requests as a host loop of single-graph solves, each uploaded
+    # from host memory like a served request
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(requests):
+        g = pool[order[k]]
+        rp, col, w = mc.to_device(g, "cuda:0")
+        mc.mincut(rp, col, w)
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    looped = {"span_s": round(loop_s, 3), "edges_per_s": float(sum(pool[i].m for i in order) / loop_s)}
+    log(f"looped single solves: {looped}")
+    out = {"pool": pool_size, "lanes": lanes, "mean_m": round(mean_m), "closed_loop": cap,
+           "looped": looped, "speedup_closed_loop": round(cap["edges_per_s"] / looped["edges_per_s"], 2)}
+    for frac in (0.3, 0.7):
+        r = run(frac * cap["requests_per_s"])
+        r["rate_frac"] = frac
+        log(f"served at {frac} of capacity: {r}")
+        out[f"at_{frac}"] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +192,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--workload", choices=["chung_lu", "batched"], default="chung_lu")
+    ap.add_argument("--workload", choices=["chung_lu", "batched", "served"], default="chung_lu")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--pool", type=int, default=32)
+    ap.add_argument("--lanes", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
@@ -127,6 +219,15 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         log(f"copied {x.numel() * 4} bytes three times")
+        return
+    if args.workload == "served":
+        sv = served_form(args.requests, args.pool, args.lanes)
+        out = {"metric": "served exact min-cut edges/s at 0.7 of capacity, p50/p99 latency, 1 GPU",
+               "value": sv["at_0.7"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+               "steps": args.requests, "warmup": 8, "ms_per_step": sv["at_0.7"]["p50_ms"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+               "data": "synthetic", "config": {"workload": "Poisson stream of Chung-Lu requests", **sv}}
+        print(json.dumps(out), flush=True)
         return
     if args.workload == "batched":
         b = batched_form(args.steps, args.warmup)
@@ -208,6 +309,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = batched_form(max(1, min(args.steps, 3)), 1)
+    served = None
+    if not args.no_served:
+        served = served_form(args.requests, args.pool, args.lanes)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -222,7 +326,7 @@ def main():
            "config": {"workload": f"chung_lu n=2^{args.n_log2} exp2.5 avgdeg32 unit-weight "
                                   f"8-core LCC", "n": g.n, "m": g.m,
                       "rounds": st["rounds"], "verified": verified},
-           "roofline": roofline, "cpu_baseline": cpu, "batched": batched}
+           "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "served": served}
     print(json.dumps(out), flush=True)
 
 

@@ -206,15 +206,18 @@ const char* mc_strerror(int code);
 typedef struct mc_server mc_server;
 
 typedef struct mc_server_cfg {
-  int32_t lanes;           /* concurrent solves; default 2 */
+  int32_t lanes;           /* concurrent solves; default 4 */
   int32_t max_batch;       /* graphs per packed solve; default 4096 */
   int64_t small_max_nnz;   /* larger requests run alone; default 2^22 */
+  int64_t max_batch_nnz;   /* entries per packed solve (a run of small requests
+                              stops before passing it); default 2^24 */
   int64_t mem_budget;      /* device bytes of the requests in flight (input,
                               side and solver workspace share); 0 = half of
                               the free memory at creation */
   int32_t queue_cap;       /* waiting requests before MC_EBUSY; default 65536 */
   int32_t device;          /* HIP device; -1 = the current one */
-  int32_t validate;        /* 1 (default): check every request on submit */
+  int32_t validate;        /* 1 (default): check every request while its lane
+                              packs it (row_ptr, columns, weights, total) */
   int32_t reserved;
   mc_options opt;          /* solver options of every solve */
 } mc_server_cfg;
@@ -244,9 +247,11 @@ void mc_server_cfg_default(mc_server_cfg* cfg);
  * configuration, MC_EHIP if the device is unusable. */
 int mc_server_create(const mc_server_cfg* cfg, mc_server** out);
 
-/* Queue one request; *ticket identifies it.  MC_ENOCUT (n < 2), MC_EINVAL /
- * MC_EOVERFLOW (validation), MC_ENOMEM (footprint above the budget),
- * MC_EBUSY (queue full), MC_ESTATE (server stopping). */
+/* Queue one request; *ticket identifies it.  MC_ENOCUT (n < 2), MC_EINVAL
+ * (null array, nnz < 0), MC_ENOMEM (footprint above the budget), MC_EBUSY
+ * (queue full), MC_ESTATE (server stopping).  A malformed graph is found
+ * while it is packed: its mc_server_wait returns MC_EINVAL or MC_EOVERFLOW
+ * and the requests batched with it are unaffected. */
 int mc_server_submit(mc_server* srv, const mc_request* req, uint64_t* ticket);
 
 /* Block until the request is done; lambda (HOST), side (HOST uint8[n] or

@@ -151,7 +151,8 @@ def _load():
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("small_max_nnz", ctypes.c_int64), ("mem_budget", ctypes.c_int64),
+                ("small_max_nnz", ctypes.c_int64), ("max_batch_nnz", ctypes.c_int64),
+                ("mem_budget", ctypes.c_int64),
                 ("queue_cap", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("reserved", ctypes.c_int32), ("opt", Options)]
 

@@ -719,6 +719,9 @@ struct Solver {
         {
           TimedScope t("vc_pr", (double)nnz * 20 + (double)n * 16);
           hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
+          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, cdeg, gid, ws.lhat, V.act,
+                             ws.parent, ws.ucount);
+          hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, src, col, w, cdeg, gid, ws.lhat, V.act,
                              ws.parent, ws.ucount, ws.ctl);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -892,7 +895,10 @@ struct Solver {
       fill<int32_t>(ws.claim, -1, n, s);
       if (opt.use_pr) {
         // src, col, w per entry; both degrees for the half with u < v
-        TimedScope t("pr", (double)nnz * 12 + (double)nnz * 8);
+        TimedScope t("pr", (double)nnz * 20 + (double)n * 32);
+        hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, ws.cdeg, gid, ws.lhat,
+                           ws.active, ws.parent, ws.ucount);
+        hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
                            ws.lhat, ws.active, ws.parent, ws.ucount, ws.ctl);
       }

@@ -355,33 +355,65 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_plan_split(int32_t G, GraphSta
 }
 
 // ------------------------------------------------------- Padberg-Rinaldi
-// For e = (u, v), u < v: PR1 w >= lambda-hat, or PR2 2w > c(u) or
-// 2w > c(v) (strict).  Both keep every minimum cut when lambda-hat <= the
-// minimum degree (sections "Related Work" and "Inexact Shared-Memory
-// Minimum Cuts" name the tests; the conditions are restated here).
+// For e = (u, v): PR1 w >= lambda-hat, or PR2 2w > c(u) or 2w > c(v)
+// (strict).  Both keep every minimum cut when lambda-hat <= the minimum
+// degree (sections "Related Work" and "Inexact Shared-Memory Minimum Cuts"
+// name the tests; the conditions are restated here).
+//
+// With a small bound almost every edge passes PR1 and the unions pile onto
+// one giant set; done edge by edge they all contend for its root.  So a
+// vertex pass first unites each vertex with the first PR_SAMPLE entries of
+// its row that pass, the forest is flattened, and the edge pass then skips
+// every passing edge whose ends already share a parent (the union is
+// idempotent, so the filter only saves work).  Per graph, ucount is set to
+// 1 once any edge passed.
+constexpr int PR_SAMPLE = 2;
+
+__device__ __forceinline__ bool pr_passes(int64_t c, int64_t lam, int64_t cu, int64_t cv) {
+  return c >= lam || 2 * c > cu || 2 * c > cv;
+}
+
+__device__ __forceinline__ void pr_flag(int32_t* ucount, int32_t g, int32_t& last) {
+  if (g != last) {
+    if (ld_relaxed(ucount + g) == 0) st_relaxed(ucount + g, 1);
+    last = g;
+  }
+}
+
+__global__ void k_pr_sample(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
+                            const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
+                            const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount) {
+  int32_t last = -1;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    const int32_t g = gid[v];
+    if (!active[g]) continue;
+    const int64_t lam = lhat[g], cv = cdeg[v];
+    const int64_t e0 = rp[v], e1 = min(rp[v + 1], e0 + PR_SAMPLE);
+    for (int64_t e = e0; e < e1; ++e) {
+      const int32_t u = col[e];
+      if (u != (int32_t)v && pr_passes(w[e], lam, cv, cdeg[u])) {
+        uf_union(parent, (int32_t)v, u);
+        pr_flag(ucount, g, last);
+      }
+    }
+  }
+}
+
 __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t* __restrict__ col,
                      const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
                      const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
                      const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount, Ctl* ctl) {
   int64_t local = 0;
-  for (int64_t e = gtid(); e - lane_id() < nnz; e += gstride()) {  // wave-uniform bound
-    bool hit = false;
-    int32_t g = -1;
-    if (e < nnz) {
-      const int32_t u = src[e], v = col[e];
-      if (u < v) {
-        g = gid[u];
-        if (active[g]) {
-          const int64_t c = w[e];
-          if (c >= lhat[g] || 2 * c > cdeg[u] || 2 * c > cdeg[v]) {
-            uf_union(parent, u, v);
-            hit = true;
-            ++local;
-          }
-        }
-      }
-    }
-    wave_add_by_key(ucount, g, 1, hit);
+  int32_t last = -1;
+  for (int64_t e = gtid(); e < nnz; e += gstride()) {
+    const int32_t u = src[e], v = col[e];
+    if (u >= v) continue;
+    const int32_t g = gid[u];
+    if (!active[g] || !pr_passes(w[e], lhat[g], cdeg[u], cdeg[v])) continue;
+    ++local;
+    pr_flag(ucount, g, last);
+    if (ld_relaxed(parent + u) != ld_relaxed(parent + v)) uf_union(parent, u, v);
   }
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }

@@ -4,7 +4,8 @@
 // with its own HIP stream and solver workspace.  A free lane admits requests
 // from the head of the queue while their device footprint fits the memory
 // budget: a large request alone, or a run of small ones coalesced into one
-// packed solve (the batched form).  Lanes run at the same time, so requests
+// packed solve (the batched form) of bounded size.  Lanes run at the same
+// time, so one lane packs on the host while another solves, and requests
 // that arrive while others are on the GPU are admitted as soon as a lane
 // and memory are free, and their kernels overlap on the device with the
 // running solves.  Every graph's contraction state stays on the device for
@@ -32,6 +33,7 @@ struct ServerRequest {
   int64_t bytes = 0;  // device footprint while in flight
   // result
   int rc = 1;  // 1 = pending
+  int rc_pack = MC_OK;
   int64_t lambda = -1;
   std::vector<uint8_t> side;
   std::chrono::steady_clock::time_point t_submit, t_start, t_done;
@@ -79,20 +81,31 @@ struct LaneBuffers {
   }
 };
 
-// Host-side validation of a request (the packed solve would reject the whole
-// batch for one malformed graph): row_ptr monotone from 0 to nnz, columns in
-// range, weights >= 1, total weight within 2 (2^31 - 1).
-inline int validate_request(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* col, const int32_t* w) {
-  if (n < 2) return MC_ENOCUT;
-  if (nnz < 0 || rp[0] != 0 || rp[n] != nnz) return MC_EINVAL;
-  for (int32_t v = 0; v < n; ++v)
-    if (rp[v + 1] < rp[v]) return MC_EINVAL;
-  int64_t total = 0;
-  for (int64_t e = 0; e < nnz; ++e) {
-    if (col[e] < 0 || col[e] >= n || w[e] < 1) return MC_EINVAL;
-    total += w[e];
+// Copy one request into the packed staging buffers at vertex offset v0 and
+// entry offset e0 (columns shifted by v0, row offsets by e0), checking it on
+// the way (the packed solve would reject the whole batch for one malformed
+// graph): row_ptr monotone from 0 to nnz, columns in range, weights >= 1,
+// total weight within 2 (2^31 - 1).  Returns MC_OK, or the error with the
+// staging left to be overwritten by the next request.
+inline int pack_request(const ServerRequest& r, int64_t v0, int64_t e0, bool check, int64_t* h_rp, int32_t* h_col,
+                        int32_t* h_w) {
+  const int32_t n = r.n;
+  if (check && (r.rp[0] != 0 || r.rp[n] != r.nnz)) return MC_EINVAL;
+  for (int32_t v = 0; v < n; ++v) {
+    if (check && r.rp[v + 1] < r.rp[v]) return MC_EINVAL;
+    h_rp[v0 + v] = r.rp[v] + e0;
   }
-  if (total > 2ll * 2147483647ll) return MC_EOVERFLOW;
+  int64_t total = 0;
+  bool bad = false;
+  for (int64_t e = 0; e < r.nnz; ++e) {
+    const int32_t c = r.col[e], x = r.w[e];
+    bad |= (c < 0) | (c >= n) | (x < 1);
+    total += x;
+    h_col[e0 + e] = c + (int32_t)v0;
+    h_w[e0 + e] = x;
+  }
+  if (check && bad) return MC_EINVAL;
+  if (check && total > 2ll * 2147483647ll) return MC_EOVERFLOW;
   return MC_OK;
 }
 
@@ -121,7 +134,7 @@ struct Server {
     hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     Workspace ws;
     LaneBuffers buf;
-    std::vector<ServerRequest*> batch;
+    std::vector<ServerRequest*> batch, kept;
     std::vector<int64_t> voff, lambdas;
     while (true) {
       batch.clear();
@@ -134,9 +147,13 @@ struct Server {
         batch.push_back(r0);
         in_flight += r0->bytes;
         if (r0->nnz <= cfg.small_max_nnz) {
+          int64_t entries = r0->nnz;
           while (!queue.empty() && (int32_t)batch.size() < cfg.max_batch) {
             ServerRequest* r = queue.front();
-            if (r->nnz > cfg.small_max_nnz || in_flight + r->bytes > budget) break;
+            if (r->nnz > cfg.small_max_nnz || in_flight + r->bytes > budget ||
+                entries + r->nnz > cfg.max_batch_nnz)
+              break;
+            entries += r->nnz;
             queue.pop_front();
             batch.push_back(r);
             in_flight += r->bytes;
@@ -144,26 +161,30 @@ struct Server {
         }
       }
       const auto t_start = std::chrono::steady_clock::now();
-      // pack: vertex and entry offsets, columns shifted into the packed range
-      const int32_t G = (int32_t)batch.size();
-      voff.assign(G + 1, 0);
-      int64_t E = 0;
-      for (int32_t g = 0; g < G; ++g) {
-        voff[g + 1] = voff[g] + batch[g]->n;
-        E += batch[g]->nnz;
+      // pack and check in one pass; a malformed request is left out and
+      // completes with its error
+      int64_t N = 0, E = 0;
+      for (const ServerRequest* r : batch) {
+        N += r->n;
+        E += r->nnz;
       }
-      const int64_t N = voff[G];
       int rc = (N >= (1ll << 30) || E >= (int64_t)UINT32_MAX) ? MC_EINVAL : buf.ensure(N, E);
+      voff.assign(1, 0);
+      kept.clear();
       if (rc == MC_OK) {
         int64_t e0 = 0;
-        for (int32_t g = 0; g < G; ++g) {
-          const ServerRequest* r = batch[g];
-          const int32_t v0 = (int32_t)voff[g];
-          for (int32_t v = 0; v < r->n; ++v) buf.h_rp[v0 + v] = r->rp[v] + e0;
-          for (int64_t e = 0; e < r->nnz; ++e) buf.h_col[e0 + e] = r->col[e] + v0;
-          std::memcpy(buf.h_w + e0, r->w, (size_t)r->nnz * 4);
+        for (ServerRequest* r : batch) {
+          r->rc_pack = pack_request(*r, voff.back(), e0, cfg.validate != 0, buf.h_rp, buf.h_col, buf.h_w);
+          if (r->rc_pack != MC_OK) continue;
+          kept.push_back(r);
+          voff.push_back(voff.back() + r->n);
           e0 += r->nnz;
         }
+        N = voff.back();
+        E = e0;
+      }
+      const int32_t G = (int32_t)kept.size();
+      if (rc == MC_OK && G > 0) {
         buf.h_rp[N] = E;
         hipMemcpyAsync(buf.rp, buf.h_rp, (N + 1) * 8, hipMemcpyHostToDevice, s);
         hipMemcpyAsync(buf.col, buf.h_col, E * 4, hipMemcpyHostToDevice, s);
@@ -181,12 +202,14 @@ struct Server {
       {
         std::lock_guard<std::mutex> lk(m);
         for (int32_t g = 0; g < G; ++g) {
-          ServerRequest* r = batch[g];
-          r->rc = rc;
+          ServerRequest* r = kept[g];
           if (rc == MC_OK) {
             r->lambda = lambdas[g];
             r->side.assign(buf.h_side + voff[g], buf.h_side + voff[g + 1]);
           }
+        }
+        for (ServerRequest* r : batch) {
+          r->rc = r->rc_pack != MC_OK ? r->rc_pack : rc;
           r->t_start = t_start;
           r->t_done = t_done;
           r->batch_graphs = G;
@@ -210,9 +233,10 @@ extern "C" {
 void mc_server_cfg_default(mc_server_cfg* c) {
   if (!c) return;
   std::memset(c, 0, sizeof(*c));
-  c->lanes = 2;
+  c->lanes = 4;
   c->max_batch = 4096;
   c->small_max_nnz = 1ll << 22;
+  c->max_batch_nnz = 1ll << 24;
   c->mem_budget = 0;
   c->queue_cap = 1 << 16;
   c->device = -1;
@@ -227,7 +251,8 @@ int mc_server_create(const mc_server_cfg* cfg, mc_server** out) {
   mc_server_cfg_default(&S->cfg);
   if (cfg) S->cfg = *cfg;
   mc_server_cfg& c = S->cfg;
-  if (c.lanes < 1 || c.lanes > 64 || c.max_batch < 1 || c.small_max_nnz < 0 || c.queue_cap < 1)
+  if (c.lanes < 1 || c.lanes > 64 || c.max_batch < 1 || c.small_max_nnz < 0 || c.max_batch_nnz < 1 ||
+      c.queue_cap < 1)
     return MC_EINVAL;
   if (c.device < 0) {
     if (hipGetDevice(&S->device) != hipSuccess) return MC_EHIP;
@@ -251,10 +276,6 @@ int mc_server_submit(mc_server* srv, const mc_request* req, uint64_t* ticket) {
   mc::Server* S = reinterpret_cast<mc::Server*>(srv);
   if (req->n < 2) return MC_ENOCUT;
   if (req->nnz < 0) return MC_EINVAL;
-  if (S->cfg.validate) {
-    const int rc = mc::validate_request(req->n, req->nnz, req->row_ptr, req->col, req->w);
-    if (rc) return rc;
-  }
   auto r = std::make_unique<mc::ServerRequest>();
   r->n = req->n;
   r->nnz = req->nnz;

@@ -140,26 +140,31 @@ def test_memory_budget_admits_one_at_a_time(reqs):
 
 
 def test_invalid_requests_are_refused():
+    # malformed graphs are found while their lane packs them: their wait
+    # reports the error, the requests batched with them are unaffected
     import paper_1808_05458_amd as mc
     with mc.Server(lanes=1) as srv:
         bad = gg.from_edges(3, [(0, 1), (1, 2)], [1, 1])
         bad.col = bad.col.copy()
         bad.col[0] = 7  # out of range
-        with pytest.raises(mc.MincutError) as e:
-            srv.submit(bad)
-        assert e.value.code == mc.MC_EINVAL
         zero = gg.from_edges(3, [(0, 1), (1, 2)], [1, 0])
-        with pytest.raises(mc.MincutError) as e:
-            srv.submit(zero)
-        assert e.value.code == mc.MC_EINVAL
+        heavy = gg.from_edges(2, [(0, 1), (0, 1)], [2**31 - 1, 2**31 - 1])  # total weight too large
+        good = [gg.complete(5), gg.two_cliques(6, 2), gg.batch_graph(9)]
+        sent = (good[0], bad, good[1], zero, heavy, good[2])
+        tickets = [srv.submit(g) for g in sent]
+        expect = {1: mc.MC_EINVAL, 3: mc.MC_EINVAL, 4: mc.MC_EOVERFLOW}
+        for k, (g, t) in enumerate(zip(sent, tickets)):
+            if k in expect:
+                with pytest.raises(mc.MincutError) as e:
+                    srv.wait(t)
+                assert e.value.code == expect[k]
+            else:
+                lam, side, lat = srv.wait(t)
+                _check(g, oracle.noi(g, 1)[0], lam, side)
         one = gg.from_edges(1, np.zeros((0, 2), np.int64), [])
         with pytest.raises(mc.MincutError) as e:
             srv.submit(one)
         assert e.value.code == mc.MC_ENOCUT
-        # the server still works after refusals; an unknown ticket is refused
-        t = srv.submit(gg.complete(5))
-        lam, side, lat = srv.wait(t)
-        assert lam == 4
         with pytest.raises(mc.MincutError) as e:
             srv._n[12345] = 3
             srv.wait(12345)
