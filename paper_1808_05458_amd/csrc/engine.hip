@@ -42,6 +42,7 @@ constexpr int WHOLE_CAP_S = 2048;
 constexpr int WHOLE_CAP_L = 8192;
 constexpr int SMALL_CAP_S = 2048;  // LDS-resident sweeps of whole small graphs
 constexpr int SMALL_CAP_L = 8192;
+constexpr int64_t SWEEP_HANDOFF_ENTRIES = 1 << 16;  // batches with longer rows run grid-wide
 
 // ------------------------------------------------------------------ timing
 struct TimingClass {
@@ -453,6 +454,7 @@ struct Solver {
     A.nb = (int32_t)(((lam - 1) >> A.shift) + 1);
     A.nwords = (A.nb + 63) / 64;
     A.big = opt.sweep_handoff > 0 ? opt.sweep_handoff : 512;
+    A.big_entries = SWEEP_HANDOFF_ENTRIES;
     uint64_t h = (opt.seed ? opt.seed : 0x5EEDull) * 0x9E3779B97F4A7C15ull +
                  (uint64_t)round * 0xBF58476D1CE4E5B9ull + (uint64_t)g;
     h ^= h >> 29;

@@ -73,6 +73,7 @@ struct SweepArgs {
   int32_t nwords;    // bitmap words in use
   int32_t nb;        // buckets in use
   int32_t big;       // batches above this size go grid-wide
+  int64_t big_entries;  // ... and so do batches whose rows hold more entries
 };
 
 // The queue and FIFO bookkeeping, addressed through generic pointers: the
@@ -367,11 +368,15 @@ __device__ __forceinline__ int64_t wave_relax_rows(const SweepArgs& A, const Swe
 // with short rows and small batches by itself.  Wide steps (a long row, a
 // larger batch) are shared with the other waves, which wait at a barrier for
 // the next command.  Exits with SW_DONE (queue empty) or SW_BIG (a batch
-// larger than A.big is pending; cap_head..cap_tail untouched).
+// larger than A.big, or with more than A.big_entries entries in its rows, is
+// pending; cap_head..cap_tail untouched).
 enum : int32_t { CMD_EXIT_DONE = 0, CMD_BATCH = 1, CMD_EXIT_BIG = 2, CMD_SINGLE = 3 };
 
 __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
   __shared__ int32_t sh_x, sh_cmd, sh_h, sh_t, sh_stamp;
+  // a wide batch chunk: its vertices, row starts and entry offsets
+  __shared__ int32_t sh_bx[SWEEP_THREADS], sh_boff[SWEEP_THREADS + 1], sh_wtot[SWEEP_THREADS / 64];
+  __shared__ int64_t sh_bbase[SWEEP_THREADS];
   __shared__ int64_t sh_sum[SWEEP_THREADS / 64], sh_int[SWEEP_THREADS / 64];
   // queue state, resident in LDS while this workgroup runs
   __shared__ int32_t l_head[SWEEP_BUCKETS], l_cur[SWEEP_BUCKETS], l_end[SWEEP_BUCKETS];
@@ -423,7 +428,16 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
         if (t > h) {
           const int32_t size = t - h;
           if (size > A.big) { cmd = CMD_EXIT_BIG; break; }
-          if (size > FAST_BATCH) {
+          // the rows' total length decides too: a few hubs can hold more
+          // entries than one workgroup (or one wave) should relax
+          int64_t entries = 0;
+          for (int32_t i = lane; i < size; i += 64) {
+            const int32_t x = ld_relaxed(A.capq + h + i);
+            entries += A.rp[x + 1] - A.rp[x];
+          }
+          entries = wave_sum_i64(entries);
+          if (entries > A.big_entries) { cmd = CMD_EXIT_BIG; break; }
+          if (size > FAST_BATCH || entries > FAST_DEG) {
             if (lane == 0) { sh_h = h; sh_t = t; sh_stamp = stamp; step = stamp; batches += 1; }
             cmd = CMD_BATCH;
             break;
@@ -494,24 +508,66 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
         internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
       }
     } else {
+      // the batch's entries spread evenly over the workgroup (a hub row in
+      // the batch no longer holds one wave while the others wait), in chunks
+      // of SWEEP_THREADS rows
       const int32_t h = sh_h, t = sh_t;
       size = t - h;
+      // every vertex of the batch is marked before any row is relaxed (edges
+      // inside the batch are recognised by their stamp)
       for (int32_t i = h + threadIdx.x; i < t; i += SWEEP_THREADS) {
-        int32_t x = ld_relaxed(A.capq + i);
+        const int32_t x = ld_relaxed(A.capq + i);
         st_relaxed(A.st + x, 2);
         st_relaxed(A.step + x, stamp);
         sum += A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
       }
       __threadfence_block();
       __syncthreads();
-      for (int32_t i = h + wave; i < t; i += nwaves) {
-        const int32_t x = ld_relaxed(A.capq + i);
-        const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
-        for (int64_t base = e0; base < e1; base += 64) {
-          const int64_t e = base + lane;
-          const bool act = e < e1;
-          internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+      for (int32_t c0 = h; c0 < t; c0 += SWEEP_THREADS) {
+        const int32_t cn = min(SWEEP_THREADS, t - c0);
+        int32_t deg = 0;
+        if ((int32_t)threadIdx.x < cn) {
+          const int32_t x = ld_relaxed(A.capq + c0 + threadIdx.x);
+          const int64_t a = A.rp[x];
+          deg = (int32_t)(A.rp[x + 1] - a);
+          sh_bx[threadIdx.x] = x;
+          sh_bbase[threadIdx.x] = a;
         }
+        int32_t incl = deg;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int32_t v = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += v;
+        }
+        if (lane == 63) sh_wtot[wave] = incl;
+        __threadfence_block();
+        __syncthreads();
+        int32_t before = 0;
+        for (int k = 0; k < wave; ++k) before += sh_wtot[k];
+        if ((int32_t)threadIdx.x < cn) sh_boff[threadIdx.x] = before + incl - deg;
+        if ((int32_t)threadIdx.x == cn - 1) sh_boff[cn] = before + incl;
+        __threadfence_block();
+        __syncthreads();
+        const int32_t total = sh_boff[cn];
+        for (int32_t i0 = 0; i0 < total; i0 += SWEEP_THREADS) {
+          const int32_t i = i0 + (int32_t)threadIdx.x;
+          const bool act = i < total;
+          int32_t x = 0, y = 0, cw = 0;
+          if (act) {
+            int32_t lo = 0, hi = cn - 1;  // the row: last k with boff[k] <= i
+            while (lo < hi) {
+              const int32_t mid = (lo + hi + 1) >> 1;
+              if (sh_boff[mid] <= i) lo = mid;
+              else hi = mid - 1;
+            }
+            const int64_t e = sh_bbase[lo] + (i - sh_boff[lo]);
+            x = sh_bx[lo];
+            y = A.col[e];
+            cw = A.w[e];
+          }
+          internal += sweep_relax(A, q, x, y, cw, stamp, act);
+        }
+        __threadfence_block();
+        __syncthreads();  // the chunk arrays are reused
       }
     }
     sum = wave_sum_i64(sum);
