@@ -142,7 +142,7 @@ struct Workspace {
   int64_t capN = 0, capE = 0, capG = 0;
   std::vector<void*> allocs;
   // vertex arrays
-  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *fb_st, *capq, *capx, *sw_seg, *newid,
+  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *capq, *capx, *sw_seg, *newid,
       *map, *ogid;
   SweepCtl* sweep;
   SweepCtl* sweep_host = nullptr;
@@ -241,7 +241,6 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.newid, (N + 1) * 4);
   ALLOC(ws.map, (N + 1) * 4);
   ALLOC(ws.ogid, (N + 1) * 4);
-  ALLOC(ws.fb_st, (N + 1) * 4);
   ALLOC(ws.capq, (N + 1) * 4);
   ALLOC(ws.capx, (N + 1) * 4);
   ALLOC(ws.sw_seg, (N + 1) * 4);
@@ -447,7 +446,7 @@ struct Solver {
                   const int32_t* col, const int32_t* w, int64_t nnz, const GraphState& S,
                   mc_stats* st) {
     if (lam <= 0 || ng < 2) return MC_OK;
-    SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_st, ws.fb_step, ws.capq, ws.capx,
+    SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_step, ws.capq, ws.capx,
                 (int2*)ws.keys_alt, ws.capE + 64, ws.sw_seg, ws.sweep, v0, ng, lam, 0, 1, 1, 0};
     const int lb = bitlen((uint64_t)(lam - 1));
     A.shift = lb > 12 ? lb - 12 : 0;

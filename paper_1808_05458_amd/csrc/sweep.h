@@ -59,8 +59,8 @@ struct SweepArgs {
   const int64_t* cdeg;
   int32_t* parent;
   int32_t* r;        // per vertex
-  int32_t* st;       // 0 unseen, 1 frontier, 2 visited
-  int32_t* step;     // visit stamp (batch number), 0 = not visited
+  int32_t* step;     // visit stamp (batch number), 0 = not visited; a frontier
+                     // vertex is an unvisited one with r > 0 (or the start)
   int32_t* capq;     // capped FIFO (each vertex enters at most once)
   int32_t* capx;     // the vertex whose edge made capq[i] cross (united later)
   int2* pool;        // bucket entries (vertex, next)
@@ -115,16 +115,29 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
   bool cross = false, push = false;
   int64_t nw = 0;
   if (act && y == x) act = false;
-  if (act) {
-    int32_t s = ld_relaxed(A.st + y);
-    if (s == 2) {
-      if (ld_relaxed(A.step + y) == stamp) internal = c;
+  if (act && PUSH) {
+    // the sequential kernel is latency-bound: the visit stamp and the add
+    // are independent, so both are in flight at once.  A visited vertex's r
+    // is never read again (alpha takes r(x) when x is marked, before any row
+    // of its batch is relaxed), so adding to it is harmless
+    const int32_t vs = ld_relaxed(A.step + y);
+    const int32_t old = atomicAdd(A.r + y, c);
+    if (vs != 0) {
+      if (vs == stamp) internal = c;
     } else {
-      int32_t old = atomicAdd(A.r + y, c);
       nw = (int64_t)old + c;
-      if (s == 0) st_relaxed(A.st + y, 1);
       cross = old < A.lam && A.lam <= nw;
-      push = PUSH && nw < A.lam;
+      push = nw < A.lam;
+    }
+  } else if (act) {
+    // grid-wide batches are bandwidth-bound: no add for visited vertices
+    const int32_t vs = ld_relaxed(A.step + y);
+    if (vs != 0) {
+      if (vs == stamp) internal = c;
+    } else {
+      const int32_t old = atomicAdd(A.r + y, c);
+      nw = (int64_t)old + c;
+      cross = old < A.lam && A.lam <= nw;
     }
   }
   // crossings: unite, and append y to the capped FIFO (through a per-wave
@@ -191,7 +204,6 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
 __global__ void k_sweep_init(SweepArgs A) {
   for (int64_t i = gtid(); i < A.ng; i += gstride()) {
     A.r[A.v0 + i] = 0;
-    A.st[A.v0 + i] = 0;
     A.step[A.v0 + i] = 0;
   }
   for (int64_t i = gtid(); i < SWEEP_BUCKETS; i += gstride()) {
@@ -218,7 +230,6 @@ __global__ void k_sweep_init(SweepArgs A) {
 
 __global__ void k_sweep_seed(SweepArgs A, int32_t start) {
   if (gtid() == 0) {
-    A.st[start] = 1;
     A.pool[0] = make_int2(start, -1);  // (vertex, next)
     A.ctl->head[0] = 0;
     A.ctl->bitmap[0] = 1ull;
@@ -236,7 +247,7 @@ __device__ __forceinline__ void sweep_close_batch(SweepCtl* c, int32_t ng, int64
 }
 
 __device__ __forceinline__ bool live_in_bucket(const SweepArgs& A, int32_t v, int32_t b, int32_t& key) {
-  if (v < 0 || ld_relaxed(A.st + v) != 1) return false;
+  if (v < 0 || ld_relaxed(A.step + v) != 0) return false;  // visited
   key = ld_relaxed(A.r + v);
   return (int64_t)key < A.lam && (key >> A.shift) == b;
 }
@@ -446,7 +457,6 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
           int64_t sum = 0;
           if (lane < size) {
             xs = ld_relaxed(A.capq + h + lane);
-            st_relaxed(A.st + xs, 2);
             st_relaxed(A.step + xs, stamp);
             sum = A.cdeg[xs] - 2 * (int64_t)ld_relaxed(A.r + xs);
           }
@@ -469,7 +479,6 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
           const int64_t deg = A.rp[x + 1] - A.rp[x];
           int64_t sum = 0;
           if (lane == 0) {
-            st_relaxed(A.st + x, 2);
             st_relaxed(A.step + x, stamp);
             sum = A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
           }
@@ -517,7 +526,6 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
       // inside the batch are recognised by their stamp)
       for (int32_t i = h + threadIdx.x; i < t; i += SWEEP_THREADS) {
         const int32_t x = ld_relaxed(A.capq + i);
-        st_relaxed(A.st + x, 2);
         st_relaxed(A.step + x, stamp);
         sum += A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
       }
@@ -625,7 +633,6 @@ __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
   for (int64_t i = h + gtid(); i - lane_id() < t; i += gstride()) {  // wave-uniform bound
     if (i < t) {
       int32_t x = A.capq[i];
-      A.st[x] = 2;
       A.step[x] = stamp;
       sum += A.cdeg[x] - 2 * (int64_t)A.r[x];
       deg += A.rp[x + 1] - A.rp[x];
@@ -710,7 +717,8 @@ __global__ void __launch_bounds__(256) k_sweep_rb_count(SweepArgs A) {
   __syncthreads();
   for (int64_t i = gtid(); i < A.ng; i += gstride()) {
     const int32_t v = A.v0 + (int32_t)i;
-    if (A.st[v] == 1 && (int64_t)A.r[v] < A.lam) atomicAdd(&h[A.r[v] >> A.shift], 1);
+    const int32_t rv = A.r[v];
+    if (A.step[v] == 0 && rv > 0 && (int64_t)rv < A.lam) atomicAdd(&h[rv >> A.shift], 1);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < A.nb; i += 256)
@@ -773,8 +781,9 @@ __global__ void __launch_bounds__(256) k_sweep_rb_fill(SweepArgs A) {
     rk[q] = 0;
     if (i < A.ng) {
       const int32_t v = A.v0 + (int32_t)i;
-      if (A.st[v] == 1 && (int64_t)A.r[v] < A.lam) {
-        bk[q] = A.r[v] >> A.shift;
+      const int32_t rv = A.r[v];
+      if (A.step[v] == 0 && rv > 0 && (int64_t)rv < A.lam) {
+        bk[q] = rv >> A.shift;
         rk[q] = atomicAdd(&h[bk[q]], 1);
       }
     }
