@@ -79,6 +79,8 @@ struct SweepArgs {
 // The queue and FIFO bookkeeping, addressed through generic pointers: the
 // persistent workgroup works on LDS copies, the grid-wide kernels on the
 // global SweepCtl.
+constexpr int SWEEP_RING = 1024;  // newest capped-FIFO entries mirrored in LDS
+
 struct SweepQ {
   int32_t* cap_head;
   int32_t* cap_tail;
@@ -87,10 +89,11 @@ struct SweepQ {
   int32_t* head;
   int32_t* seg_cur;
   int32_t* seg_end;
+  int32_t* ring;  // LDS mirror of capq[i] at i % SWEEP_RING (persistent kernel only)
 };
 
 __device__ __forceinline__ SweepQ global_q(SweepCtl* c) {
-  return SweepQ{&c->cap_head, &c->cap_tail, &c->pool_next, c->bitmap, c->head, c->seg_cur, c->seg_end};
+  return SweepQ{&c->cap_head, &c->cap_tail, &c->pool_next, c->bitmap, c->head, c->seg_cur, c->seg_end, nullptr};
 }
 
 __device__ __forceinline__ int2 pool_at(const SweepArgs& A, int32_t idx) {
@@ -159,9 +162,10 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
     if (lane == leader) base = atomicAdd(q.cap_tail, popc64(cm));
     base = shfl(base, leader);
     if (cross) {
-      const int32_t q = base + popc64(cm & lanemask_lt());
-      A.capq[q] = y;
-      A.capx[q] = x;
+      const int32_t at = base + popc64(cm & lanemask_lt());
+      A.capq[at] = y;
+      A.capx[at] = x;
+      if (q.ring) q.ring[at & (SWEEP_RING - 1)] = y;
     }
   }
   // pushes below the cap: one pool reservation per wave, then one list
@@ -357,15 +361,15 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A, const SweepQ& q) {
 constexpr int FAST_BATCH = 32;     // batches up to this size run on wave 0 alone
 constexpr int64_t FAST_DEG = 2048;  // single pops with rows up to this run on wave 0 alone
 
-// Relax the rows of `cnt` batch vertices held by lanes 0..cnt-1 of `xs` with
-// one wave; returns the batch-internal weight of this wave's lanes.
-__device__ __forceinline__ int64_t wave_relax_rows(const SweepArgs& A, const SweepQ& q, int32_t xs, int cnt,
-                                                   int32_t stamp) {
+// Relax the rows [ra, rb) of `cnt` batch vertices held by lanes 0..cnt-1 of
+// `xs` with one wave; returns the batch-internal weight of this wave's lanes.
+__device__ __forceinline__ int64_t wave_relax_known(const SweepArgs& A, const SweepQ& q, int32_t xs, int64_t ra,
+                                                    int64_t rb, int cnt, int32_t stamp) {
   const int lane = lane_id();
   int64_t internal = 0;
   for (int j = 0; j < cnt; ++j) {
     const int32_t x = shfl(xs, j);
-    const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
+    const int64_t e0 = shfl(ra, j), e1 = shfl(rb, j);
     for (int64_t base = e0; base < e1; base += 64) {
       const int64_t e = base + lane;
       const bool act = e < e1;
@@ -394,6 +398,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
   __shared__ uint64_t l_bitmap[SWEEP_BUCKETS / 64];
   __shared__ int32_t l_cap_head, l_cap_tail;
   __shared__ int64_t l_pool_next;
+  __shared__ int32_t l_ring[SWEEP_RING];
   SweepCtl* c = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int nwaves = SWEEP_THREADS / 64;
@@ -419,7 +424,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
     batches = c->batches;
   }
   __syncthreads();
-  const SweepQ q{&l_cap_head, &l_cap_tail, &l_pool_next, l_bitmap, l_head, l_cur, l_end};
+  const SweepQ q{&l_cap_head, &l_cap_tail, &l_pool_next, l_bitmap, l_head, l_cur, l_end, l_ring};
+  // FIFO entries appended before this launch are not in the ring
+  const int32_t ring_lo = ld_relaxed(&l_cap_tail);
+  auto fifo_at = [&](int32_t i, int32_t tail) -> int32_t {
+    return (i >= ring_lo && i >= tail - SWEEP_RING) ? l_ring[i & (SWEEP_RING - 1)] : ld_relaxed(A.capq + i);
+  };
   auto close = [&](int64_t sum, int64_t internal, int32_t size, int32_t stamp) {
     alpha += sum - internal;
     visited += size;
@@ -440,11 +450,15 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
           const int32_t size = t - h;
           if (size > A.big) { cmd = CMD_EXIT_BIG; break; }
           // the rows' total length decides too: a few hubs can hold more
-          // entries than one workgroup (or one wave) should relax
-          int64_t entries = 0;
+          // entries than one workgroup (or one wave) should relax.  The
+          // first 64 vertices keep their row bounds for the relax.
+          int64_t entries = 0, ra = 0, rb = 0;
+          int32_t xs = -1;
           for (int32_t i = lane; i < size; i += 64) {
-            const int32_t x = ld_relaxed(A.capq + h + i);
-            entries += A.rp[x + 1] - A.rp[x];
+            const int32_t x = fifo_at(h + i, t);
+            const int64_t a = A.rp[x], b = A.rp[x + 1];
+            entries += b - a;
+            if (i == lane) { xs = x; ra = a; rb = b; }
           }
           entries = wave_sum_i64(entries);
           if (entries > A.big_entries) { cmd = CMD_EXIT_BIG; break; }
@@ -453,17 +467,16 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
             cmd = CMD_BATCH;
             break;
           }
-          int32_t xs = -1;
           int64_t sum = 0;
           if (lane < size) {
-            xs = ld_relaxed(A.capq + h + lane);
             st_relaxed(A.step + xs, stamp);
             sum = A.cdeg[xs] - 2 * (int64_t)ld_relaxed(A.r + xs);
           }
-          // the marks must be visible before the rows are relaxed (edges
-          // inside the batch are recognised by their stamp)
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          int64_t internal = wave_relax_rows(A, q, xs, size, stamp);
+          // with more than one vertex the marks must be visible before the
+          // rows are relaxed (edges inside the batch are recognised by their
+          // stamp); a lone vertex has no such edge (self-loops are skipped)
+          if (size > 1) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          int64_t internal = wave_relax_known(A, q, xs, ra, rb, size, stamp);
           sum = wave_sum_i64(sum);
           internal = wave_sum_i64(internal);
           if (lane == 0) {
@@ -476,7 +489,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
         } else {
           const int32_t x = sweep_pop_wave0(A, q);
           if (x < 0) { cmd = CMD_EXIT_DONE; break; }
-          const int64_t deg = A.rp[x + 1] - A.rp[x];
+          const int64_t ra = A.rp[x], rb = A.rp[x + 1];
+          const int64_t deg = rb - ra;
           int64_t sum = 0;
           if (lane == 0) {
             st_relaxed(A.step + x, stamp);
@@ -488,7 +502,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
             break;
           }
           // a single vertex has no edge inside its batch (self-loops skipped)
-          int64_t internal = wave_relax_rows(A, q, lane == 0 ? x : -1, 1, stamp);
+          int64_t internal = wave_relax_known(A, q, x, ra, rb, 1, stamp);
           internal = wave_sum_i64(internal);
           if (lane == 0) {
             step = stamp;
