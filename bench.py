@@ -95,6 +95,32 @@ def batched_form(steps, warmup):
             "verified": {"lambdas_equal_oracle": packed_ok and loop_ok, "side_weights_equal": sides_ok}}
 
 
+def rmat_form(steps):
+    """R-MAT scale 24 (2^28 draws, (0.57, 0.19, 0.19, 0.05), multiplicity
+    weights), 10-core, largest component, resident in HBM: exact solves."""
+    import torch
+    import graphgen as gg
+    import paper_1808_05458_amd as mc
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json"))).get("rmat_24_10core")
+    t0 = time.time()
+    g = gg.rmat_24_10core()
+    log(f"rmat: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
+    rp, col, w = mc.to_device(g, "cuda:0")
+    mc.mincut(rp, col, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lam, side, st = mc.mincut(rp, col, w)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    s = side.cpu().numpy()[: g.n].astype(bool)
+    cut = int(g.w[s[g.src()] != s[g.col]].sum()) // 2
+    out = {"n": g.n, "m": g.m, "ms": round(dt * 1e3, 3), "edges_per_s": g.m / dt, "rounds": st["rounds"],
+           "lambda": lam, "oracle_lambda": gold["lambda"] if gold else None, "side_cut_weight": cut}
+    log(f"rmat: {out}")
+    return out
+
+
 def served_form(requests, pool_size, lanes, seed=5):
     """Poisson arrivals of min-cut requests (Chung-Lu, exponent 2.5, average
     degree 16, n log-uniform in [2^10, 2^20], weights in [1, 50], largest
@@ -194,6 +220,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--workload", choices=["chung_lu", "batched", "served"], default="chung_lu")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-rmat", action="store_true")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--pool", type=int, default=32)
     ap.add_argument("--lanes", type=int, default=3)
@@ -312,6 +339,9 @@ def main():
     served = None
     if not args.no_served:
         served = served_form(args.requests, args.pool, args.lanes)
+    rmat = None
+    if not args.no_rmat:
+        rmat = rmat_form(max(1, min(args.steps, 3)))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -326,7 +356,8 @@ def main():
            "config": {"workload": f"chung_lu n=2^{args.n_log2} exp2.5 avgdeg32 unit-weight "
                                   f"8-core LCC", "n": g.n, "m": g.m,
                       "rounds": st["rounds"], "verified": verified},
-           "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "served": served}
+           "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "served": served,
+           "rmat_scale24": rmat}
     print(json.dumps(out), flush=True)
 
 
