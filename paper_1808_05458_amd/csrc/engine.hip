@@ -43,6 +43,7 @@ constexpr int WHOLE_CAP_L = 8192;
 constexpr int SMALL_CAP_S = 2048;  // LDS-resident sweeps of whole small graphs
 constexpr int SMALL_CAP_L = 8192;
 constexpr int64_t SWEEP_HANDOFF_ENTRIES = 1 << 16;  // batches with longer rows run grid-wide
+constexpr int32_t MAX_SWEEPS = 256;                 // full-graph sweeps run at once
 
 // ------------------------------------------------------------------ timing
 struct TimingClass {
@@ -144,8 +145,14 @@ struct Workspace {
   // vertex arrays
   int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *capq, *capx, *sw_seg, *newid,
       *map, *ogid;
-  SweepCtl* sweep;
-  SweepCtl* sweep_host = nullptr;
+  SweepCtl* sweep;                  // MAX_SWEEPS queues
+  SweepCtl* sweep_host = nullptr;   // pinned, for single-field readbacks
+  SweepArgs* sw_args;               // per swept graph
+  int32_t* sw_run;                  // graphs still running
+  SweepStatus* sw_status;
+  SweepArgs* sw_args_host = nullptr;  // pinned mirrors
+  int32_t* sw_run_host = nullptr;
+  SweepStatus* sw_status_host = nullptr;
   int64_t* sw_info;
   int64_t *rp, *cdeg;
   // entry arrays
@@ -187,6 +194,12 @@ struct Workspace {
     allocs.clear();
     if (ctl_host) hipHostFree(ctl_host);
     if (sweep_host) hipHostFree(sweep_host);
+    if (sw_args_host) hipHostFree(sw_args_host);
+    if (sw_run_host) hipHostFree(sw_run_host);
+    if (sw_status_host) hipHostFree(sw_status_host);
+    sw_args_host = nullptr;
+    sw_run_host = nullptr;
+    sw_status_host = nullptr;
     ctl_host = nullptr;
     sweep_host = nullptr;
     capN = capE = capG = 0;
@@ -197,9 +210,11 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
   size_t b = 0;
-  b += align_up((N + 1) * 4) * 17 + align_up(sizeof(SweepCtl)) + align_up((G + 1) * 24);
+  b += align_up((N + 1) * 4) * 17 + align_up((G + 1) * 40);
+  b += align_up(sizeof(SweepCtl) * MAX_SWEEPS) + align_up(sizeof(SweepArgs) * MAX_SWEEPS) +
+       2 * align_up(sizeof(SweepStatus) * MAX_SWEEPS);
   b += align_up((N + 2) * 8) * 2;
-  b += align_up(E * 4) * 3 + align_up((E + 64) * 8) * 2 + align_up(E * 4) * 2;
+  b += align_up(E * 4) * 3 + align_up((E + 64) * 8) + align_up((E + G + 64) * 8) + align_up(E * 4) * 2;
   b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 16 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
   b += align_up((2 * N + G + 64) * 4);
@@ -213,6 +228,13 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   int dev = 0;
   MC_HIP(hipGetDevice(&dev));
   if (ws.device == dev && N <= ws.capN && E <= ws.capE && G <= ws.capG) return MC_OK;
+  // growing: a quarter of headroom, so a caller whose sizes vary (the
+  // server's lanes) settles after a few reallocations
+  if (ws.device == dev && ws.capN > 0) {
+    N = std::max(N, ws.capN + ws.capN / 4);
+    E = std::max(E, ws.capE + ws.capE / 4);
+    G = std::max(G, ws.capG + ws.capG / 4);
+  }
   ws.release();
   ws.device = dev;
   N = std::max<int64_t>(N, 16);
@@ -244,15 +266,18 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.capq, (N + 1) * 4);
   ALLOC(ws.capx, (N + 1) * 4);
   ALLOC(ws.sw_seg, (N + 1) * 4);
-  ALLOC(ws.sweep, sizeof(SweepCtl));
-  ALLOC(ws.sw_info, (G + 1) * 3 * 8);
+  ALLOC(ws.sweep, sizeof(SweepCtl) * MAX_SWEEPS);
+  ALLOC(ws.sw_args, sizeof(SweepArgs) * MAX_SWEEPS);
+  ALLOC(ws.sw_run, sizeof(int32_t) * MAX_SWEEPS);
+  ALLOC(ws.sw_status, sizeof(SweepStatus) * MAX_SWEEPS);
+  ALLOC(ws.sw_info, (G + 1) * 5 * 8);
   ALLOC(ws.rp, (N + 2) * 8);
   ALLOC(ws.cdeg, (N + 2) * 8);
   ALLOC(ws.src, E * 4);
   ALLOC(ws.col, E * 4);
   ALLOC(ws.w, E * 4);
   ALLOC(ws.keys, (E + 64) * 8);
-  ALLOC(ws.keys_alt, (E + 64) * 8);  // also the sweep's bucket pool (one entry per relaxation)
+  ALLOC(ws.keys_alt, (E + G + 64) * 8);  // also the sweeps' bucket pools (one entry per relaxation)
   ALLOC(ws.vals, E * 4);
   ALLOC(ws.vals_alt, E * 4);
   ALLOC(ws.voff, (G + 1) * 8);
@@ -285,7 +310,11 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.ctl, sizeof(Ctl));
 #undef ALLOC
   if (hipHostMalloc((void**)&ws.ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&ws.sweep_host, sizeof(SweepCtl), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&ws.sweep_host, sizeof(SweepCtl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ws.sw_args_host, sizeof(SweepArgs) * MAX_SWEEPS, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ws.sw_run_host, sizeof(int32_t) * MAX_SWEEPS, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ws.sw_status_host, sizeof(SweepStatus) * MAX_SWEEPS, hipHostMallocDefault) !=
+          hipSuccess) {
     ws.release();
     return MC_ENOMEM;
   }
@@ -441,91 +470,122 @@ struct Solver {
     }
   }
 
-  // One full-graph capped sweep over graph g (vertex range [v0, v0 + ng)).
-  int sweep_graph(int32_t g, int32_t v0, int32_t ng, int64_t lam, int round, const int64_t* rp,
-                  const int32_t* col, const int32_t* w, int64_t nnz, const GraphState& S,
-                  mc_stats* st) {
-    if (lam <= 0 || ng < 2) return MC_OK;
-    SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_step, ws.capq, ws.capx,
-                (int2*)ws.keys_alt, ws.capE + 64, ws.sw_seg, ws.sweep, v0, ng, lam, 0, 1, 1, 0};
-    const int lb = bitlen((uint64_t)(lam - 1));
-    A.shift = lb > 12 ? lb - 12 : 0;
-    A.nb = (int32_t)(((lam - 1) >> A.shift) + 1);
-    A.nwords = (A.nb + 63) / 64;
-    A.big = opt.sweep_handoff > 0 ? opt.sweep_handoff : 512;
-    A.big_entries = SWEEP_HANDOFF_ENTRIES;
-    uint64_t h = (opt.seed ? opt.seed : 0x5EEDull) * 0x9E3779B97F4A7C15ull +
-                 (uint64_t)round * 0xBF58476D1CE4E5B9ull + (uint64_t)g;
-    h ^= h >> 29;
-    const int32_t start = v0 + (int32_t)(h % (uint64_t)ng);
+  // Full-graph capped sweeps of the listed graphs, all at once: the
+  // sequential kernel runs one workgroup per graph, each with its own queue
+  // (SweepCtl), FIFO range [v0, v0 + ng) and pool range (the graph's entry
+  // range shifted by the graph id, one slot longer for the seed entry; entry
+  // ranges are ordered by graph id, so the pools are disjoint).  Between
+  // launches the host runs the pending grid-wide batches
+  // of every graph that handed one back.  info: per graph (first vertex,
+  // vertex count, bound, first entry, end entry).
+  int sweep_graphs(const std::vector<int32_t>& glist, const std::vector<int64_t>& info, int round,
+                   const int64_t* rp, const int32_t* col, const int32_t* w, const GraphState& S) {
     const int TB = 256;
-    hipLaunchKernelGGL(k_sweep_init, dim3(grid_for(std::max<int64_t>(ng, SWEEP_BUCKETS), TB, num_cu * 16)),
-                       dim3(TB), 0, s, A);
-    hipLaunchKernelGGL(k_sweep_seed, dim3(1), dim3(64), 0, s, A, start);
-    double big_deg = 0;
-    int64_t seq_vertices = ng;
-    for (int iter = 0;; ++iter) {
-      {
-        TimedScope t("sweep_seq", 0.0);
-        hipLaunchKernelGGL(k_sweep_seq, dim3(1), dim3(SWEEP_THREADS), 0, s, A);
+    const int32_t total = (int32_t)glist.size();
+    std::vector<int32_t> run, next;
+    for (int32_t c0 = 0; c0 < total; c0 += MAX_SWEEPS) {
+      const int32_t kq = std::min<int32_t>(MAX_SWEEPS, total - c0);
+      int32_t k = 0;
+      int64_t max_ng = 0, entries = 0;
+      for (int32_t i = 0; i < kq; ++i) {
+        const int32_t q = c0 + i;
+        const int32_t v0 = (int32_t)info[5 * q], ng = (int32_t)info[5 * q + 1];
+        const int64_t lam = info[5 * q + 2], e0 = info[5 * q + 3], e1 = info[5 * q + 4];
+        if (lam <= 0 || ng < 2) continue;
+        SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_step, ws.capq + v0, ws.capx + v0,
+                    (int2*)ws.keys_alt + e0 + glist[q], e1 - e0 + 1, ws.sw_seg + v0, ws.sweep + k, v0, ng, lam,
+                    0, 1, 1, 0};
+        const int lb = bitlen((uint64_t)(lam - 1));
+        A.shift = lb > 12 ? lb - 12 : 0;
+        A.nb = (int32_t)(((lam - 1) >> A.shift) + 1);
+        A.nwords = (A.nb + 63) / 64;
+        A.big = opt.sweep_handoff > 0 ? opt.sweep_handoff : 512;
+        A.big_entries = SWEEP_HANDOFF_ENTRIES;
+        uint64_t h = (opt.seed ? opt.seed : 0x5EEDull) * 0x9E3779B97F4A7C15ull +
+                     (uint64_t)round * 0xBF58476D1CE4E5B9ull + (uint64_t)glist[q];
+        h ^= h >> 29;
+        A.start = v0 + (int32_t)(h % (uint64_t)ng);
+        A.g = glist[q];
+        ws.sw_args_host[k++] = A;
+        max_ng = std::max<int64_t>(max_ng, ng);
+        entries += e1 - e0;
       }
-      MC_HIP(hipMemcpyAsync(ws.sweep_host, ws.sweep, 64, hipMemcpyDeviceToHost, s));
-      MC_HIP(hipStreamSynchronize(s));
-      const SweepCtl& c = *ws.sweep_host;
-      if (c.status == SW_DONE) break;
-      if (c.status != SW_BIG) return MC_EINTERNAL;
-      const int32_t bh = c.cap_head, bt = c.cap_tail;
-      const int64_t bsz = bt - bh;
-      MC_HIP(hipMemsetAsync(&ws.sweep->batch_sum, 0, 24, s));
-      hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
-      int64_t deg_sum = 0;
-      if (timer().on) {
-        MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &ws.sweep->batch_deg, 8, hipMemcpyDeviceToHost, s));
+      if (k == 0) continue;
+      MC_HIP(hipMemcpyAsync(ws.sw_args, ws.sw_args_host, sizeof(SweepArgs) * k, hipMemcpyHostToDevice, s));
+      const int gx = std::max(1, std::min(grid_for(std::max<int64_t>(max_ng, SWEEP_BUCKETS), TB, num_cu * 16),
+                                          (num_cu * 16 + k - 1) / k));
+      hipLaunchKernelGGL(k_sweep_init, dim3(gx, k), dim3(TB), 0, s, ws.sw_args);
+      hipLaunchKernelGGL(k_sweep_seed, dim3(grid_for(k, TB, num_cu)), dim3(TB), 0, s, ws.sw_args, k);
+      run.resize(k);
+      for (int32_t i = 0; i < k; ++i) run[i] = i;
+      double big_deg = 0;
+      while (!run.empty()) {
+        const int32_t nrun = (int32_t)run.size();
+        std::memcpy(ws.sw_run_host, run.data(), sizeof(int32_t) * nrun);
+        MC_HIP(hipMemcpyAsync(ws.sw_run, ws.sw_run_host, sizeof(int32_t) * nrun, hipMemcpyHostToDevice, s));
+        {
+          TimedScope t("sweep_seq", 0.0);
+          hipLaunchKernelGGL(k_sweep_seq, dim3(nrun), dim3(SWEEP_THREADS), 0, s, ws.sw_args, ws.sw_run);
+        }
+        hipLaunchKernelGGL(k_sweep_status, dim3(grid_for(nrun, TB, num_cu)), dim3(TB), 0, s, ws.sw_args,
+                           ws.sw_run, nrun, ws.sw_status);
+        MC_HIP(hipMemcpyAsync(ws.sw_status_host, ws.sw_status, sizeof(SweepStatus) * nrun, hipMemcpyDeviceToHost,
+                              s));
         MC_HIP(hipStreamSynchronize(s));
-        deg_sum = ws.sweep_host->batch_deg;
-        big_deg += (double)deg_sum;
-        seq_vertices -= bsz;
+        next.clear();
+        for (int32_t j = 0; j < nrun; ++j) {
+          const SweepStatus c = ws.sw_status_host[j];
+          if (c.status == SW_DONE) continue;
+          if (c.status != SW_BIG) return MC_EINTERNAL;
+          const SweepArgs& A = ws.sw_args_host[run[j]];
+          const int32_t bh = c.cap_head, bt = c.cap_tail;
+          const int64_t bsz = bt - bh;
+          MC_HIP(hipMemsetAsync(&A.ctl->batch_sum, 0, 24, s));
+          hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
+          int64_t deg_sum = 0;
+          if (timer().on) {
+            MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &A.ctl->batch_deg, 8, hipMemcpyDeviceToHost, s));
+            MC_HIP(hipStreamSynchronize(s));
+            deg_sum = ws.sweep_host->batch_deg;
+            big_deg += (double)deg_sum;
+          }
+          {
+            // every row of the batch once (col, w: 8 B per entry), the state
+            // gather and the r read-modify-write of each neighbour (12 B), and
+            // per batch vertex its FIFO slot and row bounds (20 B)
+            TimedScope t("sweep_relax", (double)deg_sum * 20 + (double)bsz * 20);
+            hipLaunchKernelGGL(k_sweep_big_relax, dim3(grid_for(bsz * 64, TB, num_cu * 32)), dim3(TB), 0, s, A,
+                               bh, bt);
+          }
+          hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
+          {
+            // exact queue rebuild: two passes over the graph's vertices
+            TimedScope t("sweep_rebuild", (double)A.ng * 16);
+            hipLaunchKernelGGL(k_sweep_rb_zero, dim3(16), dim3(256), 0, s, A);
+            hipLaunchKernelGGL(k_sweep_rb_count, dim3(grid_for(A.ng, TB, num_cu * 4)), dim3(TB), 0, s, A);
+            hipLaunchKernelGGL(k_sweep_rb_scan, dim3(1), dim3(1024), 0, s, A);
+            hipLaunchKernelGGL(k_sweep_rb_fill, dim3((A.ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);
+          }
+          next.push_back(run[j]);
+        }
+        run.swap(next);
       }
-      {
-        // every row of the batch once (col, w: 8 B per entry), the state
-        // gather and the r read-modify-write of each neighbour (12 B), and
-        // per batch vertex its FIFO slot and row bounds (20 B)
-        TimedScope t("sweep_relax", (double)deg_sum * 20 + (double)bsz * 20);
-        hipLaunchKernelGGL(k_sweep_big_relax, dim3(grid_for(bsz * 64, TB, num_cu * 32)), dim3(TB), 0, s, A, bh,
-                           bt);
-      }
-      hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
-      {
-        // exact queue rebuild: two passes over the graph's vertices
-        TimedScope t("sweep_rebuild", (double)ng * 16);
-        hipLaunchKernelGGL(k_sweep_rb_zero, dim3(16), dim3(256), 0, s, A);
-        hipLaunchKernelGGL(k_sweep_rb_count, dim3(grid_for(ng, TB, num_cu * 4)), dim3(TB), 0, s, A);
-        hipLaunchKernelGGL(k_sweep_rb_scan, dim3(1), dim3(1024), 0, s, A);
-        hipLaunchKernelGGL(k_sweep_rb_fill, dim3((ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);
-      }
-    }
-    if (timer().on) {
       // the sequential kernel relaxed every row the grid-wide batches did not
-      int64_t ends[2] = {0, 0};
-      MC_HIP(hipMemcpyAsync(&ends[0], rp + v0, 8, hipMemcpyDeviceToHost, s));
-      MC_HIP(hipMemcpyAsync(&ends[1], rp + v0 + ng, 8, hipMemcpyDeviceToHost, s));
-      MC_HIP(hipStreamSynchronize(s));
-      const double seq_rows = (double)(ends[1] - ends[0]) - big_deg;
-      timer().add_bytes("sweep_seq", seq_rows * 20 + (double)seq_vertices * 32);
+      if (timer().on) timer().add_bytes("sweep_seq", ((double)entries - big_deg) * 20);
+      hipLaunchKernelGGL(k_sweep_unite, dim3(gx, k), dim3(TB), 0, s, ws.sw_args);
+      hipLaunchKernelGGL(k_sweep_report, dim3(grid_for(k, TB, num_cu)), dim3(TB), 0, s, ws.sw_args, k, S);
+      if (debug_on()) {
+        MC_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < k; ++i) {
+          SweepCtl c;
+          MC_HIP(hipMemcpy(&c, ws.sw_args_host[i].ctl, 128, hipMemcpyDeviceToHost));
+          fprintf(stderr, "[mc] sweep g=%d v0=%d ng=%d lam=%lld visited=%d singles=%d batches=%d big=%d "
+                  "rebuilds=%d unions=%d best_alpha=%lld step=%d\n", ws.sw_args_host[i].g, ws.sw_args_host[i].v0,
+                  ws.sw_args_host[i].ng, (long long)ws.sw_args_host[i].lam, c.visited, c.singles, c.batches,
+                  c.big_batches, c.rebuilds, c.cap_tail, (long long)c.best_alpha, c.best_step);
+        }
+      }
     }
-    hipLaunchKernelGGL(k_sweep_unite, dim3(grid_for(ng, TB, num_cu * 16)), dim3(TB), 0, s, A);
-    hipLaunchKernelGGL(k_sweep_report, dim3(1), dim3(64), 0, s, ws.sweep, g, S);
-    if (debug_on()) {
-      hipStreamSynchronize(s);
-      SweepCtl c;
-      hipMemcpy(&c, ws.sweep, sizeof(SweepCtl), hipMemcpyDeviceToHost);
-      fprintf(stderr, "[mc] sweep g=%d v0=%d ng=%d lam=%lld visited=%d singles=%d batches=%d big=%d "
-              "rebuilds=%d unions=%d best_alpha=%lld step=%d\n", g, v0, ng, (long long)lam, c.visited,
-              c.singles, c.batches, c.big_batches, c.rebuilds, c.cap_tail, (long long)c.best_alpha,
-              c.best_step);
-    }
-    (void)nnz;
-    (void)st;
     return MC_OK;
   }
 
@@ -980,7 +1040,7 @@ struct Solver {
       const int sweep_region = (opt.scan_mode != 1 || opt.force_fallback) ? 1 : 0;
       hipLaunchKernelGGL(k_sweep_list, grid(G), dim3(TB), 0, s, G, S, sweep_region, ws.ctl);
       hipLaunchKernelGGL(k_sweep_info, grid(G), dim3(TB), 0, s, ws.fb_list, ws.ctl, ws.cvoff, ws.gn,
-                         ws.lhat, ws.sw_info);
+                         ws.lhat, rp, ws.sw_info);
       rc = read_ctl();
       if (rc) return rc;
       // whole scans: col and w per entry; row_ptr, cdeg, claim and step (one-pop
@@ -997,16 +1057,13 @@ struct Solver {
       }
       const int32_t n_sweeps = ws.ctl_host->n_fallback;
       if (n_sweeps > 0) {
-        std::vector<int64_t> info((size_t)n_sweeps * 3);
+        std::vector<int64_t> info((size_t)n_sweeps * 5);
         std::vector<int32_t> glist(n_sweeps);
         MC_HIP(hipMemcpyAsync(info.data(), ws.sw_info, info.size() * 8, hipMemcpyDeviceToHost, s));
         MC_HIP(hipMemcpyAsync(glist.data(), ws.fb_list, n_sweeps * 4, hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
-        for (int32_t q = 0; q < n_sweeps; ++q) {
-          rc = sweep_graph(glist[q], (int32_t)info[3 * q], (int32_t)info[3 * q + 1], info[3 * q + 2],
-                           round, rp, col, w, nnz, S, st);
-          if (rc) return rc;
-        }
+        rc = sweep_graphs(glist, info, round, rp, col, w, S);
+        if (rc) return rc;
         if (st) st->fallbacks += n_sweeps;
       }
       // union-find finish and block numbering

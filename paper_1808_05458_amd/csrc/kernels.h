@@ -428,23 +428,29 @@ __global__ void k_sweep_list(int32_t G, GraphState S, int32_t sweep_region, Ctl*
     }
 }
 
+// Per swept graph: first vertex, vertex count, bound and entry range.
 __global__ void k_sweep_info(const int32_t* list, const Ctl* ctl, const int32_t* cvoff, const int32_t* gn,
-                             const int64_t* lhat, int64_t* info) {
+                             const int64_t* lhat, const int64_t* rp, int64_t* info) {
   for (int64_t i = gtid(); i < ctl->n_fallback; i += gstride()) {
-    int32_t g = list[i];
-    info[3 * i] = cvoff[g];
-    info[3 * i + 1] = gn[g];
-    info[3 * i + 2] = lhat[g];
+    const int32_t g = list[i];
+    info[5 * i] = cvoff[g];
+    info[5 * i + 1] = gn[g];
+    info[5 * i + 2] = lhat[g];
+    info[5 * i + 3] = rp[cvoff[g]];
+    info[5 * i + 4] = rp[cvoff[g] + gn[g]];
   }
 }
 
-__global__ void k_sweep_report(const SweepCtl* c, int32_t g, GraphState S) {
-  if (gtid() != 0) return;
-  if (c->best_alpha < S.lhat[g]) {
-    S.fb_k[g] = c->best_step;
-    atomic_min_u64(S.balpha + g, ((uint64_t)c->best_alpha << 32) | (uint32_t)SWEEP_SID);
+__global__ void k_sweep_report(const SweepArgs* args, int32_t k, GraphState S) {
+  for (int64_t i = gtid(); i < k; i += gstride()) {
+    const SweepCtl* c = args[i].ctl;
+    const int32_t g = args[i].g;
+    if (c->best_alpha < S.lhat[g]) {
+      S.fb_k[g] = c->best_step;
+      atomic_min_u64(S.balpha + g, ((uint64_t)c->best_alpha << 32) | (uint32_t)SWEEP_SID);
+    }
+    atomicAdd(S.ucount + g, c->cap_tail);  // every crossing vertex entered the FIFO once
   }
-  atomicAdd(S.ucount + g, c->cap_tail);  // every crossing vertex entered the FIFO once
 }
 
 // ------------------------------------------------------------ compaction

@@ -64,8 +64,10 @@ struct LaneBuffers {
   int ensure(int64_t N, int64_t E) {
     if (N <= capN && E <= capE) return MC_OK;
     release();
-    N = std::max<int64_t>(N, 1024);
-    E = std::max<int64_t>(E, 4096);
+    // geometric growth: pinning and freeing are slow, so a lane settles on
+    // its largest batch after a few reallocations
+    N = std::max<int64_t>(N + N / 2, 1 << 16);
+    E = std::max<int64_t>(E + E / 2, 1 << 20);
     if (hipMalloc(&rp, (N + 1) * 8) != hipSuccess || hipMalloc(&col, E * 4) != hipSuccess ||
         hipMalloc(&w, E * 4) != hipSuccess || hipMalloc(&side, N) != hipSuccess ||
         hipHostMalloc((void**)&h_rp, (N + 1) * 8, hipHostMallocDefault) != hipSuccess ||
@@ -291,9 +293,10 @@ int mc_server_submit(mc_server* srv, const mc_request* req, uint64_t* ticket) {
     r->col = r->own_col.data();
     r->w = r->own_w.data();
   }
-  // input CSR, side, and the solver's share of a workspace
+  // input CSR, side, and the solver's share of a workspace (its size-
+  // dependent part: the fixed part is held by each lane once)
   r->bytes = (int64_t)(req->n + 1) * 8 + req->nnz * 8 + req->n +
-             (int64_t)mc::workspace_bytes(req->n, req->nnz, 1);
+             (int64_t)(mc::workspace_bytes(req->n, req->nnz, 1) - mc::workspace_bytes(0, 0, 0));
   if (r->bytes > S->budget) return MC_ENOMEM;
   r->t_submit = std::chrono::steady_clock::now();
   {

@@ -74,6 +74,8 @@ struct SweepArgs {
   int32_t nb;        // buckets in use
   int32_t big;       // batches above this size go grid-wide
   int64_t big_entries;  // ... and so do batches whose rows hold more entries
+  int32_t start;     // the first vertex (global id)
+  int32_t g;         // the graph
 };
 
 // The queue and FIFO bookkeeping, addressed through generic pointers: the
@@ -204,19 +206,21 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
   return internal;
 }
 
-// Reset the graph's range and the queue.
-__global__ void k_sweep_init(SweepArgs A) {
-  for (int64_t i = gtid(); i < A.ng; i += gstride()) {
+// Reset each graph's range and queue: graph blockIdx.y of the argument array.
+__global__ void k_sweep_init(const SweepArgs* args) {
+  const SweepArgs A = args[blockIdx.y];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = tid; i < A.ng; i += nth) {
     A.r[A.v0 + i] = 0;
     A.step[A.v0 + i] = 0;
   }
-  for (int64_t i = gtid(); i < SWEEP_BUCKETS; i += gstride()) {
+  for (int64_t i = tid; i < SWEEP_BUCKETS; i += nth) {
     A.ctl->head[i] = -1;
     A.ctl->seg_cur[i] = 0;
     A.ctl->seg_end[i] = 0;
   }
-  for (int64_t i = gtid(); i < SWEEP_BUCKETS / 64; i += gstride()) A.ctl->bitmap[i] = 0;
-  if (gtid() == 0) {
+  for (int64_t i = tid; i < SWEEP_BUCKETS / 64; i += nth) A.ctl->bitmap[i] = 0;
+  if (tid == 0) {
     SweepCtl* c = A.ctl;
     c->cap_head = c->cap_tail = 0;
     c->visited = 0;
@@ -232,9 +236,11 @@ __global__ void k_sweep_init(SweepArgs A) {
   }
 }
 
-__global__ void k_sweep_seed(SweepArgs A, int32_t start) {
-  if (gtid() == 0) {
-    A.pool[0] = make_int2(start, -1);  // (vertex, next)
+// The start of every graph in bucket 0 (thread i: graph i of k).
+__global__ void k_sweep_seed(const SweepArgs* args, int32_t k) {
+  for (int64_t i = gtid(); i < k; i += gstride()) {
+    const SweepArgs& A = args[i];
+    A.pool[0] = make_int2(A.start, -1);  // (vertex, next)
     A.ctl->head[0] = 0;
     A.ctl->bitmap[0] = 1ull;
   }
@@ -387,7 +393,9 @@ __device__ __forceinline__ int64_t wave_relax_known(const SweepArgs& A, const Sw
 // pending; cap_head..cap_tail untouched).
 enum : int32_t { CMD_EXIT_DONE = 0, CMD_BATCH = 1, CMD_EXIT_BIG = 2, CMD_SINGLE = 3 };
 
-__global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
+__global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* args, const int32_t* run) {
+  // one workgroup per graph still running: graph run[blockIdx.x]
+  const SweepArgs A = args[run[blockIdx.x]];
   __shared__ int32_t sh_x, sh_cmd, sh_h, sh_t, sh_stamp;
   // a wide batch chunk: its vertices, row starts and entry offsets
   __shared__ int32_t sh_bx[SWEEP_THREADS], sh_boff[SWEEP_THREADS + 1], sh_wtot[SWEEP_THREADS / 64];
@@ -633,10 +641,25 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(SweepArgs A) {
   }
 }
 
-// The crossing edges found by the sweep, united after it: (capx[i], capq[i]).
-__global__ void k_sweep_unite(SweepArgs A) {
+// The crossing edges found by the sweeps, united after them: (capx[i],
+// capq[i]) of graph blockIdx.y.
+__global__ void k_sweep_unite(const SweepArgs* args) {
+  const SweepArgs& A = args[blockIdx.y];
   const int32_t n = A.ctl->cap_tail;
-  for (int64_t i = gtid(); i < n; i += gstride()) uf_union(A.parent, A.capx[i], A.capq[i]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    uf_union(A.parent, A.capx[i], A.capq[i]);
+}
+
+// Per graph: status, FIFO bounds and row entries of the pending batch, for
+// the host (one small copy instead of one per graph).
+struct SweepStatus {
+  int32_t status, cap_head, cap_tail, pad;
+};
+__global__ void k_sweep_status(const SweepArgs* args, const int32_t* run, int32_t k, SweepStatus* out) {
+  for (int64_t i = gtid(); i < k; i += gstride()) {
+    const SweepCtl* c = args[run[i]].ctl;
+    out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, 0};
+  }
 }
 
 // Grid-wide batch [h, t): mark every vertex visited.

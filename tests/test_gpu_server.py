@@ -121,7 +121,7 @@ def test_memory_budget_admits_one_at_a_time(reqs):
     announce("server budget", len(small))
 
     def footprint(g):  # as the server counts it: input, side, solver share
-        return (g.n + 1) * 8 + g.nnz * 8 + g.n + mc.workspace_bytes(g.n, g.nnz, 1)
+        return (g.n + 1) * 8 + g.nnz * 8 + g.n + mc.workspace_bytes(g.n, g.nnz, 1) - mc.workspace_bytes(0, 0, 0)
 
     fp = [footprint(g) for g, _ in small]
     budget = max(fp)  # the largest request fits alone
