@@ -161,7 +161,7 @@ struct Workspace {
   int32_t *vals, *vals_alt;
   // graph arrays
   int64_t *voff, *lhat, *wsum;
-  int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole,
+  int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole, *gmaxw, *prok,
       *whole2, *fb_list, *root0, *flip, *nvoff, *npairs;
   uint64_t *bdeg, *balpha;
   uint8_t* mode;
@@ -215,7 +215,7 @@ size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
        2 * align_up(sizeof(SweepStatus) * MAX_SWEEPS);
   b += align_up((N + 2) * 8) * 2;
   b += align_up(E * 4) * 3 + align_up((E + 64) * 8) + align_up((E + G + 64) * 8) + align_up(E * 4) * 2;
-  b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 16 + align_up((G + 1) * 8) * 2 +
+  b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 18 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
   b += align_up((2 * N + G + 64) * 4);
   size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
@@ -299,6 +299,8 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.flip, (G + 1) * 4);
   ALLOC(ws.nvoff, (G + 1) * 4);
   ALLOC(ws.npairs, (G + 1) * 4);
+  ALLOC(ws.gmaxw, (G + 1) * 4);
+  ALLOC(ws.prok, (G + 1) * 4);
   ALLOC(ws.bdeg, (G + 1) * 8);
   ALLOC(ws.balpha, (G + 1) * 8);
   ALLOC(ws.mode, G + 1);
@@ -854,8 +856,9 @@ struct Solver {
       TimedScope t("ingest", (double)E * 12 + (double)N * 24);
       hipLaunchKernelGGL(k_init_vertices, grid(N), dim3(TB), 0, s, N, ws.voff, G, gid, ws.ogid, ws.map);
       fill<int64_t>(ws.cdeg, 0, N, s);
+      fill<int32_t>(ws.gmaxw, 0, G, s);
       hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + 64 * INGEST_STEPS - 1) / (64 * INGEST_STEPS) * 64, TB, num_cu * 16)),
-                         dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, ws.src, ws.cdeg, ws.ctl);
+                         dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, ws.src, ws.cdeg, ws.gmaxw, ws.ctl);
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
       fill<int64_t>(ws.wsum, 0, G, s);
       hipLaunchKernelGGL(k_min_degree, gridr(N), dim3(TB), 0, s, N, ws.cdeg, gid, (const int32_t*)nullptr,
@@ -879,7 +882,8 @@ struct Solver {
     } else {
       fill<int32_t>(ws.nnew, 1, G, s);  // one component assumed; see above
     }
-    hipLaunchKernelGGL(k_graph_init, grid(G), dim3(TB), 0, s, G, S, ws.root0, ws.parent, ws.ctl);
+    hipLaunchKernelGGL(k_graph_init, grid(G), dim3(TB), 0, s, G, S, ws.root0, ws.parent, ws.gmaxw, ws.prok,
+                       ws.ctl);
     if (want_side) {
       TimedScope t("side", (double)N * 13);
       SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
@@ -901,6 +905,12 @@ struct Solver {
     if (rc) return rc;
     if (ws.ctl_host->err == -3) return MC_EOVERFLOW;
     if (ws.ctl_host->err) return MC_EINVAL;
+    // the first round's tests run only where one can pass (a lower starting
+    // bound from the caller or the clustering bound may enable PR1)
+    const bool pr_first_round = ws.ctl_host->n_pr > 0 || lhat_in != nullptr || opt.use_viecut;
+    // in the first round only the graphs marked in prok are tested, unless a
+    // lower starting bound may have enabled PR1 elsewhere
+    const bool pr_first_all = lhat_in != nullptr || opt.use_viecut;
     if (st) {
       std::vector<int64_t> l0(G);
       MC_HIP(hipMemcpy(l0.data(), ws.lhat, G * sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -954,14 +964,15 @@ struct Solver {
       hipLaunchKernelGGL(k_round_reset, grid(G), dim3(TB), 0, s, G, S);
       hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
       fill<int32_t>(ws.claim, -1, n, s);
-      if (opt.use_pr) {
+      if (opt.use_pr && (round > 1 || pr_first_round)) {
         // src, col, w per entry; both degrees for the half with u < v
         TimedScope t("pr", (double)nnz * 20 + (double)n * 32);
+        const int32_t* tested = (round == 1 && !pr_first_all) ? ws.prok : ws.active;
         hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, ws.cdeg, gid, ws.lhat,
-                           ws.active, ws.parent, ws.ucount);
+                           tested, ws.parent, ws.ucount);
         hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
-                           ws.lhat, ws.active, ws.parent, ws.ucount, ws.ctl);
+                           ws.lhat, tested, ws.parent, ws.ucount, ws.ctl);
       }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -1287,9 +1298,10 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
   int64_t voff[2] = {0, g->n};
   MC_HIP(hipMemcpyAsync(ws.voff, voff, 16, hipMemcpyHostToDevice, s));
   fill<int32_t>(ws.gid[0], 0, g->n, s);
+  fill<int32_t>(ws.gmaxw, 0, 1, s);
   hipLaunchKernelGGL(k_ingest, dim3(grid_for((nnz + 64 * INGEST_STEPS - 1) / (64 * INGEST_STEPS) * 64, TB, ncu * 16)),
                      dim3(TB), 0, s, g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff, ws.src, ws.cdeg,
-                     ws.ctl);
+                     ws.gmaxw, ws.ctl);
   const int bb = std::max(1, bitlen((uint64_t)n_new - 1));
   hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, ncu * 8)), dim3(TB), 0, s, nnz,
                      ws.src, g->col, g->w, labels, bb, ws.keys, ws.vals, ws.ctl);

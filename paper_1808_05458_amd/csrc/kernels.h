@@ -88,11 +88,14 @@ __global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const in
                                                 const int32_t* __restrict__ w,
                                                 const int32_t* __restrict__ gid,
                                                 const int64_t* __restrict__ voff,
-                                                int32_t* __restrict__ src, int64_t* cdeg, Ctl* ctl) {
+                                                int32_t* __restrict__ src, int64_t* cdeg, int32_t* gmaxw,
+                                                Ctl* ctl) {
   const int lane = lane_id();
   const int64_t wave_global = gtid() >> 6;
   const int64_t nwaves = gstride() >> 6;
+  int32_t wg = -1, wm = 0;  // this wave's graph and its largest weight, flushed on change
   for (int64_t chunk = wave_global; chunk * 64 * INGEST_STEPS < nnz; chunk += nwaves) {
+    int32_t mg = -1, mw = 0;  // this lane's graph in the chunk and its largest weight
     int64_t e = chunk * 64 * INGEST_STEPS + lane;
     // row of the first entry: upper_bound(rp, e) - 1
     int32_t r = 0;
@@ -113,13 +116,38 @@ __global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const in
         src[e] = r;
         int32_t g = gid[r];
         if (y < voff[g] || y >= voff[g + 1] || c < 1) atomicExch(&ctl->err, -1);
+        if (g != mg) {
+          if (mg >= 0) atomicMax(gmaxw + mg, mw);
+          mg = g;
+          mw = 0;
+        }
+        mw = c > mw ? c : mw;
       }
       int64_t val = (ok && y != r) ? (int64_t)c : 0;
       bool tail;
       int64_t sum = wave_segsum<int32_t, int64_t>(ok ? r : -1, val, ok, tail);
       if (ok && tail && sum) atomicAdd((unsigned long long*)(cdeg + r), (unsigned long long)sum);
     }
+    // largest weight per graph: a chunk in one graph (the usual case) folds
+    // into the wave's running maximum, flushed when the graph changes
+    const int32_t g0 = shfl(mg, 0);
+    if (ballot(mg == g0) == ~0ull) {
+      int32_t m = mw;
+      for (int o = 32; o > 0; o >>= 1) {
+        const int32_t t = __shfl_xor(m, o, 64);
+        m = t > m ? t : m;
+      }
+      if (g0 != wg) {
+        if (lane == 0 && wg >= 0) atomicMax(gmaxw + wg, wm);
+        wg = g0;
+        wm = 0;
+      }
+      wm = m > wm ? m : wm;
+    } else if (mg >= 0) {
+      atomicMax(gmaxw + mg, mw);
+    }
   }
+  if (lane == 0 && wg >= 0) atomicMax(gmaxw + wg, wm);
 }
 
 // Per-graph minimum weighted degree (the trivial cut, section "Basic
@@ -216,7 +244,12 @@ __global__ void k_count_roots(int32_t n, const int32_t* parent, const int32_t* g
 }
 
 // ----------------------------------------------------- per-graph bookkeeping
-__global__ void k_graph_init(int32_t G, GraphState S, int32_t* root0, const int32_t* parent, Ctl* ctl) {
+// prok[g] (and the count ctl->n_pr) marks the graphs where a Padberg-Rinaldi
+// test can pass in the first round: PR1 needs an edge of weight >=
+// lambda-hat, PR2 one of weight above half the minimum degree (the largest
+// weight bounds both).
+__global__ void k_graph_init(int32_t G, GraphState S, int32_t* root0, const int32_t* parent,
+                             const int32_t* gmaxw, int32_t* prok, Ctl* ctl) {
   for (int64_t g = gtid(); g < G; g += gstride()) {
     int32_t ng = (int32_t)(S.voff[g + 1] - S.voff[g]);
     S.n[g] = ng;
@@ -236,7 +269,15 @@ __global__ void k_graph_init(int32_t G, GraphState S, int32_t* root0, const int3
     } else {
       S.active[g] = ng > 2 ? 1 : 0;
     }
-    if (S.active[g]) atomicAdd(&ctl->n_active, 1);
+    prok[g] = 0;
+    if (S.active[g]) {
+      atomicAdd(&ctl->n_active, 1);
+      const int64_t mw = gmaxw[g];
+      if (mw >= S.lhat[g] || 2 * mw > lam) {
+        prok[g] = 1;
+        atomicAdd(&ctl->n_pr, 1);
+      }
+    }
   }
 }
 
