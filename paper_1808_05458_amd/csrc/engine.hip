@@ -1036,7 +1036,7 @@ struct Solver {
         {
           TimedScope t("small_sweep", 0.0);
           MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
-          hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_L>, dim3(num_cu * 2), dim3(SS_THREADS),
+          hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_L>, dim3(num_cu * 3), dim3(SS_THREADS),
                              sizeof(SmallSweepLds<SMALL_CAP_L>), s, SA);
         }
         hipLaunchKernelGGL(k_small_sweep_unite, dim3(num_cu * 4), dim3(TB), 0, s, ws.whole, &ws.ctl->n_whole,

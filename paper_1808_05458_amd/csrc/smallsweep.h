@@ -57,7 +57,7 @@ struct SmallSweepLds {
   static constexpr int NC = CAP / 64;
   int32_t r[CAP];
   uint16_t capped[CAP];  // vertices in the order their r reached the cap
-  uint8_t st[CAP];       // 0 unvisited, 2 visited, 3 in the current batch
+  uint32_t st[CAP / 16];  // 2 bits per vertex: 0 unvisited, 2 visited, 3 in the current batch
   uint32_t cmax[NC];     // per 64-vertex chunk: >= r of its unvisited vertices
   int32_t boff[SS_THREADS + 1];  // a batch chunk: entry offsets of its rows
   int32_t bbase[SS_THREADS];     //   and each row's first entry (graph-relative)
@@ -66,6 +66,22 @@ struct SmallSweepLds {
   int32_t b0, nb, stamp;  // the batch capped[b0, b0 + nb); nb < 0: sweep done
   int64_t wsum[SS_NW], wint[SS_NW];
 };
+
+// The 2-bit visit state.  Marking is 0 -> 3 (an OR of both bits) and a
+// batch becomes visited by 3 -> 2 (clearing the low bit), so concurrent marks
+// of vertices sharing a word are atomic bit operations.
+template <int CAP>
+__device__ __forceinline__ uint32_t ss_state(const SmallSweepLds<CAP>& L, int32_t v) {
+  return (L.st[v >> 4] >> (2 * (v & 15))) & 3u;
+}
+template <int CAP>
+__device__ __forceinline__ void ss_mark(SmallSweepLds<CAP>& L, int32_t v) {
+  atomicOr(&L.st[v >> 4], 3u << (2 * (v & 15)));
+}
+template <int CAP>
+__device__ __forceinline__ void ss_visited(SmallSweepLds<CAP>& L, int32_t v) {
+  atomicAnd(&L.st[v >> 4], ~(1u << (2 * (v & 15))));
+}
 
 __device__ __forceinline__ void ss_wave_sync() {
   __builtin_amdgcn_wave_barrier();
@@ -82,7 +98,7 @@ __device__ __forceinline__ void ss_relax(SmallSweepLds<CAP>& L, const SmallSweep
   bool cross = false;
   if (ok && yl != xl) {
     rows += c;
-    const uint8_t s = L.st[yl];
+    const uint32_t s = ss_state(L, yl);
     if (s == 3) {
       internal += c;
     } else if (s == 0) {
@@ -127,7 +143,7 @@ __device__ __forceinline__ int32_t ss_select(SmallSweepLds<CAP>& L, int32_t ng) 
     if (bound == 0) return -1;
     const int c = (int)(uint32_t)bc;
     const int32_t v = c * 64 + lane;
-    const uint32_t key = (v < ng && L.st[v] == 0) ? (uint32_t)L.r[v] : 0u;
+    const uint32_t key = (v < ng && ss_state(L, v) == 0) ? (uint32_t)L.r[v] : 0u;
     const uint64_t kv = wave_max_u64(((uint64_t)key << 32) | (uint32_t)v);
     const uint32_t exact = (uint32_t)(kv >> 32);
     if (exact == bound) return (int32_t)(uint32_t)kv;
@@ -154,9 +170,9 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
     const int64_t ebase = A.rp[v0];
     for (int i = threadIdx.x; i < ng; i += SS_THREADS) {
       L.r[i] = 0;
-      L.st[i] = 0;
       A.fb_step[v0 + i] = 0;
     }
+    for (int i = threadIdx.x; i < (ng + 15) / 16; i += SS_THREADS) L.st[i] = 0;
     for (int c = threadIdx.x; c < SmallSweepLds<CAP>::NC; c += SS_THREADS) L.cmax[c] = 0;
     uint64_t h = A.seed * 0x9E3779B97F4A7C15ull + (uint64_t)g * 0xBF58476D1CE4E5B9ull;
     h ^= h >> 29;
@@ -184,7 +200,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
             if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = L.stamp; }
           }
           const int32_t pb0 = L.b0;
-          for (int k = lane; k < pnb; k += 64) L.st[L.capped[pb0 + k]] = 2;
+          for (int k = lane; k < pnb; k += 64) ss_visited(L, L.capped[pb0 + k]);
           ss_wave_sync();
         }
         // single pops, by this wave alone, while no vertex is at the cap
@@ -203,7 +219,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           if (xl < 0) { done = true; break; }
           ++stamp;
           if (lane == 0) {
-            L.st[xl] = 3;
+            ss_mark(L, xl);
             A.fb_step[v0 + xl] = stamp;
           }
           ss_wave_sync();
@@ -219,7 +235,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
             alpha += rows - 2 * (int64_t)L.r[xl];
             visited += 1;
             if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = stamp; }
-            L.st[xl] = 2;
+            ss_visited(L, xl);
           }
         }
         // publish the next batch: every vertex that reached the cap; mark it
@@ -240,7 +256,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           int64_t r2 = 0;
           for (int k = lane; k < nb; k += 64) {
             const int32_t x = L.capped[b0 + k];
-            L.st[x] = 3;
+            ss_mark(L, x);
             A.fb_step[v0 + x] = stamp;
             r2 += 2 * (int64_t)L.r[x];
           }
