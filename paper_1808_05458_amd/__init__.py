@@ -44,7 +44,6 @@ class MincutError(RuntimeError):
         msg = lib.mc_strerror(code).decode()
         super().__init__(f"{what}: {msg} (code {code})")
         self.code = code
-        self.code = code
 
 
 class Options(ctypes.Structure):

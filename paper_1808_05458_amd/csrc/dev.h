@@ -4,6 +4,11 @@
 #include <stdint.h>
 
 #define MC_WAVE 64
+// Global memory.  Pointers that kernels read from device memory (argument
+// arrays) are generic to the compiler, and accesses through generic
+// pointers are flat accesses, which also count against the LDS wait
+// counter; typing them as global gives global accesses.
+#define MC_GLOBAL __attribute__((address_space(1)))
 
 namespace mc {
 
@@ -47,6 +52,58 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
+// Wave-wide maximum of a 32-bit value (all lanes receive it; all 64 lanes
+// must be active).  DPP moves inside each row of 16 lanes (swap neighbours,
+// swap pairs, half-row mirror, row mirror) leave every row holding its
+// maximum; four lane reads combine the rows.  No LDS traffic, unlike the
+// permute-based shuffles above.
+// DPP controls: quad_perm 1,0,3,2 and 2,3,0,1, row_half_mirror, row_mirror.
+// Applied in this order, each lane combines with a lane of the other half of
+// a group that doubles every time (2, 4, 8, 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_i64(int64_t v) {
+  const uint32_t lo = dpp_u32<CTRL>((uint32_t)(uint64_t)v);
+  const uint32_t hi = dpp_u32<CTRL>((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  uint32_t t;
+  t = dpp_u32<0xB1>(v);
+  v = t > v ? t : v;
+  t = dpp_u32<0x4E>(v);
+  v = t > v ? t : v;
+  t = dpp_u32<0x141>(v);
+  v = t > v ? t : v;
+  t = dpp_u32<0x140>(v);
+  v = t > v ? t : v;
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+  const uint32_t ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
+// Wave-wide 64-bit sum by the same DPP steps (all 64 lanes active); the
+// result is uniform.
+__device__ __forceinline__ int64_t wave_sum_i64_dpp(int64_t v) {
+  v += dpp_i64<0xB1>(v);
+  v += dpp_i64<0x4E>(v);
+  v += dpp_i64<0x141>(v);
+  v += dpp_i64<0x140>(v);
+  return readlane_i64(v, 0) + readlane_i64(v, 16) + readlane_i64(v, 32) + readlane_i64(v, 48);
+}
+
 // Relaxed device-scope loads and stores for data other waves update.
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {
@@ -56,12 +113,26 @@ template <typename T>
 __device__ __forceinline__ void st_relaxed(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(const MC_GLOBAL T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed(MC_GLOBAL T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Relaxed device-scope fetch-add, for generic and global pointers.
+template <typename P, typename T>
+__device__ __forceinline__ T atomic_add(P p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // Lock-free union-find over int32 parents.  Invariant: parent[v] <= v, so a
 // root is always linked under a smaller root and path halving only ever
 // shortens a path to an ancestor; concurrent finds and unions stay safe.
-__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+template <typename P>
+__device__ __forceinline__ int32_t uf_find(P parent, int32_t x) {
   int32_t p = ld_relaxed(parent + x);
   while (p != x) {
     int32_t gp = ld_relaxed(parent + p);
@@ -73,7 +144,8 @@ __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
 }
 
 // Returns true if this call merged two different sets.
-__device__ __forceinline__ bool uf_union(int32_t* parent, int32_t a, int32_t b) {
+template <typename P>
+__device__ __forceinline__ bool uf_union(P parent, int32_t a, int32_t b) {
   while (true) {
     a = uf_find(parent, a);
     b = uf_find(parent, b);

@@ -1030,7 +1030,7 @@ struct Solver {
       } else {
         // whole small graphs: LDS-resident capped sweeps, one workgroup each,
         // the large-map list first (both lists are ordered largest first)
-        SmallSweepArgs SA{rp, col, w, ws.lhat, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
+        SmallSweepArgs SA{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
                           &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_step, ws.capq, ws.capx, ws.npairs,
                           ws.balpha, ws.fb_k, ws.ucount, A.seed};
         {

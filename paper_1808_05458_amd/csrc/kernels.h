@@ -484,7 +484,7 @@ __global__ void k_sweep_info(const int32_t* list, const Ctl* ctl, const int32_t*
 
 __global__ void k_sweep_report(const SweepArgs* args, int32_t k, GraphState S) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
-    const SweepCtl* c = args[i].ctl;
+    const MC_GLOBAL SweepCtl* c = (const MC_GLOBAL SweepCtl*)args[i].ctl;
     const int32_t g = args[i].g;
     if (c->best_alpha < S.lhat[g]) {
       S.fb_k[g] = c->best_step;

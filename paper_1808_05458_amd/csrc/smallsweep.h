@@ -29,6 +29,7 @@ struct SmallSweepArgs {
   const int64_t* rp;
   const int32_t* col;
   const int32_t* w;
+  const int64_t* cdeg;         // weighted degree without self-loops
   const int64_t* lhat;
   const int32_t* gn;
   const int32_t* gvoff;
@@ -92,7 +93,7 @@ __device__ __forceinline__ void ss_wave_sync() {
 // bound, and record the crossing r(y) < cap <= r(y) + c as a pair and a
 // capped vertex.  Must be called by all lanes of the wave.
 template <int CAP>
-__device__ __forceinline__ void ss_relax(SmallSweepLds<CAP>& L, const SmallSweepArgs& A, int32_t v0, int64_t lam,
+__device__ __forceinline__ bool ss_relax(SmallSweepLds<CAP>& L, const SmallSweepArgs& A, int32_t v0, int64_t lam,
                                          bool ok, int32_t xl, int32_t yl, int32_t c, int64_t& rows,
                                          int64_t& internal) {
   bool cross = false;
@@ -123,30 +124,40 @@ __device__ __forceinline__ void ss_relax(SmallSweepLds<CAP>& L, const SmallSweep
       L.capped[qa + rank] = (uint16_t)yl;
     }
   }
+  return cm != 0;
 }
 
-// The unvisited vertex of largest r > 0 (one wave, no other wave active);
-// -1 when none is left.
+// An unvisited vertex of largest r > 0, and that r (one wave, all lanes, no
+// other wave active); -1 when none is left.  Among equal keys the lowest
+// chunk and the lowest vertex in it are taken (any maximum is a legal next
+// vertex).  The caller visits the vertex, so its chunk's bound drops to the
+// largest key left in the chunk.
 template <int CAP>
-__device__ __forceinline__ int32_t ss_select(SmallSweepLds<CAP>& L, int32_t ng) {
+__device__ __forceinline__ int32_t ss_select(SmallSweepLds<CAP>& L, int32_t ng, uint32_t& rx) {
   constexpr int NC = SmallSweepLds<CAP>::NC;
   const int lane = lane_id();
   const int nc = (ng + 63) >> 6;
   while (true) {
-    uint64_t bc = 0;
+    uint32_t mine = 0;
+    int32_t mine_c = 0;
     for (int c = lane; c < nc && c < NC; c += 64) {
-      const uint64_t k = ((uint64_t)L.cmax[c] << 32) | (uint32_t)c;
-      bc = k > bc ? k : bc;
+      const uint32_t k = L.cmax[c];
+      if (k > mine) { mine = k; mine_c = c; }
     }
-    bc = wave_max_u64(bc);
-    const uint32_t bound = (uint32_t)(bc >> 32);
+    const uint32_t bound = wave_max_u32(mine);
     if (bound == 0) return -1;
-    const int c = (int)(uint32_t)bc;
+    const int holder = (int)__builtin_ctzll(ballot(mine == bound));
+    const int c = __builtin_amdgcn_readlane(mine_c, holder);
     const int32_t v = c * 64 + lane;
     const uint32_t key = (v < ng && ss_state(L, v) == 0) ? (uint32_t)L.r[v] : 0u;
-    const uint64_t kv = wave_max_u64(((uint64_t)key << 32) | (uint32_t)v);
-    const uint32_t exact = (uint32_t)(kv >> 32);
-    if (exact == bound) return (int32_t)(uint32_t)kv;
+    const uint32_t exact = wave_max_u32(key);
+    if (exact == bound) {
+      const int at = (int)__builtin_ctzll(ballot(key == exact));
+      const uint32_t rest = wave_max_u32(lane == at ? 0u : key);
+      if (lane == 0) L.cmax[c] = rest;
+      rx = exact;
+      return c * 64 + at;
+    }
     if (lane == 0) L.cmax[c] = exact;  // the bound was stale: lower it, retry
     ss_wave_sync();
   }
@@ -206,15 +217,17 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
         // single pops, by this wave alone, while no vertex is at the cap
         int32_t stamp = L.stamp;
         bool done = false;
-        while (true) {
+        ss_wave_sync();
+        bool crossed = L.cap_head != L.cap_tail;  // the batch relax filled the queue
+        while (!crossed) {
           ss_wave_sync();
-          if (L.cap_head != L.cap_tail) break;
           int32_t xl = L.first;
+          uint32_t rx = 0;  // r of the first vertex is 0: nothing is visited yet
           if (xl >= 0) {
             ss_wave_sync();
             if (lane == 0) L.first = -1;
           } else {
-            xl = ss_select<CAP>(L, ng);
+            xl = ss_select<CAP>(L, ng, rx);
           }
           if (xl < 0) { done = true; break; }
           ++stamp;
@@ -224,15 +237,15 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           }
           ss_wave_sync();
           const int64_t e0 = A.rp[v0 + xl], e1 = A.rp[v0 + xl + 1];
-          int64_t rows = 0, internal = 0;
+          const int64_t dx = A.cdeg[v0 + xl];
+          int64_t rows = 0, internal = 0;  // unused here: the degree comes from cdeg
           for (int64_t base = e0; base < e1; base += 64) {
             const int64_t e = base + lane;
             const bool ok = e < e1;
-            ss_relax<CAP>(L, A, v0, lam, ok, xl, ok ? A.col[e] - v0 : 0, ok ? A.w[e] : 0, rows, internal);
+            crossed |= ss_relax<CAP>(L, A, v0, lam, ok, xl, ok ? A.col[e] - v0 : 0, ok ? A.w[e] : 0, rows, internal);
           }
-          rows = wave_sum_i64(rows);
           if (lane == 0) {
-            alpha += rows - 2 * (int64_t)L.r[xl];
+            alpha += dx - 2 * (int64_t)rx;
             visited += 1;
             if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = stamp; }
             ss_visited(L, xl);

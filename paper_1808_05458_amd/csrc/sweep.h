@@ -78,10 +78,45 @@ struct SweepArgs {
   int32_t g;         // the graph
 };
 
+// The kernels that read their arguments from the per-graph argument array
+// work on this view of them, with every array typed as global memory.
+struct SweepDev {
+  const MC_GLOBAL int64_t* rp;
+  const MC_GLOBAL int32_t* col;
+  const MC_GLOBAL int32_t* w;
+  const MC_GLOBAL int64_t* cdeg;
+  MC_GLOBAL int32_t* parent;
+  MC_GLOBAL int32_t* r;
+  MC_GLOBAL int32_t* step;
+  MC_GLOBAL int32_t* capq;
+  MC_GLOBAL int32_t* capx;
+  MC_GLOBAL int2* pool;
+  int64_t pool_cap;
+  MC_GLOBAL int32_t* seg;
+  MC_GLOBAL SweepCtl* ctl;
+  int32_t v0, ng;
+  int64_t lam;
+  int32_t shift, nwords, nb, big;
+  int64_t big_entries;
+  int32_t start, g;
+};
+
+__device__ __forceinline__ SweepDev dev_view(const SweepArgs& a) {
+  return SweepDev{(const MC_GLOBAL int64_t*)a.rp, (const MC_GLOBAL int32_t*)a.col, (const MC_GLOBAL int32_t*)a.w,
+                  (const MC_GLOBAL int64_t*)a.cdeg, (MC_GLOBAL int32_t*)a.parent, (MC_GLOBAL int32_t*)a.r,
+                  (MC_GLOBAL int32_t*)a.step, (MC_GLOBAL int32_t*)a.capq, (MC_GLOBAL int32_t*)a.capx,
+                  (MC_GLOBAL int2*)a.pool, a.pool_cap, (MC_GLOBAL int32_t*)a.seg, (MC_GLOBAL SweepCtl*)a.ctl,
+                  a.v0, a.ng, a.lam, a.shift, a.nwords, a.nb, a.big, a.big_entries, a.start, a.g};
+}
+
+__device__ __forceinline__ uint64_t* pool_word(int2* p) { return (uint64_t*)p; }
+__device__ __forceinline__ MC_GLOBAL uint64_t* pool_word(MC_GLOBAL int2* p) { return (MC_GLOBAL uint64_t*)p; }
+
 // The queue and FIFO bookkeeping, addressed through generic pointers: the
 // persistent workgroup works on LDS copies, the grid-wide kernels on the
 // global SweepCtl.
-constexpr int SWEEP_RING = 1024;  // newest capped-FIFO entries mirrored in LDS
+constexpr int SWEEP_RING = 1024;   // newest capped-FIFO entries mirrored in LDS
+constexpr int POOL_RING = 2048;    // newest bucket entries mirrored in LDS
 
 struct SweepQ {
   int32_t* cap_head;
@@ -91,42 +126,72 @@ struct SweepQ {
   int32_t* head;
   int32_t* seg_cur;
   int32_t* seg_end;
-  int32_t* ring;  // LDS mirror of capq[i] at i % SWEEP_RING (persistent kernel only)
+  // persistent kernel only (nullptr elsewhere): LDS mirrors of capq[i] and
+  // of its row bounds at i % SWEEP_RING
+  int32_t* ring;
+  int64_t* ring_a;
+  int64_t* ring_b;
+  // wave-0 steps of the persistent kernel only: LDS mirror of pool[i] at
+  // i % POOL_RING, valid for i >= max(*pring_lo, *pool_next - POOL_RING)
+  uint64_t* pring;
+  int64_t* pring_lo;
 };
 
 __device__ __forceinline__ SweepQ global_q(SweepCtl* c) {
-  return SweepQ{&c->cap_head, &c->cap_tail, &c->pool_next, c->bitmap, c->head, c->seg_cur, c->seg_end, nullptr};
+  return SweepQ{&c->cap_head, &c->cap_tail, &c->pool_next, c->bitmap, c->head, c->seg_cur, c->seg_end,
+                nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
-__device__ __forceinline__ int2 pool_at(const SweepArgs& A, int32_t idx) {
-  uint64_t u = ld_relaxed((const uint64_t*)(A.pool + idx));
+__device__ __forceinline__ bool pool_mirrored(const SweepQ& q, int64_t idx) {
+  if (!q.pring) return false;
+  const int64_t lo = *q.pool_next - POOL_RING;
+  return idx >= *q.pring_lo && idx >= lo;
+}
+
+template <class SA>
+__device__ __forceinline__ int2 pool_at(const SA& A, const SweepQ& q, int32_t idx) {
+  const uint64_t u = pool_mirrored(q, idx) ? q.pring[idx & (POOL_RING - 1)] : ld_relaxed(pool_word(A.pool + idx));
   return make_int2((int32_t)(uint32_t)u, (int32_t)(u >> 32));
 }
 
-__device__ __forceinline__ void pool_put(const SweepArgs& A, int64_t idx, int32_t v, int32_t next) {
-  st_relaxed((uint64_t*)(A.pool + idx), ((uint64_t)(uint32_t)next << 32) | (uint32_t)v);
+template <class SA>
+__device__ __forceinline__ void pool_put(const SA& A, const SweepQ& q, int64_t idx, int32_t v, int32_t next) {
+  const uint64_t u = ((uint64_t)(uint32_t)next << 32) | (uint32_t)v;
+  st_relaxed(pool_word(A.pool + idx), u);
+  if (pool_mirrored(q, idx)) q.pring[idx & (POOL_RING - 1)] = u;
 }
 
 // Relax edge (x, y, c) while batch `stamp` is being visited.  Every lane of
 // the wave calls this (act = false for idle lanes) so that queue and counter
 // updates are aggregated per wave.  Returns the weight to add to the
 // batch-internal sum (edge inside the batch).
-template <bool PUSH = true>
-__device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ& q, int32_t x, int32_t y,
+//
+// member: y is known to be in the batch (the caller compared it with the
+// batch's vertices), so neither its stamp nor its r is touched.
+template <bool PUSH = true, class SA>
+__device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int32_t x, int32_t y,
                                                int32_t c, int32_t stamp, bool act, int32_t* wbuf = nullptr,
-                                               int32_t* wcnt = nullptr) {
+                                               int32_t* wcnt = nullptr, bool member = false) {
   const int lane = lane_id();
   int64_t internal = 0;
   bool cross = false, push = false;
-  int64_t nw = 0;
+  int64_t nw = 0, ya = 0, yb = 0;
   if (act && y == x) act = false;
-  if (act && PUSH) {
-    // the sequential kernel is latency-bound: the visit stamp and the add
-    // are independent, so both are in flight at once.  A visited vertex's r
-    // is never read again (alpha takes r(x) when x is marked, before any row
-    // of its batch is relaxed), so adding to it is harmless
+  if (act && PUSH && member) {
+    internal = c;
+  } else if (act && PUSH) {
+    // the sequential kernel is latency-bound: the visit stamp, the add and
+    // the row bounds (kept with the FIFO entry if y crosses) are independent,
+    // so all are in flight at once.  A visited vertex's r is never read
+    // again (alpha takes r(x) of a batch vertex before its batch's rows add
+    // to it, or the caller keeps batch vertices out of the adds), so adding
+    // to it is harmless
     const int32_t vs = ld_relaxed(A.step + y);
-    const int32_t old = atomicAdd(A.r + y, c);
+    const int32_t old = atomic_add(A.r + y, c);
+    if (q.ring_a) {
+      ya = A.rp[y];
+      yb = A.rp[y + 1];
+    }
     if (vs != 0) {
       if (vs == stamp) internal = c;
     } else {
@@ -140,7 +205,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
     if (vs != 0) {
       if (vs == stamp) internal = c;
     } else {
-      const int32_t old = atomicAdd(A.r + y, c);
+      const int32_t old = atomic_add(A.r + y, c);
       nw = (int64_t)old + c;
       cross = old < A.lam && A.lam <= nw;
     }
@@ -167,7 +232,11 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
       const int32_t at = base + popc64(cm & lanemask_lt());
       A.capq[at] = y;
       A.capx[at] = x;
-      if (q.ring) q.ring[at & (SWEEP_RING - 1)] = y;
+      if (q.ring) {
+        q.ring[at & (SWEEP_RING - 1)] = y;
+        q.ring_a[at & (SWEEP_RING - 1)] = ya;
+        q.ring_b[at & (SWEEP_RING - 1)] = yb;
+      }
     }
   }
   // pushes below the cap: one pool reservation per wave, then one list
@@ -200,7 +269,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
       }
       old_head = shfl(old_head, hi);
       const int64_t prev_idx = shfl(idx, prev_lane);
-      if (mine && idx < A.pool_cap) pool_put(A, idx, y, lower ? (int32_t)prev_idx : old_head);
+      if (mine && idx < A.pool_cap) pool_put(A, q, idx, y, lower ? (int32_t)prev_idx : old_head);
     }
   }
   return internal;
@@ -208,7 +277,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SweepArgs& A, const SweepQ&
 
 // Reset each graph's range and queue: graph blockIdx.y of the argument array.
 __global__ void k_sweep_init(const SweepArgs* args) {
-  const SweepArgs A = args[blockIdx.y];
+  const SweepDev A = dev_view(args[blockIdx.y]);
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < A.ng; i += nth) {
     A.r[A.v0 + i] = 0;
@@ -221,7 +290,7 @@ __global__ void k_sweep_init(const SweepArgs* args) {
   }
   for (int64_t i = tid; i < SWEEP_BUCKETS / 64; i += nth) A.ctl->bitmap[i] = 0;
   if (tid == 0) {
-    SweepCtl* c = A.ctl;
+    MC_GLOBAL SweepCtl* c = A.ctl;
     c->cap_head = c->cap_tail = 0;
     c->visited = 0;
     c->step = 0;
@@ -239,8 +308,8 @@ __global__ void k_sweep_init(const SweepArgs* args) {
 // The start of every graph in bucket 0 (thread i: graph i of k).
 __global__ void k_sweep_seed(const SweepArgs* args, int32_t k) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
-    const SweepArgs& A = args[i];
-    A.pool[0] = make_int2(A.start, -1);  // (vertex, next)
+    const SweepDev A = dev_view(args[i]);
+    *pool_word(A.pool) = (~0ull << 32) | (uint32_t)A.start;  // (vertex, next = -1)
     A.ctl->head[0] = 0;
     A.ctl->bitmap[0] = 1ull;
   }
@@ -256,19 +325,41 @@ __device__ __forceinline__ void sweep_close_batch(SweepCtl* c, int32_t ng, int64
   }
 }
 
-__device__ __forceinline__ bool live_in_bucket(const SweepArgs& A, int32_t v, int32_t b, int32_t& key) {
-  if (v < 0 || ld_relaxed(A.step + v) != 0) return false;  // visited
+// A bucket entry is live if its vertex is unvisited and its r still maps to
+// the bucket.  Both loads are issued together.
+template <class SA>
+__device__ __forceinline__ bool live_in_bucket(const SA& A, int32_t v, int32_t b, int32_t& key) {
+  if (v < 0) return false;
+  const int32_t vs = ld_relaxed(A.step + v);
   key = ld_relaxed(A.r + v);
-  return (int64_t)key < A.lam && (key >> A.shift) == b;
+  return vs == 0 && (int64_t)key < A.lam && (key >> A.shift) == b;
+}
+
+// What the single-pop step needs of the popped vertex besides its id: its
+// row bounds, its weighted degree and its r (the key it was popped with).
+struct PopRow {
+  int64_t ra, rb, cd;
+  int32_t key;
+};
+
+template <class SA>
+__device__ __forceinline__ void pop_row_load(const SA& A, int32_t x, int32_t key, PopRow& pr) {
+  pr.ra = A.rp[x];
+  pr.rb = A.rp[x + 1];
+  pr.cd = A.cdeg[x];
+  pr.key = key;
 }
 
 // Single pop by wave 0: the highest non-empty bucket (bitmap words read by
 // the lanes, one each); in it, the recent-push list (lane 0 walks it,
-// dropping stale entries) and then the rebuilt segment (64 entries per read,
-// cursor only moves forward).  With one key per bucket the first live entry
-// is a maximum; with wider buckets the largest live key of the whole bucket
-// is taken (the segment entry is then tombstoned).  -1: queue empty.
-__device__ int32_t sweep_pop_wave0(const SweepArgs& A, const SweepQ& q) {
+// dropping stale entries, with the row of each candidate loaded alongside
+// its liveness) and then the rebuilt segment (64 entries per read, cursor
+// only moves forward).  With one key per bucket the first live entry is a
+// maximum; with wider buckets the largest live key of the whole bucket is
+// taken (the segment entry is then tombstoned).  -1: queue empty.  On
+// success pr describes the vertex (the same in every lane).
+template <class SA>
+__device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
   const int lane = lane_id();
   while (true) {
     uint64_t word = lane < A.nwords ? ld_relaxed(&q.bitmap[lane]) : 0ull;
@@ -282,32 +373,46 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A, const SweepQ& q) {
       if (lane == 0) {
         int32_t idx = ld_relaxed(&q.head[b]);
         while (idx >= 0) {
-          int2 e = pool_at(A, idx);
+          int2 e = pool_at(A, q, idx);
           idx = e.y;
-          int32_t k;
-          if (live_in_bucket(A, e.x, b, k)) { x = e.x; break; }
+          int32_t k = 0;
+          PopRow cand;
+          const bool live = live_in_bucket(A, e.x, b, k);
+          if (e.x >= 0) pop_row_load(A, e.x, k, cand);  // in flight with the liveness loads
+          if (live) { x = e.x; pr = cand; break; }
         }
         st_relaxed(&q.head[b], idx);
       }
       x = shfl(x, 0);
-      if (x >= 0) return x;
+      if (x >= 0) {
+        pr.ra = shfl(pr.ra, 0);
+        pr.rb = shfl(pr.rb, 0);
+        pr.cd = shfl(pr.cd, 0);
+        pr.key = shfl(pr.key, 0);
+        return x;
+      }
       int32_t cur = ld_relaxed(&q.seg_cur[b]);
       const int32_t end = ld_relaxed(&q.seg_end[b]);
+      int32_t key = 0;
       while (cur < end) {
         const int32_t i = cur + lane;
         const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
-        int32_t k;
+        int32_t k = 0;
         const uint64_t ok = ballot(live_in_bucket(A, v, b, k));
         if (ok) {
           const int first = __builtin_ctzll(ok);
           x = shfl(v, first);
+          key = shfl(k, first);
           cur += first + 1;
           break;
         }
         cur += 64;
       }
       if (lane == 0) st_relaxed(&q.seg_cur[b], cur < end ? cur : end);
-      if (x >= 0) return x;
+      if (x >= 0) {
+        pop_row_load(A, x, key, pr);
+        return x;
+      }
     } else {
       // wide bucket: exact maximum over the list and the segment
       int64_t best_key = -1;
@@ -315,11 +420,11 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A, const SweepQ& q) {
       if (lane == 0) {
         int32_t idx = ld_relaxed(&q.head[b]), prev = -1;
         while (idx >= 0) {
-          int2 e = pool_at(A, idx);
-          int32_t k;
+          int2 e = pool_at(A, q, idx);
+          int32_t k = 0;
           if (!live_in_bucket(A, e.x, b, k)) {
             if (prev < 0) st_relaxed(&q.head[b], e.y);
-            else pool_put(A, prev, pool_at(A, prev).x, e.y);
+            else pool_put(A, q, prev, pool_at(A, q, prev).x, e.y);
           } else {
             if (k > best_key) { best_key = k; best_v = e.x; best_idx = idx; best_prev = prev; }
             prev = idx;
@@ -336,24 +441,30 @@ __device__ int32_t sweep_pop_wave0(const SweepArgs& A, const SweepQ& q) {
       for (int32_t base = cur0; base < end; base += 64) {
         const int32_t i = base + lane;
         const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
-        int32_t k;
+        int32_t k = 0;
         if (live_in_bucket(A, v, b, k) && k > seg_best) { seg_best = k; seg_pos = i; }
       }
       const uint64_t packed =
           wave_max_u64(seg_best < 0 ? 0ull : (((uint64_t)(seg_best + 1) << 32) | (uint32_t)seg_pos));
+      int32_t key = 0;
       if (packed != 0 && (int64_t)(packed >> 32) - 1 > best_key) {
         const int32_t pos = (int32_t)(uint32_t)packed;
         x = ld_relaxed(A.seg + pos);
+        key = (int32_t)(packed >> 32) - 1;
         if (lane == 0) st_relaxed(A.seg + pos, -1);
       } else if (best_v >= 0) {
         x = best_v;
+        key = (int32_t)best_key;
         if (lane == 0) {
-          const int32_t nx = pool_at(A, best_idx).y;
+          const int32_t nx = pool_at(A, q, best_idx).y;
           if (best_prev < 0) st_relaxed(&q.head[b], nx);
-          else pool_put(A, best_prev, pool_at(A, best_prev).x, nx);
+          else pool_put(A, q, best_prev, pool_at(A, q, best_prev).x, nx);
         }
       }
-      if (x >= 0) return x;
+      if (x >= 0) {
+        pop_row_load(A, x, key, pr);
+        return x;
+      }
       if (lane == 0) {
         st_relaxed(&q.head[b], -1);
         st_relaxed(&q.seg_cur[b], end);
@@ -369,17 +480,24 @@ constexpr int64_t FAST_DEG = 2048;  // single pops with rows up to this run on w
 
 // Relax the rows [ra, rb) of `cnt` batch vertices held by lanes 0..cnt-1 of
 // `xs` with one wave; returns the batch-internal weight of this wave's lanes.
-__device__ __forceinline__ int64_t wave_relax_known(const SweepArgs& A, const SweepQ& q, int32_t xs, int64_t ra,
+// Batch membership is decided by comparing with xs, so the batch's visit
+// stamps need not be visible yet.
+template <class SA>
+__device__ __forceinline__ int64_t wave_relax_known(const SA& A, const SweepQ& q, int32_t xs, int64_t ra,
                                                     int64_t rb, int cnt, int32_t stamp) {
   const int lane = lane_id();
   int64_t internal = 0;
   for (int j = 0; j < cnt; ++j) {
-    const int32_t x = shfl(xs, j);
-    const int64_t e0 = shfl(ra, j), e1 = shfl(rb, j);
+    const int32_t x = __builtin_amdgcn_readlane(xs, j);
+    const int64_t e0 = readlane_i64(ra, j), e1 = readlane_i64(rb, j);
     for (int64_t base = e0; base < e1; base += 64) {
       const int64_t e = base + lane;
       const bool act = e < e1;
-      internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+      const int32_t y = act ? A.col[e] : 0;
+      const int32_t c = act ? A.w[e] : 0;
+      bool member = false;  // with one vertex, y == x is a self-loop, skipped anyway
+      for (int k = 0; k < cnt && cnt > 1; ++k) member |= y == __builtin_amdgcn_readlane(xs, k);
+      internal += sweep_relax(A, q, x, y, c, stamp, act, nullptr, nullptr, member);
     }
   }
   return internal;
@@ -395,7 +513,7 @@ enum : int32_t { CMD_EXIT_DONE = 0, CMD_BATCH = 1, CMD_EXIT_BIG = 2, CMD_SINGLE 
 
 __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* args, const int32_t* run) {
   // one workgroup per graph still running: graph run[blockIdx.x]
-  const SweepArgs A = args[run[blockIdx.x]];
+  const SweepDev A = dev_view(args[run[blockIdx.x]]);
   __shared__ int32_t sh_x, sh_cmd, sh_h, sh_t, sh_stamp;
   // a wide batch chunk: its vertices, row starts and entry offsets
   __shared__ int32_t sh_bx[SWEEP_THREADS], sh_boff[SWEEP_THREADS + 1], sh_wtot[SWEEP_THREADS / 64];
@@ -407,7 +525,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
   __shared__ int32_t l_cap_head, l_cap_tail;
   __shared__ int64_t l_pool_next;
   __shared__ int32_t l_ring[SWEEP_RING];
-  SweepCtl* c = A.ctl;
+  __shared__ int64_t l_ring_a[SWEEP_RING], l_ring_b[SWEEP_RING];
+  __shared__ uint64_t l_pring[POOL_RING];
+  __shared__ int64_t l_pring_lo;
+  MC_GLOBAL SweepCtl* c = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int nwaves = SWEEP_THREADS / 64;
   for (int i = threadIdx.x; i < A.nb; i += SWEEP_THREADS) {
@@ -423,6 +544,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     l_cap_head = c->cap_head;
     l_cap_tail = c->cap_tail;
     l_pool_next = c->pool_next;
+    l_pring_lo = c->pool_next;  // entries from before this launch are not mirrored
     step = c->step;
     visited = c->visited;
     alpha = c->alpha;
@@ -432,11 +554,26 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     batches = c->batches;
   }
   __syncthreads();
-  const SweepQ q{&l_cap_head, &l_cap_tail, &l_pool_next, l_bitmap, l_head, l_cur, l_end, l_ring};
+  // q: steps shared by all waves; qf: wave-0 steps, which also mirror new
+  // bucket entries in LDS (only one wave pushes there)
+  const SweepQ q{&l_cap_head, &l_cap_tail, &l_pool_next, l_bitmap, l_head, l_cur, l_end,
+                 l_ring, l_ring_a, l_ring_b, nullptr, nullptr};
+  SweepQ qf = q;
+  qf.pring = l_pring;
+  qf.pring_lo = &l_pring_lo;
   // FIFO entries appended before this launch are not in the ring
   const int32_t ring_lo = ld_relaxed(&l_cap_tail);
-  auto fifo_at = [&](int32_t i, int32_t tail) -> int32_t {
-    return (i >= ring_lo && i >= tail - SWEEP_RING) ? l_ring[i & (SWEEP_RING - 1)] : ld_relaxed(A.capq + i);
+  // FIFO entry i (below tail) and its row bounds
+  auto fifo_row = [&](int32_t i, int32_t tail, int64_t& a, int64_t& b) -> int32_t {
+    if (i >= ring_lo && i >= tail - SWEEP_RING) {
+      a = l_ring_a[i & (SWEEP_RING - 1)];
+      b = l_ring_b[i & (SWEEP_RING - 1)];
+      return l_ring[i & (SWEEP_RING - 1)];
+    }
+    const int32_t x = ld_relaxed(A.capq + i);
+    a = A.rp[x];
+    b = A.rp[x + 1];
+    return x;
   };
   auto close = [&](int64_t sum, int64_t internal, int32_t size, int32_t stamp) {
     alpha += sum - internal;
@@ -463,30 +600,31 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           int64_t entries = 0, ra = 0, rb = 0;
           int32_t xs = -1;
           for (int32_t i = lane; i < size; i += 64) {
-            const int32_t x = fifo_at(h + i, t);
-            const int64_t a = A.rp[x], b = A.rp[x + 1];
+            int64_t a, b;
+            const int32_t x = fifo_row(h + i, t, a, b);
             entries += b - a;
             if (i == lane) { xs = x; ra = a; rb = b; }
           }
-          entries = wave_sum_i64(entries);
+          entries = wave_sum_i64_dpp(entries);
           if (entries > A.big_entries) { cmd = CMD_EXIT_BIG; break; }
           if (size > FAST_BATCH || entries > FAST_DEG) {
             if (lane == 0) { sh_h = h; sh_t = t; sh_stamp = stamp; step = stamp; batches += 1; }
             cmd = CMD_BATCH;
             break;
           }
-          int64_t sum = 0;
-          if (lane < size) {
-            st_relaxed(A.step + xs, stamp);
-            sum = A.cdeg[xs] - 2 * (int64_t)ld_relaxed(A.r + xs);
-          }
-          // with more than one vertex the marks must be visible before the
-          // rows are relaxed (edges inside the batch are recognised by their
-          // stamp); a lone vertex has no such edge (self-loops are skipped)
-          if (size > 1) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-          int64_t internal = wave_relax_known(A, q, xs, ra, rb, size, stamp);
-          sum = wave_sum_i64(sum);
-          internal = wave_sum_i64(internal);
+          // mark; the batch's own edges are found by comparing with xs, and
+          // its r values are read while the rows are relaxed (no add reaches
+          // a batch vertex in this step)
+          // (loads outside any branch: a load inside a branch is waited for
+          // at the branch's end)
+          const int32_t xq = lane < size ? xs : __builtin_amdgcn_readlane(xs, 0);
+          const int64_t cd = A.cdeg[xq];
+          const int32_t rx = ld_relaxed(A.r + xq);
+          if (lane < size) st_relaxed(A.step + xs, stamp);
+          int64_t internal = wave_relax_known(A, qf, xs, ra, rb, size, stamp);
+          int64_t sum = lane < size ? cd - 2 * (int64_t)rx : 0;
+          sum = wave_sum_i64_dpp(sum);
+          internal = wave_sum_i64_dpp(internal);
           if (lane == 0) {
             step = stamp;
             batches += 1;
@@ -495,14 +633,15 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         } else {
-          const int32_t x = sweep_pop_wave0(A, q);
+          PopRow pr;
+          const int32_t x = sweep_pop_wave0(A, qf, pr);
           if (x < 0) { cmd = CMD_EXIT_DONE; break; }
-          const int64_t ra = A.rp[x], rb = A.rp[x + 1];
+          const int64_t ra = pr.ra, rb = pr.rb;
           const int64_t deg = rb - ra;
           int64_t sum = 0;
           if (lane == 0) {
             st_relaxed(A.step + x, stamp);
-            sum = A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
+            sum = pr.cd - 2 * (int64_t)pr.key;
           }
           if (deg > FAST_DEG) {
             if (lane == 0) { sh_x = x; sh_stamp = stamp; step = stamp; singles += 1; sh_sum[0] = sum; }
@@ -510,8 +649,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
             break;
           }
           // a single vertex has no edge inside its batch (self-loops skipped)
-          int64_t internal = wave_relax_known(A, q, x, ra, rb, 1, stamp);
-          internal = wave_sum_i64(internal);
+          int64_t internal = wave_relax_known(A, qf, x, ra, rb, 1, stamp);
+          internal = wave_sum_i64_dpp(internal);
           if (lane == 0) {
             step = stamp;
             singles += 1;
@@ -615,6 +754,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
       for (int i = 0; i < nwaves; ++i) { s2 += sh_sum[i]; in += sh_int[i]; }
       if (cmd == CMD_BATCH) *q.cap_head = sh_t;
       close(s2, in, size, stamp);
+      l_pring_lo = l_pool_next;  // the bucket entries of a shared step are in global memory only
     }
     __threadfence_block();
     __syncthreads();
@@ -644,7 +784,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
 // The crossing edges found by the sweeps, united after them: (capx[i],
 // capq[i]) of graph blockIdx.y.
 __global__ void k_sweep_unite(const SweepArgs* args) {
-  const SweepArgs& A = args[blockIdx.y];
+  const SweepDev A = dev_view(args[blockIdx.y]);
   const int32_t n = A.ctl->cap_tail;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     uf_union(A.parent, A.capx[i], A.capq[i]);
@@ -657,7 +797,7 @@ struct SweepStatus {
 };
 __global__ void k_sweep_status(const SweepArgs* args, const int32_t* run, int32_t k, SweepStatus* out) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
-    const SweepCtl* c = args[run[i]].ctl;
+    const MC_GLOBAL SweepCtl* c = (const MC_GLOBAL SweepCtl*)args[run[i]].ctl;
     out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, 0};
   }
 }
