@@ -135,11 +135,15 @@ struct SweepQ {
   // i % POOL_RING, valid for i >= max(*pring_lo, *pool_next - POOL_RING)
   uint64_t* pring;
   int64_t* pring_lo;
+  // wave-0 steps only: the last 64-entry chunk of a rebuilt segment read
+  // from global memory (sc_hdr: bucket or -1, first index)
+  int32_t* sc_v;
+  int32_t* sc_hdr;
 };
 
 __device__ __forceinline__ SweepQ global_q(SweepCtl* c) {
   return SweepQ{&c->cap_head, &c->cap_tail, &c->pool_next, c->bitmap, c->head, c->seg_cur, c->seg_end,
-                nullptr, nullptr, nullptr, nullptr, nullptr};
+                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 __device__ __forceinline__ bool pool_mirrored(const SweepQ& q, int64_t idx) {
@@ -378,7 +382,7 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
           int32_t k = 0;
           PopRow cand;
           const bool live = live_in_bucket(A, e.x, b, k);
-          if (e.x >= 0) pop_row_load(A, e.x, k, cand);  // in flight with the liveness loads
+          pop_row_load(A, e.x >= 0 ? e.x : A.start, k, cand);  // in flight with the liveness loads
           if (live) { x = e.x; pr = cand; break; }
         }
         st_relaxed(&q.head[b], idx);
@@ -391,28 +395,45 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
         pr.key = shfl(pr.key, 0);
         return x;
       }
+      // the segment, from the cursor on, 64 entries per pass (a chunk read
+      // from global memory stays in LDS for the next pops); every lane
+      // loads its entry's row with the liveness
       int32_t cur = ld_relaxed(&q.seg_cur[b]);
       const int32_t end = ld_relaxed(&q.seg_end[b]);
-      int32_t key = 0;
       while (cur < end) {
+        const bool cached = q.sc_v && q.sc_hdr[0] == b && cur >= q.sc_hdr[1] && cur < q.sc_hdr[1] + 64;
+        const int32_t base = cached ? q.sc_hdr[1] : cur;
+        const int32_t lim = min(base + 64, end);
         const int32_t i = cur + lane;
-        const int32_t v = i < end ? ld_relaxed(A.seg + i) : -1;
+        int32_t v = -1;
+        if (cached) {
+          if (i < lim) v = q.sc_v[i - base];
+        } else {
+          if (i < lim) v = ld_relaxed(A.seg + i);
+          if (q.sc_v) {
+            q.sc_v[lane] = v;
+            if (lane == 0) { q.sc_hdr[0] = b; q.sc_hdr[1] = cur; }
+          }
+        }
         int32_t k = 0;
-        const uint64_t ok = ballot(live_in_bucket(A, v, b, k));
+        PopRow cand{0, 0, 0, 0};
+        const bool live = live_in_bucket(A, v, b, k);
+        pop_row_load(A, v >= 0 ? v : A.start, k, cand);  // no branch: no wait at its end
+        const uint64_t ok = ballot(live);
         if (ok) {
           const int first = __builtin_ctzll(ok);
-          x = shfl(v, first);
-          key = shfl(k, first);
+          x = __builtin_amdgcn_readlane(v, first);
+          pr.ra = readlane_i64(cand.ra, first);
+          pr.rb = readlane_i64(cand.rb, first);
+          pr.cd = readlane_i64(cand.cd, first);
+          pr.key = __builtin_amdgcn_readlane(cand.key, first);
           cur += first + 1;
           break;
         }
-        cur += 64;
+        cur = lim;
       }
       if (lane == 0) st_relaxed(&q.seg_cur[b], cur < end ? cur : end);
-      if (x >= 0) {
-        pop_row_load(A, x, key, pr);
-        return x;
-      }
+      if (x >= 0) return x;
     } else {
       // wide bucket: exact maximum over the list and the segment
       int64_t best_key = -1;
@@ -528,6 +549,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
   __shared__ int64_t l_ring_a[SWEEP_RING], l_ring_b[SWEEP_RING];
   __shared__ uint64_t l_pring[POOL_RING];
   __shared__ int64_t l_pring_lo;
+  __shared__ int32_t l_sc_v[64], l_sc_hdr[2];
   MC_GLOBAL SweepCtl* c = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int nwaves = SWEEP_THREADS / 64;
@@ -545,6 +567,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     l_cap_tail = c->cap_tail;
     l_pool_next = c->pool_next;
     l_pring_lo = c->pool_next;  // entries from before this launch are not mirrored
+    l_sc_hdr[0] = -1;           // segments were rebuilt since the last launch
     step = c->step;
     visited = c->visited;
     alpha = c->alpha;
@@ -557,10 +580,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
   // q: steps shared by all waves; qf: wave-0 steps, which also mirror new
   // bucket entries in LDS (only one wave pushes there)
   const SweepQ q{&l_cap_head, &l_cap_tail, &l_pool_next, l_bitmap, l_head, l_cur, l_end,
-                 l_ring, l_ring_a, l_ring_b, nullptr, nullptr};
+                 l_ring, l_ring_a, l_ring_b, nullptr, nullptr, nullptr, nullptr};
   SweepQ qf = q;
   qf.pring = l_pring;
   qf.pring_lo = &l_pring_lo;
+  qf.sc_v = l_sc_v;
+  qf.sc_hdr = l_sc_hdr;
   // FIFO entries appended before this launch are not in the ring
   const int32_t ring_lo = ld_relaxed(&l_cap_tail);
   // FIFO entry i (below tail) and its row bounds
