@@ -143,7 +143,7 @@ struct Workspace {
   int64_t capN = 0, capE = 0, capG = 0;
   std::vector<void*> allocs;
   // vertex arrays
-  int32_t *gid[2], *parent, *lab, *claim, *step, *fb_r, *fb_step, *capq, *capx, *sw_seg, *newid,
+  int32_t *gid[2], *parent, *lab, *claim, *step, *capq, *capx, *sw_seg, *newid,
       *map, *ogid;
   SweepCtl* sweep;                  // MAX_SWEEPS queues
   SweepCtl* sweep_host = nullptr;   // pinned, for single-field readbacks
@@ -155,6 +155,7 @@ struct Workspace {
   SweepStatus* sw_status_host = nullptr;
   int64_t* sw_info;
   int64_t *rp, *cdeg;
+  uint64_t* fb_rs;  // sweeps: per vertex (r, visit stamp)
   // entry arrays
   int32_t *src, *col, *w;
   uint64_t *keys, *keys_alt;
@@ -210,7 +211,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
   size_t b = 0;
-  b += align_up((N + 1) * 4) * 17 + align_up((G + 1) * 40);
+  b += align_up((N + 1) * 4) * 15 + align_up((N + 1) * 8) + align_up((G + 1) * 40);
   b += align_up(sizeof(SweepCtl) * MAX_SWEEPS) + align_up(sizeof(SweepArgs) * MAX_SWEEPS) +
        2 * align_up(sizeof(SweepStatus) * MAX_SWEEPS);
   b += align_up((N + 2) * 8) * 2;
@@ -258,8 +259,7 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.lab, (N + 1) * 4);
   ALLOC(ws.claim, (N + 1) * 4);
   ALLOC(ws.step, (N + 1) * 4);
-  ALLOC(ws.fb_r, (N + 1) * 4);
-  ALLOC(ws.fb_step, (N + 1) * 4);
+  ALLOC(ws.fb_rs, (N + 1) * 8);
   ALLOC(ws.newid, (N + 1) * 4);
   ALLOC(ws.map, (N + 1) * 4);
   ALLOC(ws.ogid, (N + 1) * 4);
@@ -494,7 +494,7 @@ struct Solver {
         const int32_t v0 = (int32_t)info[5 * q], ng = (int32_t)info[5 * q + 1];
         const int64_t lam = info[5 * q + 2], e0 = info[5 * q + 3], e1 = info[5 * q + 4];
         if (lam <= 0 || ng < 2) continue;
-        SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_r, ws.fb_step, ws.capq + v0, ws.capx + v0,
+        SweepArgs A{rp, col, w, ws.cdeg, ws.parent, ws.fb_rs, ws.capq + v0, ws.capx + v0,
                     (int2*)ws.keys_alt + e0 + glist[q], e1 - e0 + 1, ws.sw_seg + v0, ws.sweep + k, v0, ng, lam,
                     0, 1, 1, 0};
         const int lb = bitlen((uint64_t)(lam - 1));
@@ -556,8 +556,15 @@ struct Solver {
             // gather and the r read-modify-write of each neighbour (12 B), and
             // per batch vertex its FIFO slot and row bounds (20 B)
             TimedScope t("sweep_relax", (double)deg_sum * 20 + (double)bsz * 20);
-            hipLaunchKernelGGL(k_sweep_big_relax, dim3(grid_for(bsz * 64, TB, num_cu * 32)), dim3(TB), 0, s, A,
-                               bh, bt);
+            // prefix sums of the batch's row lengths (ws.keys and ws.vals are
+            // free until the contraction) and each entry tile's first row
+            int64_t* off = (int64_t*)ws.keys;
+            int32_t* tile_row = ws.vals;
+            exclusive_scan<int64_t, BatchDeg>(BatchDeg{A.capq + bh, rp}, bsz, off, off + bsz, ws.tmp, s);
+            hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
+                               (int32_t)bsz, tile_row);
+            hipLaunchKernelGGL(k_sweep_big_relax, dim3(num_cu * 8), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
+                               tile_row);
           }
           hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
           {
@@ -710,7 +717,7 @@ struct Solver {
     const int32_t* gid = gid_in;
     int next = 0;  // level-graph buffer the next contraction writes
     SideArgs sa{N, ws.ogid, V.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
-                ws.fb_step, ws.parent, ws.root0, side, REC_DEG};
+                ws.fb_rs, ws.parent, ws.root0, side, REC_DEG};
     // contract the current graph by ws.lab (ws.nnew holds the new per-graph
     // counts), update the bounds and sides, and move to the new graph
     auto step = [&](int32_t n_next, int end_of_level, int last_level) -> int {
@@ -887,7 +894,7 @@ struct Solver {
     if (want_side) {
       TimedScope t("side", (double)N * 13);
       SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
-                  ws.fb_step, ws.parent, ws.root0, side, REC_DEG};
+                  ws.fb_rs, ws.parent, ws.root0, side, REC_DEG};
       hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
       sa.want = REC_DISCONNECTED;
       hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
@@ -1031,7 +1038,7 @@ struct Solver {
         // whole small graphs: LDS-resident capped sweeps, one workgroup each,
         // the large-map list first (both lists are ordered largest first)
         SmallSweepArgs SA{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
-                          &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_step, ws.capq, ws.capx, ws.npairs,
+                          &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_rs, ws.capq, ws.capx, ws.npairs,
                           ws.balpha, ws.fb_k, ws.ucount, A.seed};
         {
           TimedScope t("small_sweep", 0.0);
@@ -1097,7 +1104,7 @@ struct Solver {
       if (want_side) {
         TimedScope t("side", (double)N * 21);
         SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
-                    ws.fb_step, ws.parent, ws.root0, side, REC_ALPHA};
+                    ws.fb_rs, ws.parent, ws.root0, side, REC_ALPHA};
         hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
       }
       rc = read_ctl();
@@ -1118,7 +1125,7 @@ struct Solver {
       if (want_side) {
         TimedScope t("side", (double)N * 9);
         SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
-                    ws.fb_step, ws.parent, ws.root0, side, REC_DEG};
+                    ws.fb_rs, ws.parent, ws.root0, side, REC_DEG};
         hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
       }
       rc = read_ctl();

@@ -291,7 +291,7 @@ struct SideArgs {
   const int32_t* rec_k;
   const int32_t* claim;
   const int32_t* step;
-  const int32_t* fb_step;
+  const uint64_t* fb_rs;    // sweeps: visit stamp in the high 32 bits
   const int32_t* parent;    // for REC_DISCONNECTED
   const int32_t* root0;
   uint8_t* side;
@@ -309,7 +309,10 @@ __global__ void k_side(SideArgs A) {
       s = c == A.rec_id[g];
     } else if (t == REC_ALPHA) {
       int32_t sid = A.rec_id[g], k = A.rec_k[g];
-      if (sid == SWEEP_SID) s = A.fb_step[c] >= 1 && A.fb_step[c] <= k;
+      if (sid == SWEEP_SID) {
+        const int32_t st = (int32_t)(A.fb_rs[c] >> 32);
+        s = st >= 1 && st <= k;
+      }
       else s = A.claim[c] == sid && A.step[c] <= k;
     } else if (t == REC_DISCONNECTED) {
       s = A.parent[v] != A.root0[g];

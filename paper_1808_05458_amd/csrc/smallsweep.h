@@ -38,7 +38,7 @@ struct SmallSweepArgs {
   const int32_t* list_b;
   const int32_t* count_b;
   int32_t* work;               // work counter (zeroed by the host)
-  int32_t* fb_step;            // visit stamp per vertex (side materialisation)
+  uint64_t* fb_rs;             // per vertex: visit stamp in the high 32 bits (side)
   int32_t* capq;               // crossing pairs (capx[i], capq[i]) at v0 + i
   int32_t* capx;
   int32_t* npairs;             // per graph: pairs recorded
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
     const int64_t ebase = A.rp[v0];
     for (int i = threadIdx.x; i < ng; i += SS_THREADS) {
       L.r[i] = 0;
-      A.fb_step[v0 + i] = 0;
+      A.fb_rs[v0 + i] = 0;
     }
     for (int i = threadIdx.x; i < (ng + 15) / 16; i += SS_THREADS) L.st[i] = 0;
     for (int c = threadIdx.x; c < SmallSweepLds<CAP>::NC; c += SS_THREADS) L.cmax[c] = 0;
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           ++stamp;
           if (lane == 0) {
             ss_mark(L, xl);
-            A.fb_step[v0 + xl] = stamp;
+            reinterpret_cast<int32_t*>(A.fb_rs + v0 + xl)[1] = stamp;
           }
           ss_wave_sync();
           const int64_t e0 = A.rp[v0 + xl], e1 = A.rp[v0 + xl + 1];
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           for (int k = lane; k < nb; k += 64) {
             const int32_t x = L.capped[b0 + k];
             ss_mark(L, x);
-            A.fb_step[v0 + x] = stamp;
+            reinterpret_cast<int32_t*>(A.fb_rs + v0 + x)[1] = stamp;
             r2 += 2 * (int64_t)L.r[x];
           }
           r2 = wave_sum_i64(r2);

@@ -58,9 +58,10 @@ struct SweepArgs {
   const int32_t* w;
   const int64_t* cdeg;
   int32_t* parent;
-  int32_t* r;        // per vertex
-  int32_t* step;     // visit stamp (batch number), 0 = not visited; a frontier
-                     // vertex is an unvisited one with r > 0 (or the start)
+  uint64_t* rs;      // per vertex: r in the low 32 bits, the visit stamp (batch
+                     // number, 0 = not visited) in the high 32 bits, so one
+                     // access reads both; a frontier vertex is an unvisited
+                     // one with r > 0 (or the start)
   int32_t* capq;     // capped FIFO (each vertex enters at most once)
   int32_t* capx;     // the vertex whose edge made capq[i] cross (united later)
   int2* pool;        // bucket entries (vertex, next)
@@ -86,8 +87,7 @@ struct SweepDev {
   const MC_GLOBAL int32_t* w;
   const MC_GLOBAL int64_t* cdeg;
   MC_GLOBAL int32_t* parent;
-  MC_GLOBAL int32_t* r;
-  MC_GLOBAL int32_t* step;
+  MC_GLOBAL uint64_t* rs;
   MC_GLOBAL int32_t* capq;
   MC_GLOBAL int32_t* capx;
   MC_GLOBAL int2* pool;
@@ -103,11 +103,19 @@ struct SweepDev {
 
 __device__ __forceinline__ SweepDev dev_view(const SweepArgs& a) {
   return SweepDev{(const MC_GLOBAL int64_t*)a.rp, (const MC_GLOBAL int32_t*)a.col, (const MC_GLOBAL int32_t*)a.w,
-                  (const MC_GLOBAL int64_t*)a.cdeg, (MC_GLOBAL int32_t*)a.parent, (MC_GLOBAL int32_t*)a.r,
-                  (MC_GLOBAL int32_t*)a.step, (MC_GLOBAL int32_t*)a.capq, (MC_GLOBAL int32_t*)a.capx,
+                  (const MC_GLOBAL int64_t*)a.cdeg, (MC_GLOBAL int32_t*)a.parent, (MC_GLOBAL uint64_t*)a.rs,
+                  (MC_GLOBAL int32_t*)a.capq, (MC_GLOBAL int32_t*)a.capx,
                   (MC_GLOBAL int2*)a.pool, a.pool_cap, (MC_GLOBAL int32_t*)a.seg, (MC_GLOBAL SweepCtl*)a.ctl,
                   a.v0, a.ng, a.lam, a.shift, a.nwords, a.nb, a.big, a.big_entries, a.start, a.g};
 }
+
+// The packed (r, stamp) word: r never exceeds the vertex's weighted degree
+// (each entry adds to it once), which is at most INT32_MAX, so an add to r
+// never carries into the stamp.
+__device__ __forceinline__ int32_t rs_r(uint64_t u) { return (int32_t)(uint32_t)u; }
+__device__ __forceinline__ int32_t rs_stamp(uint64_t u) { return (int32_t)(u >> 32); }
+__device__ __forceinline__ int32_t* rs_stamp_ptr(uint64_t* p) { return (int32_t*)p + 1; }
+__device__ __forceinline__ MC_GLOBAL int32_t* rs_stamp_ptr(MC_GLOBAL uint64_t* p) { return (MC_GLOBAL int32_t*)p + 1; }
 
 __device__ __forceinline__ uint64_t* pool_word(int2* p) { return (uint64_t*)p; }
 __device__ __forceinline__ MC_GLOBAL uint64_t* pool_word(MC_GLOBAL int2* p) { return (MC_GLOBAL uint64_t*)p; }
@@ -190,8 +198,8 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
     // again (alpha takes r(x) of a batch vertex before its batch's rows add
     // to it, or the caller keeps batch vertices out of the adds), so adding
     // to it is harmless
-    const int32_t vs = ld_relaxed(A.step + y);
-    const int32_t old = atomic_add(A.r + y, c);
+    const uint64_t prev = atomic_add(A.rs + y, (uint64_t)(uint32_t)c);
+    const int32_t vs = rs_stamp(prev), old = rs_r(prev);
     if (q.ring_a) {
       ya = A.rp[y];
       yb = A.rp[y + 1];
@@ -205,11 +213,12 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
     }
   } else if (act) {
     // grid-wide batches are bandwidth-bound: no add for visited vertices
-    const int32_t vs = ld_relaxed(A.step + y);
+    // (the stamps do not change while a grid-wide batch is relaxed)
+    const int32_t vs = rs_stamp(ld_relaxed(A.rs + y));
     if (vs != 0) {
       if (vs == stamp) internal = c;
     } else {
-      const int32_t old = atomic_add(A.r + y, c);
+      const int32_t old = rs_r(atomic_add(A.rs + y, (uint64_t)(uint32_t)c));
       nw = (int64_t)old + c;
       cross = old < A.lam && A.lam <= nw;
     }
@@ -283,10 +292,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
 __global__ void k_sweep_init(const SweepArgs* args) {
   const SweepDev A = dev_view(args[blockIdx.y]);
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = tid; i < A.ng; i += nth) {
-    A.r[A.v0 + i] = 0;
-    A.step[A.v0 + i] = 0;
-  }
+  for (int64_t i = tid; i < A.ng; i += nth) A.rs[A.v0 + i] = 0;
   for (int64_t i = tid; i < SWEEP_BUCKETS; i += nth) {
     A.ctl->head[i] = -1;
     A.ctl->seg_cur[i] = 0;
@@ -334,9 +340,9 @@ __device__ __forceinline__ void sweep_close_batch(SweepCtl* c, int32_t ng, int64
 template <class SA>
 __device__ __forceinline__ bool live_in_bucket(const SA& A, int32_t v, int32_t b, int32_t& key) {
   if (v < 0) return false;
-  const int32_t vs = ld_relaxed(A.step + v);
-  key = ld_relaxed(A.r + v);
-  return vs == 0 && (int64_t)key < A.lam && (key >> A.shift) == b;
+  const uint64_t u = ld_relaxed(A.rs + v);
+  key = rs_r(u);
+  return rs_stamp(u) == 0 && (int64_t)key < A.lam && (key >> A.shift) == b;
 }
 
 // What the single-pop step needs of the popped vertex besides its id: its
@@ -644,8 +650,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           // at the branch's end)
           const int32_t xq = lane < size ? xs : __builtin_amdgcn_readlane(xs, 0);
           const int64_t cd = A.cdeg[xq];
-          const int32_t rx = ld_relaxed(A.r + xq);
-          if (lane < size) st_relaxed(A.step + xs, stamp);
+          const int32_t rx = rs_r(ld_relaxed(A.rs + xq));
+          if (lane < size) st_relaxed(rs_stamp_ptr(A.rs + xs), stamp);
           int64_t internal = wave_relax_known(A, qf, xs, ra, rb, size, stamp);
           int64_t sum = lane < size ? cd - 2 * (int64_t)rx : 0;
           sum = wave_sum_i64_dpp(sum);
@@ -665,7 +671,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           const int64_t deg = rb - ra;
           int64_t sum = 0;
           if (lane == 0) {
-            st_relaxed(A.step + x, stamp);
+            st_relaxed(rs_stamp_ptr(A.rs + x), stamp);
             sum = pr.cd - 2 * (int64_t)pr.key;
           }
           if (deg > FAST_DEG) {
@@ -712,8 +718,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
       // inside the batch are recognised by their stamp)
       for (int32_t i = h + threadIdx.x; i < t; i += SWEEP_THREADS) {
         const int32_t x = ld_relaxed(A.capq + i);
-        st_relaxed(A.step + x, stamp);
-        sum += A.cdeg[x] - 2 * (int64_t)ld_relaxed(A.r + x);
+        sum += A.cdeg[x] - 2 * (int64_t)rs_r(ld_relaxed(A.rs + x));
+        st_relaxed(rs_stamp_ptr(A.rs + x), stamp);
       }
       __threadfence_block();
       __syncthreads();
@@ -835,8 +841,8 @@ __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
   for (int64_t i = h + gtid(); i - lane_id() < t; i += gstride()) {  // wave-uniform bound
     if (i < t) {
       int32_t x = A.capq[i];
-      A.step[x] = stamp;
-      sum += A.cdeg[x] - 2 * (int64_t)A.r[x];
+      sum += A.cdeg[x] - 2 * (int64_t)rs_r(A.rs[x]);
+      *rs_stamp_ptr(A.rs + x) = stamp;
       deg += A.rp[x + 1] - A.rp[x];
     }
   }
@@ -846,7 +852,7 @@ __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
   if (lane_id() == 0 && deg) atomicAdd((unsigned long long*)&c->batch_deg, (unsigned long long)deg);
 }
 
-// Grid-wide batch [h, t): relax every edge of the batch, one wave per vertex.
+// Grid-wide batch [h, t): relax every edge of the batch.
 // No queue pushes (the queue is rebuilt exactly after the batch); crossing
 // vertices collect in a per-wave LDS buffer and go to the FIFO in blocks.
 constexpr int BIG_BUF = 256;
@@ -866,27 +872,98 @@ __device__ __forceinline__ void flush_wave_buf(const SweepArgs& A, int32_t* wbuf
   __builtin_amdgcn_wave_barrier();
 }
 
-__global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h, int32_t t) {
+// The batch's entries are cut into tiles of BIG_TILE consecutive entries
+// (in batch order, from a prefix sum of the row lengths), one tile per
+// workgroup at a time and BIG_UNROLL consecutive entries per thread: the
+// work is even whatever the row lengths (a few hubs, or many short rows), and
+// every thread has several gathers in flight.
+constexpr int BIG_UNROLL = 4;
+constexpr int BIG_TILE = 256 * BIG_UNROLL;
+
+// Row length of batch vertex i (the prefix sum's input).
+struct BatchDeg {
+  const int32_t* capq;  // the batch's FIFO entries
+  const int64_t* rp;
+  __device__ __forceinline__ int64_t operator()(int64_t i) const {
+    const int32_t x = capq[i];
+    return rp[x + 1] - rp[x];
+  }
+};
+
+// tile_row[j]: the batch row holding entry j * BIG_TILE (each tile start
+// lies in exactly one row of nonzero length).
+__global__ void k_sweep_big_tiles(const int64_t* off, int32_t bsz, int32_t* tile_row) {
+  for (int64_t i = gtid(); i < bsz; i += gstride()) {
+    const int64_t a = off[i], b = off[i + 1];
+    for (int64_t j = (a + BIG_TILE - 1) / BIG_TILE; j * BIG_TILE < b; ++j) tile_row[j] = (int32_t)i;
+  }
+}
+
+// off: bsz + 1 prefix sums of the batch's row lengths (off[bsz] = entries).
+__global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h, int32_t bsz, const int64_t* off,
+                                                         const int32_t* tile_row) {
   __shared__ int32_t buf[4][2 * BIG_BUF];
   __shared__ int32_t cnt[4];
+  __shared__ int32_t s_x[BIG_TILE];
+  __shared__ int64_t s_off[BIG_TILE + 1], s_base[BIG_TILE];
   SweepCtl* c = A.ctl;
   const int32_t stamp = c->step + 1;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   int32_t* wbuf = buf[wave];
   int32_t* wcnt = &cnt[wave];
   if (lane == 0) *wcnt = 0;
-  __builtin_amdgcn_wave_barrier();
-  const int64_t wave0 = gtid() >> 6, nw = gstride() >> 6;
   const SweepQ gq = global_q(c);
+  const int64_t total = off[bsz];
+  const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
   int64_t internal = 0;
-  for (int64_t i = h + wave0; i < t; i += nw) {
-    const int32_t x = A.capq[i];
-    const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
-    for (int64_t base = e0; base < e1; base += 64) {
-      const int64_t e = base + lane;
-      const bool act = e < e1;
-      internal += sweep_relax<false>(A, gq, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act, wbuf, wcnt);
-      if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
+  for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
+    const int64_t t0 = j * BIG_TILE, t1 = min(t0 + BIG_TILE, total);
+    const int32_t r0 = tile_row[j], r1 = j + 1 < ntiles ? tile_row[j + 1] : bsz - 1;
+    // rows [r0, r1] hold the tile; more than BIG_TILE of them only if some
+    // are empty, so they go in slices of BIG_TILE rows
+    for (int32_t rb = r0; rb <= r1; rb += BIG_TILE) {
+      const int32_t nr = min(BIG_TILE, r1 + 1 - rb);
+      for (int32_t k = threadIdx.x; k < nr; k += 256) {
+        const int32_t x = A.capq[h + rb + k];
+        s_x[k] = x;
+        s_base[k] = A.rp[x];
+        s_off[k] = off[rb + k];
+      }
+      if (threadIdx.x == 0) s_off[nr] = off[rb + nr];
+      __syncthreads();
+      const int64_t lo_e = max(s_off[0], t0), hi_e = min(s_off[nr], t1);
+      const int64_t i0 = lo_e + (int64_t)threadIdx.x * BIG_UNROLL;
+      int32_t row = 0;
+      if (i0 < hi_e) {
+        int32_t lo = 0, hi = nr - 1;  // last row with s_off[row] <= i0
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= i0) lo = mid;
+          else hi = mid - 1;
+        }
+        row = lo;
+      }
+      int32_t xs[BIG_UNROLL], ys[BIG_UNROLL], cs[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        const int64_t i = i0 + u;
+        xs[u] = -1;
+        ys[u] = 0;
+        cs[u] = 0;
+        if (i < hi_e) {
+          while (s_off[row + 1] <= i) ++row;
+          const int64_t e = s_base[row] + (i - s_off[row]);
+          xs[u] = s_x[row];
+          ys[u] = A.col[e];
+          cs[u] = A.w[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        internal += sweep_relax<false>(A, gq, xs[u], ys[u], cs[u], stamp, xs[u] >= 0, wbuf, wcnt);
+        if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
+      }
+      __syncthreads();  // the slice arrays are reused
     }
   }
   flush_wave_buf(A, wbuf, wcnt);
@@ -919,8 +996,9 @@ __global__ void __launch_bounds__(256) k_sweep_rb_count(SweepArgs A) {
   __syncthreads();
   for (int64_t i = gtid(); i < A.ng; i += gstride()) {
     const int32_t v = A.v0 + (int32_t)i;
-    const int32_t rv = A.r[v];
-    if (A.step[v] == 0 && rv > 0 && (int64_t)rv < A.lam) atomicAdd(&h[rv >> A.shift], 1);
+    const uint64_t u = A.rs[v];
+    const int32_t rv = rs_r(u);
+    if (rs_stamp(u) == 0 && rv > 0 && (int64_t)rv < A.lam) atomicAdd(&h[rv >> A.shift], 1);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < A.nb; i += 256)
@@ -983,8 +1061,9 @@ __global__ void __launch_bounds__(256) k_sweep_rb_fill(SweepArgs A) {
     rk[q] = 0;
     if (i < A.ng) {
       const int32_t v = A.v0 + (int32_t)i;
-      const int32_t rv = A.r[v];
-      if (A.step[v] == 0 && rv > 0 && (int64_t)rv < A.lam) {
+      const uint64_t u = A.rs[v];
+      const int32_t rv = rs_r(u);
+      if (rs_stamp(u) == 0 && rv > 0 && (int64_t)rv < A.lam) {
         bk[q] = rv >> A.shift;
         rk[q] = atomicAdd(&h[bk[q]], 1);
       }
