@@ -47,7 +47,8 @@ enum {
   MC_EHIP = -5,      /* a HIP runtime call failed */
   MC_EBUSY = -6,     /* server admission full (non-blocking submit) */
   MC_ESTATE = -7,    /* unknown ticket or server stopped */
-  MC_EINTERNAL = -8  /* a round made no progress (never expected; reported, not looped) */
+  MC_EINTERNAL = -8, /* a round made no progress (never expected; reported, not looped) */
+  MC_EMISMATCH = -9  /* the autotuner's launch shapes disagreed on a lambda (never expected) */
 };
 
 typedef struct mc_graph {
@@ -98,6 +99,14 @@ typedef struct mc_options {
                               per graph; 0 = default (2) */
   int32_t viecut_levels;   /* at most this many clustering levels; 0 =
                               default (32) */
+  /* Launch shapes (results do not depend on them; mc_tune_batched picks
+   * them for a batch): */
+  int32_t sweep_threads;   /* threads per LDS-sweep workgroup: 128, 256 or
+                              512; 0 = default (256) */
+  int32_t sweep_groups;    /* LDS-sweep workgroups per compute unit, 1..3,
+                              clamped to what LDS holds; 0 = default (3) */
+  int32_t sort_tile;       /* keys per radix-sort workgroup: 2048, 4096 or
+                              8192; 0 = default (4096) */
   int32_t reserved[1];
 } mc_options;
 
@@ -132,6 +141,26 @@ int mc_mincut(const mc_graph* g, void* stream, const mc_options* opt, int64_t* l
  * on side 0.  MC_ENOCUT if any graph has fewer than two vertices. */
 int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, int64_t* lambdas,
                       uint8_t* sides, mc_stats* stats);
+
+/* Autotuner for the batched form (not in the paper: the packed form and its
+ * launch shapes are this library's).  Solves the batch `b` once per
+ * candidate launch shape and keeps the fastest: first the LDS sweep's
+ * threads per workgroup (128, 256, 512) and workgroups per compute unit
+ * (2, 3), then, with that, the radix sort's keys per workgroup (2048, 4096,
+ * 8192).  Each shape is solved `reps` times (at least 1) and its best wall
+ * time counts.  Every solve must give the same lambdas (the shapes change
+ * the schedule, never the result): otherwise MC_EMISMATCH.  base: the other
+ * options (NULL = defaults); out->best is base with the chosen shape.
+ * The batch's inputs are read only; no output buffer is written but *out. */
+typedef struct mc_tune_result {
+  mc_options best;        /* base with sweep_threads, sweep_groups, sort_tile chosen */
+  int32_t candidates;     /* launch shapes solved */
+  int32_t reps;           /* solves per shape */
+  double best_ms;         /* best wall time of one packed solve with `best` */
+  double default_ms;      /* ... with the default shape */
+} mc_tune_result;
+int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int32_t reps,
+                    mc_tune_result* out);
 
 /* Test hook for per-step parity: runs ingest and the first round's
  * Padberg-Rinaldi tests and CAPFOREST scans (Algorithm 2, first loop

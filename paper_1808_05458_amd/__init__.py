@@ -27,6 +27,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 MC_OK, MC_EINVAL, MC_ENOCUT, MC_EOVERFLOW, MC_ENOMEM, MC_EHIP, MC_EBUSY, MC_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 MC_EINTERNAL = -8
+MC_EMISMATCH = -9
 
 
 def build() -> str:
@@ -54,7 +55,17 @@ class Options(ctypes.Structure):
                 ("force_fallback", ctypes.c_int32), ("whole_max", ctypes.c_int32),
                 ("lp_sweeps", ctypes.c_int32), ("scan_mode", ctypes.c_int32),
                 ("sweep_handoff", ctypes.c_int32), ("viecut_stop", ctypes.c_int32),
-                ("viecut_levels", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("viecut_levels", ctypes.c_int32), ("sweep_threads", ctypes.c_int32),
+                ("sweep_groups", ctypes.c_int32), ("sort_tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Options), ("candidates", ctypes.c_int32), ("reps", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -114,6 +125,8 @@ def _load():
     lib.mc_mincut.restype = ctypes.c_int
     lib.mc_mincut_batched.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_mincut_batched.restype = ctypes.c_int
+    lib.mc_tune_batched.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.mc_tune_batched.restype = ctypes.c_int
     lib.mc_debug_first_round.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_debug_first_round.restype = ctypes.c_int
     lib.mc_debug_contract.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
@@ -307,6 +320,32 @@ def mincut_batched(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool =
     if rc != MC_OK:
         raise MincutError(rc, "mc_mincut_batched")
     return lams, sides, st.as_dict()
+
+
+def tune_batched(row_ptr, col, w, vtx_off: Sequence[int], *, reps: int = 2, stream=None,
+                 opts: Optional[Options] = None, **kw):
+    """Autotune the batched form's launch shapes on this batch.  Returns
+    (Options with the chosen shape, report dict)."""
+    import torch
+    lib = _load()
+    voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    G = len(voff) - 1
+    n = row_ptr.numel() - 1
+    b = Batch(G, n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"),
+              voff.ctypes.data_as(ctypes.c_void_p))
+    o = opts if opts is not None else options(**kw)
+    out = TuneResult()
+    rc = lib.mc_tune_batched(ctypes.byref(b), _stream(stream), ctypes.byref(o), int(reps),
+                             ctypes.byref(out))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_tune_batched")
+    best = Options()
+    ctypes.memmove(ctypes.byref(best), ctypes.byref(out.best), ctypes.sizeof(Options))
+    report = {"candidates": out.candidates, "reps": out.reps, "best_ms": out.best_ms,
+              "default_ms": out.default_ms, "sweep_threads": best.sweep_threads,
+              "sweep_groups": best.sweep_groups, "sort_tile": best.sort_tile}
+    return best, report
 
 
 def viecut_bound(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool = True, stream=None,

@@ -42,6 +42,7 @@ constexpr int WHOLE_CAP_S = 2048;
 constexpr int WHOLE_CAP_L = 8192;
 constexpr int SMALL_CAP_S = 2048;  // LDS-resident sweeps of whole small graphs
 constexpr int SMALL_CAP_L = 8192;
+constexpr int LDS_PER_CU = 160 * 1024;
 constexpr int64_t SWEEP_HANDOFF_ENTRIES = 1 << 16;  // batches with longer rows run grid-wide
 constexpr int32_t MAX_SWEEPS = 256;                 // full-graph sweeps run at once
 
@@ -399,6 +400,23 @@ struct Problem {
 
 static int bitlen(uint64_t x) { return x == 0 ? 0 : 64 - __builtin_clzll(x); }
 
+// The LDS sweep at a launch shape: threads per workgroup (128, 256, 512)
+// and workgroups per compute unit (at most what the CU's 160 KiB of LDS
+// holds).  The workgroups take graphs from a shared counter, so any shape
+// gives the same sweeps.
+template <int T>
+static void launch_small_sweep_t(int groups, int num_cu, const SmallSweepArgs& SA, hipStream_t s) {
+  constexpr int bytes = (int)sizeof(SmallSweepLds<SMALL_CAP_L, T>);
+  const int fit = std::max(1, LDS_PER_CU / bytes);
+  groups = std::max(1, std::min(groups > 0 ? groups : 3, fit));
+  hipLaunchKernelGGL((k_small_sweep<SMALL_CAP_L, T>), dim3(num_cu * groups), dim3(T), bytes, s, SA);
+}
+static void launch_small_sweep(int threads, int groups, int num_cu, const SmallSweepArgs& SA, hipStream_t s) {
+  if (threads == 128) launch_small_sweep_t<128>(groups, num_cu, SA, s);
+  else if (threads == 512) launch_small_sweep_t<512>(groups, num_cu, SA, s);
+  else launch_small_sweep_t<256>(groups, num_cu, SA, s);
+}
+
 static bool debug_on() {
   static int v = -1;
   if (v < 0) {
@@ -647,7 +665,7 @@ struct Solver {
         else if (kind == 2) cur = timer().begin(nm.sort_scatter, ev0);
         else timer().end(cur, ev0, (double)m * 24);
       };
-      which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s, hook);
+      which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s, hook, opt.sort_tile);
     }
     uint64_t* sk = which ? ws.keys_alt : ws.keys;
     int32_t* sv = which ? ws.vals_alt : ws.vals;
@@ -832,9 +850,17 @@ struct Solver {
         e = hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_S>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sizeof(ScanLds<WHOLE_CAP_S>));
       if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L>,
+        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L, 128>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(SmallSweepLds<SMALL_CAP_L>));
+                                (int)sizeof(SmallSweepLds<SMALL_CAP_L, 128>));
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L, 256>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(SmallSweepLds<SMALL_CAP_L, 256>));
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L, 512>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(SmallSweepLds<SMALL_CAP_L, 512>));
       attrs_err = e;
     });
     MC_HIP(attrs_err);
@@ -1043,8 +1069,7 @@ struct Solver {
         {
           TimedScope t("small_sweep", 0.0);
           MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
-          hipLaunchKernelGGL(k_small_sweep<SMALL_CAP_L>, dim3(num_cu * 3), dim3(SS_THREADS),
-                             sizeof(SmallSweepLds<SMALL_CAP_L>), s, SA);
+          launch_small_sweep(opt.sweep_threads, opt.sweep_groups, num_cu, SA, s);
         }
         hipLaunchKernelGGL(k_small_sweep_unite, dim3(num_cu * 4), dim3(TB), 0, s, ws.whole, &ws.ctl->n_whole,
                            ws.cvoff, ws.npairs, ws.capq, ws.capx, ws.parent);
@@ -1241,6 +1266,78 @@ int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, in
   return mc::run(P, stream, opt, lambdas, sides, stats);
 }
 
+int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int32_t reps,
+                    mc_tune_result* out) {
+  if (!b || !out || !b->vtx_off || b->num_graphs < 1) return MC_EINVAL;
+  mc_options o;
+  if (base) o = *base;
+  else mc_options_default(&o);
+  o.timing = 0;
+  reps = std::max(1, reps);
+  std::vector<int64_t> ref, lam((size_t)b->num_graphs);
+  int count = 0;
+  // best wall time of `reps` solves at shape c; every solve's lambdas must
+  // equal the first solve's
+  auto solve_ms = [&](const mc_options& c, double& ms) -> int {
+    ms = 1e300;
+    for (int r = 0; r < reps; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      const int rc = mc_mincut_batched(b, stream, &c, lam.data(), nullptr, nullptr);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rc) return rc;
+      ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+      if (ref.empty()) ref = lam;
+      else if (lam != ref) return MC_EMISMATCH;
+    }
+    ++count;
+    return MC_OK;
+  };
+  // workgroups per CU that one LDS sweep of `threads` threads can have
+  auto fit = [](int threads) {
+    const int bytes = threads == 128   ? (int)sizeof(mc::SmallSweepLds<mc::SMALL_CAP_L, 128>)
+                      : threads == 512 ? (int)sizeof(mc::SmallSweepLds<mc::SMALL_CAP_L, 512>)
+                                       : (int)sizeof(mc::SmallSweepLds<mc::SMALL_CAP_L, 256>);
+    return std::max(1, mc::LDS_PER_CU / bytes);
+  };
+  mc_options best = o;
+  best.sweep_threads = 256;
+  best.sweep_groups = std::min(3, fit(256));
+  best.sort_tile = 4096;
+  double best_ms = 0, default_ms = 0;
+  int rc = solve_ms(best, default_ms);
+  if (rc) return rc;
+  best_ms = default_ms;
+  // the LDS sweep's shape
+  const mc_options shape0 = best;
+  for (int threads : {128, 256, 512}) {
+    for (int groups : {2, 3}) {
+      if (groups > fit(threads)) continue;
+      if (threads == shape0.sweep_threads && groups == shape0.sweep_groups) continue;
+      mc_options c = shape0;
+      c.sweep_threads = threads;
+      c.sweep_groups = groups;
+      double ms = 0;
+      if ((rc = solve_ms(c, ms))) return rc;
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+  }
+  // the sort tile, with that shape
+  const mc_options shape1 = best;
+  for (int tile : {2048, 8192}) {
+    mc_options c = shape1;
+    c.sort_tile = tile;
+    double ms = 0;
+    if ((rc = solve_ms(c, ms))) return rc;
+    if (ms < best_ms) { best_ms = ms; best = c; }
+  }
+  out->best = best;
+  out->candidates = count;
+  out->reps = reps;
+  out->best_ms = best_ms;
+  out->default_ms = default_ms;
+  return MC_OK;
+}
+
 int mc_debug_first_round(const mc_batch* b, void* stream, const mc_options* opt, const int64_t* lhat_in,
                           int32_t* labels, int64_t* lhat_used) {
   if (!b || !labels || !lhat_used || !b->vtx_off || b->num_graphs < 1) return MC_EINVAL;
@@ -1360,6 +1457,7 @@ const char* mc_strerror(int code) {
     case MC_EBUSY: return "server admission queue full";
     case MC_ESTATE: return "unknown ticket or stopped server";
     case MC_EINTERNAL: return "internal error: a round made no progress";
+    case MC_EMISMATCH: return "internal error: launch shapes gave different results";
     default: return "unknown error";
   }
 }

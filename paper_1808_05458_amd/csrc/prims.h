@@ -127,21 +127,23 @@ void exclusive_scan(In in, int64_t n, Tout* out, Tout* total, void* tmp, hipStre
 // LSD radix sort, 8-bit digits.  Per pass: tile histograms (digit-major),
 // one exclusive scan over them, then a stable scatter whose in-tile ranks come
 // from wave ballots (8 ballots give each lane the set of lanes holding the
-// same digit).
+// same digit).  A workgroup sorts a tile of RS_THREADS * ITEMS keys; the
+// tile size is a launch-shape choice (8, 16 or 32 keys per thread).
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;                          // per thread
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;        // 4096 keys per workgroup
+constexpr int RS_ITEMS_DEFAULT = 16;                  // 4096 keys per workgroup
+constexpr int RS_ITEMS_MIN = 8;                       // sizes the histogram buffers
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_WAVE_ITEMS = RS_TILE / RS_WAVES;     // 1024 consecutive keys per wave
 
+template <int ITEMS>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
                                                         int shift, uint32_t* __restrict__ hist,
                                                         int64_t ntiles) {
+  constexpr int TILE = RS_THREADS * ITEMS;
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-  for (int r = 0; r < RS_ITEMS; ++r) {
+  const int64_t base = (int64_t)blockIdx.x * TILE;
+  for (int r = 0; r < ITEMS; ++r) {
     int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
   }
@@ -159,22 +161,25 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
   return m;
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(
     const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals, int64_t n, int shift,
     const uint32_t* __restrict__ offs, int64_t ntiles, uint64_t* __restrict__ okeys,
     int32_t* __restrict__ ovals) {
+  constexpr int TILE = RS_THREADS * ITEMS;
+  constexpr int WAVE_ITEMS = TILE / RS_WAVES;  // consecutive keys per wave
   __shared__ uint32_t cnt[RS_WAVES][256];
   __shared__ uint32_t tile_off[256];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0;
   tile_off[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
   __syncthreads();
-  const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * RS_WAVE_ITEMS;
-  uint64_t k[RS_ITEMS];
-  int32_t v[RS_ITEMS];
-  uint32_t pos[RS_ITEMS];
+  const int64_t wbase = (int64_t)blockIdx.x * TILE + (int64_t)wave * WAVE_ITEMS;
+  uint64_t k[ITEMS];
+  int32_t v[ITEMS];
+  uint32_t pos[ITEMS];
 #pragma unroll
-  for (int r = 0; r < RS_ITEMS; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     int64_t i = wbase + r * 64 + lane;
     bool ok = i < n;
     k[r] = ok ? keys[i] : 0;
@@ -202,7 +207,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < RS_ITEMS; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     if (pos[r] == 0xFFFFFFFFu) continue;
     uint32_t d = (uint32_t)((k[r] >> shift) & 255);
     uint32_t o = cnt[wave][d] + pos[r];
@@ -212,7 +217,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(
 }
 
 inline size_t radix_tmp_bytes(int64_t n) {
-  int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+  const int64_t tile = RS_THREADS * RS_ITEMS_MIN;  // the most tiles of any shape
+  int64_t ntiles = (n + tile - 1) / tile;
   size_t h = (size_t)ntiles * 256 * sizeof(uint32_t);
   return 2 * ((h + 255) & ~(size_t)255) + scan_tmp_bytes<uint32_t>(ntiles * 256) + 1024;
 }
@@ -226,11 +232,12 @@ struct NoHook {
   void operator()(int, int) const {}
 };
 
-template <typename Hook = NoHook>
-inline int radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
-                            int64_t n, int bits, void* tmp, hipStream_t s, Hook hook = Hook()) {
+template <int ITEMS, typename Hook>
+inline int radix_sort_pairs_t(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                              int64_t n, int bits, void* tmp, hipStream_t s, Hook hook) {
   if (n <= 1 || bits <= 0) return 0;
-  int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+  constexpr int TILE = RS_THREADS * ITEMS;
+  int64_t ntiles = (n + TILE - 1) / TILE;
   size_t hb = ((size_t)ntiles * 256 * sizeof(uint32_t) + 255) & ~(size_t)255;
   uint32_t* hist = (uint32_t*)tmp;
   uint32_t* offs = (uint32_t*)((char*)tmp + hb);
@@ -242,17 +249,29 @@ inline int radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, i
     uint64_t* ko = which ? keys : keys_alt;
     int32_t* vo = which ? vals : vals_alt;
     hook(0, pass);
-    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, ki, n, shift, hist, ntiles);
+    hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(ntiles), dim3(RS_THREADS), 0, s, ki, n, shift, hist, ntiles);
     hook(1, pass);
     exclusive_scan<uint32_t, ArrayIn<uint32_t>>(ArrayIn<uint32_t>{hist}, ntiles * 256, offs,
                                                 (uint32_t*)nullptr, stmp, s);
     hook(2, pass);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, ki, vi, n, shift, offs,
+    hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(ntiles), dim3(RS_THREADS), 0, s, ki, vi, n, shift, offs,
                        ntiles, ko, vo);
     hook(3, pass);
     which ^= 1;
   }
   return which;
+}
+
+// tile: keys per workgroup (2048, 4096 or 8192; anything else = 4096).
+template <typename Hook = NoHook>
+inline int radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                            int64_t n, int bits, void* tmp, hipStream_t s, Hook hook = Hook(),
+                            int tile = RS_THREADS * RS_ITEMS_DEFAULT) {
+  if (tile == RS_THREADS * 8)
+    return radix_sort_pairs_t<8>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s, hook);
+  if (tile == RS_THREADS * 32)
+    return radix_sort_pairs_t<32>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s, hook);
+  return radix_sort_pairs_t<16>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s, hook);
 }
 
 }  // namespace mc

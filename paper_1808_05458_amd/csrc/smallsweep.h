@@ -48,39 +48,40 @@ struct SmallSweepArgs {
   uint64_t seed;
 };
 
-constexpr int SS_THREADS = 256;
-constexpr int SS_NW = SS_THREADS / 64;
 constexpr int SS_UNROLL = 4;  // entries in flight per thread in a batch relax
 
-template <int CAP>
+// LDS of one sweep: CAP vertices, THREADS threads per workgroup.
+template <int CAP, int THREADS>
 struct SmallSweepLds {
   static_assert(CAP <= 65536 && CAP % 64 == 0, "16-bit local vertex ids, whole chunks");
+  static_assert(THREADS % 64 == 0 && THREADS <= 1024, "whole waves");
   static constexpr int NC = CAP / 64;
+  static constexpr int NW = THREADS / 64;
   int32_t r[CAP];
   uint16_t capped[CAP];  // vertices in the order their r reached the cap
   uint32_t st[CAP / 16];  // 2 bits per vertex: 0 unvisited, 2 visited, 3 in the current batch
   uint32_t cmax[NC];     // per 64-vertex chunk: >= r of its unvisited vertices
-  int32_t boff[SS_THREADS + 1];  // a batch chunk: entry offsets of its rows
-  int32_t bbase[SS_THREADS];     //   and each row's first entry (graph-relative)
-  int32_t wtot[SS_NW];
+  int32_t boff[THREADS + 1];  // a batch chunk: entry offsets of its rows
+  int32_t bbase[THREADS];     //   and each row's first entry (graph-relative)
+  int32_t wtot[NW];
   int32_t cap_head, cap_tail, npairs, first;
   int32_t b0, nb, stamp;  // the batch capped[b0, b0 + nb); nb < 0: sweep done
-  int64_t wsum[SS_NW], wint[SS_NW];
+  int64_t wsum[NW], wint[NW];
 };
 
 // The 2-bit visit state.  Marking is 0 -> 3 (an OR of both bits) and a
 // batch becomes visited by 3 -> 2 (clearing the low bit), so concurrent marks
 // of vertices sharing a word are atomic bit operations.
-template <int CAP>
-__device__ __forceinline__ uint32_t ss_state(const SmallSweepLds<CAP>& L, int32_t v) {
+template <class LDS>
+__device__ __forceinline__ uint32_t ss_state(const LDS& L, int32_t v) {
   return (L.st[v >> 4] >> (2 * (v & 15))) & 3u;
 }
-template <int CAP>
-__device__ __forceinline__ void ss_mark(SmallSweepLds<CAP>& L, int32_t v) {
+template <class LDS>
+__device__ __forceinline__ void ss_mark(LDS& L, int32_t v) {
   atomicOr(&L.st[v >> 4], 3u << (2 * (v & 15)));
 }
-template <int CAP>
-__device__ __forceinline__ void ss_visited(SmallSweepLds<CAP>& L, int32_t v) {
+template <class LDS>
+__device__ __forceinline__ void ss_visited(LDS& L, int32_t v) {
   atomicAnd(&L.st[v >> 4], ~(1u << (2 * (v & 15))));
 }
 
@@ -92,8 +93,8 @@ __device__ __forceinline__ void ss_wave_sync() {
 // Relax one entry x -> y of weight c (local ids): update r(y) and its chunk
 // bound, and record the crossing r(y) < cap <= r(y) + c as a pair and a
 // capped vertex.  Must be called by all lanes of the wave.
-template <int CAP>
-__device__ __forceinline__ bool ss_relax(SmallSweepLds<CAP>& L, const SmallSweepArgs& A, int32_t v0, int64_t lam,
+template <class LDS>
+__device__ __forceinline__ bool ss_relax(LDS& L, const SmallSweepArgs& A, int32_t v0, int64_t lam,
                                          bool ok, int32_t xl, int32_t yl, int32_t c, int64_t& rows,
                                          int64_t& internal) {
   bool cross = false;
@@ -132,9 +133,9 @@ __device__ __forceinline__ bool ss_relax(SmallSweepLds<CAP>& L, const SmallSweep
 // chunk and the lowest vertex in it are taken (any maximum is a legal next
 // vertex).  The caller visits the vertex, so its chunk's bound drops to the
 // largest key left in the chunk.
-template <int CAP>
-__device__ __forceinline__ int32_t ss_select(SmallSweepLds<CAP>& L, int32_t ng, uint32_t& rx) {
-  constexpr int NC = SmallSweepLds<CAP>::NC;
+template <class LDS>
+__device__ __forceinline__ int32_t ss_select(LDS& L, int32_t ng, uint32_t& rx) {
+  constexpr int NC = LDS::NC;
   const int lane = lane_id();
   const int nc = (ng + 63) >> 6;
   while (true) {
@@ -163,10 +164,12 @@ __device__ __forceinline__ int32_t ss_select(SmallSweepLds<CAP>& L, int32_t ng, 
   }
 }
 
-template <int CAP>
-__global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
+template <int CAP, int THREADS>
+__global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
+  using LDS = SmallSweepLds<CAP, THREADS>;
+  constexpr int NW = LDS::NW;
   extern __shared__ char lds_raw[];
-  SmallSweepLds<CAP>& L = *reinterpret_cast<SmallSweepLds<CAP>*>(lds_raw);
+  LDS& L = *reinterpret_cast<LDS*>(lds_raw);
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   __shared__ int32_t sh_item;
   while (true) {
@@ -179,12 +182,12 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
     const int32_t v0 = A.gvoff[g], ng = A.gn[g];
     const int64_t lam = A.lhat[g];
     const int64_t ebase = A.rp[v0];
-    for (int i = threadIdx.x; i < ng; i += SS_THREADS) {
+    for (int i = threadIdx.x; i < ng; i += THREADS) {
       L.r[i] = 0;
       A.fb_rs[v0 + i] = 0;
     }
-    for (int i = threadIdx.x; i < (ng + 15) / 16; i += SS_THREADS) L.st[i] = 0;
-    for (int c = threadIdx.x; c < SmallSweepLds<CAP>::NC; c += SS_THREADS) L.cmax[c] = 0;
+    for (int i = threadIdx.x; i < (ng + 15) / 16; i += THREADS) L.st[i] = 0;
+    for (int c = threadIdx.x; c < LDS::NC; c += THREADS) L.cmax[c] = 0;
     uint64_t h = A.seed * 0x9E3779B97F4A7C15ull + (uint64_t)g * 0xBF58476D1CE4E5B9ull;
     h ^= h >> 29;
     if (threadIdx.x == 0) {
@@ -205,7 +208,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
         if (pnb > 0) {
           if (lane == 0) {
             int64_t sum = 0, in = 0;
-            for (int k = 0; k < SS_NW; ++k) { sum += L.wsum[k]; in += L.wint[k]; }
+            for (int k = 0; k < NW; ++k) { sum += L.wsum[k]; in += L.wint[k]; }
             alpha += sum - pend - in;
             visited += pnb;
             if (visited < ng && alpha < best_alpha) { best_alpha = alpha; best_step = L.stamp; }
@@ -227,7 +230,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
             ss_wave_sync();
             if (lane == 0) L.first = -1;
           } else {
-            xl = ss_select<CAP>(L, ng, rx);
+            xl = ss_select(L, ng, rx);
           }
           if (xl < 0) { done = true; break; }
           ++stamp;
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           for (int64_t base = e0; base < e1; base += 64) {
             const int64_t e = base + lane;
             const bool ok = e < e1;
-            crossed |= ss_relax<CAP>(L, A, v0, lam, ok, xl, ok ? A.col[e] - v0 : 0, ok ? A.w[e] : 0, rows, internal);
+            crossed |= ss_relax(L, A, v0, lam, ok, xl, ok ? A.col[e] - v0 : 0, ok ? A.w[e] : 0, rows, internal);
           }
           if (lane == 0) {
             alpha += dx - 2 * (int64_t)rx;
@@ -281,11 +284,11 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
       const int32_t nb = L.nb;
       if (nb < 0) break;
       // batch relax: the batch's entries spread evenly over the workgroup, in
-      // chunks of SS_THREADS rows
+      // chunks of THREADS rows
       const int32_t b0 = L.b0;
       int64_t rows = 0, internal = 0;
-      for (int32_t c0 = 0; c0 < nb; c0 += SS_THREADS) {
-        const int32_t cn = min(SS_THREADS, nb - c0);
+      for (int32_t c0 = 0; c0 < nb; c0 += THREADS) {
+        const int32_t cn = min(THREADS, nb - c0);
         int32_t deg = 0;
         if ((int32_t)threadIdx.x < cn) {
           const int32_t x = v0 + L.capped[b0 + c0 + threadIdx.x];
@@ -306,11 +309,11 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
         if ((int32_t)threadIdx.x == cn - 1) L.boff[cn] = before + incl;
         __syncthreads();
         const int32_t total = L.boff[cn];
-        for (int32_t i0 = 0; i0 < total; i0 += SS_THREADS * SS_UNROLL) {
+        for (int32_t i0 = 0; i0 < total; i0 += THREADS * SS_UNROLL) {
           int32_t ys[SS_UNROLL], cs[SS_UNROLL], xs[SS_UNROLL];
 #pragma unroll
           for (int u = 0; u < SS_UNROLL; ++u) {
-            const int32_t i = i0 + u * SS_THREADS + (int32_t)threadIdx.x;
+            const int32_t i = i0 + u * THREADS + (int32_t)threadIdx.x;
             xs[u] = -1;
             ys[u] = 0;
             cs[u] = 0;
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(SS_THREADS) k_small_sweep(SmallSweepArgs A) {
           }
 #pragma unroll
           for (int u = 0; u < SS_UNROLL; ++u)
-            ss_relax<CAP>(L, A, v0, lam, xs[u] >= 0, xs[u], ys[u], cs[u], rows, internal);
+            ss_relax(L, A, v0, lam, xs[u] >= 0, xs[u], ys[u], cs[u], rows, internal);
         }
         __syncthreads();  // boff and bbase are reused by the next chunk
       }

@@ -47,7 +47,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_error_strings_and_defaults(lib):
     lib.mc_strerror.restype = ctypes.c_char_p
-    for code in range(-8, 1):
+    for code in range(-9, 1):
         assert lib.mc_strerror(code)
     o = mc.options()
     assert o.use_pr == 1 and o.eager_blacklist == 1 and o.timing == 0
@@ -64,10 +64,11 @@ def test_struct_layouts_match_header():
     #include <stddef.h>
     #include "mincut.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mc_graph), sizeof(mc_batch),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mc_graph), sizeof(mc_batch),
              sizeof(mc_options), sizeof(mc_stats), sizeof(mc_timing_entry),
              offsetof(mc_stats, ms), offsetof(mc_options, timing), sizeof(mc_server_cfg),
-             sizeof(mc_request), sizeof(mc_latency), offsetof(mc_server_cfg, opt));
+             sizeof(mc_request), sizeof(mc_latency), offsetof(mc_server_cfg, opt),
+             offsetof(mc_options, sort_tile), sizeof(mc_tune_result), offsetof(mc_tune_result, best_ms));
       return 0;
     }
     """
@@ -88,6 +89,9 @@ def test_struct_layouts_match_header():
     assert vals[10] == mc.ServerCfg.opt.offset
     assert vals[5] == mc.Stats.ms.offset
     assert vals[6] == mc.Options.timing.offset
+    assert vals[11] == mc.Options.sort_tile.offset
+    assert vals[12] == ctypes.sizeof(mc.TuneResult)
+    assert vals[13] == mc.TuneResult.best_ms.offset
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
