@@ -51,6 +51,7 @@ def _load():
         lib.mco_pair_connectivity.argtypes = [ctypes.c_int32, vp, vp, vp, vp]
         lib.mco_stoer_wagner.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         lib.mco_noi.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64, vp, vp, vp]
+        lib.mco_matula.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64, ctypes.c_int64, vp, vp, vp]
         lib.mco_lp_sweep.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         i32 = ctypes.c_int32
         lib.mco_viecut.argtypes = [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
@@ -114,6 +115,18 @@ def noi(g, seed: int = 0):
     rounds = np.zeros(1, np.int32)
     _check(_load().mco_noi(g.n, _p(rp), _p(col), _p(w), ctypes.c_uint64(seed), _p(lam),
                            _p(side), _p(rounds)), "noi")
+    return int(lam[0]), side, int(rounds[0])
+
+
+def matula(g, eps_ppm: int, seed: int = 0):
+    """Matula's (2+eps)-approximation, eps = eps_ppm / 10^6: (cut value, side,
+    rounds); the value is a real cut of g."""
+    rp, col, w = _arrs(g)
+    lam = np.zeros(1, np.int64)
+    side = np.zeros(g.n, np.uint8)
+    rounds = np.zeros(1, np.int32)
+    _check(_load().mco_matula(g.n, _p(rp), _p(col), _p(w), ctypes.c_uint64(seed), int(eps_ppm), _p(lam),
+                              _p(side), _p(rounds)), "matula")
     return int(lam[0]), side, int(rounds[0])
 
 

@@ -20,6 +20,10 @@
 // (lambda(G,s,t) for all pairs by enumeration).
 // Upper bound: mco_viecut (the VieCut-style bound of Algorithm 2's first
 // step) and its label-propagation step mco_lp_sweep.
+// Approximation: mco_matula - Matula's (2+eps)-approximation as the paper
+// describes it (section "Nagamochi, Ono and Ibaraki's Algorithm" and
+// "Bounded Priority Queues"): NOI whose contraction bound is (1/2 - eps)
+// times the minimum degree rather than the best cut found.
 //
 // All arithmetic is exact 64-bit integer.  Inputs are a symmetric CSR
 // (row_ptr int64[n+1], col int32[nnz], w int32[nnz]); self-loops are ignored
@@ -270,7 +274,13 @@ WGraph from_input(const Csr& in) {  // G without self-loops
   return g;
 }
 
-int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* rounds_out) {
+// eps_ppm < 0: the exact algorithm (O3).  eps_ppm >= 0: Matula's
+// approximation with eps = eps_ppm / 10^6 < 1/2: a round contracts the edges
+// with q(e) >= k = min(lambda-hat, max(1, floor((1/2 - eps) * delta))), delta
+// the current graph's minimum degree; lambda-hat stays the smallest real cut
+// seen (degrees, prefix cuts), so the answer is a cut of G.
+int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* rounds_out,
+        i64 eps_ppm = -1) {
   const int32_t n0 = in.n;
   if (n0 < 2) return -2;
   std::vector<uint8_t> reach;
@@ -305,7 +315,13 @@ int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* r
   int32_t rounds = 0;
   while (g.n > 2 && lhat > 0) {
     ++rounds;
-    const i64 lsnap = lhat;  // bound used by the contraction rule this round
+    i64 lsnap = lhat;  // bound used by the contraction rule this round
+    if (eps_ppm >= 0) {
+      i64 delta = g.deg[0];
+      for (int32_t v = 1; v < g.n; ++v) delta = std::min(delta, g.deg[v]);
+      const i64 k = delta * (1000000 - 2 * eps_ppm) / 2000000;
+      lsnap = std::min(lhat, std::max<i64>(1, k));
+    }
     std::vector<i64> r(g.n, 0);
     std::vector<uint8_t> visited(g.n, 0);
     std::vector<int32_t> order;
@@ -488,6 +504,12 @@ int mco_stoer_wagner(int32_t n, const int64_t* rp, const int32_t* col, const int
 int mco_noi(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, uint64_t seed,
             int64_t* lambda, uint8_t* side, int32_t* rounds) {
   return noi(Csr{n, rp, col, w}, seed, lambda, side, rounds);
+}
+
+int mco_matula(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, uint64_t seed,
+               int64_t eps_ppm, int64_t* lambda, uint8_t* side, int32_t* rounds) {
+  if (eps_ppm < 0 || eps_ppm >= 500000) return -1;
+  return noi(Csr{n, rp, col, w}, seed, lambda, side, rounds, eps_ppm);
 }
 
 

@@ -360,3 +360,67 @@ def test_viecut_on_workload_shapes():
         assert lam <= b <= min_degree(g), g.name
         assert oracle.cut_value(g, side) == b
         assert levels >= 1
+
+
+# ------------------------------------------ Matula's (2+eps)-approximation
+def matula_bound(lam, ppm):
+    # a round whose bound k = floor((1/2 - eps) delta) is at most lambda has
+    # delta < (lambda + 1) / (1/2 - eps), and delta is a cut the answer counts
+    return (lam + 1) * 2_000_000 // (1_000_000 - 2 * ppm)
+
+
+@pytest.mark.parametrize("ppm", [1, 100_000, 250_000, 490_000])
+def test_matula_is_a_cut_within_its_bound(ppm):
+    rng = np.random.default_rng(900 + ppm % 97)
+    for trial in range(300):
+        n = int(rng.integers(2, 12))
+        g = random_graph(rng, n, float(rng.uniform(0.1, 1.0)), int(rng.choice([1, 3, 10, 100])),
+                         connected=bool(rng.random() < 0.9))
+        lam = oracle.bruteforce(g)[0]
+        a, side, _ = oracle.matula(g, ppm, trial)
+        check_side(g, a, side)
+        assert lam <= a <= matula_bound(lam, ppm), (trial, lam, a)
+        assert a <= min_degree(g)
+
+
+def _hypercube(d):
+    n = 1 << d
+    return gg.from_edges(n, [(v, v ^ (1 << i)) for v in range(n) for i in range(d) if v < v ^ (1 << i)],
+                         name=f"Q{d}")
+
+
+def _kab(a, b):
+    return gg.from_edges(a + b, [(i, a + j) for i in range(a) for j in range(b)], name=f"K{a},{b}")
+
+
+@pytest.mark.parametrize("g", [gg.complete(9), gg.complete(6, 5), _hypercube(4), _kab(3, 7)],
+                         ids=lambda g: g.name)
+def test_matula_is_exact_when_lambda_is_the_min_degree(g):
+    # the answer is a cut (>= lambda) and never above the minimum degree
+    lam = oracle.bruteforce(g)[0] if g.n <= 20 else oracle.noi(g)[0]
+    assert lam == min_degree(g)
+    for ppm in (1, 100_000, 400_000):
+        assert oracle.matula(g, ppm)[0] == lam
+
+
+def test_matula_lowers_the_contraction_bound():
+    # with the bound below the best cut a round contracts at least as much:
+    # never more rounds than the exact loop on the same graphs, and fewer on
+    # most of them (the exact loop's bound would give the same counts)
+    graphs = [gg.planted_4096()] + [gg.batch_graph(i) for i in range(0, 400, 37)]
+    fewer = 0
+    for g in graphs:
+        e, _, re_ = oracle.noi(g, 1)
+        a, side, ra = oracle.matula(g, 100_000, 1)
+        assert e <= a <= matula_bound(e, 100_000)
+        assert oracle.cut_value(g, side) == a
+        assert ra <= re_, g.name
+        fewer += ra < re_
+    assert fewer >= len(graphs) // 2
+
+
+def test_matula_rejects_eps_out_of_range():
+    with pytest.raises(ValueError):
+        oracle.matula(gg.complete(4), 500_000)
+    with pytest.raises(ValueError):
+        oracle.matula(gg.complete(4), -1)
