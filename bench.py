@@ -234,6 +234,7 @@ def main():
     ap.add_argument("--workload", choices=["chung_lu", "batched", "served"], default="chung_lu")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-rmat", action="store_true")
+    ap.add_argument("--no-approx", action="store_true", help="skip the (2+eps)-approximation runs")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--pool", type=int, default=32)
     ap.add_argument("--lanes", type=int, default=3)
@@ -352,6 +353,27 @@ def main():
                     "oracle_lambda": gold["lambda"] if gold else None}
         log(f"verify: {verified}")
 
+    # Matula's (2+eps)-approximation on the same resident graph (the same
+    # kernels with a lower contraction bound); its answer is a real cut
+    approx = None
+    if not args.no_approx:
+        approx = []
+        for ppm in (100_000, 250_000):
+            mc.mincut(rp, col, w, approx_ppm=ppm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(3):
+                lam_a, side_a, st_a = mc.mincut(rp, col, w, approx_ppm=ppm)
+            torch.cuda.synchronize()
+            dt_a = (time.perf_counter() - t0) / 3
+            s_a = side_a.cpu().numpy()[: g.n].astype(bool)
+            src = g.src()
+            cut_a = int(g.w[s_a[src] != s_a[g.col]].sum()) // 2
+            approx.append({"eps": ppm / 1e6, "ms": round(dt_a * 1e3, 2), "edges_per_s": g.m / dt_a,
+                           "lambda": lam_a, "side_cut_weight": cut_a, "rounds": st_a["rounds"],
+                           "exact_lambda": lams[0]})
+            log(f"approx eps={ppm / 1e6}: {approx[-1]}")
+
     batched = None
     if not args.no_batched:
         batched = batched_form(max(1, min(args.steps, 3)), 1)
@@ -376,7 +398,7 @@ def main():
                                   f"8-core LCC", "n": g.n, "m": g.m,
                       "rounds": st["rounds"], "verified": verified},
            "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "served": served,
-           "rmat_scale24": rmat}
+           "rmat_scale24": rmat, "matula_approx": approx}
     print(json.dumps(out), flush=True)
 
 

@@ -107,6 +107,15 @@ typedef struct mc_options {
                               clamped to what LDS holds; 0 = default (3) */
   int32_t sort_tile;       /* keys per radix-sort workgroup: 2048, 4096 or
                               8192; 0 = default (4096) */
+  int32_t approx_ppm;      /* 0 (default): exact.  1 .. 499999: Matula's
+                              (2+eps)-approximation with eps = approx_ppm /
+                              10^6 (the paper names it beside NOI: the
+                              contraction bound of a round is (1/2 - eps)
+                              times the graph's minimum degree, capped by the
+                              best cut found).  lambda is then a real cut
+                              with lambda(G) <= lambda < (lambda(G) + 1) /
+                              (1/2 - eps), and the side realises it.
+                              Outside 0 .. 499999: MC_EINVAL. */
   int32_t reserved[1];
 } mc_options;
 

@@ -162,7 +162,7 @@ struct Workspace {
   uint64_t *keys, *keys_alt;
   int32_t *vals, *vals_alt;
   // graph arrays
-  int64_t *voff, *lhat, *wsum;
+  int64_t *voff, *lhat, *wsum, *kcap;
   int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole, *gmaxw, *prok,
       *whole2, *fb_list, *root0, *flip, *nvoff, *npairs;
   uint64_t *bdeg, *balpha;
@@ -217,7 +217,7 @@ size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
        2 * align_up(sizeof(SweepStatus) * MAX_SWEEPS);
   b += align_up((N + 2) * 8) * 2;
   b += align_up(E * 4) * 3 + align_up((E + 64) * 8) + align_up((E + G + 64) * 8) + align_up(E * 4) * 2;
-  b += align_up((G + 1) * 8) * 3 + align_up((G + 1) * 4) * 18 + align_up((G + 1) * 8) * 2 +
+  b += align_up((G + 1) * 8) * 4 + align_up((G + 1) * 4) * 18 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
   b += align_up((2 * N + G + 64) * 4);
   size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
@@ -283,6 +283,7 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.vals_alt, E * 4);
   ALLOC(ws.voff, (G + 1) * 8);
   ALLOC(ws.lhat, (G + 1) * 8);
+  ALLOC(ws.kcap, (G + 1) * 8);
   ALLOC(ws.wsum, (G + 1) * 8);
   ALLOC(ws.gn, (G + 1) * 4);
   ALLOC(ws.cvoff, (G + 1) * 4);
@@ -940,10 +941,15 @@ struct Solver {
     if (ws.ctl_host->err) return MC_EINVAL;
     // the first round's tests run only where one can pass (a lower starting
     // bound from the caller or the clustering bound may enable PR1)
-    const bool pr_first_round = ws.ctl_host->n_pr > 0 || lhat_in != nullptr || opt.use_viecut;
+    // (Matula's bound lies below the best cut, so its tests always run)
+    const bool approx = opt.approx_ppm > 0;
+    const bool pr_first_round = ws.ctl_host->n_pr > 0 || lhat_in != nullptr || opt.use_viecut || approx;
     // in the first round only the graphs marked in prok are tested, unless a
     // lower starting bound may have enabled PR1 elsewhere
-    const bool pr_first_all = lhat_in != nullptr || opt.use_viecut;
+    const bool pr_first_all = lhat_in != nullptr || opt.use_viecut || approx;
+    // the bound the round's tests and scans contract with: the best cut
+    // found (exact), or Matula's (1/2 - eps) delta below it
+    const int64_t* cap = approx ? ws.kcap : ws.lhat;
     if (st) {
       std::vector<int64_t> l0(G);
       MC_HIP(hipMemcpy(l0.data(), ws.lhat, G * sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -992,8 +998,10 @@ struct Solver {
     while (n_active > 0 && (opt.max_rounds <= 0 || round < opt.max_rounds)) {
       if (st && round < 64) { st->n_round[round] = n; st->nnz_round[round] = nnz; }
       ++round;
-      // per-round control fields
+      // per-round control fields (Matula's bound reads the minimum degree
+      // before the reset clears it)
       MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
+      if (approx) hipLaunchKernelGGL(k_matula_cap, grid(G), dim3(TB), 0, s, G, S, (int64_t)opt.approx_ppm, ws.kcap);
       hipLaunchKernelGGL(k_round_reset, grid(G), dim3(TB), 0, s, G, S);
       hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
       fill<int32_t>(ws.claim, -1, n, s);
@@ -1001,11 +1009,11 @@ struct Solver {
         // src, col, w per entry; both degrees for the half with u < v
         TimedScope t("pr", (double)nnz * 20 + (double)n * 32);
         const int32_t* tested = (round == 1 && !pr_first_all) ? ws.prok : ws.active;
-        hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, ws.cdeg, gid, ws.lhat,
+        hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, ws.cdeg, gid, cap,
                            tested, ws.parent, ws.ucount);
         hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
-                           ws.lhat, tested, ws.parent, ws.ucount, ws.ctl);
+                           cap, tested, ws.parent, ws.ucount, ws.ctl);
       }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -1017,7 +1025,7 @@ struct Solver {
       // scans
       ScanArgs A{};
       A.n = n; A.rp = rp; A.col = col; A.w = w; A.cdeg = ws.cdeg; A.gid = gid;
-      A.lhat = ws.lhat; A.gn = ws.gn; A.gvoff = ws.cvoff; A.gmode = ws.mode;
+      A.lhat = cap; A.gn = ws.gn; A.gvoff = ws.cvoff; A.gmode = ws.mode;
       A.claim = ws.claim; A.step = ws.step; A.pairs = ws.keys_alt; A.pairs_cap = ws.capE;
       A.best_alpha = ws.balpha; A.scan_k = ws.scan_k; A.scan_k_cap = (int32_t)std::min<int64_t>(ws.scan_k_cap, INT32_MAX);
       A.ucount = ws.ucount; A.ctl = ws.ctl;
@@ -1063,7 +1071,7 @@ struct Solver {
       } else {
         // whole small graphs: LDS-resident capped sweeps, one workgroup each,
         // the large-map list first (both lists are ordered largest first)
-        SmallSweepArgs SA{rp, col, w, ws.cdeg, ws.lhat, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
+        SmallSweepArgs SA{rp, col, w, ws.cdeg, cap, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
                           &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_rs, ws.capq, ws.capx, ws.npairs,
                           ws.balpha, ws.fb_k, ws.ucount, A.seed};
         {
@@ -1083,7 +1091,7 @@ struct Solver {
       const int sweep_region = (opt.scan_mode != 1 || opt.force_fallback) ? 1 : 0;
       hipLaunchKernelGGL(k_sweep_list, grid(G), dim3(TB), 0, s, G, S, sweep_region, ws.ctl);
       hipLaunchKernelGGL(k_sweep_info, grid(G), dim3(TB), 0, s, ws.fb_list, ws.ctl, ws.cvoff, ws.gn,
-                         ws.lhat, rp, ws.sw_info);
+                         cap, rp, ws.sw_info);
       rc = read_ctl();
       if (rc) return rc;
       // whole scans: col and w per entry; row_ptr, cdeg, claim and step (one-pop
@@ -1205,6 +1213,7 @@ int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt,
   mc_options o;
   mc_options_default(&o);
   if (opt) o = *opt;
+  if (o.approx_ppm < 0 || o.approx_ppm >= 500000) return MC_EINVAL;
   if (st) {
     std::memset(st, 0, sizeof(*st));
   }

@@ -324,6 +324,23 @@ __global__ void k_side(SideArgs A) {
 // Round planning: graphs up to whole_small vertices are scanned whole with
 // the small LDS map (mode 1), up to whole_max with the large map (mode 3),
 // larger ones by region scans (mode 2).  Inactive graphs idle (mode 0).
+// Matula's approximation: the round's contraction bound per graph,
+// k = min(lambda-hat, max(1, floor((1/2 - eps) delta))) with eps = ppm / 10^6
+// and delta the graph's minimum degree (bdeg, before the round clears it).
+__global__ void k_matula_cap(int32_t G, GraphState S, int64_t ppm, int64_t* kcap) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    const int64_t lam = S.lhat[g];
+    const uint64_t bd = S.bdeg[g];
+    int64_t k = lam;
+    if (bd != ~0ull) {
+      const int64_t delta = (int64_t)(bd >> 32);
+      const int64_t m = delta * (1000000 - 2 * ppm) / 2000000;
+      k = min(lam, max((int64_t)1, m));
+    }
+    kcap[g] = k;
+  }
+}
+
 __global__ void k_round_reset(int32_t G, GraphState S) {
   for (int64_t g = gtid(); g < G; g += gstride()) {
     S.ucount[g] = 0;
