@@ -52,6 +52,7 @@ def _load():
         lib.mco_stoer_wagner.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         lib.mco_noi.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64, vp, vp, vp]
         lib.mco_matula.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_uint64, ctypes.c_int64, vp, vp, vp]
+        lib.mco_pr_tests.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
         lib.mco_lp_sweep.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         i32 = ctypes.c_int32
         lib.mco_viecut.argtypes = [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
@@ -116,6 +117,15 @@ def noi(g, seed: int = 0):
     _check(_load().mco_noi(g.n, _p(rp), _p(col), _p(w), ctypes.c_uint64(seed), _p(lam),
                            _p(side), _p(rounds)), "noi")
     return int(lam[0]), side, int(rounds[0])
+
+
+def pr_tests(g, lhat: int, max_deg: int = 64):
+    """Padberg-Rinaldi tests per entry (u, v), u < v: uint8 bits PR1 (1),
+    PR2 (2), PR3 (4), PR4 (8); 0 for the other entries."""
+    rp, col, w = _arrs(g)
+    flags = np.zeros(len(col), np.uint8)
+    _check(_load().mco_pr_tests(g.n, _p(rp), _p(col), _p(w), int(lhat), int(max_deg), _p(flags)), "pr_tests")
+    return flags
 
 
 def matula(g, eps_ppm: int, seed: int = 0):

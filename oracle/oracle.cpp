@@ -20,6 +20,10 @@
 // (lambda(G,s,t) for all pairs by enumeration).
 // Upper bound: mco_viecut (the VieCut-style bound of Algorithm 2's first
 // step) and its label-propagation step mco_lp_sweep.
+// Local tests: mco_pr_tests - the Padberg-Rinaldi tests of one edge (section
+// "Exact Minimum Cut Algorithms", the heuristics of Padberg and Rinaldi; the
+// paper names them without restating them, so each is written from the cut
+// argument that makes it sound).
 // Approximation: mco_matula - Matula's (2+eps)-approximation as the paper
 // describes it (section "Nagamochi, Ono and Ibaraki's Algorithm" and
 // "Bounded Priority Queues"): NOI whose contraction bound is (1/2 - eps)
@@ -472,9 +476,69 @@ int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i6
   return 0;
 }
 
+// Padberg-Rinaldi tests of every entry e = (u, v) with u < v, as bits of
+// flags[e] (0 for every other entry):
+//   bit 0  PR1: c(e) >= lhat;
+//   bit 1  PR2: 2 c(e) > c(u) or 2 c(e) > c(v)  (c(x): weighted degree
+//          without self-loops);
+//   bit 2  PR3: a common neighbour w (w != u, v) with c(u) <= 2 (c(e) + c(u,w))
+//          and c(v) <= 2 (c(e) + c(v,w));
+//   bit 3  PR4: c(e) + sum over common neighbours w of min(c(u,w), c(v,w))
+//          >= lhat.
+// c(e) is the entry's weight.  PR3 and PR4 are evaluated only where both rows
+// list their neighbours in strictly increasing order (so c(u,w) is one entry)
+// and hold at most max_deg entries each; elsewhere their bits are 0.
+int pr_tests(const Csr& g, i64 lhat, int32_t max_deg, uint8_t* flags) {
+  std::vector<i64> deg(g.n, 0);
+  for (int32_t u = 0; u < g.n; ++u)
+    for (i64 e = g.rp[u]; e < g.rp[u + 1]; ++e)
+      if (g.col[e] != u) deg[u] += g.w[e];
+  auto increasing = [&](int32_t x) {
+    for (i64 e = g.rp[x] + 1; e < g.rp[x + 1]; ++e)
+      if (g.col[e] <= g.col[e - 1]) return false;
+    return true;
+  };
+  for (int32_t u = 0; u < g.n; ++u)
+    for (i64 e = g.rp[u]; e < g.rp[u + 1]; ++e) {
+      flags[e] = 0;
+      const int32_t v = g.col[e];
+      if (u >= v) continue;
+      const i64 c = g.w[e];
+      uint8_t f = 0;
+      if (c >= lhat) f |= 1;
+      if (2 * c > deg[u] || 2 * c > deg[v]) f |= 2;
+      const i64 du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];
+      if (du <= max_deg && dv <= max_deg && increasing(u) && increasing(v)) {
+        // the common neighbours, by looking each of u's up in v's row
+        bool pr3 = false;
+        i64 paths = c;  // the edge, then one two-edge path per common neighbour
+        for (i64 a = g.rp[u]; a < g.rp[u + 1]; ++a) {
+          const int32_t x = g.col[a];
+          if (x == u || x == v) continue;
+          for (i64 b = g.rp[v]; b < g.rp[v + 1]; ++b)
+            if (g.col[b] == x) {
+              const i64 cu = g.w[a], cv = g.w[b];
+              paths += std::min(cu, cv);
+              if (deg[u] <= 2 * (c + cu) && deg[v] <= 2 * (c + cv)) pr3 = true;
+            }
+        }
+        if (pr3) f |= 4;
+        if (paths >= lhat) f |= 8;
+      }
+      flags[e] = f;
+    }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
+
+int mco_pr_tests(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, int64_t lhat,
+                 int32_t max_deg, uint8_t* flags) {
+  if (n < 0 || !rp || !flags) return -1;
+  return pr_tests(Csr{n, rp, col, w}, lhat, max_deg, flags);
+}
 
 int mco_cut_value(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w,
                   const uint8_t* side, int64_t* value) {

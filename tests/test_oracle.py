@@ -424,3 +424,81 @@ def test_matula_rejects_eps_out_of_range():
         oracle.matula(gg.complete(4), 500_000)
     with pytest.raises(ValueError):
         oracle.matula(gg.complete(4), -1)
+
+
+# ------------------------------------------------ Padberg-Rinaldi tests
+PR1, PR2, PR3, PR4 = 1, 2, 4, 8
+
+
+def _edge_entries(g):
+    src = g.src()
+    return [(int(e), int(src[e]), int(g.col[e])) for e in range(len(g.col)) if src[e] < g.col[e]]
+
+
+def test_pr_tests_hand_examples():
+    # a triangle whose light edge (0,1) sits beside two heavy ones
+    g = gg.from_edges(3, [(0, 1), (0, 2), (1, 2)], [1, 5, 5])
+    f = oracle.pr_tests(g, 6)
+    e01 = [e for e, u, v in _edge_entries(g) if (u, v) == (0, 1)][0]
+    # c(0) = c(1) = 6 <= 2 (1 + 5); 1 + min(5, 5) = 6 >= 6; not PR1, not PR2
+    assert f[e01] == PR3 | PR4
+    assert oracle.pr_tests(g, 7)[e01] == PR3
+    # K_n, unit weights: one edge plus n - 2 two-edge paths = n - 1 = lambda;
+    # PR3 needs n - 1 <= 4
+    for n in (4, 5, 6, 8):
+        g = gg.complete(n)
+        f = oracle.pr_tests(g, n - 1)
+        for e, u, v in _edge_entries(g):
+            assert f[e] & PR4
+            assert bool(f[e] & PR3) == (n <= 5)
+            assert not f[e] & (PR1 | PR2)
+        assert not any(oracle.pr_tests(g, n)[e] & PR4 for e, _, _ in _edge_entries(g))
+
+
+def test_pr_tests_need_sorted_short_rows():
+    g = gg.complete(6)
+    f = oracle.pr_tests(g, 5, max_deg=4)  # rows of 5 entries exceed the limit
+    assert not any(x & (PR3 | PR4) for x in f)
+    # the same graph with row 0 listed backwards: its edges lose PR3/PR4
+    col = g.col.copy()
+    a, b = g.row_ptr[0], g.row_ptr[1]
+    col[a:b] = col[a:b][::-1].copy()
+    w = g.w.copy()
+    w[a:b] = w[a:b][::-1].copy()
+    h = gg.Graph(g.n, g.row_ptr.copy(), col, w, "K6-rev")
+    f = oracle.pr_tests(h, 5)
+    for e, u, v in _edge_entries(h):
+        assert bool(f[e] & PR4) == (u != 0)
+
+
+def test_pr_tests_are_sound_by_brute_force():
+    # a passing edge keeps the minimum cut: min(bound, delta, lambda(G/e))
+    # = lambda(G), with the bound a real cut (lambda itself, or delta); PR4
+    # never claims more than the pair's connectivity
+    rng = np.random.default_rng(4242)
+    checked = {PR1: 0, PR2: 0, PR3: 0, PR4: 0}
+    for trial in range(250):
+        n = int(rng.integers(3, 10))
+        g = random_graph(rng, n, float(rng.uniform(0.3, 1.0)), int(rng.choice([1, 2, 5, 20])))
+        lam = oracle.bruteforce(g)[0]
+        delta = min_degree(g)
+        conn = oracle.pair_connectivity(g)
+        for bound in {lam, delta}:
+            f = oracle.pr_tests(g, bound)
+            for e, u, v in _edge_entries(g):
+                if f[e] & PR4:
+                    assert conn[u, v] >= bound, (trial, u, v)
+                if not f[e]:
+                    continue
+                lab = np.arange(g.n)
+                lab[v] = u
+                h, _ = oracle.contract(g, lab)
+                lh = oracle.bruteforce(h)[0] if h.n >= 2 else bound
+                assert min(bound, delta, lh) == lam, (trial, bound, f[e])
+                for bit in checked:
+                    checked[bit] += bool(f[e] & bit)
+        # PR4's path sum never exceeds the pair's connectivity
+        for e, u, v in _edge_entries(g):
+            f1 = oracle.pr_tests(g, int(conn[u, v]) + 1)
+            assert not f1[e] & PR4
+    assert min(checked.values()) > 20, checked
