@@ -481,10 +481,15 @@ int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i6
 //   bit 0  PR1: c(e) >= lhat;
 //   bit 1  PR2: 2 c(e) > c(u) or 2 c(e) > c(v)  (c(x): weighted degree
 //          without self-loops);
-//   bit 2  PR3: a common neighbour w (w != u, v) with c(u) <= 2 (c(e) + c(u,w))
-//          and c(v) <= 2 (c(e) + c(v,w));
+//   bit 2  PR3: a common neighbour w (w != u, v) with c(u) < 2 (c(e) + c(u,w))
+//          and c(v) < 2 (c(e) + c(v,w));
 //   bit 3  PR4: c(e) + sum over common neighbours w of min(c(u,w), c(v,w))
 //          >= lhat.
+// Strict PR2 and PR3 hold for every non-trivial minimum cut at once (a cut
+// that separates u and v with more than v, say, on v's side becomes strictly
+// smaller when v crosses over), and PR1 and PR4 bound lambda(u, v) from below,
+// so all passing edges can be contracted together while the trivial cuts
+// and lambda-hat are kept.
 // c(e) is the entry's weight.  PR3 and PR4 are evaluated only where both rows
 // list their neighbours in strictly increasing order (so c(u,w) is one entry)
 // and hold at most max_deg entries each; elsewhere their bits are 0.
@@ -519,7 +524,7 @@ int pr_tests(const Csr& g, i64 lhat, int32_t max_deg, uint8_t* flags) {
             if (g.col[b] == x) {
               const i64 cu = g.w[a], cv = g.w[b];
               paths += std::min(cu, cv);
-              if (deg[u] <= 2 * (c + cu) && deg[v] <= 2 * (c + cv)) pr3 = true;
+              if (deg[u] < 2 * (c + cu) && deg[v] < 2 * (c + cv)) pr3 = true;
             }
         }
         if (pr3) f |= 4;

@@ -440,17 +440,17 @@ def test_pr_tests_hand_examples():
     g = gg.from_edges(3, [(0, 1), (0, 2), (1, 2)], [1, 5, 5])
     f = oracle.pr_tests(g, 6)
     e01 = [e for e, u, v in _edge_entries(g) if (u, v) == (0, 1)][0]
-    # c(0) = c(1) = 6 <= 2 (1 + 5); 1 + min(5, 5) = 6 >= 6; not PR1, not PR2
+    # c(0) = c(1) = 6 < 2 (1 + 5); 1 + min(5, 5) = 6 >= 6; not PR1, not PR2
     assert f[e01] == PR3 | PR4
     assert oracle.pr_tests(g, 7)[e01] == PR3
     # K_n, unit weights: one edge plus n - 2 two-edge paths = n - 1 = lambda;
-    # PR3 needs n - 1 <= 4
+    # PR3 needs n - 1 < 4
     for n in (4, 5, 6, 8):
         g = gg.complete(n)
         f = oracle.pr_tests(g, n - 1)
         for e, u, v in _edge_entries(g):
             assert f[e] & PR4
-            assert bool(f[e] & PR3) == (n <= 5)
+            assert bool(f[e] & PR3) == (n <= 4)
             assert not f[e] & (PR1 | PR2)
         assert not any(oracle.pr_tests(g, n)[e] & PR4 for e, _, _ in _edge_entries(g))
 
@@ -472,9 +472,10 @@ def test_pr_tests_need_sorted_short_rows():
 
 
 def test_pr_tests_are_sound_by_brute_force():
-    # a passing edge keeps the minimum cut: min(bound, delta, lambda(G/e))
-    # = lambda(G), with the bound a real cut (lambda itself, or delta); PR4
-    # never claims more than the pair's connectivity
+    # contracting a passing edge keeps the minimum cut: min(bound, delta,
+    # lambda(G/e)) = lambda(G), with the bound a real cut (lambda itself, or
+    # delta); so does contracting all passing edges at once, as a round does;
+    # PR4 never claims more than the pair's connectivity
     rng = np.random.default_rng(4242)
     checked = {PR1: 0, PR2: 0, PR3: 0, PR4: 0}
     for trial in range(250):
@@ -497,6 +498,21 @@ def test_pr_tests_are_sound_by_brute_force():
                 assert min(bound, delta, lh) == lam, (trial, bound, f[e])
                 for bit in checked:
                     checked[bit] += bool(f[e] & bit)
+            # every passing edge at once
+            parent = np.arange(g.n)
+
+            def find(x):
+                while parent[x] != x:
+                    x = parent[x]
+                return x
+            for e, u, v in _edge_entries(g):
+                if f[e]:
+                    a, b = find(u), find(v)
+                    parent[max(a, b)] = min(a, b)
+            lab = np.array([find(x) for x in range(g.n)])
+            h, _ = oracle.contract(g, lab)
+            lh = oracle.bruteforce(h)[0] if h.n >= 2 else bound
+            assert min(bound, delta, lh) == lam, (trial, bound, "all")
         # PR4's path sum never exceeds the pair's connectivity
         for e, u, v in _edge_entries(g):
             f1 = oracle.pr_tests(g, int(conn[u, v]) + 1)
