@@ -107,6 +107,11 @@ typedef struct mc_options {
                               clamped to what LDS holds; 0 = default (3) */
   int32_t sort_tile;       /* keys per radix-sort workgroup: 2048, 4096 or
                               8192; 0 = default (4096) */
+  int32_t pr_triangle_deg; /* 0 (default): Padberg-Rinaldi tests PR1 and PR2
+                              only.  > 0: also the triangle tests PR3 and PR4
+                              (see mc_debug_pr_tests) on edges whose two rows
+                              hold at most this many entries in increasing
+                              neighbour order */
   int32_t approx_ppm;      /* 0 (default): exact.  1 .. 499999: Matula's
                               (2+eps)-approximation with eps = approx_ppm /
                               10^6 (the paper names it beside NOI: the
@@ -208,6 +213,21 @@ int mc_viecut_bound(const mc_batch* b, void* stream, const mc_options* opt, int6
  * DEVICE int32[n], labels in [0, n).  Self-loops are ignored; a vertex
  * without neighbours keeps its label. */
 int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labels_out, void* stream);
+
+/* Test hook for the Padberg-Rinaldi tests (the heuristics of Padberg and
+ * Rinaldi that the paper applies in its clustering bound and names in its
+ * related work; their conditions are not restated there).  For every entry
+ * e = (u, v) with u < v, flags[e] (DEVICE uint8[nnz]) receives bit 1 if
+ * c(e) >= lhat (PR1), bit 2 if 2 c(e) > c(u) or 2 c(e) > c(v) (PR2), bit 4 if
+ * some common neighbour w != u, v has c(u) < 2 (c(e) + c(u,w)) and
+ * c(v) < 2 (c(e) + c(v,w)) (PR3), bit 8 if c(e) + sum over common
+ * neighbours of min(c(u,w), c(v,w)) >= lhat (PR4); every other entry gets 0.
+ * c(e) is the entry's weight and c(x) the weighted degree without
+ * self-loops; PR3 and PR4 are evaluated only where both rows hold at most
+ * max_deg entries in strictly increasing neighbour order (else bits 4 and 8
+ * are 0).  These are the tests the solve applies (PR3 and PR4 when
+ * opt->pr_triangle_deg > 0). */
+int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max_deg, uint8_t* flags);
 
 /* Test hook for the contraction step alone (section "Parallel Graph
  * Contraction"): labels (DEVICE int32[n], values in [0, n_new)) name each

@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
                 ("sweep_handoff", ctypes.c_int32), ("viecut_stop", ctypes.c_int32),
                 ("viecut_levels", ctypes.c_int32), ("sweep_threads", ctypes.c_int32),
                 ("sweep_groups", ctypes.c_int32), ("sort_tile", ctypes.c_int32),
-                ("approx_ppm", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("pr_triangle_deg", ctypes.c_int32), ("approx_ppm", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -133,6 +134,8 @@ def _load():
     lib.mc_debug_contract.restype = ctypes.c_int
     lib.mc_debug_lp_sweep.argtypes = [vp, vp, vp, vp]
     lib.mc_debug_lp_sweep.restype = ctypes.c_int
+    lib.mc_debug_pr_tests.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
+    lib.mc_debug_pr_tests.restype = ctypes.c_int
     lib.mc_viecut_bound.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_viecut_bound.restype = ctypes.c_int
     lib.mc_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
@@ -388,6 +391,22 @@ def debug_lp_sweep(row_ptr, col, w, labels, *, stream=None):
     if rc != MC_OK:
         raise MincutError(rc, "mc_debug_lp_sweep")
     return out
+
+
+def debug_pr_tests(row_ptr, col, w, lhat: int, max_deg: int = 64, *, stream=None):
+    """Padberg-Rinaldi test outcomes per entry of one graph (device
+    tensors): uint8 tensor of bits PR1 1, PR2 2, PR3 4, PR4 8."""
+    import torch
+    lib = _load()
+    n = row_ptr.numel() - 1
+    g = Graph(n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"))
+    flags = torch.empty(max(col.numel(), 1), dtype=torch.uint8, device=row_ptr.device)
+    rc = lib.mc_debug_pr_tests(ctypes.byref(g), _stream(stream), int(lhat), int(max_deg),
+                               ctypes.c_void_p(flags.data_ptr()))
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_debug_pr_tests")
+    return flags[: col.numel()]
 
 
 def debug_first_round(row_ptr, col, w, vtx_off, *, lhat_in=None, stream=None,

@@ -1015,6 +1015,12 @@ struct Solver {
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
                            cap, tested, ws.parent, ws.ucount, ws.ctl);
       }
+      if (opt.use_pr && opt.pr_triangle_deg > 0) {
+        // the triangle tests: per tested edge both rows (at most the limit)
+        TimedScope t("pr34", (double)nnz * 20);
+        hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
+                           ws.active, opt.pr_triangle_deg, ws.parent, ws.ucount, ws.ctl);
+      }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
       hipLaunchKernelGGL(k_count_roots, gridr(n), dim3(TB), 0, s, n, ws.parent, gid, ws.nnew);
@@ -1386,6 +1392,33 @@ int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labe
            &ws.ctl->lp_items, ws.vc.best};
   lp_items_prefix(L, ws, s);
   lp_sweep(L, ncu, s);
+  MC_HIP(hipStreamSynchronize(s));
+  MC_HIP(hipGetLastError());
+  return MC_OK;
+}
+
+// weighted degree of every row without self-loops (test hooks only)
+__global__ void k_row_degrees(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, int64_t* cdeg) {
+  for (int64_t u = mc::gtid(); u < n; u += mc::gstride()) {
+    int64_t d = 0;
+    for (int64_t e = rp[u]; e < rp[u + 1]; ++e)
+      if (col[e] != (int32_t)u) d += w[e];
+    cdeg[u] = d;
+  }
+}
+
+int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max_deg, uint8_t* flags) {
+  using namespace mc;
+  if (!g || !flags || g->n < 1 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w))) return MC_EINVAL;
+  std::lock_guard<std::mutex> lock(api_mutex());
+  Workspace& ws = global_ws();
+  int rc = ensure(ws, g->n, g->nnz, 1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(grid_for(g->n, 256, 65536));
+  hipLaunchKernelGGL(k_row_degrees, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg);
+  hipLaunchKernelGGL(k_pr_flags, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg, lhat, max_deg,
+                     flags);
   MC_HIP(hipStreamSynchronize(s));
   MC_HIP(hipGetLastError());
   return MC_OK;

@@ -479,6 +479,92 @@ __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
 
+// The triangle tests of edge (u, v), c = its entry's weight: PR3 (a common
+// neighbour w with c(u) < 2 (c + c(u,w)) and c(v) < 2 (c + c(v,w))) and PR4
+// (c + the sum over common neighbours of min(c(u,w), c(v,w)) >= lambda-hat).
+// Strict PR3 holds for every non-trivial minimum cut at once, PR4 bounds
+// lambda(u, v) from below, so passing edges contract together with the
+// round's other unions.  Evaluated only when both rows hold at most max_deg
+// entries in strictly increasing neighbour order (then c(u,w) is one entry;
+// contracted graphs always are); one merge walks both rows to their ends,
+// checking the order as it goes.  Returns bit 4 (PR3) and bit 8 (PR4).
+__device__ __forceinline__ uint32_t pr34_eval(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
+                                              int32_t u, int32_t v, int64_t c, int64_t lam, int32_t max_deg) {
+  const int64_t a1 = rp[u + 1], b1 = rp[v + 1];
+  int64_t a = rp[u], b = rp[v];
+  if (a1 - a > max_deg || b1 - b > max_deg) return 0;
+  const int64_t du = cdeg[u], dv = cdeg[v];
+  constexpr int32_t END = INT32_MAX;  // past a row's end (vertex ids are below 2^30)
+  int32_t x = a < a1 ? col[a] : END, y = b < b1 ? col[b] : END;
+  int64_t paths = c;
+  bool pr3 = false;
+  while (x != END || y != END) {
+    const bool adv_a = x <= y, adv_b = y <= x;
+    if (x == y && x != u && x != v) {
+      const int64_t cu = w[a], cv = w[b];
+      paths += cu < cv ? cu : cv;
+      pr3 = pr3 || (du < 2 * (c + cu) && dv < 2 * (c + cv));
+    }
+    if (adv_a) {
+      const int32_t px = x;
+      ++a;
+      x = a < a1 ? col[a] : END;
+      if (x != END && x <= px) return 0;
+    }
+    if (adv_b) {
+      const int32_t py = y;
+      ++b;
+      y = b < b1 ? col[b] : END;
+      if (y != END && y <= py) return 0;
+    }
+  }
+  return (pr3 ? 4u : 0u) | (paths >= lam ? 8u : 0u);
+}
+
+// Unions of the edges passing PR3 or PR4 (and not already PR1/PR2 unions).
+__global__ void k_pr34(int64_t nnz, const int32_t* __restrict__ src, const int32_t* __restrict__ col,
+                       const int32_t* __restrict__ w, const int64_t* __restrict__ rp,
+                       const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
+                       const int64_t* __restrict__ lhat, const int32_t* __restrict__ active, int32_t max_deg,
+                       int32_t* parent, int32_t* ucount, Ctl* ctl) {
+  int64_t local = 0;
+  int32_t last = -1;
+  for (int64_t e = gtid(); e < nnz; e += gstride()) {
+    const int32_t u = src[e], v = col[e];
+    if (u >= v) continue;
+    const int32_t g = gid[u];
+    if (!active[g]) continue;
+    const int64_t lam = lhat[g];
+    if (pr_passes(w[e], lam, cdeg[u], cdeg[v])) continue;  // united by the PR1/PR2 pass
+    if (!pr34_eval(rp, col, w, cdeg, u, v, w[e], lam, max_deg)) continue;
+    ++local;
+    pr_flag(ucount, g, last);
+    if (ld_relaxed(parent + u) != ld_relaxed(parent + v)) uf_union(parent, u, v);
+  }
+  if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
+}
+
+// Every test's outcome per entry (u, v), u < v (bits PR1 1, PR2 2, PR3 4,
+// PR4 8; 0 for the other entries), one thread per vertex row.
+__global__ void k_pr_flags(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg, int64_t lam,
+                           int32_t max_deg, uint8_t* flags) {
+  for (int64_t u = gtid(); u < n; u += gstride()) {
+    for (int64_t e = rp[u]; e < rp[u + 1]; ++e) {
+      const int32_t v = col[e];
+      uint32_t f = 0;
+      if ((int32_t)u < v) {
+        const int64_t c = w[e];
+        if (c >= lam) f |= 1;
+        if (2 * c > cdeg[u] || 2 * c > cdeg[v]) f |= 2;
+        f |= pr34_eval(rp, col, w, cdeg, (int32_t)u, v, c, lam, max_deg);
+      }
+      flags[e] = (uint8_t)f;
+    }
+  }
+}
+
 // Graphs that get a full-graph sweep this round: region-mode graphs when the
 // sweep is the scan of choice, and any graph whose scans found no pair.
 __global__ void k_sweep_list(int32_t G, GraphState S, int32_t sweep_region, Ctl* ctl) {
