@@ -152,14 +152,24 @@ __global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const in
 
 // Per-graph minimum weighted degree (the trivial cut, section "Basic
 // Concepts") and weight totals.
-// Each lane keeps a running minimum and sum for the graph it is in and
-// flushes when the graph changes; the last flush is combined per wave.
+// Each thread takes a contiguous range of vertices (graphs are contiguous
+// ranges too, so a thread meets few graph changes), keeps a running minimum
+// and sum for the graph it is in and flushes when the graph changes; the
+// last flush is combined per wave when the wave ends in one graph.
+__device__ __forceinline__ void thread_range(int64_t n, int64_t& a, int64_t& b) {
+  const int64_t t = gstride(), per = (n + t - 1) / t;
+  a = min(n, gtid() * per);
+  b = min(n, a + per);
+}
+
 __global__ void k_min_degree(int32_t n, const int64_t* cdeg, const int32_t* gid,
                              const int32_t* active, uint64_t* bdeg, int64_t* wsum) {
   int32_t cur = -1;
   uint64_t best = ~0ull;
   int64_t sum = 0;
-  for (int64_t v = gtid(); v < n; v += gstride()) {
+  int64_t va, vb;
+  thread_range(n, va, vb);
+  for (int64_t v = va; v < vb; ++v) {
     const int32_t g = gid[v];
     if (active && !active[g]) continue;
     if (g != cur) {
@@ -230,7 +240,9 @@ __global__ void k_union_pairs(const uint64_t* pairs, const Ctl* ctl, int64_t cap
 // CAPFOREST": a disconnected graph leaves vertices unvisited).
 __global__ void k_count_roots(int32_t n, const int32_t* parent, const int32_t* gid, int32_t* cnt) {
   int32_t cur = -1, acc = 0;
-  for (int64_t v = gtid(); v < n; v += gstride()) {
+  int64_t va, vb;
+  thread_range(n, va, vb);
+  for (int64_t v = va; v < vb; ++v) {
     if (parent[v] != v) continue;
     const int32_t g = gid[v];
     if (g != cur) {
