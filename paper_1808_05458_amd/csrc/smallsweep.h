@@ -132,9 +132,12 @@ __device__ __forceinline__ bool ss_relax(LDS& L, const SmallSweepArgs& A, int32_
 // other wave active); -1 when none is left.  Among equal keys the lowest
 // chunk and the lowest vertex in it are taken (any maximum is a legal next
 // vertex).  The caller visits the vertex, so its chunk's bound drops to the
-// largest key left in the chunk.
+// largest key left in the chunk.  Once the chunk is known every lane loads
+// its vertex's row bounds and degree, so the winner's are in flight while
+// the chunk is scanned: (ra, rb, cd) of the returned vertex.
 template <class LDS>
-__device__ __forceinline__ int32_t ss_select(LDS& L, int32_t ng, uint32_t& rx) {
+__device__ __forceinline__ int32_t ss_select(LDS& L, const SmallSweepArgs& A, int32_t v0, int32_t ng,
+                                             uint32_t& rx, int64_t& ra, int64_t& rb, int64_t& cd) {
   constexpr int NC = LDS::NC;
   const int lane = lane_id();
   const int nc = (ng + 63) >> 6;
@@ -150,6 +153,8 @@ __device__ __forceinline__ int32_t ss_select(LDS& L, int32_t ng, uint32_t& rx) {
     const int holder = (int)__builtin_ctzll(ballot(mine == bound));
     const int c = __builtin_amdgcn_readlane(mine_c, holder);
     const int32_t v = c * 64 + lane;
+    const int32_t vq = v < ng ? v : ng - 1;
+    const int64_t la = A.rp[v0 + vq], lb = A.rp[v0 + vq + 1], lc = A.cdeg[v0 + vq];
     const uint32_t key = (v < ng && ss_state(L, v) == 0) ? (uint32_t)L.r[v] : 0u;
     const uint32_t exact = wave_max_u32(key);
     if (exact == bound) {
@@ -157,6 +162,9 @@ __device__ __forceinline__ int32_t ss_select(LDS& L, int32_t ng, uint32_t& rx) {
       const uint32_t rest = wave_max_u32(lane == at ? 0u : key);
       if (lane == 0) L.cmax[c] = rest;
       rx = exact;
+      ra = readlane_i64(la, at);
+      rb = readlane_i64(lb, at);
+      cd = readlane_i64(lc, at);
       return c * 64 + at;
     }
     if (lane == 0) L.cmax[c] = exact;  // the bound was stale: lower it, retry
@@ -226,11 +234,15 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
           ss_wave_sync();
           int32_t xl = L.first;
           uint32_t rx = 0;  // r of the first vertex is 0: nothing is visited yet
+          int64_t e0 = 0, e1 = 0, dx = 0;
           if (xl >= 0) {
             ss_wave_sync();
             if (lane == 0) L.first = -1;
+            e0 = A.rp[v0 + xl];
+            e1 = A.rp[v0 + xl + 1];
+            dx = A.cdeg[v0 + xl];
           } else {
-            xl = ss_select(L, ng, rx);
+            xl = ss_select(L, A, v0, ng, rx, e0, e1, dx);
           }
           if (xl < 0) { done = true; break; }
           ++stamp;
@@ -239,8 +251,6 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
             reinterpret_cast<int32_t*>(A.fb_rs + v0 + xl)[1] = stamp;
           }
           ss_wave_sync();
-          const int64_t e0 = A.rp[v0 + xl], e1 = A.rp[v0 + xl + 1];
-          const int64_t dx = A.cdeg[v0 + xl];
           int64_t rows = 0, internal = 0;  // unused here: the degree comes from cdeg
           for (int64_t base = e0; base < e1; base += 64) {
             const int64_t e = base + lane;
