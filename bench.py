@@ -43,7 +43,7 @@ def cpu_baseline():
                       f"(n={g.n}, m={g.m}, lambda={lam}, {rounds} rounds) in {dt:.2f} s"}
 
 
-def batched_form(steps, warmup):
+def batched_form(steps, warmup, loop=True):
     """The 4096-graph batch (planted clusters, n log-uniform in [64, 8192],
     2-16 clusters, intra degree U[8, 32], 1-4 inter edges per cluster pair,
     weights U[1, 100]) solved as one packed CSR, against a host loop of
@@ -83,6 +83,13 @@ def batched_form(steps, warmup):
     sides_ok = bool(np.array_equal(cut // 2, ref))
     log(f"batch packed: {dt_packed * 1e3:.1f} ms, {st['rounds']} rounds, lambdas equal: {packed_ok}, "
         f"side weights equal: {sides_ok}")
+    out = {"graphs": len(graphs), "sum_n": packed.n, "sum_m": packed.m,
+           "packed": {"ms": round(dt_packed * 1e3, 2), "edges_per_s": packed.m / dt_packed,
+                      "rounds": st["rounds"], "steps": steps},
+           "autotune": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tune.items()},
+           "verified": {"lambdas_equal_oracle": packed_ok, "side_weights_equal": sides_ok}}
+    if not loop:
+        return out
     # the loop: one single-graph solve per graph, same device-resident CSRs
     dev = [mc.to_device(g, "cuda:0") for g in graphs]
     for g in dev[:16]:
@@ -94,13 +101,10 @@ def batched_form(steps, warmup):
     dt_loop = time.perf_counter() - t0
     loop_ok = bool(np.array_equal(np.asarray(looped), ref))
     log(f"batch looped: {dt_loop * 1e3:.1f} ms, lambdas equal: {loop_ok}")
-    return {"graphs": len(graphs), "sum_n": packed.n, "sum_m": packed.m,
-            "packed": {"ms": round(dt_packed * 1e3, 2), "edges_per_s": packed.m / dt_packed,
-                       "rounds": st["rounds"], "steps": steps},
-            "looped": {"ms": round(dt_loop * 1e3, 2), "edges_per_s": packed.m / dt_loop},
-            "speedup": round(dt_loop / dt_packed, 2),
-            "autotune": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tune.items()},
-            "verified": {"lambdas_equal_oracle": packed_ok and loop_ok, "side_weights_equal": sides_ok}}
+    out["looped"] = {"ms": round(dt_loop * 1e3, 2), "edges_per_s": packed.m / dt_loop}
+    out["speedup"] = round(dt_loop / dt_packed, 2)
+    out["verified"]["lambdas_equal_oracle"] = packed_ok and loop_ok
+    return out
 
 
 def rmat_form(steps):
@@ -235,6 +239,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-rmat", action="store_true")
     ap.add_argument("--no-approx", action="store_true", help="skip the (2+eps)-approximation runs")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="batched form: skip the loop of single solves (profiling the packed solve alone)")
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--pool", type=int, default=32)
     ap.add_argument("--lanes", type=int, default=3)
@@ -271,7 +277,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.workload == "batched":
-        b = batched_form(args.steps, args.warmup)
+        b = batched_form(args.steps, args.warmup, loop=not args.no_loop)
         out = {"metric": "batched exact min-cut edges/s (sum of m / packed solve time) at 1 GPU",
                "value": b["packed"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["packed"]["ms"],
