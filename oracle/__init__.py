@@ -55,7 +55,7 @@ def _load():
         lib.mco_pr_tests.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
         lib.mco_lp_sweep.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         i32 = ctypes.c_int32
-        lib.mco_viecut.argtypes = [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp]
+        lib.mco_viecut.argtypes = [i32, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -150,14 +150,15 @@ def lp_sweep(g, labels):
     return out
 
 
-def viecut(g, sweeps: int = 2, stop_n: int = 2, max_levels: int = 32):
-    """VieCut-style upper bound: (lambda-hat, side, levels)."""
+def viecut(g, sweeps: int = 2, stop_n: int = 2, max_levels: int = 32, exact_finish: bool = False):
+    """VieCut-style upper bound: (lambda-hat, side, levels); exact_finish
+    solves the last level graph exactly."""
     rp, col, w = _arrs(g)
     lam = np.zeros(1, np.int64)
     side = np.zeros(g.n, np.uint8)
     levels = np.zeros(1, np.int32)
-    _check(_load().mco_viecut(g.n, _p(rp), _p(col), _p(w), sweeps, stop_n, max_levels, _p(lam),
-                              _p(side), _p(levels)), "viecut")
+    _check(_load().mco_viecut(g.n, _p(rp), _p(col), _p(w), sweeps, stop_n, max_levels, int(exact_finish),
+                              _p(lam), _p(side), _p(levels)), "viecut")
     return int(lam[0]), side, int(levels[0])
 
 

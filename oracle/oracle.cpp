@@ -413,8 +413,11 @@ void lp_sweep(const WGraph& g, const std::vector<int32_t>& cur, std::vector<int3
 // vertices, the bound is above 0, fewer than max_levels levels ran and the
 // last level removed at least a tenth of the vertices.  Every vertex of a
 // contracted graph is a vertex set of G, so every bound is a real cut value.
+// exact_finish: the last level graph is solved exactly (O3), as the
+// clustering algorithm finishes in the paper's description of it, and its
+// minimum cut (a cut of G) lowers the bound.
 int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i64* lambda,
-           uint8_t* side_out, int32_t* levels_out) {
+           uint8_t* side_out, int32_t* levels_out, int32_t exact_finish = 0) {
   const int32_t n0 = in.n;
   if (n0 < 2) return -2;
   WGraph g = from_input(in);
@@ -469,6 +472,18 @@ int viecut(const Csr& in, int32_t sweeps, int32_t stop_n, int32_t max_levels, i6
       bound();
     }
     if ((int64_t)g.n * 10 > (int64_t)n_before * 9) break;  // shrank by less than a tenth
+  }
+  if (exact_finish && g.n > 2 && lhat > 0) {
+    std::vector<int32_t> w32(g.w.size());
+    for (size_t i = 0; i < g.w.size(); ++i) w32[i] = (int32_t)g.w[i];
+    i64 lg = 0;
+    std::vector<uint8_t> sg(g.n);
+    int rc = noi(Csr{g.n, g.rp.data(), g.col.data(), w32.data()}, 1, &lg, sg.data(), nullptr);
+    if (rc) return rc;
+    if (lg < lhat) {
+      lhat = lg;
+      for (int32_t v = 0; v < n0; ++v) side[v] = sg[map[v]];
+    }
   }
   *lambda = lhat;
   if (side_out) std::memcpy(side_out, side.data(), n0);
@@ -594,8 +609,9 @@ int mco_lp_sweep(int32_t n, const int64_t* rp, const int32_t* col, const int32_t
 }
 
 int mco_viecut(int32_t n, const int64_t* rp, const int32_t* col, const int32_t* w, int32_t sweeps,
-               int32_t stop_n, int32_t max_levels, int64_t* lambda, uint8_t* side, int32_t* levels) {
-  return viecut(Csr{n, rp, col, w}, sweeps, stop_n, max_levels, lambda, side, levels);
+               int32_t stop_n, int32_t max_levels, int32_t exact_finish, int64_t* lambda, uint8_t* side,
+               int32_t* levels) {
+  return viecut(Csr{n, rp, col, w}, sweeps, stop_n, max_levels, lambda, side, levels, exact_finish);
 }
 
 }  // extern "C"

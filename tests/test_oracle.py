@@ -518,3 +518,47 @@ def test_pr_tests_are_sound_by_brute_force():
             f1 = oracle.pr_tests(g, int(conn[u, v]) + 1)
             assert not f1[e] & PR4
     assert min(checked.values()) > 20, checked
+
+
+# ----------------------------------- clustering bound with an exact finish
+def test_viecut_exact_finish_without_levels_is_lambda():
+    # no clustering level: the last level graph is G itself, solved exactly
+    rng = np.random.default_rng(515)
+    for trial in range(300):
+        n = int(rng.integers(3, 13))
+        g = random_graph(rng, n, float(rng.uniform(0.15, 1.0)), int(rng.choice([1, 3, 20])),
+                         connected=bool(rng.random() < 0.9))
+        lam = oracle.bruteforce(g)[0]
+        b, side, levels = oracle.viecut(g, max_levels=0, exact_finish=True)
+        assert levels == 0 and b == lam, trial
+        check_side(g, b, side)
+
+
+def test_viecut_exact_finish_never_worse():
+    rng = np.random.default_rng(516)
+    for trial in range(300):
+        n = int(rng.integers(3, 14))
+        g = random_graph(rng, n, float(rng.uniform(0.15, 1.0)), int(rng.choice([1, 3, 20])))
+        lam = oracle.bruteforce(g)[0]
+        for stop in (2, 4, 8):
+            plain = oracle.viecut(g, stop_n=stop)[0]
+            b, side, _ = oracle.viecut(g, stop_n=stop, exact_finish=True)
+            assert lam <= b <= plain, (trial, stop)
+            check_side(g, b, side)
+
+
+def test_viecut_exact_finish_on_workload_shapes():
+    # stopping the levels at 64 vertices leaves level graphs whose minimum
+    # degree is far above lambda on some batch graphs; solving them exactly
+    # recovers lambda (from the independent NOI route)
+    lowered = 0
+    for g in [gg.planted_4096()] + [gg.batch_graph(i) for i in range(0, 400, 37)]:
+        lam = oracle.noi(g, 1)[0]
+        plain = oracle.viecut(g, stop_n=64)[0]
+        b, side, _ = oracle.viecut(g, stop_n=64, exact_finish=True)
+        assert lam <= b <= plain
+        assert oracle.cut_value(g, side) == b
+        lowered += b < plain
+        if g.name in ("batch_74", "batch_222"):
+            assert plain > lam and b == lam, g.name
+    assert lowered >= 2
