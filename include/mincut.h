@@ -112,6 +112,11 @@ typedef struct mc_options {
                               (see mc_debug_pr_tests) on edges whose two rows
                               hold at most this many entries in increasing
                               neighbour order */
+  int32_t viecut_exact;    /* mc_viecut_bound only: 1 = finish the clustering
+                              levels by solving the last level graph exactly
+                              (its minimum cut, a cut of G, lowers the
+                              bound, as the clustering algorithm ends in the
+                              paper); 0 (default) = the levels' bound alone */
   int32_t approx_ppm;      /* 0 (default): exact.  1 .. 499999: Matula's
                               (2+eps)-approximation with eps = approx_ppm /
                               10^6 (the paper names it beside NOI: the

@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
                 ("sweep_handoff", ctypes.c_int32), ("viecut_stop", ctypes.c_int32),
                 ("viecut_levels", ctypes.c_int32), ("sweep_threads", ctypes.c_int32),
                 ("sweep_groups", ctypes.c_int32), ("sort_tile", ctypes.c_int32),
-                ("pr_triangle_deg", ctypes.c_int32), ("approx_ppm", ctypes.c_int32),
+                ("pr_triangle_deg", ctypes.c_int32), ("viecut_exact", ctypes.c_int32),
+                ("approx_ppm", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):

@@ -709,7 +709,16 @@ struct Solver {
   // new bound is written at once.  The input graph's entries, sources and
   // degrees are left as they are for the exact loop, and no union found
   // here enters it.
-  int viecut(const Problem& P, GraphState S, const int32_t* gid_in, uint8_t* side) {
+  // The last level graph, when the clustering bound is finished exactly.
+  struct LevelGraph {
+    int32_t n;
+    int64_t nnz;
+    const int64_t* rp;
+    const int32_t *col, *w, *src, *gid;
+    const int64_t* cdeg;
+  };
+
+  int viecut(const Problem& P, GraphState S, const int32_t* gid_in, uint8_t* side, LevelGraph* last = nullptr) {
     const int32_t G = P.G, N = P.n;
     int rc = ensure_vc(ws, N, P.nnz, G);
     if (rc) return rc;
@@ -719,6 +728,9 @@ struct Solver {
     const int32_t stop = opt.viecut_stop > 0 ? opt.viecut_stop : 2;
     const int32_t max_levels = opt.viecut_levels > 0 ? opt.viecut_levels : 32;
     const int32_t sweeps = std::max(0, opt.lp_sweeps);
+    // with the exact finish, graphs that stop keep their last level graph in
+    // the level graphs that follow
+    const int32_t carry = last != nullptr ? 1 : 0;
     MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
     hipLaunchKernelGGL(k_vc_init, grid(G), dim3(TB), 0, s, G, S, stop, V.act, V.n0, ws.ctl);
     hipLaunchKernelGGL(k_iota, grid(N), dim3(TB), 0, s, V.map, N);
@@ -749,7 +761,7 @@ struct Solver {
                                                 ws.tmp, s);
       MC_HIP(hipMemsetAsync(&ws.ctl->n_active, 0, sizeof(int32_t), s));
       hipLaunchKernelGGL(k_vc_level, grid(G), dim3(TB), 0, s, G, S, ws.nvoff, stop, end_of_level, last_level,
-                         V.act, V.n0, ws.ctl);
+                         carry, V.act, V.n0, ws.ctl);
       hipLaunchKernelGGL(k_compose_map, grid(N), dim3(TB), 0, s, N, V.map, ws.lab);
       if (side) {
         TimedScope t("side", (double)N * 13);
@@ -789,12 +801,12 @@ struct Solver {
         }
         // classes numbered by label value
         fill<int32_t>(V.flag, 0, n, s);
-        hipLaunchKernelGGL(k_lp_flag, grid(n), dim3(TB), 0, s, n, cur, gid, V.act, V.flag);
+        hipLaunchKernelGGL(k_lp_flag, grid(n), dim3(TB), 0, s, n, cur, gid, V.act, carry, V.flag);
         exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{V.flag}, n, ws.newid, &ws.ctl->n_next,
                                                   ws.tmp, s);
         fill<int32_t>(ws.nnew, 0, G, s);
-        hipLaunchKernelGGL(k_lp_relabel, grid(n), dim3(TB), 0, s, n, cur, gid, V.act, V.flag, ws.newid, ws.lab,
-                           V.gid[next], ws.nnew);
+        hipLaunchKernelGGL(k_lp_relabel, grid(n), dim3(TB), 0, s, n, cur, gid, V.act, carry, V.flag, ws.newid,
+                           ws.lab, V.gid[next], ws.nnew);
       }
       rc = read_ctl();
       if (rc) return rc;
@@ -814,11 +826,11 @@ struct Solver {
           hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, src, col, w, cdeg, gid, ws.lhat, V.act,
                              ws.parent, ws.ucount, ws.ctl);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
-          exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, V.act}, n, ws.newid, &ws.ctl->n_next, ws.tmp,
-                                            s);
+          exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, V.act, carry}, n, ws.newid, &ws.ctl->n_next,
+                                            ws.tmp, s);
           fill<int32_t>(ws.nnew, 0, G, s);
-          hipLaunchKernelGGL(k_relabel, grid(n), dim3(TB), 0, s, n, ws.parent, gid, V.act, ws.newid, ws.lab,
-                             V.gid[next], ws.nnew);
+          hipLaunchKernelGGL(k_relabel, grid(n), dim3(TB), 0, s, n, ws.parent, gid, V.act, carry, ws.newid,
+                             ws.lab, V.gid[next], ws.nnew);
         }
         rc = read_ctl();
         if (rc) return rc;
@@ -828,6 +840,14 @@ struct Solver {
     }
     vc_levels_run = level;
     MC_HIP(hipMemsetAsync(&ws.ctl->n_active, 0, sizeof(int32_t), s));
+    if (last) {
+      // hand the last level graph to the exact loop: its map becomes the
+      // loop's original -> current map
+      hipLaunchKernelGGL(k_vc_exact_start, grid(G), dim3(TB), 0, s, G, S, ws.ctl);
+      MC_HIP(hipMemcpyAsync(ws.map, V.map, (size_t)N * 4, hipMemcpyDeviceToDevice, s));
+      *last = LevelGraph{n, nnz, rp, col, w, src, gid, cdeg};
+      return MC_OK;
+    }
     hipLaunchKernelGGL(k_vc_done, grid(G), dim3(TB), 0, s, G, S, ws.ctl);
     return MC_OK;
   }
@@ -943,10 +963,14 @@ struct Solver {
     // bound from the caller or the clustering bound may enable PR1)
     // (Matula's bound lies below the best cut, so its tests always run)
     const bool approx = opt.approx_ppm > 0;
-    const bool pr_first_round = ws.ctl_host->n_pr > 0 || lhat_in != nullptr || opt.use_viecut || approx;
+    // the clustering bound finished exactly: the exact loop runs on the last
+    // level graph, starting from the clustering bound
+    const bool finish = viecut_only && opt.viecut_exact;
+    const bool pr_first_round =
+        ws.ctl_host->n_pr > 0 || lhat_in != nullptr || opt.use_viecut || approx || finish;
     // in the first round only the graphs marked in prok are tested, unless a
     // lower starting bound may have enabled PR1 elsewhere
-    const bool pr_first_all = lhat_in != nullptr || opt.use_viecut || approx;
+    const bool pr_first_all = lhat_in != nullptr || opt.use_viecut || approx || finish;
     // the bound the round's tests and scans contract with: the best cut
     // found (exact), or Matula's (1/2 - eps) delta below it
     const int64_t* cap = approx ? ws.kcap : ws.lhat;
@@ -956,8 +980,9 @@ struct Solver {
       st->lambda_initial = l0[0];
       st->lambda_viecut = -1;
     }
+    LevelGraph last{};
     if (opt.use_viecut || viecut_only) {
-      rc = viecut(P, S, gid, side);
+      rc = viecut(P, S, gid, side, finish ? &last : nullptr);
       if (rc) return rc;
       rc = read_ctl();
       if (rc) return rc;
@@ -965,7 +990,7 @@ struct Solver {
         MC_HIP(hipMemcpyAsync(&st->lambda_viecut, ws.lhat, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
       }
-      if (viecut_only) {
+      if (viecut_only && !finish) {
         if (want_side) {
           hipLaunchKernelGGL(k_normalize_side, grid(G), dim3(TB), 0, s, G, ws.voff, side, ws.flip);
           hipLaunchKernelGGL(k_apply_flip, grid(N), dim3(TB), 0, s, N, ws.ogid, ws.flip, side);
@@ -982,6 +1007,20 @@ struct Solver {
     const int64_t* rp = P.rp;
     const int32_t* col = P.col;
     const int32_t* w = P.w;
+    if (finish) {
+      // the last level graph is the input: its entry sources, degrees and
+      // graph ids go where the loop reads the input's
+      n = last.n;
+      nnz = last.nnz;
+      rp = last.rp;
+      col = last.col;
+      w = last.w;
+      if (last.src != ws.src && nnz > 0)
+        MC_HIP(hipMemcpyAsync(ws.src, last.src, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
+      if (last.cdeg != ws.cdeg)
+        MC_HIP(hipMemcpyAsync(ws.cdeg, last.cdeg, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+      if (last.gid != gid) MC_HIP(hipMemcpyAsync(gid, last.gid, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    }
     int32_t n_active = ws.ctl_host->n_active;
     int round = 0;
     dump("ingest", n, nnz, rp, col, w);
@@ -1133,10 +1172,10 @@ struct Solver {
           MC_HIP(hipStreamSynchronize(s));
           return MC_OK;
         }
-        exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, ws.active}, n, ws.newid,
+        exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, ws.active, 0}, n, ws.newid,
                                           &ws.ctl->n_next, ws.tmp, s);
         fill<int32_t>(ws.nnew, 0, G, s);
-        hipLaunchKernelGGL(k_relabel, grid(n), dim3(TB), 0, s, n, ws.parent, gid, ws.active,
+        hipLaunchKernelGGL(k_relabel, grid(n), dim3(TB), 0, s, n, ws.parent, gid, ws.active, 0,
                            ws.newid, ws.lab, gid_next, ws.nnew);
       }
       hipLaunchKernelGGL(k_update_alpha, grid(G), dim3(TB), 0, s, G, S, ws.scan_k, ws.ctl);

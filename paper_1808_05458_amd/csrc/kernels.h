@@ -619,17 +619,18 @@ struct RootFlag {
   const int32_t* parent;
   const int32_t* gid;
   const int32_t* keep;  // per graph
+  int32_t carry;        // 1: every graph is kept
   __device__ __forceinline__ int32_t operator()(int64_t v) const {
-    return (parent[v] == v && keep[gid[v]]) ? 1 : 0;
+    return (parent[v] == v && (carry || keep[gid[v]])) ? 1 : 0;
   }
 };
 
 __global__ void k_relabel(int32_t n, const int32_t* parent, const int32_t* gid, const int32_t* keep,
-                          const int32_t* newid, int32_t* lab, int32_t* ngid, int32_t* nnew) {
+                          int32_t carry, const int32_t* newid, int32_t* lab, int32_t* ngid, int32_t* nnew) {
   for (int64_t v = gtid(); v - lane_id() < n; v += gstride()) {  // wave-uniform bound
     const bool ok = v < n;
     const int32_t g = ok ? gid[v] : -1;
-    const bool kept = ok && keep[g];
+    const bool kept = ok && (carry || keep[g]);
     bool root = false;
     if (ok) {
       const int32_t r = parent[v];
@@ -826,11 +827,19 @@ __global__ void k_vc_init(int32_t G, GraphState S, int32_t stop, int32_t* vc_act
 // lambda-hat (each of its vertices is a vertex set of the input graph).
 // end_of_level: also stop graphs that shrank by less than a tenth over the
 // level, or reached the level limit.
+// carry: graphs that stopped stay in the level graph (as themselves), so
+// their counts and offsets follow it.
 __global__ void k_vc_level(int32_t G, GraphState S, const int32_t* nvoff_scan, int32_t stop, int32_t end_of_level,
-                           int32_t last_level, int32_t* vc_act, int32_t* vc_n0, Ctl* ctl) {
+                           int32_t last_level, int32_t carry, int32_t* vc_act, int32_t* vc_n0, Ctl* ctl) {
   for (int64_t g = gtid(); g < G; g += gstride()) {
     S.rec_type[g] = REC_NONE;
-    if (!vc_act[g]) continue;
+    if (!vc_act[g]) {
+      if (carry) {
+        S.n[g] = S.nnew[g];
+        S.cvoff[g] = nvoff_scan[g];
+      }
+      continue;
+    }
     const int32_t nn = S.nnew[g];
     S.n[g] = nn;
     S.cvoff[g] = nvoff_scan[g];
@@ -852,6 +861,18 @@ __global__ void k_vc_level(int32_t G, GraphState S, const int32_t* nvoff_scan, i
     }
     vc_act[g] = go ? 1 : 0;
     if (go) atomicAdd(&ctl->n_active, 1);
+  }
+}
+
+// The last level graphs become the exact loop's input (the exact finish):
+// their counts and offsets stay; a graph with at most two vertices or a zero
+// bound is final.
+__global__ void k_vc_exact_start(int32_t G, GraphState S, Ctl* ctl) {
+  for (int64_t g = gtid(); g < G; g += gstride()) {
+    S.rec_type[g] = REC_NONE;
+    const int32_t act = (S.active[g] && S.n[g] > 2 && S.lhat[g] > 0) ? 1 : 0;
+    S.active[g] = act;
+    if (act) atomicAdd(&ctl->n_active, 1);
   }
 }
 

@@ -233,21 +233,26 @@ __global__ void k_lp_finish(LpArgs A) {
 
 // Label classes -> dense block ids, numbered by label value: flag every label
 // in use, prefix-sum the flags, then look each vertex's label up.
+// carry: graphs not swept keep every vertex as a class of its own (their
+// labels were not written), so the level graph still holds them.
 __global__ void k_lp_flag(int32_t n, const int32_t* label, const int32_t* gid, const int32_t* active,
-                          int32_t* flag) {
-  for (int64_t v = gtid(); v < n; v += gstride())
+                          int32_t carry, int32_t* flag) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
     if (active[gid[v]]) flag[label[v]] = 1;
+    else if (carry) flag[v] = 1;
+  }
 }
 
 __global__ void k_lp_relabel(int32_t n, const int32_t* label, const int32_t* gid, const int32_t* active,
-                             const int32_t* flag, const int32_t* newid, int32_t* lab, int32_t* ngid,
-                             int32_t* nnew) {
+                             int32_t carry, const int32_t* flag, const int32_t* newid, int32_t* lab,
+                             int32_t* ngid, int32_t* nnew) {
   for (int64_t v = gtid(); v - lane_id() < n; v += gstride()) {  // wave-uniform bound
     const bool ok = v < n;
     const int32_t g = ok ? gid[v] : -1;
-    const bool kept = ok && active[g];
+    const bool swept = ok && active[g];
+    const bool kept = swept || (ok && carry);
     const bool head = kept && flag[v];  // v is the label of a class (of its own graph)
-    if (ok) lab[v] = kept ? newid[label[v]] : -1;
+    if (ok) lab[v] = kept ? newid[swept ? label[v] : (int32_t)v] : -1;
     if (head) ngid[newid[v]] = g;
     wave_add_by_key(nnew, g, 1, head);
   }

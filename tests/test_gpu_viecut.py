@@ -81,17 +81,17 @@ def test_lp_sweep_equals_oracle():
         assert np.array_equal(out, ref), (g.name, np.flatnonzero(out != ref)[:8])
 
 
-def _bounds_equal(graphs, sweeps=2, stop=2, levels=32, **extra):
+def _bounds_equal(graphs, sweeps=2, stop=2, levels=32, exact=False, **extra):
     import paper_1808_05458_amd as mc
     packed, vo, eo = gg.pack(graphs)
     rp, col, w = mc.to_device(packed, "cuda")
-    announce("viecut bound", len(graphs), packed.n, packed.m, sweeps, stop, levels)
+    announce("viecut bound", len(graphs), packed.n, packed.m, sweeps, stop, levels, exact)
     bounds, sides, lv = mc.viecut_bound(rp, col, w, vo, lp_sweeps=sweeps, viecut_stop=stop,
-                                        viecut_levels=levels, **extra)
+                                        viecut_levels=levels, viecut_exact=int(exact), **extra)
     s = sides.cpu().numpy()
     most = 0
     for i, g in enumerate(graphs):
-        b, _, l = oracle.viecut(g, sweeps=sweeps, stop_n=stop, max_levels=levels)
+        b, _, l = oracle.viecut(g, sweeps=sweeps, stop_n=stop, max_levels=levels, exact_finish=exact)
         assert bounds[i] == b, (i, g.name, bounds[i], b)
         check_side(g, b, s[vo[i]:vo[i + 1]])
         most = max(most, l)
@@ -156,3 +156,24 @@ def test_exact_solve_from_viecut_bound():
         assert lam == oracle.noi(g, 3)[0]
         assert st["lambda_viecut"] >= lam
         check_side(g, lam, side.cpu().numpy()[: g.n])
+
+
+@pytest.mark.parametrize("stop,levels", [(64, 32), (2, 32), (256, 2), (16, 1)])
+def test_viecut_exact_finish(stop, levels):
+    # the last level graph of every graph solved exactly: graphs stop at
+    # different levels, and those that stop early stay in the later level
+    # graphs as they are
+    graphs = [gg.batch_graph(i) for i in range(40, 160)] + [gg.planted_4096()]
+    _bounds_equal(graphs, stop=stop, levels=levels, exact=True)
+
+
+def test_viecut_exact_finish_mixed_shapes():
+    rng = np.random.default_rng(18)
+    graphs = [gg.two_cliques(9, 2), gg.complete(5), gg.from_edges(2, [(0, 1)], [9]),
+              gg.from_edges(6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)])]  # disconnected: 0
+    graphs += [random_graph(rng, int(rng.integers(3, 40)), 0.3, 20) for _ in range(30)]
+    graphs.append(gg.chung_lu(9, 1 << 15, 2.5, 16.0, 1, 50, kcore=0, lcc=True))
+    bounds = _bounds_equal(graphs, stop=32, exact=True)
+    # the exact finish reaches lambda where the levels stopped above it
+    lams = [oracle.noi(g, 1)[0] for g in graphs]
+    assert all(b >= l for b, l in zip(bounds, lams))
