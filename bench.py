@@ -107,6 +107,55 @@ def batched_form(steps, warmup, loop=True):
     return out
 
 
+def ablation():
+    """Scan policies, rounds against time (every variant returns the same
+    lambdas): the capped sweeps with ties at the cap batched (default),
+    one-pop-at-a-time scans with an LDS hash map (scan_mode 2, small graphs),
+    concurrent region scans (Algorithm 1, scan_mode 1, large graphs), and the
+    triangle tests; on the 4096-graph batch and the Chung-Lu 2^22 8-core."""
+    import torch
+    import graphgen as gg
+    import paper_1808_05458_amd as mc
+    out = {}
+
+    def run(name, f, reps=2):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lam, st = f()
+        torch.cuda.synchronize()
+        out[name] = {"ms": round((time.perf_counter() - t0) / reps * 1e3, 2), "rounds": st["rounds"],
+                     "lambda": lam}
+        log(f"ablation {name}: {out[name]}")
+
+    graphs = [gg.batch_graph(i) for i in range(4096)]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda:0")
+
+    def batch(**kw):
+        def f():
+            lams, _, st = mc.mincut_batched(rp, col, w, vo, want_side=False, **kw)
+            return int(np.asarray(lams, np.int64).sum()), st
+        return f
+    run("batch_capped_sweeps", batch())
+    run("batch_one_pop_scans", batch(scan_mode=2))
+    run("batch_capped_sweeps_pr34", batch(pr_triangle_deg=64))
+    del rp, col, w
+    g = gg.chung_lu_4m_8core(22)
+    rp, col, w = mc.to_device(g, "cuda:0")
+
+    def single(**kw):
+        def f():
+            lam, _, st = mc.mincut(rp, col, w, want_side=False, **kw)
+            return lam, st
+        return f
+    run("chung_lu_capped_sweep", single())
+    run("chung_lu_region_scans", single(scan_mode=1), reps=1)
+    run("chung_lu_one_pop_hashed_small_graphs", single(scan_mode=2))
+    return out
+
+
 def rmat_form(steps):
     """R-MAT scale 24 (2^28 draws, (0.57, 0.19, 0.19, 0.05), multiplicity
     weights), 10-core, largest component, resident in HBM: exact solves."""
@@ -239,6 +288,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-rmat", action="store_true")
     ap.add_argument("--no-approx", action="store_true", help="skip the (2+eps)-approximation runs")
+    ap.add_argument("--ablation", action="store_true",
+                    help="print scan-policy ablations (rounds against time) instead of the bench line")
     ap.add_argument("--no-loop", action="store_true",
                     help="batched form: skip the loop of single solves (profiling the packed solve alone)")
     ap.add_argument("--requests", type=int, default=400)
@@ -275,6 +326,10 @@ def main():
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
                "data": "synthetic", "config": {"workload": "Poisson stream of Chung-Lu requests", **sv}}
         print(json.dumps(out), flush=True)
+        return
+    if args.ablation:
+        ab = ablation()
+        print(json.dumps({"ablation": ab}), flush=True)
         return
     if args.workload == "batched":
         b = batched_form(args.steps, args.warmup, loop=not args.no_loop)
