@@ -112,7 +112,9 @@ def ablation():
     lambdas): the capped sweeps with ties at the cap batched (default),
     one-pop-at-a-time scans with an LDS hash map (scan_mode 2, small graphs),
     concurrent region scans (Algorithm 1, scan_mode 1, large graphs), and the
-    triangle tests; on the 4096-graph batch and the Chung-Lu 2^22 8-core."""
+    triangle tests (default: from the second round; also without them and
+    from the first round); on the 4096-graph batch and the Chung-Lu 2^22
+    8-core."""
     import torch
     import graphgen as gg
     import paper_1808_05458_amd as mc
@@ -139,8 +141,9 @@ def ablation():
             return int(np.asarray(lams, np.int64).sum()), st
         return f
     run("batch_capped_sweeps", batch())
+    run("batch_capped_sweeps_no_triangle_tests", batch(pr_triangle_deg=0))
+    run("batch_capped_sweeps_triangle_tests_from_round_1", batch(pr_triangle_deg=-64))
     run("batch_one_pop_scans", batch(scan_mode=2))
-    run("batch_capped_sweeps_pr34", batch(pr_triangle_deg=64))
     del rp, col, w
     g = gg.chung_lu_4m_8core(22)
     rp, col, w = mc.to_device(g, "cuda:0")

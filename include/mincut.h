@@ -107,11 +107,13 @@ typedef struct mc_options {
                               clamped to what LDS holds; 0 = default (3) */
   int32_t sort_tile;       /* keys per radix-sort workgroup: 2048, 4096 or
                               8192; 0 = default (4096) */
-  int32_t pr_triangle_deg; /* 0 (default): Padberg-Rinaldi tests PR1 and PR2
-                              only.  > 0: also the triangle tests PR3 and PR4
-                              (see mc_debug_pr_tests) on edges whose two rows
-                              hold at most this many entries in increasing
-                              neighbour order */
+  int32_t pr_triangle_deg; /* the triangle tests PR3 and PR4 (see
+                              mc_debug_pr_tests) on edges whose two rows hold
+                              at most |pr_triangle_deg| entries in
+                              increasing neighbour order.  > 0: from the
+                              second round on (contracted graphs; default
+                              64); < 0: from the first round on; 0: PR1 and
+                              PR2 only */
   int32_t viecut_exact;    /* mc_viecut_bound only: 1 = finish the clustering
                               levels by solving the last level graph exactly
                               (its minimum cut, a cut of G, lowers the

@@ -1054,11 +1054,13 @@ struct Solver {
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
                            cap, tested, ws.parent, ws.ucount, ws.ctl);
       }
-      if (opt.use_pr && opt.pr_triangle_deg > 0) {
-        // the triangle tests: per tested edge both rows (at most the limit)
+      // the triangle tests on contracted graphs (from the second round; a
+      // negative limit also tests the input): per tested edge both rows
+      const int32_t tri_deg = opt.pr_triangle_deg < 0 ? -opt.pr_triangle_deg : opt.pr_triangle_deg;
+      if (opt.use_pr && tri_deg > 0 && (round > 1 || opt.pr_triangle_deg < 0)) {
         TimedScope t("pr34", (double)nnz * 20);
         hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
-                           ws.active, opt.pr_triangle_deg, ws.parent, ws.ucount, ws.ctl);
+                           ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
       }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -1302,6 +1304,7 @@ void mc_options_default(mc_options* o) {
   o->use_viecut = 0;
   o->eager_blacklist = 1;
   o->lp_sweeps = 2;
+  o->pr_triangle_deg = 64;
 }
 
 int mc_mincut(const mc_graph* g, void* stream, const mc_options* opt, int64_t* lambda,

@@ -92,8 +92,8 @@ def test_solves_with_triangle_tests_equal_oracle():
     refs = [oracle.noi(g, 5)[0] for g in graphs]
     packed, vo, eo = gg.pack(graphs)
     rp, col, w = mc.to_device(packed, "cuda")
-    for opts in [dict(pr_triangle_deg=64), dict(pr_triangle_deg=16, scan_mode=2),
-                 dict(pr_triangle_deg=64, approx_ppm=0, whole_max=64)]:
+    for opts in [dict(pr_triangle_deg=-64), dict(pr_triangle_deg=16, scan_mode=2),
+                 dict(pr_triangle_deg=-64, whole_max=64), dict(pr_triangle_deg=0)]:
         announce("pr34 batch", opts)
         lams, sides, st = mc.mincut_batched(rp, col, w, vo, **opts)
         assert list(lams) == refs, opts
@@ -103,7 +103,7 @@ def test_solves_with_triangle_tests_equal_oracle():
     for g in [gg.planted_4096(), gg.chung_lu(9, 1 << 13, avg_deg=16.0, wmin=1, wmax=9, name="cl13")]:
         lam = oracle.noi(g, 1)[0]
         rp, col, w = mc.to_device(g, "cuda")
-        for opts in [dict(pr_triangle_deg=64), dict(pr_triangle_deg=64, whole_max=16)]:
+        for opts in [dict(pr_triangle_deg=-64), dict(pr_triangle_deg=-64, whole_max=16), dict(pr_triangle_deg=0)]:
             announce("pr34", g.name, opts)
             got, side, st = mc.mincut(rp, col, w, **opts)
             assert got == lam
@@ -122,7 +122,7 @@ def test_first_round_with_triangle_tests_keeps_lambda():
     for margin in (1, 20, 200):
         announce("pr34 round", margin)
         lin = [l + margin for l in lams]
-        labels, used = mc.debug_first_round(rp, col, w, vo, lhat_in=lin, pr_triangle_deg=64)
+        labels, used = mc.debug_first_round(rp, col, w, vo, lhat_in=lin, pr_triangle_deg=-64)
         lab = labels.cpu().numpy()
         checked = 0
         for i, g in enumerate(graphs):
