@@ -164,7 +164,8 @@ struct Workspace {
   // graph arrays
   int64_t *voff, *lhat, *wsum, *kcap;
   int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole, *gmaxw, *prok,
-      *whole2, *fb_list, *root0, *flip, *nvoff, *npairs;
+      *whole2, *fb_list, *root0, *flip, *nvoff, *npairs, *bref;
+  uint32_t* inref;
   uint64_t *bdeg, *balpha;
   uint8_t* mode;
   int32_t* scan_k;
@@ -217,9 +218,9 @@ size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
        2 * align_up(sizeof(SweepStatus) * MAX_SWEEPS);
   b += align_up((N + 2) * 8) * 2;
   b += align_up(E * 4) * 3 + align_up((E + 64) * 8) + align_up((E + G + 64) * 8) + align_up(E * 4) * 2;
-  b += align_up((G + 1) * 8) * 4 + align_up((G + 1) * 4) * 18 + align_up((G + 1) * 8) * 2 +
+  b += align_up((G + 1) * 8) * 4 + align_up((G + 1) * 4) * 19 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
-  b += align_up((2 * N + G + 64) * 4);
+  b += align_up((2 * N + G + 64) * 4) + align_up(((N + 63) / 64 + 1) * 8);
   size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
   t = std::max(t, scan_tmp_bytes<int32_t>(N + 1));
   b += align_up(t) + align_up(sizeof(Ctl));
@@ -300,6 +301,8 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.root0, (G + 1) * 4);
   ALLOC(ws.flip, (G + 1) * 4);
   ALLOC(ws.nvoff, (G + 1) * 4);
+  ALLOC(ws.bref, (G + 1) * 4);
+  ALLOC(ws.inref, ((N + 63) / 64 + 1) * 8);
   ALLOC(ws.npairs, (G + 1) * 4);
   ALLOC(ws.gmaxw, (G + 1) * 4);
   ALLOC(ws.prok, (G + 1) * 4);
@@ -437,6 +440,7 @@ struct Solver {
   const int64_t* lhat_in = nullptr; // optional starting bounds (host, per graph)
   bool viecut_only = false;         // stop after the clustering bound
   int32_t vc_levels_run = 0;        // clustering levels run (most over graphs)
+  int32_t ngraphs = 1;              // graphs in the problem being solved
 
   int read_ctl() {
     MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -637,8 +641,10 @@ struct Solver {
   // fold each graph's minimum degree into ws.bdeg (cleared by the caller).
   // The entry inputs are consumed before the outputs are written, so `out`
   // may alias them.
+  // n_cur, gid_cur: the graph being contracted (vertex count, graph ids).
   int contract(int64_t nnz, const int32_t* src, const int32_t* col, const int32_t* w, const int32_t* lab,
-               int32_t n_next, const int32_t* gid_next, Out out, int64_t* m2_out, const StageNames& nm) {
+               int32_t n_cur, const int32_t* gid_cur, int32_t n_next, const int32_t* gid_next, Out out,
+               int64_t* m2_out, const StageNames& nm) {
     const int TB = 256;
     auto grid = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 16)); };
     auto gridr = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 2)); };
@@ -648,8 +654,12 @@ struct Solver {
       // src, col, w and two label gathers per entry; the keys it writes are
       // counted with the sort
       TimedScope t(nm.emit, (double)nnz * 20);
+      hipLaunchKernelGGL(k_block_ref, dim3(grid_for((int64_t)ngraphs * 64, TB, num_cu * 8)), dim3(TB), 0, s,
+                         ngraphs, n_cur, ws.cvoff, ws.gn, lab, ws.bref);
+      hipLaunchKernelGGL(k_block_bits, dim3(grid_for(n_cur, TB, num_cu * 16)), dim3(TB), 0, s, n_cur, lab, gid_cur,
+                         ws.bref, ws.inref);
       hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, num_cu * 8)), dim3(TB), 0, s, nnz,
-                         src, col, w, lab, bb, ws.keys, ws.vals, ws.ctl);
+                         src, col, w, lab, bb, ws.inref, ws.keys, ws.vals, ws.ctl);
     }
     int rc = read_ctl();
     if (rc) return rc;
@@ -755,7 +765,7 @@ struct Solver {
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
       int64_t m2 = 0;
       Out o{V.src[next], V.col[next], V.w[next], V.rp[next], V.cdeg[next]};
-      int r = contract(nnz, src, col, w, ws.lab, n_next, V.gid[next], o, &m2, kVcNames);
+      int r = contract(nnz, src, col, w, ws.lab, n, gid, n_next, V.gid[next], o, &m2, kVcNames);
       if (r) return r;
       exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff, (int32_t*)nullptr,
                                                 ws.tmp, s);
@@ -854,6 +864,7 @@ struct Solver {
 
   int solve(const Problem& P, int64_t* lambdas, uint8_t* side, mc_stats* st) {
     const int32_t G = P.G;
+    ngraphs = G;
     const int32_t N = P.n;
     const int64_t E = P.nnz;
     const bool want_side = side != nullptr;
@@ -1194,7 +1205,7 @@ struct Solver {
       if (st) st->pairs_scan += ws.ctl_host->pairs;
       // contraction: emit, sort, merge, CSR, degrees
       int64_t m2 = 0;
-      rc = contract(nnz, ws.src, col, w, ws.lab, n_next, gid_next,
+      rc = contract(nnz, ws.src, col, w, ws.lab, n, gid, n_next, gid_next,
                     Out{ws.src, ws.col, ws.w, ws.rp, ws.cdeg}, &m2, kExactNames);
       if (rc) return rc;
       exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff,
@@ -1492,7 +1503,7 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
                      ws.gmaxw, ws.ctl);
   const int bb = std::max(1, bitlen((uint64_t)n_new - 1));
   hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, ncu * 8)), dim3(TB), 0, s, nnz,
-                     ws.src, g->col, g->w, labels, bb, ws.keys, ws.vals, ws.ctl);
+                     ws.src, g->col, g->w, labels, bb, (const uint32_t*)nullptr, ws.keys, ws.vals, ws.ctl);
   MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   MC_HIP(hipStreamSynchronize(s));
   if (ws.ctl_host->err) return MC_EINVAL;

@@ -668,10 +668,54 @@ __global__ void k_update_alpha(int32_t G, GraphState S, const int32_t* scan_k, C
 // Emit (lab[u] << bits | lab[v], w) for every entry whose ends lie in
 // different blocks (internal edges vanish; section "Basic Concepts",
 // contraction G/(u,v)).  Workgroup-aggregated compaction.
+// The entries inside one block are dropped by the emit, and after a sweep
+// most of a graph's vertices usually share one block.  Per graph a reference
+// block (the most common block among 64 evenly spaced vertices: any block is
+// correct, a large one saves most) and a bitmap of the vertices in it let the
+// emit drop an entry whose two ends are both in it from two bit tests in an
+// L2-resident bitmap, without gathering the labels.
+__global__ void k_block_ref(int32_t G, int32_t n, const int32_t* cvoff, const int32_t* gn, const int32_t* lab,
+                            int32_t* ref) {
+  const int lane = lane_id();
+  for (int64_t g = gtid() >> 6; g < G; g += gstride() >> 6) {
+    const int64_t c0 = cvoff[g], cn = gn[g];
+    const int64_t v = c0 + (int64_t)lane * cn / 64;
+    int32_t l = (cn > 0 && v >= 0 && v < n) ? lab[v] : -1;
+    uint64_t todo = ballot(l >= 0);
+    int32_t best = -1, best_cnt = 0;
+    while (todo) {
+      const int32_t cand = __builtin_amdgcn_readlane(l, __builtin_ctzll(todo));
+      const uint64_t same = ballot(l == cand);
+      const int32_t cnt = popc64(same);
+      if (cnt > best_cnt) { best_cnt = cnt; best = cand; }
+      todo &= ~same;
+    }
+    if (lane == 0) ref[g] = best;
+  }
+}
+
+// bit v of inref: v's block is its graph's reference block (one wave per 64
+// vertices).
+__global__ void k_block_bits(int32_t n, const int32_t* lab, const int32_t* gid, const int32_t* ref,
+                             uint32_t* inref) {
+  for (int64_t base = (gtid() >> 6) << 6; base < n; base += gstride()) {
+    const int64_t v = base + lane_id();
+    const bool in = v < n && lab[v] >= 0 && lab[v] == ref[gid[v]];
+    const uint64_t m = ballot(in);
+    if (lane_id() == 0) {
+      inref[base >> 5] = (uint32_t)m;
+      inref[(base >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+  }
+}
+
+__device__ __forceinline__ bool bit_at(const uint32_t* b, int32_t v) { return (b[v >> 5] >> (v & 31)) & 1u; }
+
 __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __restrict__ src,
                                               const int32_t* __restrict__ col,
                                               const int32_t* __restrict__ w,
                                               const int32_t* __restrict__ lab, int bits,
+                                              const uint32_t* __restrict__ inref,
                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
                                               Ctl* ctl) {
   __shared__ uint32_t wcnt[4];
@@ -687,8 +731,16 @@ __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __rest
     for (int r = 0; r < 8; ++r) {
       int64_t e = t0 + (int64_t)wave * 512 + r * 64 + lane;
       bool ok = e < nnz;
-      int32_t a = ok ? lab[src[e]] : -1;
-      int32_t b = ok ? lab[col[e]] : -1;
+      int32_t a = -1, b = -1;
+      if (ok) {
+        const int32_t u = src[e], x = col[e];
+        if (inref && bit_at(inref, u) && bit_at(inref, x)) {
+          ok = false;  // inside the reference block
+        } else {
+          a = lab[u];
+          b = lab[x];
+        }
+      }
       ok = ok && a >= 0 && b >= 0 && a != b;
       k[r] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
       vv[r] = ok ? w[e] : 0;
