@@ -49,7 +49,7 @@ struct Ctl {
   int64_t whole_nnz;     // adjacency entries of the graphs scanned whole
   int64_t whole_nv;      // vertices of the graphs scanned whole
   int32_t lp_items;      // workgroup items of label propagation (long rows)
-  int32_t n_pr;          // graphs where a Padberg-Rinaldi test can pass in round 1
+  int32_t n_pr;          // graphs where a Padberg-Rinaldi test can pass in the first contraction round
 };
 
 struct ScanArgs {

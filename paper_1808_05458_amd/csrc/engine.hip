@@ -165,7 +165,7 @@ struct Workspace {
   int64_t *voff, *lhat, *wsum, *kcap;
   int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole, *gmaxw, *prok,
       *whole2, *fb_list, *root0, *flip, *nvoff, *npairs, *bref;
-  uint32_t* inref;
+  uint32_t *inref, *bbits;
   uint64_t *bdeg, *balpha;
   uint8_t* mode;
   int32_t* scan_k;
@@ -220,7 +220,7 @@ size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
   b += align_up(E * 4) * 3 + align_up((E + 64) * 8) + align_up((E + G + 64) * 8) + align_up(E * 4) * 2;
   b += align_up((G + 1) * 8) * 4 + align_up((G + 1) * 4) * 19 + align_up((G + 1) * 8) * 2 +
        align_up(G + 1);
-  b += align_up((2 * N + G + 64) * 4) + align_up(((N + 63) / 64 + 1) * 8);
+  b += align_up((2 * N + G + 64) * 4) + 2 * align_up(((N + 63) / 64 + 1) * 8);
   size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
   t = std::max(t, scan_tmp_bytes<int32_t>(N + 1));
   b += align_up(t) + align_up(sizeof(Ctl));
@@ -303,6 +303,7 @@ int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   ALLOC(ws.nvoff, (G + 1) * 4);
   ALLOC(ws.bref, (G + 1) * 4);
   ALLOC(ws.inref, ((N + 63) / 64 + 1) * 8);
+  ALLOC(ws.bbits, ((N + 63) / 64 + 1) * 8);
   ALLOC(ws.npairs, (G + 1) * 4);
   ALLOC(ws.gmaxw, (G + 1) * 4);
   ALLOC(ws.prok, (G + 1) * 4);
@@ -586,8 +587,12 @@ struct Solver {
             exclusive_scan<int64_t, BatchDeg>(BatchDeg{A.capq + bh, rp}, bsz, off, off + bsz, ws.tmp, s);
             hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
                                (int32_t)bsz, tile_row);
+            // the graph's visit state as two bitmaps (ws.inref is free until
+            // the contraction)
+            hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.inref,
+                               ws.bbits);
             hipLaunchKernelGGL(k_sweep_big_relax, dim3(num_cu * 8), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
-                               tile_row);
+                               tile_row, ws.inref, ws.bbits);
           }
           hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
           {

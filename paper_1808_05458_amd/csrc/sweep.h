@@ -180,10 +180,14 @@ __device__ __forceinline__ void pool_put(const SA& A, const SweepQ& q, int64_t i
 //
 // member: y is known to be in the batch (the caller compared it with the
 // batch's vertices), so neither its stamp nor its r is touched.
+//
+// unvisited: (grid-wide batches) y is known to be unvisited, so its stamp is
+// not read.
 template <bool PUSH = true, class SA>
 __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int32_t x, int32_t y,
                                                int32_t c, int32_t stamp, bool act, int32_t* wbuf = nullptr,
-                                               int32_t* wcnt = nullptr, bool member = false) {
+                                               int32_t* wcnt = nullptr, bool member = false,
+                                               bool unvisited = false) {
   const int lane = lane_id();
   int64_t internal = 0;
   bool cross = false, push = false;
@@ -214,7 +218,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
   } else if (act) {
     // grid-wide batches are bandwidth-bound: no add for visited vertices
     // (the stamps do not change while a grid-wide batch is relaxed)
-    const int32_t vs = rs_stamp(ld_relaxed(A.rs + y));
+    const int32_t vs = unvisited ? 0 : rs_stamp(ld_relaxed(A.rs + y));
     if (vs != 0) {
       if (vs == stamp) internal = c;
     } else {
@@ -880,6 +884,24 @@ __device__ __forceinline__ void flush_wave_buf(const SweepArgs& A, int32_t* wbuf
 constexpr int BIG_UNROLL = 4;
 constexpr int BIG_TILE = 256 * BIG_UNROLL;
 
+// Before a grid-wide batch is relaxed: bit i of visited is set if vertex
+// v0 + i was visited before the batch, bit i of batch if it is in the batch
+// (two bits per vertex in L2 instead of an 8-byte word gathered from HBM).
+__global__ void k_sweep_bits(SweepArgs A, uint32_t* visited, uint32_t* batch) {
+  const int32_t stamp = A.ctl->step + 1;
+  for (int64_t base = (gtid() >> 6) << 6; base < A.ng; base += gstride()) {
+    const int64_t i = base + lane_id();
+    const int32_t st = i < A.ng ? rs_stamp(A.rs[A.v0 + i]) : 0;
+    const uint64_t vis = ballot(st != 0 && st != stamp), bat = ballot(st == stamp);
+    if (lane_id() == 0) {
+      visited[base >> 5] = (uint32_t)vis;
+      visited[(base >> 5) + 1] = (uint32_t)(vis >> 32);
+      batch[base >> 5] = (uint32_t)bat;
+      batch[(base >> 5) + 1] = (uint32_t)(bat >> 32);
+    }
+  }
+}
+
 // Row length of batch vertex i (the prefix sum's input).
 struct BatchDeg {
   const int32_t* capq;  // the batch's FIFO entries
@@ -901,7 +923,8 @@ __global__ void k_sweep_big_tiles(const int64_t* off, int32_t bsz, int32_t* tile
 
 // off: bsz + 1 prefix sums of the batch's row lengths (off[bsz] = entries).
 __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h, int32_t bsz, const int64_t* off,
-                                                         const int32_t* tile_row) {
+                                                         const int32_t* tile_row, const uint32_t* visited,
+                                                         const uint32_t* batch) {
   __shared__ int32_t buf[4][2 * BIG_BUF];
   __shared__ int32_t cnt[4];
   __shared__ int32_t s_x[BIG_TILE];
@@ -960,7 +983,19 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
       }
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) {
-        internal += sweep_relax<false>(A, gq, xs[u], ys[u], cs[u], stamp, xs[u] >= 0, wbuf, wcnt);
+        // the neighbour's state from the bitmaps: inside the batch, visited
+        // before it, or unvisited (then the add, and maybe a crossing)
+        bool act = xs[u] >= 0 && ys[u] != xs[u];
+        if (act) {
+          const int32_t i = ys[u] - A.v0;
+          if ((batch[i >> 5] >> (i & 31)) & 1u) {
+            internal += cs[u];
+            act = false;
+          } else if ((visited[i >> 5] >> (i & 31)) & 1u) {
+            act = false;
+          }
+        }
+        internal += sweep_relax<false>(A, gq, xs[u], ys[u], cs[u], stamp, act, wbuf, wcnt, false, true);
         if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
       }
       __syncthreads();  // the slice arrays are reused
