@@ -273,9 +273,11 @@ typedef struct mc_server mc_server;
 typedef struct mc_server_cfg {
   int32_t lanes;           /* concurrent solves; default 4 */
   int32_t max_batch;       /* graphs per packed solve; default 4096 */
-  int64_t small_max_nnz;   /* larger requests run alone; default 2^22 */
+  int64_t small_max_nnz;   /* larger requests run alone; default 2^25 (large
+                              graphs packed together are swept at once, one
+                              workgroup each) */
   int64_t max_batch_nnz;   /* entries per packed solve (a run of small requests
-                              stops before passing it); default 2^24 */
+                              stops before passing it); default 2^26 */
   int64_t mem_budget;      /* device bytes of the requests in flight (input,
                               side and solver workspace share); 0 = half of
                               the free memory at creation */

@@ -237,8 +237,8 @@ void mc_server_cfg_default(mc_server_cfg* c) {
   std::memset(c, 0, sizeof(*c));
   c->lanes = 4;
   c->max_batch = 4096;
-  c->small_max_nnz = 1ll << 22;
-  c->max_batch_nnz = 1ll << 24;
+  c->small_max_nnz = 1ll << 25;
+  c->max_batch_nnz = 1ll << 26;
   c->mem_budget = 0;
   c->queue_cap = 1 << 16;
   c->device = -1;
