@@ -50,6 +50,7 @@ struct Ctl {
   int64_t whole_nv;      // vertices of the graphs scanned whole
   int32_t lp_items;      // workgroup items of label propagation (long rows)
   int32_t n_pr;          // graphs where a Padberg-Rinaldi test can pass in the first contraction round
+  int64_t lam_floor;     // the smallest bound of a tested graph (Padberg-Rinaldi prefilter)
 };
 
 struct ScanArgs {

@@ -838,6 +838,7 @@ struct Solver {
           hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, cdeg, gid, ws.lhat, V.act,
                              ws.parent, ws.ucount);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+          hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, ws.lhat, V.act, ws.ctl);
           hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, src, col, w, cdeg, gid, ws.lhat, V.act,
                              ws.parent, ws.ucount, ws.ctl);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -1067,6 +1068,7 @@ struct Solver {
         hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, ws.cdeg, gid, cap,
                            tested, ws.parent, ws.ucount);
         hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+        hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, cap, tested, ws.ctl);
         hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
                            cap, tested, ws.parent, ws.ucount, ws.ctl);
       }

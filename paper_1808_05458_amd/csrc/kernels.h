@@ -446,6 +446,11 @@ __device__ __forceinline__ bool pr_passes(int64_t c, int64_t lam, int64_t cu, in
   return c >= lam || 2 * c > cu || 2 * c > cv;
 }
 
+// An edge with 2c <= lambda-hat passes neither test: lambda-hat is at most
+// the minimum degree, so 2c <= c(u) and 2c <= c(v), and c < lambda-hat.
+// Checked first, it spares the two degree gathers of most edges.
+__device__ __forceinline__ bool pr_hopeless(int64_t c, int64_t lam) { return 2 * c <= lam; }
+
 __device__ __forceinline__ void pr_flag(int32_t* ucount, int32_t g, int32_t& last) {
   if (g != last) {
     if (ld_relaxed(ucount + g) == 0) st_relaxed(ucount + g, 1);
@@ -465,12 +470,30 @@ __global__ void k_pr_sample(int32_t n, const int64_t* __restrict__ rp, const int
     const int64_t e0 = rp[v], e1 = min(rp[v + 1], e0 + PR_SAMPLE);
     for (int64_t e = e0; e < e1; ++e) {
       const int32_t u = col[e];
-      if (u != (int32_t)v && pr_passes(w[e], lam, cv, cdeg[u])) {
+      const int64_t c = w[e];
+      if (u != (int32_t)v && !pr_hopeless(c, lam) && pr_passes(c, lam, cv, cdeg[u])) {
         uf_union(parent, (int32_t)v, u);
         pr_flag(ucount, g, last);
       }
     }
   }
+}
+
+// ctl->lam_floor = the smallest bound among the tested graphs (one
+// workgroup): with it, k_pr drops an edge from its weight alone.
+__global__ void __launch_bounds__(256) k_lam_floor(int32_t G, const int64_t* lhat, const int32_t* active,
+                                                   Ctl* ctl) {
+  __shared__ int64_t part[4];
+  int64_t m = INT64_MAX;
+  for (int32_t g = threadIdx.x; g < G; g += 256)
+    if (active[g]) m = min(m, lhat[g]);
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t t = __shfl_xor(m, o, 64);
+    m = min(m, t);
+  }
+  if (lane_id() == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) ctl->lam_floor = min(min(part[0], part[1]), min(part[2], part[3]));
 }
 
 __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t* __restrict__ col,
@@ -479,11 +502,15 @@ __global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t
                      const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount, Ctl* ctl) {
   int64_t local = 0;
   int32_t last = -1;
+  const int64_t floor = ctl->lam_floor;  // hopeless for every graph: 2c <= floor
   for (int64_t e = gtid(); e < nnz; e += gstride()) {
+    if (pr_hopeless(w[e], floor)) continue;
     const int32_t u = src[e], v = col[e];
     if (u >= v) continue;
     const int32_t g = gid[u];
-    if (!active[g] || !pr_passes(w[e], lhat[g], cdeg[u], cdeg[v])) continue;
+    if (!active[g]) continue;
+    const int64_t c = w[e], lam = lhat[g];
+    if (pr_hopeless(c, lam) || !pr_passes(c, lam, cdeg[u], cdeg[v])) continue;
     ++local;
     pr_flag(ucount, g, last);
     if (ld_relaxed(parent + u) != ld_relaxed(parent + v)) uf_union(parent, u, v);
