@@ -835,7 +835,7 @@ struct Solver {
         {
           TimedScope t("vc_pr", (double)nnz * 20 + (double)n * 16);
           hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
-          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, cdeg, gid, ws.lhat, V.act,
+          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, cdeg, gid, ws.lhat, V.act,
                              ws.parent, ws.ucount);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, ws.lhat, V.act, ws.ctl);
@@ -928,8 +928,13 @@ struct Solver {
       hipLaunchKernelGGL(k_init_vertices, grid(N), dim3(TB), 0, s, N, ws.voff, G, gid, ws.ogid, ws.map);
       fill<int64_t>(ws.cdeg, 0, N, s);
       fill<int32_t>(ws.gmaxw, 0, G, s);
-      hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + 64 * INGEST_STEPS - 1) / (64 * INGEST_STEPS) * 64, TB, num_cu * 16)),
-                         dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, ws.src, ws.cdeg, ws.gmaxw, ws.ctl);
+      if (E > 0) {
+        // chunk first rows in the sort keys' buffer (free until the first contraction)
+        int32_t* first = (int32_t*)ws.keys;
+        hipLaunchKernelGGL(k_chunk_rows, grid(N), dim3(TB), 0, s, N, P.rp, first);
+        hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + INGEST_CH - 1) / INGEST_CH * TB, TB, num_cu * 8)), dim3(TB),
+                           0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, first, ws.src, ws.cdeg, ws.gmaxw, ws.ctl);
+      }
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
       fill<int64_t>(ws.wsum, 0, G, s);
       hipLaunchKernelGGL(k_min_degree, gridr(N), dim3(TB), 0, s, N, ws.cdeg, gid, (const int32_t*)nullptr,
@@ -1065,7 +1070,7 @@ struct Solver {
         // src, col, w per entry; both degrees for the half with u < v
         TimedScope t("pr", (double)nnz * 20 + (double)n * 32);
         const int32_t* tested = (round == 1 && !pr_first_all) ? ws.prok : ws.active;
-        hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, rp, col, w, ws.cdeg, gid, cap,
+        hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, ws.cdeg, gid, cap,
                            tested, ws.parent, ws.ucount);
         hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
         hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, cap, tested, ws.ctl);
@@ -1077,8 +1082,13 @@ struct Solver {
       const int32_t tri_deg = opt.pr_triangle_deg < 0 ? -opt.pr_triangle_deg : opt.pr_triangle_deg;
       if (opt.use_pr && tri_deg > 0 && (round > 1 || opt.pr_triangle_deg < 0)) {
         TimedScope t("pr34", (double)nnz * 20);
-        hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
-                           ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
+        if (tri_deg <= PR34W_MAX)
+          hipLaunchKernelGGL(k_pr34w<false>, dim3(grid_for((int64_t)n * 64, TB, num_cu * 16)), dim3(TB), 0, s, n,
+                             rp, col, w, ws.cdeg, gid, cap, ws.active, (int64_t)0, tri_deg, ws.parent, ws.ucount,
+                             (uint8_t*)nullptr, ws.ctl);
+        else
+          hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
+                             ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
       }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -1477,8 +1487,13 @@ int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid(grid_for(g->n, 256, 65536));
   hipLaunchKernelGGL(k_row_degrees, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg);
-  hipLaunchKernelGGL(k_pr_flags, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg, lhat, max_deg,
-                     flags);
+  if (max_deg <= PR34W_MAX)
+    hipLaunchKernelGGL(k_pr34w<true>, dim3(grid_for((int64_t)g->n * 64, 256, 65536)), dim3(256), 0, s, g->n,
+                       g->row_ptr, g->col, g->w, ws.cdeg, (const int32_t*)nullptr, (const int64_t*)nullptr,
+                       (const int32_t*)nullptr, lhat, max_deg, (int32_t*)nullptr, (int32_t*)nullptr, flags, ws.ctl);
+  else
+    hipLaunchKernelGGL(k_pr_flags, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg, lhat, max_deg,
+                       flags);
   MC_HIP(hipStreamSynchronize(s));
   MC_HIP(hipGetLastError());
   return MC_OK;
@@ -1505,9 +1520,22 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
   MC_HIP(hipMemcpyAsync(ws.voff, voff, 16, hipMemcpyHostToDevice, s));
   fill<int32_t>(ws.gid[0], 0, g->n, s);
   fill<int32_t>(ws.gmaxw, 0, 1, s);
-  hipLaunchKernelGGL(k_ingest, dim3(grid_for((nnz + 64 * INGEST_STEPS - 1) / (64 * INGEST_STEPS) * 64, TB, ncu * 16)),
-                     dim3(TB), 0, s, g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff, ws.src, ws.cdeg,
-                     ws.gmaxw, ws.ctl);
+  hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(g->n, TB, ncu * 16)), dim3(TB), 0, s, g->n, nnz, g->row_ptr,
+                     ws.ctl);
+  MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  MC_HIP(hipStreamSynchronize(s));
+  if (ws.ctl_host->err) return MC_EINVAL;
+  if (nnz > 0) {
+    int32_t* first = (int32_t*)ws.keys;
+    hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(g->n, TB, ncu * 16)), dim3(TB), 0, s, g->n, g->row_ptr, first);
+    hipLaunchKernelGGL(k_ingest, dim3(grid_for((nnz + INGEST_CH - 1) / INGEST_CH * TB, TB, ncu * 8)), dim3(TB), 0, s,
+                       g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff, first, ws.src, ws.cdeg, ws.gmaxw,
+                       ws.ctl);
+  }
+  // every col inside [0, n) before the emit indexes the labels by it
+  MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  MC_HIP(hipStreamSynchronize(s));
+  if (ws.ctl_host->err) return MC_EINVAL;
   const int bb = std::max(1, bitlen((uint64_t)n_new - 1));
   hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, ncu * 8)), dim3(TB), 0, s, nnz,
                      ws.src, g->col, g->w, labels, bb, (const uint32_t*)nullptr, ws.keys, ws.vals, ws.ctl);

@@ -81,73 +81,135 @@ __global__ void k_init_vertices(int32_t n, const int64_t* voff, int32_t G, int32
 }
 
 // Entry source ids, validation, and weighted degrees (self-loops excluded;
-// they never cross a cut).  Each wave walks 64 consecutive entries per step.
-constexpr int INGEST_STEPS = 16;
+// they never cross a cut).  A workgroup takes INGEST_CH consecutive entries
+// per step.  The row of each entry comes from the row starts that fall in
+// the chunk: they are marked in LDS (one coalesced read of row_ptr), and a
+// maximum scan over the chunk's positions carries each row id to its
+// entries; the chunk's first row is found beforehand by k_chunk_rows.  Each
+// wave then takes 64 consecutive entries per step, so the row sums are
+// wave-segmented sums.
+constexpr int INGEST_CH = 2048;
+
+// first[c] = the row holding entry c * INGEST_CH (one writer per chunk: the
+// non-empty row whose entry range contains it).
+__global__ void k_chunk_rows(int32_t n, const int64_t* __restrict__ rp, int32_t* __restrict__ first) {
+  for (int64_t r = gtid(); r < n; r += gstride()) {
+    const int64_t lo = rp[r], hi = rp[r + 1];
+    for (int64_t c = (lo + INGEST_CH - 1) / INGEST_CH; c * INGEST_CH < hi; ++c) first[c] = (int32_t)r;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col,
                                                 const int32_t* __restrict__ w,
                                                 const int32_t* __restrict__ gid,
                                                 const int64_t* __restrict__ voff,
+                                                const int32_t* __restrict__ first,
                                                 int32_t* __restrict__ src, int64_t* cdeg, int32_t* gmaxw,
                                                 Ctl* ctl) {
-  const int lane = lane_id();
-  const int64_t wave_global = gtid() >> 6;
-  const int64_t nwaves = gstride() >> 6;
-  int32_t wg = -1, wm = 0;  // this wave's graph and its largest weight, flushed on change
-  for (int64_t chunk = wave_global; chunk * 64 * INGEST_STEPS < nnz; chunk += nwaves) {
-    int32_t mg = -1, mw = 0;  // this lane's graph in the chunk and its largest weight
-    int64_t e = chunk * 64 * INGEST_STEPS + lane;
-    // row of the first entry: upper_bound(rp, e) - 1
-    int32_t r = 0;
-    if (e < nnz) {
-      int32_t lo = 0, hi = n;  // rp[lo] <= e < rp[hi]
-      while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
-        if (rp[mid] <= e) lo = mid; else hi = mid;
-      }
-      r = lo;
+  constexpr int PER = INGEST_CH / 256;  // entries per thread
+  __shared__ int32_t row_at[INGEST_CH];
+  __shared__ int32_t wave_max[4];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int64_t nch = (nnz + INGEST_CH - 1) / INGEST_CH;
+  // largest weight of the chunks in one graph, per lane, folded into
+  // gmaxw when the graph changes (same-address atomics serialise)
+  int32_t run_g = -1, run_m = 0;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const int64_t cs = ch * INGEST_CH, ce = min(cs + (int64_t)INGEST_CH, nnz);
+    const int len = (int)(ce - cs);
+    // this thread's entries (wave-contiguous steps), in flight meanwhile
+    int32_t y[PER], c[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int p = wave * (64 * PER) + k * 64 + lane;
+      const int64_t e = cs + (p < len ? p : 0);
+      y[k] = col[e];
+      c[k] = w[e];
     }
-    for (int s = 0; s < INGEST_STEPS; ++s, e += 64) {
-      bool ok = e < nnz;
-      if (ok) while (rp[r + 1] <= e) ++r;
-      int32_t y = ok ? col[e] : 0;
-      int32_t c = ok ? w[e] : 0;
+    int32_t r0 = first[ch];
+    r0 = r0 < 0 ? 0 : (r0 >= n ? n - 1 : r0);
+    // the first row's graph and its vertex range (graphs are contiguous
+    // vertex ranges, so the chunk lies in one graph if its last row does)
+    const int32_t g0 = gid[r0];
+    const int64_t lo0 = voff[g0], hi0 = voff[g0 + 1];
+    __syncthreads();  // the previous chunk's reads of row_at are done
+#pragma unroll
+    for (int k = 0; k < PER; ++k) row_at[tid + k * 256] = -1;
+    __syncthreads();
+    if (tid == 0) row_at[0] = r0;
+    // rows starting inside the chunk; empty rows share a start with the
+    // next row, and the largest id there owns the entries
+    for (int64_t base = (int64_t)r0 + 1;; base += 256) {
+      const int64_t r = base + tid;
+      const int64_t st = r < n ? rp[r] : nnz;
+      if (st > cs && st < ce) atomicMax(&row_at[st - cs], (int32_t)r);
+      if (!__syncthreads_or(tid == 255 && st < ce)) break;
+    }
+    // maximum scan over positions: each thread scans 8 consecutive ones
+    int32_t v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) v[k] = row_at[tid * PER + k];
+#pragma unroll
+    for (int k = 1; k < PER; ++k) v[k] = v[k] > v[k - 1] ? v[k] : v[k - 1];
+    int32_t inc = v[PER - 1];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(inc, o, 64);
+      if (lane >= o && t > inc) inc = t;
+    }
+    if (lane == 63) wave_max[wave] = inc;
+    int32_t ex = __shfl_up(inc, 1, 64);
+    if (lane == 0) ex = -1;
+    __syncthreads();
+    for (int i = 0; i < wave; ++i) ex = wave_max[i] > ex ? wave_max[i] : ex;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) row_at[tid * PER + k] = v[k] > ex ? v[k] : ex;
+    __syncthreads();
+    const bool one = row_at[len - 1] < hi0;
+    if (one && g0 != run_g) {  // block-uniform
+      const uint32_t m = wave_max_u32((uint32_t)run_m);
+      if (lane == 0 && m) atomicMax(gmaxw + run_g, (int32_t)m);
+      run_g = g0;
+      run_m = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int p = wave * (64 * PER) + k * 64 + lane;
+      const bool ok = p < len;
+      const int64_t e = cs + p;
+      const int32_t row = row_at[ok ? p : 0];
+      int32_t g = g0;
+      int64_t lo = lo0, hi = hi0;
+      if (!one) {  // a chunk across a graph boundary (block-uniform)
+        g = gid[row];
+        lo = voff[g];
+        hi = voff[g + 1];
+      }
       if (ok) {
-        src[e] = r;
-        int32_t g = gid[r];
-        if (y < voff[g] || y >= voff[g + 1] || c < 1) atomicExch(&ctl->err, -1);
-        if (g != mg) {
-          if (mg >= 0) atomicMax(gmaxw + mg, mw);
-          mg = g;
-          mw = 0;
-        }
-        mw = c > mw ? c : mw;
+        src[e] = row;
+        if (y[k] < lo || y[k] >= hi || c[k] < 1) atomicExch(&ctl->err, -1);
       }
-      int64_t val = (ok && y != r) ? (int64_t)c : 0;
+      const int64_t val = (ok && y[k] != row) ? (int64_t)c[k] : 0;
       bool tail;
-      int64_t sum = wave_segsum<int32_t, int64_t>(ok ? r : -1, val, ok, tail);
-      if (ok && tail && sum) atomicAdd((unsigned long long*)(cdeg + r), (unsigned long long)sum);
-    }
-    // largest weight per graph: a chunk in one graph (the usual case) folds
-    // into the wave's running maximum, flushed when the graph changes
-    const int32_t g0 = shfl(mg, 0);
-    if (ballot(mg == g0) == ~0ull) {
-      int32_t m = mw;
-      for (int o = 32; o > 0; o >>= 1) {
-        const int32_t t = __shfl_xor(m, o, 64);
-        m = t > m ? t : m;
+      const int64_t sum = wave_segsum<int32_t, int64_t>(ok ? row : -1, val, ok, tail);
+      if (ok && tail && sum) atomicAdd((unsigned long long*)(cdeg + row), (unsigned long long)sum);
+      const int32_t ck = ok ? c[k] : 0;
+      if (one) {
+        run_m = ck > run_m ? ck : run_m;
+      } else {
+        const int32_t gk = __builtin_amdgcn_readfirstlane(g);
+        if (ballot(g == gk) == ~0ull) {
+          const uint32_t m = wave_max_u32((uint32_t)ck);
+          if (lane == 0 && m) atomicMax(gmaxw + gk, (int32_t)m);
+        } else if (ok) {
+          atomicMax(gmaxw + g, ck);
+        }
       }
-      if (g0 != wg) {
-        if (lane == 0 && wg >= 0) atomicMax(gmaxw + wg, wm);
-        wg = g0;
-        wm = 0;
-      }
-      wm = m > wm ? m : wm;
-    } else if (mg >= 0) {
-      atomicMax(gmaxw + mg, mw);
     }
   }
-  if (lane == 0 && wg >= 0) atomicMax(gmaxw + wg, wm);
+  const uint32_t m = wave_max_u32((uint32_t)run_m);
+  if (lane == 0 && m) atomicMax(gmaxw + run_g, (int32_t)m);
 }
 
 // Per-graph minimum weighted degree (the trivial cut, section "Basic
@@ -458,24 +520,41 @@ __device__ __forceinline__ void pr_flag(int32_t* ucount, int32_t g, int32_t& las
   }
 }
 
-__global__ void k_pr_sample(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
-                            const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
-                            const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount) {
+// Loads are grouped so that each round trip serves every entry the thread
+// holds, and no load waits inside a divergent branch: an entry that needs
+// nothing reads a shared dummy address instead.
+__global__ void k_pr_sample(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                            const int32_t* __restrict__ col, const int32_t* __restrict__ w,
+                            const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
+                            const int64_t* __restrict__ lhat, const int32_t* __restrict__ active, int32_t* parent,
+                            int32_t* ucount) {
+  if (nnz <= 0) return;
   int32_t last = -1;
   for (int64_t v = gtid(); v < n; v += gstride()) {
     const int32_t g = gid[v];
-    if (!active[g]) continue;
-    const int64_t lam = lhat[g], cv = cdeg[v];
-    const int64_t e0 = rp[v], e1 = min(rp[v + 1], e0 + PR_SAMPLE);
-    for (int64_t e = e0; e < e1; ++e) {
-      const int32_t u = col[e];
-      const int64_t c = w[e];
-      if (u != (int32_t)v && !pr_hopeless(c, lam) && pr_passes(c, lam, cv, cdeg[u])) {
-        uf_union(parent, (int32_t)v, u);
+    const int64_t cv = cdeg[v], e0 = rp[v], e1 = rp[v + 1];
+    const bool act = active[g] != 0;
+    const int64_t lam = lhat[g];
+    int32_t u[PR_SAMPLE], c[PR_SAMPLE];
+#pragma unroll
+    for (int k = 0; k < PR_SAMPLE; ++k) {
+      const int64_t e = e0 + k < e1 ? e0 + k : 0;
+      u[k] = col[e];
+      c[k] = w[e];
+    }
+    bool keep[PR_SAMPLE];
+    int64_t cu[PR_SAMPLE];
+#pragma unroll
+    for (int k = 0; k < PR_SAMPLE; ++k) {
+      keep[k] = act && e0 + k < e1 && u[k] != (int32_t)v && !pr_hopeless(c[k], lam);
+      cu[k] = cdeg[keep[k] ? u[k] : (int32_t)v];
+    }
+#pragma unroll
+    for (int k = 0; k < PR_SAMPLE; ++k)
+      if (keep[k] && pr_passes(c[k], lam, cv, cu[k])) {
+        uf_union(parent, (int32_t)v, u[k]);
         pr_flag(ucount, g, last);
       }
-    }
   }
 }
 
@@ -496,24 +575,62 @@ __global__ void __launch_bounds__(256) k_lam_floor(int32_t G, const int64_t* lha
   if (threadIdx.x == 0) ctl->lam_floor = min(min(part[0], part[1]), min(part[2], part[3]));
 }
 
-__global__ void k_pr(int64_t nnz, const int32_t* __restrict__ src, const int32_t* __restrict__ col,
-                     const int32_t* __restrict__ w, const int64_t* __restrict__ cdeg,
-                     const int32_t* __restrict__ gid, const int64_t* __restrict__ lhat,
-                     const int32_t* __restrict__ active, int32_t* parent, int32_t* ucount, Ctl* ctl) {
+// PR_TILE entries per thread and workgroup step, loaded in five rounds
+// (weight; ends; graph; its bound; both degrees), each round for all of
+// them; an entry already decided reads a shared dummy address.
+constexpr int PR_TILE = 4;
+__global__ void __launch_bounds__(256) k_pr(int64_t nnz, const int32_t* __restrict__ src,
+                                            const int32_t* __restrict__ col, const int32_t* __restrict__ w,
+                                            const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
+                                            const int64_t* __restrict__ lhat, const int32_t* __restrict__ active,
+                                            int32_t* parent, int32_t* ucount, Ctl* ctl) {
   int64_t local = 0;
   int32_t last = -1;
   const int64_t floor = ctl->lam_floor;  // hopeless for every graph: 2c <= floor
-  for (int64_t e = gtid(); e < nnz; e += gstride()) {
-    if (pr_hopeless(w[e], floor)) continue;
-    const int32_t u = src[e], v = col[e];
-    if (u >= v) continue;
-    const int32_t g = gid[u];
-    if (!active[g]) continue;
-    const int64_t c = w[e], lam = lhat[g];
-    if (pr_hopeless(c, lam) || !pr_passes(c, lam, cdeg[u], cdeg[v])) continue;
-    ++local;
-    pr_flag(ucount, g, last);
-    if (ld_relaxed(parent + u) != ld_relaxed(parent + v)) uf_union(parent, u, v);
+  for (int64_t t0 = (int64_t)blockIdx.x * 256 * PR_TILE; t0 < nnz; t0 += (int64_t)gridDim.x * 256 * PR_TILE) {
+    const int64_t e0 = t0 + threadIdx.x;
+    int32_t c[PR_TILE], u[PR_TILE], v[PR_TILE], g[PR_TILE];
+    bool keep[PR_TILE];
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i) c[i] = w[e0 + i * 256 < nnz ? e0 + i * 256 : t0];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i) {
+      keep[i] = e0 + i * 256 < nnz && !pr_hopeless(c[i], floor);
+      any = any || keep[i];
+    }
+    if (ballot(any) == 0) continue;  // wave-uniform: nothing left to test
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i) {
+      const int64_t e = keep[i] ? e0 + i * 256 : t0;
+      u[i] = src[e];
+      v[i] = col[e];
+    }
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i) {
+      keep[i] = keep[i] && u[i] < v[i];
+      g[i] = gid[keep[i] ? u[i] : 0];
+    }
+    int64_t lam[PR_TILE];
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i) {
+      const bool act = active[g[i]] != 0;
+      lam[i] = lhat[g[i]];
+      keep[i] = keep[i] && act && !pr_hopeless(c[i], lam[i]);
+    }
+    int64_t cu[PR_TILE], cv[PR_TILE];
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i) {
+      cu[i] = cdeg[keep[i] ? u[i] : 0];
+      cv[i] = cdeg[keep[i] ? v[i] : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < PR_TILE; ++i)
+      if (keep[i] && pr_passes(c[i], lam[i], cu[i], cv[i])) {
+        ++local;
+        pr_flag(ucount, g[i], last);
+        if (ld_relaxed(parent + u[i]) != ld_relaxed(parent + v[i])) uf_union(parent, u[i], v[i]);
+      }
   }
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
@@ -582,6 +699,110 @@ __global__ void k_pr34(int64_t nnz, const int32_t* __restrict__ src, const int32
     if (ld_relaxed(parent + u) != ld_relaxed(parent + v)) uf_union(parent, u, v);
   }
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
+}
+
+// The same tests, one wave per vertex u, for limits of at most 64 entries:
+// the lanes load u's row (one entry each) into LDS and, with it, the row
+// bounds and degree of every neighbour; then for each neighbour v > u that
+// needs the tests, the lanes load v's row together and look each entry up
+// in u's row by binary search.  Both rows are read once, every row in one
+// round trip, instead of one dependent load per merge step.  Per edge the
+// outcome is pr34_eval's.
+// FLAGS: write every test's bits per entry (k_pr_flags' output, lhat =
+// lam_all for every vertex); else unite the edges that pass PR3 or PR4 but
+// not PR1/PR2 (those were united before), as k_pr34 does.
+constexpr int PR34W_MAX = 64;
+template <bool FLAGS>
+__global__ void __launch_bounds__(256) k_pr34w(int32_t n, const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col, const int32_t* __restrict__ w,
+                                               const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
+                                               const int64_t* __restrict__ lhat, const int32_t* __restrict__ active,
+                                               int64_t lam_all, int32_t max_deg, int32_t* parent, int32_t* ucount,
+                                               uint8_t* flags, Ctl* ctl) {
+  __shared__ int32_t xs_all[4][PR34W_MAX];
+  __shared__ int32_t wx_all[4][PR34W_MAX];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int32_t* xs = xs_all[wave];
+  int32_t* wx = wx_all[wave];
+  int64_t local = 0;
+  int32_t last = -1;
+  for (int64_t uu = gtid() >> 6; uu < n; uu += gstride() >> 6) {
+    const int32_t u = (int32_t)uu;
+    const int64_t a = rp[u], du = rp[u + 1] - a;
+    int32_t g = 0;
+    int64_t lam = lam_all;
+    if (!FLAGS) {
+      g = gid[u];
+      if (!active[g] || du > max_deg) continue;
+      lam = lhat[g];
+    }
+    if (du <= 0) continue;
+    if (FLAGS && du > PR34W_MAX) {  // PR1 and PR2 only
+      const int64_t cu = cdeg[u];
+      for (int64_t e = a + lane; e < a + du; e += 64) {
+        const int32_t v = col[e];
+        const int64_t c = w[e];
+        uint32_t f = 0;
+        if (u < v) f = (c >= lam ? 1u : 0u) | ((2 * c > cu || 2 * c > cdeg[v]) ? 2u : 0u);
+        flags[e] = (uint8_t)f;
+      }
+      continue;
+    }
+    const bool in_row = lane < du;
+    const int64_t ea = in_row ? a + lane : a;
+    const int32_t x = col[ea], cx = w[ea];
+    const int64_t cu = cdeg[u];
+    // the neighbour's row bounds and degree, for all entries at once
+    const int32_t xv = in_row ? x : u;
+    const int64_t vb = rp[xv], vlen = rp[xv + 1] - vb, cv = cdeg[xv];
+    xs[lane] = in_row ? x : INT32_MAX;
+    wx[lane] = cx;
+    const int32_t prev = __shfl_up(x, 1, 64);
+    const bool u_sorted = ballot(in_row && lane > 0 && x <= prev) == 0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int64_t c = cx;
+    const bool up = in_row && u < x;
+    const uint32_t f12 = (c >= lam ? 1u : 0u) | ((2 * c > cu || 2 * c > cv) ? 2u : 0u);
+    const bool tri = u_sorted && du <= max_deg && vlen <= max_deg;
+    uint64_t todo = ballot(up && tri && (FLAGS || f12 == 0));
+    uint32_t f34 = 0;
+    while (todo) {
+      const int j = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int32_t v = __builtin_amdgcn_readlane(x, j);
+      const int32_t cj = __builtin_amdgcn_readlane(cx, j);
+      const int64_t b = readlane_i64(vb, j), dv = readlane_i64(vlen, j), cvv = readlane_i64(cv, j);
+      const bool in_v = lane < dv;
+      const int64_t eb = in_v ? b + lane : a;
+      const int32_t y = col[eb], cy = w[eb];
+      const int32_t py = __shfl_up(y, 1, 64);
+      const bool v_sorted = ballot(in_v && lane > 0 && y <= py) == 0;
+      // position of y in u's row (entries past the row's end read INT32_MAX)
+      int pos = 0;
+#pragma unroll
+      for (int step = PR34W_MAX / 2; step > 0; step >>= 1) pos += xs[pos + step - 1] < y ? step : 0;
+      pos = pos < PR34W_MAX ? pos : PR34W_MAX - 1;
+      const bool hit = in_v && xs[pos] == y && y != u && y != v;
+      const int64_t cuy = hit ? wx[pos] : 0, cvy = cy;
+      const int64_t m = hit ? (cuy < cvy ? cuy : cvy) : 0;
+      const int64_t paths = (int64_t)cj + wave_sum_i64_dpp(m);
+      const bool pr3 = ballot(hit && cu < 2 * (cj + cuy) && cvv < 2 * (cj + cvy)) != 0;
+      const uint32_t bits = v_sorted ? ((pr3 ? 4u : 0u) | (paths >= lam ? 8u : 0u)) : 0u;
+      if (lane == j) f34 = bits;
+    }
+    if (FLAGS) {
+      if (in_row) flags[a + lane] = (uint8_t)(up ? (f12 | f34) : 0u);
+    } else if (f34) {
+      ++local;
+      pr_flag(ucount, g, last);
+      if (ld_relaxed(parent + u) != ld_relaxed(parent + x)) uf_union(parent, u, x);
+    }
+  }
+  if (!FLAGS) {
+    const int64_t tot = wave_sum_i64(local);
+    if (lane == 0 && tot) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)tot);
+  }
 }
 
 // Every test's outcome per entry (u, v), u < v (bits PR1 1, PR2 2, PR3 4,
@@ -750,29 +971,43 @@ __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __rest
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t tile = 256 * 8;
   for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nnz; t0 += (int64_t)gridDim.x * tile) {
+    // Each load step is issued for all eight entries before any result is
+    // used, and no load sits in a divergent branch: a lane that has nothing
+    // to fetch reads the tile's first element instead (one shared line), so
+    // a wave waits for three rounds of loads, not three per entry.
+    const int64_t e0 = t0 + (int64_t)wave * 512 + lane;
+    const int64_t safe = t0 < nnz ? t0 : 0;
+    int32_t u[8], x[8];
+    bool in[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t e = e0 + r * 64;
+      const int64_t ec = e < nnz ? e : safe;
+      u[r] = src[ec];
+      x[r] = col[ec];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) in[r] = e0 + r * 64 >= nnz;
+    if (inref) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t bu = inref[u[r] >> 5], bx = inref[x[r] >> 5];
+        in[r] = in[r] | (((bu >> (u[r] & 31)) & (bx >> (x[r] & 31)) & 1u) != 0);
+      }
+    }
     uint64_t k[8];
     int32_t vv[8];
     uint64_t msk[8];
-    uint32_t mine = 0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      int64_t e = t0 + (int64_t)wave * 512 + r * 64 + lane;
-      bool ok = e < nnz;
-      int32_t a = -1, b = -1;
-      if (ok) {
-        const int32_t u = src[e], x = col[e];
-        if (inref && bit_at(inref, u) && bit_at(inref, x)) {
-          ok = false;  // inside the reference block
-        } else {
-          a = lab[u];
-          b = lab[x];
-        }
-      }
-      ok = ok && a >= 0 && b >= 0 && a != b;
+      // in[r]: past the end, or inside the reference block (never crossing)
+      const int32_t a = lab[in[r] ? 0 : u[r]];
+      const int32_t b = lab[in[r] ? 0 : x[r]];
+      const int32_t c = w[in[r] ? safe : e0 + r * 64];
+      const bool ok = !in[r] && a >= 0 && b >= 0 && a != b;
       k[r] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
-      vv[r] = ok ? w[e] : 0;
+      vv[r] = ok ? c : 0;
       msk[r] = ballot(ok);
-      mine += ok ? 1u : 0u;
     }
     uint32_t wtot = 0;
 #pragma unroll
@@ -797,7 +1032,6 @@ __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __rest
       o += popc64(msk[r]);
     }
     __syncthreads();
-    (void)mine;
   }
 }
 

@@ -306,6 +306,15 @@ def test_contraction_kernels_equal_cpu_contraction():
     packed, vo, eo = gg.pack([gg.batch_graph(i) for i in range(100, 160)])
     cases.append(packed)
     cases.append(gg.from_edges(5, [(0, 1), (0, 1), (1, 2), (2, 2), (3, 4), (4, 0)], [1, 2, 3, 9, 4, 5]))
+    # a hub whose row spans many ingest chunks, with every odd vertex
+    # isolated (runs of empty rows inside chunks)
+    leaves = np.arange(0, 24000, 2)
+    leaves = leaves[leaves != 12000]
+    cases.append(gg.from_edges(24001, [(12000, int(v)) for v in leaves], rng.integers(1, 9, size=len(leaves)),
+                               name="hub-with-empty-rows"))
+    # a long run of empty rows before a small dense part
+    dense = [(50000 + i, 50000 + j) for i in range(40) for j in range(i + 1, 40)]
+    cases.append(gg.from_edges(50040, dense, rng.integers(1, 5, size=len(dense)), name="empty-prefix"))
     for g in cases:
         for k in [1, 2, 3, 17, 1000, g.n]:
             k = min(k, g.n)

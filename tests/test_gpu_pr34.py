@@ -65,7 +65,7 @@ def test_flags_equal_oracle_on_random_graphs():
             g = gg.from_edges(g.n, e, rng.integers(1, 4, size=len(e)), name="parallel")
         lam = oracle.bruteforce(g)[0] if g.n <= 14 else oracle.noi(g)[0]
         for lhat in (max(lam, 1), lam + 3):
-            for max_deg in (3, 64):
+            for max_deg in (3, 64, 100):
                 f = _flags_equal(g, lhat, max_deg)
                 np.add.at(seen, f, 1)
     # every combination of the four bits that occurs is compared; PR3 and PR4
@@ -80,6 +80,7 @@ def test_flags_equal_oracle_on_workload_shapes():
         for lhat in (lam, lam + 10):
             announce("pr flags", g.name, lhat)
             _flags_equal(g, lhat, 64)
+            _flags_equal(g, lhat, 100)
         # a contracted graph (sorted rows, summed parallel edges)
         lab = np.arange(g.n) // 3
         h, _ = oracle.contract(g, lab)
@@ -93,7 +94,7 @@ def test_solves_with_triangle_tests_equal_oracle():
     packed, vo, eo = gg.pack(graphs)
     rp, col, w = mc.to_device(packed, "cuda")
     for opts in [dict(pr_triangle_deg=-64), dict(pr_triangle_deg=16, scan_mode=2),
-                 dict(pr_triangle_deg=-64, whole_max=64), dict(pr_triangle_deg=0)]:
+                 dict(pr_triangle_deg=-64, whole_max=64), dict(pr_triangle_deg=-100), dict(pr_triangle_deg=0)]:
         announce("pr34 batch", opts)
         lams, sides, st = mc.mincut_batched(rp, col, w, vo, **opts)
         assert list(lams) == refs, opts
