@@ -141,7 +141,7 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
   const int32_t ng = A.gn[g];
   int32_t sid = 0;
   if (lane == 0) sid = atomicAdd(&A.ctl->scan_ids, 1);
-  sid = shfl(sid, 0);
+  sid = bcast(sid, 0);
 
   int64_t alpha = 0, best_a = INT64_MAX;
   int32_t k = 0, best_k = 0;
@@ -166,7 +166,7 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
     const int64_t rx = m.r[slot];
     int32_t old = 0;
     if (lane == 0) old = atomicCAS(A.claim + x, -1, sid);
-    old = shfl(old, 0);
+    old = bcast(old, 0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (old != -1 && old != sid) {
       if (lane == 0) m.vid[slot] |= ST_BLACK;  // visited elsewhere: blacklist, leave at once
@@ -215,7 +215,7 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
         int cnt = popc64(cm);
         int64_t pbase = 0;
         if (lane == 0) pbase = atomicAdd((unsigned long long*)&A.ctl->pairs, (unsigned long long)cnt);
-        pbase = shfl(pbase, 0);
+        pbase = bcast(pbase, 0);
         if (cross) {
           int64_t at = pbase + popc64(cm & lanemask_lt());
           if (at < A.pairs_cap) A.pairs[at] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) k_capforest(ScanArgs A) {
   while (true) {
     int32_t item = 0;
     if (lane == 0) item = atomicAdd(&A.ctl->work_next, 1);
-    item = shfl(item, 0);
+    item = bcast(item, 0);
     if (A.whole_mode) {
       if (item >= *A.whole_count) break;
       const int32_t g = A.whole[item];
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_capforest(ScanArgs A) {
     while (todo) {
       const int src_lane = __builtin_ctzll(todo);
       todo &= todo - 1;
-      const int32_t s = shfl((int32_t)v, src_lane);
+      const int32_t s = bcast((int32_t)v, src_lane);
       if (ld_relaxed(A.claim + s) != -1) continue;
       run_scan<CAP>(A, m, s, A.gid[s]);
     }

@@ -28,6 +28,22 @@ __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 template <typename T>
 __device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, MC_WAVE); }
 
+// The value of lane l, which must be the same for the whole wave (a
+// constant, or taken from a ballot): a scalar lane read, where shfl is an
+// LDS permute with its round trip.  Lane l must have computed v.
+template <typename T>
+__device__ __forceinline__ T bcast(T v, int l) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+
 // Wave-wide reductions (all lanes receive the result).
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, MC_WAVE);

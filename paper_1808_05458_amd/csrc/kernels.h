@@ -247,7 +247,7 @@ __global__ void k_min_degree(int32_t n, const int64_t* cdeg, const int32_t* gid,
     best = key < best ? key : best;
     sum += cdeg[v];
   }
-  const int32_t g0 = shfl(cur, 0);
+  const int32_t g0 = bcast(cur, 0);
   const bool uniform = ballot(cur == g0) == ~0ull;
   if (uniform && g0 >= 0) {
     const uint64_t m = wave_min_u64(best);

@@ -116,8 +116,8 @@ __device__ __forceinline__ bool ss_relax(LDS& L, const SmallSweepArgs& A, int32_
       at = atomicAdd(&L.npairs, popc64(cm));
       qa = atomicAdd(&L.cap_tail, popc64(cm));
     }
-    at = shfl(at, 0);
-    qa = shfl(qa, 0);
+    at = bcast(at, 0);
+    qa = bcast(qa, 0);
     if (cross) {
       const int32_t rank = popc64(cm & lanemask_lt());
       A.capq[v0 + at + rank] = v0 + yl;

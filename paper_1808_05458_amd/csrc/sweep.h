@@ -244,7 +244,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
     const int leader = __builtin_ctzll(cm);
     int32_t base = 0;
     if (lane == leader) base = atomicAdd(q.cap_tail, popc64(cm));
-    base = shfl(base, leader);
+    base = bcast(base, leader);
     if (cross) {
       const int32_t at = base + popc64(cm & lanemask_lt());
       A.capq[at] = y;
@@ -264,11 +264,12 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
     int64_t pbase = 0;
     if (lane == leader)
       pbase = (int64_t)atomicAdd((unsigned long long*)q.pool_next, (unsigned long long)popc64(pm));
-    pbase = shfl(pbase, leader);
-    const int64_t idx = pbase + popc64(pm & lanemask_lt());
+    pbase = bcast(pbase, leader);
+    const uint64_t pm0 = pm;
+    const int64_t idx = pbase + popc64(pm0 & lanemask_lt());
     const int32_t b = push ? (int32_t)(nw >> A.shift) : -1;
     while (pm) {
-      const int32_t b0 = shfl(b, __builtin_ctzll(pm));
+      const int32_t b0 = bcast(b, __builtin_ctzll(pm));
       const bool mine = push && b == b0;
       const uint64_t grp = ballot(mine);
       pm &= ~grp;
@@ -284,8 +285,8 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
         if (!(ld_relaxed(&q.bitmap[b0 >> 6]) & wbit))
           atomicOr((unsigned long long*)&q.bitmap[b0 >> 6], wbit);
       }
-      old_head = shfl(old_head, hi);
-      const int64_t prev_idx = shfl(idx, prev_lane);
+      old_head = bcast(old_head, hi);
+      const int64_t prev_idx = pbase + popc64(pm0 & ((1ull << prev_lane) - 1));  // idx of prev_lane
       if (mine && idx < A.pool_cap) pool_put(A, q, idx, y, lower ? (int32_t)prev_idx : old_head);
     }
   }
@@ -380,7 +381,7 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
     uint64_t m = ballot(word != 0);
     if (m == 0) return -1;
     const int bw = 63 - __builtin_clzll(m);
-    const uint64_t wv = shfl(word, bw);
+    const uint64_t wv = bcast(word, bw);
     const int b = bw * 64 + 63 - __builtin_clzll(wv);
     int32_t x = -1;
     if (A.shift == 0) {
@@ -397,12 +398,12 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
         }
         st_relaxed(&q.head[b], idx);
       }
-      x = shfl(x, 0);
+      x = bcast(x, 0);
       if (x >= 0) {
-        pr.ra = shfl(pr.ra, 0);
-        pr.rb = shfl(pr.rb, 0);
-        pr.cd = shfl(pr.cd, 0);
-        pr.key = shfl(pr.key, 0);
+        pr.ra = bcast(pr.ra, 0);
+        pr.rb = bcast(pr.rb, 0);
+        pr.cd = bcast(pr.cd, 0);
+        pr.key = bcast(pr.key, 0);
         return x;
       }
       // the segment, from the cursor on, 64 entries per pass (a chunk read
@@ -463,8 +464,8 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
           idx = e.y;
         }
       }
-      best_key = shfl(best_key, 0);
-      best_v = shfl(best_v, 0);
+      best_key = bcast(best_key, 0);
+      best_v = bcast(best_v, 0);
       int64_t seg_best = -1;
       int32_t seg_pos = -1;
       const int32_t cur0 = ld_relaxed(&q.seg_cur[b]);
@@ -625,7 +626,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
       int cmd = -1;
       while (cmd < 0) {
         const int32_t h = ld_relaxed(q.cap_head), t = ld_relaxed(q.cap_tail);
-        const int32_t stamp = shfl(step, 0) + 1;
+        const int32_t stamp = bcast(step, 0) + 1;
         if (t > h) {
           const int32_t size = t - h;
           if (size > A.big) { cmd = CMD_EXIT_BIG; break; }
@@ -817,12 +818,39 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
 }
 
 // The crossing edges found by the sweeps, united after them: (capx[i],
-// capq[i]) of graph blockIdx.y.
+// capq[i]) of graph blockIdx.y.  Consecutive FIFO entries usually share
+// capx (one scanned vertex crossed many neighbours); united one by one,
+// their links all target the same root and retry on each other.  So per
+// run of equal capx in a wave, the smallest capq is united with capx and
+// the others with it: the same sets, and each of the others links under a
+// smaller root through its own entry.
 __global__ void k_sweep_unite(const SweepArgs* args) {
   const SweepDev A = dev_view(args[blockIdx.y]);
   const int32_t n = A.ctl->cap_tail;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    uf_union(A.parent, A.capx[i], A.capq[i]);
+  const int lane = lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
+       base += (int64_t)gridDim.x * blockDim.x) {  // wave-uniform bound
+    const int64_t i = base + lane;
+    const bool ok = i < n;
+    const int32_t x = ok ? A.capx[i] : -1;
+    const int32_t q = ok ? A.capq[i] : INT32_MAX;
+    const int32_t xp = __shfl_up(x, 1, 64), xn = __shfl_down(x, 1, 64);
+    int start = (lane == 0 || xp != x) ? lane : 0;  // first lane of the run
+    int end = (lane == 63 || xn != x) ? lane : 63;  // last lane of the run
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(start, o, 64);
+      if (lane >= o && t > start) start = t;
+      const int u = __shfl_down(end, o, 64);
+      if (lane + o < 64 && u < end) end = u;
+    }
+    int32_t m = q;  // minimum of capq over [lane, end]
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_down(m, o, 64);
+      if (lane + o <= end && t < m) m = t;
+    }
+    const int32_t run_min = __shfl(m, start, 64);
+    if (ok) uf_union(A.parent, q == run_min ? x : run_min, q);
+  }
 }
 
 // Per graph: status, FIFO bounds and row entries of the pending batch, for
@@ -866,7 +894,7 @@ __device__ __forceinline__ void flush_wave_buf(const SweepArgs& A, int32_t* wbuf
   if (cnt == 0) return;
   int32_t base = 0;
   if (lane == 0) base = atomicAdd(&A.ctl->cap_tail, cnt);
-  base = shfl(base, 0);
+  base = bcast(base, 0);
   for (int32_t i = lane; i < cnt; i += 64) {
     A.capq[base + i] = wbuf[2 * i];
     A.capx[base + i] = wbuf[2 * i + 1];
