@@ -915,7 +915,8 @@ struct Solver {
 
     // ---- ingest: validation, entry sources, weighted degrees, trivial bound
     {
-      TimedScope t("ingest", (double)(N + 1) * 8 + (double)E * 12 + (double)E * 4 + N * 8);
+      // row_ptr read once
+      TimedScope t("ingest", (double)(N + 1) * 8);
       hipLaunchKernelGGL(k_check_rowptr, grid(N), dim3(TB), 0, s, N, E, P.rp, ws.ctl);
     }
     int rc = read_ctl();
@@ -924,6 +925,8 @@ struct Solver {
     int32_t* gid = ws.gid[0];
     int32_t* gid_next = ws.gid[1];
     {
+      // col, w read and src written per entry (12 B); per vertex row_ptr
+      // for the chunk rows, the degree written and read back, graph ids
       TimedScope t("ingest", (double)E * 12 + (double)N * 24);
       hipLaunchKernelGGL(k_init_vertices, grid(N), dim3(TB), 0, s, N, ws.voff, G, gid, ws.ogid, ws.map);
       fill<int64_t>(ws.cdeg, 0, N, s);
@@ -1082,13 +1085,8 @@ struct Solver {
       const int32_t tri_deg = opt.pr_triangle_deg < 0 ? -opt.pr_triangle_deg : opt.pr_triangle_deg;
       if (opt.use_pr && tri_deg > 0 && (round > 1 || opt.pr_triangle_deg < 0)) {
         TimedScope t("pr34", (double)nnz * 20);
-        if (tri_deg <= PR34W_MAX)
-          hipLaunchKernelGGL(k_pr34w<false>, dim3(grid_for((int64_t)n * 64, TB, num_cu * 16)), dim3(TB), 0, s, n,
-                             rp, col, w, ws.cdeg, gid, cap, ws.active, (int64_t)0, tri_deg, ws.parent, ws.ucount,
-                             (uint8_t*)nullptr, ws.ctl);
-        else
-          hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
-                             ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
+        hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
+                           ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
       }
       // blocks left by the tests; graphs already at two blocks skip the scans
       hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
@@ -1487,13 +1485,8 @@ int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid(grid_for(g->n, 256, 65536));
   hipLaunchKernelGGL(k_row_degrees, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg);
-  if (max_deg <= PR34W_MAX)
-    hipLaunchKernelGGL(k_pr34w<true>, dim3(grid_for((int64_t)g->n * 64, 256, 65536)), dim3(256), 0, s, g->n,
-                       g->row_ptr, g->col, g->w, ws.cdeg, (const int32_t*)nullptr, (const int64_t*)nullptr,
-                       (const int32_t*)nullptr, lhat, max_deg, (int32_t*)nullptr, (int32_t*)nullptr, flags, ws.ctl);
-  else
-    hipLaunchKernelGGL(k_pr_flags, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg, lhat, max_deg,
-                       flags);
+  hipLaunchKernelGGL(k_pr_flags, grid, dim3(256), 0, s, g->n, g->row_ptr, g->col, g->w, ws.cdeg, lhat, max_deg,
+                     flags);
   MC_HIP(hipStreamSynchronize(s));
   MC_HIP(hipGetLastError());
   return MC_OK;

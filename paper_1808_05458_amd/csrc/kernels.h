@@ -701,110 +701,6 @@ __global__ void k_pr34(int64_t nnz, const int32_t* __restrict__ src, const int32
   if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
 
-// The same tests, one wave per vertex u, for limits of at most 64 entries:
-// the lanes load u's row (one entry each) into LDS and, with it, the row
-// bounds and degree of every neighbour; then for each neighbour v > u that
-// needs the tests, the lanes load v's row together and look each entry up
-// in u's row by binary search.  Both rows are read once, every row in one
-// round trip, instead of one dependent load per merge step.  Per edge the
-// outcome is pr34_eval's.
-// FLAGS: write every test's bits per entry (k_pr_flags' output, lhat =
-// lam_all for every vertex); else unite the edges that pass PR3 or PR4 but
-// not PR1/PR2 (those were united before), as k_pr34 does.
-constexpr int PR34W_MAX = 64;
-template <bool FLAGS>
-__global__ void __launch_bounds__(256) k_pr34w(int32_t n, const int64_t* __restrict__ rp,
-                                               const int32_t* __restrict__ col, const int32_t* __restrict__ w,
-                                               const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
-                                               const int64_t* __restrict__ lhat, const int32_t* __restrict__ active,
-                                               int64_t lam_all, int32_t max_deg, int32_t* parent, int32_t* ucount,
-                                               uint8_t* flags, Ctl* ctl) {
-  __shared__ int32_t xs_all[4][PR34W_MAX];
-  __shared__ int32_t wx_all[4][PR34W_MAX];
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
-  int32_t* xs = xs_all[wave];
-  int32_t* wx = wx_all[wave];
-  int64_t local = 0;
-  int32_t last = -1;
-  for (int64_t uu = gtid() >> 6; uu < n; uu += gstride() >> 6) {
-    const int32_t u = (int32_t)uu;
-    const int64_t a = rp[u], du = rp[u + 1] - a;
-    int32_t g = 0;
-    int64_t lam = lam_all;
-    if (!FLAGS) {
-      g = gid[u];
-      if (!active[g] || du > max_deg) continue;
-      lam = lhat[g];
-    }
-    if (du <= 0) continue;
-    if (FLAGS && du > PR34W_MAX) {  // PR1 and PR2 only
-      const int64_t cu = cdeg[u];
-      for (int64_t e = a + lane; e < a + du; e += 64) {
-        const int32_t v = col[e];
-        const int64_t c = w[e];
-        uint32_t f = 0;
-        if (u < v) f = (c >= lam ? 1u : 0u) | ((2 * c > cu || 2 * c > cdeg[v]) ? 2u : 0u);
-        flags[e] = (uint8_t)f;
-      }
-      continue;
-    }
-    const bool in_row = lane < du;
-    const int64_t ea = in_row ? a + lane : a;
-    const int32_t x = col[ea], cx = w[ea];
-    const int64_t cu = cdeg[u];
-    // the neighbour's row bounds and degree, for all entries at once
-    const int32_t xv = in_row ? x : u;
-    const int64_t vb = rp[xv], vlen = rp[xv + 1] - vb, cv = cdeg[xv];
-    xs[lane] = in_row ? x : INT32_MAX;
-    wx[lane] = cx;
-    const int32_t prev = __shfl_up(x, 1, 64);
-    const bool u_sorted = ballot(in_row && lane > 0 && x <= prev) == 0;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int64_t c = cx;
-    const bool up = in_row && u < x;
-    const uint32_t f12 = (c >= lam ? 1u : 0u) | ((2 * c > cu || 2 * c > cv) ? 2u : 0u);
-    const bool tri = u_sorted && du <= max_deg && vlen <= max_deg;
-    uint64_t todo = ballot(up && tri && (FLAGS || f12 == 0));
-    uint32_t f34 = 0;
-    while (todo) {
-      const int j = __builtin_ctzll(todo);
-      todo &= todo - 1;
-      const int32_t v = __builtin_amdgcn_readlane(x, j);
-      const int32_t cj = __builtin_amdgcn_readlane(cx, j);
-      const int64_t b = readlane_i64(vb, j), dv = readlane_i64(vlen, j), cvv = readlane_i64(cv, j);
-      const bool in_v = lane < dv;
-      const int64_t eb = in_v ? b + lane : a;
-      const int32_t y = col[eb], cy = w[eb];
-      const int32_t py = __shfl_up(y, 1, 64);
-      const bool v_sorted = ballot(in_v && lane > 0 && y <= py) == 0;
-      // position of y in u's row (entries past the row's end read INT32_MAX)
-      int pos = 0;
-#pragma unroll
-      for (int step = PR34W_MAX / 2; step > 0; step >>= 1) pos += xs[pos + step - 1] < y ? step : 0;
-      pos = pos < PR34W_MAX ? pos : PR34W_MAX - 1;
-      const bool hit = in_v && xs[pos] == y && y != u && y != v;
-      const int64_t cuy = hit ? wx[pos] : 0, cvy = cy;
-      const int64_t m = hit ? (cuy < cvy ? cuy : cvy) : 0;
-      const int64_t paths = (int64_t)cj + wave_sum_i64_dpp(m);
-      const bool pr3 = ballot(hit && cu < 2 * (cj + cuy) && cvv < 2 * (cj + cvy)) != 0;
-      const uint32_t bits = v_sorted ? ((pr3 ? 4u : 0u) | (paths >= lam ? 8u : 0u)) : 0u;
-      if (lane == j) f34 = bits;
-    }
-    if (FLAGS) {
-      if (in_row) flags[a + lane] = (uint8_t)(up ? (f12 | f34) : 0u);
-    } else if (f34) {
-      ++local;
-      pr_flag(ucount, g, last);
-      if (ld_relaxed(parent + u) != ld_relaxed(parent + x)) uf_union(parent, u, x);
-    }
-  }
-  if (!FLAGS) {
-    const int64_t tot = wave_sum_i64(local);
-    if (lane == 0 && tot) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)tot);
-  }
-}
-
 // Every test's outcome per entry (u, v), u < v (bits PR1 1, PR2 2, PR3 4,
 // PR4 8; 0 for the other entries), one thread per vertex row.
 __global__ void k_pr_flags(int32_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
