@@ -188,8 +188,12 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
     for (int64_t base = e0; base < e1; base += 64) {
       const int64_t e = base + lane;
       bool act = e < e1;
-      int32_t y = act ? A.col[e] : 0;
-      int32_t c = act ? A.w[e] : 0;
+      const int64_t ec = act ? e : base;  // loads outside branches: no wait at a branch end
+      int32_t y = A.col[ec];
+      int32_t c = A.w[ec];
+      keep(c);
+      y = act ? y : 0;
+      c = act ? c : 0;
       if (y == x) act = false;
       if (act && A.eager) {
         int32_t cl = ld_relaxed(A.claim + y);

@@ -44,6 +44,12 @@ __device__ __forceinline__ T bcast(T v, int l) {
   }
 }
 
+// Takes v as used at this point: keeps the compiler from sinking the load
+// that produced it into the branch that consumes it, so loads issued
+// together are waited for together (a load sunk into a branch issues only
+// after the branch's condition, which often waits for another load).
+__device__ __forceinline__ void keep(int32_t& v) { asm volatile("" : "+v"(v)); }
+
 // Wave-wide reductions (all lanes receive the result).
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, MC_WAVE);

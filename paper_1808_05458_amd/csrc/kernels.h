@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const in
     // next row, and the largest id there owns the entries
     for (int64_t base = (int64_t)r0 + 1;; base += 256) {
       const int64_t r = base + tid;
-      const int64_t st = r < n ? rp[r] : nnz;
+      const int64_t st = rp[r < n ? r : n];  // row_ptr[n] = nnz ends the chunk
       if (st > cs && st < ce) atomicMax(&row_at[st - cs], (int32_t)r);
       if (!__syncthreads_or(tid == 255 && st < ce)) break;
     }

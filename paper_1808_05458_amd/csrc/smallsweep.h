@@ -255,7 +255,12 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
           for (int64_t base = e0; base < e1; base += 64) {
             const int64_t e = base + lane;
             const bool ok = e < e1;
-            crossed |= ss_relax(L, A, v0, lam, ok, xl, ok ? A.col[e] - v0 : 0, ok ? A.w[e] : 0, rows, internal);
+            // loads outside branches (a load inside one is waited for at
+            // its end, and the weight's load would wait for the column's)
+            const int64_t ec = ok ? e : base;
+            int32_t yv = A.col[ec], cv = A.w[ec];
+            keep(cv);
+            crossed |= ss_relax(L, A, v0, lam, ok, xl, ok ? yv - v0 : 0, ok ? cv : 0, rows, internal);
           }
           if (lane == 0) {
             alpha += dx - 2 * (int64_t)rx;

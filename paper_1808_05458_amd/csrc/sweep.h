@@ -525,8 +525,12 @@ __device__ __forceinline__ int64_t wave_relax_known(const SA& A, const SweepQ& q
     for (int64_t base = e0; base < e1; base += 64) {
       const int64_t e = base + lane;
       const bool act = e < e1;
-      const int32_t y = act ? A.col[e] : 0;
-      const int32_t c = act ? A.w[e] : 0;
+      // loads outside branches (a load inside one is waited for at its end)
+      const int64_t ec = act ? e : base;
+      int32_t yv = A.col[ec], cv = A.w[ec];
+      keep(cv);
+      const int32_t y = act ? yv : 0;
+      const int32_t c = act ? cv : 0;
       bool member = false;  // with one vertex, y == x is a self-loop, skipped anyway
       for (int k = 0; k < cnt && cnt > 1; ++k) member |= y == __builtin_amdgcn_readlane(xs, k);
       internal += sweep_relax(A, q, x, y, c, stamp, act, nullptr, nullptr, member);
@@ -711,7 +715,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
       for (int64_t base = e0 + wave * 64; base < e1; base += SWEEP_THREADS) {
         const int64_t e = base + lane;
         const bool act = e < e1;
-        internal += sweep_relax(A, q, x, act ? A.col[e] : 0, act ? A.w[e] : 0, stamp, act);
+        const int64_t ec = act ? e : base;
+        int32_t yv = A.col[ec], cv = A.w[ec];
+        keep(cv);
+        internal += sweep_relax(A, q, x, act ? yv : 0, act ? cv : 0, stamp, act);
       }
     } else {
       // the batch's entries spread evenly over the workgroup (a hub row in
