@@ -878,11 +878,15 @@ __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
   const int32_t stamp = c->step + 1;
   int64_t sum = 0, deg = 0;
   for (int64_t i = h + gtid(); i - lane_id() < t; i += gstride()) {  // wave-uniform bound
-    if (i < t) {
-      int32_t x = A.capq[i];
-      sum += A.cdeg[x] - 2 * (int64_t)rs_r(A.rs[x]);
+    // loads outside the branch (one round trip for all of them); a lane past
+    // the end reads the batch's first vertex
+    const bool in = i < t;
+    const int32_t x = A.capq[in ? i : h];
+    const int64_t cd = A.cdeg[x], r = rs_r(A.rs[x]), d = A.rp[x + 1] - A.rp[x];
+    if (in) {
+      sum += cd - 2 * r;
       *rs_stamp_ptr(A.rs + x) = stamp;
-      deg += A.rp[x + 1] - A.rp[x];
+      deg += d;
     }
   }
   sum = wave_sum_i64(sum);
@@ -973,6 +977,7 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
   const SweepQ gq = global_q(c);
   const int64_t total = off[bsz];
   const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
+  const int64_t e_idle = A.rp[A.v0];  // an entry of the graph (it has some: a batch is being relaxed)
   int64_t internal = 0;
   for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
     const int64_t t0 = j * BIG_TILE, t1 = min(t0 + BIG_TILE, total);
@@ -1001,37 +1006,83 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
         }
         row = lo;
       }
-      int32_t xs[BIG_UNROLL], ys[BIG_UNROLL], cs[BIG_UNROLL];
+      // Each step below is issued for all BIG_UNROLL entries before any
+      // result is used, and no global access sits in a divergent branch:
+      // the tile costs three round trips (entries, neighbour state, adds),
+      // not three per entry.  An idle slot reads the graph's first entry.
+      int32_t xs[BIG_UNROLL];
+      int64_t es[BIG_UNROLL];
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) {
         const int64_t i = i0 + u;
         xs[u] = -1;
-        ys[u] = 0;
-        cs[u] = 0;
+        es[u] = e_idle;
         if (i < hi_e) {
-          while (s_off[row + 1] <= i) ++row;
-          const int64_t e = s_base[row] + (i - s_off[row]);
+          while (s_off[row + 1] <= i) ++row;  // LDS only
+          es[u] = s_base[row] + (i - s_off[row]);
           xs[u] = s_x[row];
-          ys[u] = A.col[e];
-          cs[u] = A.w[e];
         }
       }
+      int32_t ys[BIG_UNROLL], cs[BIG_UNROLL];
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) {
-        // the neighbour's state from the bitmaps: inside the batch, visited
-        // before it, or unvisited (then the add, and maybe a crossing)
-        bool act = xs[u] >= 0 && ys[u] != xs[u];
-        if (act) {
-          const int32_t i = ys[u] - A.v0;
-          if ((batch[i >> 5] >> (i & 31)) & 1u) {
-            internal += cs[u];
-            act = false;
-          } else if ((visited[i >> 5] >> (i & 31)) & 1u) {
-            act = false;
+        ys[u] = A.col[es[u]];
+        cs[u] = A.w[es[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) keep(cs[u]);  // weights in with the columns
+      // the neighbour's state from the bitmaps: inside the batch, visited
+      // before it, or unvisited (then the add, and maybe a crossing)
+      uint32_t bw[BIG_UNROLL], vw[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        const int32_t i = ys[u] - A.v0;
+        bw[u] = batch[i >> 5];
+        vw[u] = visited[i >> 5];
+      }
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {  // all states in before any add issues
+        keep(bw[u]);
+        keep(vw[u]);
+      }
+      bool upd[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        const int32_t i = ys[u] - A.v0;
+        const bool act = xs[u] >= 0 && ys[u] != xs[u];
+        const bool inb = (bw[u] >> (i & 31)) & 1u, vis = (vw[u] >> (i & 31)) & 1u;
+        if (act && inb) internal += cs[u];
+        upd[u] = act && !inb && !vis;
+      }
+      // the adds go to r alone, the low half of the word (r + c stays below
+      // 2^31, so it never carries into the stamp): a 32-bit return leaves no
+      // dead half whose register the compiler would reuse while the add is
+      // in flight, which forces a wait for it
+      int32_t old[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) old[u] = 0;
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u)
+        if (upd[u]) old[u] = atomic_add((int32_t*)(A.rs + ys[u]), cs[u]);
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) keep(old[u]);  // all adds issue before the first is used
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        const int64_t r_old = old[u];
+        const bool cross = upd[u] && r_old < A.lam && A.lam <= r_old + cs[u];
+        const uint64_t cm = ballot(cross);
+        if (cm) {
+          const int32_t at = *wcnt;
+          if (cross) {
+            const int32_t k = at + popc64(cm & lanemask_lt());
+            wbuf[2 * k] = ys[u];
+            wbuf[2 * k + 1] = xs[u];
           }
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) *wcnt = at + popc64(cm);
+          __builtin_amdgcn_wave_barrier();
+          if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
         }
-        internal += sweep_relax<false>(A, gq, xs[u], ys[u], cs[u], stamp, act, wbuf, wcnt, false, true);
-        if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
       }
       __syncthreads();  // the slice arrays are reused
     }
