@@ -50,6 +50,7 @@ __device__ __forceinline__ T bcast(T v, int l) {
 // after the branch's condition, which often waits for another load).
 __device__ __forceinline__ void keep(int32_t& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void keep(uint32_t& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void keep(int64_t& v) { asm volatile("" : "+v"(v)); }
 
 // Wave-wide reductions (all lanes receive the result).
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {

@@ -341,13 +341,16 @@ __device__ __forceinline__ void sweep_close_batch(SweepCtl* c, int32_t ng, int64
 }
 
 // A bucket entry is live if its vertex is unvisited and its r still maps to
-// the bucket.  Both loads are issued together.
+// the bucket (u: the vertex's packed word).
+template <class SA>
+__device__ __forceinline__ bool live_word(const SA& A, uint64_t u, int32_t v, int32_t b, int32_t& key) {
+  key = rs_r(u);
+  return v >= 0 && rs_stamp(u) == 0 && (int64_t)key < A.lam && (key >> A.shift) == b;
+}
 template <class SA>
 __device__ __forceinline__ bool live_in_bucket(const SA& A, int32_t v, int32_t b, int32_t& key) {
-  if (v < 0) return false;
-  const uint64_t u = ld_relaxed(A.rs + v);
-  key = rs_r(u);
-  return rs_stamp(u) == 0 && (int64_t)key < A.lam && (key >> A.shift) == b;
+  // no branch around the load (v < 0, an empty slot, reads the start's word)
+  return live_word(A, ld_relaxed(A.rs + (v >= 0 ? v : A.start)), v, b, key);
 }
 
 // What the single-pop step needs of the popped vertex besides its id: its
@@ -363,6 +366,20 @@ __device__ __forceinline__ void pop_row_load(const SA& A, int32_t x, int32_t key
   pr.rb = A.rp[x + 1];
   pr.cd = A.cdeg[x];
   pr.key = key;
+}
+
+// A candidate v of bucket b (v < 0: an empty slot): its liveness word and
+// its row loaded together, and all four taken as used at once, so they
+// complete in one round trip (left to itself, the compiler sinks the row
+// loads into the branch taken for a live candidate, after the liveness
+// result).
+template <class SA>
+__device__ __forceinline__ bool pop_candidate(const SA& A, int32_t v, int32_t b, PopRow& cand) {
+  const int32_t vx = v >= 0 ? v : A.start;
+  uint64_t u = ld_relaxed(A.rs + vx);
+  pop_row_load(A, vx, 0, cand);
+  asm volatile("" : "+v"(u), "+v"(cand.ra), "+v"(cand.rb), "+v"(cand.cd));
+  return live_word(A, u, v, b, cand.key);
 }
 
 // Single pop by wave 0: the highest non-empty bucket (bitmap words read by
@@ -390,11 +407,8 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
         while (idx >= 0) {
           int2 e = pool_at(A, q, idx);
           idx = e.y;
-          int32_t k = 0;
           PopRow cand;
-          const bool live = live_in_bucket(A, e.x, b, k);
-          pop_row_load(A, e.x >= 0 ? e.x : A.start, k, cand);  // in flight with the liveness loads
-          if (live) { x = e.x; pr = cand; break; }
+          if (pop_candidate(A, e.x, b, cand)) { x = e.x; pr = cand; break; }
         }
         st_relaxed(&q.head[b], idx);
       }
@@ -426,10 +440,8 @@ __device__ int32_t sweep_pop_wave0(const SA& A, const SweepQ& q, PopRow& pr) {
             if (lane == 0) { q.sc_hdr[0] = b; q.sc_hdr[1] = cur; }
           }
         }
-        int32_t k = 0;
         PopRow cand{0, 0, 0, 0};
-        const bool live = live_in_bucket(A, v, b, k);
-        pop_row_load(A, v >= 0 ? v : A.start, k, cand);  // no branch: no wait at its end
+        const bool live = pop_candidate(A, v, b, cand);
         const uint64_t ok = ballot(live);
         if (ok) {
           const int first = __builtin_ctzll(ok);
