@@ -325,13 +325,15 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
         __syncthreads();
         const int32_t total = L.boff[cn];
         for (int32_t i0 = 0; i0 < total; i0 += THREADS * SS_UNROLL) {
+          // rows from LDS first, then every entry's loads together, outside
+          // any branch (an idle slot reads the graph's first entry)
           int32_t ys[SS_UNROLL], cs[SS_UNROLL], xs[SS_UNROLL];
+          int64_t es[SS_UNROLL];
 #pragma unroll
           for (int u = 0; u < SS_UNROLL; ++u) {
             const int32_t i = i0 + u * THREADS + (int32_t)threadIdx.x;
             xs[u] = -1;
-            ys[u] = 0;
-            cs[u] = 0;
+            es[u] = ebase;
             if (i < total) {
               int32_t lo = 0, hi = cn - 1;  // the row: last k with boff[k] <= i
               while (lo < hi) {
@@ -339,11 +341,21 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
                 if (L.boff[mid] <= i) lo = mid;
                 else hi = mid - 1;
               }
-              const int64_t e = ebase + L.bbase[lo] + (i - L.boff[lo]);
+              es[u] = ebase + L.bbase[lo] + (i - L.boff[lo]);
               xs[u] = L.capped[b0 + c0 + lo];
-              ys[u] = A.col[e] - v0;
-              cs[u] = A.w[e];
             }
+          }
+#pragma unroll
+          for (int u = 0; u < SS_UNROLL; ++u) {
+            ys[u] = A.col[es[u]];
+            cs[u] = A.w[es[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < SS_UNROLL; ++u) {
+            keep(ys[u]);
+            keep(cs[u]);
+            ys[u] = xs[u] >= 0 ? ys[u] - v0 : 0;
+            cs[u] = xs[u] >= 0 ? cs[u] : 0;
           }
 #pragma unroll
           for (int u = 0; u < SS_UNROLL; ++u)
