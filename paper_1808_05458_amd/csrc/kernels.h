@@ -765,7 +765,11 @@ struct RootFlag {
   const int32_t* keep;  // per graph
   int32_t carry;        // 1: every graph is kept
   __device__ __forceinline__ int32_t operator()(int64_t v) const {
-    return (parent[v] == v && (carry || keep[gid[v]])) ? 1 : 0;
+    // every load issued whatever the parent and the mode (no load behind a
+    // short circuit or a branch: those wait for it at once)
+    const int32_t p = parent[v], g = gid[v];
+    const int32_t k = keep[g];
+    return (int32_t)(p == v) & (int32_t)((carry | k) != 0);
   }
 };
 
@@ -934,7 +938,8 @@ __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __rest
 struct HeadFlag {
   const uint64_t* keys;
   __device__ __forceinline__ int64_t operator()(int64_t i) const {
-    return (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+    const uint64_t a = keys[i], b = keys[i > 0 ? i - 1 : 0];  // no load behind a short circuit
+    return (i == 0 || a != b) ? 1 : 0;
   }
 };
 

@@ -43,10 +43,20 @@ template <typename Tout, typename In>
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(In in, int64_t n, Tout* partial) {
   __shared__ Tout wt[SCAN_THREADS / 64];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  Tout s = 0;
+  // every row's element read before any is added (an element past the end
+  // reads the last one and counts zero), so the loads overlap instead of
+  // waiting one by one
+  Tout v[SCAN_ROWS];
+#pragma unroll
   for (int r = 0; r < SCAN_ROWS; ++r) {
-    int64_t i = base + (int64_t)r * SCAN_THREADS + threadIdx.x;
-    if (i < n) s += (Tout)in(i);
+    const int64_t i = base + (int64_t)r * SCAN_THREADS + threadIdx.x;
+    v[r] = (Tout)in(i < n ? i : n - 1);
+  }
+  Tout s = 0;
+#pragma unroll
+  for (int r = 0; r < SCAN_ROWS; ++r) {
+    const int64_t i = base + (int64_t)r * SCAN_THREADS + threadIdx.x;
+    s += i < n ? v[r] : (Tout)0;
   }
   Tout tot;
   block_inclusive_scan<Tout>(s, wt, tot);
@@ -61,9 +71,16 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(In in, int64_t n, co
   __shared__ Tout wt[SCAN_THREADS / 64];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
   Tout carry = partial ? partial[blockIdx.x] : (Tout)0;
+  Tout vs[SCAN_ROWS];  // all rows read first (see k_scan_reduce)
+#pragma unroll
+  for (int r = 0; r < SCAN_ROWS; ++r) {
+    const int64_t i = base + (int64_t)r * SCAN_THREADS + threadIdx.x;
+    vs[r] = (Tout)in(i < n ? i : n - 1);
+  }
+#pragma unroll
   for (int r = 0; r < SCAN_ROWS; ++r) {
     int64_t i = base + (int64_t)r * SCAN_THREADS + threadIdx.x;
-    Tout v = (i < n) ? (Tout)in(i) : (Tout)0;
+    Tout v = (i < n) ? vs[r] : (Tout)0;
     Tout rowtot;
     Tout inc = block_inclusive_scan<Tout>(v, wt, rowtot);
     if (i < n) out[i] = carry + inc - v;
@@ -143,9 +160,18 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t* __restri
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * TILE;
+  // every key of the thread loaded before the first is counted (no load in
+  // a branch: a slot past the end reads the tile's first key)
+  uint64_t k[ITEMS];
+#pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
+    const int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
+    k[r] = keys[i < n ? i : base];
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&h[(k[r] >> shift) & 255], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -178,12 +204,19 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(
   uint64_t k[ITEMS];
   int32_t v[ITEMS];
   uint32_t pos[ITEMS];
+  // all of the thread's keys and values in flight together (no load in a
+  // branch: a slot past the end reads the tile's first entry)
+  const int64_t first = (int64_t)blockIdx.x * TILE;
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    k[r] = keys[i < n ? i : first];
+    v[r] = vals[i < n ? i : first];
+  }
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     int64_t i = wbase + r * 64 + lane;
     bool ok = i < n;
-    k[r] = ok ? keys[i] : 0;
-    v[r] = ok ? vals[i] : 0;
     uint32_t d = ok ? (uint32_t)((k[r] >> shift) & 255) : 0u;
     uint64_t valid = ballot(ok);
     uint64_t peers = match_digit(d) & valid;  // every lane takes part in the ballots
