@@ -233,7 +233,9 @@ int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labe
  * self-loops; PR3 and PR4 are evaluated only where both rows hold at most
  * max_deg entries in strictly increasing neighbour order (else bits 4 and 8
  * are 0).  These are the tests the solve applies (PR3 and PR4 when
- * opt->pr_triangle_deg > 0). */
+ * opt->pr_triangle_deg > 0).  MC_EINVAL for a null pointer or n < 1; the
+ * graph itself is not checked (row_ptr monotone from 0 to nnz, every col in
+ * [0, n)). */
 int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max_deg, uint8_t* flags);
 
 /* Test hook for the contraction step alone (section "Parallel Graph
@@ -241,7 +243,10 @@ int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max
  * vertex's block; the contracted graph (one vertex per block, parallel
  * edges summed, internal edges dropped, rows sorted by neighbour) is written
  * to row_ptr_out (DEVICE int64[n_new+1]), col_out and w_out (DEVICE int32,
- * at least g->nnz entries); *nnz_out (HOST) receives its entry count. */
+ * at least g->nnz entries); *nnz_out (HOST) receives its entry count.
+ * MC_EINVAL for a null pointer, n_new < 1, a row_ptr that does not rise
+ * from 0 to nnz, a col outside [0, n) or a weight below 1 (checked before
+ * any kernel indexes by col); the labels are not checked. */
 int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, void* stream,
                       int64_t* row_ptr_out, int32_t* col_out, int32_t* w_out, int64_t* nnz_out);
 
