@@ -859,6 +859,12 @@ __global__ void k_block_bits(int32_t n, const int32_t* lab, const int32_t* gid, 
 
 __device__ __forceinline__ bool bit_at(const uint32_t* b, int32_t v) { return (b[v >> 5] >> (v & 31)) & 1u; }
 
+// Surviving entries are staged in LDS and written out in blocks: one atomic
+// reservation per EMIT_STAGE entries instead of one per tile (per-tile
+// reservations on the one counter serialise, and each waits for its reply
+// behind a workgroup barrier).  The order of the emitted entries is free:
+// they are sorted next.
+constexpr int EMIT_STAGE = 2048;  // at least one tile
 __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __restrict__ src,
                                               const int32_t* __restrict__ col,
                                               const int32_t* __restrict__ w,
@@ -866,11 +872,36 @@ __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __rest
                                               const uint32_t* __restrict__ inref,
                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
                                               Ctl* ctl) {
-  __shared__ uint32_t wcnt[4];
+  __shared__ uint32_t wcnt_buf[2][4];  // per tile parity: a wave may write the next tile's
+                                       // counts while another still reads this tile's
   __shared__ unsigned long long base_s;
+  __shared__ uint64_t st_k[EMIT_STAGE];
+  __shared__ int32_t st_v[EMIT_STAGE];
+  __shared__ uint32_t st_n;
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int64_t tile = 256 * 8;
+  static_assert(EMIT_STAGE >= 256 * 8, "a tile's survivors fit the stage");
+  if (threadIdx.x == 0) st_n = 0;
+  __syncthreads();
+  // write the staged entries out (block-uniform call)
+  auto flush = [&]() {
+    const uint32_t n = st_n;
+    if (n == 0) return;
+    if (threadIdx.x == 0) base_s = atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)n);
+    __syncthreads();
+    const uint64_t base = base_s;
+    for (uint32_t i = threadIdx.x; i < n; i += 256) {
+      keys[base + i] = st_k[i];
+      vals[base + i] = st_v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) st_n = 0;
+    __syncthreads();
+  };
+  int parity = 0;
   for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nnz; t0 += (int64_t)gridDim.x * tile) {
+    uint32_t* wcnt = wcnt_buf[parity];
+    parity ^= 1;
     // Each load step is issued for all eight entries before any result is
     // used, and no load sits in a divergent branch: a lane that has nothing
     // to fetch reads the tile's first element instead (one shared line), so
@@ -914,25 +945,26 @@ __global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __rest
     for (int r = 0; r < 8; ++r) wtot += popc64(msk[r]);
     if (lane == 0) wcnt[wave] = wtot;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t s = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-      base_s = s ? atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)s) : 0;
-    }
-    __syncthreads();
-    uint64_t o = base_s;
+    const uint32_t tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (tot == 0) continue;  // block-uniform
+    if (st_n + tot > (uint32_t)EMIT_STAGE) flush();
+    uint32_t o = st_n;
     for (int i = 0; i < wave; ++i) o += wcnt[i];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      bool ok = (msk[r] >> lane) & 1;
+      const bool ok = (msk[r] >> lane) & 1;
       if (ok) {
-        uint64_t at = o + popc64(msk[r] & lanemask_lt());
-        keys[at] = k[r];
-        vals[at] = vv[r];
+        const uint32_t at = o + popc64(msk[r] & lanemask_lt());
+        st_k[at] = k[r];
+        st_v[at] = vv[r];
       }
       o += popc64(msk[r]);
     }
     __syncthreads();
+    if (threadIdx.x == 0) st_n += tot;
+    __syncthreads();
   }
+  flush();
 }
 
 struct HeadFlag {
