@@ -632,7 +632,9 @@ __global__ void __launch_bounds__(256) k_pr(int64_t nnz, const int32_t* __restri
         if (ld_relaxed(parent + u[i]) != ld_relaxed(parent + v[i])) uf_union(parent, u[i], v[i]);
       }
   }
-  if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
+  // one add per wave: per-thread adds on the one counter serialise
+  local = wave_sum_i64(local);
+  if (lane_id() == 0 && local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
 
 // The triangle tests of edge (u, v), c = its entry's weight: PR3 (a common
@@ -698,7 +700,9 @@ __global__ void k_pr34(int64_t nnz, const int32_t* __restrict__ src, const int32
     pr_flag(ucount, g, last);
     if (ld_relaxed(parent + u) != ld_relaxed(parent + v)) uf_union(parent, u, v);
   }
-  if (local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
+  // one add per wave: per-thread adds on the one counter serialise
+  local = wave_sum_i64(local);
+  if (lane_id() == 0 && local) atomicAdd((unsigned long long*)&ctl->unions_pr, (unsigned long long)local);
 }
 
 // Every test's outcome per entry (u, v), u < v (bits PR1 1, PR2 2, PR3 4,

@@ -901,10 +901,25 @@ __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
       deg += d;
     }
   }
+  // one add per workgroup and counter (adds on one address serialise)
+  __shared__ int64_t part[2][8];
   sum = wave_sum_i64(sum);
   deg = wave_sum_i64(deg);
-  if (lane_id() == 0 && sum) atomicAdd((unsigned long long*)&c->batch_sum, (unsigned long long)sum);
-  if (lane_id() == 0 && deg) atomicAdd((unsigned long long*)&c->batch_deg, (unsigned long long)deg);
+  const int wave = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    part[0][wave] = sum;
+    part[1][wave] = deg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0, d = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      s += part[0][k];
+      d += part[1][k];
+    }
+    if (s) atomicAdd((unsigned long long*)&c->batch_sum, (unsigned long long)s);
+    if (d) atomicAdd((unsigned long long*)&c->batch_deg, (unsigned long long)d);
+  }
 }
 
 // Grid-wide batch [h, t): relax every edge of the batch.
@@ -1100,8 +1115,15 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
     }
   }
   flush_wave_buf(A, wbuf, wcnt);
+  // one add per workgroup (adds on one address serialise)
+  __shared__ int64_t part[4];
   internal = wave_sum_i64(internal);
-  if (lane == 0 && internal) atomicAdd((unsigned long long*)&c->batch_internal, (unsigned long long)internal);
+  if (lane == 0) part[wave] = internal;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t tot = part[0] + part[1] + part[2] + part[3];
+    if (tot) atomicAdd((unsigned long long*)&c->batch_internal, (unsigned long long)tot);
+  }
 }
 
 __global__ void k_sweep_big_finish(SweepArgs A, int32_t t) {
