@@ -1114,7 +1114,22 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
       __syncthreads();  // the slice arrays are reused
     }
   }
-  flush_wave_buf(A, wbuf, wcnt);
+  // the waves' last crossings: one FIFO reservation for the workgroup
+  __shared__ int32_t blk_base;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int32_t tot = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    blk_base = tot ? atomicAdd(&c->cap_tail, tot) : 0;
+  }
+  __syncthreads();
+  {
+    int32_t o = blk_base;
+    for (int k = 0; k < wave; ++k) o += cnt[k];
+    for (int32_t i = lane; i < *wcnt; i += 64) {
+      A.capq[o + i] = wbuf[2 * i];
+      A.capx[o + i] = wbuf[2 * i + 1];
+    }
+  }
   // one add per workgroup (adds on one address serialise)
   __shared__ int64_t part[4];
   internal = wave_sum_i64(internal);
