@@ -303,8 +303,8 @@ def main():
                          "kernel for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; the batched and served forms "
-              "shard graphs across GPUs by design, but no multi-GPU run is part of it.",
+        print("bench.py: measures one GPU only; graphs of the batched and served forms would "
+              "shard across GPUs (independent graphs), but no multi-GPU path is implemented.",
               file=sys.stderr)
         sys.exit(2)
 
