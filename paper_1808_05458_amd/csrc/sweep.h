@@ -257,37 +257,23 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
     }
   }
   // pushes below the cap: one pool reservation per wave, then one list
-  // splice per distinct bucket
-  uint64_t pm = PUSH ? ballot(push) : 0ull;
+  // exchange per pushing lane, all in one instruction: lanes that push to
+  // the same bucket are applied one after another, each receiving the entry
+  // the previous one left, so every bucket's list stays a chain (no loop
+  // over the distinct buckets)
+  const uint64_t pm = PUSH ? ballot(push) : 0ull;
   if (pm) {
     const int leader = __builtin_ctzll(pm);
     int64_t pbase = 0;
     if (lane == leader)
       pbase = (int64_t)atomicAdd((unsigned long long*)q.pool_next, (unsigned long long)popc64(pm));
     pbase = bcast(pbase, leader);
-    const uint64_t pm0 = pm;
-    const int64_t idx = pbase + popc64(pm0 & lanemask_lt());
-    const int32_t b = push ? (int32_t)(nw >> A.shift) : -1;
-    while (pm) {
-      const int32_t b0 = bcast(b, __builtin_ctzll(pm));
-      const bool mine = push && b == b0;
-      const uint64_t grp = ballot(mine);
-      pm &= ~grp;
-      const int hi = 63 - __builtin_clzll(grp);
-      const uint64_t lower = grp & lanemask_lt();
-      const int prev_lane = lower ? 63 - __builtin_clzll(lower) : lane;
-      // the highest lane of the group becomes the head; each lane links to
-      // the next lower lane of its group, the lowest to the old head
-      int32_t old_head = -1;
-      if (lane == hi) {
-        if (idx < A.pool_cap) old_head = atomicExch(&q.head[b0], (int32_t)idx);
-        const uint64_t wbit = 1ull << (b0 & 63);
-        if (!(ld_relaxed(&q.bitmap[b0 >> 6]) & wbit))
-          atomicOr((unsigned long long*)&q.bitmap[b0 >> 6], wbit);
-      }
-      old_head = bcast(old_head, hi);
-      const int64_t prev_idx = pbase + popc64(pm0 & ((1ull << prev_lane) - 1));  // idx of prev_lane
-      if (mine && idx < A.pool_cap) pool_put(A, q, idx, y, lower ? (int32_t)prev_idx : old_head);
+    const int64_t idx = pbase + popc64(pm & lanemask_lt());
+    if (push && idx < A.pool_cap) {
+      const int32_t b = (int32_t)(nw >> A.shift);
+      const int32_t old_head = atomicExch(&q.head[b], (int32_t)idx);
+      atomicOr((unsigned long long*)&q.bitmap[b >> 6], 1ull << (b & 63));
+      pool_put(A, q, idx, y, old_head);
     }
   }
   return internal;
