@@ -422,6 +422,17 @@ static void launch_small_sweep(int threads, int groups, int num_cu, const SmallS
   else launch_small_sweep_t<256>(groups, num_cu, SA, s);
 }
 
+// Workgroups of a kernel (threads per workgroup, no dynamic LDS) resident on
+// the device at once.  Grid-stride kernels whose workgroups all get the same
+// amount of work launch this many: a larger grid leaves a partial second
+// wave of workgroups that starts only after the first has finished.
+static int resident_grid(const void* kernel, int threads, int num_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 4;
+  return per_cu * num_cu;
+}
+
 static bool debug_on() {
   static int v = -1;
   if (v < 0) {
@@ -591,7 +602,8 @@ struct Solver {
             // the contraction)
             hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.inref,
                                ws.bbits);
-            hipLaunchKernelGGL(k_sweep_big_relax, dim3(num_cu * 8), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
+            static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
+            hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
                                tile_row, ws.inref, ws.bbits);
           }
           hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
@@ -663,7 +675,8 @@ struct Solver {
                          ngraphs, n_cur, ws.cvoff, ws.gn, lab, ws.bref);
       hipLaunchKernelGGL(k_block_bits, dim3(grid_for(n_cur, TB, num_cu * 16)), dim3(TB), 0, s, n_cur, lab, gid_cur,
                          ws.bref, ws.inref);
-      hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, num_cu * 8)), dim3(TB), 0, s, nnz,
+      static const int emit_grid = resident_grid((const void*)&k_emit, TB, num_cu);
+      hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, emit_grid)), dim3(TB), 0, s, nnz,
                          src, col, w, lab, bb, ws.inref, ws.keys, ws.vals, ws.ctl);
     }
     int rc = read_ctl();
@@ -935,7 +948,8 @@ struct Solver {
         // chunk first rows in the sort keys' buffer (free until the first contraction)
         int32_t* first = (int32_t*)ws.keys;
         hipLaunchKernelGGL(k_chunk_rows, grid(N), dim3(TB), 0, s, N, P.rp, first);
-        hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + INGEST_CH - 1) / INGEST_CH * TB, TB, num_cu * 8)), dim3(TB),
+        static const int ingest_grid = resident_grid((const void*)&k_ingest, TB, num_cu);
+        hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + INGEST_CH - 1) / INGEST_CH * TB, TB, ingest_grid)), dim3(TB),
                            0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, first, ws.src, ws.cdeg, ws.gmaxw, ws.ctl);
       }
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
