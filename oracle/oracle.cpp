@@ -280,7 +280,7 @@ WGraph from_input(const Csr& in) {  // G without self-loops
 
 // eps_ppm < 0: the exact algorithm (O3).  eps_ppm >= 0: Matula's
 // approximation with eps = eps_ppm / 10^6 < 1/2: a round contracts the edges
-// with q(e) >= k = min(lambda-hat, max(1, floor((1/2 - eps) * delta))), delta
+// with q(e) >= k = min(lambda-hat, max(1, ceil((1/2 - eps) * delta))), delta
 // the current graph's minimum degree; lambda-hat stays the smallest real cut
 // seen (degrees, prefix cuts), so the answer is a cut of G.
 int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* rounds_out,
@@ -323,7 +323,9 @@ int noi(const Csr& in, uint64_t seed, i64* lambda, uint8_t* side_out, int32_t* r
     if (eps_ppm >= 0) {
       i64 delta = g.deg[0];
       for (int32_t v = 1; v < g.n; ++v) delta = std::min(delta, g.deg[v]);
-      const i64 k = delta * (1000000 - 2 * eps_ppm) / 2000000;
+      // q(e) >= (1/2 - eps) delta for an integer q(e) means q(e) >= the
+      // ceiling of that product
+      const i64 k = (delta * (1000000 - 2 * eps_ppm) + 1999999) / 2000000;
       lsnap = std::min(lhat, std::max<i64>(1, k));
     }
     std::vector<i64> r(g.n, 0);

@@ -304,9 +304,13 @@ def test_viecut_hand_examples():
     spec = json.load(open(os.path.join(GOLDEN, "lp_examples.json")))
     for ex in spec["bounds"]:
         g = _fixture_graph(ex)
-        lam, side, levels = oracle.viecut(g)
+        lam, side, levels = oracle.viecut(g, stop_n=ex.get("stop_n", 2))
         assert (lam, levels) == (ex["bound"], ex["levels"]), ex["name"]
         assert oracle.cut_value(g, side) == lam and 0 < side.sum() < g.n, ex["name"]
+        if "side" in ex:
+            s = sorted(np.flatnonzero(side).tolist())
+            other = sorted(set(range(g.n)) - set(ex["side"]))
+            assert s in (ex["side"], other), ex["name"]
 
 
 @pytest.mark.parametrize("a", [4, 5, 6, 8, 12])
@@ -364,9 +368,11 @@ def test_viecut_on_workload_shapes():
 
 # ------------------------------------------ Matula's (2+eps)-approximation
 def matula_bound(lam, ppm):
-    # a round whose bound k = floor((1/2 - eps) delta) is at most lambda has
-    # delta < (lambda + 1) / (1/2 - eps), and delta is a cut the answer counts
-    return (lam + 1) * 2_000_000 // (1_000_000 - 2 * ppm)
+    # the paper's guarantee: a round contracts the edges with q(e) >= k, k at
+    # least (1/2 - eps) delta; a minimum-cut edge has q(e) <= lambda, so if
+    # one is contracted then delta <= lambda / (1/2 - eps), and delta is a
+    # cut the answer counts; if none is, the minimum cut survives to the end
+    return lam * 2_000_000 // (1_000_000 - 2 * ppm)
 
 
 @pytest.mark.parametrize("ppm", [1, 100_000, 250_000, 490_000])
@@ -381,6 +387,20 @@ def test_matula_is_a_cut_within_its_bound(ppm):
         check_side(g, a, side)
         assert lam <= a <= matula_bound(lam, ppm), (trial, lam, a)
         assert a <= min_degree(g)
+
+
+def test_matula_fixtures_where_a_floor_threshold_breaks_the_bound():
+    # graphs on which contracting at q(e) >= floor((1/2 - eps) delta) answered
+    # above lambda / (1/2 - eps); the paper's threshold keeps the bound
+    fx = json.load(open(os.path.join(GOLDEN, "matula_examples.json")))["examples"]
+    assert len(fx) >= 3
+    for ex in fx:
+        g = gg.from_edges(ex["n"], ex["edges"], ex["weights"])
+        lam = oracle.bruteforce(g)[0]
+        assert ex["floor_answer"] > matula_bound(lam, ex["ppm"])
+        a, side, _ = oracle.matula(g, ex["ppm"], ex["seed"])
+        check_side(g, a, side)
+        assert lam <= a <= matula_bound(lam, ex["ppm"]), (ex["n"], lam, a)
 
 
 def _hypercube(d):
