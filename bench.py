@@ -2,14 +2,17 @@
 
 A step is one complete exact solve (every round of the contraction loop:
 Padberg-Rinaldi tests, CAPFOREST scans, union-find, contraction, bound
-updates, side) of the workload graph, already resident in HBM.  The
-workload is a Chung-Lu power-law graph (n = 2^22, exponent 2.5, average
-degree 32, unit weights) reduced to its 8-core and largest component.
+updates, side) of the workload graph, already resident in HBM.  The default
+workload is the largest single-graph one: an R-MAT graph (scale 24, 2^28
+edge draws, parameters 0.57/0.19/0.19/0.05, multiplicity weights) reduced to
+its 10-core and largest component.
 
 Prints one JSON line: edges/s (undirected edges of the solved graph divided
 by the solve time), the dominant kernel's roofline figures (event-timed on
-the launch stream during the timed steps) and the CPU oracle's rate on a
-bounded sample of the same workload family.
+the launch stream during the timed steps), the CPU oracle's rate on a
+bounded sample of the same recipe, and the other workloads (the planted
+4096-vertex graph, the Chung-Lu 2^22 8-core, the 4096-graph batch, the
+served stream) as extra keys.
 """
 import argparse
 import json
@@ -29,18 +32,45 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline():
-    """Oracle (sequential NOI, one thread) on a smaller graph of the same
-    recipe: Chung-Lu n = 2^19, exponent 2.5, average degree 32, 8-core, LCC."""
+def source_digest():
+    """Digest of the kernel and library sources: a counter summary taken on
+    other sources no longer describes the kernels."""
+    import hashlib
+    h = hashlib.blake2b(digest_size=8)
+    d = os.path.join(ROOT, "paper_1808_05458_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "mincut.h"), "rb").read())
+    return h.hexdigest()
+
+
+def golden():
+    return json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))
+
+
+def cpu_baseline(workload):
+    """Oracle (sequential NOI, one thread) fully solving a smaller graph of
+    the headline's recipe; the stored full-size oracle time is printed beside
+    it (measured once when the expected values were written)."""
     import graphgen as gg
     import oracle
-    g = gg.chung_lu_4m_8core(19)
+    if workload == "rmat":
+        g, full_key, recipe = gg.rmat_24_10core(20, 24), "rmat_24_10core", "rmat scale 20 (2^24 draws) 10-core LCC"
+    else:
+        g, full_key, recipe = gg.chung_lu_4m_8core(19), "chung_lu_4m_8core", "chung_lu n=2^19 8-core LCC"
     t0 = time.perf_counter()
     lam, side, rounds = oracle.noi(g, 1)
     dt = time.perf_counter() - t0
+    full = golden().get(full_key, {})
     return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential NOI (O3) full solve of chung_lu n=2^19 8-core LCC "
-                      f"(n={g.n}, m={g.m}, lambda={lam}, {rounds} rounds) in {dt:.2f} s"}
+            "sample": f"sequential NOI (O3) full solve of {recipe} (n={g.n}, m={g.m}, "
+                      f"lambda={lam}, {rounds} rounds) in {dt:.2f} s",
+            "full_size": {"graph": full_key, "m": full.get("m"), "oracle_seconds": full.get("oracle_seconds"),
+                          "edges_per_s": (full["m"] / full["oracle_seconds"]) if full else None,
+                          "note": "stored when the expected values were written (one thread, build host), "
+                                  "not re-run here"}}
 
 
 def batched_form(steps, warmup, loop=True):
@@ -159,32 +189,6 @@ def ablation():
     return out
 
 
-def rmat_form(steps):
-    """R-MAT scale 24 (2^28 draws, (0.57, 0.19, 0.19, 0.05), multiplicity
-    weights), 10-core, largest component, resident in HBM: exact solves."""
-    import torch
-    import graphgen as gg
-    import paper_1808_05458_amd as mc
-    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json"))).get("rmat_24_10core")
-    t0 = time.time()
-    g = gg.rmat_24_10core()
-    log(f"rmat: n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
-    rp, col, w = mc.to_device(g, "cuda:0")
-    mc.mincut(rp, col, w)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        lam, side, st = mc.mincut(rp, col, w)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    s = side.cpu().numpy()[: g.n].astype(bool)
-    cut = int(g.w[s[g.src()] != s[g.col]].sum()) // 2
-    out = {"n": g.n, "m": g.m, "ms": round(dt * 1e3, 3), "edges_per_s": g.m / dt, "rounds": st["rounds"],
-           "lambda": lam, "oracle_lambda": gold["lambda"] if gold else None, "side_cut_weight": cut}
-    log(f"rmat: {out}")
-    return out
-
-
 def served_form(requests, pool_size, lanes, seed=5):
     """Poisson arrivals of min-cut requests (Chung-Lu, exponent 2.5, average
     degree 16, n log-uniform in [2^10, 2^20], weights in [1, 50], largest
@@ -278,18 +282,134 @@ def served_form(requests, pool_size, lanes, seed=5):
     return out
 
 
+def solve_single(g, steps, warmup, gold_lambda, label):
+    """Time `steps` exact solves of one resident graph, with the kernel
+    classes event-timed on the solve stream."""
+    import torch
+    import paper_1808_05458_amd as mc
+    rp, col, w = mc.to_device(g, "cuda:0")
+    for i in range(warmup):
+        lam, side, st = mc.mincut(rp, col, w)
+        log(f"{label} warmup {i}: lambda={lam} rounds={st['rounds']} {st['ms']:.1f} ms n_round={st['n_round']}")
+    topts = mc.options(timing=1)
+    mc.timing_reset()
+    lams = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        lam, side, st = mc.mincut(rp, col, w, opts=topts)
+        lams.append(lam)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    classes = mc.timing()
+    log(f"{label} kernel classes: " + ", ".join(f"{c['name']}={c['ms'] / steps:.2f}ms"
+                                               for c in sorted(classes, key=lambda c: -c["ms"])))
+    s = side.cpu().numpy()[: g.n].astype(bool)
+    cut = int(g.w[s[g.src()] != s[g.col]].sum()) // 2
+    verified = {"lambda": lams[0], "all_steps_equal": len(set(lams)) == 1, "oracle_lambda": gold_lambda,
+                "equals_oracle": gold_lambda is not None and all(x == gold_lambda for x in lams),
+                "side_cut_weight": cut, "side_size": int(s.sum())}
+    log(f"{label} verify: {verified}")
+    sweep = {"big_batches": st["sweep_big_batches"], "singles": st["sweep_singles"],
+             "batches": st["sweep_batches"], "crossings": st["sweep_cross"]}
+    del rp, col, w
+    return {"ms_per_step": dt * 1000.0 / steps, "value": g.m * steps / dt, "rounds": st["rounds"],
+            "n_round": st["n_round"], "classes": classes, "verified": verified, "sweep_phases": sweep}
+
+
+def roofline_of(classes, steps, traffic_file):
+    """The dominant kernel (most device time per step) against HBM peak:
+    algorithmic bytes per launch over its average launch time, plus the
+    counter-measured bytes per launch when a summary taken on these sources
+    exists."""
+    def rate(c):
+        per_launch_s = c["ms"] / 1000.0 / c["launches"]
+        per_launch_bytes = c["algo_bytes"] / c["launches"]
+        return per_launch_bytes / per_launch_s / 1e9, per_launch_bytes
+
+    measured, digest_ok = {}, False
+    if os.path.exists(traffic_file):
+        for line in open(traffic_file):
+            f = line.split()
+            if len(f) == 2 and f[0] == "source_digest":
+                digest_ok = f[1] == source_digest()
+            if len(f) == 6 and f[0] == "traffic":
+                measured[f[1]] = int(f[5])
+    if not digest_ok:
+        measured = {}
+    dom = max(classes, key=lambda c: c["ms"])
+    achieved, dom_bytes = rate(dom)
+
+    def entry(c):
+        e = {"ms_per_step": round(c["ms"] / steps, 3), "launches_per_step": c["launches"] / steps,
+             "algo_GBps": round(rate(c)[0], 1), "frac": round(rate(c)[0] / HBM_PEAK_GBS, 5)}
+        if c["name"] in measured:
+            e["counter_bytes_per_launch"] = measured[c["name"]]
+            e["counter_GBps"] = round(measured[c["name"]] / (c["ms"] / 1000.0 / c["launches"]) / 1e9, 1)
+        return e
+    return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured.get(dom["name"]),
+            "kernel": dom["name"], "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
+            "launches_per_step": dom["launches"] / steps, "algo_bytes_per_launch": dom_bytes,
+            "traffic_source": os.path.relpath(traffic_file, ROOT) if measured else None,
+            "kernels": {c["name"]: entry(c) for c in sorted(classes, key=lambda c: -c["ms"])[:10]}}
+
+
+def planted_form(steps):
+    """The planted-cluster graph (n = 4096, 8 clusters of 512): edges/s and
+    rounds (its CSR fits in L2; latency-bound, so no HBM fraction)."""
+    import graphgen as gg
+    g = gg.planted_4096()
+    r = solve_single(g, steps, 1, golden()["planted_4096"]["lambda"], "planted")
+    return {"n": g.n, "m": g.m, "ms": round(r["ms_per_step"], 3), "edges_per_s": r["value"],
+            "rounds": r["rounds"], "verified": r["verified"]}
+
+
+def chung_lu_form(steps, approx=True):
+    """The Chung-Lu 2^22 8-core: exact solves, its kernel classes, and
+    Matula's (2+eps)-approximation on the same resident graph."""
+    import torch
+    import graphgen as gg
+    import paper_1808_05458_amd as mc
+    g = gg.chung_lu_4m_8core(22)
+    r = solve_single(g, steps, 1, golden()["chung_lu_4m_8core"]["lambda"], "chung_lu")
+    out = {"n": g.n, "m": g.m, "ms": round(r["ms_per_step"], 3), "edges_per_s": r["value"],
+           "rounds": r["rounds"], "verified": r["verified"], "sweep_phases": r["sweep_phases"],
+           "roofline": roofline_of(r["classes"], steps,
+                                   os.path.join(ROOT, "profiles", "hbm_traffic_chung_lu_2^22_8core.txt"))}
+    if approx:
+        rp, col, w = mc.to_device(g, "cuda:0")
+        out["matula_approx"] = []
+        for ppm in (100_000, 250_000):
+            mc.mincut(rp, col, w, approx_ppm=ppm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(3):
+                lam_a, side_a, st_a = mc.mincut(rp, col, w, approx_ppm=ppm)
+            torch.cuda.synchronize()
+            dt_a = (time.perf_counter() - t0) / 3
+            s_a = side_a.cpu().numpy()[: g.n].astype(bool)
+            cut_a = int(g.w[s_a[g.src()] != s_a[g.col]].sum()) // 2
+            out["matula_approx"].append({"eps": ppm / 1e6, "ms": round(dt_a * 1e3, 2), "edges_per_s": g.m / dt_a,
+                                         "lambda": lam_a, "side_cut_weight": cut_a, "rounds": st_a["rounds"],
+                                         "exact_lambda": r["verified"]["lambda"]})
+            log(f"approx eps={ppm / 1e6}: {out['matula_approx'][-1]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n-log2", type=int, default=22)
+    ap.add_argument("--workload", choices=["rmat", "chung_lu", "batched", "served"], default="rmat")
+    ap.add_argument("--only", action="store_true",
+                    help="the headline workload alone (no other workloads, no CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--workload", choices=["chung_lu", "batched", "served"], default="chung_lu")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--no-rmat", action="store_true")
+    ap.add_argument("--no-planted", action="store_true")
+    ap.add_argument("--no-chung-lu", action="store_true")
     ap.add_argument("--no-approx", action="store_true", help="skip the (2+eps)-approximation runs")
     ap.add_argument("--ablation", action="store_true",
                     help="print scan-policy ablations (rounds against time) instead of the bench line")
@@ -310,7 +430,6 @@ def main():
 
     import torch
     import graphgen as gg
-    import paper_1808_05458_amd as mc
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -343,126 +462,43 @@ def main():
                "data": "synthetic", "config": {"workload": "batch of 4096 planted-cluster graphs", **b}}
         print(json.dumps(out), flush=True)
         return
+
     t0 = time.time()
-    g = gg.chung_lu_4m_8core(args.n_log2)
+    if args.workload == "rmat":
+        g = gg.rmat_24_10core()
+        gold_key, traffic_name = "rmat_24_10core", "hbm_traffic_rmat_24_10core.txt"
+        workload = ("rmat scale 24, 2^28 draws (0.57, 0.19, 0.19, 0.05), multiplicity weights, "
+                    "10-core, largest component")
+    else:
+        g = gg.chung_lu_4m_8core(22)
+        gold_key, traffic_name = "chung_lu_4m_8core", "hbm_traffic_chung_lu_2^22_8core.txt"
+        workload = "chung_lu n=2^22 exp2.5 avgdeg32 unit-weight 8-core LCC"
     log(f"generated {g.name}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
-    rp, col, w = mc.to_device(g, "cuda:0")
-    stream = torch.cuda.current_stream()
-
-    opts = mc.options()
-    for i in range(args.warmup):
-        lam, side, st = mc.mincut(rp, col, w, opts=opts)
-        log(f"warmup {i}: lambda={lam} rounds={st['rounds']} {st['ms']:.1f} ms "
-            f"n_round={st['n_round']}")
-    torch.cuda.synchronize()
-
-    topts = mc.options(timing=1)
-    mc.timing_reset()
-    lams = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        lam, side, st = mc.mincut(rp, col, w, opts=topts)
-        lams.append(lam)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt * 1000.0 / args.steps
-    value = g.m * args.steps / dt
-    classes = mc.timing()
-    log("kernel classes: " + ", ".join(f"{c['name']}={c['ms'] / args.steps:.2f}ms"
-                                      for c in sorted(classes, key=lambda c: -c["ms"])))
-
-    def rate(c):
-        per_launch_s = c["ms"] / 1000.0 / c["launches"]
-        per_launch_bytes = c["algo_bytes"] / c["launches"]
-        return per_launch_bytes / per_launch_s / 1e9, per_launch_bytes
-
-    dom = max(classes, key=lambda c: c["ms"])
-    achieved, dom_bytes = rate(dom)
-    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of
-    # this workload (scaled by the same counters on a plain copy), when the
-    # summary is present; it is only valid for the build it was taken on
-    measured = {}  # class -> counter bytes per launch of its main kernel
-    tpath = os.path.join(ROOT, "profiles", f"hbm_traffic_chung_lu_2^{args.n_log2}_8core.txt")
-    if os.path.exists(tpath):
-        for line in open(tpath):
-            f = line.split()
-            if len(f) == 7 and f[0] == "traffic":
-                measured[f[1]] = int(f[6])
-    traffic = measured.get(dom["name"])
-
-    def kernel_entry(c):
-        e = {"ms_per_step": round(c["ms"] / args.steps, 3), "GBps": round(rate(c)[0], 1),
-             "frac": round(rate(c)[0] / HBM_PEAK_GBS, 4)}
-        if c["name"] in measured:
-            # counter bytes (not algorithmic) over this run's event time
-            e["traffic_GBps"] = round(measured[c["name"]] / (c["ms"] / 1000.0 / c["launches"]) / 1e9, 1)
-        return e
-    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                "kernel": dom["name"], "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
-                "launches_per_step": dom["launches"] / args.steps,
-                "algo_bytes_per_launch": dom_bytes,
-                "kernels": {c["name"]: kernel_entry(c) for c in sorted(classes, key=lambda c: -c["ms"])[:8]}}
-
-    verified = None
-    if not args.no_verify:
-        gold_path = os.path.join(ROOT, "tests", "golden", "workloads.json")
-        gold = json.load(open(gold_path)).get("chung_lu_4m_8core") if args.n_log2 == 22 else None
-        s = side.cpu().numpy()[: g.n].astype(bool)
-        src = g.src()
-        cut = int(g.w[s[src] != s[g.col]].sum()) // 2
-        verified = {"lambda": lams[0], "all_steps_equal": len(set(lams)) == 1,
-                    "side_cut_weight": cut, "side_size": int(s.sum()),
-                    "oracle_lambda": gold["lambda"] if gold else None}
-        log(f"verify: {verified}")
-
-    # Matula's (2+eps)-approximation on the same resident graph (the same
-    # kernels with a lower contraction bound); its answer is a real cut
-    approx = None
-    if not args.no_approx:
-        approx = []
-        for ppm in (100_000, 250_000):
-            mc.mincut(rp, col, w, approx_ppm=ppm)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for i in range(3):
-                lam_a, side_a, st_a = mc.mincut(rp, col, w, approx_ppm=ppm)
-            torch.cuda.synchronize()
-            dt_a = (time.perf_counter() - t0) / 3
-            s_a = side_a.cpu().numpy()[: g.n].astype(bool)
-            src = g.src()
-            cut_a = int(g.w[s_a[src] != s_a[g.col]].sum()) // 2
-            approx.append({"eps": ppm / 1e6, "ms": round(dt_a * 1e3, 2), "edges_per_s": g.m / dt_a,
-                           "lambda": lam_a, "side_cut_weight": cut_a, "rounds": st_a["rounds"],
-                           "exact_lambda": lams[0]})
-            log(f"approx eps={ppm / 1e6}: {approx[-1]}")
-
-    batched = None
-    if not args.no_batched:
-        batched = batched_form(max(1, min(args.steps, 3)), 1)
-    served = None
-    if not args.no_served:
-        served = served_form(args.requests, args.pool, args.lanes)
-    rmat = None
-    if not args.no_rmat:
-        rmat = rmat_form(max(1, min(args.steps, 3)))
-
+    r = solve_single(g, args.steps, args.warmup, golden().get(gold_key, {}).get("lambda"), args.workload)
+    roofline = roofline_of(r["classes"], args.steps, os.path.join(ROOT, "profiles", traffic_name))
+    n, m = g.n, g.m
+    del g
+    extra = {}
+    if not args.only:
+        if not args.no_planted:
+            extra["planted_4096"] = planted_form(args.steps)
+        if not args.no_chung_lu and args.workload != "chung_lu":
+            extra["chung_lu_2^22_8core"] = chung_lu_form(max(1, min(args.steps, 5)), approx=not args.no_approx)
+        if not args.no_batched:
+            extra["batched"] = batched_form(max(1, min(args.steps, 3)), 1)
+        if not args.no_served:
+            extra["served"] = served_form(args.requests, args.pool, args.lanes)
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline()
+    if not args.only and not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload)
         log(f"cpu baseline: {cpu}")
-
     out = {"metric": "exact min-cut edges/s (m / solve time) at 1 GPU",
-           "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "int64",
-           "data": "synthetic",
-           "config": {"workload": f"chung_lu n=2^{args.n_log2} exp2.5 avgdeg32 unit-weight "
-                                  f"8-core LCC", "n": g.n, "m": g.m,
-                      "rounds": st["rounds"], "verified": verified},
-           "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "served": served,
-           "rmat_scale24": rmat, "matula_approx": approx}
+           "value": r["value"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": workload, "n": n, "m": m, "rounds": r["rounds"], "n_round": r["n_round"],
+                      "verified": r["verified"], "sweep_phases": r["sweep_phases"]},
+           "roofline": roofline, "cpu_baseline": cpu, **extra}
     print(json.dumps(out), flush=True)
 
 

@@ -170,6 +170,24 @@ def _u01(seed: int, i: int) -> float:
     return (z >> 11) * 2.0 ** -53
 
 
+def _cached(name: str, make) -> Graph:
+    """make(), or its copy saved under $MC_GRAPH_CACHE when that is set
+    (plain .npy arrays; several runs of one command reuse a large graph)."""
+    d = os.environ.get("MC_GRAPH_CACHE")
+    if not d:
+        return make()
+    paths = [os.path.join(d, f"{name}.{k}.npy") for k in ("row_ptr", "col", "w")]
+    if all(os.path.exists(q) for q in paths):
+        rp, col, w = (np.load(q, allow_pickle=False) for q in paths)
+        return Graph(len(rp) - 1, rp, col, w, name)
+    g = make()
+    os.makedirs(d, exist_ok=True)
+    for q, arr in zip(paths, (g.row_ptr, g.col, g.w)):
+        np.save(q + ".tmp.npy", arr, allow_pickle=False)
+        os.replace(q + ".tmp.npy", q)
+    return g
+
+
 def planted_4096() -> Graph:
     """8 clusters of 512, intra-cluster G(512, 0.04), 64 inter-cluster edges,
     weights uniform in [1, 10], seed 1."""
@@ -179,15 +197,61 @@ def planted_4096() -> Graph:
 def chung_lu_4m_8core(n_log2: int = 22) -> Graph:
     """Chung-Lu, n = 2^22, exponent 2.5, average degree 32, unit weights,
     8-core, largest component, seed 2."""
-    return chung_lu(2, 1 << n_log2, 2.5, 32.0, 1, 1, kcore=8, lcc=True,
-                    name=f"chung_lu_2^{n_log2}_8core")
+    name = f"chung_lu_2^{n_log2}_8core"
+    return _cached(name, lambda: chung_lu(2, 1 << n_log2, 2.5, 32.0, 1, 1, kcore=8, lcc=True, name=name))
 
 
 def rmat_24_10core(scale: int = 24, draws_log2: int = 28) -> Graph:
     """R-MAT scale 24, 2^28 draws, (0.57, 0.19, 0.19, 0.05), multiplicity
     weights, 10-core, largest component, seed 3."""
-    return rmat(3, scale, 1 << draws_log2, 0.57, 0.19, 0.19, kcore=10, lcc=True,
-                name=f"rmat_{scale}_10core")
+    name = f"rmat_{scale}_10core"
+    return _cached(name, lambda: rmat(3, scale, 1 << draws_log2, 0.57, 0.19, 0.19, kcore=10, lcc=True,
+                                      name=name))
+
+
+def _mix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser, elementwise on uint64."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def bridged_8cores(n_log2: int = 21, k: int = 3) -> Graph:
+    """Two Chung-Lu graphs (n = 2^n_log2 each, exponent 2.5, average degree
+    32, unit weights, seeds 6 and 7), each reduced to its 8-core and largest
+    component, joined by k unit edges whose 2k endpoints are distinct, then
+    every vertex id permuted (seed 8).  For k below 8 the minimum cut is the
+    k bridges and lies below the minimum degree 8 (unless a half has a
+    smaller cut of its own: the oracle decides)."""
+    name = f"bridged_8cores_2^{n_log2}_k{k}"
+
+    def make():
+        a = chung_lu(6, 1 << n_log2, 2.5, 32.0, 1, 1, kcore=8, lcc=True)
+        b = chung_lu(7, 1 << n_log2, 2.5, 32.0, 1, 1, kcore=8, lcc=True)
+        n = a.n + b.n
+        # bridge endpoints: the first k distinct picks on each side
+        ends = []
+        for side, h, off in ((0, a, 0), (1, b, a.n)):
+            picks, i = [], 0
+            while len(picks) < k:
+                v = int(_mix64(np.array([8_000_000 + 1000 * side + i], np.uint64))[0] % np.uint64(h.n))
+                if v not in picks:
+                    picks.append(v)
+                i += 1
+            ends.append([off + v for v in picks])
+        perm = np.argsort(_mix64(np.arange(n, dtype=np.uint64) + np.uint64(8 << 40)), kind="stable")
+        src = np.concatenate([a.src(), b.src() + a.n, ends[0], ends[1]]).astype(np.int64)
+        dst = np.concatenate([a.col, b.col + a.n, ends[1], ends[0]]).astype(np.int64)
+        key = np.sort((perm[src] << 32) | perm[dst])
+        del src, dst
+        s2 = (key >> 32).astype(np.int32)
+        col = (key & 0xFFFFFFFF).astype(np.int32)
+        rp = np.zeros(n + 1, np.int64)
+        rp[1:] = np.cumsum(np.bincount(s2, minlength=n))
+        return Graph(n, rp, col, np.ones(len(col), np.int32), name)
+    return _cached(name, make)
 
 
 def batch_graph_params(g: int):

@@ -21,10 +21,14 @@
  *    2 * (2^31 - 1), so every cut fits in 31 bits (MC_EOVERFLOW otherwise).
  *  - At most 2^30 - 1 vertices in total and nnz < 2^32 per call.
  *  - Inputs are never modified.  The caller owns all input and output
- *    buffers; the library owns its workspace (allocated on first use, grown
- *    when needed, kept per device until mc_release()).
+ *    buffers.  The library owns its workspace: one per (device, stream),
+ *    allocated on first use, grown when needed, kept until mc_release();
+ *    or the caller lends one (mc_options.workspace).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls return
- *    after the stream work has finished.  Calls are serialised internally.
+ *    after the stream work has finished.  Calls on different streams are
+ *    independent and may run at the same time from different host threads
+ *    (each uses its stream's workspace); calls on the same stream take
+ *    turns.
  *  - Every function returns MC_OK (0) or a negative MC_E* code; nothing
  *    throws across the ABI.  On error the outputs are unspecified.
  */
@@ -124,11 +128,43 @@ typedef struct mc_options {
                               10^6 (the paper names it beside NOI: the
                               contraction bound of a round is (1/2 - eps)
                               times the graph's minimum degree, capped by the
-                              best cut found).  lambda is then a real cut
-                              with lambda(G) <= lambda < (lambda(G) + 1) /
-                              (1/2 - eps), and the side realises it.
+                              best cut found; an edge contracts when its
+                              q(e) reaches that product, i.e. its ceiling).
+                              lambda is then a real cut with lambda(G) <=
+                              lambda <= lambda(G) / (1/2 - eps), and the side
+                              realises it.
                               Outside 0 .. 499999: MC_EINVAL. */
-  int32_t reserved[1];
+  int32_t validate;        /* 1: also check that every graph is symmetric
+                              (for each pair u != v the weights of u's
+                              entries to v add up to those of v's entries
+                              to u); MC_EINVAL if not.  Costs one sort of the
+                              entries.  0 (default): asymmetric input gives
+                              an undefined result. */
+  void* workspace;         /* NULL (default): the library's workspace for
+                              the call's (device, stream), allocated on
+                              first use and grown when needed.  Otherwise a
+                              DEVICE buffer of workspace_bytes bytes that the
+                              call uses instead (no device allocation);
+                              it must hold mc_workspace_bytes(n, nnz, G),
+                              plus mc_viecut_workspace_bytes(n, nnz, G)
+                              when the clustering bound runs (use_viecut or
+                              mc_viecut_bound), else MC_EINVAL.  Its
+                              contents need no initialisation and are
+                              garbage afterwards; two calls in flight must
+                              not share one. */
+  uint64_t workspace_bytes;
+  int32_t sweep_tail;      /* the end of a full-graph capped sweep: 0
+                              (default): once its last grid-wide batch has
+                              left at most a quarter of the graph (and at
+                              most 2^18 vertices) and at least 256 vertices
+                              below the cap, the rest is scanned by many
+                              concurrent processes that start from the
+                              visited set (Algorithm 1's parallel CAPFOREST
+                              with blacklisting); > 0: the same with this
+                              lower limit; -1: never (one vertex at a time
+                              to the end).  Changes which pairs a round
+                              unites, never lambda. */
+  int32_t reserved[3];
 } mc_options;
 
 typedef struct mc_stats {
@@ -144,6 +180,16 @@ typedef struct mc_stats {
   double ms;               /* wall time of the call */
   int32_t n_round[64];     /* vertices at the start of each round (first 64) */
   int64_t nnz_round[64];   /* entries at the start of each round */
+  /* Filled only with opt->timing = 1.  Full-graph capped sweeps (graphs
+   * above whole_max), summed over graphs and rounds, per phase: phase k
+   * holds the steps of the sequential sweep kernel after k grid-wide
+   * batches of its graph (the last phase also every later one). */
+  int32_t sweep_phases;      /* phases in use (1 + most grid-wide batches, at most 8) */
+  int32_t sweep_big_batches; /* grid-wide batches */
+  int32_t sweep_singles[8];  /* single pops below the cap */
+  int32_t sweep_batches[8];  /* batches of capped vertices run by the sweep kernel */
+  int32_t sweep_cross[8];    /* crossings (each unites two vertices) made by those steps */
+  int64_t sweep_tail_pops;   /* vertices visited by the concurrent tail scans */
 } mc_stats;
 
 /* Fill `opt` with the defaults. */
@@ -257,7 +303,8 @@ size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs
  * (use_viecut or mc_viecut_bound): two level graphs and their labels. */
 size_t mc_viecut_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs);
 
-/* Free the cached workspace of the current device. */
+/* Free the cached workspaces of every stream of the current device
+ * (waiting for a call in progress on one to finish). */
 void mc_release(void);
 
 const char* mc_strerror(int code);
@@ -328,7 +375,8 @@ int mc_server_submit(mc_server* srv, const mc_request* req, uint64_t* ticket);
 
 /* Block until the request is done; lambda (HOST), side (HOST uint8[n] or
  * NULL; side[0] = 0) and lat (or NULL) receive its result.  The ticket is
- * released.  MC_ESTATE for an unknown ticket; otherwise the solve's code. */
+ * released.  MC_ESTATE for an unknown ticket or one another thread is
+ * already waiting on; otherwise the solve's code. */
 int mc_server_wait(mc_server* srv, uint64_t ticket, int64_t* lambda, uint8_t* side, mc_latency* lat);
 
 /* Finish every queued request, stop the lanes and free the server.

@@ -58,8 +58,9 @@ class Options(ctypes.Structure):
                 ("viecut_levels", ctypes.c_int32), ("sweep_threads", ctypes.c_int32),
                 ("sweep_groups", ctypes.c_int32), ("sort_tile", ctypes.c_int32),
                 ("pr_triangle_deg", ctypes.c_int32), ("viecut_exact", ctypes.c_int32),
-                ("approx_ppm", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("approx_ppm", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("sweep_tail", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -76,7 +77,10 @@ class Stats(ctypes.Structure):
                 ("scans", ctypes.c_int64), ("pops", ctypes.c_int64),
                 ("overflows", ctypes.c_int64), ("lambda_initial", ctypes.c_int64),
                 ("lambda_viecut", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("n_round", ctypes.c_int32 * 64), ("nnz_round", ctypes.c_int64 * 64)]
+                ("n_round", ctypes.c_int32 * 64), ("nnz_round", ctypes.c_int64 * 64),
+                ("sweep_phases", ctypes.c_int32), ("sweep_big_batches", ctypes.c_int32),
+                ("sweep_singles", ctypes.c_int32 * 8), ("sweep_batches", ctypes.c_int32 * 8),
+                ("sweep_cross", ctypes.c_int32 * 8), ("sweep_tail_pops", ctypes.c_int64)]
 
     def as_dict(self):
         r = min(self.rounds, 64)
@@ -85,7 +89,12 @@ class Stats(ctypes.Structure):
                 "scans": self.scans, "pops": self.pops, "overflows": self.overflows,
                 "lambda_initial": self.lambda_initial, "lambda_viecut": self.lambda_viecut,
                 "ms": self.ms, "n_round": list(self.n_round[:r]),
-                "nnz_round": list(self.nnz_round[:r])}
+                "nnz_round": list(self.nnz_round[:r]),
+                "sweep_big_batches": self.sweep_big_batches,
+                "sweep_singles": list(self.sweep_singles[:self.sweep_phases]),
+                "sweep_batches": list(self.sweep_batches[:self.sweep_phases]),
+                "sweep_cross": list(self.sweep_cross[:self.sweep_phases]),
+                "sweep_tail_pops": self.sweep_tail_pops}
 
 
 class Graph(ctypes.Structure):
@@ -458,6 +467,10 @@ def debug_contract(row_ptr, col, w, labels, n_new, *, stream=None):
 
 def workspace_bytes(n_total: int, nnz_total: int, num_graphs: int = 1) -> int:
     return int(_load().mc_workspace_bytes(n_total, nnz_total, num_graphs))
+
+
+def viecut_workspace_bytes(n_total: int, nnz_total: int, num_graphs: int = 1) -> int:
+    return int(_load().mc_viecut_workspace_bytes(n_total, nnz_total, num_graphs))
 
 
 def release():

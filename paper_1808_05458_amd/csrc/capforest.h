@@ -51,6 +51,8 @@ struct Ctl {
   int32_t lp_items;      // workgroup items of label propagation (long rows)
   int32_t n_pr;          // graphs where a Padberg-Rinaldi test can pass in the first contraction round
   int64_t lam_floor;     // the smallest bound of a tested graph (Padberg-Rinaldi prefilter)
+  int32_t asym;          // symmetry check: some vertex pair's two directions differ
+  int32_t pad_;
 };
 
 struct ScanArgs {

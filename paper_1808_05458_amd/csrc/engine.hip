@@ -14,8 +14,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mincut.h"
@@ -33,7 +36,7 @@ namespace mc {
   } while (0)
 
 inline hipError_t& last_hip_error() {
-  static hipError_t e = hipSuccess;
+  static thread_local hipError_t e = hipSuccess;
   return e;
 }
 
@@ -142,18 +145,17 @@ struct Buf {
 struct Workspace {
   int device = -1;
   int64_t capN = 0, capE = 0, capG = 0;
-  std::vector<void*> allocs;
+  // device arrays, carved from one block: the library's own (block != null)
+  // or the caller's (opt->workspace)
+  void* block = nullptr;
   // vertex arrays
   int32_t *gid[2], *parent, *lab, *claim, *step, *capq, *capx, *sw_seg, *newid,
       *map, *ogid;
-  SweepCtl* sweep;                  // MAX_SWEEPS queues
-  SweepCtl* sweep_host = nullptr;   // pinned, for single-field readbacks
+  SweepCtl* sweep;                  // sweep_slots queues
+  int32_t sweep_slots = 0;          // full-graph sweeps run at once (at most MAX_SWEEPS)
   SweepArgs* sw_args;               // per swept graph
   int32_t* sw_run;                  // graphs still running
   SweepStatus* sw_status;
-  SweepArgs* sw_args_host = nullptr;  // pinned mirrors
-  int32_t* sw_run_host = nullptr;
-  SweepStatus* sw_status_host = nullptr;
   int64_t* sw_info;
   int64_t *rp, *cdeg;
   uint64_t* fb_rs;  // sweeps: per vertex (r, visit stamp)
@@ -173,205 +175,263 @@ struct Workspace {
   void* tmp;
   size_t tmp_bytes = 0;
   Ctl* ctl;
+  // pinned host staging for small read-backs (owned unless borrowed from
+  // the stream's own workspace for a call on the caller's memory)
+  bool host_owned = true;
   Ctl* ctl_host = nullptr;
-  // clustering levels (allocated on first use): two level graphs that the
-  // contractions alternate between, labels, class flags, the long-row list,
-  // the map from input vertices to level vertices, per-graph state
+  SweepCtl* sweep_host = nullptr;   // single-field readbacks
+  SweepArgs* sw_args_host = nullptr;
+  int32_t* sw_run_host = nullptr;
+  SweepStatus* sw_status_host = nullptr;
+  // clustering levels (on first use; after the core arrays in the caller's
+  // block): two level graphs that the contractions alternate between,
+  // labels, class flags, the long-row list, the map from input vertices to
+  // level vertices, per-graph state
   struct Vc {
     int64_t capN = 0, capE = 0, capG = 0;
-    std::vector<void*> allocs;
+    void* block = nullptr;
     int32_t *src[2], *col[2], *w[2], *gid[2], *label[2], *map, *flag, *item_off, *act, *n0;
     int64_t *rp[2], *cdeg[2];
     uint64_t* best;
   } vc;
 
   void release_vc() {
-    for (void* p : vc.allocs) hipFree(p);
-    vc.allocs.clear();
-    vc.capN = vc.capE = vc.capG = 0;
+    if (vc.block) hipFree(vc.block);
+    vc = Vc{};
+  }
+
+  void release_device() {
+    release_vc();
+    if (block) hipFree(block);
+    block = nullptr;
+    capN = capE = capG = 0;
   }
 
   void release() {
-    release_vc();
-    for (void* p : allocs) hipFree(p);
-    allocs.clear();
-    if (ctl_host) hipHostFree(ctl_host);
-    if (sweep_host) hipHostFree(sweep_host);
-    if (sw_args_host) hipHostFree(sw_args_host);
-    if (sw_run_host) hipHostFree(sw_run_host);
-    if (sw_status_host) hipHostFree(sw_status_host);
+    release_device();
+    if (host_owned) {
+      if (ctl_host) hipHostFree(ctl_host);
+      if (sweep_host) hipHostFree(sweep_host);
+      if (sw_args_host) hipHostFree(sw_args_host);
+      if (sw_run_host) hipHostFree(sw_run_host);
+      if (sw_status_host) hipHostFree(sw_status_host);
+    }
+    ctl_host = nullptr;
+    sweep_host = nullptr;
     sw_args_host = nullptr;
     sw_run_host = nullptr;
     sw_status_host = nullptr;
-    ctl_host = nullptr;
-    sweep_host = nullptr;
-    capN = capE = capG = 0;
+    device = -1;
+  }
+
+  int ensure_host() {
+    if (ctl_host) return MC_OK;
+    if (hipHostMalloc((void**)&ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sweep_host, sizeof(SweepCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sw_args_host, sizeof(SweepArgs) * MAX_SWEEPS, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sw_run_host, sizeof(int32_t) * MAX_SWEEPS, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&sw_status_host, sizeof(SweepStatus) * MAX_SWEEPS, hipHostMallocDefault) !=
+            hipSuccess) {
+      release();
+      return MC_ENOMEM;
+    }
+    host_owned = true;
+    return MC_OK;
   }
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
-  size_t b = 0;
-  b += align_up((N + 1) * 4) * 15 + align_up((N + 1) * 8) + align_up((G + 1) * 40);
-  b += align_up(sizeof(SweepCtl) * MAX_SWEEPS) + align_up(sizeof(SweepArgs) * MAX_SWEEPS) +
-       2 * align_up(sizeof(SweepStatus) * MAX_SWEEPS);
-  b += align_up((N + 2) * 8) * 2;
-  b += align_up(E * 4) * 3 + align_up((E + 64) * 8) + align_up((E + G + 64) * 8) + align_up(E * 4) * 2;
-  b += align_up((G + 1) * 8) * 4 + align_up((G + 1) * 4) * 19 + align_up((G + 1) * 8) * 2 +
-       align_up(G + 1);
-  b += align_up((2 * N + G + 64) * 4) + 2 * align_up(((N + 63) / 64 + 1) * 8);
-  size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
-  t = std::max(t, scan_tmp_bytes<int32_t>(N + 1));
-  b += align_up(t) + align_up(sizeof(Ctl));
-  return b;
+// The sizes a problem of N vertices, E entries and G graphs is laid out for.
+static void clamp_sizes(int64_t& N, int64_t& E, int64_t& G) {
+  N = std::max<int64_t>(N, 16);
+  E = std::max<int64_t>(E, 64);
+  G = std::max<int64_t>(G, 1);
 }
 
+// Lay the core arrays out from `base` (or only measure, base == nullptr):
+// returns the bytes they take, every array 256-byte aligned.
+size_t carve(Workspace& ws, char* base, int64_t N, int64_t E, int64_t G) {
+  size_t off = 0;
+  auto take = [&](auto& ptr, size_t bytes) {
+    using P = std::remove_reference_t<decltype(ptr)>;
+    if (base) ptr = reinterpret_cast<P>(base + off);
+    off += align_up(bytes);
+  };
+  take(ws.gid[0], (N + 1) * 4);
+  take(ws.gid[1], (N + 1) * 4);
+  take(ws.parent, (N + 1) * 4);
+  take(ws.lab, (N + 1) * 4);
+  take(ws.claim, (N + 1) * 4);
+  take(ws.step, (N + 1) * 4);
+  take(ws.fb_rs, (N + 1) * 8);
+  take(ws.newid, (N + 1) * 4);
+  take(ws.map, (N + 1) * 4);
+  take(ws.ogid, (N + 1) * 4);
+  take(ws.capq, (N + 1) * 4);
+  take(ws.capx, (N + 1) * 4);
+  take(ws.sw_seg, (N + 1) * 4);
+  const int64_t slots = std::min<int64_t>(G, MAX_SWEEPS);  // no more graphs than these are swept at once
+  if (base) ws.sweep_slots = (int32_t)slots;
+  take(ws.sweep, sizeof(SweepCtl) * slots);
+  take(ws.sw_args, sizeof(SweepArgs) * slots);
+  take(ws.sw_run, sizeof(int32_t) * slots);
+  take(ws.sw_status, sizeof(SweepStatus) * slots);
+  take(ws.sw_info, (G + 1) * 5 * 8);
+  take(ws.rp, (N + 2) * 8);
+  take(ws.cdeg, (N + 2) * 8);
+  take(ws.src, E * 4);
+  take(ws.col, E * 4);
+  take(ws.w, E * 4);
+  take(ws.keys, (E + 64) * 8);
+  take(ws.keys_alt, (E + G + 64) * 8);  // also the sweeps' bucket pools (one entry per relaxation)
+  take(ws.vals, E * 4);
+  take(ws.vals_alt, E * 4);
+  take(ws.voff, (G + 1) * 8);
+  take(ws.lhat, (G + 1) * 8);
+  take(ws.kcap, (G + 1) * 8);
+  take(ws.wsum, (G + 1) * 8);
+  take(ws.gn, (G + 1) * 4);
+  take(ws.cvoff, (G + 1) * 4);
+  take(ws.nnew, (G + 1) * 4);
+  take(ws.active, (G + 1) * 4);
+  take(ws.ucount, (G + 1) * 4);
+  take(ws.rec_type, (G + 1) * 4);
+  take(ws.rec_id, (G + 1) * 4);
+  take(ws.rec_k, (G + 1) * 4);
+  take(ws.fb_k, (G + 1) * 4);
+  take(ws.whole, (G + 1) * 4);
+  take(ws.whole2, (G + 1) * 4);
+  take(ws.fb_list, (G + 1) * 4);
+  take(ws.root0, (G + 1) * 4);
+  take(ws.flip, (G + 1) * 4);
+  take(ws.nvoff, (G + 1) * 4);
+  take(ws.bref, (G + 1) * 4);
+  take(ws.inref, ((N + 63) / 64 + 1) * 8);
+  take(ws.bbits, ((N + 63) / 64 + 1) * 8);
+  take(ws.npairs, (G + 1) * 4);
+  take(ws.gmaxw, (G + 1) * 4);
+  take(ws.prok, (G + 1) * 4);
+  take(ws.bdeg, (G + 1) * 8);
+  take(ws.balpha, (G + 1) * 8);
+  take(ws.mode, G + 1);
+  if (base) ws.scan_k_cap = 2 * N + G + 64;
+  take(ws.scan_k, (2 * N + G + 64) * 4);
+  size_t t = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
+  t = std::max(t, scan_tmp_bytes<int32_t>(N + 1));
+  if (base) ws.tmp_bytes = t;
+  take(ws.tmp, t);
+  take(ws.ctl, sizeof(Ctl));
+  return off;
+}
+
+size_t carve_vc(Workspace::Vc& v, char* base, int64_t N, int64_t E, int64_t G) {
+  size_t off = 0;
+  auto take = [&](auto& ptr, size_t bytes) {
+    using P = std::remove_reference_t<decltype(ptr)>;
+    if (base) ptr = reinterpret_cast<P>(base + off);
+    off += align_up(bytes);
+  };
+  for (int k = 0; k < 2; ++k) {
+    take(v.src[k], E * 4);
+    take(v.col[k], E * 4);
+    take(v.w[k], E * 4);
+    take(v.gid[k], (N + 1) * 4);
+    take(v.label[k], (N + 1) * 4);
+    take(v.rp[k], (N + 2) * 8);
+    take(v.cdeg[k], (N + 2) * 8);
+  }
+  take(v.map, (N + 1) * 4);
+  take(v.flag, (N + 1) * 4);
+  take(v.item_off, (N + 1) * 4);
+  take(v.best, (N + 1) * 8);
+  take(v.act, (G + 1) * 4);
+  take(v.n0, (G + 1) * 4);
+  return off;
+}
+
+size_t workspace_bytes(int64_t N, int64_t E, int64_t G) {
+  clamp_sizes(N, E, G);
+  Workspace dummy;
+  return carve(dummy, nullptr, N, E, G);
+}
+
+size_t vc_workspace_bytes(int64_t N, int64_t E, int64_t G) {
+  clamp_sizes(N, E, G);
+  Workspace::Vc dummy;
+  return carve_vc(dummy, nullptr, N, E, G);
+}
+
+// The core arrays for a problem of this size in the library's own block,
+// grown (with a quarter of headroom, so a caller whose sizes vary settles
+// after a few reallocations) when the problem no longer fits.
 int ensure(Workspace& ws, int64_t N, int64_t E, int64_t G) {
   int dev = 0;
   MC_HIP(hipGetDevice(&dev));
-  if (ws.device == dev && N <= ws.capN && E <= ws.capE && G <= ws.capG) return MC_OK;
-  // growing: a quarter of headroom, so a caller whose sizes vary (the
-  // server's lanes) settles after a few reallocations
+  int rc = ws.ensure_host();
+  if (rc) return rc;
+  if (ws.device == dev && ws.block && N <= ws.capN && E <= ws.capE && G <= ws.capG) return MC_OK;
   if (ws.device == dev && ws.capN > 0) {
     N = std::max(N, ws.capN + ws.capN / 4);
     E = std::max(E, ws.capE + ws.capE / 4);
     G = std::max(G, ws.capG + ws.capG / 4);
   }
-  ws.release();
+  ws.release_device();
+  clamp_sizes(N, E, G);
+  const size_t bytes = carve(ws, nullptr, N, E, G);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return MC_ENOMEM;
+  ws.block = p;
   ws.device = dev;
-  N = std::max<int64_t>(N, 16);
-  E = std::max<int64_t>(E, 64);
-  G = std::max<int64_t>(G, 1);
-  auto A = [&](size_t bytes, void** out) -> int {
-    void* p = nullptr;
-    if (hipMalloc(&p, align_up(bytes)) != hipSuccess) return MC_ENOMEM;
-    ws.allocs.push_back(p);
-    *out = p;
-    return MC_OK;
-  };
-#define ALLOC(ptr, bytes)                                     \
-  do {                                                        \
-    int rc_ = A((bytes), (void**)&(ptr));                     \
-    if (rc_) { ws.release(); return rc_; }                    \
-  } while (0)
-  ALLOC(ws.gid[0], (N + 1) * 4);
-  ALLOC(ws.gid[1], (N + 1) * 4);
-  ALLOC(ws.parent, (N + 1) * 4);
-  ALLOC(ws.lab, (N + 1) * 4);
-  ALLOC(ws.claim, (N + 1) * 4);
-  ALLOC(ws.step, (N + 1) * 4);
-  ALLOC(ws.fb_rs, (N + 1) * 8);
-  ALLOC(ws.newid, (N + 1) * 4);
-  ALLOC(ws.map, (N + 1) * 4);
-  ALLOC(ws.ogid, (N + 1) * 4);
-  ALLOC(ws.capq, (N + 1) * 4);
-  ALLOC(ws.capx, (N + 1) * 4);
-  ALLOC(ws.sw_seg, (N + 1) * 4);
-  ALLOC(ws.sweep, sizeof(SweepCtl) * MAX_SWEEPS);
-  ALLOC(ws.sw_args, sizeof(SweepArgs) * MAX_SWEEPS);
-  ALLOC(ws.sw_run, sizeof(int32_t) * MAX_SWEEPS);
-  ALLOC(ws.sw_status, sizeof(SweepStatus) * MAX_SWEEPS);
-  ALLOC(ws.sw_info, (G + 1) * 5 * 8);
-  ALLOC(ws.rp, (N + 2) * 8);
-  ALLOC(ws.cdeg, (N + 2) * 8);
-  ALLOC(ws.src, E * 4);
-  ALLOC(ws.col, E * 4);
-  ALLOC(ws.w, E * 4);
-  ALLOC(ws.keys, (E + 64) * 8);
-  ALLOC(ws.keys_alt, (E + G + 64) * 8);  // also the sweeps' bucket pools (one entry per relaxation)
-  ALLOC(ws.vals, E * 4);
-  ALLOC(ws.vals_alt, E * 4);
-  ALLOC(ws.voff, (G + 1) * 8);
-  ALLOC(ws.lhat, (G + 1) * 8);
-  ALLOC(ws.kcap, (G + 1) * 8);
-  ALLOC(ws.wsum, (G + 1) * 8);
-  ALLOC(ws.gn, (G + 1) * 4);
-  ALLOC(ws.cvoff, (G + 1) * 4);
-  ALLOC(ws.nnew, (G + 1) * 4);
-  ALLOC(ws.active, (G + 1) * 4);
-  ALLOC(ws.ucount, (G + 1) * 4);
-  ALLOC(ws.rec_type, (G + 1) * 4);
-  ALLOC(ws.rec_id, (G + 1) * 4);
-  ALLOC(ws.rec_k, (G + 1) * 4);
-  ALLOC(ws.fb_k, (G + 1) * 4);
-  ALLOC(ws.whole, (G + 1) * 4);
-  ALLOC(ws.whole2, (G + 1) * 4);
-  ALLOC(ws.fb_list, (G + 1) * 4);
-  ALLOC(ws.root0, (G + 1) * 4);
-  ALLOC(ws.flip, (G + 1) * 4);
-  ALLOC(ws.nvoff, (G + 1) * 4);
-  ALLOC(ws.bref, (G + 1) * 4);
-  ALLOC(ws.inref, ((N + 63) / 64 + 1) * 8);
-  ALLOC(ws.bbits, ((N + 63) / 64 + 1) * 8);
-  ALLOC(ws.npairs, (G + 1) * 4);
-  ALLOC(ws.gmaxw, (G + 1) * 4);
-  ALLOC(ws.prok, (G + 1) * 4);
-  ALLOC(ws.bdeg, (G + 1) * 8);
-  ALLOC(ws.balpha, (G + 1) * 8);
-  ALLOC(ws.mode, G + 1);
-  ws.scan_k_cap = 2 * N + G + 64;
-  ALLOC(ws.scan_k, ws.scan_k_cap * 4);
-  ws.tmp_bytes = std::max(scan_tmp_bytes<int64_t>(E + 1), radix_tmp_bytes(E + 1));
-  ws.tmp_bytes = std::max(ws.tmp_bytes, scan_tmp_bytes<int32_t>(N + 1));
-  ALLOC(ws.tmp, ws.tmp_bytes);
-  ALLOC(ws.ctl, sizeof(Ctl));
-#undef ALLOC
-  if (hipHostMalloc((void**)&ws.ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&ws.sweep_host, sizeof(SweepCtl), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&ws.sw_args_host, sizeof(SweepArgs) * MAX_SWEEPS, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&ws.sw_run_host, sizeof(int32_t) * MAX_SWEEPS, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&ws.sw_status_host, sizeof(SweepStatus) * MAX_SWEEPS, hipHostMallocDefault) !=
-          hipSuccess) {
-    ws.release();
-    return MC_ENOMEM;
-  }
+  carve(ws, (char*)p, N, E, G);
   ws.capN = N;
   ws.capE = E;
   ws.capG = G;
   return MC_OK;
 }
 
-size_t vc_workspace_bytes(int64_t N, int64_t E, int64_t G) {
-  return 2 * (3 * align_up(E * 4) + 2 * align_up((N + 1) * 4) + 2 * align_up((N + 2) * 8)) +
-         3 * align_up((N + 1) * 4) + align_up((N + 1) * 8) + 2 * align_up((G + 1) * 4);
+// The core arrays in the caller's block (no allocation; MC_EINVAL if it is
+// smaller than workspace_bytes).  The clustering arrays follow them there.
+int carve_caller(Workspace& ws, void* base, size_t bytes, int64_t N, int64_t E, int64_t G) {
+  int dev = 0;
+  MC_HIP(hipGetDevice(&dev));
+  clamp_sizes(N, E, G);
+  const size_t need = carve(ws, nullptr, N, E, G);
+  if (!base || bytes < need) return MC_EINVAL;
+  carve(ws, (char*)base, N, E, G);
+  ws.device = dev;
+  ws.capN = N;
+  ws.capE = E;
+  ws.capG = G;
+  ws.vc = Workspace::Vc{};
+  return MC_OK;
 }
 
-int ensure_vc(Workspace& ws, int64_t N, int64_t E, int64_t G) {
+struct CallerBlock {
+  char* base = nullptr;   // the caller's workspace, or nullptr
+  size_t bytes = 0;
+  size_t core = 0;        // bytes the core arrays took
+};
+
+int ensure_vc(Workspace& ws, int64_t N, int64_t E, int64_t G, const CallerBlock& cb) {
   Workspace::Vc& v = ws.vc;
-  if (N <= v.capN && E <= v.capE && G <= v.capG) return MC_OK;
-  ws.release_vc();
-  N = std::max<int64_t>(N, 16);
-  E = std::max<int64_t>(E, 64);
-  G = std::max<int64_t>(G, 1);
-  auto A = [&](size_t bytes, void** out) -> int {
-    void* p = nullptr;
-    if (hipMalloc(&p, align_up(bytes)) != hipSuccess) return MC_ENOMEM;
-    v.allocs.push_back(p);
-    *out = p;
+  clamp_sizes(N, E, G);
+  if (cb.base) {
+    const size_t need = carve_vc(v, nullptr, N, E, G);
+    if (cb.bytes < cb.core + need) return MC_EINVAL;
+    carve_vc(v, cb.base + cb.core, N, E, G);
+    v.capN = N;
+    v.capE = E;
+    v.capG = G;
     return MC_OK;
-  };
-#define ALLOC(ptr, bytes)                                     \
-  do {                                                        \
-    int rc_ = A((bytes), (void**)&(ptr));                     \
-    if (rc_) { ws.release_vc(); return rc_; }                 \
-  } while (0)
-  for (int k = 0; k < 2; ++k) {
-    ALLOC(v.src[k], E * 4);
-    ALLOC(v.col[k], E * 4);
-    ALLOC(v.w[k], E * 4);
-    ALLOC(v.gid[k], (N + 1) * 4);
-    ALLOC(v.label[k], (N + 1) * 4);
-    ALLOC(v.rp[k], (N + 2) * 8);
-    ALLOC(v.cdeg[k], (N + 2) * 8);
   }
-  ALLOC(v.map, (N + 1) * 4);
-  ALLOC(v.flag, (N + 1) * 4);
-  ALLOC(v.item_off, (N + 1) * 4);
-  ALLOC(v.best, (N + 1) * 8);
-  ALLOC(v.act, (G + 1) * 4);
-  ALLOC(v.n0, (G + 1) * 4);
-#undef ALLOC
+  if (v.block && N <= v.capN && E <= v.capE && G <= v.capG) return MC_OK;
+  ws.release_vc();
+  const size_t bytes = carve_vc(v, nullptr, N, E, G);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return MC_ENOMEM;
+  v.block = p;
+  carve_vc(v, (char*)p, N, E, G);
   v.capN = N;
   v.capE = E;
   v.capG = G;
@@ -452,6 +512,8 @@ struct Solver {
   const int64_t* lhat_in = nullptr; // optional starting bounds (host, per graph)
   bool viecut_only = false;         // stop after the clustering bound
   int32_t vc_levels_run = 0;        // clustering levels run (most over graphs)
+  mc_stats* stats_out = nullptr;    // per-phase sweep counters (when wanted)
+  CallerBlock cb;                   // the caller's workspace, if any
   int32_t ngraphs = 1;              // graphs in the problem being solved
 
   int read_ctl() {
@@ -520,8 +582,8 @@ struct Solver {
     const int TB = 256;
     const int32_t total = (int32_t)glist.size();
     std::vector<int32_t> run, next;
-    for (int32_t c0 = 0; c0 < total; c0 += MAX_SWEEPS) {
-      const int32_t kq = std::min<int32_t>(MAX_SWEEPS, total - c0);
+    for (int32_t c0 = 0; c0 < total; c0 += ws.sweep_slots) {
+      const int32_t kq = std::min<int32_t>(ws.sweep_slots, total - c0);
       int32_t k = 0;
       int64_t max_ng = 0, entries = 0;
       for (int32_t i = 0; i < kq; ++i) {
@@ -538,6 +600,11 @@ struct Solver {
         A.nwords = (A.nb + 63) / 64;
         A.big = opt.sweep_handoff > 0 ? opt.sweep_handoff : 512;
         A.big_entries = SWEEP_HANDOFF_ENTRIES;
+        // the tail: concurrent scans once at most a quarter of the graph (at
+        // most 2^18 vertices: the pops of a process fit 20 bits) and at
+        // least tail_min vertices are left
+        A.tail_min = opt.sweep_tail < 0 ? 0 : opt.sweep_tail > 0 ? opt.sweep_tail : 256;
+        A.tail_max = std::min(ng / 4, 1 << 18);
         uint64_t h = (opt.seed ? opt.seed : 0x5EEDull) * 0x9E3779B97F4A7C15ull +
                      (uint64_t)round * 0xBF58476D1CE4E5B9ull + (uint64_t)glist[q];
         h ^= h >> 29;
@@ -555,13 +622,13 @@ struct Solver {
       hipLaunchKernelGGL(k_sweep_seed, dim3(grid_for(k, TB, num_cu)), dim3(TB), 0, s, ws.sw_args, k);
       run.resize(k);
       for (int32_t i = 0; i < k; ++i) run[i] = i;
-      double big_deg = 0;
+      double big_deg = 0, big_vtx = 0;
       while (!run.empty()) {
         const int32_t nrun = (int32_t)run.size();
         std::memcpy(ws.sw_run_host, run.data(), sizeof(int32_t) * nrun);
         MC_HIP(hipMemcpyAsync(ws.sw_run, ws.sw_run_host, sizeof(int32_t) * nrun, hipMemcpyHostToDevice, s));
         {
-          TimedScope t("sweep_seq", 0.0);
+          TimedScope t("k_sweep_seq", 0.0);
           hipLaunchKernelGGL(k_sweep_seq, dim3(nrun), dim3(SWEEP_THREADS), 0, s, ws.sw_args, ws.sw_run);
         }
         hipLaunchKernelGGL(k_sweep_status, dim3(grid_for(nrun, TB, num_cu)), dim3(TB), 0, s, ws.sw_args,
@@ -573,12 +640,34 @@ struct Solver {
         for (int32_t j = 0; j < nrun; ++j) {
           const SweepStatus c = ws.sw_status_host[j];
           if (c.status == SW_DONE) continue;
-          if (c.status != SW_BIG) return MC_EINTERNAL;
+          if (c.status != SW_BIG && c.status != SW_TAIL) return MC_EINTERNAL;
           const SweepArgs& A = ws.sw_args_host[run[j]];
+          if (c.status == SW_TAIL) {
+            // the tail as concurrent scans over the exact frontier list
+            {
+              TimedScope t("sweep_rebuild", (double)A.ng * 16);
+              hipLaunchKernelGGL(k_sweep_rb_zero, dim3(16), dim3(256), 0, s, A);
+              hipLaunchKernelGGL(k_sweep_rb_count, dim3(grid_for(A.ng, TB, num_cu * 4)), dim3(TB), 0, s, A);
+              hipLaunchKernelGGL(k_sweep_rb_scan, dim3(1), dim3(1024), 0, s, A);
+              hipLaunchKernelGGL(k_sweep_rb_fill, dim3((A.ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);
+            }
+            const int32_t left = A.ng - c.visited;
+            int32_t nf = std::min<int32_t>(TAIL_MAX_FORKS, std::max<int32_t>(64, left / 8));
+            nf = (nf + TAIL_WAVES - 1) / TAIL_WAVES * TAIL_WAVES;
+            hipLaunchKernelGGL(k_sweep_tail_init, dim3(1), dim3(64), 0, s, A);
+            TimedScope t("k_sweep_tail", 0.0);
+            hipLaunchKernelGGL(k_sweep_tail, dim3(nf / TAIL_WAVES), dim3(64 * TAIL_WAVES), 0, s, A, nf);
+            continue;  // the graph's sweep ends with its tail
+          }
           const int32_t bh = c.cap_head, bt = c.cap_tail;
           const int64_t bsz = bt - bh;
           MC_HIP(hipMemsetAsync(&A.ctl->batch_sum, 0, 24, s));
-          hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
+          {
+            // per batch vertex its FIFO slot, degree, r word and stamp
+            TimedScope t("k_sweep_big_mark", (double)bsz * 32);
+            hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
+          }
+          big_vtx += (double)bsz;
           int64_t deg_sum = 0;
           if (timer().on) {
             MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &A.ctl->batch_deg, 8, hipMemcpyDeviceToHost, s));
@@ -586,15 +675,14 @@ struct Solver {
             deg_sum = ws.sweep_host->batch_deg;
             big_deg += (double)deg_sum;
           }
+          // prefix sums of the batch's row lengths (ws.keys and ws.vals are
+          // free until the contraction) and each entry tile's first row
+          int64_t* off = (int64_t*)ws.keys;
+          int32_t* tile_row = ws.vals;
           {
-            // every row of the batch once (col, w: 8 B per entry), the state
-            // gather and the r read-modify-write of each neighbour (12 B), and
-            // per batch vertex its FIFO slot and row bounds (20 B)
-            TimedScope t("sweep_relax", (double)deg_sum * 20 + (double)bsz * 20);
-            // prefix sums of the batch's row lengths (ws.keys and ws.vals are
-            // free until the contraction) and each entry tile's first row
-            int64_t* off = (int64_t*)ws.keys;
-            int32_t* tile_row = ws.vals;
+            // per batch vertex its FIFO slot and row bounds, the prefix sum
+            // written; then the graph's visit state read once, two bits written
+            TimedScope t("sweep_batch_prep", (double)bsz * 28 + (double)A.ng * 8);
             exclusive_scan<int64_t, BatchDeg>(BatchDeg{A.capq + bh, rp}, bsz, off, off + bsz, ws.tmp, s);
             hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
                                (int32_t)bsz, tile_row);
@@ -602,6 +690,11 @@ struct Solver {
             // the contraction)
             hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.inref,
                                ws.bbits);
+          }
+          {
+            // every row of the batch once (col, w: 8 B per entry) and per
+            // batch vertex its row bounds
+            TimedScope t("k_sweep_big_relax", (double)deg_sum * 8 + (double)bsz * 8);
             static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
             hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
                                tile_row, ws.inref, ws.bbits);
@@ -619,15 +712,51 @@ struct Solver {
         }
         run.swap(next);
       }
-      // the sequential kernel relaxed every row the grid-wide batches did not
-      if (timer().on) timer().add_bytes("sweep_seq", ((double)entries - big_deg) * 20);
-      hipLaunchKernelGGL(k_sweep_unite, dim3(gx, k), dim3(TB), 0, s, ws.sw_args);
+      // the sequential kernel relaxed every row the grid-wide batches did
+      // not (8 B per entry) and visited every other vertex (row bounds,
+      // degree, r and stamp, the claim and its union: 40 B per vertex)
+      // (timing mode only, which synchronises anyway: the counters are
+      // read back per graph, with the per-phase step counts for the stats)
+      double crossings = 0;
+      if (timer().on) {
+        double visited = 0, seq_rows = 0, tail_rows = 0, tail_pops = 0;
+        for (int32_t i = 0; i < k; ++i) {
+          SweepCtl c;
+          MC_HIP(hipMemcpyAsync(&c, ws.sw_args_host[i].ctl, offsetof(SweepCtl, bitmap), hipMemcpyDeviceToHost, s));
+          MC_HIP(hipStreamSynchronize(s));
+          visited += c.visited;
+          seq_rows += (double)c.seq_rows;
+          tail_rows += (double)c.tail_rows;
+          tail_pops += c.tail_pops;
+          crossings += std::min(c.cap_tail, ws.sw_args_host[i].ng);
+          if (stats_out) {
+            stats_out->sweep_phases = std::max(stats_out->sweep_phases, std::min(c.big_batches + 1, SWEEP_PHASES));
+            stats_out->sweep_big_batches += c.big_batches;
+            for (int p = 0; p < SWEEP_PHASES; ++p) {
+              stats_out->sweep_singles[p] += c.ph_singles[p];
+              stats_out->sweep_batches[p] += c.ph_batches[p];
+              stats_out->sweep_cross[p] += c.ph_cross[p];
+            }
+          }
+        }
+        timer().add_bytes("k_sweep_seq", seq_rows * 8 + (visited - big_vtx) * 40);
+        timer().add_bytes("k_sweep_tail", tail_rows * 8 + tail_pops * 40);
+        if (stats_out) {
+          stats_out->sweep_tail_pops += (int64_t)tail_pops;
+        }
+      }
+      {
+        // one union (a parent word read and written) per crossing
+        TimedScope t("k_sweep_unite", 0.0);
+        hipLaunchKernelGGL(k_sweep_unite, dim3(gx, k), dim3(TB), 0, s, ws.sw_args);
+      }
+      if (timer().on) timer().add_bytes("k_sweep_unite", crossings * 8);
       hipLaunchKernelGGL(k_sweep_report, dim3(grid_for(k, TB, num_cu)), dim3(TB), 0, s, ws.sw_args, k, S);
       if (debug_on()) {
         MC_HIP(hipStreamSynchronize(s));
         for (int32_t i = 0; i < k; ++i) {
           SweepCtl c;
-          MC_HIP(hipMemcpy(&c, ws.sw_args_host[i].ctl, 128, hipMemcpyDeviceToHost));
+          MC_HIP(hipMemcpy(&c, ws.sw_args_host[i].ctl, offsetof(SweepCtl, bitmap), hipMemcpyDeviceToHost));
           fprintf(stderr, "[mc] sweep g=%d v0=%d ng=%d lam=%lld visited=%d singles=%d batches=%d big=%d "
                   "rebuilds=%d unions=%d best_alpha=%lld step=%d\n", ws.sw_args_host[i].g, ws.sw_args_host[i].v0,
                   ws.sw_args_host[i].ng, (long long)ws.sw_args_host[i].lam, c.visited, c.singles, c.batches,
@@ -638,12 +767,45 @@ struct Solver {
     return MC_OK;
   }
 
+  // Opt-in check that the input is symmetric (the entry sources are in
+  // ws.src): one sort of the entries keyed by unordered pair, with the two
+  // directions' weights summed with opposite signs.  The contraction's
+  // buffers are free until the first round.
+  int check_symmetry(int32_t N, int64_t E, const int32_t* col, const int32_t* w) {
+    const int TB = 256;
+    const int bb = std::max(1, bitlen((uint64_t)N - 1));
+    MC_HIP(hipMemsetAsync(&ws.ctl->emit, 0, sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_sym_emit, dim3(grid_for(E, TB, num_cu * 16)), dim3(TB), 0, s, E, ws.src, col, w, bb,
+                       ws.keys, ws.vals, ws.ctl);
+    int rc = read_ctl();
+    if (rc) return rc;
+    const int64_t m = ws.ctl_host->emit;
+    if (m == 0) return MC_OK;
+    const int which = radix_sort_pairs(ws.keys, ws.vals, ws.keys_alt, ws.vals_alt, m, 2 * bb, ws.tmp, s);
+    uint64_t* sk = which ? ws.keys_alt : ws.keys;
+    int32_t* sv = which ? ws.vals_alt : ws.vals;
+    int32_t* spare = which ? ws.vals : ws.vals_alt;
+    int64_t* pos = (int64_t*)(which ? ws.keys : ws.keys_alt);
+    exclusive_scan<int64_t, HeadFlag>(HeadFlag{sk}, m, pos, (int64_t*)&ws.ctl->unique, ws.tmp, s);
+    rc = read_ctl();
+    if (rc) return rc;
+    const int64_t m2 = ws.ctl_host->unique;
+    fill<int32_t>(ws.w, 0, m2, s);
+    hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s, m, sk, sv,
+                       pos, bb, ws.col, spare, ws.w);
+    hipLaunchKernelGGL(k_sym_nonzero, dim3(grid_for(m2, TB, num_cu * 4)), dim3(TB), 0, s, m2, ws.w, ws.ctl);
+    rc = read_ctl();
+    if (rc) return rc;
+    return ws.ctl_host->asym ? MC_EINVAL : MC_OK;
+  }
+
   // Timing class names of one contraction's stages.
   struct StageNames {
-    const char *emit, *sort_hist, *sort_scatter, *merge_scan, *merge, *csr;
+    const char *block_bits, *emit, *sort_hist, *sort_scatter, *merge_scan, *merge, *csr;
   };
-  static constexpr StageNames kExactNames{"emit", "sort_hist", "sort_scatter", "merge_scan", "merge", "csr"};
-  static constexpr StageNames kVcNames{"vc_contract", "vc_contract", "vc_contract",
+  static constexpr StageNames kExactNames{"block_bits", "k_emit", "k_rs_hist", "k_rs_scatter",
+                                          "merge_scan", "k_merge", "csr"};
+  static constexpr StageNames kVcNames{"vc_contract", "vc_contract", "vc_contract", "vc_contract",
                                        "vc_contract", "vc_contract", "vc_contract"};
   struct Out {
     int32_t *src, *col, *w;
@@ -668,13 +830,17 @@ struct Solver {
     const int bb = std::max(1, bitlen((uint64_t)std::max(n_next, 1) - 1));
     MC_HIP(hipMemsetAsync(&ws.ctl->emit, 0, sizeof(int64_t), s));
     {
-      // src, col, w and two label gathers per entry; the keys it writes are
-      // counted with the sort
-      TimedScope t(nm.emit, (double)nnz * 20);
+      // the labels read once, one bit written per vertex
+      TimedScope t(nm.block_bits, (double)n_cur * 8);
       hipLaunchKernelGGL(k_block_ref, dim3(grid_for((int64_t)ngraphs * 64, TB, num_cu * 8)), dim3(TB), 0, s,
                          ngraphs, n_cur, ws.cvoff, ws.gn, lab, ws.bref);
       hipLaunchKernelGGL(k_block_bits, dim3(grid_for(n_cur, TB, num_cu * 16)), dim3(TB), 0, s, n_cur, lab, gid_cur,
                          ws.bref, ws.inref);
+    }
+    {
+      // per entry col and w and the label gather (12 B); per emitted entry
+      // its key and weight (12 B, added once the count is read back)
+      TimedScope t(nm.emit, (double)nnz * 12);
       static const int emit_grid = resident_grid((const void*)&k_emit, TB, num_cu);
       hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, emit_grid)), dim3(TB), 0, s, nnz,
                          src, col, w, lab, bb, ws.inref, ws.keys, ws.vals, ws.ctl);
@@ -682,6 +848,7 @@ struct Solver {
     int rc = read_ctl();
     if (rc) return rc;
     const int64_t m = ws.ctl_host->emit;
+    timer().add_bytes(nm.emit, (double)m * 12);
     int which = 0;
     {
       // per pass: the histogram reads every key (8 B); the scatter reads
@@ -706,10 +873,10 @@ struct Solver {
     rc = read_ctl();
     if (rc) return rc;
     const int64_t m2 = m > 0 ? ws.ctl_host->unique : 0;
+    fill<int32_t>(out.w, 0, m2, s);
     {
-      fill<int32_t>(out.w, 0, m2, s);
-      // keys, weights and positions in; the merged entries out
-      TimedScope t(nm.merge, (double)m * 20 + (double)m2 * 12);
+      // sorted keys and weights in (12 B); the merged entries out (12 B)
+      TimedScope t(nm.merge, (double)m * 12 + (double)m2 * 12);
       if (m > 0)
         hipLaunchKernelGGL(k_merge, dim3(grid_for((m + 255) / 256 * 256, TB, num_cu * 16)), dim3(TB), 0, s, m, sk,
                            sv, pos, bb, out.src, out.col, out.w);
@@ -748,7 +915,7 @@ struct Solver {
 
   int viecut(const Problem& P, GraphState S, const int32_t* gid_in, uint8_t* side, LevelGraph* last = nullptr) {
     const int32_t G = P.G, N = P.n;
-    int rc = ensure_vc(ws, N, P.nnz, G);
+    int rc = ensure_vc(ws, N, P.nnz, G, cb);
     if (rc) return rc;
     Workspace::Vc& V = ws.vc;
     const int TB = 256;
@@ -792,7 +959,7 @@ struct Solver {
                          carry, V.act, V.n0, ws.ctl);
       hipLaunchKernelGGL(k_compose_map, grid(N), dim3(TB), 0, s, N, V.map, ws.lab);
       if (side) {
-        TimedScope t("side", (double)N * 13);
+        TimedScope t("k_side", (double)N * 13);
         hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
       }
       r = read_ctl();
@@ -929,7 +1096,7 @@ struct Solver {
     // ---- ingest: validation, entry sources, weighted degrees, trivial bound
     {
       // row_ptr read once
-      TimedScope t("ingest", (double)(N + 1) * 8);
+      TimedScope t("k_check_rowptr", (double)(N + 1) * 8);
       hipLaunchKernelGGL(k_check_rowptr, grid(N), dim3(TB), 0, s, N, E, P.rp, ws.ctl);
     }
     int rc = read_ctl();
@@ -938,9 +1105,6 @@ struct Solver {
     int32_t* gid = ws.gid[0];
     int32_t* gid_next = ws.gid[1];
     {
-      // col, w read and src written per entry (12 B); per vertex row_ptr
-      // for the chunk rows, the degree written and read back, graph ids
-      TimedScope t("ingest", (double)E * 12 + (double)N * 24);
       hipLaunchKernelGGL(k_init_vertices, grid(N), dim3(TB), 0, s, N, ws.voff, G, gid, ws.ogid, ws.map);
       fill<int64_t>(ws.cdeg, 0, N, s);
       fill<int32_t>(ws.gmaxw, 0, G, s);
@@ -948,6 +1112,9 @@ struct Solver {
         // chunk first rows in the sort keys' buffer (free until the first contraction)
         int32_t* first = (int32_t*)ws.keys;
         hipLaunchKernelGGL(k_chunk_rows, grid(N), dim3(TB), 0, s, N, P.rp, first);
+        // per entry col and w (8 B); per vertex its row bounds and its
+        // weighted degree (16 B)
+        TimedScope t("k_ingest", (double)E * 8 + (double)N * 16);
         static const int ingest_grid = resident_grid((const void*)&k_ingest, TB, num_cu);
         hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + INGEST_CH - 1) / INGEST_CH * TB, TB, ingest_grid)), dim3(TB),
                            0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, first, ws.src, ws.cdeg, ws.gmaxw, ws.ctl);
@@ -961,6 +1128,10 @@ struct Solver {
     rc = read_ctl();
     if (rc) return rc;
     if (ws.ctl_host->err) return MC_EINVAL;
+    if (opt.validate && E > 0) {
+      rc = check_symmetry(N, E, P.col, P.w);
+      if (rc) return rc;
+    }
     if (opt.scan_mode == 1) {
       // Region scans may never cover a component, so components are found
       // up front.  Sweeps and whole scans need no such pass: a scan that
@@ -978,7 +1149,7 @@ struct Solver {
     hipLaunchKernelGGL(k_graph_init, grid(G), dim3(TB), 0, s, G, S, ws.root0, ws.parent, ws.gmaxw, ws.prok,
                        ws.ctl);
     if (want_side) {
-      TimedScope t("side", (double)N * 13);
+      TimedScope t("k_side", (double)N * 13);
       SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
                   ws.fb_rs, ws.parent, ws.root0, side, REC_DEG};
       hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
@@ -1084,21 +1255,29 @@ struct Solver {
       hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
       fill<int32_t>(ws.claim, -1, n, s);
       if (opt.use_pr && (round > 1 || pr_first_round)) {
-        // src, col, w per entry; both degrees for the half with u < v
-        TimedScope t("pr", (double)nnz * 20 + (double)n * 32);
         const int32_t* tested = (round == 1 && !pr_first_all) ? ws.prok : ws.active;
-        hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, ws.cdeg, gid, cap,
-                           tested, ws.parent, ws.ucount);
-        hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+        {
+          // per vertex its row bounds, degree, bound and parent, and its
+          // first two entries with their neighbours' degrees
+          TimedScope t("k_pr_sample", (double)n * 64);
+          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, ws.cdeg, gid, cap,
+                             tested, ws.parent, ws.ucount);
+          hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
+        }
         hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, cap, tested, ws.ctl);
-        hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
-                           cap, tested, ws.parent, ws.ucount, ws.ctl);
+        {
+          // per entry col, w and the gather of c(v) (16 B); per vertex its
+          // row bounds and c(u) (16 B)
+          TimedScope t("k_pr", (double)nnz * 16 + (double)n * 16);
+          hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
+                             cap, tested, ws.parent, ws.ucount, ws.ctl);
+        }
       }
       // the triangle tests on contracted graphs (from the second round; a
       // negative limit also tests the input): per tested edge both rows
       const int32_t tri_deg = opt.pr_triangle_deg < 0 ? -opt.pr_triangle_deg : opt.pr_triangle_deg;
       if (opt.use_pr && tri_deg > 0 && (round > 1 || opt.pr_triangle_deg < 0)) {
-        TimedScope t("pr34", (double)nnz * 20);
+        TimedScope t("k_pr34", (double)nnz * 20);
         hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
                            ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
       }
@@ -1162,7 +1341,7 @@ struct Solver {
                           &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_rs, ws.capq, ws.capx, ws.npairs,
                           ws.balpha, ws.fb_k, ws.ucount, A.seed};
         {
-          TimedScope t("small_sweep", 0.0);
+          TimedScope t("k_small_sweep", 0.0);
           MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
           launch_small_sweep(opt.sweep_threads, opt.sweep_groups, num_cu, SA, s);
         }
@@ -1172,7 +1351,7 @@ struct Solver {
                            ws.cvoff, ws.npairs, ws.capq, ws.capx, ws.parent);
       }
       {
-        TimedScope t("union", (double)n * 8);
+        TimedScope t("k_union_pairs", (double)n * 8);
         hipLaunchKernelGGL(k_union_pairs, grid(n), dim3(TB), 0, s, ws.keys_alt, ws.ctl, ws.capE, ws.parent);
       }
       const int sweep_region = (opt.scan_mode != 1 || opt.force_fallback) ? 1 : 0;
@@ -1186,7 +1365,7 @@ struct Solver {
       if (hashed)
         timer().add_bytes("capforest_whole", (double)ws.ctl_host->whole_nnz * 8 + (double)ws.ctl_host->whole_nv * 32);
       else
-        timer().add_bytes("small_sweep", (double)ws.ctl_host->whole_nnz * 8 + (double)ws.ctl_host->whole_nv * 24);
+        timer().add_bytes("k_small_sweep", (double)ws.ctl_host->whole_nnz * 8 + (double)ws.ctl_host->whole_nv * 40);
       if (st) {
         st->unions_pr += ws.ctl_host->unions_pr;
         st->scans += ws.ctl_host->scan_ids;
@@ -1206,7 +1385,7 @@ struct Solver {
       }
       // union-find finish and block numbering
       {
-        TimedScope t("compact", (double)n * 24);
+        TimedScope t("compact", (double)n * 16);
         hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
         if (debug_labels) {
           MC_HIP(hipMemcpyAsync(debug_labels, ws.parent, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
@@ -1222,7 +1401,7 @@ struct Solver {
       }
       hipLaunchKernelGGL(k_update_alpha, grid(G), dim3(TB), 0, s, G, S, ws.scan_k, ws.ctl);
       if (want_side) {
-        TimedScope t("side", (double)N * 21);
+        TimedScope t("k_side", (double)N * 21);
         SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
                     ws.fb_rs, ws.parent, ws.root0, side, REC_ALPHA};
         hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
@@ -1243,7 +1422,7 @@ struct Solver {
       MC_HIP(hipMemsetAsync(&ws.ctl->n_active, 0, sizeof(int32_t), s));
       hipLaunchKernelGGL(k_finish_round, grid(G), dim3(TB), 0, s, G, S, ws.nvoff, ws.ctl);
       if (want_side) {
-        TimedScope t("side", (double)N * 9);
+        TimedScope t("k_side", (double)N * 9);
         SideArgs sa{N, ws.ogid, ws.map, ws.rec_type, ws.rec_id, ws.rec_k, ws.claim, ws.step,
                     ws.fb_rs, ws.parent, ws.root0, side, REC_DEG};
         hipLaunchKernelGGL(k_side, grid(N), dim3(TB), 0, s, sa);
@@ -1275,17 +1454,37 @@ struct Solver {
   }
 };
 
-std::mutex& api_mutex() {
+// One cached workspace per (device, stream): calls on different streams
+// run concurrently, each on its own arrays; calls on one stream take turns
+// on its slot.
+struct Slot {
+  std::mutex m;
+  Workspace ws;
+};
+
+std::mutex& registry_mutex() {
   static std::mutex m;
   return m;
 }
 
-Workspace& global_ws() {
-  static Workspace ws;
-  return ws;
+std::map<std::pair<int, void*>, std::unique_ptr<Slot>>& registry() {
+  static std::map<std::pair<int, void*>, std::unique_ptr<Slot>> r;
+  return r;
+}
+
+int slot_for(void* stream, Slot** out) {
+  int dev = 0;
+  MC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(registry_mutex());
+  auto& p = registry()[{dev, stream}];
+  if (!p) p = std::make_unique<Slot>();
+  *out = p.get();
+  return MC_OK;
 }
 
 // A solve on a given workspace and stream (no lock: the caller owns both).
+// With opt->workspace the device arrays are carved from the caller's block
+// (ws then only lends its pinned host staging).
 int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
            mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
            const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
@@ -1304,13 +1503,36 @@ int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt,
   if (st) {
     std::memset(st, 0, sizeof(*st));
   }
-  int rc = ensure(ws, P.n, P.nnz, P.G);
-  if (rc) return rc;
+  Workspace caller_ws;
+  Workspace* W = &ws;
+  CallerBlock cb;
+  int rc = MC_OK;
+  if (o.workspace) {
+    rc = ws.ensure_host();
+    if (rc) return rc;
+    caller_ws.host_owned = false;
+    caller_ws.ctl_host = ws.ctl_host;
+    caller_ws.sweep_host = ws.sweep_host;
+    caller_ws.sw_args_host = ws.sw_args_host;
+    caller_ws.sw_run_host = ws.sw_run_host;
+    caller_ws.sw_status_host = ws.sw_status_host;
+    rc = carve_caller(caller_ws, o.workspace, (size_t)o.workspace_bytes, P.n, P.nnz, P.G);
+    if (rc) return rc;
+    cb.base = (char*)o.workspace;
+    cb.bytes = (size_t)o.workspace_bytes;
+    cb.core = workspace_bytes(P.n, P.nnz, P.G);
+    W = &caller_ws;
+  } else {
+    rc = ensure(ws, P.n, P.nnz, P.G);
+    if (rc) return rc;
+  }
   hipStream_t s = (hipStream_t)stream;
   Timer& T = timer();
   T.on = o.timing != 0;
   T.s = s;
-  Solver sv{ws, s, o};
+  Solver sv{*W, s, o};
+  sv.cb = cb;
+  sv.stats_out = st;
   sv.debug_labels = debug_labels;
   sv.debug_lhat = debug_lhat;
   sv.lhat_in = lhat_in;
@@ -1323,13 +1545,15 @@ int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt,
   return rc;
 }
 
-// The library's own entry points share one cached workspace per process.
+// The library's own entry points: the stream's cached workspace.
 int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
         mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
         const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
-  std::lock_guard<std::mutex> lock(api_mutex());
-  return run_on(global_ws(), P, stream, opt, lambdas, side, st, debug_labels, debug_lhat, lhat_in,
-                viecut_levels);
+  Slot* sl = nullptr;
+  int rc = slot_for(stream, &sl);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(sl->m);
+  return run_on(sl->ws, P, stream, opt, lambdas, side, st, debug_labels, debug_lhat, lhat_in, viecut_levels);
 }
 
 }  // namespace mc
@@ -1345,6 +1569,7 @@ void mc_options_default(mc_options* o) {
   o->eager_blacklist = 1;
   o->lp_sweeps = 2;
   o->pr_triangle_deg = 64;
+  o->sweep_tail = 0;
 }
 
 int mc_mincut(const mc_graph* g, void* stream, const mc_options* opt, int64_t* lambda,
@@ -1456,15 +1681,18 @@ int mc_viecut_bound(const mc_batch* b, void* stream, const mc_options* opt, int6
 int mc_debug_lp_sweep(const mc_graph* g, const int32_t* labels_in, int32_t* labels_out, void* stream) {
   using namespace mc;
   if (!g || !labels_in || !labels_out || g->n < 1 || !g->row_ptr || !g->col || !g->w) return MC_EINVAL;
-  std::lock_guard<std::mutex> lock(api_mutex());
-  Workspace& ws = global_ws();
-  int rc = ensure(ws, g->n, g->nnz, 1);
+  Slot* sl = nullptr;
+  int rc = slot_for(stream, &sl);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(sl->m);
+  Workspace& ws = sl->ws;
+  rc = ensure(ws, g->n, g->nnz, 1);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0, ncu = 0;
   MC_HIP(hipGetDevice(&dev));
   MC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  rc = ensure_vc(ws, g->n, g->nnz, 1);
+  rc = ensure_vc(ws, g->n, g->nnz, 1, CallerBlock{});
   if (rc) return rc;
   MC_HIP(hipMemsetAsync(ws.ctl, 0, sizeof(Ctl), s));
   fill<int32_t>(ws.gid[0], 0, g->n, s);
@@ -1492,9 +1720,12 @@ __global__ void k_row_degrees(int32_t n, const int64_t* rp, const int32_t* col, 
 int mc_debug_pr_tests(const mc_graph* g, void* stream, int64_t lhat, int32_t max_deg, uint8_t* flags) {
   using namespace mc;
   if (!g || !flags || g->n < 1 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w))) return MC_EINVAL;
-  std::lock_guard<std::mutex> lock(api_mutex());
-  Workspace& ws = global_ws();
-  int rc = ensure(ws, g->n, g->nnz, 1);
+  Slot* sl = nullptr;
+  int rc = slot_for(stream, &sl);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(sl->m);
+  Workspace& ws = sl->ws;
+  rc = ensure(ws, g->n, g->nnz, 1);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid(grid_for(g->n, 256, 65536));
@@ -1510,9 +1741,12 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
                       int64_t* row_ptr_out, int32_t* col_out, int32_t* w_out, int64_t* nnz_out) {
   using namespace mc;
   if (!g || !labels || !row_ptr_out || !col_out || !w_out || !nnz_out || n_new < 1) return MC_EINVAL;
-  std::lock_guard<std::mutex> lock(api_mutex());
-  Workspace& ws = global_ws();
-  int rc = ensure(ws, std::max(g->n, n_new), g->nnz, 1);
+  Slot* sl = nullptr;
+  int rc = slot_for(stream, &sl);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(sl->m);
+  Workspace& ws = sl->ws;
+  rc = ensure(ws, std::max(g->n, n_new), g->nnz, 1);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0, ncu = 0;
@@ -1579,8 +1813,16 @@ size_t mc_viecut_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num
 }
 
 void mc_release(void) {
-  std::lock_guard<std::mutex> lock(mc::api_mutex());
-  mc::global_ws().release();
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lock(mc::registry_mutex());
+  auto& r = mc::registry();
+  // the slots stay (another thread may be about to lock one); their memory goes
+  for (auto& kv : r) {
+    if (kv.first.first != dev) continue;
+    std::lock_guard<std::mutex> l2(kv.second->m);  // waits for a call in progress on that stream
+    kv.second->ws.release();
+  }
 }
 
 const char* mc_strerror(int code) {

@@ -8,6 +8,7 @@
 #include "prims.h"
 #include "smallsweep.h"
 #include "sweep.h"
+#include "tail.h"
 #include "lp.h"
 
 namespace mc {
@@ -386,6 +387,12 @@ __global__ void k_side(SideArgs A) {
       if (sid == SWEEP_SID) {
         const int32_t st = (int32_t)(A.fb_rs[c] >> 32);
         s = st >= 1 && st <= k;
+      } else if (sid == TAIL_SID) {
+        // the sweep's visited set and the first pops of tail process f
+        const uint64_t u = A.fb_rs[c];
+        const int32_t st = (int32_t)(u >> 32);
+        const int32_t f = (k >> 20) & 1023, kk = k & 0xFFFFF;
+        s = st >= 1 || ((uint32_t)st == tail_pop(f) && (int32_t)(uint32_t)u <= kk);
       }
       else s = A.claim[c] == sid && A.step[c] <= k;
     } else if (t == REC_DISCONNECTED) {
@@ -399,7 +406,7 @@ __global__ void k_side(SideArgs A) {
 // the small LDS map (mode 1), up to whole_max with the large map (mode 3),
 // larger ones by region scans (mode 2).  Inactive graphs idle (mode 0).
 // Matula's approximation: the round's contraction bound per graph,
-// k = min(lambda-hat, max(1, floor((1/2 - eps) delta))) with eps = ppm / 10^6
+// k = min(lambda-hat, max(1, ceil((1/2 - eps) delta))) with eps = ppm / 10^6
 // and delta the graph's minimum degree (bdeg, before the round clears it).
 __global__ void k_matula_cap(int32_t G, GraphState S, int64_t ppm, int64_t* kcap) {
   for (int64_t g = gtid(); g < G; g += gstride()) {
@@ -408,7 +415,8 @@ __global__ void k_matula_cap(int32_t G, GraphState S, int64_t ppm, int64_t* kcap
     int64_t k = lam;
     if (bd != ~0ull) {
       const int64_t delta = (int64_t)(bd >> 32);
-      const int64_t m = delta * (1000000 - 2 * ppm) / 2000000;
+      // contract q(e) >= (1/2 - eps) delta: for integer q, the ceiling
+      const int64_t m = (delta * (1000000 - 2 * ppm) + 1999999) / 2000000;
       k = min(lam, max((int64_t)1, m));
     }
     kcap[g] = k;
@@ -752,11 +760,23 @@ __global__ void k_sweep_report(const SweepArgs* args, int32_t k, GraphState S) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
     const MC_GLOBAL SweepCtl* c = (const MC_GLOBAL SweepCtl*)args[i].ctl;
     const int32_t g = args[i].g;
-    if (c->best_alpha < S.lhat[g]) {
-      S.fb_k[g] = c->best_step;
-      atomic_min_u64(S.balpha + g, ((uint64_t)c->best_alpha << 32) | (uint32_t)SWEEP_SID);
+    // the best prefix of the sweep, or of a tail process (record k: the
+    // process in bits 20..29, its pops in the low 20 bits)
+    int64_t a = c->best_alpha;
+    uint32_t sid = (uint32_t)SWEEP_SID;
+    int32_t k = c->best_step;
+    const uint64_t tb = c->tail_best;
+    if (tb != ~0ull && (int64_t)(tb >> 32) < a) {
+      const int32_t f = (int32_t)(uint32_t)tb;
+      a = (int64_t)(tb >> 32);
+      sid = (uint32_t)TAIL_SID;
+      k = (f << 20) | c->tail_k[f];
     }
-    atomicAdd(S.ucount + g, c->cap_tail);  // every crossing vertex entered the FIFO once
+    if (a < S.lhat[g]) {
+      S.fb_k[g] = k;
+      atomic_min_u64(S.balpha + g, ((uint64_t)a << 32) | sid);
+    }
+    atomicAdd(S.ucount + g, min(c->cap_tail, args[i].ng));  // one union per crossing recorded
   }
 }
 
@@ -810,7 +830,7 @@ __global__ void k_update_alpha(int32_t G, GraphState S, const int32_t* scan_k, C
       S.lhat[g] = a;
       S.rec_type[g] = REC_ALPHA;
       S.rec_id[g] = sid;
-      S.rec_k[g] = sid == SWEEP_SID ? S.fb_k[g] : scan_k[sid];
+      S.rec_k[g] = (sid == SWEEP_SID || sid == TAIL_SID) ? S.fb_k[g] : scan_k[sid];
       atomicAdd(&ctl->improved, 1);
     }
   }
@@ -1004,6 +1024,44 @@ __global__ void __launch_bounds__(256) k_merge(int64_t m, const uint64_t* __rest
     int32_t s = wave_segsum<int64_t, int32_t>(p, ok ? vals[i] : 0, ok, tail);
     if (ok && tail) atomicAdd(nw + p, s);
   }
+}
+
+// Opt-in symmetry check of the input.  Every entry (u, v, c) with u != v
+// becomes the key of its unordered pair {u, v} with +c when it sits in the
+// row of the smaller end and -c otherwise; sorted and summed per key
+// (k_merge), a symmetric graph leaves every sum 0.
+__global__ void __launch_bounds__(256) k_sym_emit(int64_t nnz, const int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ w, int bits,
+                                                  uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                  Ctl* ctl) {
+  const int lane = lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63); base < nnz;
+       base += (int64_t)gridDim.x * 256) {  // wave-uniform bound
+    const int64_t e = base + lane;
+    const bool ok = e < nnz;
+    const int64_t ec = ok ? e : base;
+    const int32_t u = src[ec], v = col[ec], c = w[ec];
+    const bool keep = ok && u != v;
+    const uint64_t m = ballot(keep);
+    if (m == 0) continue;
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)popc64(m));
+    at = bcast(at, 0);
+    if (keep) {
+      const int64_t i = (int64_t)at + popc64(m & lanemask_lt());
+      const uint32_t lo = (uint32_t)min(u, v), hi = (uint32_t)max(u, v);
+      keys[i] = ((uint64_t)lo << bits) | hi;
+      vals[i] = u < v ? c : -c;
+    }
+  }
+}
+
+// Any nonzero per-pair sum left by the symmetry check sets ctl->asym.
+__global__ void k_sym_nonzero(int64_t m, const int32_t* sums, Ctl* ctl) {
+  bool bad = false;
+  for (int64_t i = gtid(); i < m; i += gstride()) bad |= sums[i] != 0;
+  if (ballot(bad) && lane_id() == 0) atomicOr(&ctl->asym, 1);
 }
 
 // row_ptr of the merged graph: rp[a] = first entry with source >= a.

@@ -38,6 +38,7 @@ struct ServerRequest {
   std::vector<uint8_t> side;
   std::chrono::steady_clock::time_point t_submit, t_start, t_done;
   int32_t batch_graphs = 0, lane = -1;
+  bool claimed = false;  // a waiter holds the ticket (a second waiter gets MC_ESTATE)
 };
 
 // Device and pinned host buffers of one lane, grown to the largest batch.
@@ -319,9 +320,12 @@ int mc_server_wait(mc_server* srv, uint64_t ticket, int64_t* lambda, uint8_t* si
   {
     std::unique_lock<std::mutex> lk(S->m);
     auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return MC_ESTATE;
+    if (it == S->reqs.end() || it->second->claimed) return MC_ESTATE;
     mc::ServerRequest* p = it->second.get();
+    p->claimed = true;  // only this waiter erases it, so p stays valid while waiting
     S->cv_done.wait(lk, [&] { return p->rc != 1; });
+    // submits may have rehashed the map while this thread waited
+    it = S->reqs.find(ticket);
     r = std::move(it->second);
     S->reqs.erase(it);
   }

@@ -29,8 +29,10 @@ constexpr int SWEEP_THREADS = 1024;
 constexpr int SWEEP_BUCKETS = 4096;  // bucket queue for keys below the cap
 constexpr int32_t SWEEP_SID = 0x7FFFFFFF;
 constexpr int RB_TILE = 4096;        // vertices per workgroup in the rebuild
+constexpr int SWEEP_PHASES = 8;      // per-phase step counters kept
+constexpr int TAIL_MAX_FORKS = 1024; // concurrent scans of a sweep's tail
 
-enum : int32_t { SW_RUNNING = 0, SW_DONE = 1, SW_BIG = 2 };
+enum : int32_t { SW_RUNNING = 0, SW_DONE = 1, SW_BIG = 2, SW_TAIL = 3 };
 
 struct SweepCtl {
   int32_t cap_head, cap_tail;  // capped FIFO: [head, tail) is the pending batch
@@ -45,11 +47,22 @@ struct SweepCtl {
   int64_t batch_internal;      // grid-wide batch: 2 w(inside)
   int64_t batch_deg;           // grid-wide batch: sum of row lengths
   int32_t singles, batches, big_batches, rebuilds;
+  // per phase (phase k: the sequential kernel's steps after k grid-wide
+  // batches, the last phase holding all later ones): single pops, batches
+  // and crossings (one union each) made by those steps
+  int32_t ph_singles[SWEEP_PHASES], ph_batches[SWEEP_PHASES], ph_cross[SWEEP_PHASES];
+  // the tail's concurrent scans (tail.h): list length and cursor, pops, and
+  // the best prefix cut (alpha << 32 | process)
+  int32_t tail_total, tail_cursor, tail_pops, tail_forks;
+  uint64_t tail_best;
+  int64_t tail_rows;           // entries of the rows the tail relaxed
+  int64_t seq_rows;            // ... and the sequential kernel
   uint64_t bitmap[SWEEP_BUCKETS / 64];
   int32_t head[SWEEP_BUCKETS];     // recent pushes (lists through the pool)
   int32_t seg_cur[SWEEP_BUCKETS];  // rebuilt segments of seg[]: unread part
   int32_t seg_end[SWEEP_BUCKETS];
   int32_t fill[SWEEP_BUCKETS];     // rebuild scratch
+  int32_t tail_k[TAIL_MAX_FORKS];  // per tail process: pops of its best prefix
 };
 
 struct SweepArgs {
@@ -77,6 +90,8 @@ struct SweepArgs {
   int64_t big_entries;  // ... and so do batches whose rows hold more entries
   int32_t start;     // the first vertex (global id)
   int32_t g;         // the graph
+  int32_t tail_min;  // hand the tail to concurrent scans once at most tail_max
+  int32_t tail_max;  // and at least tail_min vertices are left (0: never)
 };
 
 // The kernels that read their arguments from the per-graph argument array
@@ -99,6 +114,7 @@ struct SweepDev {
   int32_t shift, nwords, nb, big;
   int64_t big_entries;
   int32_t start, g;
+  int32_t tail_min, tail_max;
 };
 
 __device__ __forceinline__ SweepDev dev_view(const SweepArgs& a) {
@@ -106,7 +122,8 @@ __device__ __forceinline__ SweepDev dev_view(const SweepArgs& a) {
                   (const MC_GLOBAL int64_t*)a.cdeg, (MC_GLOBAL int32_t*)a.parent, (MC_GLOBAL uint64_t*)a.rs,
                   (MC_GLOBAL int32_t*)a.capq, (MC_GLOBAL int32_t*)a.capx,
                   (MC_GLOBAL int2*)a.pool, a.pool_cap, (MC_GLOBAL int32_t*)a.seg, (MC_GLOBAL SweepCtl*)a.ctl,
-                  a.v0, a.ng, a.lam, a.shift, a.nwords, a.nb, a.big, a.big_entries, a.start, a.g};
+                  a.v0, a.ng, a.lam, a.shift, a.nwords, a.nb, a.big, a.big_entries, a.start, a.g,
+                  a.tail_min, a.tail_max};
 }
 
 // The packed (r, stamp) word: r never exceeds the vertex's weighted degree
@@ -290,6 +307,11 @@ __global__ void k_sweep_init(const SweepArgs* args) {
     A.ctl->seg_end[i] = 0;
   }
   for (int64_t i = tid; i < SWEEP_BUCKETS / 64; i += nth) A.ctl->bitmap[i] = 0;
+  for (int64_t i = tid; i < SWEEP_PHASES; i += nth) {
+    A.ctl->ph_singles[i] = 0;
+    A.ctl->ph_batches[i] = 0;
+    A.ctl->ph_cross[i] = 0;
+  }
   if (tid == 0) {
     MC_GLOBAL SweepCtl* c = A.ctl;
     c->cap_head = c->cap_tail = 0;
@@ -303,6 +325,9 @@ __global__ void k_sweep_init(const SweepArgs* args) {
     c->batch_sum = c->batch_internal = 0;
     c->batch_deg = 0;
     c->singles = c->batches = c->big_batches = c->rebuilds = 0;
+    c->tail_total = c->tail_cursor = c->tail_pops = c->tail_forks = 0;
+    c->tail_best = ~0ull;
+    c->tail_rows = c->seq_rows = 0;
   }
 }
 
@@ -543,7 +568,7 @@ __device__ __forceinline__ int64_t wave_relax_known(const SA& A, const SweepQ& q
 // the next command.  Exits with SW_DONE (queue empty) or SW_BIG (a batch
 // larger than A.big, or with more than A.big_entries entries in its rows, is
 // pending; cap_head..cap_tail untouched).
-enum : int32_t { CMD_EXIT_DONE = 0, CMD_BATCH = 1, CMD_EXIT_BIG = 2, CMD_SINGLE = 3 };
+enum : int32_t { CMD_EXIT_DONE = 0, CMD_BATCH = 1, CMD_EXIT_BIG = 2, CMD_SINGLE = 3, CMD_EXIT_TAIL = 4 };
 
 __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* args, const int32_t* run) {
   // one workgroup per graph still running: graph run[blockIdx.x]
@@ -574,7 +599,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
   for (int i = threadIdx.x; i < SWEEP_BUCKETS / 64; i += SWEEP_THREADS) l_bitmap[i] = c->bitmap[i];
   // bookkeeping of thread 0 (the only thread that closes batches)
   int32_t step = 0, visited = 0, best_step = 0, singles = 0, batches = 0;
-  int64_t alpha = 0, best_alpha = 0;
+  int32_t singles0 = 0, batches0 = 0, tail0 = 0;
+  int64_t alpha = 0, best_alpha = 0, seq_rows = 0;
   if (threadIdx.x == 0) {
     l_cap_head = c->cap_head;
     l_cap_tail = c->cap_tail;
@@ -588,6 +614,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     best_step = c->best_step;
     singles = c->singles;
     batches = c->batches;
+    singles0 = singles;
+    batches0 = batches;
+    tail0 = c->cap_tail;
   }
   __syncthreads();
   // q: steps shared by all waves; qf: wave-0 steps, which also mirror new
@@ -601,6 +630,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
   qf.sc_hdr = l_sc_hdr;
   // FIFO entries appended before this launch are not in the ring
   const int32_t ring_lo = ld_relaxed(&l_cap_tail);
+  const bool tail_ok = A.tail_min > 0 && A.shift == 0 && c->big_batches > 0;
   // FIFO entry i (below tail) and its row bounds
   auto fifo_row = [&](int32_t i, int32_t tail, int64_t& a, int64_t& b) -> int32_t {
     if (i >= ring_lo && i >= tail - SWEEP_RING) {
@@ -645,6 +675,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           }
           entries = wave_sum_i64_dpp(entries);
           if (entries > A.big_entries) { cmd = CMD_EXIT_BIG; break; }
+          if (lane == 0) seq_rows += entries;
           if (size > FAST_BATCH || entries > FAST_DEG) {
             if (lane == 0) { sh_h = h; sh_t = t; sh_stamp = stamp; step = stamp; batches += 1; }
             cmd = CMD_BATCH;
@@ -671,11 +702,18 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         } else {
+          // below the cap after a grid-wide batch with few vertices left:
+          // the tail goes to concurrent scans (tail.h)
+          if (tail_ok) {
+            const int32_t left = A.ng - bcast(visited, 0);
+            if (left >= A.tail_min && left <= A.tail_max) { cmd = CMD_EXIT_TAIL; break; }
+          }
           PopRow pr;
           const int32_t x = sweep_pop_wave0(A, qf, pr);
           if (x < 0) { cmd = CMD_EXIT_DONE; break; }
           const int64_t ra = pr.ra, rb = pr.rb;
           const int64_t deg = rb - ra;
+          if (lane == 0) seq_rows += deg;
           int64_t sum = 0;
           if (lane == 0) {
             st_relaxed(rs_stamp_ptr(A.rs + x), stamp);
@@ -702,7 +740,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     __threadfence_block();
     __syncthreads();
     const int cmd = sh_cmd;
-    if (cmd == CMD_EXIT_DONE || cmd == CMD_EXIT_BIG) { exit_cmd = cmd; break; }
+    if (cmd == CMD_EXIT_DONE || cmd == CMD_EXIT_BIG || cmd == CMD_EXIT_TAIL) { exit_cmd = cmd; break; }
     // a wide step shared by all waves
     const int32_t stamp = sh_stamp;
     int64_t sum = 0, internal = 0;
@@ -818,7 +856,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     c->best_step = best_step;
     c->singles = singles;
     c->batches = batches;
-    c->status = exit_cmd == CMD_EXIT_DONE ? SW_DONE : SW_BIG;
+    c->seq_rows += seq_rows;
+    const int ph = min(c->big_batches, SWEEP_PHASES - 1);
+    c->ph_singles[ph] += singles - singles0;
+    c->ph_batches[ph] += batches - batches0;
+    c->ph_cross[ph] += l_cap_tail - tail0;
+    c->status = exit_cmd == CMD_EXIT_DONE ? SW_DONE : exit_cmd == CMD_EXIT_TAIL ? SW_TAIL : SW_BIG;
   }
 }
 
@@ -831,7 +874,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
 // smaller root through its own entry.
 __global__ void k_sweep_unite(const SweepArgs* args) {
   const SweepDev A = dev_view(args[blockIdx.y]);
-  const int32_t n = A.ctl->cap_tail;
+  const int32_t n = min(A.ctl->cap_tail, A.ng);  // the tail may count pairs it had no room for
   const int lane = lane_id();
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
        base += (int64_t)gridDim.x * blockDim.x) {  // wave-uniform bound
@@ -861,12 +904,12 @@ __global__ void k_sweep_unite(const SweepArgs* args) {
 // Per graph: status, FIFO bounds and row entries of the pending batch, for
 // the host (one small copy instead of one per graph).
 struct SweepStatus {
-  int32_t status, cap_head, cap_tail, pad;
+  int32_t status, cap_head, cap_tail, visited;
 };
 __global__ void k_sweep_status(const SweepArgs* args, const int32_t* run, int32_t k, SweepStatus* out) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
     const MC_GLOBAL SweepCtl* c = (const MC_GLOBAL SweepCtl*)args[run[i]].ctl;
-    out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, 0};
+    out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, c->visited};
   }
 }
 

@@ -27,6 +27,7 @@ RECIPES = {
     "chung_lu_2^19_8core": lambda: gg.chung_lu_4m_8core(19),
     "rmat_24_10core": gg.rmat_24_10core,
     "rmat_20_10core": lambda: gg.rmat_24_10core(20, 24),
+    "bridged_8cores_2^21_k3": lambda: gg.bridged_8cores(21, 3),
 }
 
 

@@ -1,6 +1,6 @@
 """GPU tests of Matula's (2+eps)-approximation mode (approx_ppm): the answer
 is a real cut (the side realises it) between lambda and the bound
-(lambda + 1) / (1/2 - eps); where lambda equals the minimum degree it is
+lambda / (1/2 - eps); where lambda equals the minimum degree it is
 exact; it never needs more rounds than the exact loop.  Several answers are
 correct, so the oracle's own approximation is not compared value for value;
 lambda comes from the exact oracle."""
@@ -29,7 +29,8 @@ def _gpu():
 
 
 def bound(lam, ppm):
-    return (lam + 1) * 2_000_000 // (1_000_000 - 2 * ppm)
+    # lambda / (1/2 - eps), the guarantee of the paper's threshold
+    return lam * 2_000_000 // (1_000_000 - 2 * ppm)
 
 
 def _check_all(graphs, exact, vo, lams, sides, ppm):
@@ -52,6 +53,20 @@ def test_random_graphs_packed(ppm):
     announce("matula random", ppm, len(graphs))
     lams, sides, st = mc.mincut_batched(rp, col, w, vo, approx_ppm=ppm)
     _check_all(graphs, exact, vo, lams, sides, ppm)
+
+
+def test_fixtures_where_a_floor_threshold_breaks_the_bound():
+    import paper_1808_05458_amd as mc
+    fx = json.load(open(os.path.join(GOLDEN, "matula_examples.json")))["examples"]
+    graphs = [gg.from_edges(ex["n"], ex["edges"], ex["weights"]) for ex in fx]
+    exact = [oracle.bruteforce(g)[0] for g in graphs]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    for ppm in sorted({ex["ppm"] for ex in fx}):
+        announce("matula fixtures", ppm)
+        for seed in (1, 2, 3):
+            lams, sides, st = mc.mincut_batched(rp, col, w, vo, approx_ppm=ppm, seed=seed)
+            _check_all(graphs, exact, vo, lams, sides, ppm)
 
 
 def test_batch_sample_within_bound():

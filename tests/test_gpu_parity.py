@@ -87,6 +87,9 @@ def test_medium_graphs_against_noi():
                                   dict(whole_max=16, scan_mode=1, eager_blacklist=0),
                                   dict(whole_max=16, sweep_handoff=1),
                                   dict(whole_max=16, sweep_handoff=3, use_pr=0),
+                                  dict(whole_max=16, sweep_handoff=1, sweep_tail=1),
+                                  dict(whole_max=16, sweep_handoff=1, sweep_tail=1, use_pr=0),
+                                  dict(whole_max=16, sweep_tail=-1),
                                   dict(scan_mode=2), dict(scan_mode=2, max_pops=3),
                                   dict(scan_mode=2, eager_blacklist=0, use_pr=0)])
 def test_planted_4096_options(opts):
@@ -106,6 +109,8 @@ def test_region_scans_on_power_law_core():
     ref, _, _ = oracle.noi(g, 1)
     for opts in [dict(whole_max=64), dict(whole_max=64, use_pr=0),
                  dict(whole_max=64, sweep_handoff=4),
+                 dict(whole_max=64, sweep_tail=-1), dict(whole_max=64, sweep_tail=1, use_pr=0),
+                 dict(whole_max=64, sweep_handoff=4, sweep_tail=1),
                  dict(whole_max=64, scan_mode=1), dict(whole_max=64, scan_mode=1, eager_blacklist=0),
                  dict(whole_max=64, scan_mode=1, max_pops=50),
                  dict(whole_max=64, scan_mode=1, use_pr=0)]:
@@ -237,11 +242,12 @@ def test_sweep_on_weighted_graphs_with_wide_buckets():
 def test_sweep_on_larger_power_law_graph():
     g = gg.chung_lu(29, 200000, 2.5, 16.0, 1, 1, kcore=5, lcc=True)
     ref, _, _ = oracle.noi(g, 1)
-    announce("chung_lu 200000 5-core", g.n, g.m, ref)
-    lam, side, st = solve(g)
-    assert lam == ref
-    check_side(g, lam, side)
-    assert st["rounds"] <= 6
+    for opts in [dict(), dict(sweep_tail=-1), dict(sweep_tail=1, use_pr=0)]:
+        announce("chung_lu 200000 5-core", g.n, g.m, ref, opts)
+        lam, side, st = solve(g, **opts)
+        assert lam == ref, opts
+        check_side(g, lam, side)
+        assert st["rounds"] <= 6
 
 
 def _round_is_sound(graphs, margins, **opts):
@@ -329,3 +335,71 @@ def test_contraction_kernels_equal_cpu_contraction():
             assert np.array_equal(rpo.cpu().numpy(), h.row_ptr)
             assert np.array_equal(colo.cpu().numpy(), h.col)
             assert np.array_equal(wo.cpu().numpy(), h.w)
+
+
+def _two_blobs(rng):
+    """Two dense random blobs (weights 1..50) joined by one to three light
+    edges: a minimum cut well below the minimum degree."""
+    a, b = int(rng.integers(3, 9)), int(rng.integers(3, 9))
+    e, w = [], []
+    for off, k in ((0, a), (a, b)):
+        for i in range(k):
+            for j in range(i + 1, k):
+                if rng.random() < 0.8:
+                    e.append((off + i, off + j))
+                    w.append(int(rng.integers(1, 51)))
+        for i in range(k - 1):  # a path keeps each blob connected
+            e.append((off + i, off + i + 1))
+            w.append(int(rng.integers(10, 51)))
+    for _ in range(int(rng.integers(1, 4))):
+        e.append((int(rng.integers(0, a)), a + int(rng.integers(0, b))))
+        w.append(int(rng.integers(1, 6)))
+    return gg.from_edges(a + b, e, w)
+
+
+_BLOCK_VARIANTS = [dict(), dict(use_pr=0), dict(whole_max=4, scan_mode=1), dict(whole_max=4, scan_mode=1, use_pr=0),
+                   dict(scan_mode=2), dict(scan_mode=2, use_pr=0), dict(whole_max=4, sweep_handoff=1),
+                   dict(whole_max=4, sweep_handoff=1, use_pr=0),
+                   dict(whole_max=4, sweep_handoff=1, sweep_tail=1),
+                   dict(whole_max=4, sweep_handoff=1, sweep_tail=1, use_pr=0),
+                   dict(whole_max=4, sweep_handoff=1, sweep_tail=-1, use_pr=0),
+                   dict(pr_triangle_deg=-64)]
+
+
+@pytest.mark.parametrize("opts", _BLOCK_VARIANTS, ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()) or "default")
+def test_round_blocks_keep_every_minimum_cut(opts):
+    """Per-step soundness of one round (section "Parallel CAPFOREST", Lemma 2;
+    the Padberg-Rinaldi conditions): wherever the bound used exceeds lambda,
+    every pair of vertices that the round puts in one block has pair
+    connectivity above lambda (no minimum cut is cut), and with the scans
+    alone (no tests) at least the bound (each union has q(e) >= the bound
+    and q(e) is at most the pair's connectivity)."""
+    import paper_1808_05458_amd as mc
+    rng = np.random.default_rng(4242 + len(opts))
+    graphs = [random_graph(rng, int(rng.integers(4, 17)), float(rng.uniform(0.2, 0.9)),
+                           int(rng.choice([1, 5, 50]))) for _ in range(80)]
+    graphs += [_two_blobs(rng) for _ in range(80)]  # lambda below the minimum degree
+    lams = [oracle.bruteforce(g)[0] for g in graphs]
+    conn = [oracle.pair_connectivity(g) for g in graphs]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    checked = 0
+    for margin in (None, 1, 7):
+        lin = None if margin is None else [l + margin for l in lams]
+        announce("round blocks", opts, margin)
+        labels, used = mc.debug_first_round(rp, col, w, vo, lhat_in=lin, **opts)
+        lab = labels.cpu().numpy()
+        for i, g in enumerate(graphs):
+            if lams[i] >= used[i]:
+                continue
+            b = lab[vo[i]:vo[i + 1]]
+            same = b[:, None] == b[None, :]
+            np.fill_diagonal(same, False)
+            c = conn[i][same]
+            if c.size == 0:
+                continue
+            checked += 1
+            assert c.min() > lams[i], (i, margin, opts, int(c.min()), lams[i])
+            if opts.get("use_pr", 1) == 0:
+                assert c.min() >= used[i], (i, margin, opts, int(c.min()), int(used[i]))
+    assert checked >= 100, checked

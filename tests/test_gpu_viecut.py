@@ -109,8 +109,10 @@ def test_viecut_hand_examples():
         else:
             e = np.array(ex["edges"])
             graphs.append(gg.from_edges(ex["n"], e[:, :2], e[:, 2]))
-    b = _bounds_equal(graphs)
-    assert list(b) == [ex["bound"] for ex in spec["bounds"]]
+    for stop in sorted({ex.get("stop_n", 2) for ex in spec["bounds"]}):
+        idx = [i for i, ex in enumerate(spec["bounds"]) if ex.get("stop_n", 2) == stop]
+        b = _bounds_equal([graphs[i] for i in idx], stop=stop)
+        assert list(b) == [spec["bounds"][i]["bound"] for i in idx]
 
 
 def test_viecut_bound_batch_recipe():

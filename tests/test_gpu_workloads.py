@@ -68,3 +68,26 @@ def test_rmat_scale20_10core():
 def test_rmat_scale24_10core():
     # about 1.5 minutes of generation on the host, then the solve
     _single("rmat_24_10core", gg.rmat_24_10core)
+
+
+@pytest.fixture(scope="module")
+def bridged():
+    gold = _gold("bridged_8cores_2^21_k3")
+    g = gg.bridged_8cores(21, 3)
+    assert (g.n, g.m) == (gold["n"], gold["m"]), "generator drifted"
+    return g, gold
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("tail", [0, -1], ids=["tail_scans", "sequential_tail"])
+def test_bridged_8cores_lambda_below_min_degree(bridged, tail):
+    # two Chung-Lu 8-cores (about 2M vertices each) joined by 3 bridges: the
+    # minimum cut (3) lies below the minimum degree (8), so the full-graph
+    # sweeps, their grid-wide batches and the tail must keep the bridges
+    # apart from everything else
+    g, gold = bridged
+    assert int(np.diff(g.row_ptr).min()) == 8 and gold["lambda"] == 3
+    announce("bridged_8cores", g.n, g.m, tail)
+    lam, side, st = solve(g, sweep_tail=tail)
+    assert lam == gold["lambda"]
+    check_side(g, lam, side)
