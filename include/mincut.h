@@ -52,7 +52,8 @@ enum {
   MC_EBUSY = -6,     /* server admission full (non-blocking submit) */
   MC_ESTATE = -7,    /* unknown ticket or server stopped */
   MC_EINTERNAL = -8, /* a round made no progress (never expected; reported, not looped) */
-  MC_EMISMATCH = -9  /* the autotuner's launch shapes disagreed on a lambda (never expected) */
+  MC_EMISMATCH = -9, /* the autotuner's launch shapes disagreed on a lambda (never expected) */
+  MC_ETOOBIG = -10   /* mc_mincut_noalloc: the graph does not fit its fixed workspace */
 };
 
 typedef struct mc_graph {
@@ -302,6 +303,21 @@ size_t mc_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs
 /* Additional device bytes held once the clustering bound has run
  * (use_viecut or mc_viecut_bound): two level graphs and their labels. */
 size_t mc_viecut_workspace_bytes(int32_t n_total, int64_t nnz_total, int32_t num_graphs);
+
+/* For callers that cannot allocate device or pinned host memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): mc_mincut with side, lambda and options as there, but the
+ * workspace is a fixed 64 MiB array in the library's code object (one per
+ * device, held until the process ends) and the host staging is static, so
+ * the call allocates nothing (no hipMalloc, hipHostMalloc, hipFree, no
+ * event).  Limits: mc_workspace_bytes(n, nnz, 1) <= 64 MiB (else
+ * MC_ETOOBIG, before any device work); opt->use_viecut and opt->workspace
+ * must be 0 (else MC_EINVAL); opt->timing is ignored.  Every call on a
+ * device uses that device's one array: calls on one device take turns (a
+ * lock), and the array keeps the last call's contents, which no call reads
+ * before writing.  Other errors as mc_mincut. */
+int mc_mincut_noalloc(const mc_graph* g, void* stream, const mc_options* opt, int64_t* lambda,
+                      uint8_t* side);
 
 /* Free the cached workspaces of every stream of the current device
  * (waiting for a call in progress on one to finish). */

@@ -28,6 +28,7 @@ MC_OK, MC_EINVAL, MC_ENOCUT, MC_EOVERFLOW, MC_ENOMEM, MC_EHIP, MC_EBUSY, MC_ESTA
     0, -1, -2, -3, -4, -5, -6, -7)
 MC_EINTERNAL = -8
 MC_EMISMATCH = -9
+MC_ETOOBIG = -10
 
 
 def build() -> str:
@@ -134,6 +135,8 @@ def _load():
     lib.mc_options_default.restype = None
     lib.mc_mincut.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_mincut.restype = ctypes.c_int
+    lib.mc_mincut_noalloc.argtypes = [vp, vp, vp, vp, vp]
+    lib.mc_mincut_noalloc.restype = ctypes.c_int
     lib.mc_mincut_batched.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_mincut_batched.restype = ctypes.c_int
     lib.mc_tune_batched.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
@@ -307,6 +310,28 @@ def mincut(row_ptr, col, w, *, want_side: bool = True, stream=None, opts: Option
     if rc != MC_OK:
         raise MincutError(rc, "mc_mincut")
     return int(lam.value), side, st.as_dict()
+
+
+def mincut_noalloc(row_ptr, col, w, side=None, *, stream=None, opts: Optional[Options] = None, **kw):
+    """mc_mincut_noalloc: lambda of one graph (device tensors), solved in the
+    library's fixed workspace.  `side`, if given, is a preallocated uint8
+    device tensor of at least n entries that receives the side."""
+    import torch
+    lib = _load()
+    n = row_ptr.numel() - 1
+    g = Graph(n, col.numel(), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+              _dev_ptr(col, torch.int32, "col"), _dev_ptr(w, torch.int32, "w"))
+    o = opts if opts is not None else options(**kw)
+    lam = ctypes.c_int64(-1)
+    sp = None
+    if side is not None:
+        if side.numel() < n:
+            raise ValueError("side must hold n entries")
+        sp = _dev_ptr(side, torch.uint8, "side")
+    rc = lib.mc_mincut_noalloc(ctypes.byref(g), _stream(stream), ctypes.byref(o), ctypes.byref(lam), sp)
+    if rc != MC_OK:
+        raise MincutError(rc, "mc_mincut_noalloc")
+    return int(lam.value)
 
 
 def mincut_batched(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool = True,

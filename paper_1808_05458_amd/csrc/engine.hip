@@ -1545,6 +1545,36 @@ int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt,
   return rc;
 }
 
+// ------------------------------------------------------------ no allocation
+// mc_mincut_noalloc's workspace: a fixed array in the code object, one copy
+// per device, held until the process ends.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device
+// (the array's name is a host-side stand-in, not a device address).
+constexpr size_t NOALLOC_BYTES = 64ull << 20;
+constexpr int NOALLOC_DEVICES = 16;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+// Pageable host staging for the same calls (no pinned allocation).
+struct NoAllocHost {
+  Ctl ctl;
+  SweepCtl sweep;
+  SweepArgs args[MAX_SWEEPS];
+  int32_t run[MAX_SWEEPS];
+  SweepStatus status[MAX_SWEEPS];
+};
+
+struct NoAllocDevice {
+  std::mutex m;          // calls on one device take turns on its array
+  void* ptr = nullptr;   // the device's copy of `scratch`
+  bool ready = false;
+  NoAllocHost host;
+};
+
+NoAllocDevice* noalloc_device(int dev) {
+  static NoAllocDevice devices[NOALLOC_DEVICES];
+  return dev >= 0 && dev < NOALLOC_DEVICES ? &devices[dev] : nullptr;
+}
+
 // The library's own entry points: the stream's cached workspace.
 int run(const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
         mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
@@ -1825,6 +1855,44 @@ void mc_release(void) {
   }
 }
 
+int mc_mincut_noalloc(const mc_graph* g, void* stream, const mc_options* opt, int64_t* lambda, uint8_t* side) {
+  using namespace mc;
+  if (!g || !lambda) return MC_EINVAL;
+  if (g->n < 2) return MC_ENOCUT;
+  if (g->n > (1 << 30) - 1 || g->nnz < 0 || g->nnz >= (int64_t)UINT32_MAX) return MC_EINVAL;
+  mc_options o;
+  mc_options_default(&o);
+  if (opt) o = *opt;
+  // the clustering bound's level graphs and event timing would allocate
+  if (o.use_viecut || o.workspace) return MC_EINVAL;
+  o.timing = 0;
+  if (workspace_bytes(g->n, g->nnz, 1) > NOALLOC_BYTES) return MC_ETOOBIG;
+  int dev = 0;
+  MC_HIP(hipGetDevice(&dev));
+  NoAllocDevice* D = noalloc_device(dev);
+  if (!D) return MC_EINVAL;
+  std::lock_guard<std::mutex> lock(D->m);
+  if (!D->ready) {
+    // once per device, with that device current
+    void* p = nullptr;
+    MC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    D->ptr = p;
+    D->ready = true;
+  }
+  Workspace lend;  // pageable staging; run_on carves the device arrays from D->ptr
+  lend.host_owned = false;
+  lend.ctl_host = &D->host.ctl;
+  lend.sweep_host = &D->host.sweep;
+  lend.sw_args_host = D->host.args;
+  lend.sw_run_host = D->host.run;
+  lend.sw_status_host = D->host.status;
+  o.workspace = D->ptr;
+  o.workspace_bytes = NOALLOC_BYTES;
+  int64_t voff[2] = {0, g->n};
+  Problem P{1, g->n, g->nnz, g->row_ptr, g->col, g->w, voff};
+  return run_on(lend, P, stream, &o, lambda, side, nullptr);
+}
+
 const char* mc_strerror(int code) {
   switch (code) {
     case MC_OK: return "ok";
@@ -1837,6 +1905,7 @@ const char* mc_strerror(int code) {
     case MC_ESTATE: return "unknown ticket or stopped server";
     case MC_EINTERNAL: return "internal error: a round made no progress";
     case MC_EMISMATCH: return "internal error: launch shapes gave different results";
+    case MC_ETOOBIG: return "graph too large for the fixed 64 MiB workspace of mc_mincut_noalloc";
     default: return "unknown error";
   }
 }
