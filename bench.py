@@ -347,8 +347,24 @@ def roofline_of(classes, steps, traffic_file):
             e["counter_bytes_per_launch"] = measured[c["name"]]
             e["counter_GBps"] = round(measured[c["name"]] / (c["ms"] / 1000.0 / c["launches"]) / 1e9, 1)
         return e
+    # the hot path's kernel classes: algorithmic bytes of all their launches
+    # over all their device time
+    groups = {"capforest": ("k_sweep_seq", "k_sweep_tail", "k_sweep_big_relax", "k_sweep_big_mark",
+                            "sweep_batch_prep", "sweep_rebuild", "k_sweep_unite", "k_small_sweep",
+                            "capforest_region", "capforest_whole", "k_union_pairs"),
+              "contraction": ("block_bits", "k_emit", "k_rs_hist", "k_rs_scatter", "merge_scan", "k_merge", "csr"),
+              "padberg_rinaldi": ("k_pr_sample", "k_pr", "k_pr34")}
+    class_frac = {}
+    for gname, members in groups.items():
+        cs = [c for c in classes if c["name"] in members]
+        ms = sum(c["ms"] for c in cs)
+        if ms > 0:
+            gbps = sum(c["algo_bytes"] for c in cs) / (ms / 1000.0) / 1e9
+            class_frac[gname] = {"ms_per_step": round(ms / steps, 3), "algo_GBps": round(gbps, 1),
+                                 "frac": round(gbps / HBM_PEAK_GBS, 5)}
     return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured.get(dom["name"]),
+            "classes": class_frac,
             "kernel": dom["name"], "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
             "launches_per_step": dom["launches"] / steps, "algo_bytes_per_launch": dom_bytes,
             "traffic_source": os.path.relpath(traffic_file, ROOT) if measured else None,
@@ -397,6 +413,69 @@ def chung_lu_form(steps, approx=True):
     return out
 
 
+def _kernel_short(name):
+    """rocprofv3's kernel name reduced to the timing-class name:
+    'void mc::k_rs_scatter<16>(...)' -> 'k_rs_scatter'."""
+    n = name.split("(")[0].replace("void ", "").strip()
+    n = n.split("<")[0]
+    return n.split("::")[-1]
+
+
+def _db(path):
+    import glob
+    import sqlite3
+    files = glob.glob(os.path.join(path, "**", "*.db"), recursive=True) if os.path.isdir(path) else [path]
+    if len(files) != 1:
+        raise SystemExit(f"expected one rocpd database under {path}, found {files}")
+    return sqlite3.connect(files[0])
+
+
+def summarize(args):
+    """Text summaries of rocprofv3 output for profiles/: kernel statistics
+    (--kernel-trace --stats), and HBM traffic per dispatch from a FETCH_SIZE
+    run and a WRITE_SIZE run, each scaled by the same counter on a plain
+    1 GiB device copy (bench.py --calibrate-copy)."""
+    lines = [f"# {args.title}", "#", "# Commands (from /tmp with TMPDIR=/tmp; R = repository root):"]
+    lines += [f"#   {c}" for c in args.command]
+    if args.stats:
+        c = _db(args.stats)
+        rows = c.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                         "order by total_duration desc").fetchall()
+        lines += ["#", "# Durations in microseconds (rocprofv3 top_kernels).", "",
+                  "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+        for name, calls, tot, avg, pct in rows[:args.top]:
+            lines.append(f"| `{name.split('(')[0].replace('void ', '')}` | {calls} | {tot:.1f} | {avg:.1f} | {pct:.2f} |")
+    if args.fetch:
+        def per_kernel(path, counter):
+            c = _db(path)
+            out = {}
+            for name, disp, val in c.execute(
+                    "select kernel_name, dispatch_id, sum(value) from counters_collection where counter_name = ? "
+                    "group by dispatch_id", (counter,)):
+                k = _kernel_short(name)
+                out.setdefault(k, []).append(val)
+            return out
+        cal_f = per_kernel(args.cal_fetch, "FETCH_SIZE")["__amd_rocclr_copyBuffer"]
+        cal_w = per_kernel(args.cal_write, "WRITE_SIZE")["__amd_rocclr_copyBuffer"]
+        copy_bytes = float(1 << 30)
+        fs = copy_bytes / (np.median(cal_f) * 1024.0)
+        ws = copy_bytes / (np.median(cal_w) * 1024.0)
+        f = per_kernel(args.fetch, "FETCH_SIZE")
+        w = per_kernel(args.write, "WRITE_SIZE")
+        lines += ["#", f"# Calibration: __amd_rocclr_copyBuffer moving {int(copy_bytes)} bytes reads FETCH_SIZE "
+                       f"{np.median(cal_f):.1f} KiB and WRITE_SIZE {np.median(cal_w):.1f} KiB per dispatch, so",
+                  "# bytes = KiB * 1024 * scale with", f"fetch_scale {fs:.4f}", f"write_scale {ws:.4f}",
+                  f"source_digest {source_digest()}",
+                  "#", "# kernel dispatches fetch_KiB_per_dispatch write_KiB_per_dispatch bytes_per_dispatch(scaled)"]
+        rank = sorted(f, key=lambda k: -sum(f[k]))
+        for k in rank[:args.top]:
+            fk = float(np.mean(f[k]))
+            wk = float(np.mean(w.get(k, [0.0])))
+            lines.append(f"traffic {k} {len(f[k])} {fk:.1f} {wk:.1f} {int(round(fk * 1024 * fs + wk * 1024 * ws))}")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    log(f"wrote {args.out}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,7 +500,21 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (the reference "
                          "kernel for scaling HBM traffic counters) and exit")
+    ap.add_argument("--summarize", action="store_true",
+                    help="write a profiles/ summary from rocprofv3 databases (no GPU work)")
+    ap.add_argument("--stats", help="rocprofv3 --kernel-trace --stats output directory")
+    ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output directory")
+    ap.add_argument("--write", help="rocprofv3 --pmc WRITE_SIZE output directory")
+    ap.add_argument("--cal-fetch", help="FETCH_SIZE output of bench.py --calibrate-copy")
+    ap.add_argument("--cal-write", help="WRITE_SIZE output of bench.py --calibrate-copy")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--top", type=int, default=30)
+    ap.add_argument("--out")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print("bench.py: measures one GPU only; graphs of the batched and served forms would "
               "shard across GPUs (independent graphs), but no multi-GPU path is implemented.",
