@@ -167,7 +167,7 @@ struct Workspace {
   int64_t *voff, *lhat, *wsum, *kcap;
   int32_t *gn, *cvoff, *nnew, *active, *ucount, *rec_type, *rec_id, *rec_k, *fb_k, *whole, *gmaxw, *prok,
       *whole2, *fb_list, *root0, *flip, *nvoff, *npairs, *bref;
-  uint32_t *inref, *bbits;
+  uint32_t *inref, *st2;
   uint64_t *bdeg, *balpha;
   uint8_t* mode;
   int32_t* scan_k;
@@ -308,7 +308,7 @@ size_t carve(Workspace& ws, char* base, int64_t N, int64_t E, int64_t G) {
   take(ws.nvoff, (G + 1) * 4);
   take(ws.bref, (G + 1) * 4);
   take(ws.inref, ((N + 63) / 64 + 1) * 8);
-  take(ws.bbits, ((N + 63) / 64 + 1) * 8);
+  take(ws.st2, ((N + 63) / 64 + 1) * 16);  // two bits per vertex, whole 64-vertex groups
   take(ws.npairs, (G + 1) * 4);
   take(ws.gmaxw, (G + 1) * 4);
   take(ws.prok, (G + 1) * 4);
@@ -669,11 +669,14 @@ struct Solver {
           }
           big_vtx += (double)bsz;
           int64_t deg_sum = 0;
-          if (timer().on) {
+          if (timer().on || debug_on()) {
             MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &A.ctl->batch_deg, 8, hipMemcpyDeviceToHost, s));
             MC_HIP(hipStreamSynchronize(s));
             deg_sum = ws.sweep_host->batch_deg;
             big_deg += (double)deg_sum;
+            if (debug_on())
+              fprintf(stderr, "[mc] grid-wide batch g=%d size=%lld rows=%lld visited_before=%d ng=%d graph_entries=%lld\n",
+                      A.g, (long long)bsz, (long long)deg_sum, c.visited, A.ng, (long long)(A.pool_cap - 1));
           }
           // prefix sums of the batch's row lengths (ws.keys and ws.vals are
           // free until the contraction) and each entry tile's first row
@@ -686,10 +689,8 @@ struct Solver {
             exclusive_scan<int64_t, BatchDeg>(BatchDeg{A.capq + bh, rp}, bsz, off, off + bsz, ws.tmp, s);
             hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
                                (int32_t)bsz, tile_row);
-            // the graph's visit state as two bitmaps (ws.inref is free until
-            // the contraction)
-            hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.inref,
-                               ws.bbits);
+            // the graph's visit states, two bits per vertex
+            hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
           }
           {
             // every row of the batch once (col, w: 8 B per entry) and per
@@ -697,7 +698,7 @@ struct Solver {
             TimedScope t("k_sweep_big_relax", (double)deg_sum * 8 + (double)bsz * 8);
             static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
             hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
-                               tile_row, ws.inref, ws.bbits);
+                               tile_row, ws.st2);
           }
           hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
           {
@@ -1266,9 +1267,10 @@ struct Solver {
         }
         hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, cap, tested, ws.ctl);
         {
-          // per entry col, w and the gather of c(v) (16 B); per vertex its
-          // row bounds and c(u) (16 B)
-          TimedScope t("k_pr", (double)nnz * 16 + (double)n * 16);
+          // every entry's weight (4 B: an entry that cannot pass for any graph
+          // is rejected from it alone), per vertex its row bounds and c(u)
+          // (16 B): a lower bound of what the tests must read
+          TimedScope t("k_pr", (double)nnz * 4 + (double)n * 16);
           hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
                              cap, tested, ws.parent, ws.ucount, ws.ctl);
         }

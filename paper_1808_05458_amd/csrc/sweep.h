@@ -200,11 +200,15 @@ __device__ __forceinline__ void pool_put(const SA& A, const SweepQ& q, int64_t i
 //
 // unvisited: (grid-wide batches) y is known to be unvisited, so its stamp is
 // not read.
+// rsum (PUSH only) adds the weight of an edge into a vertex visited before
+// the batch: summed over the batch's rows it is the batch's weight to the
+// visited set, which alpha needs (a capped vertex's own r stops being exact
+// once the grid-wide relax skips the adds that reach it after its crossing).
 template <bool PUSH = true, class SA>
 __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int32_t x, int32_t y,
-                                               int32_t c, int32_t stamp, bool act, int32_t* wbuf = nullptr,
-                                               int32_t* wcnt = nullptr, bool member = false,
-                                               bool unvisited = false) {
+                                               int32_t c, int32_t stamp, bool act, int64_t& rsum,
+                                               int32_t* wbuf = nullptr, int32_t* wcnt = nullptr,
+                                               bool member = false, bool unvisited = false) {
   const int lane = lane_id();
   int64_t internal = 0;
   bool cross = false, push = false;
@@ -227,6 +231,7 @@ __device__ __forceinline__ int64_t sweep_relax(const SA& A, const SweepQ& q, int
     }
     if (vs != 0) {
       if (vs == stamp) internal = c;
+      else rsum += c;
     } else {
       nw = (int64_t)old + c;
       cross = old < A.lam && A.lam <= nw;
@@ -539,7 +544,7 @@ constexpr int64_t FAST_DEG = 2048;  // single pops with rows up to this run on w
 // stamps need not be visible yet.
 template <class SA>
 __device__ __forceinline__ int64_t wave_relax_known(const SA& A, const SweepQ& q, int32_t xs, int64_t ra,
-                                                    int64_t rb, int cnt, int32_t stamp) {
+                                                    int64_t rb, int cnt, int32_t stamp, int64_t& rsum) {
   const int lane = lane_id();
   int64_t internal = 0;
   for (int j = 0; j < cnt; ++j) {
@@ -556,7 +561,7 @@ __device__ __forceinline__ int64_t wave_relax_known(const SA& A, const SweepQ& q
       const int32_t c = act ? cv : 0;
       bool member = false;  // with one vertex, y == x is a self-loop, skipped anyway
       for (int k = 0; k < cnt && cnt > 1; ++k) member |= y == __builtin_amdgcn_readlane(xs, k);
-      internal += sweep_relax(A, q, x, y, c, stamp, act, nullptr, nullptr, member);
+      internal += sweep_relax(A, q, x, y, c, stamp, act, rsum, nullptr, nullptr, member);
     }
   }
   return internal;
@@ -688,10 +693,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           // at the branch's end)
           const int32_t xq = lane < size ? xs : __builtin_amdgcn_readlane(xs, 0);
           const int64_t cd = A.cdeg[xq];
-          const int32_t rx = rs_r(ld_relaxed(A.rs + xq));
           if (lane < size) st_relaxed(rs_stamp_ptr(A.rs + xs), stamp);
-          int64_t internal = wave_relax_known(A, qf, xs, ra, rb, size, stamp);
-          int64_t sum = lane < size ? cd - 2 * (int64_t)rx : 0;
+          // sum of c(x) - 2 r(x) over the batch, r(x) = weight to the visited set
+          int64_t rsum = 0;
+          int64_t internal = wave_relax_known(A, qf, xs, ra, rb, size, stamp, rsum);
+          int64_t sum = (lane < size ? cd : 0) - 2 * rsum;
           sum = wave_sum_i64_dpp(sum);
           internal = wave_sum_i64_dpp(internal);
           if (lane == 0) {
@@ -713,6 +719,19 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           if (x < 0) { cmd = CMD_EXIT_DONE; break; }
           const int64_t ra = pr.ra, rb = pr.rb;
           const int64_t deg = rb - ra;
+          if (deg > A.big_entries) {
+            // a row longer than one workgroup should relax: relaxed grid-wide,
+            // as a batch of this one vertex (the FIFO is empty here); its
+            // pair with itself unites nothing
+            if (lane == 0) {
+              const int32_t t = *q.cap_tail;
+              A.capq[t] = x;
+              A.capx[t] = x;
+              *q.cap_tail = t + 1;
+            }
+            cmd = CMD_EXIT_BIG;
+            break;
+          }
           if (lane == 0) seq_rows += deg;
           int64_t sum = 0;
           if (lane == 0) {
@@ -724,8 +743,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
             cmd = CMD_SINGLE;
             break;
           }
-          // a single vertex has no edge inside its batch (self-loops skipped)
-          int64_t internal = wave_relax_known(A, qf, x, ra, rb, 1, stamp);
+          // a single vertex has no edge inside its batch (self-loops skipped);
+          // its r (below the cap, every add reached it) is exact
+          int64_t unused = 0;
+          int64_t internal = wave_relax_known(A, qf, x, ra, rb, 1, stamp, unused);
           internal = wave_sum_i64_dpp(internal);
           if (lane == 0) {
             step = stamp;
@@ -754,7 +775,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
         const int64_t ec = act ? e : base;
         int32_t yv = A.col[ec], cv = A.w[ec];
         keep(cv);
-        internal += sweep_relax(A, q, x, act ? yv : 0, act ? cv : 0, stamp, act);
+        int64_t unused = 0;
+        internal += sweep_relax(A, q, x, act ? yv : 0, act ? cv : 0, stamp, act, unused);
       }
     } else {
       // the batch's entries spread evenly over the workgroup (a hub row in
@@ -766,7 +788,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
       // inside the batch are recognised by their stamp)
       for (int32_t i = h + threadIdx.x; i < t; i += SWEEP_THREADS) {
         const int32_t x = ld_relaxed(A.capq + i);
-        sum += A.cdeg[x] - 2 * (int64_t)rs_r(ld_relaxed(A.rs + x));
+        sum += A.cdeg[x];  // minus twice the batch's weight to the visited set, summed by the relax
         st_relaxed(rs_stamp_ptr(A.rs + x), stamp);
       }
       __threadfence_block();
@@ -812,7 +834,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
             y = A.col[e];
             cw = A.w[e];
           }
-          internal += sweep_relax(A, q, x, y, cw, stamp, act);
+          int64_t rsum = 0;
+          internal += sweep_relax(A, q, x, y, cw, stamp, act, rsum);
+          sum -= 2 * rsum;
         }
         __threadfence_block();
         __syncthreads();  // the chunk arrays are reused
@@ -923,9 +947,9 @@ __global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
     // the end reads the batch's first vertex
     const bool in = i < t;
     const int32_t x = A.capq[in ? i : h];
-    const int64_t cd = A.cdeg[x], r = rs_r(A.rs[x]), d = A.rp[x + 1] - A.rp[x];
+    const int64_t cd = A.cdeg[x], d = A.rp[x + 1] - A.rp[x];
     if (in) {
-      sum += cd - 2 * r;
+      sum += cd;  // minus twice the batch's weight to the visited set, summed by the relax
       *rs_stamp_ptr(A.rs + x) = stamp;
       deg += d;
     }
@@ -979,21 +1003,29 @@ __device__ __forceinline__ void flush_wave_buf(const SweepArgs& A, int32_t* wbuf
 constexpr int BIG_UNROLL = 4;
 constexpr int BIG_TILE = 256 * BIG_UNROLL;
 
-// Before a grid-wide batch is relaxed: bit i of visited is set if vertex
-// v0 + i was visited before the batch, bit i of batch if it is in the batch
-// (two bits per vertex in L2 instead of an 8-byte word gathered from HBM).
-__global__ void k_sweep_bits(SweepArgs A, uint32_t* visited, uint32_t* batch) {
+// The 2-bit state of each vertex while a grid-wide batch is relaxed (16 per
+// word, in L2 instead of an 8-byte word gathered from HBM): free, crossed
+// the cap during this relax, in the batch, visited before the batch.
+enum : uint32_t { BS_FREE = 0, BS_CROSSED = 1, BS_BATCH = 2, BS_VISITED = 3 };
+
+// Before a grid-wide batch is relaxed: the states of the graph's vertices
+// (a crossed vertex is in the FIFO, so at this point none is BS_CROSSED).
+__global__ void k_sweep_bits(SweepArgs A, uint32_t* st2) {
   const int32_t stamp = A.ctl->step + 1;
   for (int64_t base = (gtid() >> 6) << 6; base < A.ng; base += gstride()) {
     const int64_t i = base + lane_id();
     const int32_t st = i < A.ng ? rs_stamp(A.rs[A.v0 + i]) : 0;
-    const uint64_t vis = ballot(st != 0 && st != stamp), bat = ballot(st == stamp);
-    if (lane_id() == 0) {
-      visited[base >> 5] = (uint32_t)vis;
-      visited[(base >> 5) + 1] = (uint32_t)(vis >> 32);
-      batch[base >> 5] = (uint32_t)bat;
-      batch[(base >> 5) + 1] = (uint32_t)(bat >> 32);
+    const uint64_t hi = ballot(st != 0);                   // in the batch or visited
+    const uint64_t lo = ballot(st != 0 && st != stamp);    // visited
+    // interleave: vertex k of a 16-vertex group at bits 2k (lo) and 2k+1 (hi)
+    uint32_t word = 0;
+    const int g = lane_id() & 3;  // lanes 0..3 each build one word of 16 vertices
+    for (int k = 0; k < 16; ++k) {
+      const int b = g * 16 + k;
+      word |= (uint32_t)((lo >> b) & 1) << (2 * k);
+      word |= (uint32_t)((hi >> b) & 1) << (2 * k + 1);
     }
+    if (lane_id() < 4) st2[(base >> 4) + g] = word;
   }
 }
 
@@ -1018,8 +1050,7 @@ __global__ void k_sweep_big_tiles(const int64_t* off, int32_t bsz, int32_t* tile
 
 // off: bsz + 1 prefix sums of the batch's row lengths (off[bsz] = entries).
 __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h, int32_t bsz, const int64_t* off,
-                                                         const int32_t* tile_row, const uint32_t* visited,
-                                                         const uint32_t* batch) {
+                                                         const int32_t* tile_row, uint32_t* st2) {
   __shared__ int32_t buf[4][2 * BIG_BUF];
   __shared__ int32_t cnt[4];
   __shared__ int32_t s_x[BIG_TILE];
@@ -1034,7 +1065,7 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
   const int64_t total = off[bsz];
   const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
   const int64_t e_idle = A.rp[A.v0];  // an entry of the graph (it has some: a batch is being relaxed)
-  int64_t internal = 0;
+  int64_t internal = 0, rsum = 0;  // 2 w(inside the batch); the batch's weight to the visited set
   for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
     const int64_t t0 = j * BIG_TILE, t1 = min(t0 + BIG_TILE, total);
     const int32_t r0 = tile_row[j], r1 = j + 1 < ntiles ? tile_row[j + 1] : bsz - 1;
@@ -1087,28 +1118,24 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
       }
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) keep(cs[u]);  // weights in with the columns
-      // the neighbour's state from the bitmaps: inside the batch, visited
-      // before it, or unvisited (then the add, and maybe a crossing)
-      uint32_t bw[BIG_UNROLL], vw[BIG_UNROLL];
+      // the neighbour's state: in the batch (internal weight), visited
+      // before it (weight to the visited set), crossed during this relax (its
+      // r no longer matters: the add is skipped, Lemma 1), or free (the add,
+      // and maybe a crossing)
+      uint32_t sw[BIG_UNROLL];
 #pragma unroll
-      for (int u = 0; u < BIG_UNROLL; ++u) {
-        const int32_t i = ys[u] - A.v0;
-        bw[u] = batch[i >> 5];
-        vw[u] = visited[i >> 5];
-      }
+      for (int u = 0; u < BIG_UNROLL; ++u) sw[u] = st2[(ys[u] - A.v0) >> 4];
 #pragma unroll
-      for (int u = 0; u < BIG_UNROLL; ++u) {  // all states in before any add issues
-        keep(bw[u]);
-        keep(vw[u]);
-      }
+      for (int u = 0; u < BIG_UNROLL; ++u) keep(sw[u]);  // all states in before any add issues
       bool upd[BIG_UNROLL];
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) {
         const int32_t i = ys[u] - A.v0;
         const bool act = xs[u] >= 0 && ys[u] != xs[u];
-        const bool inb = (bw[u] >> (i & 31)) & 1u, vis = (vw[u] >> (i & 31)) & 1u;
-        if (act && inb) internal += cs[u];
-        upd[u] = act && !inb && !vis;
+        const uint32_t st = (sw[u] >> (2 * (i & 15))) & 3u;
+        if (act && st == BS_BATCH) internal += cs[u];
+        if (act && st == BS_VISITED) rsum += cs[u];
+        upd[u] = act && st == BS_FREE;
       }
       // the adds go to r alone, the low half of the word (r + c stays below
       // 2^31, so it never carries into the stamp): a 32-bit return leaves no
@@ -1126,6 +1153,10 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
       for (int u = 0; u < BIG_UNROLL; ++u) {
         const int64_t r_old = old[u];
         const bool cross = upd[u] && r_old < A.lam && A.lam <= r_old + cs[u];
+        if (cross) {  // later adds to this vertex are skipped
+          const int32_t i = ys[u] - A.v0;
+          atomicOr(&st2[i >> 4], BS_CROSSED << (2 * (i & 15)));
+        }
         const uint64_t cm = ballot(cross);
         if (cm) {
           const int32_t at = *wcnt;
@@ -1159,14 +1190,20 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
       A.capx[o + i] = wbuf[2 * i + 1];
     }
   }
-  // one add per workgroup (adds on one address serialise)
-  __shared__ int64_t part[4];
+  // one add per workgroup and counter (adds on one address serialise)
+  __shared__ int64_t part[2][4];
   internal = wave_sum_i64(internal);
-  if (lane == 0) part[wave] = internal;
+  rsum = wave_sum_i64(rsum);
+  if (lane == 0) {
+    part[0][wave] = internal;
+    part[1][wave] = rsum;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int64_t tot = part[0] + part[1] + part[2] + part[3];
+    const int64_t tot = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    const int64_t rs = part[1][0] + part[1][1] + part[1][2] + part[1][3];
     if (tot) atomicAdd((unsigned long long*)&c->batch_internal, (unsigned long long)tot);
+    if (rs) atomicAdd((unsigned long long*)&c->batch_sum, (unsigned long long)(-2 * rs));
   }
 }
 
