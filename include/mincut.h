@@ -165,7 +165,14 @@ typedef struct mc_options {
                               lower limit; -1: never (one vertex at a time
                               to the end).  Changes which pairs a round
                               unites, never lambda. */
-  int32_t reserved[3];
+  int32_t sweep_pull;      /* a full-graph sweep's grid-wide batch: 0
+                              (default) pushes the batch's rows into their
+                              neighbours, or, when the vertices still free
+                              hold fewer entries, pulls (each free vertex
+                              sums its edges into the batch); 1: always
+                              pull; -1: always push.  Changes which pairs a
+                              round unites, never lambda. */
+  int32_t reserved[2];
 } mc_options;
 
 typedef struct mc_stats {

@@ -61,7 +61,8 @@ class Options(ctypes.Structure):
                 ("pr_triangle_deg", ctypes.c_int32), ("viecut_exact", ctypes.c_int32),
                 ("approx_ppm", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
-                ("sweep_tail", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("sweep_tail", ctypes.c_int32), ("sweep_pull", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

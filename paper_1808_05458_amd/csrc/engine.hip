@@ -662,45 +662,77 @@ struct Solver {
           const int32_t bh = c.cap_head, bt = c.cap_tail;
           const int64_t bsz = bt - bh;
           MC_HIP(hipMemsetAsync(&A.ctl->batch_sum, 0, 24, s));
+          MC_HIP(hipMemsetAsync(&A.ctl->pull_alpha, 0, 8, s));
           {
             // per batch vertex its FIFO slot, degree, r word and stamp
             TimedScope t("k_sweep_big_mark", (double)bsz * 32);
             hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
           }
           big_vtx += (double)bsz;
-          int64_t deg_sum = 0;
-          if (timer().on || debug_on()) {
-            MC_HIP(hipMemcpyAsync(&ws.sweep_host->batch_deg, &A.ctl->batch_deg, 8, hipMemcpyDeviceToHost, s));
-            MC_HIP(hipStreamSynchronize(s));
-            deg_sum = ws.sweep_host->batch_deg;
-            big_deg += (double)deg_sum;
-            if (debug_on())
-              fprintf(stderr, "[mc] grid-wide batch g=%d size=%lld rows=%lld visited_before=%d ng=%d graph_entries=%lld\n",
-                      A.g, (long long)bsz, (long long)deg_sum, c.visited, A.ng, (long long)(A.pool_cap - 1));
-          }
-          // prefix sums of the batch's row lengths (ws.keys and ws.vals are
-          // free until the contraction) and each entry tile's first row
+          // push or pull: the batch's rows against the rows of the vertices
+          // still free (neither visited nor in the batch), whose count takes
+          // one pass over the graph's vertices
+          MC_HIP(hipMemcpyAsync(ws.sweep_host, A.ctl, offsetof(SweepCtl, bitmap), hipMemcpyDeviceToHost, s));
+          MC_HIP(hipStreamSynchronize(s));
+          const int64_t deg_sum = ws.sweep_host->batch_deg;
+          const int64_t free_rows = (A.pool_cap - 1) - ws.sweep_host->rows_done - deg_sum;
+          const bool pull = opt.sweep_pull >= 0 && (opt.sweep_pull > 0 || deg_sum > free_rows + A.ng / 8);
+          big_deg += (double)deg_sum;
+          if (debug_on())
+            fprintf(stderr, "[mc] grid-wide batch g=%d size=%lld rows=%lld free_rows=%lld visited_before=%d ng=%d %s\n",
+                    A.g, (long long)bsz, (long long)deg_sum, (long long)free_rows, c.visited, A.ng,
+                    pull ? "pull" : "push");
+          // prefix sums of row lengths (ws.keys and ws.vals are free until
+          // the contraction) and each entry tile's first row
           int64_t* off = (int64_t*)ws.keys;
           int32_t* tile_row = ws.vals;
-          {
-            // per batch vertex its FIFO slot and row bounds, the prefix sum
-            // written; then the graph's visit state read once, two bits written
-            TimedScope t("sweep_batch_prep", (double)bsz * 28 + (double)A.ng * 8);
-            exclusive_scan<int64_t, BatchDeg>(BatchDeg{A.capq + bh, rp}, bsz, off, off + bsz, ws.tmp, s);
-            hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
-                               (int32_t)bsz, tile_row);
-            // the graph's visit states, two bits per vertex
-            hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
+          if (!pull) {
+            {
+              // per batch vertex its FIFO slot and row bounds, the prefix sum
+              // written; then the graph's visit state read once, two bits written
+              TimedScope t("sweep_batch_prep", (double)bsz * 28 + (double)A.ng * 8);
+              exclusive_scan<int64_t, BatchDeg>(BatchDeg{A.capq + bh, rp}, bsz, off, off + bsz, ws.tmp, s);
+              hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
+                                 (int32_t)bsz, tile_row);
+              // the graph's visit states, two bits per vertex
+              hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
+            }
+            {
+              // every row of the batch once (col, w: 8 B per entry) and per
+              // batch vertex its row bounds
+              TimedScope t("k_sweep_big_relax", (double)deg_sum * 8 + (double)bsz * 8);
+              static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
+              hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
+                                 tile_row, ws.st2);
+            }
+          } else {
+            // the free vertices (a list in ws.lab, positions in ws.newid:
+            // both free until the compaction) and their rows' prefix sums
+            int32_t* list = ws.lab;
+            int32_t nfree = 0;
+            {
+              TimedScope t("sweep_batch_prep", (double)A.ng * 16);
+              hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
+              exclusive_scan<int32_t, FreeFlag>(FreeFlag{ws.st2}, A.ng, ws.newid, &A.ctl->free_count, ws.tmp, s);
+              hipLaunchKernelGGL(k_sweep_free_list, dim3(grid_for(A.ng, TB, num_cu * 4)), dim3(TB), 0, s, A, ws.st2,
+                                 (const int32_t*)ws.newid, list);
+              MC_HIP(hipMemcpyAsync(&ws.sweep_host->free_count, &A.ctl->free_count, 4, hipMemcpyDeviceToHost, s));
+              MC_HIP(hipStreamSynchronize(s));
+              nfree = ws.sweep_host->free_count;
+              exclusive_scan<int64_t, BatchDeg>(BatchDeg{list, rp}, nfree, off, off + nfree, ws.tmp, s);
+              hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(std::max(nfree, 1), TB, num_cu * 16)), dim3(TB), 0,
+                                 s, off, nfree, tile_row);
+            }
+            // every free row once (col, w: 8 B per entry) and per free vertex
+            // its row bounds and r
+            TimedScope t("k_sweep_big_pull", (double)free_rows * 8 + (double)nfree * 16);
+            if (nfree > 0) {
+              static const int pull_grid = resident_grid((const void*)&k_sweep_big_pull, TB, num_cu);
+              hipLaunchKernelGGL(k_sweep_big_pull, dim3(pull_grid), dim3(TB), 0, s, A, (const int32_t*)list, nfree,
+                                 (const int64_t*)off, (const int32_t*)tile_row, (const uint32_t*)ws.st2);
+            }
           }
-          {
-            // every row of the batch once (col, w: 8 B per entry) and per
-            // batch vertex its row bounds
-            TimedScope t("k_sweep_big_relax", (double)deg_sum * 8 + (double)bsz * 8);
-            static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
-            hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
-                               tile_row, ws.st2);
-          }
-          hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt);
+          hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt, pull ? 1 : 0);
           {
             // exact queue rebuild: two passes over the graph's vertices
             TimedScope t("sweep_rebuild", (double)A.ng * 16);

@@ -53,10 +53,12 @@ struct SweepCtl {
   int32_t ph_singles[SWEEP_PHASES], ph_batches[SWEEP_PHASES], ph_cross[SWEEP_PHASES];
   // the tail's concurrent scans (tail.h): list length and cursor, pops, and
   // the best prefix cut (alpha << 32 | process)
-  int32_t tail_total, tail_cursor, tail_pops, tail_forks;
+  int32_t tail_total, tail_cursor, tail_pops, free_count;
   uint64_t tail_best;
   int64_t tail_rows;           // entries of the rows the tail relaxed
   int64_t seq_rows;            // ... and the sequential kernel
+  int64_t rows_done;           // entries in the rows of every visited vertex
+  int64_t pull_alpha;          // pull form of a grid-wide batch: c(S + B), summed
   uint64_t bitmap[SWEEP_BUCKETS / 64];
   int32_t head[SWEEP_BUCKETS];     // recent pushes (lists through the pool)
   int32_t seg_cur[SWEEP_BUCKETS];  // rebuilt segments of seg[]: unread part
@@ -330,9 +332,9 @@ __global__ void k_sweep_init(const SweepArgs* args) {
     c->batch_sum = c->batch_internal = 0;
     c->batch_deg = 0;
     c->singles = c->batches = c->big_batches = c->rebuilds = 0;
-    c->tail_total = c->tail_cursor = c->tail_pops = c->tail_forks = 0;
+    c->tail_total = c->tail_cursor = c->tail_pops = c->free_count = 0;
     c->tail_best = ~0ull;
-    c->tail_rows = c->seq_rows = 0;
+    c->tail_rows = c->seq_rows = c->rows_done = c->pull_alpha = 0;
   }
 }
 
@@ -881,6 +883,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
     c->singles = singles;
     c->batches = batches;
     c->seq_rows += seq_rows;
+    c->rows_done += seq_rows;
     const int ph = min(c->big_batches, SWEEP_PHASES - 1);
     c->ph_singles[ph] += singles - singles0;
     c->ph_batches[ph] += batches - batches0;
@@ -1207,7 +1210,9 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
   }
 }
 
-__global__ void k_sweep_big_finish(SweepArgs A, int32_t t) {
+// pull: the batch was relaxed in pull form, whose c(S + B) replaces alpha
+// (the sum of the free vertices' new r, each their weight to S + B).
+__global__ void k_sweep_big_finish(SweepArgs A, int32_t t, int32_t pull) {
   if (gtid() != 0) return;
   SweepCtl* c = A.ctl;
   const int32_t h = c->cap_head;
@@ -1215,10 +1220,184 @@ __global__ void k_sweep_big_finish(SweepArgs A, int32_t t) {
   c->batches += 1;
   c->big_batches += 1;
   c->cap_head = t;
+  c->rows_done += c->batch_deg;
+  if (pull) {
+    c->batch_sum = c->pull_alpha - c->alpha;
+    c->batch_internal = 0;
+  }
   sweep_close_batch(c, A.ng, c->batch_sum, c->batch_internal, t - h, stamp);
   c->batch_sum = 0;
   c->batch_internal = 0;
   c->status = SW_RUNNING;
+}
+
+// ---- pull form of a grid-wide batch
+// When the batch's rows hold more entries than the rows of the vertices
+// still free (neither visited nor in the batch), each free vertex y sums the
+// weight of its edges into the batch instead: one pass over the free rows,
+// no atomic on r unless a row spans tiles.  The batch's members tie at the
+// cap, so any order of them is legal; y's edges into the batch are taken in
+// row order, and the one at which r(y) reaches lambda-hat is y's crossing
+// (united later).  alpha after the batch is c(S + B) = the sum over free
+// vertices of their new r (each the weight to S + B).
+
+// Free vertices of the graph (flag for the prefix scan).
+struct FreeFlag {
+  const uint32_t* st2;
+  __device__ __forceinline__ int32_t operator()(int64_t i) const {
+    return ((st2[i >> 4] >> (2 * (i & 15))) & 3u) == BS_FREE;
+  }
+};
+
+// list[pos[i]] = v0 + i for every free vertex; pull_alpha += their r (the
+// weight to S, exact for a vertex that never crossed the cap).
+__global__ void __launch_bounds__(256) k_sweep_free_list(SweepArgs A, const uint32_t* st2, const int32_t* pos,
+                                                         int32_t* list) {
+  int64_t rsum = 0;
+  for (int64_t i = gtid(); i < A.ng; i += gstride()) {
+    const uint32_t st = (st2[i >> 4] >> (2 * (i & 15))) & 3u;
+    const uint64_t u = A.rs[A.v0 + i];
+    if (st == BS_FREE) {
+      list[pos[i]] = A.v0 + (int32_t)i;
+      rsum += rs_r(u);
+    }
+  }
+  __shared__ int64_t part[4];
+  rsum = wave_sum_i64(rsum);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = rsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t t = part[0] + part[1] + part[2] + part[3];
+    if (t) atomicAdd((unsigned long long*)&A.ctl->pull_alpha, (unsigned long long)t);
+  }
+}
+
+// The free rows in tiles of BIG_TILE entries (off: prefix sums of the list's
+// row lengths; tile_row: each tile's first row, as for the push form).
+__global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32_t* list, int32_t nl,
+                                                        const int64_t* off, const int32_t* tile_row,
+                                                        const uint32_t* st2) {
+  __shared__ int32_t s_y[BIG_TILE];
+  __shared__ int64_t s_off[BIG_TILE + 1], s_base[BIG_TILE];
+  __shared__ int32_t e_w[BIG_TILE], e_x[BIG_TILE];
+  SweepCtl* c = A.ctl;
+  const int lane = lane_id();
+  const int64_t total = off[nl];
+  const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
+  const int64_t e_idle = A.rp[A.v0];
+  int64_t into = 0;  // weight of free rows' edges into the batch
+  for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
+    const int64_t t0 = j * BIG_TILE, t1 = min(t0 + BIG_TILE, total);
+    const int32_t r0 = tile_row[j], r1 = j + 1 < ntiles ? tile_row[j + 1] : nl - 1;
+    for (int32_t rb = r0; rb <= r1; rb += BIG_TILE) {
+      const int32_t nr = min(BIG_TILE, r1 + 1 - rb);
+      for (int32_t k = threadIdx.x; k < nr; k += 256) {
+        const int32_t y = list[rb + k];
+        s_y[k] = y;
+        s_base[k] = A.rp[y];
+        s_off[k] = off[rb + k];
+      }
+      if (threadIdx.x == 0) s_off[nr] = off[rb + nr];
+      __syncthreads();
+      const int64_t lo_e = max(s_off[0], t0), hi_e = min(s_off[nr], t1);
+      const int64_t i0 = lo_e + (int64_t)threadIdx.x * BIG_UNROLL;
+      int32_t row = 0;
+      if (i0 < hi_e) {
+        int32_t lo = 0, hi = nr - 1;  // last row with s_off[row] <= i0
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= i0) lo = mid;
+          else hi = mid - 1;
+        }
+        row = lo;
+      }
+      // every entry's loads issued before any is used; an idle slot reads
+      // the graph's first entry
+      int64_t es[BIG_UNROLL];
+      bool ok[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        const int64_t i = i0 + u;
+        ok[u] = i < hi_e;
+        es[u] = e_idle;
+        if (ok[u]) {
+          while (s_off[row + 1] <= i) ++row;  // LDS only
+          es[u] = s_base[row] + (i - s_off[row]);
+        }
+      }
+      int32_t xs[BIG_UNROLL], cs[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        xs[u] = A.col[es[u]];
+        cs[u] = A.w[es[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) keep(cs[u]);
+      uint32_t sw[BIG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) sw[u] = st2[(xs[u] - A.v0) >> 4];
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        if (!ok[u]) continue;
+        const int32_t i = xs[u] - A.v0;
+        const bool inb = ((sw[u] >> (2 * (i & 15))) & 3u) == BS_BATCH;
+        const int32_t p = (int32_t)(i0 + u - lo_e);
+        e_w[p] = inb ? cs[u] : 0;
+        e_x[p] = xs[u];
+        into += inb ? cs[u] : 0;
+      }
+      __syncthreads();
+      // per row: its part of the tile, summed; the crossing, if any
+      for (int32_t k0 = 0; k0 < nr; k0 += 256) {
+        const int32_t k = k0 + (int32_t)threadIdx.x;
+        int32_t y = -1, partner = -1;
+        if (k < nr) {
+          const int64_t a = max(s_off[k], lo_e), b = min(s_off[k + 1], hi_e);
+          int64_t sum = 0;
+          for (int64_t q = a; q < b; ++q) sum += e_w[q - lo_e];
+          if (sum > 0) {
+            y = s_y[k];
+            // a row wholly inside this tile has no other writer
+            const bool whole = s_off[k] >= t0 && s_off[k + 1] <= t1;
+            int32_t* rp32 = (int32_t*)(A.rs + y);
+            const int32_t old = whole ? *rp32 : atomic_add(rp32, (int32_t)sum);
+            if (whole) *rp32 = old + (int32_t)sum;
+            if ((int64_t)old < A.lam && A.lam <= (int64_t)old + sum) {
+              int64_t run = old;
+              for (int64_t q = a; q < b; ++q) {
+                run += e_w[q - lo_e];
+                if (run >= A.lam) {
+                  partner = e_x[q - lo_e];
+                  break;
+                }
+              }
+            }
+          }
+        }
+        const bool cross = partner >= 0;
+        const uint64_t cm = ballot(cross);
+        if (cm) {
+          int32_t at = 0;
+          if (lane == 0) at = atomicAdd(&c->cap_tail, popc64(cm));
+          at = bcast(at, 0);
+          if (cross) {
+            const int32_t q = at + popc64(cm & lanemask_lt());
+            A.capq[q] = y;
+            A.capx[q] = partner;
+          }
+        }
+      }
+      __syncthreads();  // the slice arrays are reused
+    }
+  }
+  __shared__ int64_t part[4];
+  into = wave_sum_i64(into);
+  if (lane == 0) part[threadIdx.x >> 6] = into;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t t = part[0] + part[1] + part[2] + part[3];
+    if (t) atomicAdd((unsigned long long*)&c->pull_alpha, (unsigned long long)t);
+  }
 }
 
 // ---- exact rebuild of the bucket queue from the frontier (counting sort)

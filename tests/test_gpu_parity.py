@@ -90,6 +90,9 @@ def test_medium_graphs_against_noi():
                                   dict(whole_max=16, sweep_handoff=1, sweep_tail=1),
                                   dict(whole_max=16, sweep_handoff=1, sweep_tail=1, use_pr=0),
                                   dict(whole_max=16, sweep_tail=-1),
+                                  dict(whole_max=16, sweep_handoff=1, sweep_pull=1),
+                                  dict(whole_max=16, sweep_handoff=2, sweep_pull=1, use_pr=0),
+                                  dict(whole_max=16, sweep_pull=-1),
                                   dict(scan_mode=2), dict(scan_mode=2, max_pops=3),
                                   dict(scan_mode=2, eager_blacklist=0, use_pr=0)])
 def test_planted_4096_options(opts):
@@ -111,6 +114,7 @@ def test_region_scans_on_power_law_core():
                  dict(whole_max=64, sweep_handoff=4),
                  dict(whole_max=64, sweep_tail=-1), dict(whole_max=64, sweep_tail=1, use_pr=0),
                  dict(whole_max=64, sweep_handoff=4, sweep_tail=1),
+                 dict(whole_max=64, sweep_handoff=4, sweep_pull=1), dict(whole_max=64, sweep_pull=-1, use_pr=0),
                  dict(whole_max=64, scan_mode=1), dict(whole_max=64, scan_mode=1, eager_blacklist=0),
                  dict(whole_max=64, scan_mode=1, max_pops=50),
                  dict(whole_max=64, scan_mode=1, use_pr=0)]:
@@ -242,7 +246,8 @@ def test_sweep_on_weighted_graphs_with_wide_buckets():
 def test_sweep_on_larger_power_law_graph():
     g = gg.chung_lu(29, 200000, 2.5, 16.0, 1, 1, kcore=5, lcc=True)
     ref, _, _ = oracle.noi(g, 1)
-    for opts in [dict(), dict(sweep_tail=-1), dict(sweep_tail=1, use_pr=0)]:
+    for opts in [dict(), dict(sweep_tail=-1), dict(sweep_tail=1, use_pr=0), dict(sweep_pull=1),
+                 dict(sweep_pull=-1, sweep_tail=-1)]:
         announce("chung_lu 200000 5-core", g.n, g.m, ref, opts)
         lam, side, st = solve(g, **opts)
         assert lam == ref, opts
@@ -363,6 +368,8 @@ _BLOCK_VARIANTS = [dict(), dict(use_pr=0), dict(whole_max=4, scan_mode=1), dict(
                    dict(whole_max=4, sweep_handoff=1, sweep_tail=1),
                    dict(whole_max=4, sweep_handoff=1, sweep_tail=1, use_pr=0),
                    dict(whole_max=4, sweep_handoff=1, sweep_tail=-1, use_pr=0),
+                   dict(whole_max=4, sweep_handoff=1, sweep_pull=1, use_pr=0),
+                   dict(whole_max=4, sweep_handoff=1, sweep_pull=1, sweep_tail=1),
                    dict(pr_triangle_deg=-64)]
 
 

@@ -79,15 +79,16 @@ def bridged():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("tail", [0, -1], ids=["tail_scans", "sequential_tail"])
-def test_bridged_8cores_lambda_below_min_degree(bridged, tail):
+@pytest.mark.parametrize("opts", [dict(), dict(sweep_tail=-1, sweep_pull=-1), dict(sweep_pull=1)],
+                         ids=["default", "sequential_tail_push", "pull"])
+def test_bridged_8cores_lambda_below_min_degree(bridged, opts):
     # two Chung-Lu 8-cores (about 2M vertices each) joined by 3 bridges: the
     # minimum cut (3) lies below the minimum degree (8), so the full-graph
     # sweeps, their grid-wide batches and the tail must keep the bridges
     # apart from everything else
     g, gold = bridged
     assert int(np.diff(g.row_ptr).min()) == 8 and gold["lambda"] == 3
-    announce("bridged_8cores", g.n, g.m, tail)
-    lam, side, st = solve(g, sweep_tail=tail)
+    announce("bridged_8cores", g.n, g.m, opts)
+    lam, side, st = solve(g, **opts)
     assert lam == gold["lambda"]
     check_side(g, lam, side)
