@@ -169,3 +169,41 @@ def test_invalid_requests_are_refused():
             srv._n[12345] = 3
             srv.wait(12345)
         assert e.value.code == mc.MC_ESTATE
+
+
+@pytest.mark.timeout(600)
+def test_distinct_stream_alone_equals_mix_equals_oracle():
+    """A stream of distinct requests shaped as the served workload (request i
+    is served_request(i), Chung-Lu with n log-uniform in [2^10, 2^20]),
+    arriving as a Poisson stream faster than the server drains it: every
+    lambda in the mix equals the same request solved alone and the oracle's
+    stored value; sides realise it."""
+    import json
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_1808_05458_amd as mc
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")))["served_2000"]
+    count = 240
+    with ThreadPoolExecutor(16) as ex:
+        graphs = list(ex.map(gg.served_request, range(count)))
+    assert [g.n for g in graphs] == gold["n"][:count] and [g.m for g in graphs] == gold["m"][:count]
+    ref = gold["lambdas"][:count]
+    alone = []
+    for g in graphs:
+        rp, col, w = mc.to_device(g, "cuda")
+        alone.append(mc.mincut(rp, col, w, want_side=False)[0])
+    assert alone == ref
+    announce("distinct stream", count, sum(g.m for g in graphs))
+    rng = np.random.default_rng(9)
+    with mc.Server(lanes=3) as srv:
+        tickets = []
+        for g in graphs:
+            time.sleep(float(rng.exponential(0.0005)))
+            tickets.append(srv.submit(g))
+        batched = 0
+        for i, t in enumerate(tickets):
+            lam, side, lat = srv.wait(t)
+            assert lam == ref[i], (i, lam, ref[i])
+            check_side(graphs[i], lam, side)
+            batched += lat["batch_graphs"] > 1
+    assert batched > 0  # some requests were coalesced into packed solves
