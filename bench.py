@@ -143,8 +143,10 @@ def ablation():
     one-pop-at-a-time scans with an LDS hash map (scan_mode 2, small graphs),
     concurrent region scans (Algorithm 1, scan_mode 1, large graphs), and the
     triangle tests (default: from the second round; also without them and
-    from the first round); on the 4096-graph batch and the Chung-Lu 2^22
-    8-core."""
+    from the first round), the priority-queue orders among equal keys
+    (pq_order: 1 bucket queue, 2 bucket stack, 3 heap) and repeated visits
+    of region scans (scan_visits); on the 4096-graph batch and the Chung-Lu
+    2^22 8-core.  n_round: vertices at the start of each round."""
     import torch
     import graphgen as gg
     import paper_1808_05458_amd as mc
@@ -158,7 +160,7 @@ def ablation():
             lam, st = f()
         torch.cuda.synchronize()
         out[name] = {"ms": round((time.perf_counter() - t0) / reps * 1e3, 2), "rounds": st["rounds"],
-                     "lambda": lam}
+                     "n_round": list(st["n_round"][:min(st["rounds"], 8)]), "lambda": lam}
         log(f"ablation {name}: {out[name]}")
 
     graphs = [gg.batch_graph(i) for i in range(4096)]
@@ -174,6 +176,9 @@ def ablation():
     run("batch_capped_sweeps_no_triangle_tests", batch(pr_triangle_deg=0))
     run("batch_capped_sweeps_triangle_tests_from_round_1", batch(pr_triangle_deg=-64))
     run("batch_one_pop_scans", batch(scan_mode=2))
+    for order, name in ((1, "bucket_queue"), (2, "bucket_stack"), (3, "heap")):
+        run(f"batch_capped_sweeps_{name}", batch(pq_order=order))
+        run(f"batch_one_pop_scans_{name}", batch(scan_mode=2, pq_order=order))
     del rp, col, w
     g = gg.chung_lu_4m_8core(22)
     rp, col, w = mc.to_device(g, "cuda:0")
@@ -185,57 +190,60 @@ def ablation():
         return f
     run("chung_lu_capped_sweep", single())
     run("chung_lu_region_scans", single(scan_mode=1), reps=1)
+    for order, name in ((1, "bucket_queue"), (2, "bucket_stack"), (3, "heap")):
+        run(f"chung_lu_region_scans_{name}", single(scan_mode=1, pq_order=order), reps=1)
+    for k in (2, 3):
+        run(f"chung_lu_region_scans_{k}_visits", single(scan_mode=1, scan_visits=k), reps=1)
     run("chung_lu_one_pop_hashed_small_graphs", single(scan_mode=2))
     return out
 
 
-def served_form(requests, pool_size, lanes, seed=5):
-    """Poisson arrivals of min-cut requests (Chung-Lu, exponent 2.5, average
-    degree 16, n log-uniform in [2^10, 2^20], weights in [1, 50], largest
-    component) drawn from a pool of generated graphs, served with continuous
-    batching.  The capacity is measured closed-loop first; the open-loop
-    runs arrive at 0.3 and 0.7 of it.  Latency = submit -> result on the host
-    (host CSR in, upload included)."""
+def served_form(requests, lanes, seed=5):
+    """Poisson arrivals of distinct min-cut requests (Chung-Lu, exponent 2.5,
+    average degree 16, n log-uniform in [2^10, 2^20], weights in [1, 50],
+    largest component; request i is served_request(i)), served with
+    continuous batching.  The capacity is measured closed-loop first; the
+    open-loop runs arrive at 0.3 and 0.7 of it.  Latency = submit -> result
+    on the host (host CSR in, upload included).  Every served lambda is
+    compared with the same request solved alone (the loop of single solves)
+    and, where stored, with the oracle's."""
     import threading
+    from concurrent.futures import ThreadPoolExecutor
     import torch
     import graphgen as gg
     import paper_1808_05458_amd as mc
     t0 = time.time()
-    pool = [gg.served_request(i) for i in range(pool_size)]
-    log(f"served: pool of {pool_size} requests, sum n={sum(g.n for g in pool)} "
-        f"sum m={sum(g.m for g in pool)} in {time.time() - t0:.1f}s")
-    alone = []
-    for g in pool:
-        rp, col, w = mc.to_device(g, "cuda:0")
-        alone.append(mc.mincut(rp, col, w, want_side=False)[0])
-    torch.cuda.synchronize()
+    with ThreadPoolExecutor(16) as ex:  # the generator releases the interpreter lock
+        pool = list(ex.map(gg.served_request, range(requests)))
+    sum_m = sum(g.m for g in pool)
+    log(f"served: {requests} distinct requests, sum n={sum(g.n for g in pool)} sum m={sum_m} "
+        f"in {time.time() - t0:.1f}s")
+    gold = golden().get("served_2000")
+    oracle_l = gold["lambdas"][:requests] if gold and gold["requests"] >= requests else None
     rng = np.random.default_rng(seed)
-    order = rng.integers(0, pool_size, size=requests)
-    mean_m = float(np.mean([pool[i].m for i in order]))
 
-    # one long-lived server for every run; a first pass over the pool lets
-    # each lane's buffers grow to their working size
+    # one long-lived server for every run; a first pass over the largest
+    # requests lets each lane's buffers grow to their working size
     srv = mc.Server(lanes=lanes)
-    warm = [srv.submit(g) for g in sorted(pool, key=lambda g: -g.nnz)]
+    warm = [srv.submit(g) for g in sorted(pool, key=lambda g: -g.nnz)[:4 * lanes]]
     for t in warm:
         srv.wait(t, want_side=False)
 
-    def run(rate):
+    def run(rate, ref):
         """rate None: everything submitted at once (closed loop)."""
-        lat, ok = [], True
+        lat, lams = [], [None] * requests
         tickets = [None] * requests
         ready = threading.Semaphore(0)
 
         def produce():
             gaps = rng.exponential(1.0 / rate, size=requests) if rate else np.zeros(requests)
-            start = time.perf_counter()
-            due = start
+            due = time.perf_counter()
             for k in range(requests):
                 due += gaps[k]
                 d = due - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
-                tickets[k] = srv.submit(pool[order[k]])
+                tickets[k] = srv.submit(pool[k])
                 ready.release()
 
         t_start = time.perf_counter()
@@ -244,37 +252,42 @@ def served_form(requests, pool_size, lanes, seed=5):
         for k in range(requests):
             ready.acquire()
             lam, _, l = srv.wait(tickets[k], want_side=False)
-            ok = ok and lam == alone[order[k]]
+            lams[k] = lam
             lat.append(l["total_ms"])
         t_end = time.perf_counter()
         th.join()
         lat = np.asarray(lat)
         span = t_end - t_start
-        return {"requests": requests, "span_s": round(span, 3),
-                "edges_per_s": float(sum(pool[i].m for i in order) / span),
-                "requests_per_s": round(requests / span, 1),
-                "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "same_as_alone": bool(ok)}
+        out = {"requests": requests, "span_s": round(span, 3), "edges_per_s": float(sum_m / span),
+               "requests_per_s": round(requests / span, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        if ref is not None:
+            out["same_as_alone"] = bool(lams == ref)
+        if oracle_l is not None:
+            out["same_as_oracle"] = bool(lams == oracle_l)
+        return out, lams
 
-    cap = run(None)
-    log(f"served closed loop: {cap}")
     # the same requests as a host loop of single-graph solves, each uploaded
-    # from host memory like a served request
+    # from host memory like a served request: the "alone" results
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(requests):
-        g = pool[order[k]]
+    alone = []
+    for g in pool:
         rp, col, w = mc.to_device(g, "cuda:0")
-        mc.mincut(rp, col, w)
+        alone.append(mc.mincut(rp, col, w, want_side=False)[0])
     torch.cuda.synchronize()
     loop_s = time.perf_counter() - t0
-    looped = {"span_s": round(loop_s, 3), "edges_per_s": float(sum(pool[i].m for i in order) / loop_s)}
+    looped = {"span_s": round(loop_s, 3), "edges_per_s": float(sum_m / loop_s),
+              "same_as_oracle": bool(oracle_l is not None and alone == oracle_l)}
     log(f"looped single solves: {looped}")
-    out = {"pool": pool_size, "lanes": lanes, "mean_m": round(mean_m), "closed_loop": cap,
-           "looped": looped, "speedup_closed_loop": round(cap["edges_per_s"] / looped["edges_per_s"], 2)}
+    cap, _ = run(None, alone)
+    log(f"served closed loop: {cap}")
+    out = {"requests": requests, "distinct": True, "lanes": lanes, "sum_m": sum_m,
+           "mean_m": round(sum_m / requests), "closed_loop": cap, "looped": looped,
+           "speedup_closed_loop": round(cap["edges_per_s"] / looped["edges_per_s"], 2)}
     for frac in (0.3, 0.7):
-        r = run(frac * cap["requests_per_s"])
+        r, _ = run(frac * cap["requests_per_s"], alone)
         r["rate_frac"] = frac
         log(f"served at {frac} of capacity: {r}")
         out[f"at_{frac}"] = r
@@ -494,8 +507,7 @@ def main():
                     help="print scan-policy ablations (rounds against time) instead of the bench line")
     ap.add_argument("--no-loop", action="store_true",
                     help="batched form: skip the loop of single solves (profiling the packed solve alone)")
-    ap.add_argument("--requests", type=int, default=400)
-    ap.add_argument("--pool", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=2000, help="distinct served requests")
     ap.add_argument("--lanes", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (the reference "
@@ -534,7 +546,7 @@ def main():
         log(f"copied {x.numel() * 4} bytes three times")
         return
     if args.workload == "served":
-        sv = served_form(args.requests, args.pool, args.lanes)
+        sv = served_form(args.requests, args.lanes)
         out = {"metric": "served exact min-cut edges/s at 0.7 of capacity, p50/p99 latency, 1 GPU",
                "value": sv["at_0.7"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
                "steps": args.requests, "warmup": 8, "ms_per_step": sv["at_0.7"]["p50_ms"],
@@ -580,7 +592,7 @@ def main():
         if not args.no_batched:
             extra["batched"] = batched_form(max(1, min(args.steps, 3)), 1)
         if not args.no_served:
-            extra["served"] = served_form(args.requests, args.pool, args.lanes)
+            extra["served"] = served_form(args.requests, args.lanes)
     cpu = None
     if not args.only and not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload)

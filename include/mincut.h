@@ -172,7 +172,35 @@ typedef struct mc_options {
                               sums its edges into the batch); 1: always
                               pull; -1: always push.  Changes which pairs a
                               round unites, never lambda. */
-  int32_t reserved[2];
+  int32_t pq_order;        /* the priority-queue order among equal keys in
+                              the LDS sweeps' single pops and in region and
+                              whole-graph scans (section "Priority Queue
+                              Implementations"): 0 (default) the fastest
+                              (the lowest chunk and lane holding the
+                              maximum; in scans the highest map slot);
+                              1 bucket queue (BQueue: the vertex whose key
+                              last rose earliest); 2 bucket stack (BStack:
+                              the one whose key last rose latest); 3 heap
+                              (a fixed pseudo-random order).  Among the
+                              increases of one step, the row order stands
+                              in for push order (rows are sorted by
+                              neighbour id after the first contraction).
+                              Values outside 0..3: MC_EINVAL.  Changes
+                              which pairs a round unites, never lambda. */
+  int32_t scan_visits;     /* region and whole-graph scans (scan_mode 1 or
+                              2): a vertex may be visited by up to this
+                              many scans (the multi-visit variant of
+                              section "Parallel CAPFOREST"); 0 or 1
+                              (default): once.  A scan reports prefix cuts
+                              only up to its first repeated visit.
+                              Negative: MC_EINVAL. */
+  int32_t use_tuned;       /* 1: take sweep_threads, sweep_groups,
+                              sort_tile, pr_triangle_deg and pq_order from
+                              what mc_tune_batched chose for this
+                              problem's size class on the current device
+                              (see mc_tune_batched), when there is one;
+                              the caller's values otherwise.  Default 0. */
+  int32_t reserved[1];
 } mc_options;
 
 typedef struct mc_stats {
@@ -219,16 +247,23 @@ int mc_mincut_batched(const mc_batch* b, void* stream, const mc_options* opt, in
 
 /* Autotuner for the batched form (not in the paper: the packed form and its
  * launch shapes are this library's).  Solves the batch `b` once per
- * candidate launch shape and keeps the fastest: first the LDS sweep's
+ * candidate and keeps the fastest, one setting at a time: the LDS sweep's
  * threads per workgroup (128, 256, 512) and workgroups per compute unit
- * (2, 3), then, with that, the radix sort's keys per workgroup (2048, 4096,
- * 8192).  Each shape is solved `reps` times (at least 1) and its best wall
- * time counts.  Every solve must give the same lambdas (the shapes change
- * the schedule, never the result): otherwise MC_EMISMATCH.  base: the other
- * options (NULL = defaults); out->best is base with the chosen shape.
- * The batch's inputs are read only; no output buffer is written but *out. */
+ * (2, 3); the radix sort's keys per workgroup (2048, 4096, 8192); the
+ * triangle tests (off, from the first round, from the second); the
+ * priority-queue order among equal keys (pq_order 0..3, which changes the
+ * rounds).  Each candidate is solved `reps` times (at least 1) and its best
+ * wall time counts.  Every solve must give the same lambdas (the settings
+ * change the schedule and the rounds, never the result): otherwise
+ * MC_EMISMATCH.  base: the other options (NULL = defaults); out->best is
+ * base with the chosen settings.  The choice is also stored, for the
+ * current device, under the batch's size class: the bit lengths of its
+ * graph count, vertex total and entry total (a factor of two in each).
+ * Solves with use_tuned = 1 whose problem falls in a stored class take it.
+ * The store is process-wide and thread-safe.  The batch's inputs are read
+ * only; no output buffer is written but *out. */
 typedef struct mc_tune_result {
-  mc_options best;        /* base with sweep_threads, sweep_groups, sort_tile chosen */
+  mc_options best;        /* base with the chosen settings */
   int32_t candidates;     /* launch shapes solved */
   int32_t reps;           /* solves per shape */
   double best_ms;         /* best wall time of one packed solve with `best` */
@@ -236,6 +271,12 @@ typedef struct mc_tune_result {
 } mc_tune_result;
 int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int32_t reps,
                     mc_tune_result* out);
+/* The settings stored for b's size class on the current device, written
+ * into *opt's tuned fields: 1 if there were some, 0 if not (opt unchanged);
+ * MC_EINVAL for a NULL argument.  Reads only b's counts. */
+int mc_tune_lookup(const mc_batch* b, mc_options* opt);
+/* Forget every stored setting. */
+void mc_tune_clear(void);
 
 /* Test hook for per-step parity: runs ingest and the first round's
  * Padberg-Rinaldi tests and CAPFOREST scans (Algorithm 2, first loop

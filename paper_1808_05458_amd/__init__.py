@@ -62,7 +62,8 @@ class Options(ctypes.Structure):
                 ("approx_ppm", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("sweep_tail", ctypes.c_int32), ("sweep_pull", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("pq_order", ctypes.c_int32), ("scan_visits", ctypes.c_int32),
+                ("use_tuned", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -142,6 +143,10 @@ def _load():
     lib.mc_mincut_batched.restype = ctypes.c_int
     lib.mc_tune_batched.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
     lib.mc_tune_batched.restype = ctypes.c_int
+    lib.mc_tune_lookup.argtypes = [vp, vp]
+    lib.mc_tune_lookup.restype = ctypes.c_int
+    lib.mc_tune_clear.argtypes = []
+    lib.mc_tune_clear.restype = None
     lib.mc_debug_first_round.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mc_debug_first_round.restype = ctypes.c_int
     lib.mc_debug_contract.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
@@ -363,8 +368,10 @@ def mincut_batched(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool =
 
 def tune_batched(row_ptr, col, w, vtx_off: Sequence[int], *, reps: int = 2, stream=None,
                  opts: Optional[Options] = None, **kw):
-    """Autotune the batched form's launch shapes on this batch.  Returns
-    (Options with the chosen shape, report dict)."""
+    """Autotune the batched form on this batch (launch shapes, triangle
+    tests, priority-queue order); the choice is also stored for the batch's
+    size class, where solves with use_tuned=1 find it.  Returns (Options
+    with the chosen settings, report dict)."""
     import torch
     lib = _load()
     voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
@@ -383,8 +390,33 @@ def tune_batched(row_ptr, col, w, vtx_off: Sequence[int], *, reps: int = 2, stre
     ctypes.memmove(ctypes.byref(best), ctypes.byref(out.best), ctypes.sizeof(Options))
     report = {"candidates": out.candidates, "reps": out.reps, "best_ms": out.best_ms,
               "default_ms": out.default_ms, "sweep_threads": best.sweep_threads,
-              "sweep_groups": best.sweep_groups, "sort_tile": best.sort_tile}
+              "sweep_groups": best.sweep_groups, "sort_tile": best.sort_tile,
+              "pr_triangle_deg": best.pr_triangle_deg, "pq_order": best.pq_order}
     return best, report
+
+
+def tune_lookup(n_total: int, nnz_total: int, vtx_off: Sequence[int], opts: Optional[Options] = None):
+    """The stored tuned settings for a batch of this size class (graph
+    count len(vtx_off) - 1, n_total vertices, nnz_total entries) applied to
+    a copy of opts (defaults if None), or None when none are stored."""
+    lib = _load()
+    voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    b = Batch(len(voff) - 1, int(n_total), int(nnz_total), None, None, None,
+              voff.ctypes.data_as(ctypes.c_void_p))
+    o = Options()
+    if opts is not None:
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(opts), ctypes.sizeof(Options))
+    else:
+        lib.mc_options_default(ctypes.byref(o))
+    rc = lib.mc_tune_lookup(ctypes.byref(b), ctypes.byref(o))
+    if rc < 0:
+        raise MincutError(rc, "mc_tune_lookup")
+    return o if rc == 1 else None
+
+
+def tune_clear():
+    """Forget every stored tuned setting."""
+    _load().mc_tune_clear()
 
 
 def viecut_bound(row_ptr, col, w, vtx_off: Sequence[int], *, want_side: bool = True, stream=None,

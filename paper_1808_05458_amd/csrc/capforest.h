@@ -83,12 +83,18 @@ struct ScanArgs {
   int32_t eager;         // skip neighbours already claimed by another scan
   int32_t max_pops;
   uint64_t seed;
+  int32_t order;         // ORD kernels: the order among equal keys (tie_rank)
+  int32_t visits;        // a vertex may be visited by up to this many scans
+  int32_t* vcount;       // visits > 1: per vertex, the visits after the first
 };
 
-template <int CAP>
+// ORD: each slot also keeps the pop count of its vertex's last increase,
+// which orders equal keys.
+template <int CAP, bool ORD = false>
 struct ScanLds {
   uint32_t vid[CAP];
   int32_t r[CAP];
+  uint16_t tick[ORD ? CAP : 2];
   int32_t used;
   int32_t pad[3];
 };
@@ -100,8 +106,8 @@ __device__ __forceinline__ uint32_t slot_hash(uint32_t v) {
 }
 
 // Find y's slot, inserting it if absent.  -1 when the map is too full.
-template <int CAP>
-__device__ __forceinline__ int map_find_insert(ScanLds<CAP>& m, uint32_t y) {
+template <int CAP, bool ORD>
+__device__ __forceinline__ int map_find_insert(ScanLds<CAP, ORD>& m, uint32_t y) {
   uint32_t h = slot_hash<CAP>(y);
   for (int probe = 0; probe < 64; ++probe) {
     uint32_t cur = m.vid[h];
@@ -127,11 +133,22 @@ __device__ __forceinline__ uint32_t perm_at(uint64_t a, uint64_t b, int bits, ui
 }
 
 // One bounded scan from `start` inside graph g.  Returns pairs recorded.
-template <int CAP>
-__device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, int32_t g) {
+//
+// With A.visits > 1 a vertex already visited by another scan may be visited
+// again, by at most visits - 1 more scans (the multi-visit variant of section
+// "Parallel CAPFOREST"): each scan stays a bounded CAPFOREST of its own, so
+// its pairs stay contractible.  claim and step describe only first visits, so
+// a scan reports prefix cuts only while every vertex it visited was a first
+// visit.
+template <int CAP, bool ORD>
+__device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP, ORD>& m, int32_t start, int32_t g) {
   const int lane = lane_id();
   // clear the map
-  for (int s = lane; s < CAP; s += 64) { m.vid[s] = SLOT_EMPTY; m.r[s] = 0; }
+  for (int s = lane; s < CAP; s += 64) {
+    m.vid[s] = SLOT_EMPTY;
+    m.r[s] = 0;
+    if constexpr (ORD) m.tick[s] = 0;
+  }
   if (lane == 0) m.used = 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -148,41 +165,69 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
   int64_t alpha = 0, best_a = INT64_MAX;
   int32_t k = 0, best_k = 0;
   int64_t npairs = 0;
-  bool stop = false;
+  bool stop = false, first_visits = true;
   while (!stop) {
-    // pop_max: argmax of capped keys over frontier slots
-    uint64_t best = 0;
-    for (int s = lane; s < CAP; s += 64) {
-      uint32_t u = m.vid[s];
-      if (u != SLOT_EMPTY && !(u & (ST_VISITED | ST_BLACK))) {
-        int64_t key = m.r[s];
-        if (key > lam) key = lam;
-        uint64_t c = ((uint64_t)(key + 1) << 32) | (uint32_t)s;
-        best = c > best ? c : best;
+    // pop_max: argmax of capped keys over frontier slots (ORD: then the
+    // rank of the chosen order, with the slot taken from the lane holding it)
+    int slot;
+    if constexpr (ORD) {
+      uint64_t best = 0;
+      int mine = 0;
+      for (int s = lane; s < CAP; s += 64) {
+        uint32_t u = m.vid[s];
+        if (u != SLOT_EMPTY && !(u & (ST_VISITED | ST_BLACK))) {
+          int64_t key = m.r[s];
+          if (key > lam) key = lam;
+          uint64_t c = ((uint64_t)(key + 1) << 32) | tie_rank(A.order, m.tick[s], u & VID_MASK);
+          if (c > best) { best = c; mine = s; }
+        }
       }
+      const uint64_t top = wave_max_u64(best);
+      if (top == 0) break;  // queue empty
+      slot = __builtin_amdgcn_readlane(mine, (int)__builtin_ctzll(ballot(best == top)));
+    } else {
+      uint64_t best = 0;
+      for (int s = lane; s < CAP; s += 64) {
+        uint32_t u = m.vid[s];
+        if (u != SLOT_EMPTY && !(u & (ST_VISITED | ST_BLACK))) {
+          int64_t key = m.r[s];
+          if (key > lam) key = lam;
+          uint64_t c = ((uint64_t)(key + 1) << 32) | (uint32_t)s;
+          best = c > best ? c : best;
+        }
+      }
+      best = wave_max_u64(best);
+      if (best == 0) break;  // queue empty
+      slot = (int)(uint32_t)best;
     }
-    best = wave_max_u64(best);
-    if (best == 0) break;  // queue empty
-    const int slot = (int)(uint32_t)best;
     const int32_t x = (int32_t)(m.vid[slot] & VID_MASK);
     const int64_t rx = m.r[slot];
     int32_t old = 0;
     if (lane == 0) old = atomicCAS(A.claim + x, -1, sid);
     old = bcast(old, 0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (old != -1 && old != sid) {
-      if (lane == 0) m.vid[slot] |= ST_BLACK;  // visited elsewhere: blacklist, leave at once
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      continue;
+    const bool first = old == -1 || old == sid;
+    if (!first) {
+      // visited elsewhere: visit it again while visits are left, else
+      // blacklist it and leave it at once
+      int32_t again = 0;
+      if (lane == 0 && A.visits > 1) again = atomicAdd(A.vcount + x, 1) < A.visits - 1;
+      again = bcast(again, 0);
+      if (!again) {
+        if (lane == 0) m.vid[slot] |= ST_BLACK;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        continue;
+      }
+      first_visits = false;
     }
     if (lane == 0) {
       m.vid[slot] |= ST_VISITED;
-      A.step[x] = k + 1;
+      if (first) A.step[x] = k + 1;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     ++k;
     alpha += A.cdeg[x] - 2 * rx;  // alpha = c(S) with S the visited prefix
-    if (k < ng && alpha < best_a) { best_a = alpha; best_k = k; }
+    if (first_visits && k < ng && alpha < best_a) { best_a = alpha; best_k = k; }
     if (k >= A.max_pops) stop = true;
 
     const int64_t e0 = A.rp[x], e1 = A.rp[x + 1];
@@ -199,7 +244,7 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
       if (y == x) act = false;
       if (act && A.eager) {
         int32_t cl = ld_relaxed(A.claim + y);
-        if (cl != -1 && cl != sid) act = false;
+        if (cl != -1 && cl != sid && (A.visits <= 1 || ld_relaxed(A.vcount + y) >= A.visits - 1)) act = false;
       }
       int sl = -1;
       if (act) {
@@ -212,6 +257,7 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
         if (u & (ST_VISITED | ST_BLACK)) act = false;
       }
       if (act) {
+        if constexpr (ORD) m.tick[sl] = (uint16_t)k;
         int64_t before = atomicAdd(&m.r[sl], c);
         int64_t after = before + c;
         cross = before < lam && lam <= after;  // crossing rule of Algorithm 1
@@ -254,11 +300,11 @@ __device__ int64_t run_scan(const ScanArgs& A, ScanLds<CAP>& m, int32_t start, i
 // at a seeded vertex and covering the whole graph (the map holds it).
 // Otherwise: region scans started at unclaimed vertices taken in a seeded
 // pseudo-random order, 64 candidates per work item.
-template <int CAP>
+template <int CAP, bool ORD = false>
 __global__ void __launch_bounds__(256) k_capforest(ScanArgs A) {
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  ScanLds<CAP>& m = reinterpret_cast<ScanLds<CAP>*>(lds_raw)[wave];
+  ScanLds<CAP, ORD>& m = reinterpret_cast<ScanLds<CAP, ORD>*>(lds_raw)[wave];
   while (true) {
     int32_t item = 0;
     if (lane == 0) item = atomicAdd(&A.ctl->work_next, 1);
@@ -270,7 +316,7 @@ __global__ void __launch_bounds__(256) k_capforest(ScanArgs A) {
       uint64_t h = A.seed * 0x9E3779B97F4A7C15ull + (uint64_t)g * 0xBF58476D1CE4E5B9ull;
       h ^= h >> 29;
       const int32_t start = A.gvoff[g] + (int32_t)(h % (uint64_t)ng);
-      run_scan<CAP>(A, m, start, g);
+      run_scan<CAP, ORD>(A, m, start, g);
       continue;
     }
     const uint64_t span = 1ull << A.perm_bits;
@@ -285,7 +331,7 @@ __global__ void __launch_bounds__(256) k_capforest(ScanArgs A) {
       todo &= todo - 1;
       const int32_t s = bcast((int32_t)v, src_lane);
       if (ld_relaxed(A.claim + s) != -1) continue;
-      run_scan<CAP>(A, m, s, A.gid[s]);
+      run_scan<CAP, ORD>(A, m, s, A.gid[s]);
     }
   }
 }

@@ -25,6 +25,23 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 
+// Rank of a vertex among equal priority keys (the larger rank is taken
+// first), for the priority-queue orders of section "Priority Queue
+// Implementations".  tick is the step of the vertex's last key increase;
+// one step's increases share it, and a contracted graph's rows list their
+// neighbours by increasing id, so the id's low 16 bits order the increases
+// of one step as a bucket would have received them.  Order 1 (bucket
+// queue): earliest increase first, then the smaller id.  Order 2 (bucket
+// stack): latest increase first, then the larger id.  Order 3 (heap): a
+// fixed pseudo-random order of the vertices, favouring neither old nor new
+// increases.
+__device__ __forceinline__ uint32_t tie_rank(int32_t order, uint32_t tick, uint32_t v) {
+  const uint32_t lo = v & 0xFFFFu;
+  if (order == 1) return ((0xFFFFu - (tick & 0xFFFFu)) << 16) | (0xFFFFu - lo);
+  if (order == 2) return ((tick & 0xFFFFu) << 16) | lo;
+  return ((v * 0x9E3779B1u) & 0xFFFF0000u) | (0xFFFFu - lo);
+}
+
 template <typename T>
 __device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, MC_WAVE); }
 
@@ -176,6 +193,29 @@ __device__ __forceinline__ bool uf_union(P parent, int32_t a, int32_t b) {
     if (a == b) return false;
     if (a > b) { int32_t t = a; a = b; b = t; }
     // link the larger root b under the smaller root a
+    int32_t expected = b;
+    if (__hip_atomic_compare_exchange_strong(parent + b, &expected, a, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+    b = expected;  // b gained a parent meanwhile; retry from there
+  }
+}
+
+// The same union with the root of smaller key(root) kept as the root.  Any
+// fixed strict total order of the vertices keeps the forest acyclic: a root
+// is only ever linked under a root of smaller key, whatever order linked
+// the trees before.  The order decides the shape: when most pairs join a
+// vertex that was never linked to a tree that grows, keying the roots by
+// when they joined (earliest first) links each newcomer under the old root
+// with a compare-and-swap on its own word, where an order by vertex id
+// would keep moving the big tree's root and make every pair retry on it.
+template <typename P, typename Key>
+__device__ __forceinline__ bool uf_union_by(P parent, int32_t a, int32_t b, Key key) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return false;
+    if (key(a) > key(b)) { int32_t t = a; a = b; b = t; }
     int32_t expected = b;
     if (__hip_atomic_compare_exchange_strong(parent + b, &expected, a, __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))

@@ -149,7 +149,7 @@ struct Workspace {
   // or the caller's (opt->workspace)
   void* block = nullptr;
   // vertex arrays
-  int32_t *gid[2], *parent, *lab, *claim, *step, *capq, *capx, *sw_seg, *newid,
+  int32_t *gid[2], *parent, *lab, *claim, *step, *vcount, *capq, *capx, *sw_seg, *newid,
       *map, *ogid;
   SweepCtl* sweep;                  // sweep_slots queues
   int32_t sweep_slots = 0;          // full-graph sweeps run at once (at most MAX_SWEEPS)
@@ -161,6 +161,7 @@ struct Workspace {
   uint64_t* fb_rs;  // sweeps: per vertex (r, visit stamp)
   // entry arrays
   int32_t *src, *col, *w;
+  int32_t* first;  // the row of every WCH-th entry of the graph being read (k_chunk_rows)
   uint64_t *keys, *keys_alt;
   int32_t *vals, *vals_alt;
   // graph arrays
@@ -264,6 +265,7 @@ size_t carve(Workspace& ws, char* base, int64_t N, int64_t E, int64_t G) {
   take(ws.lab, (N + 1) * 4);
   take(ws.claim, (N + 1) * 4);
   take(ws.step, (N + 1) * 4);
+  take(ws.vcount, (N + 1) * 4);
   take(ws.fb_rs, (N + 1) * 8);
   take(ws.newid, (N + 1) * 4);
   take(ws.map, (N + 1) * 4);
@@ -281,6 +283,7 @@ size_t carve(Workspace& ws, char* base, int64_t N, int64_t E, int64_t G) {
   take(ws.rp, (N + 2) * 8);
   take(ws.cdeg, (N + 2) * 8);
   take(ws.src, E * 4);
+  take(ws.first, (E / WCH + 2) * 4);
   take(ws.col, E * 4);
   take(ws.w, E * 4);
   take(ws.keys, (E + 64) * 8);
@@ -469,17 +472,29 @@ static int bitlen(uint64_t x) { return x == 0 ? 0 : 64 - __builtin_clzll(x); }
 // and workgroups per compute unit (at most what the CU's 160 KiB of LDS
 // holds).  The workgroups take graphs from a shared counter, so any shape
 // gives the same sweeps.
-template <int T>
+template <int T, bool ORD>
 static void launch_small_sweep_t(int groups, int num_cu, const SmallSweepArgs& SA, hipStream_t s) {
-  constexpr int bytes = (int)sizeof(SmallSweepLds<SMALL_CAP_L, T>);
+  constexpr int bytes = (int)sizeof(SmallSweepLds<SMALL_CAP_L, T, ORD>);
   const int fit = std::max(1, LDS_PER_CU / bytes);
   groups = std::max(1, std::min(groups > 0 ? groups : 3, fit));
-  hipLaunchKernelGGL((k_small_sweep<SMALL_CAP_L, T>), dim3(num_cu * groups), dim3(T), bytes, s, SA);
+  hipLaunchKernelGGL((k_small_sweep<SMALL_CAP_L, T, ORD>), dim3(num_cu * groups), dim3(T), bytes, s, SA);
 }
+// SA.order > 0: the kernels that follow a priority-queue order among equal keys
 static void launch_small_sweep(int threads, int groups, int num_cu, const SmallSweepArgs& SA, hipStream_t s) {
-  if (threads == 128) launch_small_sweep_t<128>(groups, num_cu, SA, s);
-  else if (threads == 512) launch_small_sweep_t<512>(groups, num_cu, SA, s);
-  else launch_small_sweep_t<256>(groups, num_cu, SA, s);
+  if (SA.order > 0) {
+    if (threads == 128) launch_small_sweep_t<128, true>(groups, num_cu, SA, s);
+    else if (threads == 512) launch_small_sweep_t<512, true>(groups, num_cu, SA, s);
+    else launch_small_sweep_t<256, true>(groups, num_cu, SA, s);
+    return;
+  }
+  if (threads == 128) launch_small_sweep_t<128, false>(groups, num_cu, SA, s);
+  else if (threads == 512) launch_small_sweep_t<512, false>(groups, num_cu, SA, s);
+  else launch_small_sweep_t<256, false>(groups, num_cu, SA, s);
+}
+
+// Opt a kernel into more than 64 KiB of dynamic LDS.
+static hipError_t allow_lds(const void* fn, int bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // Workgroups of a kernel (threads per workgroup, no dynamic LDS) resident on
@@ -515,6 +530,43 @@ struct Solver {
   mc_stats* stats_out = nullptr;    // per-phase sweep counters (when wanted)
   CallerBlock cb;                   // the caller's workspace, if any
   int32_t ngraphs = 1;              // graphs in the problem being solved
+  // ws.first is valid for the graph (rp, n, nnz) named here; a contraction
+  // makes it stale
+  const int64_t* first_rp = nullptr;
+  int32_t first_n = -1;
+  int64_t first_nnz = -1;
+  // ws.src holds the sources of the loop's current graph (the ingest leaves
+  // them unwritten; only some consumers index entries one at a time)
+  bool src_ok = false;
+
+  // The row of every WCH-th entry of graph (n, nnz, rp) in ws.first.
+  void need_first(int32_t n, int64_t nnz, const int64_t* rp) {
+    if (first_rp == rp && first_n == n && first_nnz == nnz) return;
+    if (nnz > 0) {
+      // row_ptr read once, one int per WCH entries written
+      TimedScope t("k_chunk_rows", (double)n * 8 + (double)(nnz / WCH) * 4);
+      hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(n, 256, num_cu * 16)), dim3(256), 0, s, n, rp, ws.first);
+    }
+    first_rp = rp;
+    first_n = n;
+    first_nnz = nnz;
+  }
+  // Launch grid for one wave per WCH-entry chunk, at most `cap` workgroups.
+  static dim3 chunk_grid(int64_t nnz, int cap) {
+    return dim3(grid_for((nnz + WCH - 1) / WCH * 64, 256, cap));
+  }
+  // src[e] = the row of entry e of graph (n, nnz, rp).
+  void fill_src(int32_t n, int64_t nnz, const int64_t* rp, int32_t* src) {
+    if (nnz <= 0) return;
+    need_first(n, nnz, rp);
+    TimedScope t("k_fill_src", (double)nnz * 4 + (double)n * 8);
+    hipLaunchKernelGGL(k_fill_src, chunk_grid(nnz, num_cu * 8), dim3(256), 0, s, n, nnz, rp, ws.first, src);
+  }
+  void need_src(int32_t n, int64_t nnz, const int64_t* rp) {
+    if (src_ok) return;
+    fill_src(n, nnz, rp, ws.src);
+    src_ok = true;
+  }
 
   int read_ctl() {
     MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -845,7 +897,7 @@ struct Solver {
     int64_t *rp, *cdeg;
   };
 
-  // Contract the graph given per entry (src, col, w over nnz entries) by the
+  // Contract the graph given as CSR (rp_cur, col, w over nnz entries) by the
   // block of every vertex (lab in [0, n_next), -1 = dropped) into n_next
   // vertices (Preliminaries, contraction G/(u,v); section "Parallel Graph
   // Contraction"): emit a (lab u, lab v) key per crossing entry, radix-sort,
@@ -854,7 +906,7 @@ struct Solver {
   // The entry inputs are consumed before the outputs are written, so `out`
   // may alias them.
   // n_cur, gid_cur: the graph being contracted (vertex count, graph ids).
-  int contract(int64_t nnz, const int32_t* src, const int32_t* col, const int32_t* w, const int32_t* lab,
+  int contract(int64_t nnz, const int64_t* rp_cur, const int32_t* col, const int32_t* w, const int32_t* lab,
                int32_t n_cur, const int32_t* gid_cur, int32_t n_next, const int32_t* gid_next, Out out,
                int64_t* m2_out, const StageNames& nm) {
     const int TB = 256;
@@ -870,13 +922,15 @@ struct Solver {
       hipLaunchKernelGGL(k_block_bits, dim3(grid_for(n_cur, TB, num_cu * 16)), dim3(TB), 0, s, n_cur, lab, gid_cur,
                          ws.bref, ws.inref);
     }
+    need_first(n_cur, nnz, rp_cur);
     {
       // per entry col and w and the label gather (12 B); per emitted entry
       // its key and weight (12 B, added once the count is read back)
       TimedScope t(nm.emit, (double)nnz * 12);
       static const int emit_grid = resident_grid((const void*)&k_emit, TB, num_cu);
-      hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, emit_grid)), dim3(TB), 0, s, nnz,
-                         src, col, w, lab, bb, ws.inref, ws.keys, ws.vals, ws.ctl);
+      if (nnz > 0)
+        hipLaunchKernelGGL(k_emit, chunk_grid(nnz, emit_grid), dim3(TB), 0, s, n_cur, nnz, rp_cur, ws.first, col,
+                           w, lab, bb, ws.inref, ws.keys, ws.vals, ws.ctl);
     }
     int rc = read_ctl();
     if (rc) return rc;
@@ -925,6 +979,7 @@ struct Solver {
                          (const int32_t*)nullptr, ws.bdeg, (int64_t*)nullptr);
     }
     *m2_out = m2;
+    first_rp = nullptr;  // the graphs may have been written over
     return MC_OK;
   }
 
@@ -983,7 +1038,7 @@ struct Solver {
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
       int64_t m2 = 0;
       Out o{V.src[next], V.col[next], V.w[next], V.rp[next], V.cdeg[next]};
-      int r = contract(nnz, src, col, w, ws.lab, n, gid, n_next, V.gid[next], o, &m2, kVcNames);
+      int r = contract(nnz, rp, col, w, ws.lab, n, gid, n_next, V.gid[next], o, &m2, kVcNames);
       if (r) return r;
       exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff, (int32_t*)nullptr,
                                                 ws.tmp, s);
@@ -1052,8 +1107,9 @@ struct Solver {
                              ws.parent, ws.ucount);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, ws.lhat, V.act, ws.ctl);
-          hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, src, col, w, cdeg, gid, ws.lhat, V.act,
-                             ws.parent, ws.ucount, ws.ctl);
+          need_first(n, nnz, rp);
+          hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(TB), 0, s, n, nnz, rp, ws.first, col, w,
+                             cdeg, gid, ws.lhat, V.act, ws.parent, ws.ucount, ws.ctl);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, V.act, carry}, n, ws.newid, &ws.ctl->n_next,
                                             ws.tmp, s);
@@ -1094,24 +1150,20 @@ struct Solver {
     static std::once_flag attrs_once;
     static hipError_t attrs_err = hipSuccess;
     std::call_once(attrs_once, [] {
-      hipError_t e = hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_L>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)sizeof(ScanLds<WHOLE_CAP_L>));
-      if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_capforest<WHOLE_CAP_S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(ScanLds<WHOLE_CAP_S>));
-      if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L, 128>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(SmallSweepLds<SMALL_CAP_L, 128>));
-      if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L, 256>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(SmallSweepLds<SMALL_CAP_L, 256>));
-      if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_small_sweep<SMALL_CAP_L, 512>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(SmallSweepLds<SMALL_CAP_L, 512>));
+      const std::pair<const void*, int> big[] = {
+          {(const void*)k_capforest<WHOLE_CAP_L, false>, (int)sizeof(ScanLds<WHOLE_CAP_L, false>)},
+          {(const void*)k_capforest<WHOLE_CAP_S, false>, (int)sizeof(ScanLds<WHOLE_CAP_S, false>)},
+          {(const void*)k_capforest<WHOLE_CAP_L, true>, (int)sizeof(ScanLds<WHOLE_CAP_L, true>)},
+          {(const void*)k_capforest<WHOLE_CAP_S, true>, (int)sizeof(ScanLds<WHOLE_CAP_S, true>)},
+          {(const void*)k_small_sweep<SMALL_CAP_L, 128, false>, (int)sizeof(SmallSweepLds<SMALL_CAP_L, 128, false>)},
+          {(const void*)k_small_sweep<SMALL_CAP_L, 256, false>, (int)sizeof(SmallSweepLds<SMALL_CAP_L, 256, false>)},
+          {(const void*)k_small_sweep<SMALL_CAP_L, 512, false>, (int)sizeof(SmallSweepLds<SMALL_CAP_L, 512, false>)},
+          {(const void*)k_small_sweep<SMALL_CAP_L, 128, true>, (int)sizeof(SmallSweepLds<SMALL_CAP_L, 128, true>)},
+          {(const void*)k_small_sweep<SMALL_CAP_L, 256, true>, (int)sizeof(SmallSweepLds<SMALL_CAP_L, 256, true>)},
+          {(const void*)k_small_sweep<SMALL_CAP_L, 512, true>, (int)sizeof(SmallSweepLds<SMALL_CAP_L, 512, true>)}};
+      hipError_t e = hipSuccess;
+      for (const auto& k : big)
+        if (e == hipSuccess) e = allow_lds(k.first, k.second);
       attrs_err = e;
     });
     MC_HIP(attrs_err);
@@ -1142,16 +1194,15 @@ struct Solver {
       fill<int64_t>(ws.cdeg, 0, N, s);
       fill<int32_t>(ws.gmaxw, 0, G, s);
       if (E > 0) {
-        // chunk first rows in the sort keys' buffer (free until the first contraction)
-        int32_t* first = (int32_t*)ws.keys;
-        hipLaunchKernelGGL(k_chunk_rows, grid(N), dim3(TB), 0, s, N, P.rp, first);
+        need_first(N, E, P.rp);
         // per entry col and w (8 B); per vertex its row bounds and its
         // weighted degree (16 B)
         TimedScope t("k_ingest", (double)E * 8 + (double)N * 16);
         static const int ingest_grid = resident_grid((const void*)&k_ingest, TB, num_cu);
-        hipLaunchKernelGGL(k_ingest, dim3(grid_for((E + INGEST_CH - 1) / INGEST_CH * TB, TB, ingest_grid)), dim3(TB),
-                           0, s, N, E, P.rp, P.col, P.w, gid, ws.voff, first, ws.src, ws.cdeg, ws.gmaxw, ws.ctl);
+        hipLaunchKernelGGL(k_ingest, chunk_grid(E, ingest_grid), dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid,
+                           ws.voff, ws.first, ws.cdeg, ws.gmaxw, ws.ctl);
       }
+      src_ok = false;
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
       fill<int64_t>(ws.wsum, 0, G, s);
       hipLaunchKernelGGL(k_min_degree, gridr(N), dim3(TB), 0, s, N, ws.cdeg, gid, (const int32_t*)nullptr,
@@ -1162,6 +1213,7 @@ struct Solver {
     if (rc) return rc;
     if (ws.ctl_host->err) return MC_EINVAL;
     if (opt.validate && E > 0) {
+      need_src(N, E, P.rp);
       rc = check_symmetry(N, E, P.col, P.w);
       if (rc) return rc;
     }
@@ -1172,6 +1224,7 @@ struct Solver {
       // one vertex has degree 0.
       TimedScope t("connectivity", (double)E * 8 + (double)N * 16);
       hipLaunchKernelGGL(k_iota, grid(N), dim3(TB), 0, s, ws.parent, N);
+      need_src(N, E, P.rp);
       hipLaunchKernelGGL(k_union_all_edges, grid(E), dim3(TB), 0, s, E, ws.src, P.col, ws.parent);
       hipLaunchKernelGGL(k_flatten, grid(N), dim3(TB), 0, s, N, ws.parent);
       fill<int32_t>(ws.nnew, 0, G, s);
@@ -1258,8 +1311,10 @@ struct Solver {
       rp = last.rp;
       col = last.col;
       w = last.w;
-      if (last.src != ws.src && nnz > 0)
+      if (last.src != ws.src && nnz > 0) {
         MC_HIP(hipMemcpyAsync(ws.src, last.src, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s));
+        src_ok = true;
+      }
       if (last.cdeg != ws.cdeg)
         MC_HIP(hipMemcpyAsync(ws.cdeg, last.cdeg, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
       if (last.gid != gid) MC_HIP(hipMemcpyAsync(gid, last.gid, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
@@ -1287,6 +1342,7 @@ struct Solver {
       hipLaunchKernelGGL(k_round_reset, grid(G), dim3(TB), 0, s, G, S);
       hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
       fill<int32_t>(ws.claim, -1, n, s);
+      if (opt.scan_visits > 1) fill<int32_t>(ws.vcount, 0, n, s);
       if (opt.use_pr && (round > 1 || pr_first_round)) {
         const int32_t* tested = (round == 1 && !pr_first_all) ? ws.prok : ws.active;
         {
@@ -1303,14 +1359,16 @@ struct Solver {
           // is rejected from it alone), per vertex its row bounds and c(u)
           // (16 B): a lower bound of what the tests must read
           TimedScope t("k_pr", (double)nnz * 4 + (double)n * 16);
-          hipLaunchKernelGGL(k_pr, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, ws.cdeg, gid,
-                             cap, tested, ws.parent, ws.ucount, ws.ctl);
+          need_first(n, nnz, rp);
+          hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(TB), 0, s, n, nnz, rp, ws.first, col, w,
+                             ws.cdeg, gid, cap, tested, ws.parent, ws.ucount, ws.ctl);
         }
       }
       // the triangle tests on contracted graphs (from the second round; a
       // negative limit also tests the input): per tested edge both rows
       const int32_t tri_deg = opt.pr_triangle_deg < 0 ? -opt.pr_triangle_deg : opt.pr_triangle_deg;
       if (opt.use_pr && tri_deg > 0 && (round > 1 || opt.pr_triangle_deg < 0)) {
+        need_src(n, nnz, rp);
         TimedScope t("k_pr34", (double)nnz * 20);
         hipLaunchKernelGGL(k_pr34, grid(nnz), dim3(TB), 0, s, nnz, ws.src, col, w, rp, ws.cdeg, gid, cap,
                            ws.active, tri_deg, ws.parent, ws.ucount, ws.ctl);
@@ -1331,6 +1389,9 @@ struct Solver {
       A.ucount = ws.ucount; A.ctl = ws.ctl;
       A.eager = opt.eager_blacklist;
       A.max_pops = opt.max_pops > 0 ? opt.max_pops : INT32_MAX;
+      A.order = opt.pq_order;
+      A.visits = opt.scan_visits > 1 ? opt.scan_visits : 1;
+      A.vcount = ws.vcount;
       uint64_t rs = seed + 0x9E3779B97F4A7C15ull * (uint64_t)round;
       rs ^= rs >> 31;
       rs *= 0xBF58476D1CE4E5B9ull;
@@ -1350,9 +1411,13 @@ struct Solver {
         A.whole = ws.whole;
         A.whole_count = &ws.ctl->n_region;  // unused in region mode
         const int wpb = 4;
-        size_t lds = sizeof(ScanLds<REGION_CAP>) * wpb;
         int blocks = std::max(1, region_waves / wpb);
-        hipLaunchKernelGGL(k_capforest<REGION_CAP>, dim3(blocks), dim3(64 * wpb), lds, s, A);
+        if (A.order > 0)
+          hipLaunchKernelGGL((k_capforest<REGION_CAP, true>), dim3(blocks), dim3(64 * wpb),
+                             sizeof(ScanLds<REGION_CAP, true>) * wpb, s, A);
+        else
+          hipLaunchKernelGGL((k_capforest<REGION_CAP, false>), dim3(blocks), dim3(64 * wpb),
+                             sizeof(ScanLds<REGION_CAP, false>) * wpb, s, A);
       }
       if (hashed) {
         TimedScope t("capforest_whole", 0.0);
@@ -1361,19 +1426,27 @@ struct Solver {
         A.whole_mode = 1;
         A.whole = ws.whole;
         A.whole_count = &ws.ctl->n_whole;
-        hipLaunchKernelGGL(k_capforest<WHOLE_CAP_S>, dim3(num_cu * 4), dim3(64),
-                           sizeof(ScanLds<WHOLE_CAP_S>), s, A);
+        if (A.order > 0)
+          hipLaunchKernelGGL((k_capforest<WHOLE_CAP_S, true>), dim3(num_cu * 4), dim3(64),
+                             sizeof(ScanLds<WHOLE_CAP_S, true>), s, A);
+        else
+          hipLaunchKernelGGL((k_capforest<WHOLE_CAP_S, false>), dim3(num_cu * 4), dim3(64),
+                             sizeof(ScanLds<WHOLE_CAP_S, false>), s, A);
         MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
         A.whole = ws.whole2;
         A.whole_count = &ws.ctl->n_whole2;
-        hipLaunchKernelGGL(k_capforest<WHOLE_CAP_L>, dim3(num_cu * 2), dim3(64),
-                           sizeof(ScanLds<WHOLE_CAP_L>), s, A);
+        if (A.order > 0)
+          hipLaunchKernelGGL((k_capforest<WHOLE_CAP_L, true>), dim3(num_cu * 2), dim3(64),
+                             sizeof(ScanLds<WHOLE_CAP_L, true>), s, A);
+        else
+          hipLaunchKernelGGL((k_capforest<WHOLE_CAP_L, false>), dim3(num_cu * 2), dim3(64),
+                             sizeof(ScanLds<WHOLE_CAP_L, false>), s, A);
       } else {
         // whole small graphs: LDS-resident capped sweeps, one workgroup each,
         // the large-map list first (both lists are ordered largest first)
         SmallSweepArgs SA{rp, col, w, ws.cdeg, cap, ws.gn, ws.cvoff, ws.whole2, &ws.ctl->n_whole2, ws.whole,
                           &ws.ctl->n_whole, &ws.ctl->work_next, ws.fb_rs, ws.capq, ws.capx, ws.npairs,
-                          ws.balpha, ws.fb_k, ws.ucount, A.seed};
+                          ws.balpha, ws.fb_k, ws.ucount, A.seed, opt.pq_order};
         {
           TimedScope t("k_small_sweep", 0.0);
           MC_HIP(hipMemsetAsync(&ws.ctl->work_next, 0, sizeof(int32_t), s));
@@ -1447,9 +1520,10 @@ struct Solver {
       if (st) st->pairs_scan += ws.ctl_host->pairs;
       // contraction: emit, sort, merge, CSR, degrees
       int64_t m2 = 0;
-      rc = contract(nnz, ws.src, col, w, ws.lab, n, gid, n_next, gid_next,
+      rc = contract(nnz, rp, col, w, ws.lab, n, gid, n_next, gid_next,
                     Out{ws.src, ws.col, ws.w, ws.rp, ws.cdeg}, &m2, kExactNames);
       if (rc) return rc;
+      src_ok = true;
       exclusive_scan<int32_t, ArrayIn<int32_t>>(ArrayIn<int32_t>{ws.nnew}, G, ws.nvoff,
                                                 (int32_t*)nullptr, ws.tmp, s);
       hipLaunchKernelGGL(k_compose_map, grid(N), dim3(TB), 0, s, N, ws.map, ws.lab);
@@ -1519,6 +1593,48 @@ int slot_for(void* stream, Slot** out) {
 // A solve on a given workspace and stream (no lock: the caller owns both).
 // With opt->workspace the device arrays are carved from the caller's block
 // (ws then only lends its pinned host staging).
+// ------------------------------------------------------------ tuned settings
+// What mc_tune_batched chose, per device and size class of the problem:
+// the bit lengths of its graph count, vertex total and entry total (each
+// class spans a factor of two in each).
+struct TuneKey {
+  int dev, g, n, e;
+  bool operator<(const TuneKey& o) const {
+    return dev != o.dev ? dev < o.dev : g != o.g ? g < o.g : n != o.n ? n < o.n : e < o.e;
+  }
+};
+struct Tuned {
+  int32_t sweep_threads, sweep_groups, sort_tile, pr_triangle_deg, pq_order;
+};
+static std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+static std::map<TuneKey, Tuned>& tune_cache() {
+  static std::map<TuneKey, Tuned> c;
+  return c;
+}
+static TuneKey size_class(int32_t G, int64_t n, int64_t nnz) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return TuneKey{dev, bitlen((uint64_t)G), bitlen((uint64_t)n), bitlen((uint64_t)nnz)};
+}
+static void apply_tuned(const Tuned& t, mc_options& o) {
+  o.sweep_threads = t.sweep_threads;
+  o.sweep_groups = t.sweep_groups;
+  o.sort_tile = t.sort_tile;
+  o.pr_triangle_deg = t.pr_triangle_deg;
+  o.pq_order = t.pq_order;
+}
+// The stored settings of P's size class into o; false if there are none.
+static bool lookup_tuned(int32_t G, int64_t n, int64_t nnz, mc_options& o) {
+  std::lock_guard<std::mutex> lock(tune_mutex());
+  const auto it = tune_cache().find(size_class(G, n, nnz));
+  if (it == tune_cache().end()) return false;
+  apply_tuned(it->second, o);
+  return true;
+}
+
 int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt, int64_t* lambdas, uint8_t* side,
            mc_stats* st, int32_t* debug_labels = nullptr, int64_t* debug_lhat = nullptr,
            const int64_t* lhat_in = nullptr, int32_t* viecut_levels = nullptr) {
@@ -1533,7 +1649,9 @@ int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt,
   mc_options o;
   mc_options_default(&o);
   if (opt) o = *opt;
+  if (o.use_tuned) lookup_tuned(P.G, P.n, P.nnz, o);
   if (o.approx_ppm < 0 || o.approx_ppm >= 500000) return MC_EINVAL;
+  if (o.pq_order < 0 || o.pq_order > 3 || o.scan_visits < 0) return MC_EINVAL;
   if (st) {
     std::memset(st, 0, sizeof(*st));
   }
@@ -1685,6 +1803,7 @@ int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int
                                        : (int)sizeof(mc::SmallSweepLds<mc::SMALL_CAP_L, 256>);
     return std::max(1, mc::LDS_PER_CU / bytes);
   };
+  o.use_tuned = 0;
   mc_options best = o;
   best.sweep_threads = 256;
   best.sweep_groups = std::min(3, fit(256));
@@ -1693,6 +1812,14 @@ int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int
   int rc = solve_ms(best, default_ms);
   if (rc) return rc;
   best_ms = default_ms;
+  // one setting at a time, each kept if it is faster (coordinate descent)
+  auto try_opts = [&](const mc_options& c) -> int {
+    double ms = 0;
+    const int r = solve_ms(c, ms);
+    if (r) return r;
+    if (ms < best_ms) { best_ms = ms; best = c; }
+    return MC_OK;
+  };
   // the LDS sweep's shape
   const mc_options shape0 = best;
   for (int threads : {128, 256, 512}) {
@@ -1702,19 +1829,36 @@ int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int
       mc_options c = shape0;
       c.sweep_threads = threads;
       c.sweep_groups = groups;
-      double ms = 0;
-      if ((rc = solve_ms(c, ms))) return rc;
-      if (ms < best_ms) { best_ms = ms; best = c; }
+      if ((rc = try_opts(c))) return rc;
     }
   }
-  // the sort tile, with that shape
+  // the sort tile
   const mc_options shape1 = best;
   for (int tile : {2048, 8192}) {
     mc_options c = shape1;
     c.sort_tile = tile;
-    double ms = 0;
-    if ((rc = solve_ms(c, ms))) return rc;
-    if (ms < best_ms) { best_ms = ms; best = c; }
+    if ((rc = try_opts(c))) return rc;
+  }
+  // the triangle tests: off, from the first round, or the base's
+  const mc_options shape2 = best;
+  for (int tri : {0, -64, 64}) {
+    if (tri == shape2.pr_triangle_deg) continue;
+    mc_options c = shape2;
+    c.pr_triangle_deg = tri;
+    if ((rc = try_opts(c))) return rc;
+  }
+  // the priority-queue order among equal keys (changes the rounds)
+  const mc_options shape3 = best;
+  for (int order : {1, 2, 3}) {
+    if (order == shape3.pq_order) continue;
+    mc_options c = shape3;
+    c.pq_order = order;
+    if ((rc = try_opts(c))) return rc;
+  }
+  {
+    std::lock_guard<std::mutex> lock(mc::tune_mutex());
+    mc::tune_cache()[mc::size_class(b->num_graphs, b->n_total, b->nnz_total)] =
+        mc::Tuned{best.sweep_threads, best.sweep_groups, best.sort_tile, best.pr_triangle_deg, best.pq_order};
   }
   out->best = best;
   out->candidates = count;
@@ -1722,6 +1866,16 @@ int mc_tune_batched(const mc_batch* b, void* stream, const mc_options* base, int
   out->best_ms = best_ms;
   out->default_ms = default_ms;
   return MC_OK;
+}
+
+int mc_tune_lookup(const mc_batch* b, mc_options* opt) {
+  if (!b || !opt || b->num_graphs < 1) return MC_EINVAL;
+  return mc::lookup_tuned(b->num_graphs, b->n_total, b->nnz_total, *opt) ? 1 : 0;
+}
+
+void mc_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(mc::tune_mutex());
+  mc::tune_cache().clear();
 }
 
 int mc_debug_first_round(const mc_batch* b, void* stream, const mc_options* opt, const int64_t* lhat_in,
@@ -1830,20 +1984,20 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
   MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   MC_HIP(hipStreamSynchronize(s));
   if (ws.ctl_host->err) return MC_EINVAL;
+  const dim3 chunks(grid_for((nnz + WCH - 1) / WCH * 64, TB, ncu * 8));
   if (nnz > 0) {
-    int32_t* first = (int32_t*)ws.keys;
-    hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(g->n, TB, ncu * 16)), dim3(TB), 0, s, g->n, g->row_ptr, first);
-    hipLaunchKernelGGL(k_ingest, dim3(grid_for((nnz + INGEST_CH - 1) / INGEST_CH * TB, TB, ncu * 8)), dim3(TB), 0, s,
-                       g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff, first, ws.src, ws.cdeg, ws.gmaxw,
-                       ws.ctl);
+    hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(g->n, TB, ncu * 16)), dim3(TB), 0, s, g->n, g->row_ptr, ws.first);
+    hipLaunchKernelGGL(k_ingest, chunks, dim3(TB), 0, s, g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff,
+                       ws.first, ws.cdeg, ws.gmaxw, ws.ctl);
   }
   // every col inside [0, n) before the emit indexes the labels by it
   MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   MC_HIP(hipStreamSynchronize(s));
   if (ws.ctl_host->err) return MC_EINVAL;
   const int bb = std::max(1, bitlen((uint64_t)n_new - 1));
-  hipLaunchKernelGGL(k_emit, dim3(grid_for((nnz + 2047) / 2048 * 256, TB, ncu * 8)), dim3(TB), 0, s, nnz,
-                     ws.src, g->col, g->w, labels, bb, (const uint32_t*)nullptr, ws.keys, ws.vals, ws.ctl);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_emit, chunks, dim3(TB), 0, s, g->n, nnz, g->row_ptr, ws.first, g->col, g->w, labels, bb,
+                       (const uint32_t*)nullptr, ws.keys, ws.vals, ws.ctl);
   MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   MC_HIP(hipStreamSynchronize(s));
   if (ws.ctl_host->err) return MC_EINVAL;

@@ -81,136 +81,202 @@ __global__ void k_init_vertices(int32_t n, const int64_t* voff, int32_t G, int32
   }
 }
 
-// Entry source ids, validation, and weighted degrees (self-loops excluded;
-// they never cross a cut).  A workgroup takes INGEST_CH consecutive entries
-// per step.  The row of each entry comes from the row starts that fall in
-// the chunk: they are marked in LDS (one coalesced read of row_ptr), and a
-// maximum scan over the chunk's positions carries each row id to its
-// entries; the chunk's first row is found beforehand by k_chunk_rows.  Each
-// wave then takes 64 consecutive entries per step, so the row sums are
-// wave-segmented sums.
-constexpr int INGEST_CH = 2048;
+// Entry rows without a source array.  A wave takes WCH consecutive entries
+// [e0, e0 + WCH), entry e0 + k * 64 + lane in slot k of each lane (every load
+// of a slot is one contiguous 256-byte run).  first[c] holds the row of entry
+// c * WCH (k_chunk_rows).  The rows starting inside the chunk are marked in
+// the wave's own LDS (pos: WCH ints; the largest id where empty rows share a
+// start) from one coalesced read of row_ptr per 64 rows, and a maximum scan
+// over the positions carries each row id to its entries.  Wave-local: no
+// workgroup barrier.
+constexpr int WCH = 512;
 
-// first[c] = the row holding entry c * INGEST_CH (one writer per chunk: the
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+__device__ __forceinline__ void chunk_rows(const int64_t* __restrict__ rp, int32_t n, int64_t e0, int32_t r0,
+                                           int32_t* pos, int32_t (&row)[8]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pos[lane * 8 + k] = -1;
+  wave_lds_sync();
+  if (lane == 0) pos[0] = r0;
+  const int64_t end = e0 + WCH;
+  for (int64_t base = (int64_t)r0 + 1;; base += 64) {
+    const int64_t r = base + lane;
+    const int64_t st = rp[r < n ? r : n];  // row_ptr[n] = nnz
+    const bool in = r <= n && st < end;   // starts are > e0: row r0 holds e0
+    if (in) atomicMax(&pos[st - e0], (int32_t)r);
+    if (!((ballot(in) >> 63) & 1)) break;  // starts ascend: lane 63 in means more may follow
+  }
+  wave_lds_sync();
+  int32_t v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = pos[lane * 8 + k];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) v[k] = v[k] > v[k - 1] ? v[k] : v[k - 1];
+  int32_t inc = v[7];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(inc, o, 64);
+    if (lane >= o && t > inc) inc = t;
+  }
+  int32_t ex = __shfl_up(inc, 1, 64);
+  if (lane == 0) ex = -1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pos[lane * 8 + k] = v[k] > ex ? v[k] : ex;
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) row[k] = pos[k * 64 + lane];
+  wave_lds_sync();  // pos is reused by the wave's next chunk
+}
+
+// first[c] = the row holding entry c * WCH (one writer per chunk: the
 // non-empty row whose entry range contains it).
 __global__ void k_chunk_rows(int32_t n, const int64_t* __restrict__ rp, int32_t* __restrict__ first) {
   for (int64_t r = gtid(); r < n; r += gstride()) {
     const int64_t lo = rp[r], hi = rp[r + 1];
-    for (int64_t c = (lo + INGEST_CH - 1) / INGEST_CH; c * INGEST_CH < hi; ++c) first[c] = (int32_t)r;
+    for (int64_t c = (lo + WCH - 1) / WCH; c * WCH < hi; ++c) first[c] = (int32_t)r;
   }
 }
 
-__global__ void __launch_bounds__(256) k_ingest(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+// The row of entry c * WCH from first[], clamped into [0, n).
+__device__ __forceinline__ int32_t chunk_first(const int32_t* first, int64_t c, int32_t n) {
+  const int32_t r0 = first[c];
+  return r0 < 0 ? 0 : (r0 >= n ? n - 1 : r0);
+}
+
+// Global wave index and count of a launch.
+__device__ __forceinline__ int64_t gwave() { return ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
+__device__ __forceinline__ int64_t gwaves() { return ((int64_t)gridDim.x * blockDim.x) >> 6; }
+
+// The entry sources as an array (src[e] = the row of entry e), for the
+// consumers that index entries one at a time.
+__global__ void __launch_bounds__(256) k_fill_src(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ first, int32_t* __restrict__ src) {
+  __shared__ int32_t pos_all[4][WCH];
+  int32_t* pos = pos_all[threadIdx.x >> 6];
+  const int lane = lane_id();
+  for (int64_t ch = gwave(); ch * WCH < nnz; ch += gwaves()) {
+    const int64_t e0 = ch * WCH;
+    int32_t row[8];
+    chunk_rows(rp, n, e0, chunk_first(first, ch, n), pos, row);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * 64 + lane;
+      if (e < nnz) src[e] = row[k];
+    }
+  }
+}
+
+// Sum of val over each run of equal row among the wave's 64 lanes (rows
+// ascend with the lane), added to out[row] once per run.  A slot held by one
+// row throughout is one wave sum (long rows); otherwise a segmented sum.
+__device__ __forceinline__ void wave_row_add(int32_t row, int64_t val, bool ok, int64_t* out) {
+  const int32_t r_first = __builtin_amdgcn_readfirstlane(row);
+  if (ballot(ok && row != r_first) == 0) {
+    const int64_t sum = wave_sum_i64_dpp(ok ? val : 0);
+    if (lane_id() == 0 && sum) atomicAdd((unsigned long long*)(out + r_first), (unsigned long long)sum);
+    return;
+  }
+  bool tail;
+  const int64_t sum = wave_segsum<int32_t, int64_t>(ok ? row : -1, val, ok, tail);
+  if (ok && tail && sum) atomicAdd((unsigned long long*)(out + row), (unsigned long long)sum);
+}
+
+// Validation and weighted degrees (self-loops excluded; they never cross a
+// cut), one WCH-entry chunk per wave step, rows from chunk_rows.  The next
+// chunk's entries and first row are loaded once this chunk's dependent
+// loads are issued, so they are in flight during its sums.
+__global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col,
                                                 const int32_t* __restrict__ w,
                                                 const int32_t* __restrict__ gid,
                                                 const int64_t* __restrict__ voff,
-                                                const int32_t* __restrict__ first,
-                                                int32_t* __restrict__ src, int64_t* cdeg, int32_t* gmaxw,
+                                                const int32_t* __restrict__ first, int64_t* cdeg, int32_t* gmaxw,
                                                 Ctl* ctl) {
-  constexpr int PER = INGEST_CH / 256;  // entries per thread
-  __shared__ int32_t row_at[INGEST_CH];
-  __shared__ int32_t wave_max[4];
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-  const int64_t nch = (nnz + INGEST_CH - 1) / INGEST_CH;
-  // largest weight of the chunks in one graph, per lane, folded into
-  // gmaxw when the graph changes (same-address atomics serialise)
+  __shared__ int32_t pos_all[4][WCH];
+  int32_t* pos = pos_all[threadIdx.x >> 6];
+  const int lane = lane_id();
+  // largest weight of the chunks in one graph, per lane, folded into gmaxw
+  // when the graph changes (same-address atomics serialise)
   int32_t run_g = -1, run_m = 0;
-  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    const int64_t cs = ch * INGEST_CH, ce = min(cs + (int64_t)INGEST_CH, nnz);
-    const int len = (int)(ce - cs);
-    // this thread's entries (wave-contiguous steps), in flight meanwhile
-    int32_t y[PER], c[PER];
+  int64_t ch = gwave();
+  int32_t y[8], c[8], f = 0;
+  auto load = [&](int64_t at) {
+    const int64_t e0 = at * WCH;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int p = wave * (64 * PER) + k * 64 + lane;
-      const int64_t e = cs + (p < len ? p : 0);
-      y[k] = col[e];
-      c[k] = w[e];
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * 64 + lane;
+      const int64_t ec = e < nnz ? e : e0;
+      y[k] = col[ec];
+      c[k] = w[ec];
     }
-    int32_t r0 = first[ch];
-    r0 = r0 < 0 ? 0 : (r0 >= n ? n - 1 : r0);
-    // the first row's graph and its vertex range (graphs are contiguous
-    // vertex ranges, so the chunk lies in one graph if its last row does)
+    f = chunk_first(first, at, n);
+  };
+  if (ch * WCH < nnz) load(ch);
+  for (; ch * WCH < nnz; ch += gwaves()) {
+    const int64_t e0 = ch * WCH;
+    const int32_t r0 = f;
+    int32_t row[8];
+    chunk_rows(rp, n, e0, r0, pos, row);
+    // the chunk's graph: the first row's, when its last row is in it too
+    // (graphs are contiguous vertex ranges)
     const int32_t g0 = gid[r0];
     const int64_t lo0 = voff[g0], hi0 = voff[g0 + 1];
-    __syncthreads();  // the previous chunk's reads of row_at are done
+    const int64_t last_e = min(e0 + WCH, nnz) - 1 - e0;  // slot and lane of the chunk's last entry
+    int32_t row_last = r0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) row_at[tid + k * 256] = -1;
-    __syncthreads();
-    if (tid == 0) row_at[0] = r0;
-    // rows starting inside the chunk; empty rows share a start with the
-    // next row, and the largest id there owns the entries
-    for (int64_t base = (int64_t)r0 + 1;; base += 256) {
-      const int64_t r = base + tid;
-      const int64_t st = rp[r < n ? r : n];  // row_ptr[n] = nnz ends the chunk
-      if (st > cs && st < ce) atomicMax(&row_at[st - cs], (int32_t)r);
-      if (!__syncthreads_or(tid == 255 && st < ce)) break;
+    for (int k = 0; k < 8; ++k)
+      if ((last_e >> 6) == k) row_last = __builtin_amdgcn_readlane(row[k], (int)(last_e & 63));
+    const bool one = row_last < hi0;
+    int32_t yc[8], cc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      yc[k] = y[k];
+      cc[k] = c[k];
     }
-    // maximum scan over positions: each thread scans 8 consecutive ones
-    int32_t v[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) v[k] = row_at[tid * PER + k];
-#pragma unroll
-    for (int k = 1; k < PER; ++k) v[k] = v[k] > v[k - 1] ? v[k] : v[k - 1];
-    int32_t inc = v[PER - 1];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t t = __shfl_up(inc, o, 64);
-      if (lane >= o && t > inc) inc = t;
-    }
-    if (lane == 63) wave_max[wave] = inc;
-    int32_t ex = __shfl_up(inc, 1, 64);
-    if (lane == 0) ex = -1;
-    __syncthreads();
-    for (int i = 0; i < wave; ++i) ex = wave_max[i] > ex ? wave_max[i] : ex;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) row_at[tid * PER + k] = v[k] > ex ? v[k] : ex;
-    __syncthreads();
-    const bool one = row_at[len - 1] < hi0;
-    if (one && g0 != run_g) {  // block-uniform
+    if (ch + gwaves() < (nnz + WCH - 1) / WCH) load(ch + gwaves());
+    if (one && g0 != run_g) {
       const uint32_t m = wave_max_u32((uint32_t)run_m);
-      if (lane == 0 && m) atomicMax(gmaxw + run_g, (int32_t)m);
+      if (lane == 0 && m && run_g >= 0) atomicMax(gmaxw + run_g, (int32_t)m);
       run_g = g0;
       run_m = 0;
     }
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int p = wave * (64 * PER) + k * 64 + lane;
-      const bool ok = p < len;
-      const int64_t e = cs + p;
-      const int32_t row = row_at[ok ? p : 0];
-      int32_t g = g0;
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * 64 + lane;
+      const bool ok = e < nnz;
+      // a chunk across a graph boundary (wave-uniform) reads each entry's
+      // graph range; graphs are contiguous vertex ranges
+      int32_t gk = g0;
       int64_t lo = lo0, hi = hi0;
-      if (!one) {  // a chunk across a graph boundary (block-uniform)
-        g = gid[row];
-        lo = voff[g];
-        hi = voff[g + 1];
+      if (!one) {
+        gk = gid[ok ? row[k] : r0];
+        lo = voff[gk];
+        hi = voff[gk + 1];
       }
-      if (ok) {
-        src[e] = row;
-        if (y[k] < lo || y[k] >= hi || c[k] < 1) atomicExch(&ctl->err, -1);
-      }
-      const int64_t val = (ok && y[k] != row) ? (int64_t)c[k] : 0;
-      bool tail;
-      const int64_t sum = wave_segsum<int32_t, int64_t>(ok ? row : -1, val, ok, tail);
-      if (ok && tail && sum) atomicAdd((unsigned long long*)(cdeg + row), (unsigned long long)sum);
-      const int32_t ck = ok ? c[k] : 0;
+      if (ok && (yc[k] < lo || yc[k] >= hi || cc[k] < 1)) atomicExch(&ctl->err, -1);
+      const int64_t val = (ok && yc[k] != row[k]) ? (int64_t)cc[k] : 0;
+      wave_row_add(row[k], val, ok, cdeg);
+      const int32_t ck = ok ? cc[k] : 0;
       if (one) {
         run_m = ck > run_m ? ck : run_m;
       } else {
-        const int32_t gk = __builtin_amdgcn_readfirstlane(g);
-        if (ballot(g == gk) == ~0ull) {
+        const int32_t gu = __builtin_amdgcn_readfirstlane(gk);
+        if (ballot(gk == gu) == ~0ull) {
           const uint32_t m = wave_max_u32((uint32_t)ck);
-          if (lane == 0 && m) atomicMax(gmaxw + gk, (int32_t)m);
+          if (lane == 0 && m) atomicMax(gmaxw + gu, (int32_t)m);
         } else if (ok) {
-          atomicMax(gmaxw + g, ck);
+          atomicMax(gmaxw + gk, ck);
         }
       }
     }
   }
   const uint32_t m = wave_max_u32((uint32_t)run_m);
-  if (lane == 0 && m) atomicMax(gmaxw + run_g, (int32_t)m);
+  if (lane == 0 && m && run_g >= 0) atomicMax(gmaxw + run_g, (int32_t)m);
 }
 
 // Per-graph minimum weighted degree (the trivial cut, section "Basic
@@ -583,61 +649,66 @@ __global__ void __launch_bounds__(256) k_lam_floor(int32_t G, const int64_t* lha
   if (threadIdx.x == 0) ctl->lam_floor = min(min(part[0], part[1]), min(part[2], part[3]));
 }
 
-// PR_TILE entries per thread and workgroup step, loaded in five rounds
-// (weight; ends; graph; its bound; both degrees), each round for all of
-// them; an entry already decided reads a shared dummy address.
-constexpr int PR_TILE = 4;
-__global__ void __launch_bounds__(256) k_pr(int64_t nnz, const int32_t* __restrict__ src,
+// One WCH-entry chunk per wave step (slot k of each lane: entry
+// e0 + k * 64 + lane), loaded in rounds (weight; rows and ends; graph; its
+// bound; both degrees), each round for all slots; an entry already decided
+// reads a shared dummy address.  A chunk none of whose weights can pass for
+// any graph is dropped before its rows are found.
+__global__ void __launch_bounds__(256) k_pr(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                                            const int32_t* __restrict__ first,
                                             const int32_t* __restrict__ col, const int32_t* __restrict__ w,
                                             const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
                                             const int64_t* __restrict__ lhat, const int32_t* __restrict__ active,
                                             int32_t* parent, int32_t* ucount, Ctl* ctl) {
+  __shared__ int32_t pos_all[4][WCH];
+  int32_t* pos = pos_all[threadIdx.x >> 6];
+  const int lane = lane_id();
   int64_t local = 0;
   int32_t last = -1;
   const int64_t floor = ctl->lam_floor;  // hopeless for every graph: 2c <= floor
-  for (int64_t t0 = (int64_t)blockIdx.x * 256 * PR_TILE; t0 < nnz; t0 += (int64_t)gridDim.x * 256 * PR_TILE) {
-    const int64_t e0 = t0 + threadIdx.x;
-    int32_t c[PR_TILE], u[PR_TILE], v[PR_TILE], g[PR_TILE];
-    bool keep[PR_TILE];
+  for (int64_t ch = gwave(); ch * WCH < nnz; ch += gwaves()) {
+    const int64_t e0 = ch * WCH;
+    int32_t c[8], u[8], v[8], g[8];
+    bool keep[8];
 #pragma unroll
-    for (int i = 0; i < PR_TILE; ++i) c[i] = w[e0 + i * 256 < nnz ? e0 + i * 256 : t0];
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * 64 + lane;
+      c[k] = w[e < nnz ? e : e0];
+    }
     bool any = false;
 #pragma unroll
-    for (int i = 0; i < PR_TILE; ++i) {
-      keep[i] = e0 + i * 256 < nnz && !pr_hopeless(c[i], floor);
-      any = any || keep[i];
+    for (int k = 0; k < 8; ++k) {
+      keep[k] = e0 + k * 64 + lane < nnz && !pr_hopeless(c[k], floor);
+      any = any || keep[k];
     }
     if (ballot(any) == 0) continue;  // wave-uniform: nothing left to test
 #pragma unroll
-    for (int i = 0; i < PR_TILE; ++i) {
-      const int64_t e = keep[i] ? e0 + i * 256 : t0;
-      u[i] = src[e];
-      v[i] = col[e];
+    for (int k = 0; k < 8; ++k) v[k] = col[keep[k] ? e0 + k * 64 + lane : e0];
+    chunk_rows(rp, n, e0, chunk_first(first, ch, n), pos, u);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      keep[k] = keep[k] && u[k] < v[k];
+      g[k] = gid[keep[k] ? u[k] : 0];
+    }
+    int64_t lam[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool act = active[g[k]] != 0;
+      lam[k] = lhat[g[k]];
+      keep[k] = keep[k] && act && !pr_hopeless(c[k], lam[k]);
+    }
+    int64_t cu[8], cv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cu[k] = cdeg[keep[k] ? u[k] : 0];
+      cv[k] = cdeg[keep[k] ? v[k] : 0];
     }
 #pragma unroll
-    for (int i = 0; i < PR_TILE; ++i) {
-      keep[i] = keep[i] && u[i] < v[i];
-      g[i] = gid[keep[i] ? u[i] : 0];
-    }
-    int64_t lam[PR_TILE];
-#pragma unroll
-    for (int i = 0; i < PR_TILE; ++i) {
-      const bool act = active[g[i]] != 0;
-      lam[i] = lhat[g[i]];
-      keep[i] = keep[i] && act && !pr_hopeless(c[i], lam[i]);
-    }
-    int64_t cu[PR_TILE], cv[PR_TILE];
-#pragma unroll
-    for (int i = 0; i < PR_TILE; ++i) {
-      cu[i] = cdeg[keep[i] ? u[i] : 0];
-      cv[i] = cdeg[keep[i] ? v[i] : 0];
-    }
-#pragma unroll
-    for (int i = 0; i < PR_TILE; ++i)
-      if (keep[i] && pr_passes(c[i], lam[i], cu[i], cv[i])) {
+    for (int k = 0; k < 8; ++k)
+      if (keep[k] && pr_passes(c[k], lam[k], cu[k], cv[k])) {
         ++local;
-        pr_flag(ucount, g[i], last);
-        if (ld_relaxed(parent + u[i]) != ld_relaxed(parent + v[i])) uf_union(parent, u[i], v[i]);
+        pr_flag(ucount, g[k], last);
+        if (ld_relaxed(parent + u[k]) != ld_relaxed(parent + v[k])) uf_union(parent, u[k], v[k]);
       }
   }
   // one add per wave: per-thread adds on the one counter serialise
@@ -883,112 +954,104 @@ __global__ void k_block_bits(int32_t n, const int32_t* lab, const int32_t* gid, 
 
 __device__ __forceinline__ bool bit_at(const uint32_t* b, int32_t v) { return (b[v >> 5] >> (v & 31)) & 1u; }
 
-// Surviving entries are staged in LDS and written out in blocks: one atomic
-// reservation per EMIT_STAGE entries instead of one per tile (per-tile
-// reservations on the one counter serialise, and each waits for its reply
-// behind a workgroup barrier).  The order of the emitted entries is free:
-// they are sorted next.
-constexpr int EMIT_STAGE = 2048;  // at least one tile
-__global__ void __launch_bounds__(256) k_emit(int64_t nnz, const int32_t* __restrict__ src,
+// Contraction keys: per crossing entry (u, x) with blocks a = lab[u] != b =
+// lab[x], the key (a << bits) | b and the entry's weight.  One WCH-entry
+// chunk per wave step, rows from chunk_rows.  Survivors are staged in the
+// wave's LDS and written out in runs of up to WCH: one atomic reservation
+// per run instead of one per chunk (reservations on the one counter
+// serialise).  inref (optional): bit v set when v's block is its graph's
+// reference block; an entry with both ends there cannot cross and is
+// dropped from the bits alone, before its labels are read.  The order of
+// the emitted entries is free: they are sorted next.
+__global__ void __launch_bounds__(256) k_emit(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ first,
                                               const int32_t* __restrict__ col,
                                               const int32_t* __restrict__ w,
                                               const int32_t* __restrict__ lab, int bits,
                                               const uint32_t* __restrict__ inref,
                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
                                               Ctl* ctl) {
-  __shared__ uint32_t wcnt_buf[2][4];  // per tile parity: a wave may write the next tile's
-                                       // counts while another still reads this tile's
-  __shared__ unsigned long long base_s;
-  __shared__ uint64_t st_k[EMIT_STAGE];
-  __shared__ int32_t st_v[EMIT_STAGE];
-  __shared__ uint32_t st_n;
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t tile = 256 * 8;
-  static_assert(EMIT_STAGE >= 256 * 8, "a tile's survivors fit the stage");
-  if (threadIdx.x == 0) st_n = 0;
-  __syncthreads();
-  // write the staged entries out (block-uniform call)
+  __shared__ int32_t pos_all[4][WCH];
+  __shared__ uint64_t stk_all[4][WCH];
+  __shared__ int32_t stv_all[4][WCH];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  int32_t* pos = pos_all[wave];
+  uint64_t* st_k = stk_all[wave];
+  int32_t* st_v = stv_all[wave];
+  uint32_t st_n = 0;  // wave-uniform
   auto flush = [&]() {
-    const uint32_t n = st_n;
-    if (n == 0) return;
-    if (threadIdx.x == 0) base_s = atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)n);
-    __syncthreads();
-    const uint64_t base = base_s;
-    for (uint32_t i = threadIdx.x; i < n; i += 256) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)st_n);
+    base = (unsigned long long)readlane_i64((int64_t)base, 0);
+    wave_lds_sync();
+    for (uint32_t i = lane; i < st_n; i += 64) {
       keys[base + i] = st_k[i];
       vals[base + i] = st_v[i];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) st_n = 0;
-    __syncthreads();
+    wave_lds_sync();
+    st_n = 0;
   };
-  int parity = 0;
-  for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nnz; t0 += (int64_t)gridDim.x * tile) {
-    uint32_t* wcnt = wcnt_buf[parity];
-    parity ^= 1;
-    // Each load step is issued for all eight entries before any result is
-    // used, and no load sits in a divergent branch: a lane that has nothing
-    // to fetch reads the tile's first element instead (one shared line), so
-    // a wave waits for three rounds of loads, not three per entry.
-    const int64_t e0 = t0 + (int64_t)wave * 512 + lane;
-    const int64_t safe = t0 < nnz ? t0 : 0;
-    int32_t u[8], x[8];
-    bool in[8];
+  for (int64_t ch = gwave(); ch * WCH < nnz; ch += gwaves()) {
+    const int64_t e0 = ch * WCH;
+    // the loads of a step are issued for all eight slots before any result
+    // is used, and none sits in a lane-divergent branch: a slot with nothing
+    // to fetch reads the chunk's first element (one shared line)
+    int32_t x[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int64_t e = e0 + r * 64;
-      const int64_t ec = e < nnz ? e : safe;
-      u[r] = src[ec];
-      x[r] = col[ec];
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * 64 + lane;
+      x[k] = col[e < nnz ? e : e0];
     }
+    int32_t u[8];
+    chunk_rows(rp, n, e0, chunk_first(first, ch, n), pos, u);
+    bool skip[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) in[r] = e0 + r * 64 >= nnz;
+    for (int k = 0; k < 8; ++k) skip[k] = e0 + k * 64 + lane >= nnz;
     if (inref) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const uint32_t bu = inref[u[r] >> 5], bx = inref[x[r] >> 5];
-        in[r] = in[r] | (((bu >> (u[r] & 31)) & (bx >> (x[r] & 31)) & 1u) != 0);
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t bu = inref[u[k] >> 5], bx = inref[x[k] >> 5];
+        skip[k] = skip[k] | (((bu >> (u[k] & 31)) & (bx >> (x[k] & 31)) & 1u) != 0);
       }
     }
-    uint64_t k[8];
+    // a slot whose entries all stay inside reference blocks (most of them,
+    // once a round has contracted most of the graph) loads nothing more:
+    // the test is wave-uniform
+    uint64_t key[8];
     int32_t vv[8];
     uint64_t msk[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      // in[r]: past the end, or inside the reference block (never crossing)
-      const int32_t a = lab[in[r] ? 0 : u[r]];
-      const int32_t b = lab[in[r] ? 0 : x[r]];
-      const int32_t c = w[in[r] ? safe : e0 + r * 64];
-      const bool ok = !in[r] && a >= 0 && b >= 0 && a != b;
-      k[r] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
-      vv[r] = ok ? c : 0;
-      msk[r] = ballot(ok);
+    for (int k = 0; k < 8; ++k) {
+      msk[k] = 0;
+      key[k] = 0;
+      vv[k] = 0;
+      if (ballot(!skip[k]) == 0) continue;
+      const int32_t a = lab[skip[k] ? 0 : u[k]];
+      const int32_t b = lab[skip[k] ? 0 : x[k]];
+      const int32_t c = w[skip[k] ? e0 : e0 + k * 64 + lane];
+      const bool ok = !skip[k] && a >= 0 && b >= 0 && a != b;
+      key[k] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
+      vv[k] = c;
+      msk[k] = ballot(ok);
     }
-    uint32_t wtot = 0;
+    uint32_t tot = 0;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) wtot += popc64(msk[r]);
-    if (lane == 0) wcnt[wave] = wtot;
-    __syncthreads();
-    const uint32_t tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    if (tot == 0) continue;  // block-uniform
-    if (st_n + tot > (uint32_t)EMIT_STAGE) flush();
+    for (int k = 0; k < 8; ++k) tot += popc64(msk[k]);
+    if (tot == 0) continue;  // wave-uniform
+    if (st_n + tot > (uint32_t)WCH) flush();
     uint32_t o = st_n;
-    for (int i = 0; i < wave; ++i) o += wcnt[i];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const bool ok = (msk[r] >> lane) & 1;
-      if (ok) {
-        const uint32_t at = o + popc64(msk[r] & lanemask_lt());
-        st_k[at] = k[r];
-        st_v[at] = vv[r];
+    for (int k = 0; k < 8; ++k) {
+      if ((msk[k] >> lane) & 1) {
+        const uint32_t at = o + popc64(msk[k] & lanemask_lt());
+        st_k[at] = key[k];
+        st_v[at] = vv[k];
       }
-      o += popc64(msk[r]);
+      o += popc64(msk[k]);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) st_n += tot;
-    __syncthreads();
+    st_n += tot;
   }
-  flush();
+  if (st_n) flush();
 }
 
 struct HeadFlag {

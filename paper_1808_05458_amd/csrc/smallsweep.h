@@ -46,21 +46,31 @@ struct SmallSweepArgs {
   int32_t* fb_k;               // per graph: stamp of the best prefix
   int32_t* ucount;
   uint64_t seed;
+  int32_t order;               // ORD kernels: the order among equal keys below
+                               // the cap (tie_rank: 1 bucket queue, 2 bucket
+                               // stack, 3 heap)
 };
 
 constexpr int SS_UNROLL = 4;  // entries in flight per thread in a batch relax
 
-// LDS of one sweep: CAP vertices, THREADS threads per workgroup.
-template <int CAP, int THREADS>
+// LDS of one sweep: CAP vertices, THREADS threads per workgroup.  ORD: the
+// single pops below the cap follow a chosen order among equal keys (the
+// chunk bounds then hold (r, rank) pairs and each vertex the step of its
+// last increase).
+template <int CAP, int THREADS, bool ORD = false>
 struct SmallSweepLds {
   static_assert(CAP <= 65536 && CAP % 64 == 0, "16-bit local vertex ids, whole chunks");
+  static_assert(!ORD || 2 * CAP < 65536, "a sweep's steps (at most two per vertex) fit the 16-bit ticks");
   static_assert(THREADS % 64 == 0 && THREADS <= 1024, "whole waves");
   static constexpr int NC = CAP / 64;
   static constexpr int NW = THREADS / 64;
+  static constexpr bool ordered = ORD;
+  using Bound = typename std::conditional<ORD, unsigned long long, uint32_t>::type;
   int32_t r[CAP];
   uint16_t capped[CAP];  // vertices in the order their r reached the cap
   uint32_t st[CAP / 16];  // 2 bits per vertex: 0 unvisited, 2 visited, 3 in the current batch
-  uint32_t cmax[NC];     // per 64-vertex chunk: >= r of its unvisited vertices
+  Bound cmax[NC];        // per 64-vertex chunk: >= the key of its unvisited vertices
+  uint16_t lt[ORD ? CAP : 2];  // ORD: step of each vertex's last increase
   int32_t boff[THREADS + 1];  // a batch chunk: entry offsets of its rows
   int32_t bbase[THREADS];     //   and each row's first entry (graph-relative)
   int32_t wtot[NW];
@@ -90,13 +100,19 @@ __device__ __forceinline__ void ss_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+template <class LDS>
+__device__ __forceinline__ unsigned long long ss_key(const LDS& L, int32_t order, int32_t v, uint32_t r) {
+  return ((unsigned long long)r << 32) | tie_rank(order, L.lt[v], (uint32_t)v);
+}
+
 // Relax one entry x -> y of weight c (local ids): update r(y) and its chunk
 // bound, and record the crossing r(y) < cap <= r(y) + c as a pair and a
-// capped vertex.  Must be called by all lanes of the wave.
+// capped vertex.  Must be called by all lanes of the wave.  tick: the step
+// (ORD kernels: the last increase's step, which orders equal keys).
 template <class LDS>
 __device__ __forceinline__ bool ss_relax(LDS& L, const SmallSweepArgs& A, int32_t v0, int64_t lam,
                                          bool ok, int32_t xl, int32_t yl, int32_t c, int64_t& rows,
-                                         int64_t& internal) {
+                                         int64_t& internal, uint32_t tick = 0) {
   bool cross = false;
   if (ok && yl != xl) {
     rows += c;
@@ -105,7 +121,12 @@ __device__ __forceinline__ bool ss_relax(LDS& L, const SmallSweepArgs& A, int32_
       internal += c;
     } else if (s == 0) {
       const int32_t old = atomicAdd(&L.r[yl], c);
-      atomicMax(&L.cmax[yl >> 6], (uint32_t)(old + c));
+      if constexpr (LDS::ordered) {
+        L.lt[yl] = (uint16_t)tick;
+        atomicMax(&L.cmax[yl >> 6], ((unsigned long long)(uint32_t)(old + c) << 32) | tie_rank(A.order, tick, (uint32_t)yl));
+      } else {
+        atomicMax(&L.cmax[yl >> 6], (uint32_t)(old + c));
+      }
       cross = (int64_t)old < lam && lam <= (int64_t)old + c;
     }
   }
@@ -141,6 +162,40 @@ __device__ __forceinline__ int32_t ss_select(LDS& L, const SmallSweepArgs& A, in
   constexpr int NC = LDS::NC;
   const int lane = lane_id();
   const int nc = (ng + 63) >> 6;
+  if constexpr (LDS::ordered) {
+    // the same two-level search over (r, rank) keys: any maximum of r is a
+    // legal next vertex, and the rank picks among them
+    while (true) {
+      unsigned long long mine = 0;
+      int32_t mine_c = 0;
+      for (int c = lane; c < nc && c < NC; c += 64) {
+        const unsigned long long k = L.cmax[c];
+        if (k > mine) { mine = k; mine_c = c; }
+      }
+      const unsigned long long bound = wave_max_u64(mine);
+      if ((bound >> 32) == 0) return -1;
+      const int holder = (int)__builtin_ctzll(ballot(mine == bound));
+      const int c = __builtin_amdgcn_readlane(mine_c, holder);
+      const int32_t v = c * 64 + lane;
+      const int32_t vq = v < ng ? v : ng - 1;
+      const int64_t la = A.rp[v0 + vq], lb = A.rp[v0 + vq + 1], lc = A.cdeg[v0 + vq];
+      const uint32_t rv = (v < ng && ss_state(L, v) == 0) ? (uint32_t)L.r[v] : 0u;
+      const unsigned long long key = rv > 0 ? ss_key(L, A.order, v, rv) : 0ull;
+      const unsigned long long exact = wave_max_u64(key);
+      if (exact == bound) {
+        const int at = (int)__builtin_ctzll(ballot(key == exact));
+        const unsigned long long rest = wave_max_u64(lane == at ? 0ull : key);
+        if (lane == 0) L.cmax[c] = rest;
+        rx = (uint32_t)(exact >> 32);
+        ra = readlane_i64(la, at);
+        rb = readlane_i64(lb, at);
+        cd = readlane_i64(lc, at);
+        return c * 64 + at;
+      }
+      if (lane == 0) L.cmax[c] = exact;  // the bound was stale: lower it, retry
+      ss_wave_sync();
+    }
+  }
   while (true) {
     uint32_t mine = 0;
     int32_t mine_c = 0;
@@ -172,11 +227,14 @@ __device__ __forceinline__ int32_t ss_select(LDS& L, const SmallSweepArgs& A, in
   }
 }
 
-template <int CAP, int THREADS>
+template <int CAP, int THREADS, bool ORD = false>
 __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
-  using LDS = SmallSweepLds<CAP, THREADS>;
+  using LDS = SmallSweepLds<CAP, THREADS, ORD>;
   constexpr int NW = LDS::NW;
-  extern __shared__ char lds_raw[];
+  // 16-byte aligned: the static LDS (sh_item) comes first, and the chunk
+  // bounds of the ordered kernels take 64-bit LDS atomics, which need
+  // naturally aligned addresses
+  extern __shared__ __align__(16) char lds_raw[];
   LDS& L = *reinterpret_cast<LDS*>(lds_raw);
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   __shared__ int32_t sh_item;
@@ -192,6 +250,7 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
     const int64_t ebase = A.rp[v0];
     for (int i = threadIdx.x; i < ng; i += THREADS) {
       L.r[i] = 0;
+      if constexpr (ORD) L.lt[i] = 0;
       A.fb_rs[v0 + i] = 0;
     }
     for (int i = threadIdx.x; i < (ng + 15) / 16; i += THREADS) L.st[i] = 0;
@@ -260,7 +319,8 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
             const int64_t ec = ok ? e : base;
             int32_t yv = A.col[ec], cv = A.w[ec];
             keep(cv);
-            crossed |= ss_relax(L, A, v0, lam, ok, xl, ok ? yv - v0 : 0, ok ? cv : 0, rows, internal);
+            crossed |= ss_relax(L, A, v0, lam, ok, xl, ok ? yv - v0 : 0, ok ? cv : 0, rows, internal,
+                                (uint32_t)stamp);
           }
           if (lane == 0) {
             alpha += dx - 2 * (int64_t)rx;
@@ -301,6 +361,7 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
       // batch relax: the batch's entries spread evenly over the workgroup, in
       // chunks of THREADS rows
       const int32_t b0 = L.b0;
+      const uint32_t btick = (uint32_t)L.stamp;  // the batch's step
       int64_t rows = 0, internal = 0;
       for (int32_t c0 = 0; c0 < nb; c0 += THREADS) {
         const int32_t cn = min(THREADS, nb - c0);
@@ -359,7 +420,7 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
           }
 #pragma unroll
           for (int u = 0; u < SS_UNROLL; ++u)
-            ss_relax(L, A, v0, lam, xs[u] >= 0, xs[u], ys[u], cs[u], rows, internal);
+            ss_relax(L, A, v0, lam, xs[u] >= 0, xs[u], ys[u], cs[u], rows, internal, btick);
         }
         __syncthreads();  // boff and bbase are reused by the next chunk
       }

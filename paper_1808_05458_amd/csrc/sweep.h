@@ -893,39 +893,20 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
 }
 
 // The crossing edges found by the sweeps, united after them: (capx[i],
-// capq[i]) of graph blockIdx.y.  Consecutive FIFO entries usually share
-// capx (one scanned vertex crossed many neighbours); united one by one,
-// their links all target the same root and retry on each other.  So per
-// run of equal capx in a wave, the smallest capq is united with capx and
-// the others with it: the same sets, and each of the others links under a
-// smaller root through its own entry.
+// capq[i]) of graph blockIdx.y.  Roots are ordered by visit stamp (then
+// id): the stamp of the sweep's batch or tail visit, in the high half of
+// the vertex's rs word (0 where never visited).  A crossed vertex q is
+// visited after the vertex x that made it cross, so nearly every pair links
+// the fresh root q under the root of x's tree, which only grows: one
+// uncontended compare-and-swap on q's own word.
 __global__ void k_sweep_unite(const SweepArgs* args) {
   const SweepDev A = dev_view(args[blockIdx.y]);
   const int32_t n = min(A.ctl->cap_tail, A.ng);  // the tail may count pairs it had no room for
-  const int lane = lane_id();
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
-       base += (int64_t)gridDim.x * blockDim.x) {  // wave-uniform bound
-    const int64_t i = base + lane;
-    const bool ok = i < n;
-    const int32_t x = ok ? A.capx[i] : -1;
-    const int32_t q = ok ? A.capq[i] : INT32_MAX;
-    const int32_t xp = __shfl_up(x, 1, 64), xn = __shfl_down(x, 1, 64);
-    int start = (lane == 0 || xp != x) ? lane : 0;  // first lane of the run
-    int end = (lane == 63 || xn != x) ? lane : 63;  // last lane of the run
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(start, o, 64);
-      if (lane >= o && t > start) start = t;
-      const int u = __shfl_down(end, o, 64);
-      if (lane + o < 64 && u < end) end = u;
-    }
-    int32_t m = q;  // minimum of capq over [lane, end]
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t t = __shfl_down(m, o, 64);
-      if (lane + o <= end && t < m) m = t;
-    }
-    const int32_t run_min = __shfl(m, start, 64);
-    if (ok) uf_union(A.parent, q == run_min ? x : run_min, q);
-  }
+  const auto key = [&](int32_t v) {
+    return ((uint64_t)(uint32_t)rs_stamp(ld_relaxed(A.rs + v)) << 32) | (uint32_t)v;
+  };
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    uf_union_by(A.parent, A.capx[i], A.capq[i], key);
 }
 
 // Per graph: status, FIFO bounds and row entries of the pending batch, for

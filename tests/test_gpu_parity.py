@@ -67,6 +67,37 @@ def test_random_tiny_graphs_against_enumeration():
         check_side(g, lam, side)
 
 
+@pytest.mark.parametrize("opts", [dict(pq_order=1), dict(pq_order=2), dict(pq_order=3),
+                                  dict(whole_max=8, scan_mode=1, pq_order=1, scan_visits=2),
+                                  dict(whole_max=8, scan_mode=1, pq_order=2, scan_visits=4, use_pr=0),
+                                  dict(scan_mode=2, pq_order=3)],
+                         ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()))
+def test_queue_orders_and_repeated_visits_against_noi(opts):
+    """The priority-queue orders (bucket queue, bucket stack, heap; section
+    "Priority Queue Implementations") and repeated visits (section "Parallel
+    CAPFOREST") change which pairs a round unites, never lambda: unweighted
+    and few-valued weights give many equal keys, so the order decides."""
+    rng = np.random.default_rng(17 + 3 * len(opts) + opts.get("pq_order", 0))
+    for t in range(24):
+        n = int(rng.integers(20, 400))
+        g = random_graph(rng, n, float(rng.uniform(0.02, 0.25)), int(rng.choice([1, 2, 3])))
+        if t % 8 == 0:
+            announce("orders", opts, t, n, g.m)
+        lam, side, _ = solve(g, **opts)
+        ref, _, _ = oracle.noi(g, 2)
+        assert lam == ref, (t, lam, ref, opts)
+        check_side(g, lam, side)
+
+
+def test_queue_orders_are_refused_outside_their_range():
+    import paper_1808_05458_amd as mc
+    g = gg.complete(6)
+    for bad in (dict(pq_order=4), dict(pq_order=-1), dict(scan_visits=-2)):
+        with pytest.raises(mc.MincutError) as e:
+            solve(g, **bad)
+        assert e.value.code == mc.MC_EINVAL
+
+
 def test_medium_graphs_against_noi():
     rng = np.random.default_rng(7)
     for t in range(40):
@@ -94,7 +125,11 @@ def test_medium_graphs_against_noi():
                                   dict(whole_max=16, sweep_handoff=2, sweep_pull=1, use_pr=0),
                                   dict(whole_max=16, sweep_pull=-1),
                                   dict(scan_mode=2), dict(scan_mode=2, max_pops=3),
-                                  dict(scan_mode=2, eager_blacklist=0, use_pr=0)])
+                                  dict(scan_mode=2, eager_blacklist=0, use_pr=0),
+                                  dict(pq_order=1), dict(pq_order=2, use_pr=0), dict(pq_order=3),
+                                  dict(whole_max=16, scan_mode=1, pq_order=2),
+                                  dict(whole_max=16, scan_mode=1, scan_visits=3, use_pr=0),
+                                  dict(scan_mode=2, pq_order=1)])
 def test_planted_4096_options(opts):
     g = gg.planted_4096()
     gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["planted_4096"]
@@ -117,7 +152,10 @@ def test_region_scans_on_power_law_core():
                  dict(whole_max=64, sweep_handoff=4, sweep_pull=1), dict(whole_max=64, sweep_pull=-1, use_pr=0),
                  dict(whole_max=64, scan_mode=1), dict(whole_max=64, scan_mode=1, eager_blacklist=0),
                  dict(whole_max=64, scan_mode=1, max_pops=50),
-                 dict(whole_max=64, scan_mode=1, use_pr=0)]:
+                 dict(whole_max=64, scan_mode=1, use_pr=0),
+                 dict(whole_max=64, scan_mode=1, pq_order=1), dict(whole_max=64, scan_mode=1, pq_order=2),
+                 dict(whole_max=64, scan_mode=1, pq_order=3, scan_visits=2),
+                 dict(whole_max=64, scan_mode=1, scan_visits=4, use_pr=0)]:
         announce("chung_lu 20000", opts)
         lam, side, st = solve(g, **opts)
         assert lam == ref, opts
@@ -370,7 +408,11 @@ _BLOCK_VARIANTS = [dict(), dict(use_pr=0), dict(whole_max=4, scan_mode=1), dict(
                    dict(whole_max=4, sweep_handoff=1, sweep_tail=-1, use_pr=0),
                    dict(whole_max=4, sweep_handoff=1, sweep_pull=1, use_pr=0),
                    dict(whole_max=4, sweep_handoff=1, sweep_pull=1, sweep_tail=1),
-                   dict(pr_triangle_deg=-64)]
+                   dict(pr_triangle_deg=-64),
+                   dict(pq_order=1, use_pr=0), dict(pq_order=2, use_pr=0), dict(pq_order=3),
+                   dict(whole_max=4, scan_mode=1, pq_order=2, scan_visits=3, use_pr=0),
+                   dict(whole_max=4, scan_mode=1, scan_visits=2),
+                   dict(scan_mode=2, pq_order=1, use_pr=0)]
 
 
 @pytest.mark.parametrize("opts", _BLOCK_VARIANTS, ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()) or "default")

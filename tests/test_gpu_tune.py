@@ -77,6 +77,34 @@ def test_autotuner_picks_a_candidate_that_equals_oracle(sample):
     assert rep["sweep_threads"] in (128, 256, 512)
     assert rep["sweep_groups"] in (2, 3)
     assert rep["sort_tile"] in (2048, 4096, 8192)
+    assert rep["pr_triangle_deg"] in (0, 64, -64) and rep["pq_order"] in (0, 1, 2, 3)
     assert 0 < rep["best_ms"] <= rep["default_ms"]
     lams, sides, st = mc.mincut_batched(rp, col, w, vo, opts=best)
     _check(graphs, refs, vo, lams, sides)
+
+
+def test_tuned_settings_are_kept_per_size_class(sample):
+    """mc_tune_batched stores its choice under the batch's size class (bit
+    lengths of graph count, vertex total, entry total); solves with
+    use_tuned=1 in that class take it and still equal the oracle; another
+    class finds nothing; mc_tune_clear forgets."""
+    import paper_1808_05458_amd as mc
+    graphs, refs, vo, (rp, col, w) = sample
+    n, nnz = rp.numel() - 1, col.numel()
+    mc.tune_clear()
+    assert mc.tune_lookup(n, nnz, vo) is None
+    best, rep = mc.tune_batched(rp, col, w, vo, reps=1)
+    got = mc.tune_lookup(n, nnz, vo)
+    assert got is not None
+    for k in ("sweep_threads", "sweep_groups", "sort_tile", "pr_triangle_deg", "pq_order"):
+        assert getattr(got, k) == getattr(best, k), k
+    # the same class: a vertex and two entries fewer, same bit lengths
+    if (n - 1).bit_length() == n.bit_length() and (nnz - 2).bit_length() == nnz.bit_length():
+        assert mc.tune_lookup(n - 1, nnz - 2, vo) is not None
+    # another class: twice the entries
+    assert mc.tune_lookup(n, 2 * nnz, vo) is None
+    announce("tuned solve", rep)
+    lams, sides, st = mc.mincut_batched(rp, col, w, vo, use_tuned=1)
+    _check(graphs, refs, vo, lams, sides)
+    mc.tune_clear()
+    assert mc.tune_lookup(n, nnz, vo) is None
