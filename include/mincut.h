@@ -200,6 +200,15 @@ typedef struct mc_options {
                               problem's size class on the current device
                               (see mc_tune_batched), when there is one;
                               the caller's values otherwise.  Default 0. */
+  int32_t emit_rows;       /* the contraction's key emit: 0 (default) reads
+                              every entry, or, on graphs of at least 2^22
+                              entries where the rows of vertices outside
+                              their graph's reference block (its most
+                              common block) hold under a quarter of the
+                              entries, only those rows (the symmetric
+                              CSR gives each skipped row's crossing
+                              entries as mirrors); 1: always row-wise;
+                              -1: never.  Changes no result. */
   int32_t reserved[1];
 } mc_options;
 

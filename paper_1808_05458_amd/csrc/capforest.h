@@ -53,6 +53,7 @@ struct Ctl {
   int64_t lam_floor;     // the smallest bound of a tested graph (Padberg-Rinaldi prefilter)
   int32_t asym;          // symmetry check: some vertex pair's two directions differ
   int32_t pad_;
+  int64_t nonref_nnz;    // contraction: entries in rows outside their graph's reference block
 };
 
 struct ScanArgs {

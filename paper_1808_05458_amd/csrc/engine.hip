@@ -45,6 +45,9 @@ constexpr int WHOLE_CAP_S = 2048;
 constexpr int WHOLE_CAP_L = 8192;
 constexpr int SMALL_CAP_S = 2048;  // LDS-resident sweeps of whole small graphs
 constexpr int SMALL_CAP_L = 8192;
+// contractions of graphs with at least this many entries count the entries
+// of rows outside the reference blocks, to choose the row-wise emit
+constexpr int64_t ROWWISE_MIN_NNZ = 1 << 22;
 constexpr int LDS_PER_CU = 160 * 1024;
 constexpr int64_t SWEEP_HANDOFF_ENTRIES = 1 << 16;  // batches with longer rows run grid-wide
 constexpr int32_t MAX_SWEEPS = 256;                 // full-graph sweeps run at once
@@ -914,16 +917,38 @@ struct Solver {
     auto gridr = [&](int64_t n) { return dim3(grid_for(n, TB, num_cu * 2)); };
     const int bb = std::max(1, bitlen((uint64_t)std::max(n_next, 1) - 1));
     MC_HIP(hipMemsetAsync(&ws.ctl->emit, 0, sizeof(int64_t), s));
+    MC_HIP(hipMemsetAsync(&ws.ctl->nonref_nnz, 0, sizeof(int64_t), s));
+    // on a large graph the entries of rows outside the reference blocks are
+    // counted: when they are few, only those rows are read (k_emit_rows)
+    const bool count_rows = nnz >= ROWWISE_MIN_NNZ;
     {
       // the labels read once, one bit written per vertex
-      TimedScope t(nm.block_bits, (double)n_cur * 8);
+      TimedScope t(nm.block_bits, (double)n_cur * (count_rows ? 24 : 8));
       hipLaunchKernelGGL(k_block_ref, dim3(grid_for((int64_t)ngraphs * 64, TB, num_cu * 8)), dim3(TB), 0, s,
                          ngraphs, n_cur, ws.cvoff, ws.gn, lab, ws.bref);
       hipLaunchKernelGGL(k_block_bits, dim3(grid_for(n_cur, TB, num_cu * 16)), dim3(TB), 0, s, n_cur, lab, gid_cur,
-                         ws.bref, ws.inref);
+                         ws.bref, ws.inref, count_rows ? rp_cur : (const int64_t*)nullptr, ws.ctl);
     }
-    need_first(n_cur, nnz, rp_cur);
-    {
+    bool rowwise = false;
+    int64_t nonref = nnz;
+    if (count_rows && opt.emit_rows >= 0) {
+      int rc = read_ctl();
+      if (rc) return rc;
+      nonref = ws.ctl_host->nonref_nnz;
+      rowwise = opt.emit_rows > 0 || nonref * 4 < nnz;
+    } else if (opt.emit_rows > 0) {
+      rowwise = true;
+    }
+    if (rowwise) {
+      // per selected vertex its label, bit and row bounds (16 B), per entry
+      // of its row col, w and the neighbour's label and bit (12 B); per
+      // emitted entry its key and weight (added once the count is read back)
+      TimedScope t(nm.emit, (double)n_cur * 8 + (double)nonref * 12);
+      static const int rows_grid = resident_grid((const void*)&k_emit_rows, TB, num_cu);
+      hipLaunchKernelGGL(k_emit_rows, dim3(grid_for((int64_t)(n_cur + 63) / 64 * 64, TB, rows_grid)), dim3(TB), 0,
+                         s, n_cur, rp_cur, col, w, lab, bb, ws.inref, ws.keys, ws.vals, ws.ctl);
+    } else {
+      need_first(n_cur, nnz, rp_cur);
       // per entry col and w and the label gather (12 B); per emitted entry
       // its key and weight (12 B, added once the count is read back)
       TimedScope t(nm.emit, (double)nnz * 12);

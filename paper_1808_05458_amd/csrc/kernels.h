@@ -198,7 +198,9 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
                                                 const int32_t* __restrict__ first, int64_t* cdeg, int32_t* gmaxw,
                                                 Ctl* ctl) {
   __shared__ int32_t pos_all[4][WCH];
+  __shared__ int32_t val_all[4][WCH];
   int32_t* pos = pos_all[threadIdx.x >> 6];
+  int32_t* vals = val_all[threadIdx.x >> 6];
   const int lane = lane_id();
   // largest weight of the chunks in one graph, per lane, folded into gmaxw
   // when the graph changes (same-address atomics serialise)
@@ -259,8 +261,7 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
         hi = voff[gk + 1];
       }
       if (ok && (yc[k] < lo || yc[k] >= hi || cc[k] < 1)) atomicExch(&ctl->err, -1);
-      const int64_t val = (ok && yc[k] != row[k]) ? (int64_t)cc[k] : 0;
-      wave_row_add(row[k], val, ok, cdeg);
+      vals[k * 64 + lane] = (ok && yc[k] != row[k]) ? cc[k] : 0;
       const int32_t ck = ok ? cc[k] : 0;
       if (one) {
         run_m = ck > run_m ? ck : run_m;
@@ -274,6 +275,43 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
         }
       }
     }
+    // weighted degrees: each lane sums its 8 consecutive entries by row
+    // (positions lane * 8 ..; rows ascend with the position): a row wholly
+    // inside the lane is added at once; its first and last rows continue in
+    // the neighbouring lanes, so the last is folded into the next lane's
+    // first, and the first rows are summed across the wave
+    wave_lds_sync();
+    int32_t rq[8];
+    int64_t vq[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      rq[k] = pos[lane * 8 + k];
+      vq[k] = vals[lane * 8 + k];
+    }
+    wave_lds_sync();  // vals is rewritten by the next chunk
+    int32_t hr = rq[0], cur = rq[0], tr = rq[0];
+    int64_t hs = 0, ts = 0, acc = 0;
+    bool in_head = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (rq[k] != cur) {
+        if (in_head) hs = acc;
+        else if (acc) atomicAdd((unsigned long long*)(cdeg + cur), (unsigned long long)acc);
+        in_head = false;
+        cur = rq[k];
+        acc = 0;
+      }
+      acc += vq[k];
+    }
+    if (in_head) hs = acc;
+    else { tr = cur; ts = acc; }
+    const bool has_tail = !in_head;
+    const int32_t next_head = __shfl_down(hr, 1, 64);
+    const bool tail_on = has_tail && lane < 63 && next_head == tr;
+    if (has_tail && !tail_on && ts) atomicAdd((unsigned long long*)(cdeg + tr), (unsigned long long)ts);
+    const int64_t carried = __shfl_up(tail_on ? ts : (int64_t)0, 1, 64);
+    if (lane > 0) hs += carried;
+    wave_row_add(hr, hs, true, cdeg);
   }
   const uint32_t m = wave_max_u32((uint32_t)run_m);
   if (lane == 0 && m && run_g >= 0) atomicMax(gmaxw + run_g, (int32_t)m);
@@ -938,17 +976,25 @@ __global__ void k_block_ref(int32_t G, int32_t n, const int32_t* cvoff, const in
 }
 
 // bit v of inref: v's block is its graph's reference block (one wave per 64
-// vertices).
+// vertices).  With rp: also the entries of the rows outside reference
+// blocks into ctl->nonref_nnz (the row-wise emit's work).
 __global__ void k_block_bits(int32_t n, const int32_t* lab, const int32_t* gid, const int32_t* ref,
-                             uint32_t* inref) {
+                             uint32_t* inref, const int64_t* rp, Ctl* ctl) {
+  int64_t rows = 0;
   for (int64_t base = (gtid() >> 6) << 6; base < n; base += gstride()) {
     const int64_t v = base + lane_id();
-    const bool in = v < n && lab[v] >= 0 && lab[v] == ref[gid[v]];
+    const int32_t l = v < n ? lab[v] : -1;
+    const bool in = l >= 0 && l == ref[gid[v]];
     const uint64_t m = ballot(in);
     if (lane_id() == 0) {
       inref[base >> 5] = (uint32_t)m;
       inref[(base >> 5) + 1] = (uint32_t)(m >> 32);
     }
+    if (rp && l >= 0 && !in) rows += rp[v + 1] - rp[v];
+  }
+  if (rp) {
+    rows = wave_sum_i64(rows);
+    if (lane_id() == 0 && rows) atomicAdd((unsigned long long*)&ctl->nonref_nnz, (unsigned long long)rows);
   }
 }
 
@@ -1050,6 +1096,81 @@ __global__ void __launch_bounds__(256) k_emit(int32_t n, int64_t nnz, const int6
       o += popc64(msk[k]);
     }
     st_n += tot;
+  }
+  if (st_n) flush();
+}
+
+// The same keys, row by row, for contractions where most vertices lie in
+// their graph's reference block: only rows of vertices outside it are read.
+// The CSR is symmetric (each edge in both rows, same weight), so an entry
+// (u, x) with x in a reference block also yields the key of its mirror
+// (x, u), whose row is skipped; an entry with both ends outside is emitted
+// from each end's own row.  One wave per 64 vertices; each selected row is
+// read by the whole wave, 64 entries a step.  Survivors are staged as in
+// k_emit.
+__global__ void __launch_bounds__(256) k_emit_rows(int32_t n, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ w,
+                                                   const int32_t* __restrict__ lab, int bits,
+                                                   const uint32_t* __restrict__ inref,
+                                                   uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                   Ctl* ctl) {
+  __shared__ uint64_t stk_all[4][WCH];
+  __shared__ int32_t stv_all[4][WCH];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  uint64_t* st_k = stk_all[wave];
+  int32_t* st_v = stv_all[wave];
+  uint32_t st_n = 0;  // wave-uniform
+  auto flush = [&]() {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long*)&ctl->emit, (unsigned long long)st_n);
+    base = (unsigned long long)readlane_i64((int64_t)base, 0);
+    wave_lds_sync();
+    for (uint32_t i = lane; i < st_n; i += 64) {
+      keys[base + i] = st_k[i];
+      vals[base + i] = st_v[i];
+    }
+    wave_lds_sync();
+    st_n = 0;
+  };
+  for (int64_t base = gwave() << 6; base < n; base += gwaves() << 6) {
+    const int64_t v = base + lane;
+    const int32_t l = v < n ? lab[v] : -1;
+    const bool in = v < n && ((inref[v >> 5] >> (v & 31)) & 1u);
+    uint64_t todo = ballot(l >= 0 && !in);
+    while (todo) {
+      const int src_lane = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int32_t u = (int32_t)base + src_lane;
+      const int32_t a = __builtin_amdgcn_readlane(l, src_lane);
+      const int64_t e0 = rp[u], e1 = rp[u + 1];
+      for (int64_t b0 = e0; b0 < e1; b0 += 64) {
+        const int64_t e = b0 + lane;
+        const bool ok = e < e1;
+        const int64_t ec = ok ? e : b0;
+        const int32_t x = col[ec];
+        const int32_t c = w[ec];
+        const bool xin = ok && ((inref[x >> 5] >> (x & 31)) & 1u);
+        const int32_t b = ok ? lab[x] : -1;
+        const bool keep = ok && b >= 0 && b != a;
+        const bool mirror = keep && xin;
+        const uint64_t mk = ballot(keep), mm = ballot(mirror);
+        const uint32_t tot = popc64(mk) + popc64(mm);
+        if (tot == 0) continue;  // wave-uniform
+        if (st_n + tot > (uint32_t)WCH) flush();
+        if (keep) {
+          const uint32_t at = st_n + popc64(mk & lanemask_lt());
+          st_k[at] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
+          st_v[at] = c;
+        }
+        if (mirror) {
+          const uint32_t at = st_n + popc64(mk) + popc64(mm & lanemask_lt());
+          st_k[at] = ((uint64_t)(uint32_t)b << bits) | (uint32_t)a;
+          st_v[at] = c;
+        }
+        st_n += tot;
+      }
+    }
   }
   if (st_n) flush();
 }

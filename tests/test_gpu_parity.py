@@ -89,6 +89,27 @@ def test_queue_orders_and_repeated_visits_against_noi(opts):
         check_side(g, lam, side)
 
 
+@pytest.mark.parametrize("emit_rows", [1, -1])
+def test_row_wise_emit_on_a_packed_batch(emit_rows):
+    """The contraction's row-wise key emit (rows outside each graph's
+    reference block only, skipped rows' entries as mirrors) and the
+    entry-wise emit give the oracle's lambda on every graph of a packed
+    batch, with sides that realise it."""
+    import paper_1808_05458_amd as mc
+    rng = np.random.default_rng(71 + emit_rows)
+    graphs = [random_graph(rng, int(rng.integers(10, 300)), float(rng.uniform(0.03, 0.3)),
+                           int(rng.choice([1, 3, 20]))) for _ in range(60)]
+    refs = [oracle.noi(g, 1)[0] for g in graphs]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    announce("emit rows", emit_rows, packed.n, packed.m)
+    lams, sides, st = mc.mincut_batched(rp, col, w, vo, emit_rows=emit_rows)
+    assert list(lams) == refs
+    s = sides.cpu().numpy()
+    for i, g in enumerate(graphs):
+        check_side(g, int(lams[i]), s[vo[i]:vo[i + 1]])
+
+
 def test_queue_orders_are_refused_outside_their_range():
     import paper_1808_05458_amd as mc
     g = gg.complete(6)
@@ -129,7 +150,9 @@ def test_medium_graphs_against_noi():
                                   dict(pq_order=1), dict(pq_order=2, use_pr=0), dict(pq_order=3),
                                   dict(whole_max=16, scan_mode=1, pq_order=2),
                                   dict(whole_max=16, scan_mode=1, scan_visits=3, use_pr=0),
-                                  dict(scan_mode=2, pq_order=1)])
+                                  dict(scan_mode=2, pq_order=1),
+                                  dict(emit_rows=1), dict(emit_rows=1, whole_max=16, use_pr=0),
+                                  dict(emit_rows=-1, whole_max=16)])
 def test_planted_4096_options(opts):
     g = gg.planted_4096()
     gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["planted_4096"]
