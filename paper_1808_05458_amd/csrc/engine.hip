@@ -678,10 +678,14 @@ struct Solver {
       run.resize(k);
       for (int32_t i = 0; i < k; ++i) run[i] = i;
       double big_deg = 0, big_vtx = 0;
+      std::vector<int32_t> run_on_device;  // the run list last copied to ws.sw_run
       while (!run.empty()) {
         const int32_t nrun = (int32_t)run.size();
-        std::memcpy(ws.sw_run_host, run.data(), sizeof(int32_t) * nrun);
-        MC_HIP(hipMemcpyAsync(ws.sw_run, ws.sw_run_host, sizeof(int32_t) * nrun, hipMemcpyHostToDevice, s));
+        if (run != run_on_device) {
+          std::memcpy(ws.sw_run_host, run.data(), sizeof(int32_t) * nrun);
+          MC_HIP(hipMemcpyAsync(ws.sw_run, ws.sw_run_host, sizeof(int32_t) * nrun, hipMemcpyHostToDevice, s));
+          run_on_device = run;
+        }
         {
           TimedScope t("k_sweep_seq", 0.0);
           hipLaunchKernelGGL(k_sweep_seq, dim3(nrun), dim3(SWEEP_THREADS), 0, s, ws.sw_args, ws.sw_run);
@@ -716,8 +720,6 @@ struct Solver {
           }
           const int32_t bh = c.cap_head, bt = c.cap_tail;
           const int64_t bsz = bt - bh;
-          MC_HIP(hipMemsetAsync(&A.ctl->batch_sum, 0, 24, s));
-          MC_HIP(hipMemsetAsync(&A.ctl->pull_alpha, 0, 8, s));
           {
             // per batch vertex its FIFO slot, degree, r word and stamp
             TimedScope t("k_sweep_big_mark", (double)bsz * 32);

@@ -1207,8 +1207,11 @@ __global__ void k_sweep_big_finish(SweepArgs A, int32_t t, int32_t pull) {
     c->batch_internal = 0;
   }
   sweep_close_batch(c, A.ng, c->batch_sum, c->batch_internal, t - h, stamp);
+  // zero for the next grid-wide batch (k_sweep_init zeroes them first)
   c->batch_sum = 0;
   c->batch_internal = 0;
+  c->batch_deg = 0;
+  c->pull_alpha = 0;
   c->status = SW_RUNNING;
 }
 
