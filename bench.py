@@ -296,8 +296,11 @@ def served_form(requests, lanes, seed=5):
 
 
 def solve_single(g, steps, warmup, gold_lambda, label):
-    """Time `steps` exact solves of one resident graph, with the kernel
-    classes event-timed on the solve stream."""
+    """Time `steps` exact solves of one resident graph.  A profile pass
+    first (up to 3 solves, every kernel class event-timed on the solve
+    stream) names the dominant class; the timed solves then record HIP
+    events around that class's launches only, so the timed region pays for
+    a few events per solve, not for every class's."""
     import torch
     import paper_1808_05458_amd as mc
     rp, col, w = mc.to_device(g, "cuda:0")
@@ -305,7 +308,18 @@ def solve_single(g, steps, warmup, gold_lambda, label):
         lam, side, st = mc.mincut(rp, col, w)
         log(f"{label} warmup {i}: lambda={lam} rounds={st['rounds']} {st['ms']:.1f} ms n_round={st['n_round']}")
     topts = mc.options(timing=1)
+    prof_steps = max(1, min(steps, 3))
+    mc.timing_focus(None)
     mc.timing_reset()
+    for i in range(prof_steps):
+        mc.mincut(rp, col, w, opts=topts)
+    torch.cuda.synchronize()
+    classes = mc.timing()
+    log(f"{label} kernel classes: " + ", ".join(f"{c['name']}={c['ms'] / prof_steps:.2f}ms"
+                                               for c in sorted(classes, key=lambda c: -c["ms"])))
+    dom_name = max(classes, key=lambda c: c["ms"])["name"]
+    mc.timing_reset()
+    mc.timing_focus(dom_name)
     lams = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -314,9 +328,9 @@ def solve_single(g, steps, warmup, gold_lambda, label):
         lams.append(lam)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    classes = mc.timing()
-    log(f"{label} kernel classes: " + ", ".join(f"{c['name']}={c['ms'] / steps:.2f}ms"
-                                               for c in sorted(classes, key=lambda c: -c["ms"])))
+    dom = [c for c in mc.timing() if c["name"] == dom_name][0]
+    mc.timing_focus(None)
+    mc.timing_reset()
     s = side.cpu().numpy()[: g.n].astype(bool)
     cut = int(g.w[s[g.src()] != s[g.col]].sum()) // 2
     verified = {"lambda": lams[0], "all_steps_equal": len(set(lams)) == 1, "oracle_lambda": gold_lambda,
@@ -327,14 +341,18 @@ def solve_single(g, steps, warmup, gold_lambda, label):
              "batches": st["sweep_batches"], "crossings": st["sweep_cross"]}
     del rp, col, w
     return {"ms_per_step": dt * 1000.0 / steps, "value": g.m * steps / dt, "rounds": st["rounds"],
-            "n_round": st["n_round"], "classes": classes, "verified": verified, "sweep_phases": sweep}
+            "n_round": st["n_round"], "classes": classes, "prof_steps": prof_steps, "dominant": dom,
+            "verified": verified, "sweep_phases": sweep}
 
 
-def roofline_of(classes, steps, traffic_file):
-    """The dominant kernel (most device time per step) against HBM peak:
-    algorithmic bytes per launch over its average launch time, plus the
+def roofline_of(r, steps, traffic_file):
+    """The dominant kernel (most device time per step in the profile pass)
+    against HBM peak: algorithmic bytes per launch over its average launch
+    time, both from the events of the timed region, plus the
     counter-measured bytes per launch when a summary taken on these sources
-    exists."""
+    exists.  Class fractions and the per-kernel table come from the profile
+    pass (r["prof_steps"] solves, every class timed)."""
+    classes, prof = r["classes"], r["prof_steps"]
     def rate(c):
         per_launch_s = c["ms"] / 1000.0 / c["launches"]
         per_launch_bytes = c["algo_bytes"] / c["launches"]
@@ -350,11 +368,11 @@ def roofline_of(classes, steps, traffic_file):
                 measured[f[1]] = int(f[5])
     if not digest_ok:
         measured = {}
-    dom = max(classes, key=lambda c: c["ms"])
+    dom = r["dominant"]
     achieved, dom_bytes = rate(dom)
 
     def entry(c):
-        e = {"ms_per_step": round(c["ms"] / steps, 3), "launches_per_step": c["launches"] / steps,
+        e = {"ms_per_step": round(c["ms"] / prof, 3), "launches_per_step": c["launches"] / prof,
              "algo_GBps": round(rate(c)[0], 1), "frac": round(rate(c)[0] / HBM_PEAK_GBS, 5)}
         if c["name"] in measured:
             e["counter_bytes_per_launch"] = measured[c["name"]]
@@ -373,7 +391,7 @@ def roofline_of(classes, steps, traffic_file):
         ms = sum(c["ms"] for c in cs)
         if ms > 0:
             gbps = sum(c["algo_bytes"] for c in cs) / (ms / 1000.0) / 1e9
-            class_frac[gname] = {"ms_per_step": round(ms / steps, 3), "algo_GBps": round(gbps, 1),
+            class_frac[gname] = {"ms_per_step": round(ms / prof, 3), "algo_GBps": round(gbps, 1),
                                  "frac": round(gbps / HBM_PEAK_GBS, 5)}
     return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": measured.get(dom["name"]),
@@ -404,7 +422,7 @@ def chung_lu_form(steps, approx=True):
     r = solve_single(g, steps, 1, golden()["chung_lu_4m_8core"]["lambda"], "chung_lu")
     out = {"n": g.n, "m": g.m, "ms": round(r["ms_per_step"], 3), "edges_per_s": r["value"],
            "rounds": r["rounds"], "verified": r["verified"], "sweep_phases": r["sweep_phases"],
-           "roofline": roofline_of(r["classes"], steps,
+           "roofline": roofline_of(r, steps,
                                    os.path.join(ROOT, "profiles", "hbm_traffic_chung_lu_2^22_8core.txt"))}
     if approx:
         rp, col, w = mc.to_device(g, "cuda:0")
@@ -580,7 +598,7 @@ def main():
         workload = "chung_lu n=2^22 exp2.5 avgdeg32 unit-weight 8-core LCC"
     log(f"generated {g.name}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
     r = solve_single(g, args.steps, args.warmup, golden().get(gold_key, {}).get("lambda"), args.workload)
-    roofline = roofline_of(r["classes"], args.steps, os.path.join(ROOT, "profiles", traffic_name))
+    roofline = roofline_of(r, args.steps, os.path.join(ROOT, "profiles", traffic_name))
     n, m = g.n, g.m
     del g
     extra = {}

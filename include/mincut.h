@@ -465,9 +465,16 @@ typedef struct mc_timing_entry {
   double algo_bytes;
 } mc_timing_entry;
 
-/* Copies up to `max` entries; returns how many classes exist. */
+/* Copies up to `max` entries; returns how many classes exist.  The events
+ * of timed solves are read here (waiting for them), not at the end of each
+ * solve, so a timed loop pays only for recording them.  Per host thread. */
 int mc_timing_get(mc_timing_entry* out, int max);
+/* Reads any pending events, then clears the classes. */
 void mc_timing_reset(void);
+/* Time only the class `name` (NULL or "" = every class), for the calling
+ * thread: a timed loop then records two events per launch of that class
+ * and none for the others. */
+void mc_timing_focus(const char* name);
 
 #ifdef __cplusplus
 }

@@ -170,6 +170,8 @@ def _load():
     lib.mc_timing_get.restype = ctypes.c_int
     lib.mc_timing_reset.argtypes = []
     lib.mc_timing_reset.restype = None
+    lib.mc_timing_focus.argtypes = [ctypes.c_char_p]
+    lib.mc_timing_focus.restype = None
     lib.mc_server_cfg_default.argtypes = [vp]
     lib.mc_server_cfg_default.restype = None
     lib.mc_server_create.argtypes = [vp, vp]
@@ -546,6 +548,11 @@ def timing():
 
 def timing_reset():
     _load().mc_timing_reset()
+
+
+def timing_focus(name=None):
+    """Time only the kernel class `name` (None: every class)."""
+    _load().mc_timing_focus(name.encode() if name else None)
 
 
 def to_device(g, device="cuda"):

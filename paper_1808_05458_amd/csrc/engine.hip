@@ -63,6 +63,7 @@ struct TimingClass {
 struct Timer {
   bool on = false;
   hipStream_t s = nullptr;
+  std::string focus;  // if set, only this class is timed (mc_timing_focus)
   std::vector<TimingClass> classes;
   struct Pending {
     int cls;
@@ -88,9 +89,10 @@ struct Timer {
     hipEventCreate(&e);
     return e;
   }
+  bool wants(const char* name) const { return on && (focus.empty() || focus == name); }
   // begin/end bracket a launch (or a short sequence) of one class
   int begin(const char* name, hipEvent_t& a) {
-    if (!on) return -1;
+    if (!wants(name)) return -1;
     a = ev();
     hipEventRecord(a, s);
     return cls(name);
@@ -100,10 +102,11 @@ struct Timer {
     hipEvent_t b = ev();
     hipEventRecord(b, s);
     pending.push_back({c, a, b, bytes});
+    if (pending.size() >= 16384) collect();  // bound the events held between reads
   }
   // bytes known only after a class's launches have run
   void add_bytes(const char* name, double bytes) {
-    if (!on) return;
+    if (!wants(name)) return;
     pending_bytes.push_back({cls(name), bytes});
   }
   std::vector<std::pair<int, double>> pending_bytes;
@@ -808,7 +811,7 @@ struct Solver {
       // (timing mode only, which synchronises anyway: the counters are
       // read back per graph, with the per-phase step counts for the stats)
       double crossings = 0;
-      if (timer().on) {
+      if (timer().wants("k_sweep_seq") || timer().wants("k_sweep_tail") || timer().wants("k_sweep_unite")) {
         double visited = 0, seq_rows = 0, tail_rows = 0, tail_pops = 0;
         for (int32_t i = 0; i < k; ++i) {
           SweepCtl c;
@@ -1718,7 +1721,8 @@ int run_on(Workspace& ws, const Problem& P, void* stream, const mc_options* opt,
   sv.viecut_only = viecut_levels != nullptr;
   rc = sv.solve(P, lambdas, side, st);
   if (viecut_levels) *viecut_levels = sv.vc_levels_run;
-  if (T.on) T.collect();
+  // the events are read when the classes are (mc_timing_get), after the
+  // caller's timed region, not at the end of every solve
   T.on = false;
   if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
@@ -2127,6 +2131,7 @@ const char* mc_strerror(int code) {
 
 int mc_timing_get(mc_timing_entry* out, int max) {
   auto& T = mc::timer();
+  T.collect();
   int n = (int)T.classes.size();
   for (int i = 0; i < n && i < max; ++i) {
     std::memset(&out[i], 0, sizeof(out[i]));
@@ -2138,7 +2143,13 @@ int mc_timing_get(mc_timing_entry* out, int max) {
   return n;
 }
 
-void mc_timing_reset(void) { mc::timer().classes.clear(); }
+void mc_timing_focus(const char* name) { mc::timer().focus = name ? name : ""; }
+
+void mc_timing_reset(void) {
+  auto& T = mc::timer();
+  T.collect();
+  T.classes.clear();
+}
 
 }  // extern "C"
 

@@ -22,6 +22,7 @@
 // entries made stale by a large batch never have to be walked.
 #pragma once
 #include "dev.h"
+#include "rows.h"
 
 namespace mc {
 
@@ -1383,6 +1384,7 @@ __global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32
     if (t) atomicAdd((unsigned long long*)&c->pull_alpha, (unsigned long long)t);
   }
 }
+
 
 // ---- exact rebuild of the bucket queue from the frontier (counting sort)
 __global__ void k_sweep_rb_zero(SweepArgs A) {
