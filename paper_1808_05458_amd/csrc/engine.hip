@@ -568,6 +568,15 @@ struct Solver {
     TimedScope t("k_fill_src", (double)nnz * 4 + (double)n * 8);
     hipLaunchKernelGGL(k_fill_src, chunk_grid(nnz, num_cu * 8), dim3(256), 0, s, n, nnz, rp, ws.first, src);
   }
+  // PR1/PR2 on every entry of graph (n, nnz, rp, col, w).
+  int pr_tests(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* col, const int32_t* w,
+               const int64_t* cdeg, const int32_t* gid, const int64_t* lhat, const int32_t* active) {
+    if (nnz <= 0) return MC_OK;
+    need_first(n, nnz, rp);
+    hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(256), 0, s, n, nnz, rp, ws.first, col, w, cdeg,
+                       gid, lhat, active, ws.parent, ws.ucount, ws.ctl);
+    return MC_OK;
+  }
   void need_src(int32_t n, int64_t nnz, const int64_t* rp) {
     if (src_ok) return;
     fill_src(n, nnz, rp, ws.src);
@@ -1137,9 +1146,8 @@ struct Solver {
                              ws.parent, ws.ucount);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, ws.lhat, V.act, ws.ctl);
-          need_first(n, nnz, rp);
-          hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(TB), 0, s, n, nnz, rp, ws.first, col, w,
-                             cdeg, gid, ws.lhat, V.act, ws.parent, ws.ucount, ws.ctl);
+          const int prc = pr_tests(n, nnz, rp, col, w, cdeg, gid, ws.lhat, V.act);
+          if (prc) return prc;
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           exclusive_scan<int32_t, RootFlag>(RootFlag{ws.parent, gid, V.act, carry}, n, ws.newid, &ws.ctl->n_next,
                                             ws.tmp, s);
@@ -1389,9 +1397,8 @@ struct Solver {
           // is rejected from it alone), per vertex its row bounds and c(u)
           // (16 B): a lower bound of what the tests must read
           TimedScope t("k_pr", (double)nnz * 4 + (double)n * 16);
-          need_first(n, nnz, rp);
-          hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(TB), 0, s, n, nnz, rp, ws.first, col, w,
-                             ws.cdeg, gid, cap, tested, ws.parent, ws.ucount, ws.ctl);
+          const int prc = pr_tests(n, nnz, rp, col, w, ws.cdeg, gid, cap, tested);
+          if (prc) return prc;
         }
       }
       // the triangle tests on contracted graphs (from the second round; a

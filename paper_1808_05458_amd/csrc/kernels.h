@@ -137,14 +137,19 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
   int32_t run_g = -1, run_m = 0;
   int64_t ch = gwave();
   int32_t y[8], c[8], f = 0;
+  // a chunk's entries through a wave-uniform base and 32-bit offsets (one
+  // address add per chunk, not one 64-bit add per entry)
   auto load = [&](int64_t at) {
     const int64_t e0 = at * WCH;
+    const int32_t len = (int32_t)min((int64_t)WCH, nnz - e0);
+    const int32_t* cb = col + e0;
+    const int32_t* wb = w + e0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int64_t e = e0 + k * 64 + lane;
-      const int64_t ec = e < nnz ? e : e0;
-      y[k] = col[ec];
-      c[k] = w[ec];
+      const int32_t o = k * 64 + lane;
+      const int32_t oc = o < len ? o : 0;
+      y[k] = cb[oc];
+      c[k] = wb[oc];
     }
     f = chunk_first(first, at, n);
   };
@@ -157,8 +162,9 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
     // the chunk's graph: the first row's, when its last row is in it too
     // (graphs are contiguous vertex ranges)
     const int32_t g0 = gid[r0];
-    const int64_t lo0 = voff[g0], hi0 = voff[g0 + 1];
-    const int64_t last_e = min(e0 + WCH, nnz) - 1 - e0;  // slot and lane of the chunk's last entry
+    const int32_t lo0 = (int32_t)voff[g0], hi0 = (int32_t)voff[g0 + 1];  // vertex ids fit 31 bits
+    const int32_t len = (int32_t)min((int64_t)WCH, nnz - e0);
+    const int32_t last_e = len - 1;  // slot and lane of the chunk's last entry
     int32_t row_last = r0;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
@@ -179,18 +185,17 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int64_t e = e0 + k * 64 + lane;
-      const bool ok = e < nnz;
+      const bool ok = k * 64 + lane < len;
       // a chunk across a graph boundary (wave-uniform) reads each entry's
       // graph range; graphs are contiguous vertex ranges
       int32_t gk = g0;
-      int64_t lo = lo0, hi = hi0;
+      int32_t lo = lo0, hi = hi0;
       if (!one) {
         gk = gid[ok ? row[k] : r0];
-        lo = voff[gk];
-        hi = voff[gk + 1];
+        lo = (int32_t)voff[gk];
+        hi = (int32_t)voff[gk + 1];
       }
-      if (ok && (yc[k] < lo || yc[k] >= hi || cc[k] < 1)) atomicExch(&ctl->err, -1);
+      if (ok && ((uint32_t)(yc[k] - lo) >= (uint32_t)(hi - lo) || cc[k] < 1)) atomicExch(&ctl->err, -1);
       vals[k * 64 + lane] = (ok && yc[k] != row[k]) ? cc[k] : 0;
       const int32_t ck = ok ? cc[k] : 0;
       if (one) {
