@@ -312,7 +312,7 @@ def solve_single(g, steps, warmup, gold_lambda, label):
     mc.timing_focus(None)
     mc.timing_reset()
     for i in range(prof_steps):
-        mc.mincut(rp, col, w, opts=topts)
+        _, _, st_prof = mc.mincut(rp, col, w, opts=topts)
     torch.cuda.synchronize()
     classes = mc.timing()
     log(f"{label} kernel classes: " + ", ".join(f"{c['name']}={c['ms'] / prof_steps:.2f}ms"
@@ -337,8 +337,9 @@ def solve_single(g, steps, warmup, gold_lambda, label):
                 "equals_oracle": gold_lambda is not None and all(x == gold_lambda for x in lams),
                 "side_cut_weight": cut, "side_size": int(s.sum())}
     log(f"{label} verify: {verified}")
-    sweep = {"big_batches": st["sweep_big_batches"], "singles": st["sweep_singles"],
-             "batches": st["sweep_batches"], "crossings": st["sweep_cross"]}
+    # (the per-phase sweep counters are read back in the profile pass)
+    sweep = {"big_batches": st_prof["sweep_big_batches"], "singles": st_prof["sweep_singles"],
+             "batches": st_prof["sweep_batches"], "crossings": st_prof["sweep_cross"]}
     del rp, col, w
     return {"ms_per_step": dt * 1000.0 / steps, "value": g.m * steps / dt, "rounds": st["rounds"],
             "n_round": st["n_round"], "classes": classes, "prof_steps": prof_steps, "dominant": dom,

@@ -801,11 +801,11 @@ struct Solver {
                                  (const int64_t*)off, (const int32_t*)tile_row, (const uint32_t*)ws.st2);
             }
           }
-          hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(64), 0, s, A, bt, pull ? 1 : 0);
+          hipLaunchKernelGGL(k_sweep_big_finish, dim3(1), dim3(256), 0, s, A, bt, pull ? 1 : 0);
           {
-            // exact queue rebuild: two passes over the graph's vertices
+            // exact queue rebuild: two passes over the graph's vertices (the
+            // finish kernel cleared the bucket counts)
             TimedScope t("sweep_rebuild", (double)A.ng * 16);
-            hipLaunchKernelGGL(k_sweep_rb_zero, dim3(16), dim3(256), 0, s, A);
             hipLaunchKernelGGL(k_sweep_rb_count, dim3(grid_for(A.ng, TB, num_cu * 4)), dim3(TB), 0, s, A);
             hipLaunchKernelGGL(k_sweep_rb_scan, dim3(1), dim3(1024), 0, s, A);
             hipLaunchKernelGGL(k_sweep_rb_fill, dim3((A.ng + RB_TILE - 1) / RB_TILE), dim3(TB), 0, s, A);

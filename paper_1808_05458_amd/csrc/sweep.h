@@ -1194,9 +1194,12 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
 
 // pull: the batch was relaxed in pull form, whose c(S + B) replaces alpha
 // (the sum of the free vertices' new r, each their weight to S + B).
+// Also clears the bucket counts for the queue rebuild that follows (the
+// work of k_sweep_rb_zero).
 __global__ void k_sweep_big_finish(SweepArgs A, int32_t t, int32_t pull) {
-  if (gtid() != 0) return;
   SweepCtl* c = A.ctl;
+  for (int64_t i = gtid(); i < SWEEP_BUCKETS; i += gstride()) c->seg_end[i] = 0;
+  if (gtid() != 0) return;
   const int32_t h = c->cap_head;
   const int32_t stamp = ++c->step;
   c->batches += 1;
@@ -1414,14 +1417,19 @@ __global__ void __launch_bounds__(1024) k_sweep_rb_scan(SweepArgs A) {
   const int b0 = threadIdx.x * per;
   int32_t s = 0;
   for (int k = 0; k < per && b0 + k < A.nb; ++k) s += c->seg_end[b0 + k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int i = 0; i < 1024; ++i) { int32_t t = part[i]; part[i] = run; run += t; }
+  // exclusive scan of the 1024 thread sums: within each wave, then over
+  // the 16 wave totals
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int32_t incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
   }
+  if (lane == 63) part[wave] = incl;
   __syncthreads();
-  int32_t run = part[threadIdx.x];
+  int32_t before = 0;
+  for (int k = 0; k < wave; ++k) before += part[k];
+  int32_t run = before + incl - s;
   for (int k = 0; k < per && b0 + k < A.nb; ++k) {
     const int b = b0 + k;
     const int32_t cnt = c->seg_end[b];
