@@ -168,6 +168,7 @@ struct Workspace {
   // entry arrays
   int32_t *src, *col, *w;
   int32_t* first;  // the row of every WCH-th entry of the graph being read (k_chunk_rows)
+  int32_t* chmax;  // the largest weight of every WCH-entry chunk of the ingested graph
   uint64_t *keys, *keys_alt;
   int32_t *vals, *vals_alt;
   // graph arrays
@@ -290,6 +291,7 @@ size_t carve(Workspace& ws, char* base, int64_t N, int64_t E, int64_t G) {
   take(ws.cdeg, (N + 2) * 8);
   take(ws.src, E * 4);
   take(ws.first, (E / WCH + 2) * 4);
+  take(ws.chmax, (E / WCH + 2) * 4);
   take(ws.col, E * 4);
   take(ws.w, E * 4);
   take(ws.keys, (E + 64) * 8);
@@ -544,6 +546,10 @@ struct Solver {
   // ws.src holds the sources of the loop's current graph (the ingest leaves
   // them unwritten; only some consumers index entries one at a time)
   bool src_ok = false;
+  // ws.chmax holds the chunk maxima of the graph (rp, w, nnz) the ingest read
+  const int64_t* chmax_rp = nullptr;
+  const int32_t* chmax_w = nullptr;
+  int64_t chmax_nnz = -1;
 
   // The row of every WCH-th entry of graph (n, nnz, rp) in ws.first.
   void need_first(int32_t n, int64_t nnz, const int64_t* rp) {
@@ -573,8 +579,11 @@ struct Solver {
                const int64_t* cdeg, const int32_t* gid, const int64_t* lhat, const int32_t* active) {
     if (nnz <= 0) return MC_OK;
     need_first(n, nnz, rp);
-    hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(256), 0, s, n, nnz, rp, ws.first, col, w, cdeg,
-                       gid, lhat, active, ws.parent, ws.ucount, ws.ctl);
+    // the ingested graph itself: its chunk maxima let the tests skip chunks
+    // without reading them
+    const int32_t* cm = (chmax_rp == rp && chmax_w == w && chmax_nnz == nnz) ? ws.chmax : nullptr;
+    hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(256), 0, s, n, nnz, rp, ws.first, col, w, cm,
+                       cdeg, gid, lhat, active, ws.parent, ws.ucount, ws.ctl);
     return MC_OK;
   }
   void need_src(int32_t n, int64_t nnz, const int64_t* rp) {
@@ -1019,6 +1028,7 @@ struct Solver {
     }
     *m2_out = m2;
     first_rp = nullptr;  // the graphs may have been written over
+    chmax_rp = nullptr;
     return MC_OK;
   }
 
@@ -1238,7 +1248,10 @@ struct Solver {
         TimedScope t("k_ingest", (double)E * 8 + (double)N * 16);
         static const int ingest_grid = resident_grid((const void*)&k_ingest, TB, num_cu);
         hipLaunchKernelGGL(k_ingest, chunk_grid(E, ingest_grid), dim3(TB), 0, s, N, E, P.rp, P.col, P.w, gid,
-                           ws.voff, ws.first, ws.cdeg, ws.gmaxw, ws.ctl);
+                           ws.voff, ws.first, G, ws.cdeg, ws.gmaxw, ws.chmax, ws.ctl);
+        chmax_rp = P.rp;
+        chmax_w = P.w;
+        chmax_nnz = E;
       }
       src_ok = false;
       fill<uint64_t>(ws.bdeg, ~0ull, G, s);
@@ -2026,7 +2039,7 @@ int mc_debug_contract(const mc_graph* g, const int32_t* labels, int32_t n_new, v
   if (nnz > 0) {
     hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(g->n, TB, ncu * 16)), dim3(TB), 0, s, g->n, g->row_ptr, ws.first);
     hipLaunchKernelGGL(k_ingest, chunks, dim3(TB), 0, s, g->n, nnz, g->row_ptr, g->col, g->w, ws.gid[0], ws.voff,
-                       ws.first, ws.cdeg, ws.gmaxw, ws.ctl);
+                       ws.first, 1, ws.cdeg, ws.gmaxw, ws.chmax, ws.ctl);
   }
   // every col inside [0, n) before the emit indexes the labels by it
   MC_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

@@ -117,16 +117,20 @@ __device__ __forceinline__ void wave_row_add(int32_t row, int64_t val, bool ok, 
 }
 
 // Validation and weighted degrees (self-loops excluded; they never cross a
-// cut), one WCH-entry chunk per wave step, rows from chunk_rows.  The next
-// chunk's entries and first row are loaded once this chunk's dependent
-// loads are issued, so they are in flight during its sums.
-__global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+// cut), one WCH-entry chunk per wave step, rows from chunk_rows.  Software
+// pipelined: once a chunk is checked and its weights are in LDS, the next
+// chunk's entries, the starts of its first rows and its first row's graph
+// go out, and the first row of the chunk after that (each a dependent load
+// of the one before), so they are in flight during the chunk's sums.
+// G = 1: one graph, whose range is [0, n) (no graph lookups).  chmax[c]: the
+// largest weight of chunk c (the tests skip chunks by it).
+__global__ void __launch_bounds__(256, 5) k_ingest(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col,
                                                 const int32_t* __restrict__ w,
                                                 const int32_t* __restrict__ gid,
                                                 const int64_t* __restrict__ voff,
-                                                const int32_t* __restrict__ first, int64_t* cdeg, int32_t* gmaxw,
-                                                Ctl* ctl) {
+                                                const int32_t* __restrict__ first, int32_t G, int64_t* cdeg,
+                                                int32_t* gmaxw, int32_t* chmax, Ctl* ctl) {
   __shared__ int32_t pos_all[4][WCH];
   __shared__ int32_t val_all[4][WCH];
   int32_t* pos = pos_all[threadIdx.x >> 6];
@@ -136,7 +140,10 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
   // when the graph changes (same-address atomics serialise)
   int32_t run_g = -1, run_m = 0;
   int64_t ch = gwave();
-  int32_t y[8], c[8], f = 0;
+  const int64_t nch = (nnz + WCH - 1) / WCH;
+  int32_t y[8], c[8];
+  int32_t f = 0, fn = 0, gq = 0;  // first row of the loaded chunk and of the next; the loaded chunk's graph
+  int64_t s0 = 0;                 // the loaded chunk's first row starts (chunk_start0)
   // a chunk's entries through a wave-uniform base and 32-bit offsets (one
   // address add per chunk, not one 64-bit add per entry)
   auto load = [&](int64_t at) {
@@ -151,18 +158,26 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
       y[k] = cb[oc];
       c[k] = wb[oc];
     }
-    f = chunk_first(first, at, n);
+    f = fn;  // first[at], loaded a step earlier
+    s0 = chunk_start0(rp, n, f);
+    gq = G > 1 ? gid[f] : 0;
+    const int64_t nx = at + gwaves();
+    fn = nx < nch ? chunk_first(first, nx, n) : 0;
   };
-  if (ch * WCH < nnz) load(ch);
-  for (; ch * WCH < nnz; ch += gwaves()) {
+  if (ch < nch) {
+    fn = chunk_first(first, ch, n);
+    load(ch);
+  }
+  for (; ch < nch; ch += gwaves()) {
     const int64_t e0 = ch * WCH;
     const int32_t r0 = f;
     int32_t row[8];
-    chunk_rows(rp, n, e0, r0, pos, row);
+    chunk_rows_from(rp, n, e0, r0, s0, pos, row);
     // the chunk's graph: the first row's, when its last row is in it too
     // (graphs are contiguous vertex ranges)
-    const int32_t g0 = gid[r0];
-    const int32_t lo0 = (int32_t)voff[g0], hi0 = (int32_t)voff[g0 + 1];  // vertex ids fit 31 bits
+    const int32_t g0 = gq;
+    const int32_t lo0 = G > 1 ? (int32_t)voff[g0] : 0;  // vertex ids fit 31 bits
+    const int32_t hi0 = G > 1 ? (int32_t)voff[g0 + 1] : n;
     const int32_t len = (int32_t)min((int64_t)WCH, nnz - e0);
     const int32_t last_e = len - 1;  // slot and lane of the chunk's last entry
     int32_t row_last = r0;
@@ -170,19 +185,14 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
     for (int k = 0; k < 8; ++k)
       if ((last_e >> 6) == k) row_last = __builtin_amdgcn_readlane(row[k], (int)(last_e & 63));
     const bool one = row_last < hi0;
-    int32_t yc[8], cc[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      yc[k] = y[k];
-      cc[k] = c[k];
-    }
-    if (ch + gwaves() < (nnz + WCH - 1) / WCH) load(ch + gwaves());
     if (one && g0 != run_g) {
       const uint32_t m = wave_max_u32((uint32_t)run_m);
       if (lane == 0 && m && run_g >= 0) atomicMax(gmaxw + run_g, (int32_t)m);
       run_g = g0;
       run_m = 0;
     }
+    bool bad = false;
+    int32_t cmx = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const bool ok = k * 64 + lane < len;
@@ -195,9 +205,10 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
         lo = (int32_t)voff[gk];
         hi = (int32_t)voff[gk + 1];
       }
-      if (ok && ((uint32_t)(yc[k] - lo) >= (uint32_t)(hi - lo) || cc[k] < 1)) atomicExch(&ctl->err, -1);
-      vals[k * 64 + lane] = (ok && yc[k] != row[k]) ? cc[k] : 0;
-      const int32_t ck = ok ? cc[k] : 0;
+      bad = bad || (ok && ((uint32_t)(y[k] - lo) >= (uint32_t)(hi - lo) || c[k] < 1));
+      vals[k * 64 + lane] = (ok && y[k] != row[k]) ? c[k] : 0;
+      const int32_t ck = ok ? c[k] : 0;
+      cmx = ck > cmx ? ck : cmx;
       if (one) {
         run_m = ck > run_m ? ck : run_m;
       } else {
@@ -210,14 +221,21 @@ __global__ void __launch_bounds__(256, 4) k_ingest(int32_t n, int64_t nnz, const
         }
       }
     }
+    if (bad) atomicExch(&ctl->err, -1);
+    {
+      const uint32_t cm = wave_max_u32((uint32_t)cmx);
+      if (lane == 0) chmax[ch] = (int32_t)cm;
+    }
+    // the chunk's weights are in LDS: the next chunk's loads go out and are
+    // in flight during the sums below and the next chunk's row mapping
+    if (ch + gwaves() < nch) load(ch + gwaves());
     // weighted degrees: each lane sums its 8 consecutive entries by row
     // (positions lane * 8 ..; rows ascend with the position): a row wholly
     // inside the lane is added at once; its first and last rows continue in
     // the neighbouring lanes, so the last is folded into the next lane's
     // first, and the first rows are summed across the wave
     wave_lds_sync();
-    int32_t rq[8];
-    int64_t vq[8];
+    int32_t rq[8], vq[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       rq[k] = pos[lane * 8 + k];
@@ -626,10 +644,13 @@ __global__ void __launch_bounds__(256) k_lam_floor(int32_t G, const int64_t* lha
 // e0 + k * 64 + lane), loaded in rounds (weight; rows and ends; graph; its
 // bound; both degrees), each round for all slots; an entry already decided
 // reads a shared dummy address.  A chunk none of whose weights can pass for
-// any graph is dropped before its rows are found.
+// any graph is dropped before its rows are found.  chmax (the chunk maxima
+// of this graph, or null): the wave reads the maxima of its next 64 chunks
+// at once and skips the hopeless ones without reading their entries.
 __global__ void __launch_bounds__(256) k_pr(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
                                             const int32_t* __restrict__ first,
                                             const int32_t* __restrict__ col, const int32_t* __restrict__ w,
+                                            const int32_t* __restrict__ chmax,
                                             const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
                                             const int64_t* __restrict__ lhat, const int32_t* __restrict__ active,
                                             int32_t* parent, int32_t* ucount, Ctl* ctl) {
@@ -639,50 +660,58 @@ __global__ void __launch_bounds__(256) k_pr(int32_t n, int64_t nnz, const int64_
   int64_t local = 0;
   int32_t last = -1;
   const int64_t floor = ctl->lam_floor;  // hopeless for every graph: 2c <= floor
-  for (int64_t ch = gwave(); ch * WCH < nnz; ch += gwaves()) {
-    const int64_t e0 = ch * WCH;
-    int32_t c[8], u[8], v[8], g[8];
-    bool keep[8];
+  const int64_t nch = (nnz + WCH - 1) / WCH, W = gwaves();
+  // the wave's chunks gwave() + m W, m = 0, 1, ..., in groups of 64
+  for (int64_t cb = gwave(); cb < nch; cb += 64 * W) {
+    const int64_t cl = cb + lane * W;
+    uint64_t todo = ballot(cl < nch && (chmax == nullptr || !pr_hopeless(chmax[cl < nch ? cl : 0], floor)));
+    while (todo) {
+      const int64_t ch = cb + (int64_t)__builtin_ctzll(todo) * W;
+      todo &= todo - 1;
+      const int64_t e0 = ch * WCH;
+      int32_t c[8], u[8], v[8], g[8];
+      bool keep[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int64_t e = e0 + k * 64 + lane;
-      c[k] = w[e < nnz ? e : e0];
-    }
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      keep[k] = e0 + k * 64 + lane < nnz && !pr_hopeless(c[k], floor);
-      any = any || keep[k];
-    }
-    if (ballot(any) == 0) continue;  // wave-uniform: nothing left to test
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = col[keep[k] ? e0 + k * 64 + lane : e0];
-    chunk_rows(rp, n, e0, chunk_first(first, ch, n), pos, u);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      keep[k] = keep[k] && u[k] < v[k];
-      g[k] = gid[keep[k] ? u[k] : 0];
-    }
-    int64_t lam[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const bool act = active[g[k]] != 0;
-      lam[k] = lhat[g[k]];
-      keep[k] = keep[k] && act && !pr_hopeless(c[k], lam[k]);
-    }
-    int64_t cu[8], cv[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      cu[k] = cdeg[keep[k] ? u[k] : 0];
-      cv[k] = cdeg[keep[k] ? v[k] : 0];
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (keep[k] && pr_passes(c[k], lam[k], cu[k], cv[k])) {
-        ++local;
-        pr_flag(ucount, g[k], last);
-        if (ld_relaxed(parent + u[k]) != ld_relaxed(parent + v[k])) uf_union(parent, u[k], v[k]);
+      for (int k = 0; k < 8; ++k) {
+        const int64_t e = e0 + k * 64 + lane;
+        c[k] = w[e < nnz ? e : e0];
       }
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        keep[k] = e0 + k * 64 + lane < nnz && !pr_hopeless(c[k], floor);
+        any = any || keep[k];
+      }
+      if (ballot(any) == 0) continue;  // wave-uniform: nothing left to test
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = col[keep[k] ? e0 + k * 64 + lane : e0];
+      chunk_rows(rp, n, e0, chunk_first(first, ch, n), pos, u);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        keep[k] = keep[k] && u[k] < v[k];
+        g[k] = gid[keep[k] ? u[k] : 0];
+      }
+      int64_t lam[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool act = active[g[k]] != 0;
+        lam[k] = lhat[g[k]];
+        keep[k] = keep[k] && act && !pr_hopeless(c[k], lam[k]);
+      }
+      int64_t cu[8], cv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        cu[k] = cdeg[keep[k] ? u[k] : 0];
+        cv[k] = cdeg[keep[k] ? v[k] : 0];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (keep[k] && pr_passes(c[k], lam[k], cu[k], cv[k])) {
+          ++local;
+          pr_flag(ucount, g[k], last);
+          if (ld_relaxed(parent + u[k]) != ld_relaxed(parent + v[k])) uf_union(parent, u[k], v[k]);
+        }
+    }
   }
   // one add per wave: per-thread adds on the one counter serialise
   local = wave_sum_i64(local);

@@ -23,20 +23,30 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-__device__ __forceinline__ void chunk_rows(const int64_t* __restrict__ rp, int32_t n, int64_t e0, int32_t r0,
-                                           int32_t* pos, int32_t (&row)[8]) {
+// The start of row r0 + 1 + lane (row_ptr[n] = nnz past the last row): the
+// first 64 row starts a chunk reads, which a caller may load a chunk ahead.
+__device__ __forceinline__ int64_t chunk_start0(const int64_t* __restrict__ rp, int32_t n, int32_t r0) {
+  const int64_t r = (int64_t)r0 + 1 + lane_id();
+  return rp[r < n ? r : n];
+}
+
+// chunk_rows with st0 = chunk_start0(rp, n, r0) already loaded.
+__device__ __forceinline__ void chunk_rows_from(const int64_t* __restrict__ rp, int32_t n, int64_t e0, int32_t r0,
+                                                int64_t st0, int32_t* pos, int32_t (&row)[8]) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < 8; ++k) pos[lane * 8 + k] = -1;
   wave_lds_sync();
   if (lane == 0) pos[0] = r0;
   const int64_t end = e0 + WCH;
+  int64_t st = st0;
   for (int64_t base = (int64_t)r0 + 1;; base += 64) {
     const int64_t r = base + lane;
-    const int64_t st = rp[r < n ? r : n];  // row_ptr[n] = nnz
-    const bool in = r <= n && st < end;   // starts are > e0: row r0 holds e0
+    const bool in = r <= n && st < end;  // starts are > e0: row r0 holds e0
     if (in) atomicMax(&pos[st - e0], (int32_t)r);
     if (!((ballot(in) >> 63) & 1)) break;  // starts ascend: lane 63 in means more may follow
+    const int64_t r2 = r + 64;
+    st = rp[r2 < n ? r2 : n];
   }
   wave_lds_sync();
   int32_t v[8];
@@ -58,6 +68,11 @@ __device__ __forceinline__ void chunk_rows(const int64_t* __restrict__ rp, int32
 #pragma unroll
   for (int k = 0; k < 8; ++k) row[k] = pos[k * 64 + lane];
   wave_lds_sync();  // pos is reused by the wave's next chunk
+}
+
+__device__ __forceinline__ void chunk_rows(const int64_t* __restrict__ rp, int32_t n, int64_t e0, int32_t r0,
+                                           int32_t* pos, int32_t (&row)[8]) {
+  chunk_rows_from(rp, n, e0, r0, chunk_start0(rp, n, r0), pos, row);
 }
 
 // first[c] = the row holding entry c * WCH (one writer per chunk: the

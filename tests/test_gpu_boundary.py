@@ -133,3 +133,49 @@ def test_symmetry_check():
     with pytest.raises(mc.MincutError) as e:
         mc.mincut_batched(prp, pcol, pw, vo, validate=1)
     assert e.value.code == mc.MC_EINVAL
+
+
+def test_unaligned_entry_arrays():
+    """Entry arrays that are not 16-byte aligned (views one to three entries
+    into larger buffers, as a caller may pass): the same lambda as the
+    oracle, single and packed, sides that realise it, and a column out of
+    range is still refused."""
+    import torch
+    import paper_1808_05458_amd as mc
+    g = gg.chung_lu(43, 20000, 2.5, 12.0, 1, 9, kcore=2, lcc=True)
+    assert g.nnz % 512 != 0  # a ragged last chunk
+    ref = oracle.noi(g, 1)[0]
+    rp, col, w = mc.to_device(g, "cuda")
+
+    def shifted(t, off, fill):
+        buf = torch.full((t.numel() + off,), fill, dtype=t.dtype, device=t.device)
+        buf[off:] = t
+        return buf, buf[off:]
+
+    for off_c, off_w in ((1, 1), (2, 3), (0, 1), (3, 0)):
+        cb, c_v = shifted(col, off_c, 0)
+        wb, w_v = shifted(w, off_w, 1)
+        assert (c_v.data_ptr() | w_v.data_ptr()) % 16 != 0
+        announce("unaligned entry arrays", off_c, off_w)
+        lam, side, _ = mc.mincut(rp, c_v, w_v)
+        assert lam == ref
+        check_side(g, lam, side.cpu().numpy())
+    # packed: two graphs, both arrays one entry off
+    h = gg.cycle(9, 3)
+    packed, vo, eo = gg.pack([g, h])
+    prp, pcol, pw = mc.to_device(packed, "cuda")
+    _, pc_v = shifted(pcol, 1, 0)
+    _, pw_v = shifted(pw, 1, 1)
+    announce("unaligned entry arrays, packed")
+    lams, sides, _ = mc.mincut_batched(prp, pc_v, pw_v, vo)
+    assert list(lams) == [ref, oracle.bruteforce(h)[0]]
+    s = sides.cpu().numpy()
+    check_side(g, int(lams[0]), s[vo[0]:vo[1]])
+    # a column out of range in an unaligned array
+    cb, c_v = shifted(col, 1, 0)
+    cb[1 + 777] = g.n + 5
+    _, w_v = shifted(w, 1, 1)
+    announce("unaligned entry arrays, bad column")
+    with pytest.raises(mc.MincutError) as e:
+        mc.mincut(rp, c_v, w_v)
+    assert e.value.code == mc.MC_EINVAL
