@@ -209,7 +209,18 @@ typedef struct mc_options {
                               CSR gives each skipped row's crossing
                               entries as mirrors); 1: always row-wise;
                               -1: never.  Changes no result. */
-  int32_t reserved[1];
+  int32_t sweep_seg;       /* push batches of the full-graph sweep: 0
+                              (default) relaxes a batch of few long rows
+                              range by range (each workgroup owns a range
+                              of vertices, whose keys it adds in LDS) when
+                              the batch rows' segments average at least 4
+                              entries; 1: range by range always; -1: never
+                              (all adds in global memory).  Range by range
+                              needs the batch rows' neighbours in ascending
+                              order: a row found out of order sends that
+                              batch, and the rest of the sweep, to the
+                              global form.  Changes which pairs a round
+                              unites, never lambda. */
 } mc_options;
 
 typedef struct mc_stats {

@@ -64,10 +64,10 @@ class Options(ctypes.Structure):
                 ("sweep_tail", ctypes.c_int32), ("sweep_pull", ctypes.c_int32),
                 ("pq_order", ctypes.c_int32), ("scan_visits", ctypes.c_int32),
                 ("use_tuned", ctypes.c_int32), ("emit_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("sweep_seg", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class TuneResult(ctypes.Structure):

@@ -476,6 +476,13 @@ struct Problem {
 
 static int bitlen(uint64_t x) { return x == 0 ? 0 : 64 - __builtin_clzll(x); }
 
+// Range size (2^shift vertices) of the range-owned push relax: about
+// 640 ranges, each within the LDS array of one workgroup.
+static int seg_shift(int32_t ng) {
+  const int64_t want = std::max<int64_t>(1, ((int64_t)ng + 639) / 640);
+  return std::min(SEG_MAX_SHIFT, std::max(6, bitlen((uint64_t)want - 1)));
+}
+
 // The LDS sweep at a launch shape: threads per workgroup (128, 256, 512)
 // and workgroups per compute unit (at most what the CU's 160 KiB of LDS
 // holds).  The workgroups take graphs from a shared counter, so any shape
@@ -775,13 +782,46 @@ struct Solver {
               // the graph's visit states, two bits per vertex
               hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
             }
-            {
+            // range by range (segments of at least four entries on average,
+            // and no batch row of this sweep found out of order so far): the
+            // segment table in ws.vals_alt
+            const int shift = seg_shift(A.ng);
+            const int64_t nr = ((int64_t)A.ng + (1 << shift) - 1) >> shift;
+            const int64_t cells = bsz * (nr + 1);
+            const bool seg = opt.sweep_seg >= 0 && ws.sweep_host->seg_unsorted == 0 && cells <= ws.capE &&
+                             (opt.sweep_seg > 0 || cells * 4 <= deg_sum);
+            if (seg) {
+              {
+                // every batch entry's column (and its predecessor's, cached)
+                // read, every cell of the table written once
+                TimedScope t("k_sweep_seg_bounds", (double)deg_sum * 4 + (double)cells * 4 + (double)bsz * 16);
+                static const int bounds_grid = resident_grid((const void*)&k_sweep_seg_bounds, TB, num_cu);
+                hipLaunchKernelGGL(k_sweep_seg_bounds, dim3(bounds_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
+                                   tile_row, shift, (int32_t)nr, ws.vals_alt);
+              }
+              {
+                // every batch entry once (col, w), two cells per row and
+                // range, and per vertex its word read and r written
+                TimedScope t("k_sweep_seg_relax", (double)deg_sum * 8 + (double)cells * 8 + (double)A.ng * 12);
+                hipLaunchKernelGGL(k_sweep_seg_relax, dim3((uint32_t)nr), dim3(SEG_THREADS), 0, s, A, bh,
+                                   (int32_t)bsz, (const int64_t*)off, shift, (int32_t)nr,
+                                   (const int32_t*)ws.vals_alt, (const uint32_t*)ws.st2);
+              }
+              {
+                // the global form, which returns at once unless the bounds
+                // found a row out of order
+                TimedScope t("k_sweep_seg_fallback", 0.0);
+                static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
+                hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
+                                   tile_row, ws.st2, 1);
+              }
+            } else {
               // every row of the batch once (col, w: 8 B per entry) and per
               // batch vertex its row bounds
               TimedScope t("k_sweep_big_relax", (double)deg_sum * 8 + (double)bsz * 8);
               static const int relax_grid = resident_grid((const void*)&k_sweep_big_relax, TB, num_cu);
               hipLaunchKernelGGL(k_sweep_big_relax, dim3(relax_grid), dim3(TB), 0, s, A, bh, (int32_t)bsz, off,
-                                 tile_row, ws.st2);
+                                 tile_row, ws.st2, 0);
             }
           } else {
             // the free vertices (a list in ws.lab, positions in ws.newid:

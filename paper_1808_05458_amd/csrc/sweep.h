@@ -60,6 +60,9 @@ struct SweepCtl {
   int64_t seq_rows;            // ... and the sequential kernel
   int64_t rows_done;           // entries in the rows of every visited vertex
   int64_t pull_alpha;          // pull form of a grid-wide batch: c(S + B), summed
+  int32_t seg_unsorted;        // a batch row met by the range-owned form lists
+                               // its neighbours out of ascending order
+  int32_t pad_;
   uint64_t bitmap[SWEEP_BUCKETS / 64];
   int32_t head[SWEEP_BUCKETS];     // recent pushes (lists through the pool)
   int32_t seg_cur[SWEEP_BUCKETS];  // rebuilt segments of seg[]: unread part
@@ -336,6 +339,7 @@ __global__ void k_sweep_init(const SweepArgs* args) {
     c->tail_total = c->tail_cursor = c->tail_pops = c->free_count = 0;
     c->tail_best = ~0ull;
     c->tail_rows = c->seq_rows = c->rows_done = c->pull_alpha = 0;
+    c->seg_unsorted = 0;
   }
 }
 
@@ -1034,8 +1038,11 @@ __global__ void k_sweep_big_tiles(const int64_t* off, int32_t bsz, int32_t* tile
 }
 
 // off: bsz + 1 prefix sums of the batch's row lengths (off[bsz] = entries).
+// fallback = 1: the launch after a range-owned attempt, which runs only if
+// that attempt found a batch row out of order (and so did nothing).
 __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h, int32_t bsz, const int64_t* off,
-                                                         const int32_t* tile_row, uint32_t* st2) {
+                                                         const int32_t* tile_row, uint32_t* st2, int32_t fallback) {
+  if (fallback && ld_relaxed(&A.ctl->seg_unsorted) == 0) return;
   __shared__ int32_t buf[4][2 * BIG_BUF];
   __shared__ int32_t cnt[4];
   __shared__ int32_t s_x[BIG_TILE];
@@ -1189,6 +1196,278 @@ __global__ void __launch_bounds__(256) k_sweep_big_relax(SweepArgs A, int32_t h,
     const int64_t rs = part[1][0] + part[1][1] + part[1][2] + part[1][3];
     if (tot) atomicAdd((unsigned long long*)&c->batch_internal, (unsigned long long)tot);
     if (rs) atomicAdd((unsigned long long*)&c->batch_sum, (unsigned long long)(-2 * rs));
+  }
+}
+
+// ---- range-owned form of a push batch
+// When the batch's rows are few and long (the hubs of a skewed graph) and
+// list their neighbours in ascending order, the graph's vertices are cut
+// into ranges of 2^shift, one workgroup per range.  A batch row's
+// entries into one range are then one contiguous segment, found once for
+// all rows and ranges (k_sweep_seg_bounds), and the range's workgroup adds
+// the segments into its range's r held in LDS: no add goes to global memory.
+// The adds into one vertex take the order of the workgroup's LDS atomics, a
+// legal order of the batch (its members tie at the cap), so the crossing a
+// vertex reports is a contractible pair, as in the global form.
+constexpr int SEG_MAX_SHIFT = 12;  // ranges of at most 4096 vertices in LDS
+constexpr int SEG_THREADS = 512;
+constexpr int SEG_UNROLL = 2;
+
+// bnd[i * (nr + 1) + q] for batch row i and range q in [0, nr]: the offset in
+// row i of its first entry whose neighbour lies in range q or above (rows in
+// ascending neighbour order), the row's length at q = nr.  One pass over the
+// batch's entries in tiles of SEG_BTILE (BIG_TILE multiples, so the global
+// relax's tile rows serve): an entry writes the cells of the ranges from the
+// one after its predecessor's up to its own, the row's last entry also those
+// after its own.  (Rows without entries write none; the relax reads their
+// length from off.)  A row out of order (an entry below its predecessor)
+// sets ctl->seg_unsorted: the range-owned relax then does nothing and the
+// global form, launched after it, relaxes the batch instead.
+constexpr int SEG_BUNROLL = 4;
+constexpr int SEG_BTILE = 256 * SEG_BUNROLL;
+static_assert(SEG_BTILE % BIG_TILE == 0, "bounds tiles are whole relax tiles");
+__global__ void __launch_bounds__(256) k_sweep_seg_bounds(SweepArgs A, int32_t h, int32_t bsz, const int64_t* off,
+                                                          const int32_t* tile_row, int32_t shift, int32_t nr,
+                                                          int32_t* bnd) {
+  constexpr int TSTEP = SEG_BTILE / BIG_TILE;
+  __shared__ int64_t s_off[SEG_BTILE + 1], s_base[SEG_BTILE];
+  const int64_t total = off[bsz];
+  const int64_t ntiles = (total + SEG_BTILE - 1) / SEG_BTILE;
+  const int64_t nbig = (total + BIG_TILE - 1) / BIG_TILE;  // tiles of tile_row
+  const int64_t e_idle = A.rp[A.v0];
+  for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
+    const int64_t t0 = j * SEG_BTILE, t1 = min(t0 + SEG_BTILE, total);
+    const int32_t r0 = tile_row[j * TSTEP], r1 = (j + 1) * TSTEP < nbig ? tile_row[(j + 1) * TSTEP] : bsz - 1;
+    for (int32_t rb = r0; rb <= r1; rb += SEG_BTILE) {
+      const int32_t nrow = min(SEG_BTILE, r1 + 1 - rb);
+      for (int32_t k = threadIdx.x; k < nrow; k += 256) {
+        s_base[k] = A.rp[A.capq[h + rb + k]];
+        s_off[k] = off[rb + k];
+      }
+      if (threadIdx.x == 0) s_off[nrow] = off[rb + nrow];
+      __syncthreads();
+      const int64_t lo_e = max(s_off[0], t0), hi_e = min(s_off[nrow], t1);
+      const int64_t i0 = lo_e + (int64_t)threadIdx.x * SEG_BUNROLL;
+      int32_t row = 0;
+      if (i0 < hi_e) {
+        int32_t lo = 0, hi = nrow - 1;  // last row with s_off[row] <= i0
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= i0) lo = mid;
+          else hi = mid - 1;
+        }
+        row = lo;
+      }
+      int64_t es[SEG_BUNROLL];
+      int32_t ps[SEG_BUNROLL], ls[SEG_BUNROLL], ri[SEG_BUNROLL];
+#pragma unroll
+      for (int u = 0; u < SEG_BUNROLL; ++u) {
+        const int64_t i = i0 + u;
+        es[u] = e_idle;
+        ps[u] = -1;
+        ls[u] = 0;
+        ri[u] = 0;
+        if (i < hi_e) {
+          while (s_off[row + 1] <= i) ++row;  // LDS only
+          ps[u] = (int32_t)(i - s_off[row]);
+          ls[u] = (int32_t)(s_off[row + 1] - s_off[row]);
+          es[u] = s_base[row] + ps[u];
+          ri[u] = rb + row;
+        }
+      }
+      int32_t ys[SEG_BUNROLL], yp[SEG_BUNROLL];
+#pragma unroll
+      for (int u = 0; u < SEG_BUNROLL; ++u) {
+        ys[u] = A.col[es[u]];
+        yp[u] = A.col[ps[u] > 0 ? es[u] - 1 : es[u]];
+      }
+      bool unsorted = false;
+#pragma unroll
+      for (int u = 0; u < SEG_BUNROLL; ++u) unsorted = unsorted || (ps[u] > 0 && yp[u] > ys[u]);
+      if (ballot(unsorted) != 0 && lane_id() == 0) st_relaxed(&A.ctl->seg_unsorted, 1);
+#pragma unroll
+      for (int u = 0; u < SEG_BUNROLL; ++u) {
+        if (ps[u] < 0) continue;
+        const int32_t q = (ys[u] - A.v0) >> shift;
+        const int32_t qp = ps[u] > 0 ? ((yp[u] - A.v0) >> shift) : -1;
+        int32_t* b = bnd + (int64_t)ri[u] * (nr + 1);
+        for (int32_t t = qp + 1; t <= q; ++t) b[t] = ps[u];
+        if (ps[u] == ls[u] - 1)
+          for (int32_t t = q + 1; t <= nr; ++t) b[t] = ls[u];
+      }
+      __syncthreads();  // the slice arrays are reused
+    }
+  }
+}
+
+// Range q = blockIdx.x of the graph's local ids [q 2^shift, (q + 1) 2^shift):
+// its r and visit states staged in LDS, then for every batch row its segment
+// into the range (chunks of SEG_THREADS rows, their entries spread evenly over
+// the threads), the adds made in LDS, and the free vertices' r written back.
+// The batch's internal weight and weight to the visited set are summed as in
+// the global form.
+__global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, int32_t h, int32_t bsz,
+                                                                 const int64_t* off, int32_t shift, int32_t nr,
+                                                                 const int32_t* bnd, const uint32_t* st2) {
+  constexpr int NW = SEG_THREADS / 64;
+  if (ld_relaxed(&A.ctl->seg_unsorted) != 0) return;  // the global form relaxes the batch
+  __shared__ int32_t r_loc[1 << SEG_MAX_SHIFT];
+  __shared__ uint32_t s_st[(1 << SEG_MAX_SHIFT) / 16];
+  __shared__ int32_t s_x[SEG_THREADS];
+  __shared__ int64_t s_base[SEG_THREADS];
+  __shared__ int64_t s_off[SEG_THREADS + 1];
+  __shared__ int64_t wtot[NW];
+  __shared__ int32_t buf[NW][2 * BIG_BUF];
+  __shared__ int32_t cnt[NW];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int32_t q = blockIdx.x;
+  const int32_t lo_v = q << shift;  // a multiple of 64
+  const int32_t nv = min(1 << shift, A.ng - lo_v);
+  for (int32_t i = tid; i < nv; i += SEG_THREADS) r_loc[i] = rs_r(A.rs[A.v0 + lo_v + i]);
+  for (int32_t i = tid; i < (nv + 15) / 16; i += SEG_THREADS) s_st[i] = st2[(lo_v >> 4) + i];
+  if (lane == 0) cnt[wave] = 0;
+  int32_t* wbuf = buf[wave];
+  int32_t* wcnt = &cnt[wave];
+  __syncthreads();
+  const int64_t e_idle = A.rp[A.v0];
+  int64_t internal = 0, rsum = 0;
+  for (int32_t c0 = 0; c0 < bsz; c0 += SEG_THREADS) {
+    const int32_t cn = min(SEG_THREADS, bsz - c0);
+    int64_t len = 0;
+    if (tid < cn) {
+      const int32_t i = c0 + tid;
+      const int32_t x = A.capq[h + i];
+      // a segment is clamped into its row (a row out of order could leave
+      // cells unwritten; reads stay inside the row)
+      const int32_t rl = (int32_t)(off[i + 1] - off[i]);
+      const int32_t* bi = bnd + (int64_t)i * (nr + 1);
+      int32_t a = 0, b = 0;
+      if (rl > 0) {
+        a = min(max(bi[q], 0), rl);
+        b = min(max(bi[q + 1], a), rl);
+      }
+      len = b - a;
+      s_x[tid] = x;
+      s_base[tid] = A.rp[x] + a;
+    }
+    int64_t incl = len;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    int64_t before = 0;
+    for (int k = 0; k < wave; ++k) before += wtot[k];
+    if (tid < cn) s_off[tid] = before + incl - len;
+    if (tid == cn - 1) s_off[cn] = before + incl;
+    __syncthreads();
+    const int64_t total = s_off[cn];
+    // every thread takes every pass (the crossings' buffer is kept per wave,
+    // with all lanes present); a slot past the end is idle
+    for (int64_t pass = 0; pass < total; pass += SEG_THREADS * SEG_UNROLL) {
+      const int64_t i0 = pass + tid * SEG_UNROLL;
+      int32_t row = 0;
+      if (i0 < total) {
+        int32_t lo = 0, hi = cn - 1;  // last row with s_off[row] <= i0
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= i0) lo = mid;
+          else hi = mid - 1;
+        }
+        row = lo;
+      }
+      int64_t es[SEG_UNROLL];
+      int32_t xs[SEG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SEG_UNROLL; ++u) {
+        const int64_t i = i0 + u;
+        es[u] = e_idle;
+        xs[u] = -1;
+        if (i < total) {
+          while (s_off[row + 1] <= i) ++row;  // LDS only
+          es[u] = s_base[row] + (i - s_off[row]);
+          xs[u] = s_x[row];
+        }
+      }
+      int32_t ys[SEG_UNROLL], cs[SEG_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SEG_UNROLL; ++u) {
+        ys[u] = A.col[es[u]];
+        cs[u] = A.w[es[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < SEG_UNROLL; ++u) {
+        const int32_t yl = ys[u] - A.v0 - lo_v;
+        // (a neighbour outside the range would mean a row out of order:
+        // never added, and never an LDS access out of bounds)
+        const bool act = xs[u] >= 0 && ys[u] != xs[u] && (uint32_t)yl < (uint32_t)nv;
+        bool cross = false;
+        if (act) {
+          const uint32_t st = (s_st[yl >> 4] >> (2 * (yl & 15))) & 3u;
+          if (st == BS_BATCH) internal += cs[u];
+          else if (st == BS_VISITED) rsum += cs[u];
+          else {
+            const int32_t old = atomicAdd(&r_loc[yl], cs[u]);
+            cross = (int64_t)old < A.lam && A.lam <= (int64_t)old + cs[u];
+          }
+        }
+        const uint64_t cm = ballot(cross);
+        if (cm) {
+          const int32_t at = *wcnt;
+          if (cross) {
+            const int32_t k = at + popc64(cm & lanemask_lt());
+            wbuf[2 * k] = ys[u];
+            wbuf[2 * k + 1] = xs[u];
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) *wcnt = at + popc64(cm);
+          __builtin_amdgcn_wave_barrier();
+          if (*wcnt > BIG_BUF - 64) flush_wave_buf(A, wbuf, wcnt);
+        }
+      }
+    }
+    __syncthreads();  // the row arrays are reused
+  }
+  // the free vertices' new r (the low half of the packed word)
+  for (int32_t i = tid; i < nv; i += SEG_THREADS) {
+    const uint32_t st = (s_st[i >> 4] >> (2 * (i & 15))) & 3u;
+    if (st == BS_FREE) reinterpret_cast<int32_t*>(A.rs + A.v0 + lo_v + i)[0] = r_loc[i];
+  }
+  // the waves' last crossings: one FIFO reservation for the workgroup
+  __shared__ int32_t blk_base;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t tot = 0;
+    for (int k = 0; k < NW; ++k) tot += cnt[k];
+    blk_base = tot ? atomicAdd(&A.ctl->cap_tail, tot) : 0;
+  }
+  __syncthreads();
+  {
+    int32_t o = blk_base;
+    for (int k = 0; k < wave; ++k) o += cnt[k];
+    for (int32_t i = lane; i < *wcnt; i += 64) {
+      A.capq[o + i] = wbuf[2 * i];
+      A.capx[o + i] = wbuf[2 * i + 1];
+    }
+  }
+  __shared__ int64_t part[2][NW];
+  internal = wave_sum_i64(internal);
+  rsum = wave_sum_i64(rsum);
+  if (lane == 0) {
+    part[0][wave] = internal;
+    part[1][wave] = rsum;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t tot = 0, rs = 0;
+    for (int k = 0; k < NW; ++k) {
+      tot += part[0][k];
+      rs += part[1][k];
+    }
+    if (tot) atomicAdd((unsigned long long*)&A.ctl->batch_internal, (unsigned long long)tot);
+    if (rs) atomicAdd((unsigned long long*)&A.ctl->batch_sum, (unsigned long long)(-2 * rs));
   }
 }
 

@@ -152,7 +152,10 @@ def test_medium_graphs_against_noi():
                                   dict(whole_max=16, scan_mode=1, scan_visits=3, use_pr=0),
                                   dict(scan_mode=2, pq_order=1),
                                   dict(emit_rows=1), dict(emit_rows=1, whole_max=16, use_pr=0),
-                                  dict(emit_rows=-1, whole_max=16)])
+                                  dict(emit_rows=-1, whole_max=16),
+                                  dict(whole_max=16, sweep_handoff=1, sweep_seg=1, sweep_pull=-1),
+                                  dict(whole_max=16, sweep_handoff=1, sweep_seg=1, sweep_pull=-1, use_pr=0),
+                                  dict(whole_max=16, sweep_handoff=1, sweep_seg=-1, sweep_pull=-1)])
 def test_planted_4096_options(opts):
     g = gg.planted_4096()
     gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["planted_4096"]
@@ -178,7 +181,9 @@ def test_region_scans_on_power_law_core():
                  dict(whole_max=64, scan_mode=1, use_pr=0),
                  dict(whole_max=64, scan_mode=1, pq_order=1), dict(whole_max=64, scan_mode=1, pq_order=2),
                  dict(whole_max=64, scan_mode=1, pq_order=3, scan_visits=2),
-                 dict(whole_max=64, scan_mode=1, scan_visits=4, use_pr=0)]:
+                 dict(whole_max=64, scan_mode=1, scan_visits=4, use_pr=0),
+                 dict(whole_max=64, sweep_handoff=4, sweep_seg=1, sweep_pull=-1),
+                 dict(whole_max=64, sweep_seg=1, sweep_pull=-1, use_pr=0), dict(whole_max=64, sweep_seg=-1)]:
         announce("chung_lu 20000", opts)
         lam, side, st = solve(g, **opts)
         assert lam == ref, opts
@@ -308,7 +313,8 @@ def test_sweep_on_larger_power_law_graph():
     g = gg.chung_lu(29, 200000, 2.5, 16.0, 1, 1, kcore=5, lcc=True)
     ref, _, _ = oracle.noi(g, 1)
     for opts in [dict(), dict(sweep_tail=-1), dict(sweep_tail=1, use_pr=0), dict(sweep_pull=1),
-                 dict(sweep_pull=-1, sweep_tail=-1)]:
+                 dict(sweep_pull=-1, sweep_tail=-1), dict(sweep_seg=1, sweep_pull=-1),
+                 dict(sweep_seg=1, sweep_pull=-1, sweep_tail=-1, use_pr=0), dict(sweep_seg=-1)]:
         announce("chung_lu 200000 5-core", g.n, g.m, ref, opts)
         lam, side, st = solve(g, **opts)
         assert lam == ref, opts
@@ -435,7 +441,9 @@ _BLOCK_VARIANTS = [dict(), dict(use_pr=0), dict(whole_max=4, scan_mode=1), dict(
                    dict(pq_order=1, use_pr=0), dict(pq_order=2, use_pr=0), dict(pq_order=3),
                    dict(whole_max=4, scan_mode=1, pq_order=2, scan_visits=3, use_pr=0),
                    dict(whole_max=4, scan_mode=1, scan_visits=2),
-                   dict(scan_mode=2, pq_order=1, use_pr=0)]
+                   dict(scan_mode=2, pq_order=1, use_pr=0),
+                   dict(whole_max=4, sweep_handoff=1, sweep_seg=1, sweep_pull=-1, use_pr=0),
+                   dict(whole_max=4, sweep_handoff=1, sweep_seg=1, sweep_pull=-1, sweep_tail=1)]
 
 
 @pytest.mark.parametrize("opts", _BLOCK_VARIANTS, ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()) or "default")
@@ -475,3 +483,37 @@ def test_round_blocks_keep_every_minimum_cut(opts):
             if opts.get("use_pr", 1) == 0:
                 assert c.min() >= used[i], (i, margin, opts, int(c.min()), int(used[i]))
     assert checked >= 100, checked
+
+
+def _shuffle_rows(g, seed):
+    """The same graph with every row's entries in a random order."""
+    rng = np.random.default_rng(seed)
+    col, w = g.col.copy(), g.w.copy()
+    for v in range(g.n):
+        a, b = int(g.row_ptr[v]), int(g.row_ptr[v + 1])
+        p = a + rng.permutation(b - a)
+        col[a:b], w[a:b] = g.col[p], g.w[p]
+    return gg.Graph(g.n, g.row_ptr.copy(), col, w, g.name + "_shuffled")
+
+
+def test_range_owned_push_and_row_order():
+    """The range-owned push relax (sweep_seg=1: every grid-wide push batch
+    relaxed range by range in LDS) on a hub-heavy R-MAT core and a power-law
+    core whose rows are in ascending order, and the same options on the same
+    graphs with every row shuffled (the segment pass finds a batch row out of
+    order, and that batch and the rest of the sweep go to the global form):
+    the oracle's lambda and a side that realises it every time."""
+    graphs = [gg.rmat(5, 15, 1 << 19, 0.57, 0.19, 0.19, kcore=6, lcc=True, name="rmat15"),
+              gg.chung_lu(31, 60000, 2.3, 14.0, 1, 4, kcore=4, lcc=True)]
+    for g in graphs:
+        assert all(np.all(np.diff(g.col[g.row_ptr[v]:g.row_ptr[v + 1]]) >= 0) for v in range(0, g.n, 97))
+        ref, _, _ = oracle.noi(g, 1)
+        h = _shuffle_rows(g, 3)
+        for opts in [dict(sweep_handoff=1, sweep_seg=1, sweep_pull=-1),
+                     dict(sweep_handoff=1, sweep_seg=1, sweep_pull=-1, use_pr=0),
+                     dict(sweep_handoff=8, sweep_seg=1, sweep_pull=-1, sweep_tail=-1), dict()]:
+            for graph in (g, h):
+                announce("range-owned push", graph.name, graph.n, graph.m, ref, opts)
+                lam, side, st = solve(graph, **opts)
+                assert lam == ref, (graph.name, opts)
+                check_side(graph, lam, side)

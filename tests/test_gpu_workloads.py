@@ -79,9 +79,9 @@ def bridged():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("opts", [dict(), dict(sweep_tail=-1, sweep_pull=-1, emit_rows=-1),
-                                  dict(sweep_pull=1, emit_rows=1)],
-                         ids=["default", "sequential_tail_push_entry_emit", "pull_row_emit"])
+@pytest.mark.parametrize("opts", [dict(), dict(sweep_tail=-1, sweep_pull=-1, emit_rows=-1, sweep_seg=-1),
+                                  dict(sweep_pull=1, emit_rows=1), dict(sweep_pull=-1, sweep_seg=1)],
+                         ids=["default", "sequential_tail_push_entry_emit", "pull_row_emit", "range_owned_push"])
 def test_bridged_8cores_lambda_below_min_degree(bridged, opts):
     # two Chung-Lu 8-cores (about 2M vertices each) joined by 3 bridges: the
     # minimum cut (3) lies below the minimum degree (8), so the full-graph
