@@ -718,6 +718,13 @@ struct Solver {
           TimedScope t("k_sweep_seq", 0.0);
           hipLaunchKernelGGL(k_sweep_seq, dim3(nrun), dim3(SWEEP_THREADS), 0, s, ws.sw_args, ws.sw_run);
         }
+        {
+          // per batch vertex its FIFO slot, degree, r word and stamp (the
+          // bytes are added once the batches' sizes are read back)
+          TimedScope t("k_sweep_big_mark", 0.0);
+          hipLaunchKernelGGL(k_sweep_big_mark, dim3(std::max(1, num_cu * 16 / nrun), nrun), dim3(TB), 0, s,
+                             ws.sw_args, ws.sw_run);
+        }
         hipLaunchKernelGGL(k_sweep_status, dim3(grid_for(nrun, TB, num_cu)), dim3(TB), 0, s, ws.sw_args,
                            ws.sw_run, nrun, ws.sw_status);
         MC_HIP(hipMemcpyAsync(ws.sw_status_host, ws.sw_status, sizeof(SweepStatus) * nrun, hipMemcpyDeviceToHost,
@@ -748,19 +755,12 @@ struct Solver {
           }
           const int32_t bh = c.cap_head, bt = c.cap_tail;
           const int64_t bsz = bt - bh;
-          {
-            // per batch vertex its FIFO slot, degree, r word and stamp
-            TimedScope t("k_sweep_big_mark", (double)bsz * 32);
-            hipLaunchKernelGGL(k_sweep_big_mark, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, A, bh, bt);
-          }
+          timer().add_bytes("k_sweep_big_mark", (double)bsz * 32);
           big_vtx += (double)bsz;
-          // push or pull: the batch's rows against the rows of the vertices
-          // still free (neither visited nor in the batch), whose count takes
-          // one pass over the graph's vertices
-          MC_HIP(hipMemcpyAsync(ws.sweep_host, A.ctl, offsetof(SweepCtl, bitmap), hipMemcpyDeviceToHost, s));
-          MC_HIP(hipStreamSynchronize(s));
-          const int64_t deg_sum = ws.sweep_host->batch_deg;
-          const int64_t free_rows = (A.pool_cap - 1) - ws.sweep_host->rows_done - deg_sum;
+          // push or pull: the batch's rows (summed by the mark) against the
+          // rows of the vertices still free (neither visited nor in the batch)
+          const int64_t deg_sum = c.batch_deg;
+          const int64_t free_rows = (A.pool_cap - 1) - c.rows_done - deg_sum;
           const bool pull = opt.sweep_pull >= 0 && (opt.sweep_pull > 0 || deg_sum > free_rows + A.ng / 8);
           big_deg += (double)deg_sum;
           if (debug_on())
@@ -788,7 +788,7 @@ struct Solver {
             const int shift = seg_shift(A.ng);
             const int64_t nr = ((int64_t)A.ng + (1 << shift) - 1) >> shift;
             const int64_t cells = bsz * (nr + 1);
-            const bool seg = opt.sweep_seg >= 0 && ws.sweep_host->seg_unsorted == 0 && cells <= ws.capE &&
+            const bool seg = opt.sweep_seg >= 0 && c.seg_unsorted == 0 && cells <= ws.capE &&
                              (opt.sweep_seg > 0 || cells * 4 <= deg_sum);
             if (seg) {
               {

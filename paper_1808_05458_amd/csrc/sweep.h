@@ -916,22 +916,34 @@ __global__ void k_sweep_unite(const SweepArgs* args) {
 
 // Per graph: status, FIFO bounds and row entries of the pending batch, for
 // the host (one small copy instead of one per graph).
+// What the host reads of each running graph after a sequential launch (and
+// the mark of a grid-wide batch it handed back): one copy for all of them.
 struct SweepStatus {
   int32_t status, cap_head, cap_tail, visited;
+  int64_t batch_deg, rows_done;
+  int32_t seg_unsorted, pad_;
 };
 __global__ void k_sweep_status(const SweepArgs* args, const int32_t* run, int32_t k, SweepStatus* out) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
     const MC_GLOBAL SweepCtl* c = (const MC_GLOBAL SweepCtl*)args[run[i]].ctl;
-    out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, c->visited};
+    out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, c->visited, c->batch_deg, c->rows_done,
+                         c->seg_unsorted, 0};
   }
 }
 
-// Grid-wide batch [h, t): mark every vertex visited.
-__global__ void k_sweep_big_mark(SweepArgs A, int32_t h, int32_t t) {
-  SweepCtl* c = A.ctl;
+// Grid-wide batch [cap_head, cap_tail) of graph run[blockIdx.y], if its
+// sequential kernel handed one back: mark every vertex visited, and sum the
+// rows' lengths (the host's push or pull choice) and degrees.  Launched
+// before the status is read, so one readback serves both.
+__global__ void k_sweep_big_mark(const SweepArgs* args, const int32_t* run) {
+  const SweepDev A = dev_view(args[run[blockIdx.y]]);
+  MC_GLOBAL SweepCtl* c = A.ctl;
+  if (c->status != SW_BIG) return;  // uniform: the graph is done, or its tail follows
+  const int32_t h = c->cap_head, t = c->cap_tail;
   const int32_t stamp = c->step + 1;
   int64_t sum = 0, deg = 0;
-  for (int64_t i = h + gtid(); i - lane_id() < t; i += gstride()) {  // wave-uniform bound
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = h + tid; i - lane_id() < t; i += nth) {  // wave-uniform bound
     // loads outside the branch (one round trip for all of them); a lane past
     // the end reads the batch's first vertex
     const bool in = i < t;
