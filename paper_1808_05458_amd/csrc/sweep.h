@@ -62,7 +62,8 @@ struct SweepCtl {
   int64_t pull_alpha;          // pull form of a grid-wide batch: c(S + B), summed
   int32_t seg_unsorted;        // a batch row met by the range-owned form lists
                                // its neighbours out of ascending order
-  int32_t pad_;
+  int32_t count_err;           // a pull batch's free vertices differed from
+                               // the count the host derived (never expected)
   uint64_t bitmap[SWEEP_BUCKETS / 64];
   int32_t head[SWEEP_BUCKETS];     // recent pushes (lists through the pool)
   int32_t seg_cur[SWEEP_BUCKETS];  // rebuilt segments of seg[]: unread part
@@ -340,6 +341,7 @@ __global__ void k_sweep_init(const SweepArgs* args) {
     c->tail_best = ~0ull;
     c->tail_rows = c->seq_rows = c->rows_done = c->pull_alpha = 0;
     c->seg_unsorted = 0;
+    c->count_err = 0;
   }
 }
 
@@ -921,13 +923,13 @@ __global__ void k_sweep_unite(const SweepArgs* args) {
 struct SweepStatus {
   int32_t status, cap_head, cap_tail, visited;
   int64_t batch_deg, rows_done;
-  int32_t seg_unsorted, pad_;
+  int32_t seg_unsorted, count_err;
 };
 __global__ void k_sweep_status(const SweepArgs* args, const int32_t* run, int32_t k, SweepStatus* out) {
   for (int64_t i = gtid(); i < k; i += gstride()) {
     const MC_GLOBAL SweepCtl* c = (const MC_GLOBAL SweepCtl*)args[run[i]].ctl;
     out[i] = SweepStatus{c->status, c->cap_head, c->cap_tail, c->visited, c->batch_deg, c->rows_done,
-                         c->seg_unsorted, 0};
+                         c->seg_unsorted, c->count_err};
   }
 }
 
@@ -1553,6 +1555,18 @@ __global__ void __launch_bounds__(256) k_sweep_free_list(SweepArgs A, const uint
 
 // The free rows in tiles of BIG_TILE entries (off: prefix sums of the list's
 // row lengths; tile_row: each tile's first row, as for the push form).
+// The free list's length is taken from the counts the host already holds
+// (the graph's vertices less the visited ones and the batch), so no
+// readback waits for the scan.  Checked here against the scan's total: a
+// difference is recorded (count_err) and the list is padded with a vertex of
+// the graph up to the assumed length, so every launch sized by it reads
+// valid vertices.
+__global__ void k_sweep_free_check(SweepArgs A, int32_t assumed, int32_t* list) {
+  const int32_t got = A.ctl->free_count;
+  if (got != assumed && threadIdx.x == 0) A.ctl->count_err = 1;
+  for (int32_t i = got + (int32_t)threadIdx.x; i < assumed; i += blockDim.x) list[i] = A.v0;
+}
+
 __global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32_t* list, int32_t nl,
                                                         const int64_t* off, const int32_t* tile_row,
                                                         const uint32_t* st2) {
