@@ -825,17 +825,15 @@ struct Solver {
                                  tile_row, ws.st2, 0);
             }
           } else {
-            // the free vertices (a list in ws.lab, positions in ws.newid:
-            // both free until the compaction) and their rows' prefix sums
+            // the free vertices (a list in ws.lab, free until the
+            // compaction) and their rows' prefix sums
             int32_t* list = ws.lab;
             // the free vertices: neither visited nor in the batch
             const int32_t nfree = (int32_t)std::max<int64_t>(0, (int64_t)A.ng - c.visited - bsz);
             {
               TimedScope t("sweep_batch_prep", (double)A.ng * 16);
-              hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
-              exclusive_scan<int32_t, FreeFlag>(FreeFlag{ws.st2}, A.ng, ws.newid, &A.ctl->free_count, ws.tmp, s);
-              hipLaunchKernelGGL(k_sweep_free_list, dim3(grid_for(A.ng, TB, num_cu * 4)), dim3(TB), 0, s, A, ws.st2,
-                                 (const int32_t*)ws.newid, list);
+              hipLaunchKernelGGL(k_sweep_free_bits, dim3((A.ng + FREE_TILE - 1) / FREE_TILE), dim3(TB), 0, s, A,
+                                 ws.st2, list);
               hipLaunchKernelGGL(k_sweep_free_check, dim3(1), dim3(256), 0, s, A, nfree, list);
               exclusive_scan<int64_t, BatchDeg>(BatchDeg{list, rp}, nfree, off, off + nfree, ws.tmp, s);
               hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(std::max(nfree, 1), TB, num_cu * 16)), dim3(TB), 0,

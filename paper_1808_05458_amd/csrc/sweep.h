@@ -1509,6 +1509,7 @@ __global__ void k_sweep_big_finish(SweepArgs A, int32_t t, int32_t pull) {
   c->batch_internal = 0;
   c->batch_deg = 0;
   c->pull_alpha = 0;
+  c->free_count = 0;
   c->status = SW_RUNNING;
 }
 
@@ -1522,39 +1523,72 @@ __global__ void k_sweep_big_finish(SweepArgs A, int32_t t, int32_t pull) {
 // (united later).  alpha after the batch is c(S + B) = the sum over free
 // vertices of their new r (each the weight to S + B).
 
-// Free vertices of the graph (flag for the prefix scan).
-struct FreeFlag {
-  const uint32_t* st2;
-  __device__ __forceinline__ int32_t operator()(int64_t i) const {
-    return ((st2[i >> 4] >> (2 * (i & 15))) & 3u) == BS_FREE;
-  }
-};
-
-// list[pos[i]] = v0 + i for every free vertex; pull_alpha += their r (the
-// weight to S, exact for a vertex that never crossed the cap).
-__global__ void __launch_bounds__(256) k_sweep_free_list(SweepArgs A, const uint32_t* st2, const int32_t* pos,
-                                                         int32_t* list) {
+// Before a pull batch: the visit states (as k_sweep_bits) and the list of
+// the free vertices with the sum of their r (pull_alpha: the weight to S,
+// exact for a vertex that never crossed the cap), in one pass.  Workgroup b
+// takes vertices [b FREE_TILE, (b + 1) FREE_TILE) in groups of 64 (one
+// ballot each), reserves its list range with one add on free_count (zeroed
+// by k_sweep_init and every batch's finish) and writes its free vertices in
+// vertex order.  The list's order across workgroups is that of the
+// reservations; nothing in the pull depends on it.
+constexpr int FREE_TILE = 4096;
+__global__ void __launch_bounds__(256) k_sweep_free_bits(SweepArgs A, uint32_t* st2, int32_t* list) {
+  constexpr int NG = FREE_TILE / 64;  // groups per tile
+  __shared__ uint64_t s_free[NG];
+  __shared__ int32_t s_pos[NG + 1];
+  __shared__ int64_t s_r[4];
+  __shared__ int32_t s_base;
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int32_t stamp = A.ctl->step + 1;
+  const int64_t t0 = (int64_t)blockIdx.x * FREE_TILE;
   int64_t rsum = 0;
-  for (int64_t i = gtid(); i < A.ng; i += gstride()) {
-    const uint32_t st = (st2[i >> 4] >> (2 * (i & 15))) & 3u;
-    const uint64_t u = A.rs[A.v0 + i];
-    if (st == BS_FREE) {
-      list[pos[i]] = A.v0 + (int32_t)i;
-      rsum += rs_r(u);
+  for (int gi = wave; gi < NG; gi += 4) {
+    const int64_t base = t0 + gi * 64;
+    const int64_t i = base + lane;
+    const uint64_t u = i < A.ng ? A.rs[A.v0 + i] : 0;
+    const int32_t st = i < A.ng ? rs_stamp(u) : 0;
+    const uint64_t hi = ballot(st != 0);                 // in the batch or visited
+    const uint64_t lo = ballot(st != 0 && st != stamp);  // visited
+    const bool fr = i < A.ng && st == 0;
+    const uint64_t fm = ballot(fr);
+    if (fr) rsum += rs_r(u);
+    uint32_t word = 0;
+    const int g = lane & 3;  // lanes 0..3 each build one word of 16 vertices
+    for (int k = 0; k < 16; ++k) {
+      const int b = g * 16 + k;
+      word |= (uint32_t)((lo >> b) & 1) << (2 * k);
+      word |= (uint32_t)((hi >> b) & 1) << (2 * k + 1);
+    }
+    if (lane < 4 && base < A.ng) st2[(base >> 4) + g] = word;
+    if (lane == 0) s_free[gi] = fm;
+  }
+  rsum = wave_sum_i64(rsum);
+  if (lane == 0) s_r[wave] = rsum;
+  __syncthreads();
+  if (wave == 0) {
+    // group offsets within the tile, and the tile's range in the list
+    const int32_t c0 = lane < NG ? popc64(s_free[lane]) : 0;
+    int32_t incl = c0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (lane < NG) s_pos[lane] = incl - c0;
+    if (lane == 63) {
+      s_pos[NG] = incl;
+      s_base = incl ? atomicAdd(&A.ctl->free_count, incl) : 0;
+      const int64_t r = s_r[0] + s_r[1] + s_r[2] + s_r[3];
+      if (r) atomicAdd((unsigned long long*)&A.ctl->pull_alpha, (unsigned long long)r);
     }
   }
-  __shared__ int64_t part[4];
-  rsum = wave_sum_i64(rsum);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = rsum;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t t = part[0] + part[1] + part[2] + part[3];
-    if (t) atomicAdd((unsigned long long*)&A.ctl->pull_alpha, (unsigned long long)t);
+  for (int gi = wave; gi < NG; gi += 4) {
+    const uint64_t fm = s_free[gi];
+    if ((fm >> lane) & 1)
+      list[s_base + s_pos[gi] + popc64(fm & lanemask_lt())] = A.v0 + (int32_t)(t0 + gi * 64 + lane);
   }
 }
 
-// The free rows in tiles of BIG_TILE entries (off: prefix sums of the list's
-// row lengths; tile_row: each tile's first row, as for the push form).
 // The free list's length is taken from the counts the host already holds
 // (the graph's vertices less the visited ones and the batch), so no
 // readback waits for the scan.  Checked here against the scan's total: a
@@ -1567,6 +1601,8 @@ __global__ void k_sweep_free_check(SweepArgs A, int32_t assumed, int32_t* list) 
   for (int32_t i = got + (int32_t)threadIdx.x; i < assumed; i += blockDim.x) list[i] = A.v0;
 }
 
+// The free rows in tiles of BIG_TILE entries (off: prefix sums of the list's
+// row lengths; tile_row: each tile's first row, as for the push form).
 __global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32_t* list, int32_t nl,
                                                         const int64_t* off, const int32_t* tile_row,
                                                         const uint32_t* st2) {
