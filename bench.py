@@ -381,7 +381,8 @@ def roofline_of(r, steps, traffic_file):
         return e
     # the hot path's kernel classes: algorithmic bytes of all their launches
     # over all their device time
-    groups = {"capforest": ("k_sweep_seq", "k_sweep_tail", "k_sweep_big_relax", "k_sweep_big_mark",
+    groups = {"capforest": ("k_sweep_seq", "k_sweep_tail", "k_sweep_big_relax", "k_sweep_big_pull",
+                            "k_sweep_seg_bounds", "k_sweep_seg_relax", "k_sweep_seg_fallback", "k_sweep_big_mark",
                             "sweep_batch_prep", "sweep_rebuild", "k_sweep_unite", "k_small_sweep",
                             "capforest_region", "capforest_whole", "k_union_pairs"),
               "contraction": ("block_bits", "k_emit", "k_rs_hist", "k_rs_scatter", "merge_scan", "k_merge", "csr"),
