@@ -145,6 +145,49 @@ __device__ __forceinline__ int64_t wave_sum_i64_dpp(int64_t v) {
   return readlane_i64(v, 0) + readlane_i64(v, 16) + readlane_i64(v, 32) + readlane_i64(v, 48);
 }
 
+// Lane-order scans and shifts over the wave's 64 lanes by DPP (all lanes
+// active), without LDS traffic: inside each row of 16 lanes by shifts of 1,
+// 2, 4 and 8 lanes (Hillis-Steele), then across rows by broadcasting lane
+// 15 to rows 1 and 3 and lane 31 to rows 2 and 3.  A lane whose source is
+// outside its row, or whose row is masked off, keeps `old` (the identity).
+// DPP controls: row_shr:n = 0x110 + n, wave_shl:1 = 0x130, wave_shr:1 =
+// 0x138, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int32_t dpp_old_i32(int32_t old, int32_t v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ int32_t wave_incl_max_i32(int32_t v) {
+  constexpr int32_t LO = INT32_MIN;
+  int32_t t;
+  t = dpp_old_i32<0x111, 0xF>(LO, v); v = t > v ? t : v;
+  t = dpp_old_i32<0x112, 0xF>(LO, v); v = t > v ? t : v;
+  t = dpp_old_i32<0x114, 0xF>(LO, v); v = t > v ? t : v;
+  t = dpp_old_i32<0x118, 0xF>(LO, v); v = t > v ? t : v;
+  t = dpp_old_i32<0x142, 0xA>(LO, v); v = t > v ? t : v;
+  t = dpp_old_i32<0x143, 0xC>(LO, v); v = t > v ? t : v;
+  return v;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int64_t dpp_old_i64(int64_t old, int64_t v) {
+  const int32_t lo = dpp_old_i32<CTRL, ROWS>((int32_t)(uint32_t)(uint64_t)old, (int32_t)(uint32_t)(uint64_t)v);
+  const int32_t hi = dpp_old_i32<CTRL, ROWS>((int32_t)((uint64_t)old >> 32), (int32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t wave_incl_sum_i64(int64_t v) {
+  v += dpp_old_i64<0x111, 0xF>(0, v);
+  v += dpp_old_i64<0x112, 0xF>(0, v);
+  v += dpp_old_i64<0x114, 0xF>(0, v);
+  v += dpp_old_i64<0x118, 0xF>(0, v);
+  v += dpp_old_i64<0x142, 0xA>(0, v);
+  v += dpp_old_i64<0x143, 0xC>(0, v);
+  return v;
+}
+// lane l receives lane l - 1's value (lane 0: `first`), or lane l + 1's
+// (lane 63: `last`)
+__device__ __forceinline__ int32_t wave_shr1_i32(int32_t v, int32_t first) { return dpp_old_i32<0x138, 0xF>(first, v); }
+__device__ __forceinline__ int64_t wave_shr1_i64(int64_t v, int64_t first) { return dpp_old_i64<0x138, 0xF>(first, v); }
+__device__ __forceinline__ int32_t wave_shl1_i32(int32_t v, int32_t last) { return dpp_old_i32<0x130, 0xF>(last, v); }
+
 // Relaxed device-scope loads and stores for data other waves update.
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {

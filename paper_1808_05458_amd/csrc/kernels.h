@@ -101,9 +101,27 @@ __global__ void __launch_bounds__(256) k_fill_src(int32_t n, int64_t nnz, const 
   }
 }
 
+// wave_segsum for 32-bit keys and 64-bit values by DPP scans (all lanes
+// active): a run's head lanes by a one-lane shift, each lane's run start by a
+// maximum scan, and its segmented sum as the difference of two prefix sums
+// (one lane read for the prefix before the run).
+__device__ __forceinline__ int64_t wave_segsum_dpp(int32_t key, int64_t val, bool valid, bool& tail) {
+  const int lane = lane_id();
+  // both shifts by every lane (inside a short-circuit the edge lane would
+  // sit out, and its neighbour would read its own value back)
+  const int32_t prev = wave_shr1_i32(key, key), next = wave_shl1_i32(key, key);
+  const bool head = lane == 0 || prev != key;
+  const int32_t start = wave_incl_max_i32(head ? lane : -1);  // lane 0 heads a run
+  const int64_t p = wave_incl_sum_i64(valid ? val : 0);
+  const int64_t before = __shfl(p, start > 0 ? start - 1 : 0, 64);
+  tail = lane == 63 || next != key;
+  return start > 0 ? p - before : p;
+}
+
 // Sum of val over each run of equal row among the wave's 64 lanes (rows
 // ascend with the lane), added to out[row] once per run.  A slot held by one
 // row throughout is one wave sum (long rows); otherwise a segmented sum.
+// All 64 lanes must be active.
 __device__ __forceinline__ void wave_row_add(int32_t row, int64_t val, bool ok, int64_t* out) {
   const int32_t r_first = __builtin_amdgcn_readfirstlane(row);
   if (ballot(ok && row != r_first) == 0) {
@@ -112,7 +130,7 @@ __device__ __forceinline__ void wave_row_add(int32_t row, int64_t val, bool ok, 
     return;
   }
   bool tail;
-  const int64_t sum = wave_segsum<int32_t, int64_t>(ok ? row : -1, val, ok, tail);
+  const int64_t sum = wave_segsum_dpp(ok ? row : -1, val, ok, tail);
   if (ok && tail && sum) atomicAdd((unsigned long long*)(out + row), (unsigned long long)sum);
 }
 
@@ -259,11 +277,10 @@ __global__ void __launch_bounds__(256, 5) k_ingest(int32_t n, int64_t nnz, const
     if (in_head) hs = acc;
     else { tr = cur; ts = acc; }
     const bool has_tail = !in_head;
-    const int32_t next_head = __shfl_down(hr, 1, 64);
+    const int32_t next_head = wave_shl1_i32(hr, hr);
     const bool tail_on = has_tail && lane < 63 && next_head == tr;
     if (has_tail && !tail_on && ts) atomicAdd((unsigned long long*)(cdeg + tr), (unsigned long long)ts);
-    const int64_t carried = __shfl_up(tail_on ? ts : (int64_t)0, 1, 64);
-    if (lane > 0) hs += carried;
+    hs += wave_shr1_i64(tail_on ? ts : (int64_t)0, 0);
     wave_row_add(hr, hs, true, cdeg);
   }
   const uint32_t m = wave_max_u32((uint32_t)run_m);

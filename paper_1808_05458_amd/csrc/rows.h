@@ -54,14 +54,9 @@ __device__ __forceinline__ void chunk_rows_from(const int64_t* __restrict__ rp, 
   for (int k = 0; k < 8; ++k) v[k] = pos[lane * 8 + k];
 #pragma unroll
   for (int k = 1; k < 8; ++k) v[k] = v[k] > v[k - 1] ? v[k] : v[k - 1];
-  int32_t inc = v[7];
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t t = __shfl_up(inc, o, 64);
-    if (lane >= o && t > inc) inc = t;
-  }
-  int32_t ex = __shfl_up(inc, 1, 64);
-  if (lane == 0) ex = -1;
+  // the largest row started at or before each lane's positions (DPP scan)
+  const int32_t inc = wave_incl_max_i32(v[7]);
+  const int32_t ex = wave_shr1_i32(inc, -1);
 #pragma unroll
   for (int k = 0; k < 8; ++k) pos[lane * 8 + k] = v[k] > ex ? v[k] : ex;
   wave_lds_sync();
