@@ -188,6 +188,36 @@ __device__ __forceinline__ int32_t wave_shr1_i32(int32_t v, int32_t first) { ret
 __device__ __forceinline__ int64_t wave_shr1_i64(int64_t v, int64_t first) { return dpp_old_i64<0x138, 0xF>(first, v); }
 __device__ __forceinline__ int32_t wave_shl1_i32(int32_t v, int32_t last) { return dpp_old_i32<0x130, 0xF>(last, v); }
 
+// The same for any 32- or 64-bit integer type.  Call with every lane of
+// the wave active, never inside a lane-dependent branch or short circuit:
+// a lane that sits out gives its neighbours the fallback value instead of
+// its own.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_old(T old, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_old_i32<CTRL, ROWS>(__builtin_bit_cast(int32_t, old),
+                                                        __builtin_bit_cast(int32_t, v)));
+  } else {
+    return __builtin_bit_cast(T, dpp_old_i64<CTRL, ROWS>(__builtin_bit_cast(int64_t, old),
+                                                        __builtin_bit_cast(int64_t, v)));
+  }
+}
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v) {
+  v += dpp_old<0x111, 0xF>((T)0, v);
+  v += dpp_old<0x112, 0xF>((T)0, v);
+  v += dpp_old<0x114, 0xF>((T)0, v);
+  v += dpp_old<0x118, 0xF>((T)0, v);
+  v += dpp_old<0x142, 0xA>((T)0, v);
+  v += dpp_old<0x143, 0xC>((T)0, v);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_shr1(T v, T first) { return dpp_old<0x138, 0xF>(first, v); }
+template <typename T>
+__device__ __forceinline__ T wave_shl1(T v, T last) { return dpp_old<0x130, 0xF>(last, v); }
+
 // Relaxed device-scope loads and stores for data other waves update.
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {

@@ -37,25 +37,21 @@ struct GraphState {  // per-graph device arrays
 };
 
 // Segmented sum of `val` over runs of equal `key` within the wave (lanes in
-// order).  Returns the run total in the run's last lane; tail = last lane.
+// order), by DPP scans: run heads by a one-lane shift, each lane's run start
+// by a maximum scan, its segmented prefix as the difference of two prefix
+// sums (one lane read for the prefix before the run).  Returns the run's
+// sum up to this lane (the run total in its last lane); tail = last lane.
+// Every lane of the wave must call it (no lane-dependent branch around it).
 template <typename K, typename V>
 __device__ __forceinline__ V wave_segsum(K key, V val, bool valid, bool& tail) {
   const int lane = lane_id();
-  K prev = __shfl_up(key, 1, 64);
-  bool head = lane == 0 || prev != key;
-  int start = head ? lane : 0;
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(start, o, 64);
-    if (lane >= o && t > start) start = t;
-  }
-  V x = valid ? val : (V)0;
-  for (int o = 1; o < 64; o <<= 1) {
-    V t = __shfl_up(x, o, 64);
-    if (lane - o >= start) x += t;
-  }
-  K next = __shfl_down(key, 1, 64);
+  const K prev = wave_shr1<K>(key, key), next = wave_shl1<K>(key, key);
+  const bool head = lane == 0 || prev != key;
+  const int32_t start = wave_incl_max_i32(head ? lane : -1);  // lane 0 heads a run
+  const V p = wave_incl_sum<V>(valid ? val : (V)0);
+  const V before = __shfl(p, start > 0 ? start - 1 : 0, 64);
   tail = lane == 63 || next != key;
-  return x;
+  return start > 0 ? (V)(p - before) : p;
 }
 
 // ------------------------------------------------------------------ ingest
@@ -101,23 +97,6 @@ __global__ void __launch_bounds__(256) k_fill_src(int32_t n, int64_t nnz, const 
   }
 }
 
-// wave_segsum for 32-bit keys and 64-bit values by DPP scans (all lanes
-// active): a run's head lanes by a one-lane shift, each lane's run start by a
-// maximum scan, and its segmented sum as the difference of two prefix sums
-// (one lane read for the prefix before the run).
-__device__ __forceinline__ int64_t wave_segsum_dpp(int32_t key, int64_t val, bool valid, bool& tail) {
-  const int lane = lane_id();
-  // both shifts by every lane (inside a short-circuit the edge lane would
-  // sit out, and its neighbour would read its own value back)
-  const int32_t prev = wave_shr1_i32(key, key), next = wave_shl1_i32(key, key);
-  const bool head = lane == 0 || prev != key;
-  const int32_t start = wave_incl_max_i32(head ? lane : -1);  // lane 0 heads a run
-  const int64_t p = wave_incl_sum_i64(valid ? val : 0);
-  const int64_t before = __shfl(p, start > 0 ? start - 1 : 0, 64);
-  tail = lane == 63 || next != key;
-  return start > 0 ? p - before : p;
-}
-
 // Sum of val over each run of equal row among the wave's 64 lanes (rows
 // ascend with the lane), added to out[row] once per run.  A slot held by one
 // row throughout is one wave sum (long rows); otherwise a segmented sum.
@@ -130,7 +109,7 @@ __device__ __forceinline__ void wave_row_add(int32_t row, int64_t val, bool ok, 
     return;
   }
   bool tail;
-  const int64_t sum = wave_segsum_dpp(ok ? row : -1, val, ok, tail);
+  const int64_t sum = wave_segsum<int32_t, int64_t>(ok ? row : -1, val, ok, tail);
   if (ok && tail && sum) atomicAdd((unsigned long long*)(out + row), (unsigned long long)sum);
 }
 

@@ -14,11 +14,7 @@ constexpr int64_t SCAN_TILE = (int64_t)SCAN_THREADS * SCAN_ROWS;  // 4096 elemen
 template <typename T>
 __device__ __forceinline__ T block_inclusive_scan(T v, T* lds_wave_tot, T& block_total) {
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  T x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    T y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  const T x = wave_incl_sum<T>(v);
   if (lane == 63) lds_wave_tot[wave] = x;
   __syncthreads();
   T base = 0, tot = 0;

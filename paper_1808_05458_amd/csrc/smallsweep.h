@@ -372,11 +372,7 @@ __global__ void __launch_bounds__(THREADS) k_small_sweep(SmallSweepArgs A) {
           deg = (int32_t)(A.rp[x + 1] - a);
           L.bbase[threadIdx.x] = (int32_t)(a - ebase);
         }
-        int32_t incl = deg;
-        for (int o = 1; o < 64; o <<= 1) {
-          const int32_t t = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += t;
-        }
+        const int32_t incl = wave_incl_sum<int32_t>(deg);
         if (lane == 63) L.wtot[wave] = incl;
         __syncthreads();
         int32_t before = 0;

@@ -812,11 +812,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_seq(const SweepArgs* ar
           sh_bx[threadIdx.x] = x;
           sh_bbase[threadIdx.x] = a;
         }
-        int32_t incl = deg;
-        for (int o = 1; o < 64; o <<= 1) {
-          const int32_t v = __shfl_up(incl, o, 64);
-          if (lane >= o) incl += v;
-        }
+        const int32_t incl = wave_incl_sum<int32_t>(deg);
         if (lane == 63) sh_wtot[wave] = incl;
         __threadfence_block();
         __syncthreads();
@@ -1365,11 +1361,7 @@ __global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, in
       s_x[tid] = x;
       s_base[tid] = A.rp[x] + a;
     }
-    int64_t incl = len;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int64_t t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
+    const int64_t incl = wave_incl_sum<int64_t>(len);
     if (lane == 63) wtot[wave] = incl;
     __syncthreads();
     int64_t before = 0;
@@ -1568,11 +1560,7 @@ __global__ void __launch_bounds__(256) k_sweep_free_bits(SweepArgs A, uint32_t* 
   if (wave == 0) {
     // group offsets within the tile, and the tile's range in the list
     const int32_t c0 = lane < NG ? popc64(s_free[lane]) : 0;
-    int32_t incl = c0;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
+    const int32_t incl = wave_incl_sum<int32_t>(c0);
     if (lane < NG) s_pos[lane] = incl - c0;
     if (lane == 63) {
       s_pos[NG] = incl;
@@ -1761,11 +1749,7 @@ __global__ void __launch_bounds__(1024) k_sweep_rb_scan(SweepArgs A) {
   // exclusive scan of the 1024 thread sums: within each wave, then over
   // the 16 wave totals
   const int lane = lane_id(), wave = threadIdx.x >> 6;
-  int32_t incl = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t t = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += t;
-  }
+  const int32_t incl = wave_incl_sum<int32_t>(s);
   if (lane == 63) part[wave] = incl;
   __syncthreads();
   int32_t before = 0;
