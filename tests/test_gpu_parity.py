@@ -517,3 +517,26 @@ def test_range_owned_push_and_row_order():
                 lam, side, st = solve(graph, **opts)
                 assert lam == ref, (graph.name, opts)
                 check_side(graph, lam, side)
+
+
+def test_range_owned_push_in_packed_sweeps():
+    """Several graphs above the LDS size swept in one packed solve (their
+    sweeps run at once, sharing the segment table in turn), the range-owned
+    relax forced, one graph's rows shuffled: every lambda equals the
+    oracle's and every side realises it."""
+    import paper_1808_05458_amd as mc
+    graphs = [gg.rmat(7, 15, 1 << 19, 0.57, 0.19, 0.19, kcore=5, lcc=True, name="rmat15"),
+              gg.chung_lu(37, 30000, 2.4, 12.0, 1, 5, kcore=3, lcc=True),
+              _shuffle_rows(gg.chung_lu(41, 25000, 2.6, 10.0, 1, 3, kcore=3, lcc=True), 5),
+              gg.planted_4096()]
+    refs = [oracle.noi(g, 1)[0] for g in graphs]
+    packed, vo, eo = gg.pack(graphs)
+    rp, col, w = mc.to_device(packed, "cuda")
+    for opts in [dict(sweep_seg=1, sweep_pull=-1, sweep_handoff=1), dict(sweep_seg=1, sweep_pull=-1),
+                 dict(sweep_seg=-1, sweep_handoff=1)]:
+        announce("packed range-owned push", packed.n, packed.m, opts)
+        lams, sides, st = mc.mincut_batched(rp, col, w, vo, **opts)
+        assert list(lams) == refs, opts
+        s = sides.cpu().numpy()
+        for i, g in enumerate(graphs):
+            check_side(g, int(lams[i]), s[vo[i]:vo[i + 1]])

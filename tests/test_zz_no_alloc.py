@@ -55,7 +55,8 @@ def test_noalloc_options_and_small_graphs():
         e += [(i, i + 1) for i in range(n - 1)]
         g = gg.from_edges(n, e, rng.integers(1, 20, size=len(e)))
         ref = oracle.stoer_wagner(g)[0]
-        for opts in [dict(), dict(whole_max=4, sweep_handoff=1), dict(scan_mode=1, whole_max=4)]:
+        for opts in [dict(), dict(whole_max=4, sweep_handoff=1), dict(scan_mode=1, whole_max=4),
+                     dict(whole_max=4, sweep_handoff=1, sweep_seg=1, sweep_pull=-1)]:
             lam_na, side_na, lam, _ = _both(g, **opts)
             assert lam_na == lam == ref, (t, opts)
             check_side(g, lam_na, side_na)
