@@ -582,13 +582,17 @@ struct Solver {
     hipLaunchKernelGGL(k_fill_src, chunk_grid(nnz, num_cu * 8), dim3(256), 0, s, n, nnz, rp, ws.first, src);
   }
   // PR1/PR2 on every entry of graph (n, nnz, rp, col, w).
+  // The chunk maxima of graph (rp, w, nnz) if the ingest recorded them, else null.
+  const int32_t* chunk_maxima(const int64_t* rp, const int32_t* w, int64_t nnz) const {
+    return (chmax_rp == rp && chmax_w == w && chmax_nnz == nnz) ? ws.chmax : nullptr;
+  }
   int pr_tests(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* col, const int32_t* w,
                const int64_t* cdeg, const int32_t* gid, const int64_t* lhat, const int32_t* active) {
     if (nnz <= 0) return MC_OK;
     need_first(n, nnz, rp);
     // the ingested graph itself: its chunk maxima let the tests skip chunks
     // without reading them
-    const int32_t* cm = (chmax_rp == rp && chmax_w == w && chmax_nnz == nnz) ? ws.chmax : nullptr;
+    const int32_t* cm = chunk_maxima(rp, w, nnz);
     hipLaunchKernelGGL(k_pr, chunk_grid(nnz, num_cu * 16), dim3(256), 0, s, n, nnz, rp, ws.first, col, w, cm,
                        cdeg, gid, lhat, active, ws.parent, ws.ucount, ws.ctl);
     return MC_OK;
@@ -1190,7 +1194,8 @@ struct Solver {
         {
           TimedScope t("vc_pr", (double)nnz * 20 + (double)n * 16);
           hipLaunchKernelGGL(k_iota, grid(n), dim3(TB), 0, s, ws.parent, n);
-          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, cdeg, gid, ws.lhat, V.act,
+          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, chunk_maxima(rp, w, nnz),
+                             cdeg, gid, ws.lhat, V.act,
                              ws.parent, ws.ucount);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
           hipLaunchKernelGGL(k_lam_floor, dim3(1), dim3(256), 0, s, G, ws.lhat, V.act, ws.ctl);
@@ -1438,7 +1443,8 @@ struct Solver {
           // per vertex its row bounds, degree, bound and parent, and its
           // first two entries with their neighbours' degrees
           TimedScope t("k_pr_sample", (double)n * 64);
-          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, ws.cdeg, gid, cap,
+          hipLaunchKernelGGL(k_pr_sample, grid(n), dim3(TB), 0, s, n, nnz, rp, col, w, chunk_maxima(rp, w, nnz),
+                             ws.cdeg, gid, cap,
                              tested, ws.parent, ws.ucount);
           hipLaunchKernelGGL(k_flatten, grid(n), dim3(TB), 0, s, n, ws.parent);
         }

@@ -583,9 +583,12 @@ __device__ __forceinline__ void pr_flag(int32_t* ucount, int32_t g, int32_t& las
 
 // Loads are grouped so that each round trip serves every entry the thread
 // holds, and no load waits inside a divergent branch: an entry that needs
-// nothing reads a shared dummy address instead.
+// nothing reads a shared dummy address instead.  chmax (the chunk maxima of
+// this graph, or null): a vertex whose sampled entries lie in chunks whose
+// largest weight cannot pass skips their loads.
 __global__ void k_pr_sample(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
                             const int32_t* __restrict__ col, const int32_t* __restrict__ w,
+                            const int32_t* __restrict__ chmax,
                             const int64_t* __restrict__ cdeg, const int32_t* __restrict__ gid,
                             const int64_t* __restrict__ lhat, const int32_t* __restrict__ active, int32_t* parent,
                             int32_t* ucount) {
@@ -596,10 +599,16 @@ __global__ void k_pr_sample(int32_t n, int64_t nnz, const int64_t* __restrict__ 
     const int64_t cv = cdeg[v], e0 = rp[v], e1 = rp[v + 1];
     const bool act = active[g] != 0;
     const int64_t lam = lhat[g];
+    bool live = e1 > e0;
+    if (chmax && live) {
+      const int64_t el = min(e0 + PR_SAMPLE, e1) - 1;  // the last sampled entry
+      const int32_t m0 = chmax[e0 / WCH], m1 = chmax[el / WCH];
+      live = !pr_hopeless(m0 > m1 ? m0 : m1, lam);
+    }
     int32_t u[PR_SAMPLE], c[PR_SAMPLE];
 #pragma unroll
     for (int k = 0; k < PR_SAMPLE; ++k) {
-      const int64_t e = e0 + k < e1 ? e0 + k : 0;
+      const int64_t e = live && e0 + k < e1 ? e0 + k : 0;
       u[k] = col[e];
       c[k] = w[e];
     }
@@ -607,7 +616,7 @@ __global__ void k_pr_sample(int32_t n, int64_t nnz, const int64_t* __restrict__ 
     int64_t cu[PR_SAMPLE];
 #pragma unroll
     for (int k = 0; k < PR_SAMPLE; ++k) {
-      keep[k] = act && e0 + k < e1 && u[k] != (int32_t)v && !pr_hopeless(c[k], lam);
+      keep[k] = act && live && e0 + k < e1 && u[k] != (int32_t)v && !pr_hopeless(c[k], lam);
       cu[k] = cdeg[keep[k] ? u[k] : (int32_t)v];
     }
 #pragma unroll
