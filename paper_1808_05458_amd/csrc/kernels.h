@@ -168,14 +168,68 @@ __global__ void __launch_bounds__(256, 5) k_ingest(int32_t n, int64_t nnz, const
   for (; ch < nch; ch += gwaves()) {
     const int64_t e0 = ch * WCH;
     const int32_t r0 = f;
-    int32_t row[8];
-    chunk_rows_from(rp, n, e0, r0, s0, pos, row);
     // the chunk's graph: the first row's, when its last row is in it too
     // (graphs are contiguous vertex ranges)
     const int32_t g0 = gq;
     const int32_t lo0 = G > 1 ? (int32_t)voff[g0] : 0;  // vertex ids fit 31 bits
     const int32_t hi0 = G > 1 ? (int32_t)voff[g0 + 1] : n;
     const int32_t len = (int32_t)min((int64_t)WCH, nnz - e0);
+    {
+      // Prefix form, taken when fewer than 64 rows start inside the chunk
+      // (lane i holds the start of row r0 + 1 + i), the chunk lies in one
+      // graph, no neighbour is one of the chunk's rows (so no self-loop)
+      // and the chunk's sums fit 31 bits: a row's share of the chunk is the
+      // difference of the chunk's prefix sums at its ends, and no entry
+      // needs its row.
+      const int64_t st = s0;
+      const bool starts = r0 + 1 + lane < n && st < e0 + len;
+      const uint64_t sm = ballot(starts);
+      const int32_t r_end = r0 + popc64(sm);  // the chunk's last row when lane 63 does not start one
+      bool near = false;
+      int32_t cmx = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool ok = k * 64 + lane < len;
+        const int32_t ck = ok ? c[k] : 0;
+        cmx = ck > cmx ? ck : cmx;
+        near = near || (ok && y[k] >= r0 && y[k] <= r_end);
+      }
+      const uint32_t cm = wave_max_u32((uint32_t)cmx);
+      if (!(sm >> 63) && r_end < hi0 && ballot(near) == 0 && cm < (1u << 22)) {
+        if (g0 != run_g) {
+          const uint32_t m = wave_max_u32((uint32_t)run_m);
+          if (lane == 0 && m && run_g >= 0) atomicMax(gmaxw + run_g, (int32_t)m);
+          run_g = g0;
+          run_m = 0;
+        }
+        run_m = cmx > run_m ? cmx : run_m;
+        bool bad = false;
+        int32_t base = 0;  // the chunk's sum before slot k
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const bool ok = k * 64 + lane < len;
+          bad = bad || (ok && ((uint32_t)(y[k] - lo0) >= (uint32_t)(hi0 - lo0) || c[k] < 1));
+          const int32_t v = ok ? c[k] : 0;
+          const int32_t inc = wave_incl_sum<int32_t>(v);
+          vals[k * 64 + lane] = base + inc - v;  // the chunk's entries before this one
+          base += __builtin_amdgcn_readlane(inc, 63);
+        }
+        if (bad) atomicExch(&ctl->err, -1);
+        if (lane == 0) chmax[ch] = (int32_t)cm;
+        if (ch + gwaves() < nch) load(ch + gwaves());
+        wave_lds_sync();
+        const int32_t at = starts ? vals[(int32_t)min(max(st - e0, (int64_t)0), (int64_t)WCH - 1)] : base;
+        wave_lds_sync();  // vals is rewritten by the next chunk
+        // lane i: row r0 + i, from the previous lane's start (or the chunk's
+        // first entry) to its own (or the chunk's end)
+        const int32_t share = at - wave_shr1<int32_t>(at, 0);
+        if (lane <= r_end - r0 && share)
+          atomicAdd((unsigned long long*)(cdeg + r0 + lane), (unsigned long long)(int64_t)share);
+        continue;
+      }
+    }
+    int32_t row[8];
+    chunk_rows_from(rp, n, e0, r0, s0, pos, row);
     const int32_t last_e = len - 1;  // slot and lane of the chunk's last entry
     int32_t row_last = r0;
 #pragma unroll
