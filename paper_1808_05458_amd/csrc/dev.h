@@ -321,6 +321,16 @@ __device__ __forceinline__ void wave_add_by_key(int32_t* arr, int32_t key, int32
 }
 
 // Grid-stride helpers
+// The chip deals workgroups to its 8 XCDs round-robin (block b runs on XCD
+// b % 8), and each XCD has its own L2.  xcd_major renumbers a grid (a
+// multiple of 8 blocks) so that each XCD takes one contiguous run of the
+// logical indices: neighbouring work items, which share cache lines at
+// their edges, then meet in one L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int32_t xcd_major(int32_t b, int32_t grid) {
+  return (b % NUM_XCD) * (grid / NUM_XCD) + b / NUM_XCD;
+}
+
 __device__ __forceinline__ int64_t gtid() {
   return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }

@@ -808,7 +808,8 @@ struct Solver {
                 // every batch entry once (col, w), two cells per row and
                 // range, and per vertex its word read and r written
                 TimedScope t("k_sweep_seg_relax", (double)deg_sum * 8 + (double)cells * 8 + (double)A.ng * 12);
-                hipLaunchKernelGGL(k_sweep_seg_relax, dim3((uint32_t)nr), dim3(SEG_THREADS), 0, s, A, bh,
+                hipLaunchKernelGGL(k_sweep_seg_relax, dim3((uint32_t)((nr + NUM_XCD - 1) / NUM_XCD * NUM_XCD)),
+                                   dim3(SEG_THREADS), 0, s, A, bh,
                                    (int32_t)bsz, (const int64_t*)off, shift, (int32_t)nr,
                                    (const int32_t*)ws.vals_alt, (const uint32_t*)ws.st2);
               }

@@ -1331,7 +1331,10 @@ __global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, in
   __shared__ int32_t cnt[NW];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int tid = threadIdx.x;
-  const int32_t q = blockIdx.x;
+  // range q, consecutive ranges on one XCD (a run's edge lines are read by
+  // the neighbouring range too); the grid is nr rounded up to whole XCDs
+  const int32_t q = xcd_major(blockIdx.x, gridDim.x);
+  if (q >= nr) return;
   const int32_t lo_v = q << shift;  // a multiple of 64
   const int32_t nv = min(1 << shift, A.ng - lo_v);
   for (int32_t i = tid; i < nv; i += SEG_THREADS) r_loc[i] = rs_r(A.rs[A.v0 + lo_v + i]);
@@ -1370,9 +1373,10 @@ __global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, in
     if (tid == cn - 1) s_off[cn] = before + incl;
     __syncthreads();
     const int64_t total = s_off[cn];
-    // every thread takes every pass (the crossings' buffer is kept per wave,
-    // with all lanes present); a slot past the end is idle
-    for (int64_t pass = 0; pass < total; pass += SEG_THREADS * SEG_UNROLL) {
+    // a pass's entries: their batch vertex and their column and weight
+    // (loads issued here, awaited where they are used)
+    int32_t xs[SEG_UNROLL], ys[SEG_UNROLL], cs[SEG_UNROLL];
+    auto fetch = [&](int64_t pass) {
       const int64_t i0 = pass + tid * SEG_UNROLL;
       int32_t row = 0;
       if (i0 < total) {
@@ -1385,7 +1389,6 @@ __global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, in
         row = lo;
       }
       int64_t es[SEG_UNROLL];
-      int32_t xs[SEG_UNROLL];
 #pragma unroll
       for (int u = 0; u < SEG_UNROLL; ++u) {
         const int64_t i = i0 + u;
@@ -1397,26 +1400,39 @@ __global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, in
           xs[u] = s_x[row];
         }
       }
-      int32_t ys[SEG_UNROLL], cs[SEG_UNROLL];
 #pragma unroll
       for (int u = 0; u < SEG_UNROLL; ++u) {
         ys[u] = A.col[es[u]];
         cs[u] = A.w[es[u]];
       }
+    };
+    if (total > 0) fetch(0);
+    // every thread takes every pass (the crossings' buffer is kept per wave,
+    // with all lanes present); a slot past the end is idle
+    for (int64_t pass = 0; pass < total; pass += SEG_THREADS * SEG_UNROLL) {
+      // this pass's entries; the next pass's loads go out before its adds
+      int32_t xc[SEG_UNROLL], yc[SEG_UNROLL], cc[SEG_UNROLL];
 #pragma unroll
       for (int u = 0; u < SEG_UNROLL; ++u) {
-        const int32_t yl = ys[u] - A.v0 - lo_v;
+        xc[u] = xs[u];
+        yc[u] = ys[u];
+        cc[u] = cs[u];
+      }
+      if (pass + SEG_THREADS * SEG_UNROLL < total) fetch(pass + SEG_THREADS * SEG_UNROLL);
+#pragma unroll
+      for (int u = 0; u < SEG_UNROLL; ++u) {
+        const int32_t yl = yc[u] - A.v0 - lo_v;
         // (a neighbour outside the range would mean a row out of order:
         // never added, and never an LDS access out of bounds)
-        const bool act = xs[u] >= 0 && ys[u] != xs[u] && (uint32_t)yl < (uint32_t)nv;
+        const bool act = xc[u] >= 0 && yc[u] != xc[u] && (uint32_t)yl < (uint32_t)nv;
         bool cross = false;
         if (act) {
           const uint32_t st = (s_st[yl >> 4] >> (2 * (yl & 15))) & 3u;
-          if (st == BS_BATCH) internal += cs[u];
-          else if (st == BS_VISITED) rsum += cs[u];
+          if (st == BS_BATCH) internal += cc[u];
+          else if (st == BS_VISITED) rsum += cc[u];
           else {
-            const int32_t old = atomicAdd(&r_loc[yl], cs[u]);
-            cross = (int64_t)old < A.lam && A.lam <= (int64_t)old + cs[u];
+            const int32_t old = atomicAdd(&r_loc[yl], cc[u]);
+            cross = (int64_t)old < A.lam && A.lam <= (int64_t)old + cc[u];
           }
         }
         const uint64_t cm = ballot(cross);
@@ -1424,8 +1440,8 @@ __global__ void __launch_bounds__(SEG_THREADS) k_sweep_seg_relax(SweepArgs A, in
           const int32_t at = *wcnt;
           if (cross) {
             const int32_t k = at + popc64(cm & lanemask_lt());
-            wbuf[2 * k] = ys[u];
-            wbuf[2 * k + 1] = xs[u];
+            wbuf[2 * k] = yc[u];
+            wbuf[2 * k + 1] = xc[u];
           }
           __builtin_amdgcn_wave_barrier();
           if (lane == 0) *wcnt = at + popc64(cm);
