@@ -1606,31 +1606,63 @@ __global__ void k_sweep_free_check(SweepArgs A, int32_t assumed, int32_t* list) 
 }
 
 // The free rows in tiles of BIG_TILE entries (off: prefix sums of the list's
-// row lengths; tile_row: each tile's first row, as for the push form).
+// row lengths; tile_row: each tile's first row, as for the push form).  A
+// workgroup's next tile, when its rows fit one slice, has its rows' vertices
+// and offsets loaded before this tile's entries and their row starts with
+// this tile's state words, so they wait in registers, not on the latency.
 __global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32_t* list, int32_t nl,
                                                         const int64_t* off, const int32_t* tile_row,
                                                         const uint32_t* st2) {
+  constexpr int PR = BIG_TILE / 256;  // prefetched rows per thread
   __shared__ int32_t s_y[BIG_TILE];
   __shared__ int64_t s_off[BIG_TILE + 1], s_base[BIG_TILE];
-  __shared__ int32_t e_w[BIG_TILE], e_x[BIG_TILE];
+  __shared__ uint32_t e_w[BIG_TILE];
+  __shared__ int32_t e_x[BIG_TILE];
+  __shared__ uint32_t s_wt[4];
+  static_assert(BIG_TILE == 4 * 64 * BIG_UNROLL, "four waves, BIG_UNROLL positions per lane");
   SweepCtl* c = A.ctl;
   const int lane = lane_id();
   const int64_t total = off[nl];
   const int64_t ntiles = (total + BIG_TILE - 1) / BIG_TILE;
   const int64_t e_idle = A.rp[A.v0];
   int64_t into = 0;  // weight of free rows' edges into the batch
+  int32_t py[PR];
+  int64_t pb[PR], po[PR], po_end = 0;
+  bool have = false;  // py, pb, po hold the rows of this tile
   for (int64_t j = blockIdx.x; j < ntiles; j += gridDim.x) {
     const int64_t t0 = j * BIG_TILE, t1 = min(t0 + BIG_TILE, total);
     const int32_t r0 = tile_row[j], r1 = j + 1 < ntiles ? tile_row[j + 1] : nl - 1;
+    // the next tile, prefetched when its rows fit one slice
+    const int64_t jn = j + gridDim.x;
+    int32_t n0 = 0, nn = 0;
+    if (jn < ntiles) {
+      n0 = tile_row[jn];
+      nn = (jn + 1 < ntiles ? tile_row[jn + 1] : nl - 1) + 1 - n0;
+    }
+    const bool pre = jn < ntiles && nn <= BIG_TILE && r1 + 1 - r0 <= BIG_TILE;
     for (int32_t rb = r0; rb <= r1; rb += BIG_TILE) {
       const int32_t nr = min(BIG_TILE, r1 + 1 - rb);
-      for (int32_t k = threadIdx.x; k < nr; k += 256) {
-        const int32_t y = list[rb + k];
-        s_y[k] = y;
-        s_base[k] = A.rp[y];
-        s_off[k] = off[rb + k];
+      if (have) {
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+          const int32_t k = (int32_t)threadIdx.x + u * 256;
+          if (k < nr) {
+            s_y[k] = py[u];
+            s_base[k] = pb[u];
+            s_off[k] = po[u];
+          }
+        }
+        if (threadIdx.x == 0) s_off[nr] = po_end;
+        have = false;
+      } else {
+        for (int32_t k = threadIdx.x; k < nr; k += 256) {
+          const int32_t y = list[rb + k];
+          s_y[k] = y;
+          s_base[k] = A.rp[y];
+          s_off[k] = off[rb + k];
+        }
+        if (threadIdx.x == 0) s_off[nr] = off[rb + nr];
       }
-      if (threadIdx.x == 0) s_off[nr] = off[rb + nr];
       __syncthreads();
       const int64_t lo_e = max(s_off[0], t0), hi_e = min(s_off[nr], t1);
       const int64_t i0 = lo_e + (int64_t)threadIdx.x * BIG_UNROLL;
@@ -1643,6 +1675,15 @@ __global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32
           else hi = mid - 1;
         }
         row = lo;
+      }
+      if (pre) {
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+          const int32_t k = (int32_t)threadIdx.x + u * 256;
+          py[u] = list[n0 + (k < nn ? k : 0)];
+          po[u] = off[n0 + (k < nn ? k : 0)];
+        }
+        if (threadIdx.x == 0) po_end = off[n0 + nn];
       }
       // every entry's loads issued before any is used; an idle slot reads
       // the graph's first entry
@@ -1669,40 +1710,68 @@ __global__ void __launch_bounds__(256) k_sweep_big_pull(SweepArgs A, const int32
       uint32_t sw[BIG_UNROLL];
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) sw[u] = st2[(xs[u] - A.v0) >> 4];
+      if (pre) {
+#pragma unroll
+        for (int u = 0; u < PR; ++u) pb[u] = A.rp[py[u]];
+        have = true;
+      }
+      // the tile's in-batch weights as prefix sums, so that a row's part is
+      // the difference of two (in 32 bits: every weighted degree fits 31):
+      // a thread's four entries in order, the wave's by a scan, the waves'
+      // totals added where a prefix is read
+      uint32_t pre4[BIG_UNROLL];
+      uint32_t run4 = 0;
+#pragma unroll
+      for (int u = 0; u < BIG_UNROLL; ++u) {
+        const int32_t i = xs[u] - A.v0;
+        const bool inb = ok[u] && ((sw[u] >> (2 * (i & 15))) & 3u) == BS_BATCH;
+        const uint32_t v = inb ? (uint32_t)cs[u] : 0u;
+        run4 += v;
+        pre4[u] = run4;
+        into += v;
+      }
+      const uint32_t wincl = wave_incl_sum<uint32_t>(run4);
+      if (lane == 63) s_wt[threadIdx.x >> 6] = wincl;
 #pragma unroll
       for (int u = 0; u < BIG_UNROLL; ++u) {
         if (!ok[u]) continue;
-        const int32_t i = xs[u] - A.v0;
-        const bool inb = ((sw[u] >> (2 * (i & 15))) & 3u) == BS_BATCH;
         const int32_t p = (int32_t)(i0 + u - lo_e);
-        e_w[p] = inb ? cs[u] : 0;
+        e_w[p] = wincl - run4 + pre4[u];
         e_x[p] = xs[u];
-        into += inb ? cs[u] : 0;
       }
       __syncthreads();
-      // per row: its part of the tile, summed; the crossing, if any
+      // P(p): the tile's in-batch weight over positions [0, p]
+      const uint32_t wb1 = s_wt[0], wb2 = wb1 + s_wt[1], wb3 = wb2 + s_wt[2];
+      auto P = [&](int32_t p) -> uint32_t {
+        const int32_t wv = p / (BIG_UNROLL * 64);  // the wave that wrote position p
+        return e_w[p] + (wv == 0 ? 0u : wv == 1 ? wb1 : wv == 2 ? wb2 : wb3);
+      };
+      // per row: its part of the tile; the crossing, if any
       for (int32_t k0 = 0; k0 < nr; k0 += 256) {
         const int32_t k = k0 + (int32_t)threadIdx.x;
         int32_t y = -1, partner = -1;
         if (k < nr) {
           const int64_t a = max(s_off[k], lo_e), b = min(s_off[k + 1], hi_e);
-          int64_t sum = 0;
-          for (int64_t q = a; q < b; ++q) sum += e_w[q - lo_e];
-          if (sum > 0) {
-            y = s_y[k];
-            // a row wholly inside this tile has no other writer
-            const bool whole = s_off[k] >= t0 && s_off[k + 1] <= t1;
-            int32_t* rp32 = (int32_t*)(A.rs + y);
-            const int32_t old = whole ? *rp32 : atomic_add(rp32, (int32_t)sum);
-            if (whole) *rp32 = old + (int32_t)sum;
-            if ((int64_t)old < A.lam && A.lam <= (int64_t)old + sum) {
-              int64_t run = old;
-              for (int64_t q = a; q < b; ++q) {
-                run += e_w[q - lo_e];
-                if (run >= A.lam) {
-                  partner = e_x[q - lo_e];
-                  break;
+          if (a < b) {
+            const int32_t qa = (int32_t)(a - lo_e), qb = (int32_t)(b - lo_e);
+            const uint32_t before = qa > 0 ? P(qa - 1) : 0u;
+            const int64_t sum = (int64_t)(P(qb - 1) - before);
+            if (sum > 0) {
+              y = s_y[k];
+              // a row wholly inside this tile has no other writer
+              const bool whole = s_off[k] >= t0 && s_off[k + 1] <= t1;
+              int32_t* rp32 = (int32_t*)(A.rs + y);
+              const int32_t old = whole ? *rp32 : atomic_add(rp32, (int32_t)sum);
+              if (whole) *rp32 = old + (int32_t)sum;
+              if ((int64_t)old < A.lam && A.lam <= (int64_t)old + sum) {
+                // the entry whose weight takes r to the cap (prefixes ascend)
+                int32_t lo = qa, hi = qb - 1;
+                while (lo < hi) {
+                  const int32_t mid = (lo + hi) >> 1;
+                  if ((int64_t)old + (int64_t)(P(mid) - before) >= A.lam) hi = mid;
+                  else lo = mid + 1;
                 }
+                partner = e_x[lo];
               }
             }
           }
