@@ -941,16 +941,29 @@ __global__ void k_sweep_big_mark(const SweepArgs* args, const int32_t* run) {
   const int32_t stamp = c->step + 1;
   int64_t sum = 0, deg = 0;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = h + tid; i - lane_id() < t; i += nth) {  // wave-uniform bound
-    // loads outside the branch (one round trip for all of them); a lane past
+  constexpr int MU = 4;  // batch vertices per thread and step, their loads in flight together
+  for (int64_t i0 = h + tid; i0 - lane_id() < t; i0 += nth * MU) {  // wave-uniform bound
+    // loads outside the branch (one round trip for all of them); a slot past
     // the end reads the batch's first vertex
-    const bool in = i < t;
-    const int32_t x = A.capq[in ? i : h];
-    const int64_t cd = A.cdeg[x], d = A.rp[x + 1] - A.rp[x];
-    if (in) {
-      sum += cd;  // minus twice the batch's weight to the visited set, summed by the relax
-      *rs_stamp_ptr(A.rs + x) = stamp;
-      deg += d;
+    int32_t x[MU];
+#pragma unroll
+    for (int u = 0; u < MU; ++u) {
+      const int64_t i = i0 + u * nth;
+      x[u] = A.capq[i < t ? i : h];
+    }
+    int64_t cd[MU], d[MU];
+#pragma unroll
+    for (int u = 0; u < MU; ++u) {
+      cd[u] = A.cdeg[x[u]];
+      d[u] = A.rp[x[u] + 1] - A.rp[x[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < MU; ++u) {
+      if (i0 + u * nth < t) {
+        sum += cd[u];  // minus twice the batch's weight to the visited set, summed by the relax
+        *rs_stamp_ptr(A.rs + x[u]) = stamp;
+        deg += d[u];
+      }
     }
   }
   // one add per workgroup and counter (adds on one address serialise)
@@ -1812,11 +1825,20 @@ __global__ void __launch_bounds__(256) k_sweep_rb_count(SweepArgs A) {
   __shared__ int32_t h[SWEEP_BUCKETS];
   for (int i = threadIdx.x; i < A.nb; i += 256) h[i] = 0;
   __syncthreads();
-  for (int64_t i = gtid(); i < A.ng; i += gstride()) {
-    const int32_t v = A.v0 + (int32_t)i;
-    const uint64_t u = A.rs[v];
-    const int32_t rv = rs_r(u);
-    if (rs_stamp(u) == 0 && rv > 0 && (int64_t)rv < A.lam) atomicAdd(&h[rv >> A.shift], 1);
+  constexpr int RU = 4;  // vertices per thread and step, their words loaded together
+  for (int64_t i0 = gtid(); i0 < A.ng; i0 += gstride() * RU) {
+    uint64_t w[RU];
+#pragma unroll
+    for (int k = 0; k < RU; ++k) {
+      const int64_t i = i0 + k * gstride();
+      w[k] = A.rs[A.v0 + (int32_t)(i < A.ng ? i : 0)];
+    }
+#pragma unroll
+    for (int k = 0; k < RU; ++k) {
+      const int32_t rv = rs_r(w[k]);
+      if (i0 + k * gstride() < A.ng && rs_stamp(w[k]) == 0 && rv > 0 && (int64_t)rv < A.lam)
+        atomicAdd(&h[rv >> A.shift], 1);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < A.nb; i += 256)
