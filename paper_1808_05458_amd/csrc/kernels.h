@@ -152,8 +152,9 @@ __global__ void __launch_bounds__(256, 5) k_ingest(int32_t n, int64_t nnz, const
     for (int k = 0; k < 8; ++k) {
       const int32_t o = k * 64 + lane;
       const int32_t oc = o < len ? o : 0;
-      y[k] = cb[oc];
-      c[k] = wb[oc];
+      // each entry is read once here: streamed past the caches
+      y[k] = __builtin_nontemporal_load(cb + oc);
+      c[k] = __builtin_nontemporal_load(wb + oc);
     }
     f = fn;  // first[at], loaded a step earlier
     s0 = chunk_start0(rp, n, f);
