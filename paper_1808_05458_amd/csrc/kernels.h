@@ -1084,24 +1084,28 @@ __global__ void __launch_bounds__(256) k_emit(int32_t n, int64_t nnz, const int6
         skip[k] = skip[k] | (((bu >> (u[k] & 31)) & (bx >> (x[k] & 31)) & 1u) != 0);
       }
     }
-    // a slot whose entries all stay inside reference blocks (most of them,
-    // once a round has contracted most of the graph) loads nothing more:
-    // the test is wave-uniform
+    // a chunk whose entries all stay inside reference blocks (most of them,
+    // once a round has contracted most of the graph) loads nothing more
+    // (the test is wave-uniform); otherwise every slot's labels and weight
+    // go out together, a skipped entry reading the chunk's first (one
+    // shared line)
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) any = any || !skip[k];
+    if (ballot(any) == 0) continue;
+    int32_t la[8], lb[8], cw[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      la[k] = lab[skip[k] ? 0 : u[k]];
+      lb[k] = lab[skip[k] ? 0 : x[k]];
+      cw[k] = w[skip[k] ? e0 : e0 + k * 64 + lane];
+    }
     uint64_t key[8];
-    int32_t vv[8];
     uint64_t msk[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      msk[k] = 0;
-      key[k] = 0;
-      vv[k] = 0;
-      if (ballot(!skip[k]) == 0) continue;
-      const int32_t a = lab[skip[k] ? 0 : u[k]];
-      const int32_t b = lab[skip[k] ? 0 : x[k]];
-      const int32_t c = w[skip[k] ? e0 : e0 + k * 64 + lane];
-      const bool ok = !skip[k] && a >= 0 && b >= 0 && a != b;
-      key[k] = ((uint64_t)(uint32_t)a << bits) | (uint32_t)b;
-      vv[k] = c;
+      const bool ok = !skip[k] && la[k] >= 0 && lb[k] >= 0 && la[k] != lb[k];
+      key[k] = ((uint64_t)(uint32_t)la[k] << bits) | (uint32_t)lb[k];
       msk[k] = ballot(ok);
     }
     uint32_t tot = 0;
@@ -1115,7 +1119,7 @@ __global__ void __launch_bounds__(256) k_emit(int32_t n, int64_t nnz, const int6
       if ((msk[k] >> lane) & 1) {
         const uint32_t at = o + popc64(msk[k] & lanemask_lt());
         st_k[at] = key[k];
-        st_v[at] = vv[k];
+        st_v[at] = cw[k];
       }
       o += popc64(msk[k]);
     }
