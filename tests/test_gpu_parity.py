@@ -213,6 +213,45 @@ def test_disconnected_and_edge_cases():
     assert lam == 9 and list(side) == [0, 1]
 
 
+def test_ingest_chunk_forms_against_noi():
+    # the weighted degrees come from two forms of the ingest: a chunk with
+    # fewer than 64 row starts, light weights and no self-loop takes each
+    # row's share from prefix sums; a chunk of short rows (a ring's degree-2
+    # rows start more than 64 per chunk), one holding a self-loop or a
+    # weight of 2^22 or more maps every entry to its row.  These graphs mix
+    # all of them: lambda equals the sequential NOI oracle's, the reported
+    # initial bound equals the minimum weighted degree summed on the host
+    # (self-loops excluded), and the side realises lambda.
+    rng = np.random.default_rng(11)
+    for t in range(8):
+        n = int(rng.integers(600, 2500))
+        edges = [(i, (i + 1) % n) for i in range(n)]
+        for h in rng.choice(n, size=4, replace=False):
+            for v in rng.choice(n, size=int(rng.integers(200, 600)), replace=False):
+                if v != h:
+                    edges.append((int(h), int(v)))
+        extra = rng.integers(0, n, size=(n // 2, 2))
+        edges += [(int(a), int(b)) for a, b in extra if a != b]
+        wts = rng.integers(1, 50, size=len(edges))
+        wts[rng.choice(len(edges), size=6, replace=False)] = rng.integers(1 << 22, 1 << 24, size=6)
+        loops = list(rng.choice(n, size=5, replace=False))
+        if t % 2:  # a heavy self-loop on a vertex of least weighted degree
+            g0 = gg.from_edges(n, edges, wts)
+            s0 = np.repeat(np.arange(n), np.diff(g0.row_ptr))
+            loops[0] = int(np.argmin(np.bincount(s0, weights=g0.w.astype(np.float64), minlength=n)))
+        edges += [(int(v), int(v)) for v in loops]
+        wts = np.concatenate([wts, rng.integers(1, 1000, size=5)])
+        g = gg.from_edges(n, edges, wts)
+        src = np.repeat(np.arange(n), np.diff(g.row_ptr))
+        deg = np.bincount(src, weights=np.where(g.col != src, g.w, 0).astype(np.float64), minlength=n)
+        ref = oracle.noi(g, 1)[0]
+        announce("ingest chunk forms", t, n, g.m, ref)
+        lam, side, st = solve(g)
+        assert lam == ref
+        check_side(g, lam, side)
+        assert st["lambda_initial"] == int(deg.min())
+
+
 def test_invalid_inputs_are_rejected():
     import torch
     import paper_1808_05458_amd as mc
