@@ -726,7 +726,7 @@ struct Solver {
           // per batch vertex its FIFO slot, degree, r word and stamp (the
           // bytes are added once the batches' sizes are read back)
           TimedScope t("k_sweep_big_mark", 0.0);
-          hipLaunchKernelGGL(k_sweep_big_mark, dim3(std::max(1, num_cu * 16 / nrun), nrun), dim3(TB), 0, s,
+          hipLaunchKernelGGL(k_sweep_big_mark, dim3(std::max(1, num_cu * 4 / nrun), nrun), dim3(TB), 0, s,
                              ws.sw_args, ws.sw_run);
         }
         hipLaunchKernelGGL(k_sweep_status, dim3(grid_for(nrun, TB, num_cu)), dim3(TB), 0, s, ws.sw_args,
@@ -785,7 +785,7 @@ struct Solver {
               hipLaunchKernelGGL(k_sweep_big_tiles, dim3(grid_for(bsz, TB, num_cu * 16)), dim3(TB), 0, s, off,
                                  (int32_t)bsz, tile_row);
               // the graph's visit states, two bits per vertex
-              hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 16)), dim3(TB), 0, s, A, ws.st2);
+              hipLaunchKernelGGL(k_sweep_bits, dim3(grid_for(A.ng, TB, num_cu * 4)), dim3(TB), 0, s, A, ws.st2);
             }
             // range by range (segments of at least four entries on average,
             // and no batch row of this sweep found out of order so far): the

@@ -1024,20 +1024,32 @@ enum : uint32_t { BS_FREE = 0, BS_CROSSED = 1, BS_BATCH = 2, BS_VISITED = 3 };
 // (a crossed vertex is in the FIFO, so at this point none is BS_CROSSED).
 __global__ void k_sweep_bits(SweepArgs A, uint32_t* st2) {
   const int32_t stamp = A.ctl->step + 1;
-  for (int64_t base = (gtid() >> 6) << 6; base < A.ng; base += gstride()) {
-    const int64_t i = base + lane_id();
-    const int32_t st = i < A.ng ? rs_stamp(A.rs[A.v0 + i]) : 0;
-    const uint64_t hi = ballot(st != 0);                   // in the batch or visited
-    const uint64_t lo = ballot(st != 0 && st != stamp);    // visited
-    // interleave: vertex k of a 16-vertex group at bits 2k (lo) and 2k+1 (hi)
-    uint32_t word = 0;
-    const int g = lane_id() & 3;  // lanes 0..3 each build one word of 16 vertices
-    for (int k = 0; k < 16; ++k) {
-      const int b = g * 16 + k;
-      word |= (uint32_t)((lo >> b) & 1) << (2 * k);
-      word |= (uint32_t)((hi >> b) & 1) << (2 * k + 1);
+  constexpr int BU = 4;  // 64-vertex groups per wave and step, their words loaded together
+  const int64_t stride = gstride();
+  for (int64_t b0 = (gtid() >> 6) << 6; b0 < A.ng; b0 += stride * BU) {
+    int32_t sts[BU];
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+      const int64_t i = b0 + u * stride + lane_id();
+      sts[u] = rs_stamp(A.rs[A.v0 + (i < A.ng ? i : 0)]);
     }
-    if (lane_id() < 4) st2[(base >> 4) + g] = word;
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+      const int64_t base = b0 + u * stride;  // wave-uniform
+      if (base >= A.ng) break;
+      const int32_t st = base + lane_id() < A.ng ? sts[u] : 0;
+      const uint64_t hi = ballot(st != 0);                 // in the batch or visited
+      const uint64_t lo = ballot(st != 0 && st != stamp);  // visited
+      // interleave: vertex k of a 16-vertex group at bits 2k (lo) and 2k+1 (hi)
+      uint32_t word = 0;
+      const int g = lane_id() & 3;  // lanes 0..3 each build one word of 16 vertices
+      for (int k = 0; k < 16; ++k) {
+        const int b = g * 16 + k;
+        word |= (uint32_t)((lo >> b) & 1) << (2 * k);
+        word |= (uint32_t)((hi >> b) & 1) << (2 * k + 1);
+      }
+      if (lane_id() < 4) st2[(base >> 4) + g] = word;
+    }
   }
 }
 
