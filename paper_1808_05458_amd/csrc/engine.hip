@@ -724,7 +724,11 @@ struct Solver {
         }
         {
           // per batch vertex its FIFO slot, degree, r word and stamp (the
-          // bytes are added once the batches' sizes are read back)
+          // bytes are added once the batches' sizes are read back).  The
+          // batch's size is not known here: four workgroups per CU, each
+          // thread with four vertices' loads in flight, cover the largest
+          // batches in a few steps without dispatching empty waves for the
+          // many small ones
           TimedScope t("k_sweep_big_mark", 0.0);
           hipLaunchKernelGGL(k_sweep_big_mark, dim3(std::max(1, num_cu * 4 / nrun), nrun), dim3(TB), 0, s,
                              ws.sw_args, ws.sw_run);
