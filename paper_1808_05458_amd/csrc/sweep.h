@@ -1310,12 +1310,15 @@ __global__ void __launch_bounds__(256) k_sweep_seg_bounds(SweepArgs A, int32_t h
           ri[u] = rb + row;
         }
       }
+      // an entry's predecessor in its row is this thread's previous entry,
+      // except for the first, whose predecessor is loaded (its line is
+      // mostly the entry's own)
       int32_t ys[SEG_BUNROLL], yp[SEG_BUNROLL];
 #pragma unroll
-      for (int u = 0; u < SEG_BUNROLL; ++u) {
-        ys[u] = A.col[es[u]];
-        yp[u] = A.col[ps[u] > 0 ? es[u] - 1 : es[u]];
-      }
+      for (int u = 0; u < SEG_BUNROLL; ++u) ys[u] = A.col[es[u]];
+      yp[0] = A.col[ps[0] > 0 ? es[0] - 1 : es[0]];
+#pragma unroll
+      for (int u = 1; u < SEG_BUNROLL; ++u) yp[u] = ys[u - 1];
       bool unsorted = false;
 #pragma unroll
       for (int u = 0; u < SEG_BUNROLL; ++u) unsorted = unsorted || (ps[u] > 0 && yp[u] > ys[u]);
